@@ -1,0 +1,365 @@
+"""Pins of the FP64 oracle to what the paper and mathematics fix (CPU only).
+
+Each test checks the oracle against something other than itself: values printed
+in the paper, closed forms, exact polynomial reproduction, library routines on
+the same inputs, brute force, invariances and convergence orders.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spl
+from scipy.spatial.distance import cdist
+
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- closed forms
+
+def test_closed_forms_satisfy_navier_stokes():
+    """Kovasznay, Taylor-Green and Ethier-Steinman flows are divergence free and
+    solve the incompressible Navier-Stokes equations exactly (rho = 1)."""
+    import sympy as s
+    x, y, z, t = s.symbols("x y z t", real=True)
+    Re = s.Integer(40)
+    nu = 1 / Re
+    lam = Re / 2 - s.sqrt(Re ** 2 / 4 + 4 * s.pi ** 2)
+    u = 1 - s.exp(lam * x) * s.cos(2 * s.pi * y)
+    v = lam / (2 * s.pi) * s.exp(lam * x) * s.sin(2 * s.pi * y)
+    p = s.Rational(1, 2) * (1 - s.exp(2 * lam * x))
+    _check_ns2(s, x, y, t, u, v, p, nu)
+    nu = s.Rational(1, 100)
+    F = s.exp(-2 * nu * t)
+    u = s.cos(x) * s.sin(y) * F
+    v = -s.sin(x) * s.cos(y) * F
+    p = -s.Rational(1, 4) * (s.cos(2 * x) + s.cos(2 * y)) * F ** 2
+    _check_ns2(s, x, y, t, u, v, p, nu)
+    a, d = s.pi / 4, s.pi / 2
+    G = s.exp(-nu * d ** 2 * t)
+    U = [-a * (s.exp(a * x) * s.sin(a * y + d * z) + s.exp(a * z) * s.cos(a * x + d * y)) * G,
+         -a * (s.exp(a * y) * s.sin(a * z + d * x) + s.exp(a * x) * s.cos(a * y + d * z)) * G,
+         -a * (s.exp(a * z) * s.sin(a * x + d * y) + s.exp(a * y) * s.cos(a * z + d * x)) * G]
+    P = -a ** 2 / 2 * (s.exp(2 * a * x) + s.exp(2 * a * y) + s.exp(2 * a * z)
+                       + 2 * s.sin(a * x + d * y) * s.cos(a * z + d * x) * s.exp(a * (y + z))
+                       + 2 * s.sin(a * y + d * z) * s.cos(a * x + d * y) * s.exp(a * (z + x))
+                       + 2 * s.sin(a * z + d * x) * s.cos(a * y + d * z) * s.exp(a * (x + y))) * G ** 2
+    X = [x, y, z]
+    div = sum(s.diff(U[i], X[i]) for i in range(3))
+    pts = [(0.1, 0.3, 0.7, 0.2), (0.9, 0.4, 0.15, 1.3)]
+    for pt in pts:
+        sub = dict(zip((x, y, z, t), pt))
+        assert abs(float(div.subs(sub))) < 1e-12
+        for i in range(3):
+            res = (s.diff(U[i], t) + sum(U[j] * s.diff(U[i], X[j]) for j in range(3))
+                   + s.diff(P, X[i]) - nu * sum(s.diff(U[i], X[j], 2) for j in range(3)))
+            assert abs(float(res.subs(sub))) < 1e-10
+    # the numpy versions used as inputs agree with the symbolic ones
+    xs, ys, zs, ts = 0.3, 0.55, 0.8, 0.4
+    un, vn, wn, pn = W.beltrami(xs, ys, zs, ts)
+    sub = {x: xs, y: ys, z: zs, t: ts}
+    assert abs(un - float(U[0].subs(sub))) < 1e-13 and abs(pn - float(P.subs(sub))) < 1e-13
+
+
+def _check_ns2(s, x, y, t, u, v, p, nu):
+    div = s.diff(u, x) + s.diff(v, y)
+    ru = s.diff(u, t) + u * s.diff(u, x) + v * s.diff(u, y) + s.diff(p, x) - nu * (s.diff(u, x, 2) + s.diff(u, y, 2))
+    rv = s.diff(v, t) + u * s.diff(v, x) + v * s.diff(v, y) + s.diff(p, y) - nu * (s.diff(v, x, 2) + s.diff(v, y, 2))
+    for pt in [(0.2, 0.3, 0.1), (-0.4, 1.2, 0.7), (1.1, -0.3, 2.0)]:
+        sub = {x: pt[0], y: pt[1], t: pt[2]}
+        for e in (div, ru, rv):
+            assert abs(float(e.subs(sub))) < 1e-10
+
+
+# ---------------------------------------------------------------- monomials
+
+def test_monomial_order_matches_paper(orc):
+    ref = np.loadtxt(os.path.join(GOLDEN, "monomials_2d_k2.txt"), dtype=int)
+    ex = orc.monomial_exponents(2, 2)
+    assert ex.shape == (6, 3)
+    np.testing.assert_array_equal(ex[:, :2], ref)
+    for dim in (2, 3):
+        for k in range(0, 7):
+            m = orc.num_monomials(dim, k)
+            from math import comb
+            assert m == comb(k + dim, dim)
+            ex = orc.monomial_exponents(dim, k)
+            tot = ex.sum(axis=1)
+            assert (np.diff(tot) >= 0).all()            # graded
+            assert len({tuple(r) for r in ex}) == m     # distinct
+            assert tot.max() == k
+
+
+# ---------------------------------------------------------------- kNN
+
+def _brute_knn(xyz, q, idx):
+    d = xyz - xyz[idx]
+    if xyz.shape[1] == 2:
+        d2 = d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]
+    else:
+        d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+    return np.lexsort((np.arange(len(xyz)), d2))[:q]
+
+
+@pytest.mark.parametrize("gen,q", [(lambda: W.kovasznay_square(nx=20), 20),
+                                   (lambda: W.beltrami_cube(n=6), 40),
+                                   (lambda: W.holed_square(900, seed=1003), 12)])
+def test_knn_matches_brute_force(orc, gen, q):
+    c = gen()
+    nbr = orc.knn(c.xyz, q)
+    assert nbr.shape == (c.n, q)
+    assert (nbr[:, 0] == np.arange(c.n)).all()
+    for i in range(0, c.n, max(1, c.n // 97)):
+        np.testing.assert_array_equal(nbr[i], _brute_knn(c.xyz, q, i))
+
+
+def test_knn_ties_broken_by_index(orc):
+    # an exact lattice: many equal distances; order must follow the index
+    g = np.arange(7, dtype=np.float64)
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    xyz = np.stack([X.ravel(), Y.ravel()], 1)
+    nbr = orc.knn(xyz, 9)
+    i = 3 * 7 + 3
+    assert list(nbr[i]) == [24, 17, 23, 25, 31, 16, 18, 30, 32]
+
+
+# ---------------------------------------------------------------- weights
+
+@pytest.mark.parametrize("dim,k,gen", [(2, 2, lambda: W.kovasznay_square(nx=12)),
+                                       (2, 3, lambda: W.kovasznay_square(nx=12)),
+                                       (2, 5, lambda: W.kovasznay_square(nx=14)),
+                                       (3, 2, lambda: W.beltrami_cube(n=5)),
+                                       (3, 3, lambda: W.beltrami_cube(n=6))])
+def test_weights_reproduce_polynomials(orc, dim, k, gen):
+    """The moment constraints (Eq. RBF_constraint) force exact differentiation of
+    every monomial of degree <= k, at interior and one-sided boundary clouds."""
+    c = gen()
+    q = orc.default_q(dim, k)
+    nbr = orc.knn(c.xyz, q)
+    w = orc.weights(c.xyz, nbr, k)
+    x = c.xyz
+    h = c.h
+    for ex in orc.monomial_exponents(dim, k):
+        f = np.prod([x[:, e] ** ex[e] for e in range(dim)], axis=0)
+        vals = f[nbr]                                    # (n, q)
+        got = np.einsum("rnq,nq->rn", w, vals)
+        ref = []
+        for e in range(dim):
+            if ex[e] == 0:
+                ref.append(np.zeros(c.n))
+            else:
+                ee = ex.copy(); ee[e] -= 1
+                ref.append(ex[e] * np.prod([x[:, j] ** ee[j] for j in range(dim)], axis=0))
+        lap = np.zeros(c.n)
+        for e in range(dim):
+            if ex[e] >= 2:
+                ee = ex.copy(); ee[e] -= 2
+                lap += ex[e] * (ex[e] - 1) * np.prod([x[:, j] ** ee[j] for j in range(dim)], axis=0)
+        ref.append(lap)
+        ref = np.stack(ref)
+        scale = np.abs(w).sum(axis=2) * (np.abs(vals).max(axis=1) + 1.0)
+        assert (np.abs(got - ref) <= 1e-10 * scale + 1e-12).all(), (ex, np.abs(got - ref).max())
+    del h
+
+
+def test_saddle_system_blocks_and_library_solve(orc):
+    """A = [Phi P; P^T 0] with Phi = r^3 of the scaled cloud (Eqs. RBF_interp_mat_vec,
+    RBF_interp_phi, RBF_interp_poly); the oracle's LU solution matches LAPACK's."""
+    c = W.kovasznay_square(nx=10)
+    k, q = 3, 20
+    nbr = orc.knn(c.xyz, q)
+    w = orc.weights(c.xyz, nbr, k)
+    for i in (0, 5, c.pin, c.n - 1):
+        A, B, s = orc.saddle_system(c.xyz, nbr, k, i)
+        xi = (c.xyz[nbr[i]] - c.xyz[i]) / s
+        np.testing.assert_allclose(A[:q, :q], cdist(xi, xi) ** 3, rtol=1e-13, atol=1e-15)
+        ex = orc.monomial_exponents(2, k)
+        Pm = np.stack([xi[:, 0] ** a * xi[:, 1] ** b for a, b, _ in ex], 1)
+        np.testing.assert_allclose(A[:q, q:], Pm, rtol=1e-13, atol=1e-15)
+        np.testing.assert_array_equal(A[q:, :q], A[:q, q:].T)
+        assert (A[q:, q:] == 0).all()
+        assert np.isclose(s, np.linalg.norm(c.xyz[nbr[i, -1]] - c.xyz[i]))
+        X = np.linalg.solve(A, B)
+        sc = np.array([s, s, s * s])
+        ref = (X[:q] / sc).T
+        np.testing.assert_allclose(w[:, i, :], ref, rtol=1e-9, atol=1e-9 * np.abs(ref).max())
+
+
+def test_weights_translation_and_scale_covariance(orc):
+    c = W.kovasznay_square(nx=10)
+    k, q = 3, 20
+    nbr = orc.knn(c.xyz, q)
+    w = orc.weights(c.xyz, nbr, k)
+    w_t = orc.weights(c.xyz + np.array([3.25, -1.5]), nbr, k)
+    np.testing.assert_allclose(w_t, w, rtol=1e-9, atol=1e-9 * np.abs(w).max())
+    sig = 0.37
+    w_s = orc.weights(c.xyz * sig, nbr, k)
+    np.testing.assert_allclose(w_s[:2] * sig, w[:2], rtol=1e-9, atol=1e-9 * np.abs(w[:2]).max())
+    np.testing.assert_allclose(w_s[2] * sig * sig, w[2], rtol=1e-9, atol=1e-9 * np.abs(w[2]).max())
+
+
+def _fit_slope(hs, errs):
+    return np.polyfit(np.log(hs), np.log(errs), 1)[0]
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_derivative_errors_fall_at_expected_order(orc, k):
+    """Expected orders k (gradient) and k-1 (Laplacian) of the PHS-RBF operators
+    (Sec. 4.1, orders k+1 / k / k-1 for interpolation / gradient / Laplacian);
+    band of +-0.7 on interior points of jittered lattices."""
+    f = lambda x, y: np.exp(x) * np.sin(np.pi * y)
+    fx = lambda x, y: np.exp(x) * np.sin(np.pi * y)
+    lap = lambda x, y: (1 - np.pi ** 2) * np.exp(x) * np.sin(np.pi * y)
+    hs, ex, el = [], [], []
+    for nx in (16, 24, 36, 54):
+        c = W.scattered_square(nx, seed=11, lo=0.0, hi=1.0)
+        ops = orc.build_operators(c, k)
+        x, y = c.xyz[:, 0], c.xyz[:, 1]
+        d = orc.apply_ops(ops.col, ops.val, f(x, y))
+        m = c.kind == 0
+        hs.append(1.0 / nx)
+        ex.append(np.abs(d[0] - fx(x, y))[m].mean())
+        el.append(np.abs(d[2] - lap(x, y))[m].mean())
+    sx, sl = _fit_slope(hs, ex), _fit_slope(hs, el)
+    assert k - 0.7 <= sx, (sx, ex)
+    assert k - 1 - 0.7 <= sl, (sl, el)
+
+
+def test_interpolation_error_falls_at_order_k_plus_1(orc):
+    f = lambda x, y: np.cos(2 * x) * np.exp(y)
+    k = 3
+    rng = np.random.default_rng(5)
+    hs, errs = [], []
+    for nx in (12, 18, 27, 40):
+        c = W.scattered_square(nx, seed=3, lo=0.0, hi=1.0)
+        q = orc.default_q(2, k)
+        xs = rng.uniform(0.3, 0.7, size=(25, 2))
+        e = []
+        for p in xs:
+            d2 = ((c.xyz - p) ** 2).sum(1)
+            cl = np.lexsort((np.arange(c.n), d2))[:q]
+            w = orc.interp_weights(c.xyz, cl, p, k)
+            e.append(abs(w @ f(c.xyz[cl, 0], c.xyz[cl, 1]) - f(*p)))
+        hs.append(1.0 / nx)
+        errs.append(np.mean(e))
+    assert _fit_slope(hs, errs) >= k + 1 - 0.7
+
+
+def test_singular_stencil_is_reported(orc):
+    # five collinear points cannot carry the y monomials: the system is singular
+    xyz = np.stack([np.arange(8.0), np.zeros(8)], 1)
+    nbr = orc.knn(xyz, 6)
+    with pytest.raises(np.linalg.LinAlgError):
+        orc.weights(xyz, nbr, 1)
+
+
+# ---------------------------------------------------------------- CSR
+
+def test_csr_is_a_permutation_matching_scipy(orc):
+    c = W.kovasznay_square(nx=15)
+    k, q = 3, 20
+    nbr = orc.knn(c.xyz, q)
+    w = orc.weights(c.xyz, nbr, k)
+    col, val = orc.csr(nbr, w)
+    assert (np.diff(col, axis=1) > 0).all()
+    for r in range(3):
+        A = sp.csr_matrix((w[r].ravel().copy(), nbr.ravel().copy(), np.arange(0, c.n * q + 1, q)),
+                          shape=(c.n, c.n))
+        A.sort_indices()
+        np.testing.assert_array_equal(A.indices.reshape(c.n, q), col)
+        np.testing.assert_array_equal(A.data.reshape(c.n, q), val[r])   # bit-exact
+
+
+def test_poisson_matrix_rows(orc):
+    c = W.kovasznay_square(nx=12)
+    ops = orc.build_operators(c, 3)
+    inter = (c.kind == 0) & (np.arange(c.n) != c.pin)
+    np.testing.assert_array_equal(ops.pval[inter], ops.val[2][inter])
+    b = c.kind != 0
+    ref = c.normal[b, 0:1] * ops.val[0][b] + c.normal[b, 1:2] * ops.val[1][b]
+    np.testing.assert_allclose(ops.pval[b], ref, rtol=1e-15, atol=1e-15)
+    np.testing.assert_array_equal(ops.pval[c.pin], (ops.col[c.pin] == c.pin).astype(float))
+    # homogeneous Neumann rows annihilate constants and the pin row fixes the level
+    ones = orc.spmv(ops.col, ops.pval, np.ones(c.n))
+    assert np.abs(ones[b]).max() < 1e-9 * np.abs(ops.pval[b]).max()
+
+
+# ---------------------------------------------------------------- Krylov
+
+def test_bicgstab_matches_direct_solve(orc):
+    c = W.kovasznay_square(nx=16)
+    ops = orc.build_operators(c, 3)
+    n, q = ops.col.shape
+    A = sp.csr_matrix((ops.pval.ravel(), ops.col.ravel(), np.arange(0, n * q + 1, q)), shape=(n, n))
+    b = np.random.default_rng(1).standard_normal(n)
+    x, its, rr, st = orc.bicgstab(ops.col, ops.pval, b, tol=1e-12)
+    assert st == 0 and rr <= 1e-12
+    xd = spl.spsolve(A.tocsc(), b)
+    assert np.linalg.norm(A @ x - b) <= 1e-10 * np.linalg.norm(b)   # true vs recursive residual drift
+    assert np.abs(x - xd).max() <= 1e-7 * np.abs(xd).max()
+    # zero right-hand side gives the zero solution
+    x0, its0, _, st0 = orc.bicgstab(ops.col, ops.pval, np.zeros(n), x0=np.ones(n))
+    assert st0 == 0 and its0 == 0 and not x0.any()
+
+
+def test_momentum_like_solve(orc):
+    c = W.kovasznay_square(nx=16)
+    ops = orc.build_operators(c, 3)
+    n, q = ops.col.shape
+    mval = 20.0 * (ops.col == np.arange(n)[:, None]) - 0.025 * ops.val[2]
+    A = sp.csr_matrix((mval.ravel(), ops.col.ravel(), np.arange(0, n * q + 1, q)), shape=(n, n))
+    b = np.random.default_rng(2).standard_normal(n)
+    x, its, rr, st = orc.bicgstab(ops.col, mval, b, tol=1e-13)
+    assert st == 0
+    np.testing.assert_allclose(x, spl.spsolve(A.tocsc(), b), rtol=1e-10, atol=1e-11)
+
+
+# ---------------------------------------------------------------- time step
+
+def _one_step_change(orc, nx, dt=0.005):
+    c = W.kovasznay_square(nx=nx)
+    ops = orc.build_operators(c, 3)
+    vel, p = W.flow_fields(c)
+    u, up, pn, st = orc.simple_step(ops, vel, vel, p, vel, 1.0, 1.0 / 40, dt, alpha=orc.BDF2,
+                                    tol_outer=0.0, tol_krylov=1e-12, max_outer=1)
+    pe = p - p.mean()
+    return (np.abs(u - vel).mean(), np.abs((pn - pn.mean()) - pe)[c.kind != 0].mean(), st)
+
+
+def test_exact_steady_flow_is_near_a_fixed_point(orc):
+    """Started from the exact Kovasznay solution, one outer iteration (momentum,
+    pressure correction, boundary pressure from the normal momentum equation,
+    corrections) moves the fields only by the discretization error, which
+    shrinks with h. A sign error in any term of Eqs. u:tilde ... p:correction or
+    in the normal momentum equation makes the change O(1)."""
+    du1, dp1, st1 = _one_step_change(orc, 20)
+    du2, dp2, st2 = _one_step_change(orc, 40)
+    # a sign error in the advection or pressure-gradient term alone moves u by
+    # ~dt |u.grad u| ~ 5e-2 here
+    assert du1 < 2e-3 and du2 < 1e-3 and du2 < du1, (du1, du2)
+    assert st1["status"] in (0, -4) and np.isfinite(dp1) and np.isfinite(dp2)
+
+
+def test_courant_time_step_scaling(orc):
+    """|lambda|max of the convection-diffusion operator grows like 1/h^2 when
+    diffusion dominates: halving h cuts dt by between 2x and 4x (Sec. 4.1 notes
+    about 3.5x for its explicit scheme)."""
+    dts = []
+    for nx in (16, 32):
+        c = W.kovasznay_square(nx=nx)
+        ops = orc.build_operators(c, 3)
+        vel, _ = W.flow_fields(c)
+        dts.append(orc.dt_from_courant(ops, vel, 1.0, 1.0, 1.0 / 40))
+    assert 2.0 <= dts[0] / dts[1] <= 4.5, dts
+
+
+def test_bdf_coefficients_fixture(orc):
+    a = np.loadtxt(os.path.join(GOLDEN, "bdf2.txt"))
+    assert tuple(a) == orc.BDF2
+    # BDF2 differentiates quadratics in t exactly at t^{n+1}
+    for f, df in ((lambda t: 3 * t * t - t + 2, lambda t: 6 * t - 1),):
+        dt, t1 = 0.1, 1.0
+        approx = (a[0] * f(t1) + a[1] * f(t1 - dt) + a[2] * f(t1 - 2 * dt)) / dt
+        assert abs(approx - df(t1)) < 1e-12

@@ -1,0 +1,369 @@
+"""Seeded synthetic inputs for the semi-implicit PHS-RBF solver.
+
+This module produces point clouds (coordinates, point kinds, outward boundary
+normals, the pressure-pin point), the closed-form flows that supply Dirichlet
+data and accuracy references, and nothing else: it holds none of the method's
+arithmetic (no neighbour search, no collocation, no operators, no solver).
+Both the HIP library's callers and the FP64 oracle read the clouds made here.
+
+Every generator is deterministic for a given seed (numpy ``default_rng``).
+Points are returned Morton-sorted (21 bits per dimension over the bounding box),
+which keeps stencil neighbours close in memory for the device kernels.
+
+Point kinds: 0 = interior, 1 = Dirichlet-velocity boundary (wall or inlet,
+where the pressure correction obeys a homogeneous Neumann condition).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+INTERIOR = 0
+DIRICHLET = 1
+
+
+@dataclass
+class Cloud:
+    dim: int
+    xyz: np.ndarray          # (n, dim) float64
+    kind: np.ndarray         # (n,) uint8
+    normal: np.ndarray       # (n, dim) float64; unit outward normal on boundary points, 0 inside
+    pin: int                 # interior point whose pressure correction is held at zero
+    name: str = ""
+    h: float = 0.0           # nominal point spacing of the generator
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.xyz.shape[0])
+
+    def boundary(self) -> np.ndarray:
+        return self.kind != INTERIOR
+
+
+# --------------------------------------------------------------------------
+# closed-form incompressible flows (rho = 1)
+# --------------------------------------------------------------------------
+
+def kovasznay(x, y, Re=40.0):
+    """Kovasznay's steady laminar wake behind a grid (Re = 1/nu)."""
+    lam = Re / 2.0 - np.sqrt(Re * Re / 4.0 + 4.0 * np.pi * np.pi)
+    e = np.exp(lam * x)
+    u = 1.0 - e * np.cos(2.0 * np.pi * y)
+    v = lam / (2.0 * np.pi) * e * np.sin(2.0 * np.pi * y)
+    p = 0.5 * (1.0 - np.exp(2.0 * lam * x))
+    return u, v, p
+
+
+def taylor_green(x, y, t, nu=0.01):
+    """Decaying Taylor-Green vortex on a periodic 2*pi square."""
+    F = np.exp(-2.0 * nu * t)
+    u = np.cos(x) * np.sin(y) * F
+    v = -np.sin(x) * np.cos(y) * F
+    p = -0.25 * (np.cos(2.0 * x) + np.cos(2.0 * y)) * F * F
+    return u, v, p
+
+
+def beltrami(x, y, z, t, a=np.pi / 4, d=np.pi / 2, nu=0.01):
+    """Ethier-Steinman three-dimensional Beltrami flow."""
+    G = np.exp(-nu * d * d * t)
+    u = -a * (np.exp(a * x) * np.sin(a * y + d * z) + np.exp(a * z) * np.cos(a * x + d * y)) * G
+    v = -a * (np.exp(a * y) * np.sin(a * z + d * x) + np.exp(a * x) * np.cos(a * y + d * z)) * G
+    w = -a * (np.exp(a * z) * np.sin(a * x + d * y) + np.exp(a * y) * np.cos(a * z + d * x)) * G
+    p = -0.5 * a * a * (
+        np.exp(2 * a * x) + np.exp(2 * a * y) + np.exp(2 * a * z)
+        + 2 * np.sin(a * x + d * y) * np.cos(a * z + d * x) * np.exp(a * (y + z))
+        + 2 * np.sin(a * y + d * z) * np.cos(a * x + d * y) * np.exp(a * (z + x))
+        + 2 * np.sin(a * z + d * x) * np.cos(a * y + d * z) * np.exp(a * (x + y))
+    ) * G * G
+    return u, v, w, p
+
+
+def flow_fields(cloud: Cloud, t: float = 0.0):
+    """Exact (velocity[dim, n], pressure[n]) of the cloud's flow at time t."""
+    x = cloud.xyz
+    flow = cloud.meta.get("flow")
+    if flow == "kovasznay":
+        u, v, p = kovasznay(x[:, 0], x[:, 1], cloud.meta.get("Re", 40.0))
+        vel = np.stack([u, v])
+    elif flow == "taylor_green":
+        u, v, p = taylor_green(x[:, 0], x[:, 1], t, cloud.meta.get("nu", 0.01))
+        vel = np.stack([u, v])
+    elif flow == "beltrami":
+        u, v, w, p = beltrami(x[:, 0], x[:, 1], x[:, 2], t, nu=cloud.meta.get("nu", 0.01))
+        vel = np.stack([u, v, w])
+    elif flow == "kovasznay_holes":
+        u, v, p = kovasznay(x[:, 0], x[:, 1], cloud.meta.get("Re", 40.0))
+        vel = np.stack([u, v])
+        on_hole = cloud.meta["on_hole"]
+        vel[:, on_hole] = 0.0          # no-slip on the holes
+    else:
+        raise ValueError(f"cloud has no closed-form flow: {flow!r}")
+    return np.ascontiguousarray(vel), np.ascontiguousarray(p)
+
+
+# --------------------------------------------------------------------------
+# helpers
+# --------------------------------------------------------------------------
+
+def _part1by1(v):
+    v = v.astype(np.uint64) & np.uint64(0x1FFFFF)
+    out = np.zeros_like(v)
+    for b in range(21):
+        out |= ((v >> np.uint64(b)) & np.uint64(1)) << np.uint64(b * 2)
+    return out
+
+
+def _part1by2(v):
+    v = v.astype(np.uint64) & np.uint64(0x1FFFFF)
+    out = np.zeros_like(v)
+    for b in range(21):
+        out |= ((v >> np.uint64(b)) & np.uint64(1)) << np.uint64(b * 3)
+    return out
+
+
+def morton_order(xyz: np.ndarray) -> np.ndarray:
+    """Stable permutation sorting points by a 21-bit-per-axis Morton code."""
+    lo = xyz.min(axis=0)
+    span = np.maximum(xyz.max(axis=0) - lo, 1e-300)
+    qv = np.floor((xyz - lo) / span * ((1 << 21) - 1)).astype(np.int64)
+    qv = np.clip(qv, 0, (1 << 21) - 1)
+    if xyz.shape[1] == 2:
+        code = _part1by1(qv[:, 0]) | (_part1by1(qv[:, 1]) << np.uint64(1))
+    else:
+        code = (_part1by2(qv[:, 0]) | (_part1by2(qv[:, 1]) << np.uint64(1))
+                | (_part1by2(qv[:, 2]) << np.uint64(2)))
+    return np.argsort(code, kind="stable")
+
+
+def _finish(dim, xyz, kind, normal, name, h, meta, centre):
+    order = morton_order(xyz)
+    xyz = np.ascontiguousarray(xyz[order], dtype=np.float64)
+    kind = np.ascontiguousarray(kind[order], dtype=np.uint8)
+    normal = np.ascontiguousarray(normal[order], dtype=np.float64)
+    for key in ("on_hole",):
+        if key in meta:
+            meta[key] = np.ascontiguousarray(meta[key][order])
+    # pressure pin: the interior point nearest the domain centre, ties -> lowest index
+    d2 = ((xyz - np.asarray(centre)) ** 2).sum(axis=1)
+    d2 = np.where(kind == INTERIOR, d2, np.inf)
+    pin = int(np.lexsort((np.arange(len(d2)), d2))[0])
+    return Cloud(dim=dim, xyz=xyz, kind=kind, normal=normal, pin=pin, name=name, h=h, meta=meta)
+
+
+def _square_perimeter(lo, hi, per_edge):
+    """Evenly spaced points on the square's edges, each edge starting at a corner
+    (all four corners included once), counter-clockwise, with outward normals;
+    a corner's normal is the normalised sum of its two edge normals."""
+    L = hi - lo
+    s = np.arange(per_edge) * (L / per_edge)
+    pts, nrm = [], []
+    edges = [((lo, lo), (1, 0), (0, -1)), ((hi, lo), (0, 1), (1, 0)),
+             ((hi, hi), (-1, 0), (0, 1)), ((lo, hi), (0, -1), (-1, 0))]
+    for (cx, cy), (tx, ty), (nx, ny) in edges:
+        px = cx + tx * s
+        py = cy + ty * s
+        pts.append(np.stack([px, py], axis=1))
+        nrm.append(np.tile(np.array([nx, ny], dtype=np.float64), (per_edge, 1)))
+    pts = np.concatenate(pts)
+    nrm = np.concatenate(nrm)
+    # corners: the first point of each edge
+    c = 1.0 / np.sqrt(2.0)
+    corner_n = [(-c, -c), (c, -c), (c, c), (-c, c)]
+    for e in range(4):
+        nrm[e * per_edge] = corner_n[e]
+    return pts, nrm
+
+
+# --------------------------------------------------------------------------
+# clouds
+# --------------------------------------------------------------------------
+
+def kovasznay_square(nx: int = 40, seed: int = 1, jitter: float = 0.2, Re: float = 40.0,
+                     lo: float = -0.5, hi: float = 1.5) -> Cloud:
+    """Kovasznay flow on [lo, hi]^2: a cell-centred nx-by-nx interior lattice with each
+    coordinate jittered by U(-jitter*h, jitter*h), plus 4*nx boundary points at spacing h."""
+    rng = np.random.default_rng(seed)
+    h = (hi - lo) / nx
+    g = lo + (np.arange(nx) + 0.5) * h
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    inter = np.stack([X.ravel(), Y.ravel()], axis=1)
+    inter = inter + rng.uniform(-jitter * h, jitter * h, size=inter.shape)
+    bpts, bnrm = _square_perimeter(lo, hi, nx)
+    xyz = np.concatenate([inter, bpts])
+    kind = np.concatenate([np.zeros(len(inter), np.uint8), np.ones(len(bpts), np.uint8)])
+    normal = np.concatenate([np.zeros_like(inter), bnrm])
+    return _finish(2, xyz, kind, normal, f"kovasznay_{nx}", h,
+                   {"flow": "kovasznay", "Re": Re, "nu": 1.0 / Re, "seed": seed},
+                   centre=((lo + hi) / 2, (lo + hi) / 2))
+
+
+def poisson_disk(rng, lo, hi, r, rounds=24):
+    """Dart throwing on a background grid of cell size r/sqrt(2) (at most one point
+    per cell). Cells are visited in 9 interleaved classes so that proposals made
+    together are never closer than r to each other; each round offers every empty
+    cell one uniform proposal, accepted when no existing point lies within r."""
+    a = r / np.sqrt(2.0)
+    G = int(np.ceil((hi - lo) / a))
+    ox = np.full((G + 4, G + 4), np.nan)
+    oy = np.full((G + 4, G + 4), np.nan)
+    r2 = r * r
+    offs = [(di, dj) for di in range(-2, 3) for dj in range(-2, 3) if (di, dj) != (0, 0)]
+    cls = []
+    for ci in range(3):
+        for cj in range(3):
+            I, J = np.meshgrid(np.arange(ci, G, 3), np.arange(cj, G, 3), indexing="ij")
+            cls.append((I.ravel(), J.ravel()))
+    for _ in range(rounds):
+        for I0, J0 in cls:
+            m = np.isnan(ox[I0 + 2, J0 + 2])
+            I, J = I0[m], J0[m]
+            px = lo + (I + rng.random(I.size)) * a
+            py = lo + (J + rng.random(J.size)) * a
+            ok = (px < hi) & (py < hi)
+            for di, dj in offs:
+                nx_ = ox[I + 2 + di, J + 2 + dj]
+                ny_ = oy[I + 2 + di, J + 2 + dj]
+                with np.errstate(invalid="ignore"):
+                    ok &= ~(((px - nx_) ** 2 + (py - ny_) ** 2) < r2)
+            ox[I[ok] + 2, J[ok] + 2] = px[ok]
+            oy[I[ok] + 2, J[ok] + 2] = py[ok]
+    m = ~np.isnan(ox)
+    return np.stack([ox[m], oy[m]], axis=1)
+
+
+# Radius giving 250,000 +- 0.5% points in [0, 2*pi]^2 with seed 2 and 24 rounds
+# (found by bisection on the point count).
+TG_RADIUS_250K = 0.01025
+
+
+def taylor_green_disk(r: float = TG_RADIUS_250K, seed: int = 2, nu: float = 0.01,
+                      rounds: int = 24) -> Cloud:
+    """Taylor-Green vortex on [0, 2*pi]^2: Poisson-disk interior of radius r (interior
+    points closer than r/2 to the boundary dropped) and boundary points at spacing ~r."""
+    rng = np.random.default_rng(seed)
+    lo, hi = 0.0, 2.0 * np.pi
+    inter = poisson_disk(rng, lo, hi, r, rounds)
+    keep = ((inter[:, 0] > lo + r / 2) & (inter[:, 0] < hi - r / 2)
+            & (inter[:, 1] > lo + r / 2) & (inter[:, 1] < hi - r / 2))
+    inter = inter[keep]
+    per_edge = int(round((hi - lo) / r))
+    bpts, bnrm = _square_perimeter(lo, hi, per_edge)
+    xyz = np.concatenate([inter, bpts])
+    kind = np.concatenate([np.zeros(len(inter), np.uint8), np.ones(len(bpts), np.uint8)])
+    normal = np.concatenate([np.zeros_like(inter), bnrm])
+    return _finish(2, xyz, kind, normal, f"taylor_green_{len(xyz)}", r,
+                   {"flow": "taylor_green", "nu": nu, "seed": seed},
+                   centre=(np.pi, np.pi))
+
+
+def beltrami_cube(n: int = 100, seed: int = 4, jitter: float = 0.2, nu: float = 0.01) -> Cloud:
+    """Ethier-Steinman flow on [0,1]^3: a cell-centred n^3 lattice jittered by
+    U(-jitter*h, jitter*h) per coordinate, plus the cell-centred n^2 lattice of each
+    of the six faces (no edge or corner points)."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    g = (np.arange(n) + 0.5) * h
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    inter = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    inter = inter + rng.uniform(-jitter * h, jitter * h, size=inter.shape)
+    A, B = np.meshgrid(g, g, indexing="ij")
+    A = A.ravel()
+    B = B.ravel()
+    zero = np.zeros_like(A)
+    one = np.ones_like(A)
+    faces, fn = [], []
+    for axis in range(3):
+        for side, val in ((-1.0, zero), (1.0, one)):
+            cols = [A, B]
+            cols.insert(axis, val)
+            faces.append(np.stack(cols, axis=1))
+            nn = np.zeros((len(A), 3))
+            nn[:, axis] = side
+            fn.append(nn)
+    bpts = np.concatenate(faces)
+    bnrm = np.concatenate(fn)
+    xyz = np.concatenate([inter, bpts])
+    kind = np.concatenate([np.zeros(len(inter), np.uint8), np.ones(len(bpts), np.uint8)])
+    normal = np.concatenate([np.zeros_like(inter), bnrm])
+    return _finish(3, xyz, kind, normal, f"beltrami_{n}", h,
+                   {"flow": "beltrami", "nu": nu, "seed": seed}, centre=(0.5, 0.5, 0.5))
+
+
+def holed_square(n_target: int, seed: int, n_holes: int | None = None, Re: float = 40.0,
+                 jitter: float = 0.2) -> Cloud:
+    """Unit square minus 0-4 circular holes (radius U(0.05, 0.15), centre in
+    [r+0.05, 1-r-0.05]^2, kept 0.05 apart). Jittered lattice interior with spacing h
+    chosen to approach n_target points; points inside a hole or within h/2 of it are
+    removed; hole boundaries carry points at spacing ~h with normals pointing into
+    the hole (outward from the fluid). Kovasznay data on the square's edges and
+    no-slip on the holes."""
+    rng = np.random.default_rng(seed)
+    nh = int(rng.integers(0, 5)) if n_holes is None else n_holes
+    holes = []
+    tries = 0
+    while len(holes) < nh and tries < 1000:
+        tries += 1
+        r = rng.uniform(0.05, 0.15)
+        c = rng.uniform(r + 0.05, 1 - r - 0.05, size=2)
+        if all(np.hypot(*(c - c2)) > r + r2 + 0.05 for c2, r2 in holes):
+            holes.append((c, r))
+    area = 1.0 - sum(np.pi * r * r for _, r in holes)
+    h = np.sqrt(area / n_target)
+    nx = max(4, int(round(1.0 / h)))
+    h = 1.0 / nx
+    g = (np.arange(nx) + 0.5) * h
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    inter = np.stack([X.ravel(), Y.ravel()], axis=1)
+    inter = inter + rng.uniform(-jitter * h, jitter * h, size=inter.shape)
+    keep = np.ones(len(inter), bool)
+    hp, hn = [], []
+    for c, r in holes:
+        keep &= np.hypot(inter[:, 0] - c[0], inter[:, 1] - c[1]) > r + h / 2
+        m = max(8, int(round(2 * np.pi * r / h)))
+        th = np.arange(m) * (2 * np.pi / m)
+        hp.append(np.stack([c[0] + r * np.cos(th), c[1] + r * np.sin(th)], axis=1))
+        hn.append(np.stack([-np.cos(th), -np.sin(th)], axis=1))
+    inter = inter[keep]
+    bpts, bnrm = _square_perimeter(0.0, 1.0, nx)
+    parts = [inter, bpts] + hp
+    xyz = np.concatenate(parts)
+    n_hole_pts = sum(len(p) for p in hp)
+    kind = np.concatenate([np.zeros(len(inter), np.uint8), np.ones(len(bpts) + n_hole_pts, np.uint8)])
+    normal = np.concatenate([np.zeros_like(inter), bnrm] + hn)
+    on_hole = np.concatenate([np.zeros(len(inter) + len(bpts), bool), np.ones(n_hole_pts, bool)])
+    return _finish(2, xyz, kind, normal, f"holed_{len(xyz)}_{seed}", h,
+                   {"flow": "kovasznay_holes", "Re": Re, "nu": 1.0 / Re, "seed": seed,
+                    "holes": [(float(c[0]), float(c[1]), float(r)) for c, r in holes],
+                    "on_hole": on_hole},
+                   centre=(0.5, 0.5))
+
+
+def scattered_square(nx: int, seed: int = 7, jitter: float = 0.2, lo: float = 0.0,
+                     hi: float = 1.0) -> Cloud:
+    """A jittered nx-by-nx lattice on [lo, hi]^2 with boundary points (no flow attached);
+    used for operator-accuracy studies."""
+    c = kovasznay_square(nx=nx, seed=seed, jitter=jitter, lo=lo, hi=hi)
+    c.meta = {"seed": seed}
+    c.name = f"square_{nx}"
+    return c
+
+
+def scattered_cube(n: int, seed: int = 9, jitter: float = 0.2) -> Cloud:
+    c = beltrami_cube(n=n, seed=seed, jitter=jitter)
+    c.meta = {"flow": "beltrami", "nu": 0.01, "seed": seed}
+    c.name = f"cube_{n}"
+    return c
+
+
+def config_c3_sizes(count: int = 256, seed: int = 1000):
+    """Per-instance (n_target, seed, poly_degree) of the 256-instance batch: sizes
+    log-uniform over 500-50k, degree uniform over 2..5."""
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng(seed + i)
+        n = int(round(np.exp(rng.uniform(np.log(500), np.log(50_000)))))
+        k = int(rng.integers(2, 6))
+        out.append((n, seed + i, k))
+    return out
