@@ -1,0 +1,219 @@
+/*
+ * rbffd.h - C ABI of the MI355X (gfx950) implementation of the data-parallel
+ * hot path of Shahane & Vanka, "A Semi-Implicit Meshless Method for
+ * Incompressible Flows in Complex Geometries" (arXiv 2106.07616):
+ *
+ *   rbffd_build_stencils  k-nearest-neighbour clouds and PHS-RBF + polynomial
+ *                         differentiation weights (Sec. 2)
+ *   rbffd_assemble        sparse operators d/dx, d/dy, (d/dz), Laplacian and the
+ *                         pressure-correction matrix (Sec. 2 closing remark,
+ *                         Eq. pressure poisson, Sec. 3.1)
+ *   simple_step           one BDF2 time step with outer momentum /
+ *                         pressure-correction iterations (Sec. 3, Sec. 3.2)
+ *   poisson_solve         preconditioned BiCGSTAB on the pressure-correction
+ *                         matrix (Sec. 3)
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: RBFFD_OK (0) or a negative RBFFD_E_* code; nothing aborts
+ *     and no C++ exception crosses the ABI. rbffd_last_error() gives a
+ *     thread-local message for the last failure on the calling thread.
+ *   - Array arguments are DEVICE pointers (hipMalloc / torch tensors on the
+ *     GPU) owned by the caller unless stated otherwise; sizes are elements.
+ *   - Arguments are validated on the host before anything is launched; an
+ *     invalid argument returns RBFFD_E_ARG and launches nothing.
+ *   - All work is enqueued on the caller's HIP stream (void* hip_stream, NULL =
+ *     the default stream). rbffd_build_stencils and rbffd_assemble return once
+ *     their small host-visible results are known (they synchronise the stream
+ *     once); simple_step and poisson_solve synchronise to take convergence
+ *     decisions and return with all work complete.
+ *   - One context per host thread; calls on one context must not overlap.
+ *   - Field layout: a velocity field is [dim][n] (component-major), a scalar
+ *     field is [n]; coordinates and normals are [n][dim] (point-major).
+ */
+#ifndef RBFFD_H
+#define RBFFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define RBFFD_OK 0
+#define RBFFD_E_ARG (-1)        /* invalid argument (checked before any launch)  */
+#define RBFFD_E_OOM (-2)        /* the context's HBM budget or the device is full */
+#define RBFFD_E_SINGULAR (-3)   /* a collocation system had a pivot <= 1e-13 max|A| */
+#define RBFFD_E_NOCONV (-4)     /* a Krylov solve or the outer iteration hit its limit */
+#define RBFFD_E_BREAKDOWN (-5)  /* BiCGSTAB breakdown (t.t == 0) */
+#define RBFFD_E_DEVICE (-6)     /* a HIP runtime call failed */
+
+/* ---- precision of the Krylov sweeps ------------------------------------ */
+#define RBFFD_FP64 0            /* everything in FP64                                  */
+#define RBFFD_FP32_IR 1         /* FP32 matrix values / vectors / SpMV inside, FP64 dot
+                                   accumulation, FP64 residual refinement outside       */
+
+/* ---- point kinds ------------------------------------------------------- */
+#define RBFFD_INTERIOR 0
+#define RBFFD_DIRICHLET 1       /* prescribed velocity (wall, inlet); homogeneous Neumann
+                                   pressure correction; boundary pressure from the
+                                   normal momentum equation (Sec. 3.1)                  */
+#define RBFFD_PRESCRIBED_PRESSURE 2 /* prescribed velocity and prescribed pressure; the
+                                   pressure correction is zero there (Sec. 3.1)          */
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *rbffd_last_error(void);
+
+/* ---- context ------------------------------------------------------------ */
+typedef struct rbffd_ctx rbffd_ctx;
+
+/* Create a context on HIP device `hip_device`. Device memory the library
+ * allocates (operators, Krylov workspace) is charged to `hbm_budget_bytes`
+ * (0 = no limit); an allocation beyond the budget returns RBFFD_E_OOM. */
+int rbffd_ctx_create(rbffd_ctx **ctx, int hip_device, size_t hbm_budget_bytes);
+/* Free the context and its workspace (operators are freed by rbffd_ops_free). */
+int rbffd_ctx_destroy(rbffd_ctx *ctx);
+/* Device bytes currently charged to the context (workspace + live operators). */
+size_t rbffd_ctx_bytes_in_use(const rbffd_ctx *ctx);
+
+/* ---- inputs ------------------------------------------------------------ */
+typedef struct {
+    int dim;                /* 2 or 3                                                */
+    int64_t n;              /* number of points, 1 <= n < 2^31                       */
+    const double *xyz;      /* device [n][dim]; no two points may coincide           */
+    const uint8_t *kind;    /* device [n]: RBFFD_INTERIOR / _DIRICHLET / _PRESCRIBED_PRESSURE */
+    const double *normal;   /* device [n][dim]: unit outward normal (boundary points) */
+    int64_t pin;            /* interior point whose pressure correction is 0, or -1
+                               (none; needed only when no prescribed-pressure point
+                               fixes the pressure level)                             */
+} rbffd_cloud;
+
+typedef struct {
+    int phs_power;          /* polyharmonic spline exponent: 3 (r^3) or 5 (r^5)     */
+    int poly_degree;        /* k, degree of the appended polynomials, 0..6           */
+    int q;                  /* cloud size including the point itself; 0 = 2m          */
+} rbffd_stencil_opts;
+
+/* Cloud size q (resolving q = 0), monomial count m = binomial(k+dim, dim) and
+ * operator count R = dim + 1 for the given options. RBFFD_E_ARG if q <= m. */
+int rbffd_stencil_sizes(int dim, const rbffd_stencil_opts *opts, int *q, int *m, int *R);
+
+/* (Sec. 2) For every point i: its cloud, the q nearest points including i in
+ * the total order (squared distance, index), with squared distance evaluated
+ * as ((dx*dx + dy*dy) + dz*dz), dx = x_j - x_i, without fused multiply-add;
+ * then the centre row of B1 = [L Phi  L P] A^{-1} for L = d/dx, d/dy, (d/dz),
+ * Laplacian, with A = [Phi P; P^T 0] built in coordinates centred at x_i and
+ * scaled by the distance to the q-th neighbour, solved by LU with partial
+ * pivoting.
+ *   nbr: device [n][q] int32 out, neighbour indices in cloud order (nbr[i][0]=i)
+ *   w:   device [R][n][q] double out, weights in cloud order
+ *   bad_point: host out (may be NULL): lowest index of a singular stencil or -1
+ * Returns RBFFD_E_SINGULAR if any stencil was singular (w is then undefined for
+ * that point), RBFFD_E_ARG for duplicate points is NOT detected here: the
+ * caller guarantees distinct points. */
+int rbffd_build_stencils(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_stencil_opts *opts,
+                         int32_t *nbr, double *w, int64_t *bad_point, void *hip_stream);
+
+/* ---- operators ---------------------------------------------------------- */
+typedef struct rbffd_ops rbffd_ops;
+
+/* (Sec. 2 closing remark, Eq. pressure poisson, Sec. 3.1) Sort each cloud by
+ * column into a sparse matrix with exactly q entries per row, carry the R
+ * weight sets along, and build the pressure-correction matrix: the Laplacian
+ * row at interior points, N . grad at velocity-Dirichlet boundary points
+ * (homogeneous Neumann), the identity row (p' = 0) at prescribed-pressure points
+ * and at the pin. `precision` selects
+ * whether FP32 copies for RBFFD_FP32_IR are made. The cloud arrays are copied;
+ * nbr and w may be freed afterwards. *out is library-owned: free it with
+ * rbffd_ops_free. */
+int rbffd_assemble(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_stencil_opts *opts,
+                   const int32_t *nbr, const double *w, int precision, rbffd_ops **out,
+                   void *hip_stream);
+int rbffd_ops_free(rbffd_ops *ops);
+/* n, q, dim and the number of boundary points of assembled operators. */
+int rbffd_ops_info(const rbffd_ops *ops, int64_t *n, int *q, int *dim, int64_t *n_boundary);
+/* Write the operators as row-major CSR with q entries per row (row_ptr[i] = i*q,
+ * columns ascending): col device [n][q] int32, val device [R+1][n][q] double
+ * holding d/dx, d/dy, (d/dz), Laplacian and the pressure-correction matrix. */
+int rbffd_ops_export_csr(const rbffd_ops *ops, int32_t *col, double *val, void *hip_stream);
+/* y = A x for operator `which` (0..dim-1: d/dx_e, dim: Laplacian, dim+1: the
+ * pressure-correction matrix); x, y device [n]. */
+int rbffd_apply(rbffd_ctx *ctx, const rbffd_ops *ops, int which, const double *x, double *y,
+                void *hip_stream);
+
+/* ---- Krylov solve ------------------------------------------------------- */
+typedef struct {
+    double tol;             /* stop when ||b - A x||_2 <= tol ||b||_2 (recursive residual) */
+    int max_iter;           /* BiCGSTAB iterations                                   */
+    int precision;          /* RBFFD_FP64 or RBFFD_FP32_IR                          */
+} rbffd_krylov_opts;
+
+typedef struct {
+    int iters;              /* BiCGSTAB iterations (FP32_IR: inner iterations, all sweeps) */
+    int status;             /* RBFFD_OK / RBFFD_E_NOCONV / RBFFD_E_BREAKDOWN         */
+    int refinements;        /* FP32_IR: FP64 residual refinement sweeps              */
+    double relres;          /* true FP64 residual ||b - A x|| / ||b|| at return      */
+} rbffd_krylov_stats;
+
+/* (Sec. 3, "preconditioned BiCGSTAB") Solve P x = rhs for the
+ * pressure-correction matrix with BiCGSTAB, right-preconditioned by the
+ * Jacobi diagonal. x holds the initial guess on entry and the solution on
+ * return. rhs, x: device [n]. */
+int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, double *x,
+                  const rbffd_krylov_opts *opts, rbffd_krylov_stats *stats, void *hip_stream);
+
+/* ---- time step ---------------------------------------------------------- */
+typedef struct {
+    double rho, mu;         /* density and dynamic viscosity                         */
+    double dt;              /* time step                                              */
+    double alpha[3];        /* BDF coefficients (1.5, -2, 0.5); (1, -1, 0) = BDF1    */
+    double tol_outer;       /* stop the outer iteration when Delta < tol_outer       */
+    double tol_krylov;      /* relative tolerance of every Krylov solve              */
+    int max_outer;          /* outer iteration limit                                  */
+    int max_krylov;         /* iteration limit of every Krylov solve                  */
+    int precision;          /* RBFFD_FP64 or RBFFD_FP32_IR                          */
+} rbffd_step_opts;
+
+typedef struct {
+    int outer_iters;        /* outer iterations taken                                */
+    int krylov_mom;         /* momentum BiCGSTAB iterations (sum over components)    */
+    int krylov_p;           /* pressure-correction BiCGSTAB iterations               */
+    int krylov_b;           /* boundary-pressure BiCGSTAB iterations                 */
+    int status;             /* RBFFD_OK or the first failure code                    */
+    double delta;           /* last Delta = sum_c mean_i |u_c^{r+1} - u_c^r|          */
+    double eps_steady;      /* max_c mean_i |u_c^{n+1} - u_c^n| / dt                  */
+} rbffd_step_stats;
+
+/* (Sec. 3 and the step list of Sec. 3.2) One BDF time step: starting from
+ * u^r = u^n (Dirichlet values of t^{n+1} on boundary points) and p^r = p^n,
+ * repeat  momentum solves for u~ (Eqs. u:tilde, v:tilde) -> pressure
+ * correction (Eq. pressure poisson) -> interior p += p' -> boundary pressure
+ * (Eq. normal momentum on velocity-Dirichlet points, solved for their block
+ * with the other pressures fixed; the given value on prescribed-pressure
+ * points) -> u = u~ - dt/(rho alpha1) grad p' on interior points -> Delta,
+ * until Delta < tol_outer or max_outer.
+ *   u:      device [dim][n] in: u^n,     out: u^{n+1}
+ *   u_prev: device [dim][n] in: u^{n-1}, out: u^n
+ *   p:      device [n]      in: p^n,     out: p^{n+1}
+ *   u_bc:   device [dim][n] Dirichlet velocity at t^{n+1} (read on boundary rows)
+ *   p_bc:   device [n] pressure at t^{n+1} (read on prescribed-pressure rows;
+ *           may be NULL when the cloud has none)
+ * Returns RBFFD_OK, or RBFFD_E_NOCONV when the outer or a Krylov iteration hit
+ * its limit (fields hold the last iterate). */
+int simple_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, double *p,
+                const double *u_bc, const double *p_bc, const rbffd_step_opts *opts,
+                rbffd_step_stats *stats, void *hip_stream);
+
+/* (Sec. 3.2) |lambda|max of the discrete convection-diffusion operator
+ * -rho (u0 . grad) + mu Laplacian on interior rows (boundary rows zero), by
+ * `iters` normalised power iterations from x_i = 1 + (i mod 7)/7; a Courant
+ * number Co gives dt = 2 Co / |lambda|max. u0: device [dim][n]. */
+int rbffd_convdiff_lambda(rbffd_ctx *ctx, const rbffd_ops *ops, const double *u0, double rho,
+                          double mu, int iters, double *lambda_out, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBFFD_H */

@@ -69,7 +69,7 @@ def lib():
             L.orc_spmv.restype = None
             L.orc_poisson_values.argtypes = [C.c_int, i64, C.c_int, P, P, i64, P, P, P]
             L.orc_bicgstab.argtypes = [i64, C.c_int, P, P, P, P, C.c_double, C.c_int, P, P]
-            L.orc_simple_step.argtypes = [P, P, P, P, P, P]
+            L.orc_simple_step.argtypes = [P, P, P, P, P, P, P]
             L.orc_convdiff_lambda.argtypes = [C.c_int, i64, C.c_int, P, P, P, P, C.c_double, C.c_double, C.c_int]
             L.orc_convdiff_lambda.restype = C.c_double
             _lib = L
@@ -254,8 +254,9 @@ BDF1 = (1.0, -1.0, 0.0)
 
 
 def simple_step(ops: Operators, u, u_prev, p, u_bc, rho, mu, dt, alpha=BDF2,
-                tol_outer=1e-6, tol_krylov=1e-10, max_outer=50, max_krylov=5000):
-    """One time step; returns (u_new, u_n, p_new, stats dict). Inputs are not modified."""
+                tol_outer=1e-6, tol_krylov=1e-10, max_outer=50, max_krylov=5000, p_bc=None):
+    """One time step; returns (u_new, u_n, p_new, stats dict). Inputs are not modified.
+    p_bc: pressure at t^{n+1} on prescribed-pressure (kind 2) points."""
     cl = ops.cloud
     n, dim = cl.n, cl.dim
     u = np.array(u, dtype=np.float64, copy=True).reshape(dim, n)
@@ -271,7 +272,10 @@ def simple_step(ops: Operators, u, u_prev, p, u_bc, rho, mu, dt, alpha=BDF2,
                    _p(val).value, _p(pv).value, rho, mu, dt, (C.c_double * 3)(*alpha),
                    tol_outer, tol_krylov, max_outer, max_krylov)
     st = _StepStats()
-    lib().orc_simple_step(C.byref(cfg), _p(u), _p(up), _p(p), _p(ubc), C.byref(st))
+    pbc = None if p_bc is None else _c(p_bc, np.float64).reshape(n)
+    if pbc is None and (cl.kind == 2).any():
+        raise ValueError("p_bc is required on clouds with prescribed-pressure points")
+    lib().orc_simple_step(C.byref(cfg), _p(u), _p(up), _p(p), _p(ubc), _p(pbc), C.byref(st))
     stats = dict(outer_iters=st.outer_iters, krylov_mom=st.krylov_mom, krylov_p=st.krylov_p,
                  krylov_b=st.krylov_b, status=st.status, delta=st.delta, eps_steady=st.eps_steady)
     return u, up, p, stats
@@ -297,7 +301,8 @@ def outer_tolerance(dt, eps_prev, first=False, cap=1e-4):
 
 
 def run_steady(ops: Operators, u0, p0, u_bc, rho, mu, dt, steady_tol=1e-8, max_steps=100000,
-               krylov_factor=1e-2, krylov_floor=1e-13, max_outer=50, max_krylov=5000, callback=None):
+               krylov_factor=1e-2, krylov_floor=1e-13, max_outer=50, max_krylov=5000, callback=None,
+               p_bc=None):
     """March in time until the steady error max_c mean|u^{n+1}-u^n|/dt <= steady_tol.
     The first step is BDF1, later steps BDF2; the outer tolerance follows Sec. 3.2
     and the Krylov tolerance is max(floor, factor * outer tolerance)."""
@@ -312,7 +317,7 @@ def run_steady(ops: Operators, u0, p0, u_bc, rho, mu, dt, steady_tol=1e-8, max_s
         u, up, p, st = simple_step(ops, u, up, p, u_bc, rho, mu, dt,
                                    alpha=BDF1 if step == 0 else BDF2,
                                    tol_outer=tol_o, tol_krylov=tol_k, max_outer=max_outer,
-                                   max_krylov=max_krylov)
+                                   max_krylov=max_krylov, p_bc=p_bc)
         eps = st["eps_steady"]
         hist.append(st)
         if callback:
@@ -323,9 +328,10 @@ def run_steady(ops: Operators, u0, p0, u_bc, rho, mu, dt, steady_tol=1e-8, max_s
 
 
 def run_transient(ops: Operators, u0, p0, bc_fn, rho, mu, dt, nsteps, tol_outer=1e-8,
-                  tol_krylov=1e-10, max_outer=50, max_krylov=5000, u_prev0=None, t0=0.0):
-    """nsteps time steps from t0 with Dirichlet data bc_fn(t) -> [dim, n]; the first
-    step is BDF1 unless u_prev0 (velocity at t0 - dt) is given."""
+                  tol_krylov=1e-10, max_outer=50, max_krylov=5000, u_prev0=None, t0=0.0, pbc_fn=None):
+    """nsteps time steps from t0 with Dirichlet data bc_fn(t) -> [dim, n] (and
+    pbc_fn(t) -> [n] on prescribed-pressure points); the first step is BDF1
+    unless u_prev0 (velocity at t0 - dt) is given."""
     u = np.array(u0, dtype=np.float64, copy=True)
     up = u.copy() if u_prev0 is None else np.array(u_prev0, dtype=np.float64, copy=True)
     p = np.array(p0, dtype=np.float64, copy=True)
@@ -335,6 +341,7 @@ def run_transient(ops: Operators, u0, p0, bc_fn, rho, mu, dt, nsteps, tol_outer=
         first = (step == 0 and u_prev0 is None)
         u, up, p, st = simple_step(ops, u, up, p, bc_fn(t_next), rho, mu, dt,
                                    alpha=BDF1 if first else BDF2, tol_outer=tol_outer,
-                                   tol_krylov=tol_krylov, max_outer=max_outer, max_krylov=max_krylov)
+                                   tol_krylov=tol_krylov, max_outer=max_outer, max_krylov=max_krylov,
+                                   p_bc=None if pbc_fn is None else pbc_fn(t_next))
         hist.append(st)
     return u, p, hist

@@ -524,9 +524,10 @@ int orc_bicgstab(int64_t n, int q, const int32_t *col, const double *val, const 
 /* pressure-correction matrix (Eq. pressure poisson, Sec. 3.1)             */
 /* ---------------------------------------------------------------------- */
 /* Rows: the PHS Laplacian at interior points, the outward normal derivative
- * (homogeneous Neumann, N . grad p' = 0) at velocity-Dirichlet boundary points,
- * and p' = 0 at the pinned interior point, which removes the constant null
- * space of the all-Neumann problem. Same sparsity as the operators. */
+ * (homogeneous Neumann, N . grad p' = 0) at velocity-Dirichlet boundary points
+ * (kind 1), p' = 0 at prescribed-pressure boundary points (kind 2), and p' = 0
+ * at the pinned interior point (pin >= 0), which removes the constant null
+ * space when every boundary is of kind 1. Same sparsity as the operators. */
 int orc_poisson_values(int dim, int64_t n, int q, const uint8_t *kind, const double *normal,
                        int64_t pin, const int32_t *col, const double *val, double *pval)
 {
@@ -535,7 +536,8 @@ int orc_poisson_values(int dim, int64_t n, int q, const uint8_t *kind, const dou
         for (int a = 0; a < q; ++a) {
             int64_t e = i * q + a;
             double v;
-            if (i == pin) {
+            if (i == pin || kind[i] == 2) {
+                /* pinned point, or prescribed-pressure boundary: p' = 0 */
                 v = (col[e] == i) ? 1.0 : 0.0;
             } else if (kind[i] == 0) {
                 v = val[(int64_t)dim * nnz + e];
@@ -581,9 +583,10 @@ typedef struct {
 
 /* u, u_prev: [dim][n] velocity at t^n and t^{n-1}, replaced by t^{n+1} and t^n.
  * p: pressure at t^n, replaced by t^{n+1}. u_bc: [dim][n] Dirichlet velocity at
- * t^{n+1} (read on boundary rows only). */
+ * t^{n+1} (read on boundary rows only). p_bc: [n] pressure at t^{n+1} on
+ * prescribed-pressure (kind 2) points, may be NULL when there are none. */
 int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p, const double *u_bc,
-                    orc_step_stats *st)
+                    const double *p_bc, orc_step_stats *st)
 {
     const int dim = c->dim, q = c->q;
     const int64_t n = c->n, nnz = n * q;
@@ -598,8 +601,8 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
     double *f = (double *)malloc(sizeof(double) * n);
     double *bm = (double *)malloc(sizeof(double) * dim * n);
     double *mval = (double *)malloc(sizeof(double) * nnz);
-    int64_t nb = 0;
-    for (int64_t i = 0; i < n; ++i) nb += (c->kind[i] != 0);
+    int64_t nb = 0;   /* velocity-Dirichlet (kind 1) points: pressure from normal momentum */
+    for (int64_t i = 0; i < n; ++i) nb += (c->kind[i] == 1);
     int64_t *bidx = (int64_t *)malloc(sizeof(int64_t) * (nb + 1));
     int64_t *bpos = (int64_t *)malloc(sizeof(int64_t) * n);
     int32_t *gcol = (int32_t *)malloc(sizeof(int32_t) * (nb * q + 1));
@@ -607,17 +610,17 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
     double *bb = (double *)malloc(sizeof(double) * (nb + 1));
     double *pb = (double *)malloc(sizeof(double) * (nb + 1));
     for (int64_t i = 0, b = 0; i < n; ++i) {
-        bpos[i] = (c->kind[i] != 0) ? b : -1;
-        if (c->kind[i] != 0) bidx[b++] = i;
+        bpos[i] = (c->kind[i] == 1) ? b : -1;
+        if (c->kind[i] == 1) bidx[b++] = i;
     }
-    /* boundary block of the normal-derivative rows: columns of interior points
-     * are moved to the right-hand side (zero value, own column) */
+    /* block of the normal-derivative rows over kind-1 points: columns of the
+     * other points are moved to the right-hand side (zero value, own column) */
     for (int64_t b = 0; b < nb; ++b) {
         const int64_t i = bidx[b];
         for (int a = 0; a < q; ++a) {
             int64_t k = i * q + a, j = c->col[k];
-            gcol[b * q + a] = (c->kind[j] != 0) ? (int32_t)bpos[j] : (int32_t)b;
-            gval[b * q + a] = (c->kind[j] != 0) ? c->pval[k] : 0.0;
+            gcol[b * q + a] = (c->kind[j] == 1) ? (int32_t)bpos[j] : (int32_t)b;
+            gval[b * q + a] = (c->kind[j] == 1) ? c->pval[k] : 0.0;
         }
     }
 
@@ -681,8 +684,10 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
             kit_p += its;
             if (s != ORC_OK) status = s;
         }
-        /* step 4: interior pressure correction (Eq. p:correction) */
-        for (int64_t i = 0; i < n; ++i) pa[i] = (c->kind[i] == 0) ? pr[i] + pc[i] : pr[i];
+        /* step 4: interior pressure correction (Eq. p:correction); prescribed
+         * pressure on kind-2 points */
+        for (int64_t i = 0; i < n; ++i)
+            pa[i] = (c->kind[i] == 0) ? pr[i] + pc[i] : (c->kind[i] == 2 ? p_bc[i] : pr[i]);
         /* step 5: boundary pressure from the normal momentum equation (Eq. normal
          * momentum), evaluated with u-tilde (the newest velocity at this step)
          * and solved for the whole boundary block with the corrected interior
@@ -705,7 +710,7 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
             }
             for (int a = 0; a < q; ++a) {
                 int64_t k = i * q + a, j = c->col[k];
-                if (c->kind[j] != 0) continue;
+                if (c->kind[j] == 1) continue;
                 rhs = rhs - c->pval[k] * pa[j];
             }
             bb[b] = rhs;
@@ -717,7 +722,7 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
             kit_b += its;
             if (s != ORC_OK) status = s;
         }
-        for (int64_t i = 0; i < n; ++i) pr[i] = (c->kind[i] == 0) ? pa[i] : pb[bpos[i]];
+        for (int64_t i = 0; i < n; ++i) pr[i] = (c->kind[i] == 1) ? pb[bpos[i]] : pa[i];
         /* step 6: velocity correction (Eqs. u:correction, v:correction) */
         const double coef = dt / (rho * a1);
         for (int e = 0; e < dim; ++e)

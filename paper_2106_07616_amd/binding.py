@@ -1,0 +1,267 @@
+"""ctypes binding of librbffd.so (the gfx950 HIP library declared in include/rbffd.h).
+
+Argument marshalling only: every computation runs in the library's kernels.
+Device arrays are torch tensors on a ROCm device; work is enqueued on torch's
+current stream. There is no CPU fallback: importing this module on a machine
+without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librbffd.so")
+
+RBFFD_OK, RBFFD_E_ARG, RBFFD_E_OOM, RBFFD_E_SINGULAR = 0, -1, -2, -3
+RBFFD_E_NOCONV, RBFFD_E_BREAKDOWN, RBFFD_E_DEVICE = -4, -5, -6
+RBFFD_FP64, RBFFD_FP32_IR = 0, 1
+STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_OOM", -3: "E_SINGULAR", -4: "E_NOCONV",
+                -5: "E_BREAKDOWN", -6: "E_DEVICE"}
+
+EXPORTED = ["rbffd_last_error", "rbffd_ctx_create", "rbffd_ctx_destroy", "rbffd_ctx_bytes_in_use",
+            "rbffd_stencil_sizes", "rbffd_build_stencils", "rbffd_assemble", "rbffd_ops_free",
+            "rbffd_ops_info", "rbffd_ops_export_csr", "rbffd_apply", "poisson_solve", "simple_step",
+            "rbffd_convdiff_lambda"]
+
+
+class RbffdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class CloudT(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int64), ("xyz", C.c_void_p), ("kind", C.c_void_p),
+                ("normal", C.c_void_p), ("pin", C.c_int64)]
+
+
+class StencilOptsT(C.Structure):
+    _fields_ = [("phs_power", C.c_int), ("poly_degree", C.c_int), ("q", C.c_int)]
+
+
+class KrylovOptsT(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int)]
+
+
+class KrylovStatsT(C.Structure):
+    _fields_ = [("iters", C.c_int), ("status", C.c_int), ("refinements", C.c_int), ("relres", C.c_double)]
+
+
+class StepOptsT(C.Structure):
+    _fields_ = [("rho", C.c_double), ("mu", C.c_double), ("dt", C.c_double), ("alpha", C.c_double * 3),
+                ("tol_outer", C.c_double), ("tol_krylov", C.c_double), ("max_outer", C.c_int),
+                ("max_krylov", C.c_int), ("precision", C.c_int)]
+
+
+class StepStatsT(C.Structure):
+    _fields_ = [("outer_iters", C.c_int), ("krylov_mom", C.c_int), ("krylov_p", C.c_int),
+                ("krylov_b", C.c_int), ("status", C.c_int), ("delta", C.c_double),
+                ("eps_steady", C.c_double)]
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"the HIP library {path} is not built; run __graft_entry__.build()")
+    L = C.CDLL(path)
+    P, I, I64, D = C.c_void_p, C.c_int, C.c_int64, C.c_double
+    L.rbffd_last_error.restype = C.c_char_p
+    L.rbffd_ctx_create.argtypes = [C.POINTER(P), I, C.c_size_t]
+    L.rbffd_ctx_destroy.argtypes = [P]
+    L.rbffd_ctx_bytes_in_use.argtypes = [P]
+    L.rbffd_ctx_bytes_in_use.restype = C.c_size_t
+    L.rbffd_stencil_sizes.argtypes = [I, C.POINTER(StencilOptsT), C.POINTER(I), C.POINTER(I), C.POINTER(I)]
+    L.rbffd_build_stencils.argtypes = [P, C.POINTER(CloudT), C.POINTER(StencilOptsT), P, P, C.POINTER(I64), P]
+    L.rbffd_assemble.argtypes = [P, C.POINTER(CloudT), C.POINTER(StencilOptsT), P, P, I, C.POINTER(P), P]
+    L.rbffd_ops_free.argtypes = [P]
+    L.rbffd_ops_info.argtypes = [P, C.POINTER(I64), C.POINTER(I), C.POINTER(I), C.POINTER(I64)]
+    L.rbffd_ops_export_csr.argtypes = [P, P, P, P]
+    L.rbffd_apply.argtypes = [P, P, I, P, P, P]
+    L.poisson_solve.argtypes = [P, P, P, P, C.POINTER(KrylovOptsT), C.POINTER(KrylovStatsT), P]
+    L.simple_step.argtypes = [P, P, P, P, P, P, P, C.POINTER(StepOptsT), C.POINTER(StepStatsT), P]
+    L.rbffd_convdiff_lambda.argtypes = [P, P, P, D, D, I, C.POINTER(D), P]
+    return L
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+def _check(code: int, allow=()):
+    if code != RBFFD_OK and code not in allow:
+        raise RbffdError(code, lib().rbffd_last_error().decode())
+    return code
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """rbffd_ctx: a device, an HBM budget (bytes, 0 = none), and workspace."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.device = device
+        h = C.c_void_p()
+        _check(lib().rbffd_ctx_create(C.byref(h), device, hbm_budget_bytes))
+        self.handle = h
+
+    def bytes_in_use(self) -> int:
+        return lib().rbffd_ctx_bytes_in_use(self.handle)
+
+    def close(self):
+        if self.handle:
+            lib().rbffd_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class DeviceCloud:
+    dim: int
+    n: int
+    xyz: torch.Tensor      # [n, dim] float64
+    kind: torch.Tensor     # [n] uint8
+    normal: torch.Tensor   # [n, dim] float64
+    pin: int
+
+    @staticmethod
+    def from_numpy(cloud, device="cuda"):
+        return DeviceCloud(cloud.dim, cloud.n,
+                           torch.as_tensor(cloud.xyz, dtype=torch.float64, device=device).contiguous(),
+                           torch.as_tensor(cloud.kind, dtype=torch.uint8, device=device).contiguous(),
+                           torch.as_tensor(cloud.normal, dtype=torch.float64, device=device).contiguous(),
+                           int(cloud.pin))
+
+    def struct(self) -> CloudT:
+        return CloudT(self.dim, self.n, _ptr(self.xyz), _ptr(self.kind), _ptr(self.normal), self.pin)
+
+
+def rbffd_stencil_sizes(dim: int, poly_degree: int, q: int = 0, phs_power: int = 3):
+    o = StencilOptsT(phs_power, poly_degree, q)
+    qq, mm, rr = C.c_int(), C.c_int(), C.c_int()
+    _check(lib().rbffd_stencil_sizes(dim, C.byref(o), C.byref(qq), C.byref(mm), C.byref(rr)))
+    return qq.value, mm.value, rr.value
+
+
+def rbffd_build_stencils(ctx: Context, cloud: DeviceCloud, poly_degree: int, q: int = 0, phs_power: int = 3,
+                         allow_singular: bool = False):
+    """Clouds nbr[n, q] (int32) and weights w[R, n, q] (float64) on the device."""
+    q, m, R = rbffd_stencil_sizes(cloud.dim, poly_degree, q, phs_power)
+    dev = cloud.xyz.device
+    nbr = torch.empty((cloud.n, q), dtype=torch.int32, device=dev)
+    w = torch.empty((R, cloud.n, q), dtype=torch.float64, device=dev)
+    o = StencilOptsT(phs_power, poly_degree, q)
+    cs = cloud.struct()
+    bad = C.c_int64(-1)
+    st = lib().rbffd_build_stencils(ctx.handle, C.byref(cs), C.byref(o), _ptr(nbr), _ptr(w), C.byref(bad), _stream())
+    _check(st, allow=(RBFFD_E_SINGULAR,) if allow_singular else ())
+    return nbr, w, bad.value
+
+
+class Operators:
+    """rbffd_ops handle (library-owned device operators)."""
+
+    def __init__(self, handle, ctx: Context, cloud: DeviceCloud, poly_degree: int, q: int, precision: int):
+        self.handle = handle
+        self.ctx = ctx
+        self.cloud = cloud
+        self.k = poly_degree
+        self.q = q
+        self.precision = precision
+        n, qq, dim, nb = C.c_int64(), C.c_int(), C.c_int(), C.c_int64()
+        _check(lib().rbffd_ops_info(handle, C.byref(n), C.byref(qq), C.byref(dim), C.byref(nb)))
+        self.n, self.dim, self.n_boundary = n.value, dim.value, nb.value
+
+    def export_csr(self):
+        col = torch.empty((self.n, self.q), dtype=torch.int32, device=self.cloud.xyz.device)
+        val = torch.empty((self.dim + 2, self.n, self.q), dtype=torch.float64, device=self.cloud.xyz.device)
+        _check(lib().rbffd_ops_export_csr(self.handle, _ptr(col), _ptr(val), _stream()))
+        return col, val
+
+    def apply(self, which: int, x: torch.Tensor) -> torch.Tensor:
+        y = torch.empty_like(x)
+        _check(lib().rbffd_apply(self.ctx.handle, self.handle, which, _ptr(x), _ptr(y), _stream()))
+        return y
+
+    def free(self):
+        if self.handle:
+            lib().rbffd_ops_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def rbffd_assemble(ctx: Context, cloud: DeviceCloud, nbr: torch.Tensor, w: torch.Tensor, poly_degree: int,
+                   q: int = 0, phs_power: int = 3, precision: int = RBFFD_FP64) -> Operators:
+    q, m, R = rbffd_stencil_sizes(cloud.dim, poly_degree, q, phs_power)
+    o = StencilOptsT(phs_power, poly_degree, q)
+    cs = cloud.struct()
+    h = C.c_void_p()
+    _check(lib().rbffd_assemble(ctx.handle, C.byref(cs), C.byref(o), _ptr(nbr), _ptr(w), precision, C.byref(h),
+                                _stream()))
+    return Operators(h, ctx, cloud, poly_degree, q, precision)
+
+
+def poisson_solve(ctx: Context, ops: Operators, rhs: torch.Tensor, x: torch.Tensor, tol: float = 1e-10,
+                  max_iter: int = 5000, precision: int = RBFFD_FP64, allow_noconv: bool = False):
+    o = KrylovOptsT(tol, max_iter, precision)
+    s = KrylovStatsT()
+    st = lib().poisson_solve(ctx.handle, ops.handle, _ptr(rhs), _ptr(x), C.byref(o), C.byref(s), _stream())
+    _check(st, allow=(RBFFD_E_NOCONV,) if allow_noconv else ())
+    return dict(iters=s.iters, status=s.status, refinements=s.refinements, relres=s.relres)
+
+
+BDF2 = (1.5, -2.0, 0.5)
+BDF1 = (1.0, -1.0, 0.0)
+
+
+def simple_step(ctx: Context, ops: Operators, u: torch.Tensor, u_prev: torch.Tensor, p: torch.Tensor,
+                u_bc: torch.Tensor, rho: float, mu: float, dt: float, alpha=BDF2, tol_outer: float = 1e-6,
+                tol_krylov: float = 1e-10, max_outer: int = 50, max_krylov: int = 5000,
+                precision: int = RBFFD_FP64, p_bc: torch.Tensor | None = None):
+    """One time step in place on u [dim, n], u_prev [dim, n], p [n]; returns stats.
+    p_bc [n]: pressure at t^{n+1} on prescribed-pressure points. A limit reached
+    (E_NOCONV) is reported in the stats, not raised."""
+    o = StepOptsT(rho, mu, dt, (C.c_double * 3)(*alpha), tol_outer, tol_krylov, max_outer, max_krylov, precision)
+    s = StepStatsT()
+    st = lib().simple_step(ctx.handle, ops.handle, _ptr(u), _ptr(u_prev), _ptr(p), _ptr(u_bc), _ptr(p_bc),
+                           C.byref(o), C.byref(s), _stream())
+    _check(st, allow=(RBFFD_E_NOCONV,))
+    return dict(outer_iters=s.outer_iters, krylov_mom=s.krylov_mom, krylov_p=s.krylov_p, krylov_b=s.krylov_b,
+                status=s.status, delta=s.delta, eps_steady=s.eps_steady)
+
+
+def rbffd_convdiff_lambda(ctx: Context, ops: Operators, u0: torch.Tensor, rho: float, mu: float,
+                          iters: int = 200) -> float:
+    lam = C.c_double()
+    _check(lib().rbffd_convdiff_lambda(ctx.handle, ops.handle, _ptr(u0), rho, mu, iters, C.byref(lam), _stream()))
+    return lam.value

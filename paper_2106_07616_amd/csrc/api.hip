@@ -1,0 +1,330 @@
+// C ABI entry points, context and error handling.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace rbffd {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return (e == hipErrorOutOfMemory) ? RBFFD_E_OOM : RBFFD_E_DEVICE;
+}
+
+int dev_alloc(rbffd_ctx *ctx, void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) return RBFFD_OK;
+    if (ctx->budget && ctx->in_use + bytes > ctx->budget)
+        return fail(RBFFD_E_OOM, "allocation of " + std::to_string(bytes) +
+                                     " bytes exceeds the context's HBM budget");
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_fail(e, "hipMalloc");
+    }
+    ctx->in_use += bytes;
+    return RBFFD_OK;
+}
+
+void dev_free(rbffd_ctx *ctx, void *p, size_t bytes)
+{
+    if (!p) return;
+    (void)hipFree(p);
+    if (ctx) ctx->in_use -= bytes;
+}
+
+int workspace(rbffd_ctx *ctx, int slot, size_t bytes, void **p)
+{
+    Buffer &b = ctx->ws[slot];
+    if (b.bytes < bytes) {
+        size_t grow = bytes + bytes / 4;
+        if (slot == WS_HOST_PINNED) {
+            if (b.ptr) (void)hipHostFree(b.ptr);
+            b.ptr = nullptr;
+            b.bytes = 0;
+            RB_HIP(hipHostMalloc(&b.ptr, grow, hipHostMallocDefault));
+        } else {
+            if (b.ptr) {
+                RB_HIP(hipDeviceSynchronize());
+                dev_free(ctx, b.ptr, b.bytes);
+            }
+            b.ptr = nullptr;
+            b.bytes = 0;
+            RB_CHECK(dev_alloc(ctx, &b.ptr, grow));
+        }
+        b.bytes = grow;
+    }
+    *p = b.ptr;
+    return RBFFD_OK;
+}
+
+int host_scratch(rbffd_ctx *ctx, size_t off, size_t bytes, void **p)
+{
+    if (off + bytes > kHostBytes) return fail(RBFFD_E_ARG, "host staging request too large");
+    char *base = nullptr;
+    RB_CHECK(workspace(ctx, WS_HOST_PINNED, kHostBytes, (void **)&base));
+    *p = base + off;
+    return RBFFD_OK;
+}
+
+static int check_cloud(const rbffd_cloud *c)
+{
+    if (!c) return fail(RBFFD_E_ARG, "cloud is NULL");
+    if (c->dim != 2 && c->dim != 3) return fail(RBFFD_E_ARG, "dim must be 2 or 3");
+    if (c->n < 1 || c->n >= (int64_t(1) << 31)) return fail(RBFFD_E_ARG, "n out of range");
+    if (!c->xyz) return fail(RBFFD_E_ARG, "cloud.xyz is NULL");
+    return RBFFD_OK;
+}
+
+static int binom(int a, int b)
+{
+    long r = 1;
+    for (int i = 1; i <= b; ++i) r = r * (a - b + i) / i;
+    return (int)r;
+}
+
+static int resolve_sizes(int dim, const rbffd_stencil_opts *o, int *q, int *m, int *R)
+{
+    if (!o) return fail(RBFFD_E_ARG, "stencil options are NULL");
+    if (dim != 2 && dim != 3) return fail(RBFFD_E_ARG, "dim must be 2 or 3");
+    if (o->phs_power != 3 && o->phs_power != 5) return fail(RBFFD_E_ARG, "phs_power must be 3 or 5");
+    if (o->poly_degree < 0 || o->poly_degree > 6) return fail(RBFFD_E_ARG, "poly_degree must be 0..6");
+    int mm = binom(o->poly_degree + dim, dim);
+    int qq = o->q ? o->q : 2 * mm;
+    if (qq <= mm) return fail(RBFFD_E_ARG, "cloud size q must exceed the monomial count m");
+    if (qq > kMaxQ) return fail(RBFFD_E_ARG, "cloud size q exceeds 128");
+    *q = qq;
+    *m = mm;
+    *R = dim + 1;
+    return RBFFD_OK;
+}
+
+}  // namespace rbffd
+
+using namespace rbffd;
+
+extern "C" {
+
+const char *rbffd_last_error(void) { return g_last_error.c_str(); }
+
+int rbffd_ctx_create(rbffd_ctx **ctx, int hip_device, size_t hbm_budget_bytes)
+{
+    if (!ctx) return fail(RBFFD_E_ARG, "ctx is NULL");
+    *ctx = nullptr;
+    int ndev = 0;
+    RB_HIP(hipGetDeviceCount(&ndev));
+    if (hip_device < 0 || hip_device >= ndev) return fail(RBFFD_E_ARG, "no such HIP device");
+    RB_HIP(hipSetDevice(hip_device));
+    rbffd_ctx *c = new (std::nothrow) rbffd_ctx();
+    if (!c) return fail(RBFFD_E_OOM, "host allocation failed");
+    c->device = hip_device;
+    c->budget = hbm_budget_bytes;
+    *ctx = c;
+    g_last_error.clear();
+    return RBFFD_OK;
+}
+
+int rbffd_ctx_destroy(rbffd_ctx *ctx)
+{
+    if (!ctx) return RBFFD_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (int s = 0; s < WS_COUNT; ++s) {
+        if (!ctx->ws[s].ptr) continue;
+        if (s == WS_HOST_PINNED)
+            (void)hipHostFree(ctx->ws[s].ptr);
+        else
+            dev_free(ctx, ctx->ws[s].ptr, ctx->ws[s].bytes);
+    }
+    delete ctx;
+    return RBFFD_OK;
+}
+
+size_t rbffd_ctx_bytes_in_use(const rbffd_ctx *ctx) { return ctx ? ctx->in_use : 0; }
+
+int rbffd_stencil_sizes(int dim, const rbffd_stencil_opts *opts, int *q, int *m, int *R)
+{
+    int qq, mm, rr;
+    RB_CHECK(resolve_sizes(dim, opts, &qq, &mm, &rr));
+    if (q) *q = qq;
+    if (m) *m = mm;
+    if (R) *R = rr;
+    return RBFFD_OK;
+}
+
+int rbffd_build_stencils(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_stencil_opts *opts,
+                         int32_t *nbr, double *w, int64_t *bad_point, void *hip_stream)
+{
+    if (!ctx) return fail(RBFFD_E_ARG, "ctx is NULL");
+    RB_CHECK(check_cloud(cloud));
+    int q, m, R;
+    RB_CHECK(resolve_sizes(cloud->dim, opts, &q, &m, &R));
+    if (q > cloud->n) return fail(RBFFD_E_ARG, "cloud size q exceeds the number of points");
+    if (!nbr || !w) return fail(RBFFD_E_ARG, "nbr or w is NULL");
+    if (q + m > 64) return fail(RBFFD_E_ARG, "collocation systems larger than 64 (q + m) are not supported");
+    RB_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    RB_CHECK(launch_knn(ctx, cloud->dim, cloud->n, cloud->xyz, q, nbr, s));
+    int64_t *bad_dev = nullptr;
+    RB_CHECK(workspace(ctx, WS_MISC, sizeof(int64_t), (void **)&bad_dev));
+    RB_CHECK(launch_weights(ctx, cloud->dim, cloud->n, cloud->xyz, q, nbr, opts->poly_degree,
+                            opts->phs_power, w, bad_dev, s));
+    int64_t *hb = nullptr;
+    RB_CHECK(host_scratch(ctx, kHostMisc, sizeof(int64_t), (void **)&hb));
+    RB_HIP(hipMemcpyAsync(hb, bad_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    RB_HIP(hipStreamSynchronize(s));
+    int64_t bad = (*hb == INT64_MAX) ? -1 : *hb;
+    if (bad_point) *bad_point = bad;
+    if (bad >= 0) return fail(RBFFD_E_SINGULAR, "singular collocation system at point " + std::to_string(bad));
+    return RBFFD_OK;
+}
+
+int rbffd_assemble(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_stencil_opts *opts,
+                   const int32_t *nbr, const double *w, int precision, rbffd_ops **out,
+                   void *hip_stream)
+{
+    if (!ctx || !out) return fail(RBFFD_E_ARG, "ctx or out is NULL");
+    *out = nullptr;
+    RB_CHECK(check_cloud(cloud));
+    if (!cloud->kind || !cloud->normal) return fail(RBFFD_E_ARG, "cloud.kind or cloud.normal is NULL");
+    if (cloud->pin < -1 || cloud->pin >= cloud->n) return fail(RBFFD_E_ARG, "pin out of range");
+    if (precision != RBFFD_FP64 && precision != RBFFD_FP32_IR) return fail(RBFFD_E_ARG, "unknown precision");
+    int q, m, R;
+    RB_CHECK(resolve_sizes(cloud->dim, opts, &q, &m, &R));
+    if (q > cloud->n) return fail(RBFFD_E_ARG, "cloud size q exceeds the number of points");
+    if (!nbr || !w) return fail(RBFFD_E_ARG, "nbr or w is NULL");
+    RB_HIP(hipSetDevice(ctx->device));
+    rbffd_ops *ops = new (std::nothrow) rbffd_ops();
+    if (!ops) return fail(RBFFD_E_OOM, "host allocation failed");
+    int st = assemble_ops(ctx, cloud, q, opts->poly_degree, opts->phs_power, nbr, w, precision, ops,
+                          (hipStream_t)hip_stream);
+    if (st != RBFFD_OK) {
+        std::string msg = g_last_error;
+        rbffd_ops_free(ops);
+        return fail(st, msg);
+    }
+    *out = ops;
+    return RBFFD_OK;
+}
+
+int rbffd_ops_free(rbffd_ops *ops)
+{
+    if (!ops) return RBFFD_OK;
+    rbffd_ctx *ctx = ops->ctx;
+    if (ctx) (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    void *ptrs[] = {ops->kind, ops->normal, ops->col, ops->val, ops->pval, ops->pdinv, ops->pval32,
+                    ops->pdinv32, ops->mval, ops->mdinv, ops->mval32, ops->mdinv32, ops->bidx,
+                    ops->bpos, ops->gcol, ops->gval, ops->gdinv};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (ctx) ctx->in_use -= ops->bytes;
+    delete ops;
+    return RBFFD_OK;
+}
+
+int rbffd_ops_info(const rbffd_ops *ops, int64_t *n, int *q, int *dim, int64_t *n_boundary)
+{
+    if (!ops) return fail(RBFFD_E_ARG, "ops is NULL");
+    if (n) *n = ops->n;
+    if (q) *q = ops->q;
+    if (dim) *dim = ops->dim;
+    if (n_boundary) *n_boundary = ops->nb;
+    return RBFFD_OK;
+}
+
+int rbffd_ops_export_csr(const rbffd_ops *ops, int32_t *col, double *val, void *hip_stream)
+{
+    if (!ops || !col || !val) return fail(RBFFD_E_ARG, "NULL argument");
+    RB_HIP(hipSetDevice(ops->ctx->device));
+    return export_csr(ops, col, val, (hipStream_t)hip_stream);
+}
+
+int rbffd_apply(rbffd_ctx *ctx, const rbffd_ops *ops, int which, const double *x, double *y,
+                void *hip_stream)
+{
+    if (!ctx || !ops || !x || !y) return fail(RBFFD_E_ARG, "NULL argument");
+    if (which < 0 || which > ops->dim + 1) return fail(RBFFD_E_ARG, "operator index out of range");
+    RB_HIP(hipSetDevice(ctx->device));
+    return apply_op(ctx, ops, which, x, y, (hipStream_t)hip_stream);
+}
+
+int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, double *x,
+                  const rbffd_krylov_opts *opts, rbffd_krylov_stats *stats, void *hip_stream)
+{
+    if (!ctx || !ops || !rhs || !x || !opts) return fail(RBFFD_E_ARG, "NULL argument");
+    if (!(opts->tol >= 0.0) || opts->max_iter < 0) return fail(RBFFD_E_ARG, "bad Krylov options");
+    if (opts->precision != RBFFD_FP64 && opts->precision != RBFFD_FP32_IR)
+        return fail(RBFFD_E_ARG, "unknown precision");
+    if (opts->precision == RBFFD_FP32_IR && !ops->pval32)
+        return fail(RBFFD_E_ARG, "operators were assembled without FP32 copies");
+    RB_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    KrylovResult res;
+    int refine = 0;
+    int st;
+    if (opts->precision == RBFFD_FP64)
+        st = bicgstab(ctx, ops->n, ops->q, ops->col, ops->pval, ops->pdinv, 1, rhs, x, opts->tol,
+                      opts->max_iter, &res, s);
+    else
+        st = bicgstab_fp32_ir(ctx, ops->n, ops->q, ops->col, ops->pval, ops->pval32, ops->pdinv32, 1,
+                              rhs, x, opts->tol, opts->max_iter, &res, &refine, s);
+    if (st != RBFFD_OK) return st;
+    double rr = 0.0;
+    RB_CHECK(residual_norms(ctx, ops->n, ops->q, ops->col, ops->pval, 1, rhs, x, &rr, s));
+    if (stats) {
+        stats->iters = res.iters[0];
+        stats->status = res.status[0];
+        stats->refinements = refine;
+        stats->relres = rr;
+    }
+    if (res.status[0] != RBFFD_OK)
+        return fail(res.status[0], "poisson_solve did not converge in " + std::to_string(res.iters[0]) +
+                                       " iterations (relres " + std::to_string(rr) + ")");
+    return RBFFD_OK;
+}
+
+int simple_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, double *p,
+                const double *u_bc, const double *p_bc, const rbffd_step_opts *opts,
+                rbffd_step_stats *stats, void *hip_stream)
+{
+    if (!ctx || !ops || !u || !u_prev || !p || !u_bc || !opts) return fail(RBFFD_E_ARG, "NULL argument");
+    if (ops->n_prescribed > 0 && !p_bc) return fail(RBFFD_E_ARG, "p_bc is required: the cloud has prescribed-pressure points");
+    if (!(opts->rho > 0.0) || !(opts->mu >= 0.0) || !(opts->dt > 0.0) || !std::isfinite(opts->dt))
+        return fail(RBFFD_E_ARG, "rho, mu, dt must be positive and finite");
+    if (!(opts->alpha[0] != 0.0) || !std::isfinite(opts->alpha[1]) || !std::isfinite(opts->alpha[2]))
+        return fail(RBFFD_E_ARG, "bad BDF coefficients");
+    if (opts->max_outer < 1 || opts->max_krylov < 1 || !(opts->tol_krylov >= 0.0) || !(opts->tol_outer >= 0.0))
+        return fail(RBFFD_E_ARG, "bad iteration limits or tolerances");
+    if (opts->precision != RBFFD_FP64 && opts->precision != RBFFD_FP32_IR)
+        return fail(RBFFD_E_ARG, "unknown precision");
+    if (opts->precision == RBFFD_FP32_IR && !ops->pval32)
+        return fail(RBFFD_E_ARG, "operators were assembled without FP32 copies");
+    RB_HIP(hipSetDevice(ctx->device));
+    rbffd_step_stats local{};
+    int st = run_step(ctx, ops, u, u_prev, p, u_bc, p_bc, opts, stats ? stats : &local, (hipStream_t)hip_stream);
+    return st;
+}
+
+int rbffd_convdiff_lambda(rbffd_ctx *ctx, const rbffd_ops *ops, const double *u0, double rho,
+                          double mu, int iters, double *lambda_out, void *hip_stream)
+{
+    if (!ctx || !ops || !u0 || !lambda_out || iters < 1) return fail(RBFFD_E_ARG, "bad argument");
+    RB_HIP(hipSetDevice(ctx->device));
+    return convdiff_lambda(ctx, ops, u0, rho, mu, iters, lambda_out, (hipStream_t)hip_stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,300 @@
+// Assembly of the stored operators (Sec. 2 closing remark: B1 precomputed and
+// kept for the whole run) and of the pressure-correction matrix (Eq. pressure
+// poisson with the boundary conditions of Sec. 3.1).
+//
+// Storage is sliced ELL with exactly q entries per row: each row's columns
+// ascending (the CSR order), entry a of 64 consecutive rows contiguous, so a
+// wavefront streams one 512-byte run of values and a 256-byte run of columns
+// per entry.
+#include <cmath>
+
+#include "internal.h"
+
+namespace rbffd {
+
+namespace {
+
+// One workgroup per 64-row slice: the slice's clouds are staged in LDS, each
+// lane ranks its row's neighbours by index and scatters weights into the slot
+// of that rank.
+__global__ __launch_bounds__(64) void sort_rows(const int32_t *__restrict__ nbr, const double *__restrict__ w,
+                                                int64_t n, int q, int R, int32_t *__restrict__ col,
+                                                double *__restrict__ val, int64_t vstride)
+{
+    extern __shared__ int32_t sh[];   // [64][q+1]
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int t = threadIdx.x;
+    const int64_t rows = min((int64_t)64, n - i0);
+    for (int64_t e = t; e < rows * q; e += 64) {
+        const int64_t r = e / q, a = e % q;
+        sh[r * (q + 1) + a] = nbr[(i0 + r) * q + a];
+    }
+    __syncthreads();
+    const int64_t i = i0 + t;
+    if (t >= rows) {
+        for (int a = 0; a < q; ++a) {
+            const int64_t slot = ell_at(i, a, q);
+            col[slot] = 0;
+            for (int r = 0; r < R; ++r) val[r * vstride + slot] = 0.0;
+        }
+        return;
+    }
+    const int32_t *mine = sh + t * (q + 1);
+    for (int a = 0; a < q; ++a) {
+        const int32_t c = mine[a];
+        int rank = 0;
+        for (int b = 0; b < q; ++b) rank += (mine[b] < c);
+        const int64_t slot = ell_at(i, rank, q);
+        col[slot] = c;
+        for (int r = 0; r < R; ++r) val[r * vstride + slot] = w[(int64_t)r * n * q + i * q + a];
+    }
+}
+
+// Pressure-correction matrix rows and its Jacobi diagonal.
+template <int DIM>
+__global__ void poisson_rows(const int32_t *__restrict__ col, const double *__restrict__ val, int64_t vstride,
+                             const uint8_t *__restrict__ kind, const double *__restrict__ normal, int64_t pin,
+                             int64_t n, int q, double *__restrict__ pval, double *__restrict__ pdinv)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= pad64(n)) return;
+    if (i >= n) {
+        for (int a = 0; a < q; ++a) pval[ell_at(i, a, q)] = 0.0;
+        pdinv[i] = 0.0;
+        return;
+    }
+    const int kd = kind[i];
+    double nv[3] = {0, 0, 0};
+    if (kd != RBFFD_INTERIOR)
+        for (int d = 0; d < DIM; ++d) nv[d] = normal[i * DIM + d];
+    double diag = 0.0;
+    for (int a = 0; a < q; ++a) {
+        const int64_t slot = ell_at(i, a, q);
+        const int32_t c = col[slot];
+        double v;
+        if (i == pin || kd == RBFFD_PRESCRIBED_PRESSURE) {
+            v = (c == i) ? 1.0 : 0.0;
+        } else if (kd == RBFFD_INTERIOR) {
+            v = val[DIM * vstride + slot];
+        } else {
+            v = nv[0] * val[slot] + nv[1] * val[vstride + slot];
+            if (DIM == 3) v = v + nv[2] * val[2 * vstride + slot];
+        }
+        pval[slot] = v;
+        if (c == i) diag += v;
+    }
+    pdinv[i] = (diag != 0.0) ? 1.0 / diag : 1.0;
+}
+
+__global__ void boundary_flags(const uint8_t *__restrict__ kind, int64_t n, int32_t *__restrict__ flag,
+                               int32_t *__restrict__ flag2)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) {
+        flag[i] = kind[i] == RBFFD_DIRICHLET;
+        flag2[i] = kind[i] == RBFFD_PRESCRIBED_PRESSURE;
+    }
+}
+
+__global__ void boundary_index(const uint8_t *__restrict__ kind, const int32_t *__restrict__ pos, int64_t n,
+                               int32_t *__restrict__ bidx, int32_t *__restrict__ bpos)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (kind[i] == RBFFD_DIRICHLET) {
+        bidx[pos[i]] = (int32_t)i;
+        bpos[i] = pos[i];
+    } else {
+        bpos[i] = -1;
+    }
+}
+
+// Block of the normal-derivative rows over velocity-Dirichlet points: entries of
+// the other columns are kept as explicit zeros on the row's own (block-local)
+// column, so every row keeps q entries.
+__global__ void boundary_block(const int32_t *__restrict__ col, const double *__restrict__ pval,
+                               const uint8_t *__restrict__ kind, const int32_t *__restrict__ bidx,
+                               const int32_t *__restrict__ bpos, int64_t nb, int q, int32_t *__restrict__ gcol,
+                               double *__restrict__ gval, double *__restrict__ gdinv)
+{
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= pad64(nb)) return;
+    if (b >= nb) {
+        for (int a = 0; a < q; ++a) {
+            gcol[ell_at(b, a, q)] = 0;
+            gval[ell_at(b, a, q)] = 0.0;
+        }
+        gdinv[b] = 0.0;
+        return;
+    }
+    const int64_t i = bidx[b];
+    double diag = 0.0;
+    for (int a = 0; a < q; ++a) {
+        const int64_t si = ell_at(i, a, q), sb = ell_at(b, a, q);
+        const int32_t j = col[si];
+        if (kind[j] == RBFFD_DIRICHLET) {
+            gcol[sb] = bpos[j];
+            gval[sb] = pval[si];
+            if (bpos[j] == b) diag += pval[si];
+        } else {
+            gcol[sb] = (int32_t)b;
+            gval[sb] = 0.0;
+        }
+    }
+    gdinv[b] = (diag != 0.0) ? 1.0 / diag : 1.0;
+}
+
+__global__ void to_fp32(const double *__restrict__ x, float *__restrict__ y, int64_t m)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < m) y[i] = (float)x[i];
+}
+
+__global__ void ell_to_csr(const int32_t *__restrict__ col, const double *__restrict__ val, int64_t vstride,
+                           const double *__restrict__ pval, int64_t n, int q, int R, int32_t *__restrict__ ocol,
+                           double *__restrict__ oval)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n * q) return;
+    const int64_t i = e / q;
+    const int a = (int)(e % q);
+    const int64_t slot = ell_at(i, a, q);
+    ocol[e] = col[slot];
+    for (int r = 0; r < R; ++r) oval[r * n * q + e] = val[r * vstride + slot];
+    oval[(int64_t)R * n * q + e] = pval[slot];
+}
+
+template <typename T>
+int alloc_ops(rbffd_ops *ops, T **p, size_t count)
+{
+    void *v = nullptr;
+    const size_t bytes = sizeof(T) * count;
+    RB_CHECK(dev_alloc(ops->ctx, &v, bytes));
+    // the context charge moves to the operator object
+    ops->bytes += bytes;
+    *p = (T *)v;
+    return RBFFD_OK;
+}
+
+}  // namespace
+
+int assemble_ops(rbffd_ctx *ctx, const rbffd_cloud *cloud, int q, int k, int phs, const int32_t *nbr,
+                 const double *w, int precision, rbffd_ops *ops, hipStream_t s)
+{
+    const int dim = cloud->dim;
+    const int64_t n = cloud->n, npad = pad64(n);
+    ops->ctx = ctx;
+    ops->dim = dim;
+    ops->q = q;
+    ops->R = dim + 1;
+    ops->k = k;
+    ops->phs = phs;
+    ops->n = n;
+    ops->npad = npad;
+    ops->pin = cloud->pin;
+    ops->precision = precision;
+    const int64_t nnz = npad * q;
+    RB_CHECK(alloc_ops(ops, &ops->kind, (size_t)n));
+    RB_CHECK(alloc_ops(ops, &ops->normal, (size_t)n * dim));
+    RB_CHECK(alloc_ops(ops, &ops->col, (size_t)nnz));
+    RB_CHECK(alloc_ops(ops, &ops->val, (size_t)nnz * ops->R));
+    RB_CHECK(alloc_ops(ops, &ops->pval, (size_t)nnz));
+    RB_CHECK(alloc_ops(ops, &ops->pdinv, (size_t)npad));
+    RB_CHECK(alloc_ops(ops, &ops->mval, (size_t)nnz));
+    RB_CHECK(alloc_ops(ops, &ops->mdinv, (size_t)npad * kMaxRhs));
+    RB_HIP(hipMemcpyAsync(ops->kind, cloud->kind, n, hipMemcpyDeviceToDevice, s));
+    RB_HIP(hipMemcpyAsync(ops->normal, cloud->normal, sizeof(double) * n * dim, hipMemcpyDeviceToDevice, s));
+
+    const unsigned nslices = (unsigned)(npad / 64);
+    hipLaunchKernelGGL(sort_rows, dim3(nslices), dim3(64), sizeof(int32_t) * 64 * (q + 1), s, nbr, w, n, q, ops->R,
+                       ops->col, ops->val, nnz);
+    RB_HIP(hipGetLastError());
+    const unsigned gb = (unsigned)((npad + kBlock - 1) / kBlock);
+    if (dim == 2)
+        hipLaunchKernelGGL(poisson_rows<2>, dim3(gb), dim3(kBlock), 0, s, ops->col, ops->val, nnz, ops->kind,
+                           ops->normal, ops->pin, n, q, ops->pval, ops->pdinv);
+    else
+        hipLaunchKernelGGL(poisson_rows<3>, dim3(gb), dim3(kBlock), 0, s, ops->col, ops->val, nnz, ops->kind,
+                           ops->normal, ops->pin, n, q, ops->pval, ops->pdinv);
+    RB_HIP(hipGetLastError());
+
+    // boundary numbering
+    int32_t *flag = nullptr, *pos = nullptr, *flag2 = nullptr, *pos2 = nullptr;
+    const size_t fbytes = sizeof(int32_t) * (4 * n + 2);
+    RB_CHECK(dev_alloc(ctx, (void **)&flag, fbytes));
+    pos = flag + n;
+    flag2 = pos + n + 1;
+    pos2 = flag2 + n;
+    const unsigned gn = (unsigned)((n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(boundary_flags, dim3(gn), dim3(kBlock), 0, s, ops->kind, n, flag, flag2);
+    int st = scan_exclusive(ctx, flag, pos, n, s);
+    if (st == RBFFD_OK) st = scan_exclusive(ctx, flag2, pos2, n, s);
+    int32_t nb32 = 0, np32 = 0;
+    if (st == RBFFD_OK) {
+        hipError_t e = hipMemcpyAsync(&nb32, pos + n, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&np32, pos2 + n, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = hip_fail(e, "boundary count");
+        ops->n_prescribed = np32;
+    }
+    if (st == RBFFD_OK) {
+        ops->nb = nb32;
+        ops->nbpad = pad64(nb32 > 0 ? nb32 : 1);
+        st = alloc_ops(ops, &ops->bidx, (size_t)ops->nbpad);
+        if (st == RBFFD_OK) st = alloc_ops(ops, &ops->bpos, (size_t)n);
+        if (st == RBFFD_OK) st = alloc_ops(ops, &ops->gcol, (size_t)ops->nbpad * q);
+        if (st == RBFFD_OK) st = alloc_ops(ops, &ops->gval, (size_t)ops->nbpad * q);
+        if (st == RBFFD_OK) st = alloc_ops(ops, &ops->gdinv, (size_t)ops->nbpad);
+    }
+    if (st == RBFFD_OK) {
+        hipLaunchKernelGGL(boundary_index, dim3(gn), dim3(kBlock), 0, s, ops->kind, pos, n, ops->bidx, ops->bpos);
+        const unsigned gbb = (unsigned)((ops->nbpad + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(boundary_block, dim3(gbb), dim3(kBlock), 0, s, ops->col, ops->pval, ops->kind, ops->bidx,
+                           ops->bpos, ops->nb, q, ops->gcol, ops->gval, ops->gdinv);
+        if (hipGetLastError() != hipSuccess) st = fail(RBFFD_E_DEVICE, "boundary block launch failed");
+    }
+    (void)hipStreamSynchronize(s);
+    dev_free(ctx, flag, fbytes);
+    RB_CHECK(st);
+
+    if (precision == RBFFD_FP32_IR) {
+        RB_CHECK(alloc_ops(ops, &ops->pval32, (size_t)nnz));
+        RB_CHECK(alloc_ops(ops, &ops->pdinv32, (size_t)npad));
+        RB_CHECK(alloc_ops(ops, &ops->mval32, (size_t)nnz));
+        RB_CHECK(alloc_ops(ops, &ops->mdinv32, (size_t)npad * kMaxRhs));
+        hipLaunchKernelGGL(to_fp32, dim3((unsigned)((nnz + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, ops->pval,
+                           ops->pval32, nnz);
+        hipLaunchKernelGGL(to_fp32, dim3(gb), dim3(kBlock), 0, s, ops->pdinv, ops->pdinv32, npad);
+        RB_HIP(hipGetLastError());
+    }
+    RB_HIP(hipStreamSynchronize(s));
+    return RBFFD_OK;
+}
+
+int launch_to_fp32(const double *x, float *y, int64_t m, hipStream_t s)
+{
+    hipLaunchKernelGGL(to_fp32, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, x, y, m);
+    RB_HIP(hipGetLastError());
+    return RBFFD_OK;
+}
+
+int export_csr(const rbffd_ops *ops, int32_t *col, double *val, hipStream_t s)
+{
+    const int64_t m = ops->n * ops->q;
+    hipLaunchKernelGGL(ell_to_csr, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, ops->col,
+                       ops->val, ops->npad * ops->q, ops->pval, ops->n, ops->q, ops->R, col, val);
+    RB_HIP(hipGetLastError());
+    RB_HIP(hipStreamSynchronize(s));
+    return RBFFD_OK;
+}
+
+int apply_op(rbffd_ctx *ctx, const rbffd_ops *ops, int which, const double *x, double *y, hipStream_t s)
+{
+    (void)ctx;
+    const double *v = (which <= ops->dim) ? ops->val + (int64_t)which * ops->npad * ops->q : ops->pval;
+    RB_CHECK(spmv(ops->n, ops->q, ops->col, v, x, y, s));
+    RB_HIP(hipStreamSynchronize(s));
+    return RBFFD_OK;
+}
+
+}  // namespace rbffd

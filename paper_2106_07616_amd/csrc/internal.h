@@ -1,0 +1,223 @@
+// Internal declarations of the gfx950 PHS-RBF library: context and operator
+// objects, device helpers, kernel launch wrappers. Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <string>
+
+#include "../../include/rbffd.h"
+
+namespace rbffd {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;          // threads per block of the streaming kernels
+constexpr int kMaxBlocks = 2048;     // grid cap of reducing kernels (partials <= this)
+constexpr int kSlice = 64;           // rows per slice of the sliced-ELL layout
+constexpr int kMaxQ = 128;           // largest cloud
+constexpr int kMaxRhs = 3;           // velocity components solved together
+
+// ---------------------------------------------------------------------------
+// error handling
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+#define RB_HIP(call)                                        \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);   \
+    } while (0)
+
+#define RB_CHECK(call)                       \
+    do {                                     \
+        int s_ = (call);                     \
+        if (s_ != RBFFD_OK) return s_;       \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// sliced ELL: row i, entry a lives at ((i / 64) * q + a) * 64 + (i % 64), so a
+// wavefront of 64 consecutive rows reads entry a of all its rows as one
+// contiguous 64-element run. Rows are padded to a multiple of 64; padding rows
+// hold column 0 and value 0.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int64_t ell_at(int64_t i, int a, int q)
+{
+    return ((i >> 6) * (int64_t)q + a) * 64 + (i & 63);
+}
+__host__ __device__ inline int64_t pad64(int64_t n) { return (n + 63) / 64 * 64; }
+
+// ---------------------------------------------------------------------------
+// context: device, HBM budget, workspace buffers grown on demand
+// ---------------------------------------------------------------------------
+struct Buffer {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+enum WorkSlot {
+    WS_KRYLOV = 0,   // FP64 Krylov vectors
+    WS_KRYLOV32,     // FP32 Krylov vectors (inner solves of the refinement)
+    WS_PARTIAL,      // FP64 solve: reduction partials + state records
+    WS_PARTIAL32,    // FP32 solve: reduction partials + state records
+    WS_REFINE,       // refinement residual / correction
+    WS_STEP,         // time-step fields
+    WS_STEP2,        // boundary-pressure solve and step reductions
+    WS_MISC,
+    WS_HOST_PINNED,  // pinned host staging for small read-backs
+    WS_COUNT
+};
+
+// fixed regions of the pinned host staging buffer
+constexpr size_t kHostKrylov = 0;      // Krylov state records
+constexpr size_t kHostRefine = 1024;   // refinement residual norms
+constexpr size_t kHostStep = 2048;     // time-step scalars
+constexpr size_t kHostMisc = 3072;
+constexpr size_t kHostBytes = 4096;
+
+}  // namespace rbffd
+
+struct rbffd_ctx {
+    int device = 0;
+    size_t budget = 0;        // 0 = unlimited
+    size_t in_use = 0;
+    rbffd::Buffer ws[rbffd::WS_COUNT];
+};
+
+namespace rbffd {
+int dev_alloc(rbffd_ctx *ctx, void **p, size_t bytes);
+void dev_free(rbffd_ctx *ctx, void *p, size_t bytes);
+// workspace slot of at least `bytes` (contents are not preserved on growth)
+int workspace(rbffd_ctx *ctx, int slot, size_t bytes, void **p);
+// region [off, off + bytes) of the pinned host staging buffer
+int host_scratch(rbffd_ctx *ctx, size_t off, size_t bytes, void **p);
+}  // namespace rbffd
+
+// Operators of one cloud, resident on the device.
+struct rbffd_ops {
+    rbffd_ctx *ctx = nullptr;
+    int dim = 2, q = 0, R = 3, k = 0, phs = 3;
+    int64_t n = 0, npad = 0, pin = 0;
+    int64_t nb = 0, nbpad = 0;          // velocity-Dirichlet boundary points (normal momentum block)
+    int64_t n_prescribed = 0;           // prescribed-pressure points
+    int precision = RBFFD_FP64;
+    size_t bytes = 0;                   // device bytes charged to ctx
+    // cloud copies
+    uint8_t *kind = nullptr;            // [n]
+    double *normal = nullptr;           // [n][dim]
+    // sliced-ELL operators
+    int32_t *col = nullptr;             // [npad*q]
+    double *val = nullptr;              // [R][npad*q]  d/dx, d/dy, (d/dz), Laplacian
+    double *pval = nullptr;             // [npad*q]     pressure-correction matrix
+    double *pdinv = nullptr;            // [npad]       1 / diag(P)
+    float *pval32 = nullptr;            // [npad*q]     FP32 copy (RBFFD_FP32_IR)
+    float *pdinv32 = nullptr;           // [npad]
+    double *mval = nullptr;             // [npad*q]     momentum matrix (rebuilt per outer iteration)
+    double *mdinv = nullptr;            // [npad]
+    float *mval32 = nullptr;            // [npad*q]
+    float *mdinv32 = nullptr;           // [npad]
+    // block of the normal-derivative rows over velocity-Dirichlet points
+    int32_t *bidx = nullptr;            // [nb]   global row of block row b
+    int32_t *bpos = nullptr;            // [n]    block row of global row i, or -1
+    int32_t *gcol = nullptr;            // [nbpad*q] sliced-ELL, boundary-local columns
+    double *gval = nullptr;             // [nbpad*q]
+    double *gdinv = nullptr;            // [nbpad]
+};
+
+namespace rbffd {
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Fixed-order block sum (blockDim.x == kBlock): identical result in every block
+// for identical inputs. `lds` holds kBlock/64 doubles.
+__device__ inline double block_sum(double v, double *lds)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) lds[w] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) t += lds[i];
+    return t;
+}
+
+// Sum of np partials in a fixed order, computed identically by every block.
+__device__ inline double sum_partials(const double *part, int np, double *lds)
+{
+    double v = 0.0;
+    for (int i = threadIdx.x; i < np; i += kBlock) v += part[i];
+    return block_sum(v, lds);
+}
+
+// XCD-aware block order: consecutive logical blocks land on the same XCD (the
+// hardware deals blocks round-robin over 8 XCDs), so neighbouring rows share an L2.
+__device__ inline int xcd_block(int nblocks)
+{
+    const int b = blockIdx.x;
+    const int per = nblocks / 8;
+    if (per == 0 || (nblocks & 7)) return b;
+    return (b & 7) * per + (b >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers (defined in the .hip files)
+// ---------------------------------------------------------------------------
+int launch_knn(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q, int32_t *nbr,
+               hipStream_t s);
+int launch_weights(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q, const int32_t *nbr,
+                   int k, int phs, double *w, int64_t *bad_dev, hipStream_t s);
+int assemble_ops(rbffd_ctx *ctx, const rbffd_cloud *cloud, int q, int k, int phs,
+                 const int32_t *nbr, const double *w, int precision, rbffd_ops *ops, hipStream_t s);
+int export_csr(const rbffd_ops *ops, int32_t *col, double *val, hipStream_t s);
+int apply_op(rbffd_ctx *ctx, const rbffd_ops *ops, int which, const double *x, double *y,
+             hipStream_t s);
+
+int launch_to_fp32(const double *x, float *y, int64_t m, hipStream_t s);
+
+// exclusive scan of int32 counts (n + 1 outputs: out[n] = total)
+int scan_exclusive(rbffd_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, hipStream_t s);
+
+// Krylov: BiCGSTAB on a sliced-ELL matrix with nrhs right-hand sides
+struct KrylovResult {
+    int iters[kMaxRhs] = {0, 0, 0};
+    int status[kMaxRhs] = {0, 0, 0};
+    double relres[kMaxRhs] = {0, 0, 0};
+};
+int bicgstab(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val,
+             const double *dinv, int nrhs, const double *b, double *x, double tol, int max_iter,
+             KrylovResult *res, hipStream_t s);
+int bicgstab_fp32_ir(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val,
+                     const float *val32, const float *dinv32, int nrhs, const double *b, double *x,
+                     double tol, int max_iter, KrylovResult *res, int *refinements, hipStream_t s);
+int spmv(int64_t n, int q, const int32_t *col, const double *val, const double *x, double *y,
+         hipStream_t s);
+int residual_norms(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val,
+                   int nrhs, const double *b, const double *x, double *relres_out, hipStream_t s);
+
+int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, double *p,
+             const double *u_bc, const double *p_bc, const rbffd_step_opts *o, rbffd_step_stats *st,
+             hipStream_t s);
+int convdiff_lambda(rbffd_ctx *ctx, const rbffd_ops *ops, const double *u0, double rho, double mu,
+                    int iters, double *lambda, hipStream_t s);
+
+}  // namespace rbffd

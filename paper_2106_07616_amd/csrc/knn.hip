@@ -1,0 +1,454 @@
+// Cloud selection (Sec. 2: a cloud of neighbouring points; Sec. 3.1: one-sided
+// clouds at boundaries): the q nearest points of every point, itself included,
+// in the total order (squared distance, index).
+//
+// Points are binned into a uniform grid (a few points per cell) with a count
+// sort. One wavefront serves one query: it visits shells of cells of growing
+// Chebyshev radius around the query's cell, keeps the q best keys in LDS, and
+// stops as soon as the q-th key is closer than every point the visited box
+// could have missed. Because the selection is by a total order on exactly
+// computed keys, the result does not depend on visiting order.
+#include <cfloat>
+#include <cmath>
+
+#include "internal.h"
+
+namespace rbffd {
+
+namespace {
+
+struct Grid {
+    double lo[3];
+    double cs[3];
+    double inv[3];
+    int nc[3];
+};
+
+// Squared distance without contraction: ((dx*dx + dy*dy) + dz*dz).
+template <int DIM>
+__device__ inline double sqdist_exact(const double *a, const double *b)
+{
+#pragma clang fp contract(off)
+    double dx = b[0] - a[0];
+    double dy = b[1] - a[1];
+    double d2 = dx * dx + dy * dy;
+    if (DIM == 3) {
+        double dz = b[2] - a[2];
+        d2 = d2 + dz * dz;
+    }
+    return d2;
+}
+
+__device__ inline bool key_less(double d1, int i1, double d2, int i2)
+{
+    return d1 < d2 || (d1 == d2 && i1 < i2);
+}
+
+template <int DIM>
+__device__ inline int cell_coord(double x, const Grid &g, int d)
+{
+    double t = floor((x - g.lo[d]) * g.inv[d]);
+    int c = (t < 0.0) ? 0 : (t > (double)(g.nc[d] - 1) ? g.nc[d] - 1 : (int)t);
+    return c;
+}
+
+template <int DIM>
+__device__ inline int64_t cell_linear(const int *c, const Grid &g)
+{
+    int64_t id = c[0] + (int64_t)g.nc[0] * c[1];
+    if (DIM == 3) id += (int64_t)g.nc[0] * g.nc[1] * c[2];
+    return id;
+}
+
+// ---- bounding box --------------------------------------------------------
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void bbox_partial(const double *__restrict__ xyz, int64_t n,
+                                                       double *__restrict__ part)
+{
+    __shared__ double lds[6][kBlock / 64];
+    double mn[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, mx[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        for (int d = 0; d < DIM; ++d) {
+            double v = xyz[i * DIM + d];
+            mn[d] = fmin(mn[d], v);
+            mx[d] = fmax(mx[d], v);
+        }
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    for (int d = 0; d < DIM; ++d) {
+        double a = mn[d], b = mx[d];
+        for (int o = 32; o > 0; o >>= 1) {
+            a = fmin(a, __shfl_xor(a, o, 64));
+            b = fmax(b, __shfl_xor(b, o, 64));
+        }
+        if (l == 0) {
+            lds[d][w] = a;
+            lds[3 + d][w] = b;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const bool isMin = threadIdx.x < 3;
+        double r = isMin ? DBL_MAX : -DBL_MAX;
+        for (int j = 0; j < kBlock / 64; ++j) r = isMin ? fmin(r, lds[threadIdx.x][j]) : fmax(r, lds[threadIdx.x][j]);
+        part[blockIdx.x * 6 + threadIdx.x] = r;
+    }
+}
+
+__global__ void bbox_final(const double *__restrict__ part, int np, double *__restrict__ out)
+{
+    if (threadIdx.x < 6) {
+        const bool isMin = threadIdx.x < 3;
+        double r = isMin ? DBL_MAX : -DBL_MAX;
+        for (int j = 0; j < np; ++j) r = isMin ? fmin(r, part[j * 6 + threadIdx.x]) : fmax(r, part[j * 6 + threadIdx.x]);
+        out[threadIdx.x] = r;
+    }
+}
+
+// ---- binning ------------------------------------------------------------
+template <int DIM>
+__global__ void cell_count(const double *__restrict__ xyz, int64_t n, Grid g, int32_t *__restrict__ cell_of,
+                           int32_t *__restrict__ count)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) c[d] = cell_coord<DIM>(xyz[i * DIM + d], g, d);
+    int32_t id = (int32_t)cell_linear<DIM>(c, g);
+    cell_of[i] = id;
+    atomicAdd(&count[id], 1);
+}
+
+template <int DIM>
+__global__ void cell_scatter(const double *__restrict__ xyz, int64_t n, const int32_t *__restrict__ cell_of,
+                             const int32_t *__restrict__ start, int32_t *__restrict__ cursor,
+                             int32_t *__restrict__ sidx, double *__restrict__ sxyz)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t c = cell_of[i];
+    int32_t pos = start[c] + atomicAdd(&cursor[c], 1);
+    sidx[pos] = (int32_t)i;
+    for (int d = 0; d < DIM; ++d) sxyz[(int64_t)pos * DIM + d] = xyz[i * DIM + d];
+}
+
+// ---- query ---------------------------------------------------------------
+template <int DIM>
+struct QueryState {
+    double Ld[2][kMaxQ];
+    int Li[2][kMaxQ];
+    double Bd[64];
+    int Bi[64];
+};
+
+// Merge the batch (nbat keys) into the sorted list (cnt keys) keeping the q
+// smallest; every key lands at its rank in the union.
+template <int DIM>
+__device__ inline void merge_batch(QueryState<DIM> &S, int &cur, int &cnt, int nbat, int q)
+{
+    __syncthreads();
+    const int lane = threadIdx.x;
+    const int nxt = cur ^ 1;
+    if (lane < nbat) {
+        const double bd = S.Bd[lane];
+        const int bi = S.Bi[lane];
+        int rb = 0;
+        for (int m = 0; m < nbat; ++m) rb += key_less(S.Bd[m], S.Bi[m], bd, bi);
+        int lo = 0, hi = cnt;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (key_less(S.Ld[cur][mid], S.Li[cur][mid], bd, bi))
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        const int pos = lo + rb;
+        if (pos < q) {
+            S.Ld[nxt][pos] = bd;
+            S.Li[nxt][pos] = bi;
+        }
+    }
+    for (int j = lane; j < cnt; j += 64) {
+        const double ld = S.Ld[cur][j];
+        const int li = S.Li[cur][j];
+        int rb = 0;
+        for (int m = 0; m < nbat; ++m) rb += key_less(S.Bd[m], S.Bi[m], ld, li);
+        const int pos = j + rb;
+        if (pos < q) {
+            S.Ld[nxt][pos] = ld;
+            S.Li[nxt][pos] = li;
+        }
+    }
+    cnt = min(q, cnt + nbat);
+    cur = nxt;
+    __syncthreads();
+}
+
+template <int DIM>
+__device__ inline void scan_range(QueryState<DIM> &S, const double *xq, int32_t start, int32_t end,
+                                  const int32_t *__restrict__ sidx, const double *__restrict__ sxyz,
+                                  int &cur, int &cnt, int &nbat, int q)
+{
+    const int lane = threadIdx.x;
+    for (int32_t base = start; base < end; base += 64) {
+        const int32_t pidx = base + lane;
+        const bool valid = pidx < end;
+        double d2 = DBL_MAX;
+        int id = 0x7fffffff;
+        if (valid) {
+            id = sidx[pidx];
+            double pc[3];
+            for (int d = 0; d < DIM; ++d) pc[d] = sxyz[(int64_t)pidx * DIM + d];
+            d2 = sqdist_exact<DIM>(xq, pc);
+        }
+        bool cand = valid && (cnt < q || key_less(d2, id, S.Ld[cur][q - 1], S.Li[cur][q - 1]));
+        uint64_t mask = __ballot(cand);
+        int nnew = __popcll(mask);
+        if (nnew == 0) continue;
+        if (nbat + nnew > 64) {
+            merge_batch<DIM>(S, cur, cnt, nbat, q);
+            nbat = 0;
+        }
+        if (cand) {
+            int pos = nbat + __popcll(mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+            S.Bd[pos] = d2;
+            S.Bi[pos] = id;
+        }
+        nbat += nnew;
+        __syncthreads();
+    }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(64) void knn_query(const double *__restrict__ xyz, const int32_t *__restrict__ cstart,
+                                                const int32_t *__restrict__ sidx, const double *__restrict__ sxyz,
+                                                Grid g, int64_t n, int q, int32_t *__restrict__ nbr)
+{
+    __shared__ QueryState<DIM> S;
+    const int64_t i = blockIdx.x;
+    if (i >= n) return;
+    double xq[3] = {0.0, 0.0, 0.0};
+    int c[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) {
+        xq[d] = xyz[i * DIM + d];
+        c[d] = cell_coord<DIM>(xq[d], g, d);
+    }
+    double csmin = g.cs[0];
+    for (int d = 1; d < DIM; ++d) csmin = fmin(csmin, g.cs[d]);
+    int cur = 0, cnt = 0, nbat = 0;
+    for (int R = 0;; ++R) {
+        // rows of the shell at Chebyshev radius R: (dy) in 2D, (dy, dz) in 3D
+        const int zlo = (DIM == 3) ? -R : 0, zhi = (DIM == 3) ? R : 0;
+        for (int dz = zlo; dz <= zhi; ++dz) {
+            const int cz = c[2] + dz;
+            if (DIM == 3 && (cz < 0 || cz >= g.nc[2])) continue;
+            for (int dy = -R; dy <= R; ++dy) {
+                const int cy = c[1] + dy;
+                if (cy < 0 || cy >= g.nc[1]) continue;
+                const int64_t rowbase = (int64_t)g.nc[0] * cy + (DIM == 3 ? (int64_t)g.nc[0] * g.nc[1] * cz : 0);
+                const bool full = (abs(dy) == R) || (DIM == 3 && abs(dz) == R);
+                if (full) {
+                    const int xa = max(c[0] - R, 0), xb = min(c[0] + R, g.nc[0] - 1);
+                    scan_range<DIM>(S, xq, cstart[rowbase + xa], cstart[rowbase + xb + 1], sidx, sxyz, cur, cnt, nbat, q);
+                } else {
+                    if (c[0] - R >= 0)
+                        scan_range<DIM>(S, xq, cstart[rowbase + c[0] - R], cstart[rowbase + c[0] - R + 1], sidx, sxyz,
+                                        cur, cnt, nbat, q);
+                    if (c[0] + R < g.nc[0])
+                        scan_range<DIM>(S, xq, cstart[rowbase + c[0] + R], cstart[rowbase + c[0] + R + 1], sidx, sxyz,
+                                        cur, cnt, nbat, q);
+                }
+            }
+        }
+        if (nbat > 0) {
+            merge_batch<DIM>(S, cur, cnt, nbat, q);
+            nbat = 0;
+        }
+        // Stop when the box of radius R covers the grid, or when the q-th key is
+        // closer than the nearest face of the box that has points beyond it.
+        bool covers = true;
+        double rg = DBL_MAX;
+        for (int d = 0; d < DIM; ++d) {
+            if (c[d] - R > 0) {
+                covers = false;
+                rg = fmin(rg, xq[d] - (g.lo[d] + (double)(c[d] - R) * g.cs[d]));
+            }
+            if (c[d] + R < g.nc[d] - 1) {
+                covers = false;
+                rg = fmin(rg, (g.lo[d] + (double)(c[d] + R + 1) * g.cs[d]) - xq[d]);
+            }
+        }
+        if (covers) break;
+        if (cnt == q) {
+            rg -= 1e-7 * csmin;   // margin against rounding of the binning
+            if (rg > 0.0 && S.Ld[cur][q - 1] < rg * rg) break;
+        }
+    }
+    for (int a = threadIdx.x; a < q; a += 64) nbr[i * q + a] = S.Li[cur][a];
+}
+
+}  // namespace
+
+// ---- exclusive scan (int32) ------------------------------------------------
+namespace {
+constexpr int kScanPer = 4;
+constexpr int kScanTile = kBlock * kScanPer;
+
+__global__ __launch_bounds__(kBlock) void scan_tile(const int32_t *__restrict__ in, int32_t *__restrict__ out,
+                                                    int64_t n, int32_t *__restrict__ tile_sum)
+{
+    __shared__ int32_t wsum[kBlock / 64];
+    const int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * kScanPer;
+    int32_t v[kScanPer];
+    int32_t t = 0;
+    for (int j = 0; j < kScanPer; ++j) {
+        v[j] = (base + j < n) ? in[base + j] : 0;
+        t += v[j];
+    }
+    // inclusive wave scan of per-thread totals
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int32_t incl = t;
+    for (int o = 1; o < 64; o <<= 1) {
+        int32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int32_t woff = 0;
+    for (int j = 0; j < w; ++j) woff += wsum[j];
+    int32_t run = woff + incl - t;
+    for (int j = 0; j < kScanPer; ++j) {
+        if (base + j < n) out[base + j] = run;
+        run += v[j];
+    }
+    if (threadIdx.x == kBlock - 1) tile_sum[blockIdx.x] = woff + incl;
+}
+
+__global__ void scan_add(int32_t *__restrict__ out, int64_t n, const int32_t *__restrict__ tile_off)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] += tile_off[i / kScanTile];
+}
+}  // namespace
+
+int scan_exclusive(rbffd_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, hipStream_t s)
+{
+    // out[0..n) = exclusive scan, out[n] = total
+    const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+    int32_t *tsum = nullptr, *toff = nullptr;
+    RB_CHECK(dev_alloc(ctx, (void **)&tsum, sizeof(int32_t) * (tiles + 1) * 2));
+    toff = tsum + tiles + 1;
+    hipLaunchKernelGGL(scan_tile, dim3((unsigned)tiles), dim3(kBlock), 0, s, in, out, n, tsum);
+    RB_HIP(hipGetLastError());
+    int st = RBFFD_OK;
+    if (tiles > 1) {
+        st = scan_exclusive(ctx, tsum, toff, tiles, s);
+        if (st == RBFFD_OK) {
+            hipLaunchKernelGGL(scan_add, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, out, n, toff);
+            if (hipGetLastError() != hipSuccess) st = fail(RBFFD_E_DEVICE, "scan_add launch failed");
+        }
+        if (st == RBFFD_OK)
+            (void)hipMemcpyAsync(out + n, toff + tiles, sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+    } else {
+        (void)hipMemcpyAsync(out + n, tsum, sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+    }
+    (void)hipStreamSynchronize(s);
+    dev_free(ctx, tsum, sizeof(int32_t) * (tiles + 1) * 2);
+    return st;
+}
+
+int launch_knn(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q, int32_t *nbr, hipStream_t s)
+{
+    // bounding box
+    const int nbb = (int)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock);
+    double *part = nullptr;
+    RB_CHECK(dev_alloc(ctx, (void **)&part, sizeof(double) * (nbb * 6 + 6)));
+    double *bb = part + nbb * 6;
+    if (dim == 2)
+        hipLaunchKernelGGL(bbox_partial<2>, dim3(nbb), dim3(kBlock), 0, s, xyz, n, part);
+    else
+        hipLaunchKernelGGL(bbox_partial<3>, dim3(nbb), dim3(kBlock), 0, s, xyz, n, part);
+    hipLaunchKernelGGL(bbox_final, dim3(1), dim3(64), 0, s, part, nbb, bb);
+    double hb[6];
+    hipError_t e = hipMemcpyAsync(hb, bb, sizeof(hb), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dev_free(ctx, part, sizeof(double) * (nbb * 6 + 6));
+    if (e != hipSuccess) return hip_fail(e, "bounding box");
+    for (int d = 0; d < dim; ++d)
+        if (!std::isfinite(hb[d]) || !std::isfinite(hb[3 + d])) return fail(RBFFD_E_ARG, "non-finite coordinates");
+
+    // grid: about q/2 (2D) or q/3 (3D) points per cell
+    Grid g{};
+    double span[3] = {1, 1, 1}, vol = 1.0;
+    int live = 0;
+    for (int d = 0; d < dim; ++d) {
+        span[d] = hb[3 + d] - hb[d];
+        if (span[d] > 0) {
+            vol *= span[d];
+            ++live;
+        }
+    }
+    const double target = std::max(2.0, dim == 2 ? q / 2.0 : q / 3.0);
+    const double hc = live ? std::pow(target * vol / (double)n, 1.0 / live) : 1.0;
+    int64_t ncell = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (d >= dim || !(span[d] > 0)) {
+            g.lo[d] = (d < dim) ? hb[d] : 0.0;
+            g.nc[d] = 1;
+            g.cs[d] = 1.0;
+            g.inv[d] = 0.0;
+            continue;
+        }
+        int64_t k = (int64_t)std::floor(span[d] / hc);
+        k = std::max<int64_t>(1, std::min<int64_t>(k, 1 << 20));
+        g.lo[d] = hb[d];
+        g.nc[d] = (int)k;
+        g.cs[d] = span[d] / (double)k;
+        g.inv[d] = 1.0 / g.cs[d];
+        ncell *= k;
+    }
+    if (ncell > (int64_t)4 * n + 64) return fail(RBFFD_E_ARG, "degenerate point distribution");
+
+    // count sort into cells
+    // layout: sxyz [n*dim] doubles first (aligned), then the int32 arrays
+    const size_t bytes = sizeof(double) * n * dim + sizeof(int32_t) * (2 * n + 3 * (ncell + 1));
+    char *buf = nullptr;
+    RB_CHECK(dev_alloc(ctx, (void **)&buf, bytes));
+    double *sxyz = (double *)buf;
+    int32_t *cell_of = (int32_t *)(sxyz + n * dim);
+    int32_t *count = cell_of + n;
+    int32_t *cstart = count + (ncell + 1);
+    int32_t *cursor = cstart + (ncell + 1);
+    int32_t *sidx = cursor + (ncell + 1);
+    int st = RBFFD_OK;
+    e = hipMemsetAsync(count, 0, sizeof(int32_t) * (ncell + 1) * 3, s);
+    const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    if (e == hipSuccess) {
+        if (dim == 2)
+            hipLaunchKernelGGL(cell_count<2>, dim3(nb), dim3(kBlock), 0, s, xyz, n, g, cell_of, count);
+        else
+            hipLaunchKernelGGL(cell_count<3>, dim3(nb), dim3(kBlock), 0, s, xyz, n, g, cell_of, count);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) st = scan_exclusive(ctx, count, cstart, ncell, s);
+    if (e == hipSuccess && st == RBFFD_OK) {
+        if (dim == 2)
+            hipLaunchKernelGGL(cell_scatter<2>, dim3(nb), dim3(kBlock), 0, s, xyz, n, cell_of, cstart, cursor, sidx, sxyz);
+        else
+            hipLaunchKernelGGL(cell_scatter<3>, dim3(nb), dim3(kBlock), 0, s, xyz, n, cell_of, cstart, cursor, sidx, sxyz);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && st == RBFFD_OK) {
+        if (dim == 2)
+            hipLaunchKernelGGL(knn_query<2>, dim3((unsigned)n), dim3(64), 0, s, xyz, cstart, sidx, sxyz, g, n, q, nbr);
+        else
+            hipLaunchKernelGGL(knn_query<3>, dim3((unsigned)n), dim3(64), 0, s, xyz, cstart, sidx, sxyz, g, n, q, nbr);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dev_free(ctx, buf, bytes);
+    if (st != RBFFD_OK) return st;
+    if (e != hipSuccess) return hip_fail(e, "neighbour search");
+    return RBFFD_OK;
+}
+
+}  // namespace rbffd

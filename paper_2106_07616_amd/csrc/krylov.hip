@@ -1,0 +1,651 @@
+// Sparse matrix-vector products and preconditioned BiCGSTAB (Sec. 3: the
+// momentum and pressure-correction equations are solved "using a
+// preconditioned BiCGSTAB"; the preconditioner is the Jacobi diagonal applied
+// on the right).
+//
+// Every kernel streams the sliced-ELL matrix with one thread per row: entry a of
+// 64 consecutive rows is one contiguous run, so column indices and values are
+// read fully coalesced, and the gathered vector entries of Morton-ordered points
+// hit in cache. Each BiCGSTAB iteration is five kernels; the global dot
+// products are finished redundantly by every block of the consuming kernel
+// from per-block partials in a fixed order, so the scalars (alpha, beta, omega)
+// never travel to the host and the result is deterministic run to run. The
+// host only reads a small state record every few iterations to stop.
+#include <cmath>
+
+#include "internal.h"
+
+namespace rbffd {
+
+namespace {
+
+// Per right-hand-side solver state. A kernel launch that finishes a solve
+// records its launch sequence number in done_at; blocks of that same launch keep
+// working (they may still owe updates of their rows), later launches skip.
+struct KState {
+    double rho_prev, alpha, omega;
+    int done_at;  // 0 running, else sequence number of the launch that finished
+    int iters;    // completed iterations
+    int status;   // RBFFD_OK / RBFFD_E_BREAKDOWN
+    int pad;
+};
+
+__device__ inline bool finished_before(const KState &s, int phase) { return s.done_at != 0 && s.done_at < phase; }
+
+enum { P_RHR = 0, P_RR, P_BB, P_RV, P_SS, P_TS, P_TT, P_COUNT };
+
+struct Work {
+    // vectors, [nrhs][npad] each
+    void *r, *rh, *ph, *v, *s, *sh, *t;
+    double *part;   // [P_COUNT][kMaxRhs][kMaxBlocks]
+    KState *st;     // [kMaxRhs]
+};
+
+__device__ inline double *partial(double *base, int kind, int r) { return base + ((int64_t)kind * kMaxRhs + r) * kMaxBlocks; }
+
+template <typename T>
+__device__ inline int64_t row_base(int64_t i, int q) { return ((i >> 6) * (int64_t)q) * 64 + (i & 63); }
+
+// acc[r] = sum_a A[i,a] x_r[col]; entries in column order.
+template <typename T, int NRHS>
+__device__ inline void row_dot(int64_t i, int q, const int32_t *__restrict__ col, const T *__restrict__ val,
+                               const T *__restrict__ x, int64_t xs, const bool *act, double *acc)
+{
+    const int64_t base = row_base<T>(i, q);
+    T s[NRHS];
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) s[r] = 0;
+#pragma unroll 4
+    for (int a = 0; a < q; ++a) {
+        const int64_t slot = base + (int64_t)a * 64;
+        const int32_t c = col[slot];
+        const T v = val[slot];
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r)
+            if (act[r]) s[r] = fma(v, x[r * xs + c], s[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) acc[r] = (double)s[r];
+}
+
+__device__ inline int logical_block() { return xcd_block(gridDim.x); }
+
+// ---- plain SpMV ------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void spmv_kernel(int64_t n, int q, const int32_t *__restrict__ col,
+                                                      const T *__restrict__ val, const T *__restrict__ x,
+                                                      T *__restrict__ y)
+{
+    const int64_t i = (int64_t)logical_block() * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const bool act[1] = {true};
+    double acc[1];
+    row_dot<T, 1>(i, q, col, val, x, 0, act, acc);
+    y[i] = (T)acc[0];
+}
+
+// ---- BiCGSTAB ---------------------------------------------------------------
+struct Scal {
+    double rhr[kMaxRhs], rr[kMaxRhs], bb[kMaxRhs];
+};
+
+template <int NRHS>
+__device__ inline bool all_done(const KState *st, int phase)
+{
+    bool d = true;
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) d = d && finished_before(st[r], phase);
+    return d;
+}
+
+// r = b - A x, r-hat = r; partials r-hat.r, r.r, b.b
+template <typename T, int NRHS>
+__global__ __launch_bounds__(kBlock) void k_init(int64_t n, int64_t np, int q, const int32_t *__restrict__ col,
+                                                 const T *__restrict__ val, const T *__restrict__ b, int64_t bs,
+                                                 const T *__restrict__ x, int64_t xs, T *__restrict__ r,
+                                                 T *__restrict__ rh, double *__restrict__ part)
+{
+    __shared__ double lds[kBlock / 64];
+    double srr[NRHS], sbb[NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) srr[k] = sbb[k] = 0.0;
+    bool act[NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) act[k] = true;
+    for (int64_t i = (int64_t)logical_block() * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        double ax[NRHS];
+        row_dot<T, NRHS>(i, q, col, val, x, xs, act, ax);
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            const double bi = (double)b[k * bs + i];
+            const T ri = (T)(bi - ax[k]);
+            r[k * np + i] = ri;
+            rh[k * np + i] = ri;
+            srr[k] += (double)ri * (double)ri;
+            sbb[k] += bi * bi;
+        }
+    }
+    const int blk = blockIdx.x;
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+        const double a = block_sum(srr[k], lds);
+        const double c = block_sum(sbb[k], lds);
+        if (threadIdx.x == 0) {
+            partial(part, P_RHR, k)[blk] = a;
+            partial(part, P_RR, k)[blk] = a;
+            partial(part, P_BB, k)[blk] = c;
+        }
+    }
+}
+
+// Common prologue: sums of r-hat.r, r.r, b.b, and the per-RHS decisions.
+template <int NRHS>
+__device__ inline void prologue_rho(const double *part, int np, double *lds, Scal &sc)
+{
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+        sc.rhr[k] = sum_partials(partial((double *)part, P_RHR, k), np, lds);
+        sc.rr[k] = sum_partials(partial((double *)part, P_RR, k), np, lds);
+        sc.bb[k] = sum_partials(partial((double *)part, P_BB, k), np, lds);
+    }
+}
+
+__device__ inline bool want_restart(const KState &s, double rhr, double rr)
+{
+    return s.iters > 0 && (fabs(rhr) < 1e-300 || fabs(rhr) < 1e-30 * rr);
+}
+
+// KP: convergence test on r; p-hat = D^-1 r + beta (p-hat - omega D^-1 v)
+template <typename T, int NRHS>
+__global__ __launch_bounds__(kBlock) void k_p(int64_t n, int64_t np, const T *__restrict__ dinv,
+                                              T *__restrict__ x, int64_t xs, T *__restrict__ r,
+                                              T *__restrict__ rh, T *__restrict__ ph, const T *__restrict__ v,
+                                              double *__restrict__ part, KState *__restrict__ st, int nblk_prev,
+                                              double tol2, int phase)
+{
+    __shared__ double lds[kBlock / 64];
+    if (all_done<NRHS>(st, phase)) return;
+    Scal sc;
+    prologue_rho<NRHS>(part, nblk_prev, lds, sc);
+    bool act[NRHS], zero[NRHS], restart[NRHS];
+    double beta[NRHS], om[NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+        const KState s = st[k];
+        act[k] = !finished_before(s, phase);
+        zero[k] = act[k] && sc.bb[k] == 0.0;
+        const bool conv = act[k] && !zero[k] && sc.rr[k] <= tol2 * sc.bb[k];
+        restart[k] = want_restart(s, sc.rhr[k], sc.rr[k]);
+        beta[k] = (s.iters == 0 || restart[k]) ? 0.0 : (sc.rhr[k] / s.rho_prev) * (s.alpha / s.omega);
+        om[k] = s.omega;
+        if ((zero[k] || conv) && blockIdx.x == 0 && threadIdx.x == 0) {
+            st[k].done_at = phase;
+            st[k].status = RBFFD_OK;
+        }
+        if (conv) act[k] = false;
+    }
+    for (int64_t i = (int64_t)logical_block() * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const T di = dinv[i];
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            if (!act[k]) continue;
+            if (zero[k]) {
+                x[k * xs + i] = 0;
+                continue;
+            }
+            const T ri = r[k * np + i];
+            if (restart[k]) rh[k * np + i] = ri;
+            const T pn = (beta[k] == 0.0) ? (T)(di * ri)
+                                          : (T)(di * ri + beta[k] * (ph[k * np + i] - om[k] * (di * v[k * np + i])));
+            ph[k * np + i] = pn;
+        }
+    }
+}
+
+// KV: v = A p-hat; partial r-hat.v
+template <typename T, int NRHS>
+__global__ __launch_bounds__(kBlock) void k_v(int64_t n, int64_t np, int q, const int32_t *__restrict__ col,
+                                              const T *__restrict__ val, const T *__restrict__ rh,
+                                              const T *__restrict__ ph, T *__restrict__ v, double *__restrict__ part,
+                                              const KState *__restrict__ st, int phase)
+{
+    __shared__ double lds[kBlock / 64];
+    if (all_done<NRHS>(st, phase)) return;
+    bool act[NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) act[k] = !finished_before(st[k], phase);
+    double srv[NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) srv[k] = 0.0;
+    for (int64_t i = (int64_t)logical_block() * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        double av[NRHS];
+        row_dot<T, NRHS>(i, q, col, val, ph, np, act, av);
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            if (!act[k]) continue;
+            const T vi = (T)av[k];
+            v[k * np + i] = vi;
+            srv[k] += (double)rh[k * np + i] * (double)vi;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+        const double a = block_sum(srv[k], lds);
+        if (threadIdx.x == 0) partial(part, P_RV, k)[blockIdx.x] = a;
+    }
+}
+
+// KS: alpha = rho / r-hat.v; s = r - alpha v; s-hat = D^-1 s; partial s.s
+template <typename T, int NRHS>
+__global__ __launch_bounds__(kBlock) void k_s(int64_t n, int64_t np, const T *__restrict__ dinv,
+                                              const T *__restrict__ r, const T *__restrict__ v, T *__restrict__ s,
+                                              T *__restrict__ sh, double *__restrict__ part, KState *__restrict__ st,
+                                              int nblk, int phase)
+{
+    __shared__ double lds[kBlock / 64];
+    if (all_done<NRHS>(st, phase)) return;
+    Scal sc;
+    prologue_rho<NRHS>(part, nblk, lds, sc);
+    bool act[NRHS];
+    double alpha[NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+        const KState stk = st[k];
+        act[k] = !finished_before(stk, phase);
+        const double rho = want_restart(stk, sc.rhr[k], sc.rr[k]) ? sc.rr[k] : sc.rhr[k];
+        const double rv = sum_partials(partial(part, P_RV, k), nblk, lds);
+        alpha[k] = (rv != 0.0) ? rho / rv : 0.0;
+        if (act[k] && blockIdx.x == 0 && threadIdx.x == 0) {
+            st[k].alpha = alpha[k];
+            st[k].rho_prev = rho;
+            if (rv == 0.0) {
+                st[k].done_at = phase;
+                st[k].status = RBFFD_E_BREAKDOWN;
+            }
+        }
+        if (rv == 0.0) act[k] = false;
+    }
+    double sss[NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) sss[k] = 0.0;
+    for (int64_t i = (int64_t)logical_block() * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const T di = dinv[i];
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            if (!act[k]) continue;
+            const T si = (T)((double)r[k * np + i] - alpha[k] * (double)v[k * np + i]);
+            s[k * np + i] = si;
+            sh[k * np + i] = di * si;
+            sss[k] += (double)si * (double)si;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+        const double a = block_sum(sss[k], lds);
+        if (threadIdx.x == 0) partial(part, P_SS, k)[blockIdx.x] = a;
+    }
+}
+
+// KT: if ||s|| is small, x += alpha p-hat and stop; else t = A s-hat, partials t.s, t.t
+template <typename T, int NRHS>
+__global__ __launch_bounds__(kBlock) void k_t(int64_t n, int64_t np, int q, const int32_t *__restrict__ col,
+                                              const T *__restrict__ val, T *__restrict__ x, int64_t xs,
+                                              const T *__restrict__ ph, const T *__restrict__ s,
+                                              const T *__restrict__ sh, T *__restrict__ t, double *__restrict__ part,
+                                              KState *__restrict__ st, int nblk, double tol2, int phase)
+{
+    __shared__ double lds[kBlock / 64];
+    if (all_done<NRHS>(st, phase)) return;
+    bool act[NRHS], half[NRHS];
+    double alpha[NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+        const KState stk = st[k];
+        act[k] = !finished_before(stk, phase);
+        alpha[k] = stk.alpha;
+        const double ss = sum_partials(partial(part, P_SS, k), nblk, lds);
+        const double bb = sum_partials(partial(part, P_BB, k), nblk, lds);
+        half[k] = act[k] && ss <= tol2 * bb;
+        if (half[k] && blockIdx.x == 0 && threadIdx.x == 0) {
+            st[k].done_at = phase;
+            st[k].status = RBFFD_OK;
+            st[k].iters = stk.iters + 1;
+        }
+    }
+    bool sp[NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) sp[k] = act[k] && !half[k];
+    double sts[NRHS], stt[NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) sts[k] = stt[k] = 0.0;
+    for (int64_t i = (int64_t)logical_block() * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k)
+            if (half[k]) x[k * xs + i] = (T)((double)x[k * xs + i] + alpha[k] * (double)ph[k * np + i]);
+        double at[NRHS];
+        row_dot<T, NRHS>(i, q, col, val, sh, np, sp, at);
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            if (!sp[k]) continue;
+            const T ti = (T)at[k];
+            t[k * np + i] = ti;
+            sts[k] += (double)ti * (double)s[k * np + i];
+            stt[k] += (double)ti * (double)ti;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+        const double a = block_sum(sts[k], lds);
+        const double c = block_sum(stt[k], lds);
+        if (threadIdx.x == 0) {
+            partial(part, P_TS, k)[blockIdx.x] = a;
+            partial(part, P_TT, k)[blockIdx.x] = c;
+        }
+    }
+}
+
+// KX: omega = t.s / t.t; x += alpha p-hat + omega s-hat; r = s - omega t; partials r-hat.r, r.r
+template <typename T, int NRHS>
+__global__ __launch_bounds__(kBlock) void k_x(int64_t n, int64_t np, T *__restrict__ x, int64_t xs,
+                                              const T *__restrict__ ph, const T *__restrict__ s,
+                                              const T *__restrict__ sh, const T *__restrict__ t, T *__restrict__ r,
+                                              const T *__restrict__ rh, double *__restrict__ part,
+                                              KState *__restrict__ st, int nblk, int phase)
+{
+    __shared__ double lds[kBlock / 64];
+    if (all_done<NRHS>(st, phase)) return;
+    bool act[NRHS];
+    double alpha[NRHS], omega[NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+        const KState stk = st[k];
+        act[k] = !finished_before(stk, phase);
+        alpha[k] = stk.alpha;
+        const double ts = sum_partials(partial(part, P_TS, k), nblk, lds);
+        const double tt = sum_partials(partial(part, P_TT, k), nblk, lds);
+        omega[k] = (tt > 0.0) ? ts / tt : 0.0;
+        if (act[k] && blockIdx.x == 0 && threadIdx.x == 0) {
+            st[k].omega = omega[k];
+            st[k].iters = stk.iters + 1;
+            if (omega[k] == 0.0) {
+                st[k].done_at = phase;
+                st[k].status = RBFFD_E_BREAKDOWN;
+            }
+        }
+    }
+    double srhr[NRHS], srr[NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) srhr[k] = srr[k] = 0.0;
+    for (int64_t i = (int64_t)logical_block() * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            if (!act[k]) continue;
+            x[k * xs + i] = (T)((double)x[k * xs + i] + alpha[k] * (double)ph[k * np + i] +
+                                omega[k] * (double)sh[k * np + i]);
+            const T ri = (T)((double)s[k * np + i] - omega[k] * (double)t[k * np + i]);
+            r[k * np + i] = ri;
+            srhr[k] += (double)rh[k * np + i] * (double)ri;
+            srr[k] += (double)ri * (double)ri;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+        const double a = block_sum(srhr[k], lds);
+        const double c = block_sum(srr[k], lds);
+        if (threadIdx.x == 0) {
+            partial(part, P_RHR, k)[blockIdx.x] = a;
+            partial(part, P_RR, k)[blockIdx.x] = c;
+        }
+    }
+}
+
+// ||b - A x||^2 and ||b||^2 per right-hand side (FP64), partials then one block
+__global__ __launch_bounds__(kBlock) void k_resid(int64_t n, int q, int nrhs, const int32_t *__restrict__ col,
+                                                  const double *__restrict__ val, const double *__restrict__ b,
+                                                  int64_t bs, const double *__restrict__ x, int64_t xs,
+                                                  double *__restrict__ part)
+{
+    __shared__ double lds[kBlock / 64];
+    for (int k = 0; k < nrhs; ++k) {
+        double srr = 0.0, sbb = 0.0;
+        const bool act[1] = {true};
+        for (int64_t i = (int64_t)logical_block() * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+            double ax[1];
+            row_dot<double, 1>(i, q, col, val, x + k * xs, 0, act, ax);
+            const double ri = b[k * bs + i] - ax[0];
+            srr += ri * ri;
+            sbb += b[k * bs + i] * b[k * bs + i];
+        }
+        const double a = block_sum(srr, lds), c = block_sum(sbb, lds);
+        if (threadIdx.x == 0) {
+            part[(2 * k) * kMaxBlocks + blockIdx.x] = a;
+            part[(2 * k + 1) * kMaxBlocks + blockIdx.x] = c;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_resid_final(const double *__restrict__ part, int np, int nrhs,
+                                                        double *__restrict__ out)
+{
+    __shared__ double lds[kBlock / 64];
+    for (int k = 0; k < nrhs; ++k) {
+        const double a = sum_partials(part + (2 * k) * kMaxBlocks, np, lds);
+        const double c = sum_partials(part + (2 * k + 1) * kMaxBlocks, np, lds);
+        if (threadIdx.x == 0) out[k] = (c > 0.0) ? sqrt(a / c) : sqrt(a);
+    }
+}
+
+// FP64 residual for refinement: res = b - A x (stored as FP32), partial ||res||^2
+__global__ __launch_bounds__(kBlock) void k_refine_res(int64_t n, int q, int nrhs, const int32_t *__restrict__ col,
+                                                       const double *__restrict__ val, const double *__restrict__ b,
+                                                       int64_t bs, const double *__restrict__ x, int64_t xs,
+                                                       float *__restrict__ res, int64_t np)
+{
+    const int64_t i = (int64_t)logical_block() * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const bool act[1] = {true};
+    for (int k = 0; k < nrhs; ++k) {
+        double ax[1];
+        row_dot<double, 1>(i, q, col, val, x + k * xs, 0, act, ax);
+        res[k * np + i] = (float)(b[k * bs + i] - ax[0]);
+    }
+}
+
+__global__ void k_refine_add(int64_t n, int nrhs, double *__restrict__ x, int64_t xs, const float *__restrict__ d,
+                             int64_t np)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 0; k < nrhs; ++k) x[k * xs + i] += (double)d[k * np + i];
+}
+
+__global__ void k_zero_f(float *__restrict__ y, int64_t m)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < m) y[i] = 0.0f;
+}
+
+inline int grid_blocks(int64_t n)
+{
+    int64_t b = (n + kBlock - 1) / kBlock;
+    if (b > kMaxBlocks) b = kMaxBlocks;
+    if (b >= 64) b = b / 8 * 8;   // multiple of 8 for the XCD-aware mapping
+    return (int)std::max<int64_t>(1, b);
+}
+
+template <typename T>
+int get_work(rbffd_ctx *ctx, int64_t npad, int nrhs, Work *w)
+{
+    const size_t vec = sizeof(T) * npad * nrhs;
+    char *base = nullptr;
+    RB_CHECK(workspace(ctx, sizeof(T) == 4 ? WS_KRYLOV32 : WS_KRYLOV, 7 * vec, (void **)&base));
+    w->r = base;
+    w->rh = base + vec;
+    w->ph = base + 2 * vec;
+    w->v = base + 3 * vec;
+    w->s = base + 4 * vec;
+    w->sh = base + 5 * vec;
+    w->t = base + 6 * vec;
+    RB_CHECK(workspace(ctx, sizeof(T) == 4 ? WS_PARTIAL32 : WS_PARTIAL,
+                       sizeof(double) * P_COUNT * kMaxRhs * kMaxBlocks + sizeof(KState) * kMaxRhs, (void **)&w->part));
+    w->st = (KState *)(w->part + P_COUNT * kMaxRhs * kMaxBlocks);
+    return RBFFD_OK;
+}
+
+template <typename T, int NRHS>
+int bicgstab_t(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const T *val, const T *dinv, const T *b,
+               int64_t bs, T *x, int64_t xs, double tol, int max_iter, KrylovResult *res, Work &w, hipStream_t s)
+{
+    const int64_t np = pad64(n);
+    const int nblk = grid_blocks(n);
+    const dim3 g(nblk), bl(kBlock);
+    T *r = (T *)w.r, *rh = (T *)w.rh, *ph = (T *)w.ph, *v = (T *)w.v, *sv = (T *)w.s, *sh = (T *)w.sh, *t = (T *)w.t;
+    const double tol2 = tol * tol;
+    RB_HIP(hipMemsetAsync(w.st, 0, sizeof(KState) * kMaxRhs, s));
+    // p-hat and v start at zero (only read after the first iteration)
+    RB_HIP(hipMemsetAsync(ph, 0, sizeof(T) * np * NRHS, s));
+    RB_HIP(hipMemsetAsync(v, 0, sizeof(T) * np * NRHS, s));
+    hipLaunchKernelGGL((k_init<T, NRHS>), g, bl, 0, s, n, np, q, col, val, b, bs, x, xs, r, rh, w.part);
+    RB_HIP(hipGetLastError());
+    KState *hst = nullptr;
+    RB_CHECK(host_scratch(ctx, kHostKrylov, sizeof(KState) * kMaxRhs, (void **)&hst));
+    int it = 0, chunk = 4, phase = 0;
+    bool finished = false;
+    while (!finished) {
+        const int todo = std::min(chunk, max_iter - it);
+        for (int c = 0; c < todo; ++c) {
+            hipLaunchKernelGGL((k_p<T, NRHS>), g, bl, 0, s, n, np, dinv, x, xs, r, rh, ph, v, w.part, w.st, nblk, tol2,
+                               ++phase);
+            hipLaunchKernelGGL((k_v<T, NRHS>), g, bl, 0, s, n, np, q, col, val, rh, ph, v, w.part, w.st, ++phase);
+            hipLaunchKernelGGL((k_s<T, NRHS>), g, bl, 0, s, n, np, dinv, r, v, sv, sh, w.part, w.st, nblk, ++phase);
+            hipLaunchKernelGGL((k_t<T, NRHS>), g, bl, 0, s, n, np, q, col, val, x, xs, ph, sv, sh, t, w.part, w.st, nblk,
+                               tol2, ++phase);
+            hipLaunchKernelGGL((k_x<T, NRHS>), g, bl, 0, s, n, np, x, xs, ph, sv, sh, t, r, rh, w.part, w.st, nblk,
+                               ++phase);
+        }
+        it += std::max(todo, 0);
+        if (it >= max_iter) {
+            // final convergence test on the last residual
+            hipLaunchKernelGGL((k_p<T, NRHS>), g, bl, 0, s, n, np, dinv, x, xs, r, rh, ph, v, w.part, w.st, nblk, tol2,
+                               ++phase);
+        }
+        RB_HIP(hipGetLastError());
+        RB_HIP(hipMemcpyAsync(hst, w.st, sizeof(KState) * kMaxRhs, hipMemcpyDeviceToHost, s));
+        RB_HIP(hipStreamSynchronize(s));
+        bool done = true;
+        for (int k = 0; k < NRHS; ++k) done = done && hst[k].done_at != 0;
+        finished = done || it >= max_iter;
+        chunk = std::min(chunk * 2, 32);
+    }
+    for (int k = 0; k < NRHS; ++k) {
+        res->iters[k] = hst[k].iters;
+        res->status[k] = hst[k].done_at ? hst[k].status : RBFFD_E_NOCONV;
+    }
+    return RBFFD_OK;
+}
+
+}  // namespace
+
+int spmv(int64_t n, int q, const int32_t *col, const double *val, const double *x, double *y, hipStream_t s)
+{
+    const int64_t nb = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(spmv_kernel<double>, dim3((unsigned)nb), dim3(kBlock), 0, s, n, q, col, val, x, y);
+    RB_HIP(hipGetLastError());
+    return RBFFD_OK;
+}
+
+int bicgstab(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val, const double *dinv, int nrhs,
+             const double *b, double *x, double tol, int max_iter, KrylovResult *res, hipStream_t s)
+{
+    Work w;
+    RB_CHECK(get_work<double>(ctx, pad64(n), nrhs, &w));
+    switch (nrhs) {
+    case 1: return bicgstab_t<double, 1>(ctx, n, q, col, val, dinv, b, n, x, n, tol, max_iter, res, w, s);
+    case 2: return bicgstab_t<double, 2>(ctx, n, q, col, val, dinv, b, n, x, n, tol, max_iter, res, w, s);
+    case 3: return bicgstab_t<double, 3>(ctx, n, q, col, val, dinv, b, n, x, n, tol, max_iter, res, w, s);
+    default: return fail(RBFFD_E_ARG, "nrhs must be 1..3");
+    }
+}
+
+// Mixed precision: FP32 matrix, vectors and sweeps with FP64 dot accumulation
+// inside; FP64 residual b - A x and FP64 update of x outside, repeated until
+// the FP64 residual meets tol.
+int bicgstab_fp32_ir(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val, const float *val32,
+                     const float *dinv32, int nrhs, const double *b, double *x, double tol, int max_iter,
+                     KrylovResult *res, int *refinements, hipStream_t s)
+{
+    if (nrhs < 1 || nrhs > kMaxRhs) return fail(RBFFD_E_ARG, "nrhs must be 1..3");
+    const int64_t np = pad64(n);
+    Work w;
+    RB_CHECK(get_work<float>(ctx, np, nrhs, &w));
+    char *scr = nullptr;
+    const size_t rbytes = sizeof(double) * (2 * kMaxRhs * kMaxBlocks + kMaxRhs);
+    RB_CHECK(workspace(ctx, WS_REFINE, sizeof(float) * np * nrhs * 2 + rbytes, (void **)&scr));
+    double *resid_dev = (double *)scr;
+    double *rout = resid_dev + 2 * kMaxRhs * kMaxBlocks;
+    float *rb = (float *)(scr + rbytes);
+    float *dx = rb + np * nrhs;
+    double *rr = nullptr;
+    RB_CHECK(host_scratch(ctx, kHostRefine, sizeof(double) * kMaxRhs, (void **)&rr));
+    const double inner_tol = std::max(tol, 1e-4);
+    int total_it[kMaxRhs] = {0, 0, 0};
+    int nref = 0;
+    const int nblk = grid_blocks(n);
+    const unsigned gb = (unsigned)((n + kBlock - 1) / kBlock);
+    bool converged = false;
+    for (int sweep = 0; sweep < 200; ++sweep) {
+        // FP64 residual norm of the current iterate
+        hipLaunchKernelGGL(k_resid, dim3(nblk), dim3(kBlock), 0, s, n, q, nrhs, col, val, b, n, x, n, resid_dev);
+        hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(kBlock), 0, s, resid_dev, nblk, nrhs, rout);
+        RB_HIP(hipGetLastError());
+        RB_HIP(hipMemcpyAsync(rr, rout, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+        RB_HIP(hipStreamSynchronize(s));
+        converged = true;
+        for (int k = 0; k < nrhs; ++k) converged = converged && rr[k] <= tol;
+        if (converged) break;
+        int left = max_iter;
+        for (int k = 0; k < nrhs; ++k) left = std::min(left, max_iter - total_it[k]);
+        if (left <= 0) break;
+        // FP32 correction equation A d = b - A x from d = 0
+        hipLaunchKernelGGL(k_refine_res, dim3(gb), dim3(kBlock), 0, s, n, q, nrhs, col, val, b, n, x, n, rb, np);
+        hipLaunchKernelGGL(k_zero_f, dim3((unsigned)((np * nrhs + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, dx,
+                           np * nrhs);
+        RB_HIP(hipGetLastError());
+        KrylovResult ir;
+        if (nrhs == 1)
+            RB_CHECK((bicgstab_t<float, 1>(ctx, n, q, col, val32, dinv32, rb, np, dx, np, inner_tol, left, &ir, w, s)));
+        else if (nrhs == 2)
+            RB_CHECK((bicgstab_t<float, 2>(ctx, n, q, col, val32, dinv32, rb, np, dx, np, inner_tol, left, &ir, w, s)));
+        else
+            RB_CHECK((bicgstab_t<float, 3>(ctx, n, q, col, val32, dinv32, rb, np, dx, np, inner_tol, left, &ir, w, s)));
+        for (int k = 0; k < nrhs; ++k) total_it[k] += ir.iters[k];
+        hipLaunchKernelGGL(k_refine_add, dim3(gb), dim3(kBlock), 0, s, n, nrhs, x, n, dx, np);
+        RB_HIP(hipGetLastError());
+        ++nref;
+    }
+    for (int k = 0; k < nrhs; ++k) {
+        res->iters[k] = total_it[k];
+        res->status[k] = (rr[k] <= tol) ? RBFFD_OK : RBFFD_E_NOCONV;
+        res->relres[k] = rr[k];
+    }
+    if (refinements) *refinements = nref;
+    return RBFFD_OK;
+}
+
+int residual_norms(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val, int nrhs,
+                   const double *b, const double *x, double *relres_out, hipStream_t s)
+{
+    const int nblk = grid_blocks(n);
+    double *dev = nullptr;
+    RB_CHECK(dev_alloc(ctx, (void **)&dev, sizeof(double) * (2 * kMaxRhs * kMaxBlocks + kMaxRhs)));
+    double *out = dev + 2 * kMaxRhs * kMaxBlocks;
+    hipLaunchKernelGGL(k_resid, dim3(nblk), dim3(kBlock), 0, s, n, q, nrhs, col, val, b, n, x, n, dev);
+    hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(kBlock), 0, s, dev, nblk, nrhs, out);
+    hipError_t e = hipMemcpyAsync(relres_out, out, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dev_free(ctx, dev, sizeof(double) * (2 * kMaxRhs * kMaxBlocks + kMaxRhs));
+    if (e != hipSuccess) return hip_fail(e, "residual norm");
+    return RBFFD_OK;
+}
+
+}  // namespace rbffd

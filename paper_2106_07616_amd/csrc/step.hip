@@ -1,0 +1,482 @@
+// One BDF time step of the semi-implicit outer iteration (Sec. 3, Eqs. u:n+1
+// ... p:correction, Eq. normal momentum, and the step list of Sec. 3.2), and
+// the Courant-number eigenvalue estimate of Sec. 3.2.
+//
+// Per outer iteration: momentum matrix + right-hand sides (one streaming pass
+// over the stored operators), d-right-hand-side BiCGSTAB sharing each matrix
+// pass, divergence right-hand side, pressure-correction BiCGSTAB, interior
+// pressure update, boundary-pressure block solve, velocity correction fused
+// with the change Delta. Only Delta (8 bytes) returns to the host per
+// iteration.
+#include <cmath>
+
+#include "internal.h"
+
+namespace rbffd {
+
+namespace {
+
+__device__ inline int lb() { return xcd_block(gridDim.x); }
+
+inline int blocks_for(int64_t n)
+{
+    int64_t b = (n + kBlock - 1) / kBlock;
+    if (b > kMaxBlocks) b = kMaxBlocks;
+    if (b >= 64) b = b / 8 * 8;
+    return (int)std::max<int64_t>(1, b);
+}
+
+// u^r = u^n with the Dirichlet values of t^{n+1} on boundary points; p^r = p^n
+__global__ void k_start(int64_t n, int dim, const uint8_t *__restrict__ kind, const double *__restrict__ u,
+                        const double *__restrict__ ubc, const double *__restrict__ p, double *__restrict__ ur,
+                        double *__restrict__ pr)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const bool b = kind[i] != RBFFD_INTERIOR;
+    for (int e = 0; e < dim; ++e) ur[e * n + i] = b ? ubc[e * n + i] : u[e * n + i];
+    pr[i] = p[i];
+}
+
+// Momentum matrix (Eqs. u:tilde, v:tilde, with u^r linearising advection):
+//   interior:  M_ij = rho a1/dt d_ij + rho sum_e u^r_e,i D_e,ij - mu L_ij
+//              b_e,i = -rho (a2 u^n_e,i + a3 u^{n-1}_e,i)/dt - (D_e p^r)_i
+//   boundary:  identity row, b_e,i = u_bc,e,i
+// With `cd` set it writes instead C = -rho (u . grad) + mu L on interior rows and
+// zero rows on the boundary (the convection-diffusion operator of Sec. 3.2).
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_momentum(int64_t n, int q, const int32_t *__restrict__ col,
+                                                     const double *__restrict__ val, int64_t vs,
+                                                     const uint8_t *__restrict__ kind, const double *__restrict__ ur,
+                                                     const double *__restrict__ un, const double *__restrict__ up,
+                                                     const double *__restrict__ ubc, const double *__restrict__ pr,
+                                                     double rho, double mu, double dt, double a1, double a2, double a3,
+                                                     int cd, double *__restrict__ mval, double *__restrict__ mdinv,
+                                                     double *__restrict__ bm)
+{
+    const int64_t i = (int64_t)lb() * kBlock + threadIdx.x;
+    if (i >= pad64(n)) return;
+    const int64_t base = ((i >> 6) * (int64_t)q) * 64 + (i & 63);
+    if (i >= n) {
+        for (int a = 0; a < q; ++a) mval[base + (int64_t)a * 64] = 0.0;
+        mdinv[i] = 0.0;
+        return;
+    }
+    if (kind[i] != RBFFD_INTERIOR) {
+        for (int a = 0; a < q; ++a) {
+            const int64_t slot = base + (int64_t)a * 64;
+            mval[slot] = (!cd && col[slot] == i) ? 1.0 : 0.0;
+        }
+        mdinv[i] = 1.0;
+        if (!cd)
+            for (int e = 0; e < DIM; ++e) bm[e * n + i] = ubc[e * n + i];
+        return;
+    }
+    double uc[DIM];
+    for (int e = 0; e < DIM; ++e) uc[e] = ur[e * n + i];
+    const double mass = rho * a1 / dt;
+    double g[DIM];
+    for (int e = 0; e < DIM; ++e) g[e] = 0.0;
+    double diag = 0.0;
+    for (int a = 0; a < q; ++a) {
+        const int64_t slot = base + (int64_t)a * 64;
+        const int32_t c = col[slot];
+        double conv = 0.0;
+        for (int e = 0; e < DIM; ++e) conv = conv + uc[e] * val[e * vs + slot];
+        double v;
+        if (cd) {
+            v = -rho * conv + mu * val[DIM * vs + slot];
+        } else {
+            v = rho * conv - mu * val[DIM * vs + slot];
+            if (c == i) v = v + mass;
+            const double pc = pr[c];
+            for (int e = 0; e < DIM; ++e) g[e] = fma(val[e * vs + slot], pc, g[e]);
+        }
+        mval[slot] = v;
+        if (c == i) diag += v;
+    }
+    mdinv[i] = (diag != 0.0) ? 1.0 / diag : 1.0;
+    if (!cd)
+        for (int e = 0; e < DIM; ++e) bm[e * n + i] = -rho * (a2 * un[e * n + i] + a3 * up[e * n + i]) / dt - g[e];
+}
+
+// f_i = (rho a1 / dt) sum_e (D_e u~_e)_i on interior rows other than the pin; 0 elsewhere
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_div_rhs(int64_t n, int q, const int32_t *__restrict__ col,
+                                                    const double *__restrict__ val, int64_t vs,
+                                                    const uint8_t *__restrict__ kind, int64_t pin,
+                                                    const double *__restrict__ ut, double coef, double *__restrict__ f)
+{
+    const int64_t i = (int64_t)lb() * kBlock + threadIdx.x;
+    if (i >= n) return;
+    if (kind[i] != RBFFD_INTERIOR || i == pin) {
+        f[i] = 0.0;
+        return;
+    }
+    const int64_t base = ((i >> 6) * (int64_t)q) * 64 + (i & 63);
+    double dv = 0.0;
+    for (int e = 0; e < DIM; ++e) {
+        double s = 0.0;
+        for (int a = 0; a < q; ++a) {
+            const int64_t slot = base + (int64_t)a * 64;
+            s = fma(val[e * vs + slot], ut[e * n + col[slot]], s);
+        }
+        dv = dv + s;
+    }
+    f[i] = coef * dv;
+}
+
+// p_a = p^r + p' on interior points, the prescribed value on prescribed-pressure
+// points, p^r on velocity-Dirichlet points (replaced by the normal-momentum solve)
+__global__ void k_p_interior(int64_t n, const uint8_t *__restrict__ kind, const double *__restrict__ pr,
+                             const double *__restrict__ pc, const double *__restrict__ pbc, double *__restrict__ pa)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int kd = kind[i];
+    pa[i] = (kd == RBFFD_INTERIOR) ? pr[i] + pc[i] : (kd == RBFFD_PRESCRIBED_PRESSURE ? pbc[i] : pr[i]);
+}
+
+// Boundary-pressure right-hand side (Eq. normal momentum) for boundary row b:
+//   R_b = sum_c N_c [ -rho (a1 u~_c + a2 u^n_c + a3 u^{n-1}_c)/dt - rho (u~ . grad) u~_c + mu L u~_c ]_b
+//         - sum_{j not velocity-Dirichlet} G_bj p_a,j
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_boundary_rhs(int64_t n, int64_t nb, int q, const int32_t *__restrict__ col,
+                                                         const double *__restrict__ val, int64_t vs,
+                                                         const double *__restrict__ pval,
+                                                         const uint8_t *__restrict__ kind,
+                                                         const double *__restrict__ normal,
+                                                         const int32_t *__restrict__ bidx, const double *__restrict__ ut,
+                                                         const double *__restrict__ un, const double *__restrict__ up,
+                                                         const double *__restrict__ pa, const double *__restrict__ pr,
+                                                         double rho, double mu, double dt, double a1, double a2,
+                                                         double a3, double *__restrict__ bb, double *__restrict__ pb)
+{
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const int64_t i = bidx[b];
+    const int64_t base = ((i >> 6) * (int64_t)q) * 64 + (i & 63);
+    double grad[DIM][DIM], lap[DIM], off = 0.0;
+    for (int c = 0; c < DIM; ++c) {
+        lap[c] = 0.0;
+        for (int g = 0; g < DIM; ++g) grad[g][c] = 0.0;
+    }
+    for (int a = 0; a < q; ++a) {
+        const int64_t slot = base + (int64_t)a * 64;
+        const int32_t j = col[slot];
+        for (int c = 0; c < DIM; ++c) {
+            const double uj = ut[c * n + j];
+            for (int g = 0; g < DIM; ++g) grad[g][c] = fma(val[g * vs + slot], uj, grad[g][c]);
+            lap[c] = fma(val[DIM * vs + slot], uj, lap[c]);
+        }
+        if (kind[j] != RBFFD_DIRICHLET) off = fma(pval[slot], pa[j], off);
+    }
+    double rhs = 0.0;
+    for (int c = 0; c < DIM; ++c) {
+        const double dudt = rho * (a1 * ut[c * n + i] + a2 * un[c * n + i] + a3 * up[c * n + i]) / dt;
+        double adv = 0.0;
+        for (int g = 0; g < DIM; ++g) adv = adv + ut[g * n + i] * grad[g][c];
+        const double comp = -dudt - rho * adv + mu * lap[c];
+        rhs = rhs + normal[i * DIM + c] * comp;
+    }
+    bb[b] = rhs - off;
+    pb[b] = pr[i];
+}
+
+__global__ void k_p_scatter(int64_t n, const uint8_t *__restrict__ kind, const int32_t *__restrict__ bpos,
+                            const double *__restrict__ pa, const double *__restrict__ pb, double *__restrict__ pr)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    pr[i] = (kind[i] == RBFFD_DIRICHLET) ? pb[bpos[i]] : pa[i];
+}
+
+// u^{r+1} = u~ - coef D p' on interior points (Eqs. u:correction, v:correction),
+// u~ on boundary points; partials of sum_i |u^{r+1}_e - u^r_e| per component.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_correct(int64_t n, int q, const int32_t *__restrict__ col,
+                                                    const double *__restrict__ val, int64_t vs,
+                                                    const uint8_t *__restrict__ kind, const double *__restrict__ pc,
+                                                    const double *__restrict__ ut, const double *__restrict__ ur,
+                                                    double coef, double *__restrict__ unew, double *__restrict__ part)
+{
+    __shared__ double lds[kBlock / 64];
+    double acc[DIM];
+    for (int e = 0; e < DIM; ++e) acc[e] = 0.0;
+    for (int64_t i = (int64_t)lb() * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        if (kind[i] != RBFFD_INTERIOR) {
+            for (int e = 0; e < DIM; ++e) {
+                const double v = ut[e * n + i];
+                unew[e * n + i] = v;
+                acc[e] += fabs(v - ur[e * n + i]);
+            }
+            continue;
+        }
+        const int64_t base = ((i >> 6) * (int64_t)q) * 64 + (i & 63);
+        double g[DIM];
+        for (int e = 0; e < DIM; ++e) g[e] = 0.0;
+        for (int a = 0; a < q; ++a) {
+            const int64_t slot = base + (int64_t)a * 64;
+            const double pj = pc[col[slot]];
+            for (int e = 0; e < DIM; ++e) g[e] = fma(val[e * vs + slot], pj, g[e]);
+        }
+        for (int e = 0; e < DIM; ++e) {
+            const double v = ut[e * n + i] - coef * g[e];
+            unew[e * n + i] = v;
+            acc[e] += fabs(v - ur[e * n + i]);
+        }
+    }
+    for (int e = 0; e < DIM; ++e) {
+        const double s = block_sum(acc[e], lds);
+        if (threadIdx.x == 0) part[e * kMaxBlocks + blockIdx.x] = s;
+    }
+}
+
+// partials of sum_i |a_e - b_e|
+__global__ __launch_bounds__(kBlock) void k_absdiff(int64_t n, int dim, const double *__restrict__ a,
+                                                    const double *__restrict__ b, double *__restrict__ part)
+{
+    __shared__ double lds[kBlock / 64];
+    for (int e = 0; e < dim; ++e) {
+        double acc = 0.0;
+        for (int64_t i = (int64_t)lb() * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+            acc += fabs(a[e * n + i] - b[e * n + i]);
+        const double s = block_sum(acc, lds);
+        if (threadIdx.x == 0) part[e * kMaxBlocks + blockIdx.x] = s;
+    }
+}
+
+// out[0] = sum_e S_e / n (Delta); out[1] = max_e S_e / n / dt (steady rate)
+__global__ __launch_bounds__(kBlock) void k_finish_sums(const double *__restrict__ part, int np, int dim, int64_t n,
+                                                        double dt, double *__restrict__ out)
+{
+    __shared__ double lds[kBlock / 64];
+    double tot = 0.0, mx = 0.0;
+    for (int e = 0; e < dim; ++e) {
+        const double s = sum_partials(part + e * kMaxBlocks, np, lds) / (double)n;
+        tot += s;
+        mx = fmax(mx, s / dt);
+    }
+    if (threadIdx.x == 0) {
+        out[0] = tot;
+        out[1] = mx;
+    }
+}
+
+// ---- power iteration -------------------------------------------------------
+__global__ void k_pow_start(int64_t n, double *__restrict__ x)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 1.0 + (double)(i % 7) / 7.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sq_partial(int64_t n, const double *__restrict__ y,
+                                                       double *__restrict__ part)
+{
+    __shared__ double lds[kBlock / 64];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)lb() * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) acc += y[i] * y[i];
+    const double s = block_sum(acc, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_normalise(int64_t n, const double *__restrict__ y, double *__restrict__ x,
+                                                      const double *__restrict__ part, int np,
+                                                      double *__restrict__ norm_out)
+{
+    __shared__ double lds[kBlock / 64];
+    const double nrm = sqrt(sum_partials(part, np, lds));
+    if (blockIdx.x == 0 && threadIdx.x == 0) *norm_out = nrm;
+    if (nrm == 0.0) return;
+    for (int64_t i = (int64_t)lb() * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) x[i] = y[i] / nrm;
+}
+
+struct StepBufs {
+    double *ur, *ut, *un, *bm, *pr, *pa, *pc, *f, *part, *scal;
+    double *bb, *pb;
+};
+
+}  // namespace
+
+int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, double *p, const double *u_bc,
+             const double *p_bc, const rbffd_step_opts *o, rbffd_step_stats *st, hipStream_t s)
+{
+    const int dim = ops->dim, q = ops->q;
+    const int64_t n = ops->n, vs = ops->npad * q;
+    const size_t vec = sizeof(double) * n;
+    StepBufs B;
+    char *w = nullptr;
+    const size_t partb = sizeof(double) * (kMaxRhs * kMaxBlocks + 8);
+    RB_CHECK(workspace(ctx, WS_STEP, vec * (4 * dim + 4) + partb, (void **)&w));
+    B.ur = (double *)w;
+    B.ut = B.ur + dim * n;
+    B.un = B.ut + dim * n;
+    B.bm = B.un + dim * n;
+    B.pr = B.bm + dim * n;
+    B.pa = B.pr + n;
+    B.pc = B.pa + n;
+    B.f = B.pc + n;
+    B.part = B.f + n;
+    B.scal = B.part + kMaxRhs * kMaxBlocks;
+    char *w2 = nullptr;
+    const int64_t nbv = std::max<int64_t>(ops->nb, 1);
+    RB_CHECK(workspace(ctx, WS_STEP2, sizeof(double) * 2 * nbv, (void **)&w2));
+    B.bb = (double *)w2;
+    B.pb = B.bb + nbv;
+    double *hs = nullptr;
+    RB_CHECK(host_scratch(ctx, kHostStep, sizeof(double) * 4, (void **)&hs));
+
+    const double rho = o->rho, mu = o->mu, dt = o->dt;
+    const double a1 = o->alpha[0], a2 = o->alpha[1], a3 = o->alpha[2];
+    const int gn = (int)((n + kBlock - 1) / kBlock);
+    const int gpad = (int)((ops->npad + kBlock - 1) / kBlock);
+    const int nblk = blocks_for(n);
+    const bool fp32 = o->precision == RBFFD_FP32_IR;
+
+    hipLaunchKernelGGL(k_start, dim3(gn), dim3(kBlock), 0, s, n, dim, ops->kind, u, u_bc, p, B.ur, B.pr);
+    RB_HIP(hipGetLastError());
+
+    int status = RBFFD_OK, outer = 0, kit_m = 0, kit_p = 0, kit_b = 0;
+    double delta = 0.0;
+    for (outer = 1; outer <= o->max_outer; ++outer) {
+        // step 2: momentum matrix, right-hand sides, and the solves from u^r
+        if (dim == 2)
+            hipLaunchKernelGGL(k_momentum<2>, dim3(gpad), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs, ops->kind,
+                               B.ur, u, u_prev, u_bc, B.pr, rho, mu, dt, a1, a2, a3, 0, ops->mval, ops->mdinv, B.bm);
+        else
+            hipLaunchKernelGGL(k_momentum<3>, dim3(gpad), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs, ops->kind,
+                               B.ur, u, u_prev, u_bc, B.pr, rho, mu, dt, a1, a2, a3, 0, ops->mval, ops->mdinv, B.bm);
+        RB_HIP(hipGetLastError());
+        RB_HIP(hipMemcpyAsync(B.ut, B.ur, vec * dim, hipMemcpyDeviceToDevice, s));
+        KrylovResult km;
+        if (fp32) {
+            RB_CHECK(launch_to_fp32(ops->mval, ops->mval32, vs, s));
+            RB_CHECK(launch_to_fp32(ops->mdinv, ops->mdinv32, ops->npad, s));
+            RB_CHECK(bicgstab_fp32_ir(ctx, n, q, ops->col, ops->mval, ops->mval32, ops->mdinv32, dim, B.bm, B.ut,
+                                      o->tol_krylov, o->max_krylov, &km, nullptr, s));
+        } else {
+            RB_CHECK(bicgstab(ctx, n, q, ops->col, ops->mval, ops->mdinv, dim, B.bm, B.ut, o->tol_krylov, o->max_krylov,
+                              &km, s));
+        }
+        for (int e = 0; e < dim; ++e) {
+            kit_m += km.iters[e];
+            if (km.status[e] != RBFFD_OK && status == RBFFD_OK) status = km.status[e];
+        }
+        // step 3: pressure correction from p' = 0
+        const double mass = rho * a1 / dt;
+        if (dim == 2)
+            hipLaunchKernelGGL(k_div_rhs<2>, dim3(gn), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs, ops->kind,
+                               ops->pin, B.ut, mass, B.f);
+        else
+            hipLaunchKernelGGL(k_div_rhs<3>, dim3(gn), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs, ops->kind,
+                               ops->pin, B.ut, mass, B.f);
+        RB_HIP(hipMemsetAsync(B.pc, 0, vec, s));
+        KrylovResult kp;
+        if (fp32)
+            RB_CHECK(bicgstab_fp32_ir(ctx, n, q, ops->col, ops->pval, ops->pval32, ops->pdinv32, 1, B.f, B.pc,
+                                      o->tol_krylov, o->max_krylov, &kp, nullptr, s));
+        else
+            RB_CHECK(bicgstab(ctx, n, q, ops->col, ops->pval, ops->pdinv, 1, B.f, B.pc, o->tol_krylov, o->max_krylov,
+                              &kp, s));
+        kit_p += kp.iters[0];
+        if (kp.status[0] != RBFFD_OK && status == RBFFD_OK) status = kp.status[0];
+        // step 4: interior pressure
+        hipLaunchKernelGGL(k_p_interior, dim3(gn), dim3(kBlock), 0, s, n, ops->kind, B.pr, B.pc, p_bc ? p_bc : B.pr,
+                           B.pa);
+        // step 5: boundary pressure from the normal momentum equation
+        if (ops->nb > 0) {
+            const unsigned gb = (unsigned)((ops->nb + kBlock - 1) / kBlock);
+            if (dim == 2)
+                hipLaunchKernelGGL(k_boundary_rhs<2>, dim3(gb), dim3(kBlock), 0, s, n, ops->nb, q, ops->col, ops->val, vs,
+                                   ops->pval, ops->kind, ops->normal, ops->bidx, B.ut, u, u_prev, B.pa, B.pr, rho, mu,
+                                   dt, a1, a2, a3, B.bb, B.pb);
+            else
+                hipLaunchKernelGGL(k_boundary_rhs<3>, dim3(gb), dim3(kBlock), 0, s, n, ops->nb, q, ops->col, ops->val, vs,
+                                   ops->pval, ops->kind, ops->normal, ops->bidx, B.ut, u, u_prev, B.pa, B.pr, rho, mu,
+                                   dt, a1, a2, a3, B.bb, B.pb);
+            RB_HIP(hipGetLastError());
+            KrylovResult kb;
+            RB_CHECK(bicgstab(ctx, ops->nb, q, ops->gcol, ops->gval, ops->gdinv, 1, B.bb, B.pb, o->tol_krylov,
+                              o->max_krylov, &kb, s));
+            kit_b += kb.iters[0];
+            if (kb.status[0] != RBFFD_OK && status == RBFFD_OK) status = kb.status[0];
+        }
+        hipLaunchKernelGGL(k_p_scatter, dim3(gn), dim3(kBlock), 0, s, n, ops->kind, ops->bpos, B.pa, B.pb, B.pr);
+        // step 6 + 7: velocity correction and Delta
+        const double coef = dt / (rho * a1);
+        if (dim == 2)
+            hipLaunchKernelGGL(k_correct<2>, dim3(nblk), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs, ops->kind,
+                               B.pc, B.ut, B.ur, coef, B.un, B.part);
+        else
+            hipLaunchKernelGGL(k_correct<3>, dim3(nblk), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs, ops->kind,
+                               B.pc, B.ut, B.ur, coef, B.un, B.part);
+        hipLaunchKernelGGL(k_finish_sums, dim3(1), dim3(kBlock), 0, s, B.part, nblk, dim, n, dt, B.scal);
+        RB_HIP(hipGetLastError());
+        RB_HIP(hipMemcpyAsync(hs, B.scal, sizeof(double), hipMemcpyDeviceToHost, s));
+        RB_HIP(hipStreamSynchronize(s));
+        delta = hs[0];
+        std::swap(B.ur, B.un);
+        // step 8
+        if (delta < o->tol_outer) break;
+    }
+    if (outer > o->max_outer) {
+        outer = o->max_outer;
+        if (status == RBFFD_OK) status = RBFFD_E_NOCONV;
+    }
+    // steady rate, then rotate the time levels
+    hipLaunchKernelGGL(k_absdiff, dim3(nblk), dim3(kBlock), 0, s, n, dim, B.ur, u, B.part);
+    hipLaunchKernelGGL(k_finish_sums, dim3(1), dim3(kBlock), 0, s, B.part, nblk, dim, n, dt, B.scal + 2);
+    RB_HIP(hipGetLastError());
+    RB_HIP(hipMemcpyAsync(u_prev, u, vec * dim, hipMemcpyDeviceToDevice, s));
+    RB_HIP(hipMemcpyAsync(u, B.ur, vec * dim, hipMemcpyDeviceToDevice, s));
+    RB_HIP(hipMemcpyAsync(p, B.pr, vec, hipMemcpyDeviceToDevice, s));
+    RB_HIP(hipMemcpyAsync(hs + 2, B.scal + 2, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+    RB_HIP(hipStreamSynchronize(s));
+    st->outer_iters = outer;
+    st->krylov_mom = kit_m;
+    st->krylov_p = kit_p;
+    st->krylov_b = kit_b;
+    st->status = status;
+    st->delta = delta;
+    st->eps_steady = hs[3];
+    if (status != RBFFD_OK)
+        return fail(status, status == RBFFD_E_NOCONV ? "simple_step: an iteration limit was reached"
+                                                     : "simple_step: Krylov breakdown");
+    return RBFFD_OK;
+}
+
+int convdiff_lambda(rbffd_ctx *ctx, const rbffd_ops *ops, const double *u0, double rho, double mu, int iters,
+                    double *lambda, hipStream_t s)
+{
+    const int dim = ops->dim, q = ops->q;
+    const int64_t n = ops->n, vs = ops->npad * q;
+    char *w = nullptr;
+    RB_CHECK(workspace(ctx, WS_STEP, sizeof(double) * (2 * n + kMaxBlocks + 8), (void **)&w));
+    double *x = (double *)w, *y = x + n, *part = y + n, *nrm = part + kMaxBlocks;
+    const int gpad = (int)((ops->npad + kBlock - 1) / kBlock);
+    const int gn = (int)((n + kBlock - 1) / kBlock);
+    const int nblk = blocks_for(n);
+    if (dim == 2)
+        hipLaunchKernelGGL(k_momentum<2>, dim3(gpad), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs, ops->kind, u0,
+                           u0, u0, u0, u0, rho, mu, 1.0, 0.0, 0.0, 0.0, 1, ops->mval, ops->mdinv, y);
+    else
+        hipLaunchKernelGGL(k_momentum<3>, dim3(gpad), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs, ops->kind, u0,
+                           u0, u0, u0, u0, rho, mu, 1.0, 0.0, 0.0, 0.0, 1, ops->mval, ops->mdinv, y);
+    hipLaunchKernelGGL(k_pow_start, dim3(gn), dim3(kBlock), 0, s, n, y);
+    hipLaunchKernelGGL(k_sq_partial, dim3(nblk), dim3(kBlock), 0, s, n, y, part);
+    hipLaunchKernelGGL(k_normalise, dim3(nblk), dim3(kBlock), 0, s, n, y, x, part, nblk, nrm);
+    for (int it = 0; it < iters; ++it) {
+        RB_CHECK(spmv(n, q, ops->col, ops->mval, x, y, s));
+        hipLaunchKernelGGL(k_sq_partial, dim3(nblk), dim3(kBlock), 0, s, n, y, part);
+        hipLaunchKernelGGL(k_normalise, dim3(nblk), dim3(kBlock), 0, s, n, y, x, part, nblk, nrm);
+    }
+    RB_HIP(hipGetLastError());
+    double *hs = nullptr;
+    RB_CHECK(host_scratch(ctx, kHostStep, sizeof(double), (void **)&hs));
+    RB_HIP(hipMemcpyAsync(hs, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+    RB_HIP(hipStreamSynchronize(s));
+    *lambda = hs[0];
+    return RBFFD_OK;
+}
+
+}  // namespace rbffd

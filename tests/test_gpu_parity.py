@@ -1,0 +1,219 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: neighbour lists and CSR structure bit-exact; FP64 weights within 1e-10
+relative (per row, against the row's largest weight); operator applications
+within 1e-14; FP64 fields within 1e-8 relative (inf-norm per field); the
+mixed-precision path within 1e-5 of the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2106_07616_amd as R  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = R.Context(0)
+    yield c
+    c.close()
+
+
+def _rel_rows(a, b):
+    """max over rows of max|a - b| / max|b| (row-wise relative error)."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    num = np.abs(a - b).max(axis=-1)
+    den = np.maximum(np.abs(b).max(axis=-1), 1e-300)
+    return float((num / den).max())
+
+
+def _relinf(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+CLOUDS = {
+    "kovasznay40_k3": (lambda: W.kovasznay_square(nx=40), 3),          # the 40x40 Kovasznay case
+    "kovasznay23_k2": (lambda: W.kovasznay_square(nx=23), 2),          # ragged: n not a multiple of 64
+    "kovasznay20_k5": (lambda: W.kovasznay_square(nx=20), 5),
+    "tg_disk_k4": (lambda: W.taylor_green_disk(r=0.06), 4),
+    "holed_k3": (lambda: W.holed_square(3000, seed=1007, n_holes=3), 3),
+    "cube9_k2": (lambda: W.beltrami_cube(n=9), 2),
+    "cube10_k3": (lambda: W.beltrami_cube(n=10), 3),
+}
+
+
+@pytest.fixture(scope="module", params=list(CLOUDS))
+def case(request, ctx, orc):
+    gen, k = CLOUDS[request.param]
+    c = gen()
+    ops_o = orc.build_operators(c, k)
+    print(f"[case] {request.param}: n={c.n} q={ops_o.q} k={k}", flush=True)
+    solver = R.Solver(ctx, c, k)
+    torch.cuda.synchronize()
+    return request.param, c, k, ops_o, solver
+
+
+def test_knn_bit_exact(case):
+    name, c, k, ops_o, s = case
+    np.testing.assert_array_equal(s.nbr.cpu().numpy(), ops_o.nbr)
+
+
+def test_weights_parity(case):
+    name, c, k, ops_o, s = case
+    w = s.w.cpu().numpy()
+    err = _rel_rows(w, ops_o.w)
+    print(f"[weights] {name}: max row-relative diff {err:.3e}", flush=True)
+    assert err <= 1e-10
+
+
+def test_csr_structure_and_values(case, orc):
+    name, c, k, ops_o, s = case
+    col, val = s.ops.export_csr()
+    col = col.cpu().numpy()
+    val = val.cpu().numpy()
+    np.testing.assert_array_equal(col, ops_o.col)
+    # assembly is a pure permutation of the device's own weights
+    col_g, val_g = orc.csr(s.nbr.cpu().numpy(), s.w.cpu().numpy())
+    np.testing.assert_array_equal(val[:c.dim + 1], val_g)
+    # pressure-correction rows against the oracle's combination of the same weights
+    pv = orc.poisson_values(c, col_g, val_g)
+    assert _rel_rows(val[c.dim + 1], pv) <= 1e-14
+    assert _rel_rows(val[c.dim + 1], ops_o.pval) <= 1e-10
+
+
+def test_operator_application(case, orc):
+    name, c, k, ops_o, s = case
+    col, val = s.ops.export_csr()
+    col = col.cpu().numpy()
+    val = val.cpu().numpy()
+    x = np.sin(3 * c.xyz[:, 0]) * np.cos(2 * c.xyz[:, 1]) + 0.3
+    xt = torch.tensor(x, device="cuda")
+    for which in range(c.dim + 2):
+        y = s.ops.apply(which, xt).cpu().numpy()
+        ref = orc.spmv(col, val[which], x)
+        scale = np.abs(val[which]).sum(axis=1) * np.abs(x).max()
+        assert (np.abs(y - ref) <= 1e-14 * scale + 1e-300).all(), which
+
+
+def test_poisson_solve_parity(case, ctx, orc):
+    name, c, k, ops_o, s = case
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(c.n)
+    b[c.pin] = 0.0
+    xo, its_o, rr_o, st_o = orc.bicgstab(ops_o.col, ops_o.pval, b, tol=1e-12, maxit=20000)
+    bt = torch.tensor(b, device="cuda")
+    xg = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+    stats = R.poisson_solve(ctx, s.ops, bt, xg, tol=1e-12, max_iter=20000)
+    err = _relinf(xg.cpu().numpy(), xo)
+    print(f"[poisson] {name}: iters gpu {stats['iters']} oracle {its_o}, relres {stats['relres']:.2e}, "
+          f"diff {err:.2e}", flush=True)
+    assert st_o == 0 and stats["status"] == 0
+    assert stats["relres"] <= 1e-9      # true residual; the recursive one met 1e-12
+    assert err <= 1e-8
+
+
+def test_poisson_solve_mixed_precision(case, ctx, orc):
+    name, c, k, ops_o, s = case
+    rng = np.random.default_rng(4)
+    b = rng.standard_normal(c.n)
+    xo, _, _, _ = orc.bicgstab(ops_o.col, ops_o.pval, b, tol=1e-12, maxit=20000)
+    s32 = R.rbffd_assemble(s.ctx, s.dcloud, s.nbr, s.w, k, precision=R.RBFFD_FP32_IR)
+    xg = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+    stats = R.poisson_solve(ctx, s32, torch.tensor(b, device="cuda"), xg, tol=1e-10, max_iter=40000,
+                            precision=R.RBFFD_FP32_IR)
+    err = _relinf(xg.cpu().numpy(), xo)
+    print(f"[poisson fp32-ir] {name}: inner iters {stats['iters']} refinements {stats['refinements']} "
+          f"relres {stats['relres']:.2e} diff {err:.2e}", flush=True)
+    assert stats["relres"] <= 1e-10
+    assert err <= 1e-5
+
+
+def test_courant_eigenvalue(case, ctx, orc):
+    name, c, k, ops_o, s = case
+    if "flow" not in c.meta:
+        pytest.skip("no flow")
+    vel, _ = W.flow_fields(c)
+    lam_o = orc.convdiff_lambda(ops_o, vel, 1.0, 0.025)
+    lam_g = R.rbffd_convdiff_lambda(ctx, s.ops, torch.tensor(vel, device="cuda"), 1.0, 0.025)
+    assert abs(lam_g - lam_o) <= 1e-8 * abs(lam_o)
+
+
+def test_simple_step_parity(case, ctx, orc):
+    """Two outer iterations of one BDF2 step from the exact flow, Krylov solves at
+    1e-12: every field within 1e-8 (inf-norm relative) of the oracle."""
+    name, c, k, ops_o, s = case
+    if "flow" not in c.meta:
+        pytest.skip("no flow")
+    vel, p = W.flow_fields(c, 0.0)
+    nu = c.meta.get("nu", 0.025)
+    dt = 0.02
+    ubc_np, pbc_np = W.flow_fields(c, dt)
+    kw = dict(tol_outer=0.0, tol_krylov=1e-13, max_outer=2, max_krylov=20000)
+    uo, upo, po, sto = orc.simple_step(ops_o, vel, vel, p, ubc_np, 1.0, nu, dt, alpha=orc.BDF2,
+                                       p_bc=pbc_np, **kw)
+    u = torch.tensor(vel, device="cuda")
+    up = torch.tensor(vel, device="cuda")
+    pg = torch.tensor(p, device="cuda")
+    ubc = torch.tensor(ubc_np, device="cuda")
+    pbc = torch.tensor(pbc_np, device="cuda")
+    st = R.simple_step(ctx, s.ops, u, up, pg, ubc, 1.0, nu, dt, R.BDF2, p_bc=pbc, **kw)
+    eu = _relinf(u.cpu().numpy(), uo)
+    ep = _relinf(pg.cpu().numpy(), po)
+    print(f"[step] {name}: outer {st['outer_iters']} mom {st['krylov_mom']}/{sto['krylov_mom']} "
+          f"p {st['krylov_p']}/{sto['krylov_p']} b {st['krylov_b']}/{sto['krylov_b']} "
+          f"du {eu:.2e} dp {ep:.2e} delta {st['delta']:.3e}/{sto['delta']:.3e}", flush=True)
+    assert st["outer_iters"] == sto["outer_iters"] == 2
+    assert eu <= 1e-8 and ep <= 1e-8
+    assert abs(st["delta"] - sto["delta"]) <= 1e-8 * abs(sto["delta"])
+    np.testing.assert_array_equal(up.cpu().numpy(), vel)
+
+
+def test_determinism(ctx):
+    c = W.kovasznay_square(nx=30)
+    s = R.Solver(ctx, c, 3)
+    b = torch.tensor(np.random.default_rng(9).standard_normal(c.n), device="cuda")
+    xs = []
+    for _ in range(2):
+        x = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+        R.poisson_solve(ctx, s.ops, b, x, tol=1e-12, max_iter=20000)
+        xs.append(x.cpu().numpy())
+    np.testing.assert_array_equal(xs[0], xs[1])
+
+
+def test_singular_stencil_reported(ctx):
+    xyz = np.stack([np.arange(70.0), np.zeros(70)], 1)
+    c = W.Cloud(dim=2, xyz=xyz, kind=np.zeros(70, np.uint8), normal=np.zeros((70, 2)), pin=0)
+    dc = R.DeviceCloud.from_numpy(c)
+    with pytest.raises(R.RbffdError) as e:
+        R.rbffd_build_stencils(ctx, dc, 1)
+    assert e.value.code == -3
+
+
+def test_invalid_arguments_rejected(ctx):
+    c = W.kovasznay_square(nx=5)
+    dc = R.DeviceCloud.from_numpy(c)
+    with pytest.raises(R.RbffdError) as e:
+        R.rbffd_build_stencils(ctx, dc, 3, q=8)      # q <= m
+    assert e.value.code == -1
+    with pytest.raises(R.RbffdError):
+        R.rbffd_build_stencils(ctx, dc, 3, q=c.n + 1)
+    with pytest.raises(R.RbffdError):
+        R.rbffd_build_stencils(ctx, dc, 2, phs_power=4)
+
+
+def test_cloud_equal_to_whole_set(ctx, orc):
+    """q = n: every cloud is the whole point set."""
+    c = W.kovasznay_square(nx=3)     # 9 + 12 = 21 points
+    s = R.Solver(ctx, c, 2, q=c.n)
+    ref = orc.knn(c.xyz, c.n)
+    np.testing.assert_array_equal(s.nbr.cpu().numpy(), ref)
+    w = orc.weights(c.xyz, ref, 2)
+    assert _rel_rows(s.w.cpu().numpy(), w) <= 1e-10

@@ -11,7 +11,9 @@ Points are returned Morton-sorted (21 bits per dimension over the bounding box),
 which keeps stencil neighbours close in memory for the device kernels.
 
 Point kinds: 0 = interior, 1 = Dirichlet-velocity boundary (wall or inlet,
-where the pressure correction obeys a homogeneous Neumann condition).
+where the pressure correction obeys a homogeneous Neumann condition and the
+boundary pressure follows the normal momentum equation), 2 = Dirichlet-velocity
+boundary with prescribed pressure (pressure correction zero there).
 """
 from __future__ import annotations
 
@@ -21,6 +23,7 @@ import numpy as np
 
 INTERIOR = 0
 DIRICHLET = 1
+PRESCRIBED_PRESSURE = 2
 
 
 @dataclass
@@ -137,7 +140,8 @@ def morton_order(xyz: np.ndarray) -> np.ndarray:
     return np.argsort(code, kind="stable")
 
 
-def _finish(dim, xyz, kind, normal, name, h, meta, centre):
+def _finish(dim, xyz, kind, normal, name, h, meta, centre, boundary_kind=DIRICHLET):
+    kind = np.where(kind != INTERIOR, boundary_kind, INTERIOR).astype(np.uint8)
     order = morton_order(xyz)
     xyz = np.ascontiguousarray(xyz[order], dtype=np.float64)
     kind = np.ascontiguousarray(kind[order], dtype=np.uint8)
@@ -149,6 +153,8 @@ def _finish(dim, xyz, kind, normal, name, h, meta, centre):
     d2 = ((xyz - np.asarray(centre)) ** 2).sum(axis=1)
     d2 = np.where(kind == INTERIOR, d2, np.inf)
     pin = int(np.lexsort((np.arange(len(d2)), d2))[0])
+    if (kind == PRESCRIBED_PRESSURE).any():
+        pin = -1   # the prescribed boundary pressure fixes the pressure level
     return Cloud(dim=dim, xyz=xyz, kind=kind, normal=normal, pin=pin, name=name, h=h, meta=meta)
 
 
@@ -181,7 +187,7 @@ def _square_perimeter(lo, hi, per_edge):
 # --------------------------------------------------------------------------
 
 def kovasznay_square(nx: int = 40, seed: int = 1, jitter: float = 0.2, Re: float = 40.0,
-                     lo: float = -0.5, hi: float = 1.5) -> Cloud:
+                     lo: float = -0.5, hi: float = 1.5, boundary_kind: int = DIRICHLET) -> Cloud:
     """Kovasznay flow on [lo, hi]^2: a cell-centred nx-by-nx interior lattice with each
     coordinate jittered by U(-jitter*h, jitter*h), plus 4*nx boundary points at spacing h."""
     rng = np.random.default_rng(seed)
@@ -196,7 +202,7 @@ def kovasznay_square(nx: int = 40, seed: int = 1, jitter: float = 0.2, Re: float
     normal = np.concatenate([np.zeros_like(inter), bnrm])
     return _finish(2, xyz, kind, normal, f"kovasznay_{nx}", h,
                    {"flow": "kovasznay", "Re": Re, "nu": 1.0 / Re, "seed": seed},
-                   centre=((lo + hi) / 2, (lo + hi) / 2))
+                   centre=((lo + hi) / 2, (lo + hi) / 2), boundary_kind=boundary_kind)
 
 
 def poisson_disk(rng, lo, hi, r, rounds=24):
@@ -239,7 +245,7 @@ TG_RADIUS_250K = 0.01025
 
 
 def taylor_green_disk(r: float = TG_RADIUS_250K, seed: int = 2, nu: float = 0.01,
-                      rounds: int = 24) -> Cloud:
+                      rounds: int = 24, boundary_kind: int = PRESCRIBED_PRESSURE) -> Cloud:
     """Taylor-Green vortex on [0, 2*pi]^2: Poisson-disk interior of radius r (interior
     points closer than r/2 to the boundary dropped) and boundary points at spacing ~r."""
     rng = np.random.default_rng(seed)
@@ -255,10 +261,11 @@ def taylor_green_disk(r: float = TG_RADIUS_250K, seed: int = 2, nu: float = 0.01
     normal = np.concatenate([np.zeros_like(inter), bnrm])
     return _finish(2, xyz, kind, normal, f"taylor_green_{len(xyz)}", r,
                    {"flow": "taylor_green", "nu": nu, "seed": seed},
-                   centre=(np.pi, np.pi))
+                   centre=(np.pi, np.pi), boundary_kind=boundary_kind)
 
 
-def beltrami_cube(n: int = 100, seed: int = 4, jitter: float = 0.2, nu: float = 0.01) -> Cloud:
+def beltrami_cube(n: int = 100, seed: int = 4, jitter: float = 0.2, nu: float = 0.01,
+                  boundary_kind: int = PRESCRIBED_PRESSURE) -> Cloud:
     """Ethier-Steinman flow on [0,1]^3: a cell-centred n^3 lattice jittered by
     U(-jitter*h, jitter*h) per coordinate, plus the cell-centred n^2 lattice of each
     of the six faces (no edge or corner points)."""
@@ -288,7 +295,8 @@ def beltrami_cube(n: int = 100, seed: int = 4, jitter: float = 0.2, nu: float = 
     kind = np.concatenate([np.zeros(len(inter), np.uint8), np.ones(len(bpts), np.uint8)])
     normal = np.concatenate([np.zeros_like(inter), bnrm])
     return _finish(3, xyz, kind, normal, f"beltrami_{n}", h,
-                   {"flow": "beltrami", "nu": nu, "seed": seed}, centre=(0.5, 0.5, 0.5))
+                   {"flow": "beltrami", "nu": nu, "seed": seed}, centre=(0.5, 0.5, 0.5),
+                   boundary_kind=boundary_kind)
 
 
 def holed_square(n_target: int, seed: int, n_holes: int | None = None, Re: float = 40.0,
@@ -350,8 +358,8 @@ def scattered_square(nx: int, seed: int = 7, jitter: float = 0.2, lo: float = 0.
     return c
 
 
-def scattered_cube(n: int, seed: int = 9, jitter: float = 0.2) -> Cloud:
-    c = beltrami_cube(n=n, seed=seed, jitter=jitter)
+def scattered_cube(n: int, seed: int = 9, jitter: float = 0.2, boundary_kind: int = DIRICHLET) -> Cloud:
+    c = beltrami_cube(n=n, seed=seed, jitter=jitter, boundary_kind=boundary_kind)
     c.meta = {"flow": "beltrami", "nu": 0.01, "seed": seed}
     c.name = f"cube_{n}"
     return c
