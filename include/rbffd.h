@@ -138,7 +138,8 @@ int rbffd_ops_info(const rbffd_ops *ops, int64_t *n, int *q, int *dim, int64_t *
  * holding d/dx, d/dy, (d/dz), Laplacian and the pressure-correction matrix. */
 int rbffd_ops_export_csr(const rbffd_ops *ops, int32_t *col, double *val, void *hip_stream);
 /* y = A x for operator `which` (0..dim-1: d/dx_e, dim: Laplacian, dim+1: the
- * pressure-correction matrix); x, y device [n]. */
+ * pressure-correction matrix); x, y device [n]. Enqueued on the stream and not
+ * synchronised (one kernel launch). */
 int rbffd_apply(rbffd_ctx *ctx, const rbffd_ops *ops, int which, const double *x, double *y,
                 void *hip_stream);
 
@@ -153,6 +154,8 @@ typedef struct {
     int iters;              /* BiCGSTAB iterations (FP32_IR: inner iterations, all sweeps) */
     int status;             /* RBFFD_OK / RBFFD_E_NOCONV / RBFFD_E_BREAKDOWN         */
     int refinements;        /* FP32_IR: FP64 residual refinement sweeps              */
+    int fp64_fallback;      /* FP32_IR: 1 when an FP32 sweep failed to halve the FP64
+                               residual and the solve finished with FP64 sweeps      */
     double relres;          /* true FP64 residual ||b - A x|| / ||b|| at return      */
 } rbffd_krylov_stats;
 

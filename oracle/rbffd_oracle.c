@@ -411,9 +411,9 @@ static double diag_value(int q, const int32_t *col, const double *val, int64_t i
 
 typedef void (*orc_apply_fn)(const void *ctx, const double *x, double *y);
 
-static int bicgstab_op(int64_t n, orc_apply_fn apply, const void *actx, const double *dinv,
-                       const double *b, double *x, double tol, int maxit, int *iters_out,
-                       double *relres_out)
+static int bicgstab_run(int64_t n, orc_apply_fn apply, const void *actx, const double *dinv,
+                        const double *b, double *x, double tol, int maxit, int *iters_out,
+                        double *relres_out)
 {
     double *r = (double *)malloc(sizeof(double) * n);
     double *rh = (double *)malloc(sizeof(double) * n);
@@ -489,6 +489,33 @@ done:
     if (relres_out) *relres_out = relres;
     free(r); free(rh); free(pv); free(ph); free(v); free(s); free(sh); free(t);
     return status;
+}
+
+/* BiCGSTAB with up to two restarts from the true residual: when the recursive
+ * residual has met the tolerance but ||b - A x|| exceeds 10 tol ||b||, the
+ * iteration starts again from the current x. */
+static int bicgstab_op(int64_t n, orc_apply_fn apply, const void *actx, const double *dinv,
+                       const double *b, double *x, double tol, int maxit, int *iters_out,
+                       double *relres_out)
+{
+    double *r = (double *)malloc(sizeof(double) * n);
+    const double bn = sqrt(dot(n, b, b));
+    int total = 0, st = ORC_OK;
+    double rel = 0.0;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        int its = 0;
+        st = bicgstab_run(n, apply, actx, dinv, b, x, tol, maxit - total, &its, &rel);
+        total += its;
+        if (st != ORC_OK || bn == 0.0) break;
+        apply(actx, x, r);
+        for (int64_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
+        rel = sqrt(dot(n, r, r)) / bn;
+        if (rel <= 10.0 * tol || total >= maxit) break;
+    }
+    free(r);
+    if (iters_out) *iters_out = total;
+    if (relres_out) *relres_out = rel;
+    return st;
 }
 
 typedef struct {

@@ -48,7 +48,8 @@ class KrylovOptsT(C.Structure):
 
 
 class KrylovStatsT(C.Structure):
-    _fields_ = [("iters", C.c_int), ("status", C.c_int), ("refinements", C.c_int), ("relres", C.c_double)]
+    _fields_ = [("iters", C.c_int), ("status", C.c_int), ("refinements", C.c_int), ("fp64_fallback", C.c_int),
+                ("relres", C.c_double)]
 
 
 class StepOptsT(C.Structure):
@@ -237,7 +238,8 @@ def poisson_solve(ctx: Context, ops: Operators, rhs: torch.Tensor, x: torch.Tens
     s = KrylovStatsT()
     st = lib().poisson_solve(ctx.handle, ops.handle, _ptr(rhs), _ptr(x), C.byref(o), C.byref(s), _stream())
     _check(st, allow=(RBFFD_E_NOCONV,) if allow_noconv else ())
-    return dict(iters=s.iters, status=s.status, refinements=s.refinements, relres=s.relres)
+    return dict(iters=s.iters, status=s.status, refinements=s.refinements, fp64_fallback=s.fp64_fallback,
+                relres=s.relres)
 
 
 BDF2 = (1.5, -2.0, 0.5)

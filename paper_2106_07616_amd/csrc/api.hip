@@ -280,7 +280,7 @@ int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, doubl
         st = bicgstab(ctx, ops->n, ops->q, ops->col, ops->pval, ops->pdinv, 1, rhs, x, opts->tol,
                       opts->max_iter, &res, s);
     else
-        st = bicgstab_fp32_ir(ctx, ops->n, ops->q, ops->col, ops->pval, ops->pval32, ops->pdinv32, 1,
+        st = bicgstab_fp32_ir(ctx, ops->n, ops->q, ops->col, ops->pval, ops->pval32, ops->pdinv32, ops->pdinv, 1,
                               rhs, x, opts->tol, opts->max_iter, &res, &refine, s);
     if (st != RBFFD_OK) return st;
     double rr = 0.0;
@@ -289,6 +289,7 @@ int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, doubl
         stats->iters = res.iters[0];
         stats->status = res.status[0];
         stats->refinements = refine;
+        stats->fp64_fallback = res.fp64_fallback ? 1 : 0;
         stats->relres = rr;
     }
     if (res.status[0] != RBFFD_OK)

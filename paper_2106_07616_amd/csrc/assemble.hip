@@ -292,9 +292,7 @@ int apply_op(rbffd_ctx *ctx, const rbffd_ops *ops, int which, const double *x, d
 {
     (void)ctx;
     const double *v = (which <= ops->dim) ? ops->val + (int64_t)which * ops->npad * ops->q : ops->pval;
-    RB_CHECK(spmv(ops->n, ops->q, ops->col, v, x, y, s));
-    RB_HIP(hipStreamSynchronize(s));
-    return RBFFD_OK;
+    return spmv(ops->n, ops->q, ops->col, v, x, y, s);
 }
 
 }  // namespace rbffd

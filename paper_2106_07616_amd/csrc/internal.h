@@ -202,13 +202,14 @@ struct KrylovResult {
     int iters[kMaxRhs] = {0, 0, 0};
     int status[kMaxRhs] = {0, 0, 0};
     double relres[kMaxRhs] = {0, 0, 0};
+    bool fp64_fallback = false;   // FP32 sweeps stalled; finished in FP64
 };
 int bicgstab(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val,
              const double *dinv, int nrhs, const double *b, double *x, double tol, int max_iter,
              KrylovResult *res, hipStream_t s);
 int bicgstab_fp32_ir(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val,
-                     const float *val32, const float *dinv32, int nrhs, const double *b, double *x,
-                     double tol, int max_iter, KrylovResult *res, int *refinements, hipStream_t s);
+                     const float *val32, const float *dinv32, const double *dinv64, int nrhs, const double *b,
+                     double *x, double tol, int max_iter, KrylovResult *res, int *refinements, hipStream_t s);
 int spmv(int64_t n, int q, const int32_t *col, const double *val, const double *x, double *y,
          hipStream_t s);
 int residual_norms(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val,

@@ -554,8 +554,9 @@ int spmv(int64_t n, int q, const int32_t *col, const double *val, const double *
     return RBFFD_OK;
 }
 
-int bicgstab(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val, const double *dinv, int nrhs,
-             const double *b, double *x, double tol, int max_iter, KrylovResult *res, hipStream_t s)
+static int bicgstab_once(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val,
+                         const double *dinv, int nrhs, const double *b, double *x, double tol, int max_iter,
+                         KrylovResult *res, hipStream_t s)
 {
     Work w;
     RB_CHECK(get_work<double>(ctx, pad64(n), nrhs, &w));
@@ -567,12 +568,45 @@ int bicgstab(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double 
     }
 }
 
+// BiCGSTAB with up to two restarts from the true residual: when the recursive
+// residual has met tol but ||b - A x|| exceeds 10 tol ||b||, iterate again from x.
+int bicgstab(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val, const double *dinv, int nrhs,
+             const double *b, double *x, double tol, int max_iter, KrylovResult *res, hipStream_t s)
+{
+    KrylovResult acc;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        int left = max_iter;
+        for (int k = 0; k < nrhs; ++k) left = std::min(left, max_iter - acc.iters[k]);
+        KrylovResult r1;
+        RB_CHECK(bicgstab_once(ctx, n, q, col, val, dinv, nrhs, b, x, tol, std::max(left, 0), &r1, s));
+        bool ok = true;
+        for (int k = 0; k < nrhs; ++k) {
+            acc.iters[k] += r1.iters[k];
+            acc.status[k] = r1.status[k];
+            ok = ok && r1.status[k] == RBFFD_OK;
+        }
+        if (!ok || left <= 0) break;
+        double rr[kMaxRhs];
+        RB_CHECK(residual_norms(ctx, n, q, col, val, nrhs, b, x, rr, s));
+        bool good = true;
+        for (int k = 0; k < nrhs; ++k) {
+            acc.relres[k] = rr[k];
+            good = good && rr[k] <= 10.0 * tol;
+        }
+        if (good) break;
+    }
+    *res = acc;
+    return RBFFD_OK;
+}
+
 // Mixed precision: FP32 matrix, vectors and sweeps with FP64 dot accumulation
 // inside; FP64 residual b - A x and FP64 update of x outside, repeated until
 // the FP64 residual meets tol.
+constexpr int kMaxInnerSweep = 4000;   // FP32 iterations per refinement sweep
+
 int bicgstab_fp32_ir(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val, const float *val32,
-                     const float *dinv32, int nrhs, const double *b, double *x, double tol, int max_iter,
-                     KrylovResult *res, int *refinements, hipStream_t s)
+                     const float *dinv32, const double *dinv64, int nrhs, const double *b, double *x, double tol,
+                     int max_iter, KrylovResult *res, int *refinements, hipStream_t s)
 {
     if (nrhs < 1 || nrhs > kMaxRhs) return fail(RBFFD_E_ARG, "nrhs must be 1..3");
     const int64_t np = pad64(n);
@@ -580,10 +614,12 @@ int bicgstab_fp32_ir(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const
     RB_CHECK(get_work<float>(ctx, np, nrhs, &w));
     char *scr = nullptr;
     const size_t rbytes = sizeof(double) * (2 * kMaxRhs * kMaxBlocks + kMaxRhs);
-    RB_CHECK(workspace(ctx, WS_REFINE, sizeof(float) * np * nrhs * 2 + rbytes, (void **)&scr));
+    const size_t xbytes = sizeof(double) * n * nrhs;
+    RB_CHECK(workspace(ctx, WS_REFINE, rbytes + xbytes + sizeof(float) * np * nrhs * 2, (void **)&scr));
     double *resid_dev = (double *)scr;
     double *rout = resid_dev + 2 * kMaxRhs * kMaxBlocks;
-    float *rb = (float *)(scr + rbytes);
+    double *xgood = (double *)(scr + rbytes);      // last iterate with a finite, improving residual
+    float *rb = (float *)(scr + rbytes + xbytes);
     float *dx = rb + np * nrhs;
     double *rr = nullptr;
     RB_CHECK(host_scratch(ctx, kHostRefine, sizeof(double) * kMaxRhs, (void **)&rr));
@@ -592,7 +628,8 @@ int bicgstab_fp32_ir(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const
     int nref = 0;
     const int nblk = grid_blocks(n);
     const unsigned gb = (unsigned)((n + kBlock - 1) / kBlock);
-    bool converged = false;
+    bool converged = false, stalled = false;
+    double prev[kMaxRhs] = {0, 0, 0};
     for (int sweep = 0; sweep < 200; ++sweep) {
         // FP64 residual norm of the current iterate
         hipLaunchKernelGGL(k_resid, dim3(nblk), dim3(kBlock), 0, s, n, q, nrhs, col, val, b, n, x, n, resid_dev);
@@ -606,6 +643,28 @@ int bicgstab_fp32_ir(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const
         int left = max_iter;
         for (int k = 0; k < nrhs; ++k) left = std::min(left, max_iter - total_it[k]);
         if (left <= 0) break;
+        // a sweep that did not halve the FP64 residual (or went non-finite): FP32
+        // cannot resolve this system; return to the last good iterate and finish
+        // with FP64 sweeps
+        if (sweep > 0) {
+            for (int k = 0; k < nrhs; ++k) stalled = stalled || !(rr[k] <= 0.5 * prev[k]);
+        }
+        if (stalled) RB_HIP(hipMemcpyAsync(x, xgood, xbytes, hipMemcpyDeviceToDevice, s));
+        for (int k = 0; k < nrhs; ++k) prev[k] = rr[k];
+        if (stalled) {
+            KrylovResult fr;
+            RB_CHECK(bicgstab(ctx, n, q, col, val, dinv64, nrhs, b, x, tol, left, &fr, s));
+            for (int k = 0; k < nrhs; ++k) {
+                total_it[k] += fr.iters[k];
+                rr[k] = fr.relres[k];
+            }
+            ++nref;
+            converged = true;
+            for (int k = 0; k < nrhs; ++k) converged = converged && fr.status[k] == RBFFD_OK;
+            break;
+        }
+        RB_HIP(hipMemcpyAsync(xgood, x, xbytes, hipMemcpyDeviceToDevice, s));
+        left = std::min(left, kMaxInnerSweep);
         // FP32 correction equation A d = b - A x from d = 0
         hipLaunchKernelGGL(k_refine_res, dim3(gb), dim3(kBlock), 0, s, n, q, nrhs, col, val, b, n, x, n, rb, np);
         hipLaunchKernelGGL(k_zero_f, dim3((unsigned)((np * nrhs + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, dx,
@@ -625,9 +684,10 @@ int bicgstab_fp32_ir(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const
     }
     for (int k = 0; k < nrhs; ++k) {
         res->iters[k] = total_it[k];
-        res->status[k] = (rr[k] <= tol) ? RBFFD_OK : RBFFD_E_NOCONV;
+        res->status[k] = (rr[k] <= tol || (stalled && converged)) ? RBFFD_OK : RBFFD_E_NOCONV;
         res->relres[k] = rr[k];
     }
+    res->fp64_fallback = stalled;
     if (refinements) *refinements = nref;
     return RBFFD_OK;
 }

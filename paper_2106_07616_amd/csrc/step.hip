@@ -352,8 +352,8 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
         if (fp32) {
             RB_CHECK(launch_to_fp32(ops->mval, ops->mval32, vs, s));
             RB_CHECK(launch_to_fp32(ops->mdinv, ops->mdinv32, ops->npad, s));
-            RB_CHECK(bicgstab_fp32_ir(ctx, n, q, ops->col, ops->mval, ops->mval32, ops->mdinv32, dim, B.bm, B.ut,
-                                      o->tol_krylov, o->max_krylov, &km, nullptr, s));
+            RB_CHECK(bicgstab_fp32_ir(ctx, n, q, ops->col, ops->mval, ops->mval32, ops->mdinv32, ops->mdinv, dim, B.bm,
+                                      B.ut, o->tol_krylov, o->max_krylov, &km, nullptr, s));
         } else {
             RB_CHECK(bicgstab(ctx, n, q, ops->col, ops->mval, ops->mdinv, dim, B.bm, B.ut, o->tol_krylov, o->max_krylov,
                               &km, s));
@@ -373,8 +373,8 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
         RB_HIP(hipMemsetAsync(B.pc, 0, vec, s));
         KrylovResult kp;
         if (fp32)
-            RB_CHECK(bicgstab_fp32_ir(ctx, n, q, ops->col, ops->pval, ops->pval32, ops->pdinv32, 1, B.f, B.pc,
-                                      o->tol_krylov, o->max_krylov, &kp, nullptr, s));
+            RB_CHECK(bicgstab_fp32_ir(ctx, n, q, ops->col, ops->pval, ops->pval32, ops->pdinv32, ops->pdinv, 1, B.f,
+                                      B.pc, o->tol_krylov, o->max_krylov, &kp, nullptr, s));
         else
             RB_CHECK(bicgstab(ctx, n, q, ops->col, ops->pval, ops->pdinv, 1, B.f, B.pc, o->tol_krylov, o->max_krylov,
                               &kp, s));

@@ -295,7 +295,7 @@ def test_bicgstab_matches_direct_solve(orc):
     A = sp.csr_matrix((ops.pval.ravel(), ops.col.ravel(), np.arange(0, n * q + 1, q)), shape=(n, n))
     b = np.random.default_rng(1).standard_normal(n)
     x, its, rr, st = orc.bicgstab(ops.col, ops.pval, b, tol=1e-12)
-    assert st == 0 and rr <= 1e-12
+    assert st == 0 and rr <= 1e-11     # true residual after the restart rule (<= 10 tol)
     xd = spl.spsolve(A.tocsc(), b)
     assert np.linalg.norm(A @ x - b) <= 1e-10 * np.linalg.norm(b)   # true vs recursive residual drift
     assert np.abs(x - xd).max() <= 1e-7 * np.abs(xd).max()
