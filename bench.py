@@ -135,7 +135,15 @@ def main():
     spmv_gbs = spmv_bytes(n, q) / (spmv_ms * 1e-3) / 1e9
     log(f"[bench] spmv: {spmv_ms * 1e3:.1f} us/launch, {spmv_gbs:.0f} GB/s algorithmic")
     if args.spmv_only:
-        print(json.dumps({"spmv_us": spmv_ms * 1e3, "spmv_gbs": spmv_gbs, "n": n, "q": q}))
+        # calibration for hardware byte counters: a plain copy of a known size
+        # (64 Mi doubles = 512 MiB read + 512 MiB written per launch)
+        src = torch.ones(64 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"spmv_us": spmv_ms * 1e3, "spmv_gbs": spmv_gbs, "n": n, "q": q,
+                          "bytes_per_launch": spmv_bytes(n, q), "copy_bytes_each_way": src.numel() * 8}))
         return
 
     # ---- pressure-correction BiCGSTAB alone: time per iteration --------------

@@ -46,26 +46,50 @@ __device__ inline double *partial(double *base, int kind, int r) { return base +
 template <typename T>
 __device__ inline int64_t row_base(int64_t i, int q) { return ((i >> 6) * (int64_t)q) * 64 + (i & 63); }
 
-// acc[r] = sum_a A[i,a] x_r[col]; entries in column order.
+// acc[r] = sum_a A[i,a] x_r[col] for the right-hand sides with act[r]; entries in
+// column order. The activity test sits outside the entry loop so the loop body
+// is branch-free and the compiler can keep several column/value/gather loads in
+// flight.
 template <typename T, int NRHS>
 __device__ inline void row_dot(int64_t i, int q, const int32_t *__restrict__ col, const T *__restrict__ val,
                                const T *__restrict__ x, int64_t xs, const bool *act, double *acc)
 {
     const int64_t base = row_base<T>(i, q);
-    T s[NRHS];
+    bool all = true, any = false;
 #pragma unroll
-    for (int r = 0; r < NRHS; ++r) s[r] = 0;
-#pragma unroll 4
-    for (int a = 0; a < q; ++a) {
-        const int64_t slot = base + (int64_t)a * 64;
-        const int32_t c = col[slot];
-        const T v = val[slot];
-#pragma unroll
-        for (int r = 0; r < NRHS; ++r)
-            if (act[r]) s[r] = fma(v, x[r * xs + c], s[r]);
+    for (int r = 0; r < NRHS; ++r) {
+        all = all && act[r];
+        any = any || act[r];
     }
 #pragma unroll
-    for (int r = 0; r < NRHS; ++r) acc[r] = (double)s[r];
+    for (int r = 0; r < NRHS; ++r) acc[r] = 0.0;
+    if (!any) return;
+    if (all) {
+        T s[NRHS];
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) s[r] = 0;
+#pragma unroll 4
+        for (int a = 0; a < q; ++a) {
+            const int64_t slot = base + (int64_t)a * 64;
+            const int32_t c = col[slot];
+            const T v = val[slot];
+#pragma unroll
+            for (int r = 0; r < NRHS; ++r) s[r] = fma(v, x[r * xs + c], s[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) acc[r] = (double)s[r];
+        return;
+    }
+    for (int r = 0; r < NRHS; ++r) {
+        if (!act[r]) continue;
+        T s1 = 0;
+#pragma unroll 4
+        for (int a = 0; a < q; ++a) {
+            const int64_t slot = base + (int64_t)a * 64;
+            s1 = fma(val[slot], x[r * xs + col[slot]], s1);
+        }
+        acc[r] = (double)s1;
+    }
 }
 
 __device__ inline int logical_block() { return xcd_block(gridDim.x); }
@@ -138,15 +162,65 @@ __global__ __launch_bounds__(kBlock) void k_init(int64_t n, int64_t np, int q, c
     }
 }
 
-// Common prologue: sums of r-hat.r, r.r, b.b, and the per-RHS decisions.
+// Sums of NV partial arrays (np entries each) in a fixed order, identical in
+// every block: all loads are issued before any add, then one block reduction.
+template <int NV>
+__device__ inline void sum_partials_n(const double *const *parts, int np, double *out)
+{
+    __shared__ double red[NV][kBlock / 64];
+    constexpr int kPer = kMaxBlocks / kBlock;
+    double ld[NV][kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int i = threadIdx.x + j * kBlock;
+#pragma unroll
+        for (int m = 0; m < NV; ++m) ld[m][j] = (i < np) ? parts[m][i] : 0.0;
+    }
+    double v[NV];
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        v[m] = 0.0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) v[m] += ld[m][j];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int m = 0; m < NV; ++m) v[m] += __shfl_xor(v[m], o, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0)
+#pragma unroll
+        for (int m = 0; m < NV; ++m) red[m][w] = v[m];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < kBlock / 64; ++j) t += red[m][j];
+        out[m] = t;
+    }
+}
+
+// Common prologue: sums of r-hat.r, r.r, b.b for every right-hand side.
 template <int NRHS>
 __device__ inline void prologue_rho(const double *part, int np, double *lds, Scal &sc)
 {
+    (void)lds;
+    const double *ps[3 * NRHS];
+    double out[3 * NRHS];
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) {
-        sc.rhr[k] = sum_partials(partial((double *)part, P_RHR, k), np, lds);
-        sc.rr[k] = sum_partials(partial((double *)part, P_RR, k), np, lds);
-        sc.bb[k] = sum_partials(partial((double *)part, P_BB, k), np, lds);
+        ps[3 * k + 0] = partial((double *)part, P_RHR, k);
+        ps[3 * k + 1] = partial((double *)part, P_RR, k);
+        ps[3 * k + 2] = partial((double *)part, P_BB, k);
+    }
+    sum_partials_n<3 * NRHS>(ps, np, out);
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+        sc.rhr[k] = out[3 * k + 0];
+        sc.rr[k] = out[3 * k + 1];
+        sc.bb[k] = out[3 * k + 2];
     }
 }
 
@@ -245,7 +319,26 @@ __global__ __launch_bounds__(kBlock) void k_s(int64_t n, int64_t np, const T *__
     __shared__ double lds[kBlock / 64];
     if (all_done<NRHS>(st, phase)) return;
     Scal sc;
-    prologue_rho<NRHS>(part, nblk, lds, sc);
+    double rvs[NRHS];
+    {
+        const double *ps[4 * NRHS];
+        double out[4 * NRHS];
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            ps[4 * k + 0] = partial(part, P_RHR, k);
+            ps[4 * k + 1] = partial(part, P_RR, k);
+            ps[4 * k + 2] = partial(part, P_BB, k);
+            ps[4 * k + 3] = partial(part, P_RV, k);
+        }
+        sum_partials_n<4 * NRHS>(ps, nblk, out);
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            sc.rhr[k] = out[4 * k + 0];
+            sc.rr[k] = out[4 * k + 1];
+            sc.bb[k] = out[4 * k + 2];
+            rvs[k] = out[4 * k + 3];
+        }
+    }
     bool act[NRHS];
     double alpha[NRHS];
 #pragma unroll
@@ -253,7 +346,7 @@ __global__ __launch_bounds__(kBlock) void k_s(int64_t n, int64_t np, const T *__
         const KState stk = st[k];
         act[k] = !finished_before(stk, phase);
         const double rho = want_restart(stk, sc.rhr[k], sc.rr[k]) ? sc.rr[k] : sc.rhr[k];
-        const double rv = sum_partials(partial(part, P_RV, k), nblk, lds);
+        const double rv = rvs[k];
         alpha[k] = (rv != 0.0) ? rho / rv : 0.0;
         if (act[k] && blockIdx.x == 0 && threadIdx.x == 0) {
             st[k].alpha = alpha[k];
@@ -298,13 +391,23 @@ __global__ __launch_bounds__(kBlock) void k_t(int64_t n, int64_t np, int q, cons
     if (all_done<NRHS>(st, phase)) return;
     bool act[NRHS], half[NRHS];
     double alpha[NRHS];
+    double sums[2 * NRHS];
+    {
+        const double *ps[2 * NRHS];
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            ps[2 * k] = partial(part, P_SS, k);
+            ps[2 * k + 1] = partial(part, P_BB, k);
+        }
+        sum_partials_n<2 * NRHS>(ps, nblk, sums);
+    }
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) {
         const KState stk = st[k];
         act[k] = !finished_before(stk, phase);
         alpha[k] = stk.alpha;
-        const double ss = sum_partials(partial(part, P_SS, k), nblk, lds);
-        const double bb = sum_partials(partial(part, P_BB, k), nblk, lds);
+        const double ss = sums[2 * k];
+        const double bb = sums[2 * k + 1];
         half[k] = act[k] && ss <= tol2 * bb;
         if (half[k] && blockIdx.x == 0 && threadIdx.x == 0) {
             st[k].done_at = phase;
@@ -356,13 +459,23 @@ __global__ __launch_bounds__(kBlock) void k_x(int64_t n, int64_t np, T *__restri
     if (all_done<NRHS>(st, phase)) return;
     bool act[NRHS];
     double alpha[NRHS], omega[NRHS];
+    double sums[2 * NRHS];
+    {
+        const double *ps[2 * NRHS];
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            ps[2 * k] = partial(part, P_TS, k);
+            ps[2 * k + 1] = partial(part, P_TT, k);
+        }
+        sum_partials_n<2 * NRHS>(ps, nblk, sums);
+    }
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) {
         const KState stk = st[k];
         act[k] = !finished_before(stk, phase);
         alpha[k] = stk.alpha;
-        const double ts = sum_partials(partial(part, P_TS, k), nblk, lds);
-        const double tt = sum_partials(partial(part, P_TT, k), nblk, lds);
+        const double ts = sums[2 * k];
+        const double tt = sums[2 * k + 1];
         omega[k] = (tt > 0.0) ? ts / tt : 0.0;
         if (act[k] && blockIdx.x == 0 && threadIdx.x == 0) {
             st[k].omega = omega[k];
