@@ -23,12 +23,33 @@ namespace {
 // records its launch sequence number in done_at; blocks of that same launch keep
 // working (they may still owe updates of their rows), later launches skip.
 struct KState {
-    double rho_prev, alpha, omega;
+    double rho_prev;  // r-hat . r of the previous iteration
+    double rho_cur;   // r-hat . r of this iteration (after a restart: r . r)
+    double alpha, omega;
     int done_at;  // 0 running, else sequence number of the launch that finished
     int iters;    // completed iterations
     int status;   // RBFFD_OK / RBFFD_E_BREAKDOWN
     int pad;
 };
+
+// BiCGSTAB kernels run 512-thread blocks on at most 1024 blocks, so that a
+// consumer kernel re-reduces at most 1024 partials per dot product.
+constexpr int kKB = 512;
+constexpr int kKMaxBlocks = 1024;
+static_assert(kKMaxBlocks <= kMaxBlocks, "partial arrays hold kMaxBlocks entries");
+
+__device__ inline double kblock_sum(double v, double *lds)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) lds[w] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kKB / 64; ++i) t += lds[i];
+    return t;
+}
 
 __device__ inline bool finished_before(const KState &s, int phase) { return s.done_at != 0 && s.done_at < phase; }
 
@@ -124,19 +145,19 @@ __device__ inline bool all_done(const KState *st, int phase)
 
 // r = b - A x, r-hat = r; partials r-hat.r, r.r, b.b
 template <typename T, int NRHS>
-__global__ __launch_bounds__(kBlock) void k_init(int64_t n, int64_t np, int q, const int32_t *__restrict__ col,
+__global__ __launch_bounds__(kKB) void k_init(int64_t n, int64_t np, int q, const int32_t *__restrict__ col,
                                                  const T *__restrict__ val, const T *__restrict__ b, int64_t bs,
                                                  const T *__restrict__ x, int64_t xs, T *__restrict__ r,
                                                  T *__restrict__ rh, double *__restrict__ part)
 {
-    __shared__ double lds[kBlock / 64];
+    __shared__ double lds[kKB / 64];
     double srr[NRHS], sbb[NRHS];
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) srr[k] = sbb[k] = 0.0;
     bool act[NRHS];
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) act[k] = true;
-    for (int64_t i = (int64_t)logical_block() * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kKB) {
         double ax[NRHS];
         row_dot<T, NRHS>(i, q, col, val, x, xs, act, ax);
 #pragma unroll
@@ -152,8 +173,8 @@ __global__ __launch_bounds__(kBlock) void k_init(int64_t n, int64_t np, int q, c
     const int blk = blockIdx.x;
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) {
-        const double a = block_sum(srr[k], lds);
-        const double c = block_sum(sbb[k], lds);
+        const double a = kblock_sum(srr[k], lds);
+        const double c = kblock_sum(sbb[k], lds);
         if (threadIdx.x == 0) {
             partial(part, P_RHR, k)[blk] = a;
             partial(part, P_RR, k)[blk] = a;
@@ -167,12 +188,12 @@ __global__ __launch_bounds__(kBlock) void k_init(int64_t n, int64_t np, int q, c
 template <int NV>
 __device__ inline void sum_partials_n(const double *const *parts, int np, double *out)
 {
-    __shared__ double red[NV][kBlock / 64];
-    constexpr int kPer = kMaxBlocks / kBlock;
+    __shared__ double red[NV][kKB / 64];
+    constexpr int kPer = kKMaxBlocks / kKB;
     double ld[NV][kPer];
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
-        const int i = threadIdx.x + j * kBlock;
+        const int i = threadIdx.x + j * kKB;
 #pragma unroll
         for (int m = 0; m < NV; ++m) ld[m][j] = (i < np) ? parts[m][i] : 0.0;
     }
@@ -197,7 +218,7 @@ __device__ inline void sum_partials_n(const double *const *parts, int np, double
     for (int m = 0; m < NV; ++m) {
         double t = 0.0;
 #pragma unroll
-        for (int j = 0; j < kBlock / 64; ++j) t += red[m][j];
+        for (int j = 0; j < kKB / 64; ++j) t += red[m][j];
         out[m] = t;
     }
 }
@@ -231,13 +252,13 @@ __device__ inline bool want_restart(const KState &s, double rhr, double rr)
 
 // KP: convergence test on r; p-hat = D^-1 r + beta (p-hat - omega D^-1 v)
 template <typename T, int NRHS>
-__global__ __launch_bounds__(kBlock) void k_p(int64_t n, int64_t np, const T *__restrict__ dinv,
+__global__ __launch_bounds__(kKB) void k_p(int64_t n, int64_t np, const T *__restrict__ dinv,
                                               T *__restrict__ x, int64_t xs, T *__restrict__ r,
                                               T *__restrict__ rh, T *__restrict__ ph, const T *__restrict__ v,
                                               double *__restrict__ part, KState *__restrict__ st, int nblk_prev,
                                               double tol2, int phase)
 {
-    __shared__ double lds[kBlock / 64];
+    __shared__ double lds[kKB / 64];
     if (all_done<NRHS>(st, phase)) return;
     Scal sc;
     prologue_rho<NRHS>(part, nblk_prev, lds, sc);
@@ -252,13 +273,14 @@ __global__ __launch_bounds__(kBlock) void k_p(int64_t n, int64_t np, const T *__
         restart[k] = want_restart(s, sc.rhr[k], sc.rr[k]);
         beta[k] = (s.iters == 0 || restart[k]) ? 0.0 : (sc.rhr[k] / s.rho_prev) * (s.alpha / s.omega);
         om[k] = s.omega;
+        if (act[k] && blockIdx.x == 0 && threadIdx.x == 0) st[k].rho_cur = restart[k] ? sc.rr[k] : sc.rhr[k];
         if ((zero[k] || conv) && blockIdx.x == 0 && threadIdx.x == 0) {
             st[k].done_at = phase;
             st[k].status = RBFFD_OK;
         }
         if (conv) act[k] = false;
     }
-    for (int64_t i = (int64_t)logical_block() * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kKB) {
         const T di = dinv[i];
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
@@ -278,12 +300,12 @@ __global__ __launch_bounds__(kBlock) void k_p(int64_t n, int64_t np, const T *__
 
 // KV: v = A p-hat; partial r-hat.v
 template <typename T, int NRHS>
-__global__ __launch_bounds__(kBlock) void k_v(int64_t n, int64_t np, int q, const int32_t *__restrict__ col,
+__global__ __launch_bounds__(kKB) void k_v(int64_t n, int64_t np, int q, const int32_t *__restrict__ col,
                                               const T *__restrict__ val, const T *__restrict__ rh,
                                               const T *__restrict__ ph, T *__restrict__ v, double *__restrict__ part,
                                               const KState *__restrict__ st, int phase)
 {
-    __shared__ double lds[kBlock / 64];
+    __shared__ double lds[kKB / 64];
     if (all_done<NRHS>(st, phase)) return;
     bool act[NRHS];
 #pragma unroll
@@ -291,7 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_v(int64_t n, int64_t np, int q, cons
     double srv[NRHS];
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) srv[k] = 0.0;
-    for (int64_t i = (int64_t)logical_block() * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kKB) {
         double av[NRHS];
         row_dot<T, NRHS>(i, q, col, val, ph, np, act, av);
 #pragma unroll
@@ -304,40 +326,26 @@ __global__ __launch_bounds__(kBlock) void k_v(int64_t n, int64_t np, int q, cons
     }
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) {
-        const double a = block_sum(srv[k], lds);
+        const double a = kblock_sum(srv[k], lds);
         if (threadIdx.x == 0) partial(part, P_RV, k)[blockIdx.x] = a;
     }
 }
 
 // KS: alpha = rho / r-hat.v; s = r - alpha v; s-hat = D^-1 s; partial s.s
 template <typename T, int NRHS>
-__global__ __launch_bounds__(kBlock) void k_s(int64_t n, int64_t np, const T *__restrict__ dinv,
+__global__ __launch_bounds__(kKB) void k_s(int64_t n, int64_t np, const T *__restrict__ dinv,
                                               const T *__restrict__ r, const T *__restrict__ v, T *__restrict__ s,
                                               T *__restrict__ sh, double *__restrict__ part, KState *__restrict__ st,
                                               int nblk, int phase)
 {
-    __shared__ double lds[kBlock / 64];
+    __shared__ double lds[kKB / 64];
     if (all_done<NRHS>(st, phase)) return;
-    Scal sc;
     double rvs[NRHS];
     {
-        const double *ps[4 * NRHS];
-        double out[4 * NRHS];
+        const double *ps[NRHS];
 #pragma unroll
-        for (int k = 0; k < NRHS; ++k) {
-            ps[4 * k + 0] = partial(part, P_RHR, k);
-            ps[4 * k + 1] = partial(part, P_RR, k);
-            ps[4 * k + 2] = partial(part, P_BB, k);
-            ps[4 * k + 3] = partial(part, P_RV, k);
-        }
-        sum_partials_n<4 * NRHS>(ps, nblk, out);
-#pragma unroll
-        for (int k = 0; k < NRHS; ++k) {
-            sc.rhr[k] = out[4 * k + 0];
-            sc.rr[k] = out[4 * k + 1];
-            sc.bb[k] = out[4 * k + 2];
-            rvs[k] = out[4 * k + 3];
-        }
+        for (int k = 0; k < NRHS; ++k) ps[k] = partial(part, P_RV, k);
+        sum_partials_n<NRHS>(ps, nblk, rvs);
     }
     bool act[NRHS];
     double alpha[NRHS];
@@ -345,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_s(int64_t n, int64_t np, const T *__
     for (int k = 0; k < NRHS; ++k) {
         const KState stk = st[k];
         act[k] = !finished_before(stk, phase);
-        const double rho = want_restart(stk, sc.rhr[k], sc.rr[k]) ? sc.rr[k] : sc.rhr[k];
+        const double rho = stk.rho_cur;
         const double rv = rvs[k];
         alpha[k] = (rv != 0.0) ? rho / rv : 0.0;
         if (act[k] && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -361,7 +369,7 @@ __global__ __launch_bounds__(kBlock) void k_s(int64_t n, int64_t np, const T *__
     double sss[NRHS];
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) sss[k] = 0.0;
-    for (int64_t i = (int64_t)logical_block() * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kKB) {
         const T di = dinv[i];
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
@@ -374,20 +382,20 @@ __global__ __launch_bounds__(kBlock) void k_s(int64_t n, int64_t np, const T *__
     }
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) {
-        const double a = block_sum(sss[k], lds);
+        const double a = kblock_sum(sss[k], lds);
         if (threadIdx.x == 0) partial(part, P_SS, k)[blockIdx.x] = a;
     }
 }
 
 // KT: if ||s|| is small, x += alpha p-hat and stop; else t = A s-hat, partials t.s, t.t
 template <typename T, int NRHS>
-__global__ __launch_bounds__(kBlock) void k_t(int64_t n, int64_t np, int q, const int32_t *__restrict__ col,
+__global__ __launch_bounds__(kKB) void k_t(int64_t n, int64_t np, int q, const int32_t *__restrict__ col,
                                               const T *__restrict__ val, T *__restrict__ x, int64_t xs,
                                               const T *__restrict__ ph, const T *__restrict__ s,
                                               const T *__restrict__ sh, T *__restrict__ t, double *__restrict__ part,
                                               KState *__restrict__ st, int nblk, double tol2, int phase)
 {
-    __shared__ double lds[kBlock / 64];
+    __shared__ double lds[kKB / 64];
     if (all_done<NRHS>(st, phase)) return;
     bool act[NRHS], half[NRHS];
     double alpha[NRHS];
@@ -421,7 +429,7 @@ __global__ __launch_bounds__(kBlock) void k_t(int64_t n, int64_t np, int q, cons
     double sts[NRHS], stt[NRHS];
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) sts[k] = stt[k] = 0.0;
-    for (int64_t i = (int64_t)logical_block() * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kKB) {
 #pragma unroll
         for (int k = 0; k < NRHS; ++k)
             if (half[k]) x[k * xs + i] = (T)((double)x[k * xs + i] + alpha[k] * (double)ph[k * np + i]);
@@ -438,8 +446,8 @@ __global__ __launch_bounds__(kBlock) void k_t(int64_t n, int64_t np, int q, cons
     }
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) {
-        const double a = block_sum(sts[k], lds);
-        const double c = block_sum(stt[k], lds);
+        const double a = kblock_sum(sts[k], lds);
+        const double c = kblock_sum(stt[k], lds);
         if (threadIdx.x == 0) {
             partial(part, P_TS, k)[blockIdx.x] = a;
             partial(part, P_TT, k)[blockIdx.x] = c;
@@ -449,13 +457,13 @@ __global__ __launch_bounds__(kBlock) void k_t(int64_t n, int64_t np, int q, cons
 
 // KX: omega = t.s / t.t; x += alpha p-hat + omega s-hat; r = s - omega t; partials r-hat.r, r.r
 template <typename T, int NRHS>
-__global__ __launch_bounds__(kBlock) void k_x(int64_t n, int64_t np, T *__restrict__ x, int64_t xs,
+__global__ __launch_bounds__(kKB) void k_x(int64_t n, int64_t np, T *__restrict__ x, int64_t xs,
                                               const T *__restrict__ ph, const T *__restrict__ s,
                                               const T *__restrict__ sh, const T *__restrict__ t, T *__restrict__ r,
                                               const T *__restrict__ rh, double *__restrict__ part,
                                               KState *__restrict__ st, int nblk, int phase)
 {
-    __shared__ double lds[kBlock / 64];
+    __shared__ double lds[kKB / 64];
     if (all_done<NRHS>(st, phase)) return;
     bool act[NRHS];
     double alpha[NRHS], omega[NRHS];
@@ -489,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_x(int64_t n, int64_t np, T *__restri
     double srhr[NRHS], srr[NRHS];
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) srhr[k] = srr[k] = 0.0;
-    for (int64_t i = (int64_t)logical_block() * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kKB) {
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
             if (!act[k]) continue;
@@ -503,8 +511,8 @@ __global__ __launch_bounds__(kBlock) void k_x(int64_t n, int64_t np, T *__restri
     }
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) {
-        const double a = block_sum(srhr[k], lds);
-        const double c = block_sum(srr[k], lds);
+        const double a = kblock_sum(srhr[k], lds);
+        const double c = kblock_sum(srr[k], lds);
         if (threadIdx.x == 0) {
             partial(part, P_RHR, k)[blockIdx.x] = a;
             partial(part, P_RR, k)[blockIdx.x] = c;
@@ -586,6 +594,14 @@ inline int grid_blocks(int64_t n)
     return (int)std::max<int64_t>(1, b);
 }
 
+inline int krylov_blocks(int64_t n)
+{
+    int64_t b = (n + kKB - 1) / kKB;
+    if (b > kKMaxBlocks) b = kKMaxBlocks;
+    if (b >= 64) b = b / 8 * 8;   // multiple of 8 for the XCD-aware mapping
+    return (int)std::max<int64_t>(1, b);
+}
+
 template <typename T>
 int get_work(rbffd_ctx *ctx, int64_t npad, int nrhs, Work *w)
 {
@@ -610,8 +626,8 @@ int bicgstab_t(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const T *va
                int64_t bs, T *x, int64_t xs, double tol, int max_iter, KrylovResult *res, Work &w, hipStream_t s)
 {
     const int64_t np = pad64(n);
-    const int nblk = grid_blocks(n);
-    const dim3 g(nblk), bl(kBlock);
+    const int nblk = krylov_blocks(n);
+    const dim3 g(nblk), bl(kKB);
     T *r = (T *)w.r, *rh = (T *)w.rh, *ph = (T *)w.ph, *v = (T *)w.v, *sv = (T *)w.s, *sh = (T *)w.sh, *t = (T *)w.t;
     const double tol2 = tol * tol;
     RB_HIP(hipMemsetAsync(w.st, 0, sizeof(KState) * kMaxRhs, s));

@@ -182,6 +182,36 @@ def test_simple_step_parity(case, ctx, orc):
     np.testing.assert_array_equal(up.cpu().numpy(), vel)
 
 
+@pytest.mark.parametrize("which", ["stagnation", "uniform"])
+def test_polynomial_flow_step(case, ctx, orc, which):
+    """One BDF2 step from an exact quadratic-in-space, linear-in-time flow lands
+    on the exact state at t^{n+1} (no discretization error for k >= 2), on the
+    GPU as in the oracle; both within 1e-8 of each other."""
+    name, c, k, ops_o, s = case
+    rho, mu, dt, t = 1.3, 0.05, 0.05, 0.3
+    un, pn = W.polynomial_flow(c.xyz, t, which, rho)
+    um, _ = W.polynomial_flow(c.xyz, t - dt, which, rho)
+    ue, pe = W.polynomial_flow(c.xyz, t + dt, which, rho)
+    has_pbc = bool((c.kind == W.PRESCRIBED_PRESSURE).any())
+    kw = dict(tol_outer=1e-12, tol_krylov=1e-13, max_outer=4, max_krylov=20000)
+    uo, _, po, sto = orc.simple_step(ops_o, un, um, pn, ue, rho, mu, dt, alpha=orc.BDF2,
+                                     p_bc=pe if has_pbc else None, **kw)
+    u = torch.tensor(un, device="cuda")
+    up = torch.tensor(um, device="cuda")
+    pg = torch.tensor(pn, device="cuda")
+    st = R.simple_step(ctx, s.ops, u, up, pg, torch.tensor(ue, device="cuda"), rho, mu, dt, R.BDF2,
+                       p_bc=torch.tensor(pe, device="cuda") if has_pbc else None, **kw)
+    ug, pgn = u.cpu().numpy(), pg.cpu().numpy()
+    su, sp_ = max(1.0, np.abs(ue).max()), max(1.0, np.abs(pe).max())
+    print(f"[poly] {name} {which}: outer {st['outer_iters']}/{sto['outer_iters']} status {st['status']}/"
+          f"{sto['status']} du_exact {np.abs(ug - ue).max() / su:.1e} dp_exact {np.abs(pgn - pe).max() / sp_:.1e} "
+          f"du_oracle {np.abs(ug - uo).max() / su:.1e}", flush=True)
+    assert np.abs(ug - ue).max() <= 1e-9 * su
+    assert np.abs(pgn - pe).max() <= 1e-8 * sp_
+    assert np.abs(ug - uo).max() <= 1e-8 * su and np.abs(pgn - po).max() <= 1e-8 * sp_
+    np.testing.assert_array_equal(up.cpu().numpy(), un)
+
+
 def test_determinism(ctx):
     c = W.kovasznay_square(nx=30)
     s = R.Solver(ctx, c, 3)

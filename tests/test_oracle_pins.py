@@ -363,3 +363,57 @@ def test_bdf_coefficients_fixture(orc):
         dt, t1 = 0.1, 1.0
         approx = (a[0] * f(t1) + a[1] * f(t1 - dt) + a[2] * f(t1 - 2 * dt)) / dt
         assert abs(approx - df(t1)) < 1e-12
+
+
+@pytest.mark.parametrize("dim,boundary_kind,k", [(2, W.DIRICHLET, 2), (2, W.DIRICHLET, 3),
+                                                 (2, W.PRESCRIBED_PRESSURE, 3), (3, W.DIRICHLET, 2),
+                                                 (3, W.PRESCRIBED_PRESSURE, 2)])
+@pytest.mark.parametrize("which", ["stagnation", "uniform"])
+@pytest.mark.parametrize("bdf", ["BDF1", "BDF2"])
+def test_polynomial_flows_are_reproduced(orc, dim, boundary_kind, k, which, bdf):
+    """Exact Navier-Stokes solutions with quadratic-in-space, linear-in-time
+    fields are fixed points of the discrete step: the operators reproduce
+    polynomials up to degree k >= 2 (Eq. RBF_constraint) and BDF1/BDF2 are exact
+    for linear-in-time fields (Eqs. u:n+1, v:n+1). One time step from the exact
+    state must land on the exact state at t^{n+1}: interior momentum (mass,
+    advection, viscous and pressure terms, Eqs. u:tilde, v:tilde), the Poisson
+    right-hand side (Eq. pressure poisson), the boundary pressure from the normal
+    momentum equation (Sec. 3.1) or a prescribed pressure, and the corrections
+    (Eqs. u:correction ... p:correction). A wrong sign or coefficient in any of
+    them, or a misplaced BDF coefficient, moves the result by O(dt)."""
+    c = (W.kovasznay_square(nx=12, boundary_kind=boundary_kind) if dim == 2
+         else W.scattered_cube(7, seed=3, boundary_kind=boundary_kind))
+    ops = orc.build_operators(c, k)
+    rho, mu, dt, t = 1.3, 0.05, 0.05, 0.3
+    un, pn = W.polynomial_flow(c.xyz, t, which, rho)
+    um, _ = W.polynomial_flow(c.xyz, t - dt, which, rho)
+    ue, pe = W.polynomial_flow(c.xyz, t + dt, which, rho)
+    pbc = pe if boundary_kind == W.PRESCRIBED_PRESSURE else None
+    u, u_n, p, st = orc.simple_step(ops, un, um, pn, ue, rho, mu, dt, alpha=getattr(orc, bdf),
+                                    tol_outer=1e-12, tol_krylov=1e-13, max_outer=4, max_krylov=20000, p_bc=pbc)
+    assert st["status"] == 0, st
+    np.testing.assert_array_equal(u_n, un)
+    assert np.abs(u - ue).max() <= 1e-10 * max(1.0, np.abs(ue).max())
+    assert np.abs(p - pe).max() <= 1e-9 * max(1.0, np.abs(pe).max())
+
+
+@pytest.mark.parametrize("mu,scale", [(1.0 / 40, 1.0), (1.0, 0.0)])
+def test_courant_lambda_matches_dense_eigenvalues(orc, mu, scale):
+    """The convection-diffusion eigenvalue used for the Courant number (Sec. 3.2)
+    from power iteration matches the largest eigenvalue modulus of the dense
+    interior operator -rho u0.grad + mu Lap computed by LAPACK, and never exceeds
+    its 2-norm (the bound of any power-iteration estimate)."""
+    c = W.kovasznay_square(nx=12)
+    ops = orc.build_operators(c, 3)
+    vel, _ = W.flow_fields(c)
+    u0 = vel * scale
+    lam = orc.convdiff_lambda(ops, u0, 1.0, mu, 200)
+    n = c.n
+    A = np.zeros((n, n))
+    for i in np.nonzero(c.kind == W.INTERIOR)[0]:
+        for a in range(ops.q):
+            A[i, ops.col[i, a]] += (-(u0[0, i] * ops.val[0, i, a] + u0[1, i] * ops.val[1, i, a])
+                                    + mu * ops.val[2, i, a])
+    lam_ref = np.abs(np.linalg.eigvals(A)).max()
+    assert abs(lam - lam_ref) <= 1e-3 * lam_ref, (lam, lam_ref)
+    assert lam <= np.linalg.norm(A, 2) * (1 + 1e-12)

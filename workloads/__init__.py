@@ -106,6 +106,37 @@ def flow_fields(cloud: Cloud, t: float = 0.0):
     return np.ascontiguousarray(vel), np.ascontiguousarray(p)
 
 
+def polynomial_flow(xyz, t: float, which: str, rho: float = 1.0):
+    """Exact Navier-Stokes solutions whose fields are polynomials of degree <= 2
+    in space and <= 1 in time, so that PHS-RBF operators with degree >= 2
+    polynomials and BDF2 reproduce them without discretization error.
+
+    "stagnation": steady u = (x, -y) [3D: (x, y, -2z)], p = -rho |grad phi|^2 / 2.
+    "uniform": spatially uniform u(t) that grows linearly in t, driven by a
+    constant pressure gradient p = -rho u'(t) . x.
+    Both are divergence free for any viscosity. Returns (vel[dim, n], p[n]).
+    """
+    xyz = np.asarray(xyz, dtype=np.float64)
+    dim = xyz.shape[1]
+    if which == "stagnation":
+        if dim == 2:
+            x, y = xyz[:, 0], xyz[:, 1]
+            vel = np.stack([x, -y])
+            p = -rho * (x * x + y * y) / 2
+        else:
+            x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+            vel = np.stack([x, y, -2.0 * z])
+            p = -rho * (x * x + y * y + 4.0 * z * z) / 2
+    elif which == "uniform":
+        a0 = np.array([0.7, -0.2, 0.1])[:dim]
+        a1 = np.array([0.5, 0.3, -0.4])[:dim]
+        vel = np.repeat((a0 + a1 * t)[:, None], len(xyz), axis=1)
+        p = -rho * (xyz @ a1)
+    else:
+        raise ValueError(which)
+    return np.ascontiguousarray(vel), np.ascontiguousarray(p)
+
+
 # --------------------------------------------------------------------------
 # helpers
 # --------------------------------------------------------------------------
