@@ -119,6 +119,7 @@ def main():
     ap.add_argument("--max-outer", type=int, default=20)
     ap.add_argument("--precision", choices=["fp64", "fp32ir"], default="fp64")
     ap.add_argument("--spmv-reps", type=int, default=200)
+    ap.add_argument("--solve-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-r", type=float, default=0.02)
     ap.add_argument("--spmv-only", action="store_true", help="run only the SpMV timing (for counter runs)")
@@ -199,6 +200,34 @@ def main():
     it_us = t_ps / max(pst["iters"], 1) * 1e6
     log(f"[bench] poisson_solve: {pst['iters']} iterations, {it_us:.1f} us/iteration, relres {pst['relres']:.1e}")
 
+    # ---- converged solves at 1e-6: plain FP64 against FP32 sweeps with FP64
+    # refinement, on the same pressure-correction system ----------------------
+    ops_mixed = R.rbffd_assemble(ctx, dcloud, solver.nbr, solver.w, k, precision=R.RBFFD_FP32_IR)
+
+    def timed_solves(prec, reps):
+        lat, its, rel, fb = [], [], [], []
+        for _ in range(reps):
+            xs.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = R.poisson_solve(ctx, ops_mixed, rhs, xs, tol=1e-6, max_iter=20000, precision=prec, allow_noconv=True)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0)
+            its.append(st["iters"])
+            rel.append(st["relres"])
+            fb.append(st["fp64_fallback"])
+        lat_ms = np.array(lat) * 1e3
+        return {"solves_per_s": round(len(lat) / sum(lat), 2), "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat_ms, 99)), 3), "iters": int(np.median(its)),
+                "max_true_relres": float(max(rel)), "fp64_fallback": int(max(fb))}
+
+    timed_solves(R.RBFFD_FP64, 1)
+    solves64 = timed_solves(R.RBFFD_FP64, args.solve_reps)
+    timed_solves(R.RBFFD_FP32_IR, 1)
+    solves32 = timed_solves(R.RBFFD_FP32_IR, args.solve_reps)
+    ops_mixed.free()
+    log(f"[bench] solves at 1e-6: fp64 {solves64}  fp32+refinement {solves32}")
+
     # ---- the benchmark step ---------------------------------------------------
     def one_step():
         nbr, w, _ = R.rbffd_build_stencils(ctx, dcloud, k)
@@ -272,6 +301,11 @@ def main():
         "bicgstab_us_per_iter": round(it_us, 2),
         "bicgstab_gbs": round(bicgstab_iter_bytes(n, q) / (it_us * 1e-6) / 1e9, 1),
         "max_abs_err_u_vs_exact": max(errs),
+        "converged_solves_1e-6": {
+            "system": f"pressure-correction matrix of the same cloud, random right-hand side (seed 1), {args.solve_reps} solves each",
+            "fp64": solves64, "fp32_sweeps_fp64_refinement": solves32,
+            "speedup_vs_fp64": round(solves32["solves_per_s"] / solves64["solves_per_s"], 3),
+        },
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args)

@@ -259,9 +259,11 @@ __global__ __launch_bounds__(kKB) void k_p(int64_t n, int64_t np, const T *__res
                                               double tol2, int phase)
 {
     __shared__ double lds[kKB / 64];
-    if (all_done<NRHS>(st, phase)) return;
+    // partial sums first: their loads overlap the state read, and finished
+    // solves only cost this prologue
     Scal sc;
     prologue_rho<NRHS>(part, nblk_prev, lds, sc);
+    if (all_done<NRHS>(st, phase)) return;
     bool act[NRHS], zero[NRHS], restart[NRHS];
     double beta[NRHS], om[NRHS];
 #pragma unroll
@@ -339,7 +341,6 @@ __global__ __launch_bounds__(kKB) void k_s(int64_t n, int64_t np, const T *__res
                                               int nblk, int phase)
 {
     __shared__ double lds[kKB / 64];
-    if (all_done<NRHS>(st, phase)) return;
     double rvs[NRHS];
     {
         const double *ps[NRHS];
@@ -347,6 +348,7 @@ __global__ __launch_bounds__(kKB) void k_s(int64_t n, int64_t np, const T *__res
         for (int k = 0; k < NRHS; ++k) ps[k] = partial(part, P_RV, k);
         sum_partials_n<NRHS>(ps, nblk, rvs);
     }
+    if (all_done<NRHS>(st, phase)) return;
     bool act[NRHS];
     double alpha[NRHS];
 #pragma unroll
@@ -396,7 +398,6 @@ __global__ __launch_bounds__(kKB) void k_t(int64_t n, int64_t np, int q, const i
                                               KState *__restrict__ st, int nblk, double tol2, int phase)
 {
     __shared__ double lds[kKB / 64];
-    if (all_done<NRHS>(st, phase)) return;
     bool act[NRHS], half[NRHS];
     double alpha[NRHS];
     double sums[2 * NRHS];
@@ -409,6 +410,7 @@ __global__ __launch_bounds__(kKB) void k_t(int64_t n, int64_t np, int q, const i
         }
         sum_partials_n<2 * NRHS>(ps, nblk, sums);
     }
+    if (all_done<NRHS>(st, phase)) return;
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) {
         const KState stk = st[k];
@@ -464,7 +466,6 @@ __global__ __launch_bounds__(kKB) void k_x(int64_t n, int64_t np, T *__restrict_
                                               KState *__restrict__ st, int nblk, int phase)
 {
     __shared__ double lds[kKB / 64];
-    if (all_done<NRHS>(st, phase)) return;
     bool act[NRHS];
     double alpha[NRHS], omega[NRHS];
     double sums[2 * NRHS];
@@ -477,6 +478,7 @@ __global__ __launch_bounds__(kKB) void k_x(int64_t n, int64_t np, T *__restrict_
         }
         sum_partials_n<2 * NRHS>(ps, nblk, sums);
     }
+    if (all_done<NRHS>(st, phase)) return;
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) {
         const KState stk = st[k];
@@ -589,16 +591,16 @@ __global__ void k_zero_f(float *__restrict__ y, int64_t m)
 inline int grid_blocks(int64_t n)
 {
     int64_t b = (n + kBlock - 1) / kBlock;
+    if (b >= 64) b = (b + 7) / 8 * 8;   // multiple of 8 for the XCD-aware mapping
     if (b > kMaxBlocks) b = kMaxBlocks;
-    if (b >= 64) b = b / 8 * 8;   // multiple of 8 for the XCD-aware mapping
     return (int)std::max<int64_t>(1, b);
 }
 
 inline int krylov_blocks(int64_t n)
 {
     int64_t b = (n + kKB - 1) / kKB;
+    if (b >= 64) b = (b + 7) / 8 * 8;   // multiple of 8 for the XCD-aware mapping
     if (b > kKMaxBlocks) b = kKMaxBlocks;
-    if (b >= 64) b = b / 8 * 8;   // multiple of 8 for the XCD-aware mapping
     return (int)std::max<int64_t>(1, b);
 }
 

@@ -21,8 +21,8 @@ __device__ inline int lb() { return xcd_block(gridDim.x); }
 inline int blocks_for(int64_t n)
 {
     int64_t b = (n + kBlock - 1) / kBlock;
+    if (b >= 64) b = (b + 7) / 8 * 8;   // whole rows per thread; multiple of 8 for the XCD mapping
     if (b > kMaxBlocks) b = kMaxBlocks;
-    if (b >= 64) b = b / 8 * 8;
     return (int)std::max<int64_t>(1, b);
 }
 
