@@ -49,6 +49,24 @@ def bicgstab_iter_bytes(n, q):
     return n * (2 * (12 * q + 16) + 8 * (4 + 2 + 5 + 2 + 8))
 
 
+# the benchmark step's workload: the 2D Taylor-Green vortex on ~250k Poisson-disk
+# points (default), or the 3D Ethier-Steinman flow on a 100^3 jittered lattice
+# plus face points (~1.06M points)
+WORKLOADS = {
+    "taylor_green": {
+        "k": 4, "make": lambda W: W.taylor_green_disk(),
+        "sample": lambda W, a: W.taylor_green_disk(r=a.cpu_sample_r),
+        "text": "Taylor-Green vortex nu=0.01 on [0,2pi]^2, {n} Poisson-disk points (seed 2), PHS r^3 + degree-4 "
+                "polynomials, q={q}, Co 10 (dt={dt:.5f})",
+    },
+    "beltrami": {
+        "k": 3, "make": lambda W: W.beltrami_cube(n=100),
+        "sample": lambda W, a: W.beltrami_cube(n=a.cpu_sample_cube),
+        "text": "Ethier-Steinman Beltrami flow nu=0.01 on [0,1]^3, {n} points (100^3 jittered lattice + faces, "
+                "seed 4), PHS r^3 + degree-3 polynomials, q={q}, Co 10 (dt={dt:.5f})",
+    },
+}
+
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "spmv_pressure_tg250k_counters.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2106_07616_amd", "csrc", f) for f in ("krylov.hip", "internal.h")]
 
@@ -88,9 +106,10 @@ def cpu_baseline(args):
     import oracle
     import workloads as W
     oracle.build()
-    c = W.taylor_green_disk(r=args.cpu_sample_r)
+    c = WORKLOADS[args.workload]["sample"](W, args)
+    kdeg = WORKLOADS[args.workload]["k"]
     t0 = time.perf_counter()
-    ops = oracle.build_operators(c, 4)
+    ops = oracle.build_operators(c, kdeg)
     vel0, p0 = W.flow_fields(c, 0.0)
     dt = oracle.dt_from_courant(ops, vel0, 10.0, 1.0, 0.01)
     t_build = time.perf_counter() - t0
@@ -104,8 +123,8 @@ def cpu_baseline(args):
     pi = c.n * (st["krylov_mom"] + st["krylov_p"]) + int((c.kind == W.DIRICHLET).sum()) * st["krylov_b"]
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(pi / t / 1e6, 3), "unit": "M point-iters/s", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 oracle, one benchmark step on a {c.n}-point Taylor-Green Poisson-disk cloud (seed 2, "
-                      f"r={args.cpu_sample_r}, k=4, q=30, Co 10, dt={dt:.5f}): operator build {t_build:.2f} s "
+            "sample": f"FP64 oracle, one benchmark step on a {c.n}-point {c.name} cloud from the same generator "
+                      f"(k={kdeg}, q={ops.q}, Co 10, dt={dt:.5f}): operator build {t_build:.2f} s "
                       f"({cores} OpenMP threads for kNN/weights), step {t_end - t1:.2f} s (sequential Krylov), "
                       f"{st['outer_iters']} outer / {st['krylov_mom']} momentum / {st['krylov_p']} pressure "
                       f"iterations, {pi} point-iters in {t:.2f} s"}
@@ -121,7 +140,9 @@ def main():
     ap.add_argument("--spmv-reps", type=int, default=200)
     ap.add_argument("--solve-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="taylor_green")
     ap.add_argument("--cpu-sample-r", type=float, default=0.02)
+    ap.add_argument("--cpu-sample-cube", type=int, default=30)
     ap.add_argument("--spmv-only", action="store_true", help="run only the SpMV timing (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -137,13 +158,13 @@ def main():
     R.lib()
     dev = "cuda"
     precision = R.RBFFD_FP64 if args.precision == "fp64" else R.RBFFD_FP32_IR
-    k, co, rho, nu = 4, 10.0, 1.0, 0.01
+    k, co, rho, nu = WORKLOADS[args.workload]["k"], 10.0, 1.0, 0.01
     t0 = time.perf_counter()
-    cloud = W.taylor_green_disk()
+    cloud = WORKLOADS[args.workload]["make"](W)
     log(f"[bench] cloud {cloud.name}: n={cloud.n} generated in {time.perf_counter() - t0:.1f}s")
     ctx = R.Context(0)
     dcloud = R.DeviceCloud.from_numpy(cloud, dev)
-    q, m, _ = R.rbffd_stencil_sizes(2, k)
+    q, m, _ = R.rbffd_stencil_sizes(cloud.dim, k)
     n = cloud.n
 
     # time step from the Courant number (computed once, outside the timed region)
@@ -229,15 +250,25 @@ def main():
     log(f"[bench] solves at 1e-6: fp64 {solves64}  fp32+refinement {solves32}")
 
     # ---- the benchmark step ---------------------------------------------------
+    phase_s = {"stencils": 0.0, "assemble": 0.0, "time_step": 0.0}
+
     def one_step():
+        ta = time.perf_counter()
         nbr, w, _ = R.rbffd_build_stencils(ctx, dcloud, k)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
         ops = R.rbffd_assemble(ctx, dcloud, nbr, w, k, precision=precision)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        phase_s["stencils"] += tb - ta
+        phase_s["assemble"] += tc - tb
         u = u0.clone()
         up = um1.clone()
         p = pt0.clone()
         st = R.simple_step(ctx, ops, u, up, p, ubc, rho, nu, dt, R.BDF2, tol_outer=1e-8, tol_krylov=1e-10,
                            max_outer=args.max_outer, max_krylov=20000, precision=precision, p_bc=pbc)
         torch.cuda.synchronize()
+        phase_s["time_step"] += time.perf_counter() - tc
         pi = n * (st["krylov_mom"] + st["krylov_p"]) + ops.n_boundary * st["krylov_b"]
         err = float((u - ubc).abs().max())
         ops.free()
@@ -247,6 +278,8 @@ def main():
         st, _, _ = one_step()
         log(f"[bench] warmup {i}: {st}")
     torch.cuda.synchronize()
+    for key in phase_s:
+        phase_s[key] = 0.0
     t0 = time.perf_counter()
     tot_pi = 0
     stats = []
@@ -277,9 +310,9 @@ def main():
         "dtype": "f64" if precision == R.RBFFD_FP64 else "f32+f64-refinement",
         "data": "synthetic",
         "config": {
-            "workload": f"Taylor-Green vortex nu=0.01 on [0,2pi]^2, {n} Poisson-disk points (seed 2), PHS r^3 + "
-                        f"degree-4 polynomials, q={q}, Co {co} (dt={dt:.5f}); step = stencil build + assembly + one "
-                        f"BDF2 time step (Krylov tol 1e-10, <= {args.max_outer} outer iterations)",
+            "workload": WORKLOADS[args.workload]["text"].format(n=n, q=q, dt=dt) +
+                        f"; step = stencil build + assembly + one BDF2 time step (Krylov tol 1e-10, outer tol 1e-8, "
+                        f"<= {args.max_outer} outer iterations)",
             "n_points": n, "q": q, "poly_degree": k, "max_outer": args.max_outer,
         },
         "roofline": {
@@ -292,8 +325,12 @@ def main():
             "traffic": counter_traffic(),
             "bytes_per_launch": spmv_bytes(n, q),
             "us_per_launch": round(spmv_ms * 1e3, 2),
-            "note": "matrix + vectors (~%.0f MB) fit the 256 MB Infinity Cache" % (spmv_bytes(n, q) / 1e6),
+            "note": ("matrix + vectors (~%.0f MB) fit the 256 MB Infinity Cache" if spmv_bytes(n, q) < 256e6 else
+                     "matrix + vectors (~%.0f MB) exceed the 256 MB Infinity Cache: HBM-resident") %
+                    (spmv_bytes(n, q) / 1e6),
         },
+        "phase_ms_per_step": {key: round(v / args.steps * 1e3, 3) for key, v in phase_s.items()},
+        "stencil_points_per_s": round(n * args.steps / max(phase_s["stencils"], 1e-12), 0),
         "outer_iters": last["outer_iters"],
         "outer_delta": last["delta"],
         "krylov_iters": {"momentum": last["krylov_mom"], "pressure": last["krylov_p"], "boundary": last["krylov_b"]},

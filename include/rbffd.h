@@ -171,7 +171,8 @@ typedef struct {
     double rho, mu;         /* density and dynamic viscosity                         */
     double dt;              /* time step                                              */
     double alpha[3];        /* BDF coefficients (1.5, -2, 0.5); (1, -1, 0) = BDF1    */
-    double tol_outer;       /* stop the outer iteration when Delta < tol_outer       */
+    double tol_outer;       /* stop the outer iteration when Delta < tol_outer; <= 0:
+                               run exactly max_outer iterations (not an error)        */
     double tol_krylov;      /* relative tolerance of every Krylov solve              */
     int max_outer;          /* outer iteration limit                                  */
     int max_krylov;         /* iteration limit of every Krylov solve                  */

@@ -775,7 +775,8 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
     }
     if (outer > c->max_outer) {
         outer = c->max_outer;
-        if (status == ORC_OK) status = ORC_E_NOCONV;
+        /* tol_outer <= 0 asks for exactly max_outer iterations: not a failure */
+        if (status == ORC_OK && c->tol_outer > 0.0) status = ORC_E_NOCONV;
     }
     /* steady-state rate: max over components of mean |u^{n+1} - u^n| / dt */
     double eps = 0.0;

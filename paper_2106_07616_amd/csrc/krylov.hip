@@ -26,6 +26,7 @@ struct KState {
     double rho_prev;  // r-hat . r of the previous iteration
     double rho_cur;   // r-hat . r of this iteration (after a restart: r . r)
     double alpha, omega;
+    double rr, bb;    // ||r||^2 (recursive) at the start of the last iteration, ||b||^2
     int done_at;  // 0 running, else sequence number of the launch that finished
     int iters;    // completed iterations
     int status;   // RBFFD_OK / RBFFD_E_BREAKDOWN
@@ -85,31 +86,34 @@ __device__ inline void row_dot(int64_t i, int q, const int32_t *__restrict__ col
 #pragma unroll
     for (int r = 0; r < NRHS; ++r) acc[r] = 0.0;
     if (!any) return;
+    // rows accumulate in FP64 also for FP32 operands: Laplacian-like rows cancel
+    // terms ~1/h^2 larger than their sum, and FP32 accumulation of that
+    // cancellation makes FP32 BiCGSTAB diverge on fine clouds
     if (all) {
-        T s[NRHS];
+        double s[NRHS];
 #pragma unroll
-        for (int r = 0; r < NRHS; ++r) s[r] = 0;
+        for (int r = 0; r < NRHS; ++r) s[r] = 0.0;
 #pragma unroll 4
         for (int a = 0; a < q; ++a) {
             const int64_t slot = base + (int64_t)a * 64;
             const int32_t c = col[slot];
-            const T v = val[slot];
+            const double v = (double)val[slot];
 #pragma unroll
-            for (int r = 0; r < NRHS; ++r) s[r] = fma(v, x[r * xs + c], s[r]);
+            for (int r = 0; r < NRHS; ++r) s[r] = fma(v, (double)x[r * xs + c], s[r]);
         }
 #pragma unroll
-        for (int r = 0; r < NRHS; ++r) acc[r] = (double)s[r];
+        for (int r = 0; r < NRHS; ++r) acc[r] = s[r];
         return;
     }
     for (int r = 0; r < NRHS; ++r) {
         if (!act[r]) continue;
-        T s1 = 0;
+        double s1 = 0.0;
 #pragma unroll 4
         for (int a = 0; a < q; ++a) {
             const int64_t slot = base + (int64_t)a * 64;
-            s1 = fma(val[slot], x[r * xs + col[slot]], s1);
+            s1 = fma((double)val[slot], (double)x[r * xs + col[slot]], s1);
         }
-        acc[r] = (double)s1;
+        acc[r] = s1;
     }
 }
 
@@ -275,7 +279,11 @@ __global__ __launch_bounds__(kKB) void k_p(int64_t n, int64_t np, const T *__res
         restart[k] = want_restart(s, sc.rhr[k], sc.rr[k]);
         beta[k] = (s.iters == 0 || restart[k]) ? 0.0 : (sc.rhr[k] / s.rho_prev) * (s.alpha / s.omega);
         om[k] = s.omega;
-        if (act[k] && blockIdx.x == 0 && threadIdx.x == 0) st[k].rho_cur = restart[k] ? sc.rr[k] : sc.rhr[k];
+        if (act[k] && blockIdx.x == 0 && threadIdx.x == 0) {
+            st[k].rho_cur = restart[k] ? sc.rr[k] : sc.rhr[k];
+            st[k].rr = sc.rr[k];
+            st[k].bb = sc.bb[k];
+        }
         if ((zero[k] || conv) && blockIdx.x == 0 && threadIdx.x == 0) {
             st[k].done_at = phase;
             st[k].status = RBFFD_OK;
@@ -558,28 +566,73 @@ __global__ __launch_bounds__(kBlock) void k_resid_final(const double *__restrict
     }
 }
 
-// FP64 residual for refinement: res = b - A x (stored as FP32), partial ||res||^2
-__global__ __launch_bounds__(kBlock) void k_refine_res(int64_t n, int q, int nrhs, const int32_t *__restrict__ col,
-                                                       const double *__restrict__ val, const double *__restrict__ b,
-                                                       int64_t bs, const double *__restrict__ x, int64_t xs,
-                                                       float *__restrict__ res, int64_t np)
-{
-    const int64_t i = (int64_t)logical_block() * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const bool act[1] = {true};
-    for (int k = 0; k < nrhs; ++k) {
-        double ax[1];
-        row_dot<double, 1>(i, q, col, val, x + k * xs, 0, act, ax);
-        res[k * np + i] = (float)(b[k * bs + i] - ax[0]);
-    }
-}
-
-__global__ void k_refine_add(int64_t n, int nrhs, double *__restrict__ x, int64_t xs, const float *__restrict__ d,
+// Reliable update of the mixed-precision solve, part 1: x (FP64) += d (FP32
+// correction accumulated since the last update), d = 0.
+__global__ void k_refine_add(int64_t n, int nrhs, double *__restrict__ x, int64_t xs, float *__restrict__ d,
                              int64_t np)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    for (int k = 0; k < nrhs; ++k) x[k * xs + i] += (double)d[k * np + i];
+    for (int k = 0; k < nrhs; ++k) {
+        x[k * xs + i] += (double)d[k * np + i];
+        d[k * np + i] = 0.0f;
+    }
+}
+
+// Part 2: the true residual r = b - A x in FP64 replaces the FP32 recursive
+// residual; partials r-hat.r and r.r for the FP32 iteration, and ||r||^2,
+// ||b||^2 of the FP64 residual for the host. With init set, r-hat = r and the
+// ||b||^2 partials of the iteration are written as well.
+template <int NRHS>
+__global__ __launch_bounds__(kKB) void k_rel_resid(int64_t n, int64_t np, int q, const int32_t *__restrict__ col,
+                                                   const double *__restrict__ val, const double *__restrict__ b,
+                                                   int64_t bs, const double *__restrict__ x, int64_t xs,
+                                                   float *__restrict__ r, float *__restrict__ rh, int init,
+                                                   double *__restrict__ part, double *__restrict__ tpart)
+{
+    __shared__ double lds[kKB / 64];
+    double rhr[NRHS], rr[NRHS], tr[NRHS], bb[NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) rhr[k] = rr[k] = tr[k] = bb[k] = 0.0;
+    bool act[NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) act[k] = true;
+    for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kKB) {
+        double ax[NRHS];
+        row_dot<double, NRHS>(i, q, col, val, x, xs, act, ax);
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            const double bi = b[k * bs + i];
+            const double ri = bi - ax[k];
+            const float rf = (float)ri;
+            r[k * np + i] = rf;
+            float hf;
+            if (init) {
+                rh[k * np + i] = rf;
+                hf = rf;
+            } else {
+                hf = rh[k * np + i];
+            }
+            rhr[k] += (double)hf * (double)rf;
+            rr[k] += (double)rf * (double)rf;
+            tr[k] += ri * ri;
+            bb[k] += bi * bi;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+        const double a1 = kblock_sum(rhr[k], lds);
+        const double a2 = kblock_sum(rr[k], lds);
+        const double a3 = kblock_sum(tr[k], lds);
+        const double a4 = kblock_sum(bb[k], lds);
+        if (threadIdx.x == 0) {
+            partial(part, P_RHR, k)[blockIdx.x] = a1;
+            partial(part, P_RR, k)[blockIdx.x] = a2;
+            if (init) partial(part, P_BB, k)[blockIdx.x] = a4;
+            tpart[(2 * k) * kMaxBlocks + blockIdx.x] = a3;
+            tpart[(2 * k + 1) * kMaxBlocks + blockIdx.x] = a4;
+        }
+    }
 }
 
 __global__ void k_zero_f(float *__restrict__ y, int64_t m)
@@ -716,7 +769,6 @@ int bicgstab(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double 
             acc.status[k] = r1.status[k];
             ok = ok && r1.status[k] == RBFFD_OK;
         }
-        if (!ok || left <= 0) break;
         double rr[kMaxRhs];
         RB_CHECK(residual_norms(ctx, n, q, col, val, nrhs, b, x, rr, s));
         bool good = true;
@@ -724,103 +776,184 @@ int bicgstab(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double 
             acc.relres[k] = rr[k];
             good = good && rr[k] <= 10.0 * tol;
         }
-        if (good) break;
+        if (!ok || left <= 0 || good) break;
     }
     *res = acc;
     return RBFFD_OK;
 }
 
-// Mixed precision: FP32 matrix, vectors and sweeps with FP64 dot accumulation
-// inside; FP64 residual b - A x and FP64 update of x outside, repeated until
-// the FP64 residual meets tol.
-constexpr int kMaxInnerSweep = 4000;   // FP32 iterations per refinement sweep
+// Mixed precision: BiCGSTAB in FP32 (matrix, vectors, SpMV; dots accumulated
+// in FP64) with reliable updates: whenever the recursive residual has fallen
+// by kRelDelta since the last update (or the recursion reports convergence),
+// the FP32 correction is added to the FP64 iterate and the FP64 residual
+// b - A x replaces the FP32 one, and the iteration continues in the same
+// Krylov space. The solve stops when the FP64 residual meets tol. If an update
+// finds a non-finite or growing FP64 residual, or FP32 BiCGSTAB breaks down,
+// the best iterate is restored and the solve finishes in FP64.
+constexpr double kRelDelta = 0.1;
+constexpr int kStallIters = 1000;   // forced update; less than 2x progress since the last one = stall
+
+template <int NRHS>
+static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val,
+                             const float *val32, const float *dinv32, const double *dinv64, const double *b,
+                             double *x, double tol, int max_iter, KrylovResult *res, int *refinements,
+                             hipStream_t s)
+{
+    const int64_t np = pad64(n);
+    Work w;
+    RB_CHECK(get_work<float>(ctx, np, NRHS, &w));
+    char *scr = nullptr;
+    const size_t tbytes = sizeof(double) * (2 * kMaxRhs * kMaxBlocks + kMaxRhs);
+    const size_t xbytes = sizeof(double) * n * NRHS;
+    RB_CHECK(workspace(ctx, WS_REFINE, tbytes + xbytes + sizeof(float) * np * NRHS, (void **)&scr));
+    double *tpart = (double *)scr;
+    double *rout = tpart + 2 * kMaxRhs * kMaxBlocks;
+    double *xgood = (double *)(scr + tbytes);       // iterate with the lowest FP64 residual so far
+    float *d = (float *)(scr + tbytes + xbytes);    // FP32 correction since the last update
+    double *rr = nullptr;
+    RB_CHECK(host_scratch(ctx, kHostRefine, sizeof(double) * kMaxRhs, (void **)&rr));
+    KState *hst = nullptr;
+    RB_CHECK(host_scratch(ctx, kHostKrylov, sizeof(KState) * kMaxRhs, (void **)&hst));
+
+    const int nblk = krylov_blocks(n);
+    const dim3 g(nblk), bl(kKB);
+    const unsigned gb = (unsigned)((n + kBlock - 1) / kBlock);
+    float *r = (float *)w.r, *rh = (float *)w.rh, *ph = (float *)w.ph, *v = (float *)w.v, *sv = (float *)w.s,
+          *sh = (float *)w.sh, *t = (float *)w.t;
+    const double tol2 = tol * tol;
+
+    // true residual of x: replaces r (and r-hat when init), norms to the host
+    auto true_residual = [&](int init) -> int {
+        hipLaunchKernelGGL((k_rel_resid<NRHS>), g, bl, 0, s, n, np, q, col, val, b, n, x, n, r, rh, init, w.part,
+                           tpart);
+        hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(kBlock), 0, s, tpart, nblk, NRHS, rout);
+        RB_HIP(hipGetLastError());
+        RB_HIP(hipMemcpyAsync(rr, rout, sizeof(double) * NRHS, hipMemcpyDeviceToHost, s));
+        RB_HIP(hipStreamSynchronize(s));
+        return RBFFD_OK;
+    };
+
+    RB_HIP(hipMemsetAsync(w.st, 0, sizeof(KState) * kMaxRhs, s));
+    hipLaunchKernelGGL(k_zero_f, dim3((unsigned)((np * NRHS + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, d,
+                       np * NRHS);
+    RB_CHECK(true_residual(1));
+    double best[NRHS], rmax[NRHS];
+    bool conv = true;
+    for (int k = 0; k < NRHS; ++k) {
+        best[k] = rmax[k] = rr[k];
+        conv = conv && rr[k] <= tol;
+    }
+    RB_HIP(hipMemcpyAsync(xgood, x, xbytes, hipMemcpyDeviceToDevice, s));
+    double prev[NRHS];
+    for (int k = 0; k < NRHS; ++k) prev[k] = rr[k];
+    int it = 0, chunk = 4, phase = 0, nref = 0, last_update = 0;
+    bool fallback = false;
+    while (!conv && it < max_iter) {
+        const int todo = std::min(chunk, max_iter - it);
+        for (int c = 0; c < todo; ++c) {
+            hipLaunchKernelGGL((k_p<float, NRHS>), g, bl, 0, s, n, np, dinv32, d, np, r, rh, ph, v, w.part, w.st, nblk,
+                               tol2, ++phase);
+            hipLaunchKernelGGL((k_v<float, NRHS>), g, bl, 0, s, n, np, q, col, val32, rh, ph, v, w.part, w.st, ++phase);
+            hipLaunchKernelGGL((k_s<float, NRHS>), g, bl, 0, s, n, np, dinv32, r, v, sv, sh, w.part, w.st, nblk,
+                               ++phase);
+            hipLaunchKernelGGL((k_t<float, NRHS>), g, bl, 0, s, n, np, q, col, val32, d, np, ph, sv, sh, t, w.part, w.st,
+                               nblk, tol2, ++phase);
+            hipLaunchKernelGGL((k_x<float, NRHS>), g, bl, 0, s, n, np, d, np, ph, sv, sh, t, r, rh, w.part, w.st, nblk,
+                               ++phase);
+        }
+        it += todo;
+        chunk = std::min(chunk * 2, 32);
+        RB_HIP(hipGetLastError());
+        RB_HIP(hipMemcpyAsync(hst, w.st, sizeof(KState) * kMaxRhs, hipMemcpyDeviceToHost, s));
+        RB_HIP(hipStreamSynchronize(s));
+        bool update = it >= max_iter || it - last_update >= kStallIters, broke = false;
+        for (int k = 0; k < NRHS; ++k) {
+            if (hst[k].done_at != 0) {
+                update = true;
+                // b == 0 (x = 0) and breakdowns are left to the FP64 solver
+                broke = broke || hst[k].status != RBFFD_OK || hst[k].bb == 0.0;
+            } else if (hst[k].bb > 0.0 && hst[k].rr <= kRelDelta * kRelDelta * rmax[k] * rmax[k] * hst[k].bb) {
+                update = true;
+            }
+        }
+        if (!update) continue;
+        // reliable update
+        hipLaunchKernelGGL(k_refine_add, dim3(gb), dim3(kBlock), 0, s, n, NRHS, x, n, d, np);
+        RB_CHECK(true_residual(0));
+        ++nref;
+        bool finite = true, worse = false, stalled = false;
+        conv = true;
+        for (int k = 0; k < NRHS; ++k) {
+            finite = finite && std::isfinite(rr[k]);
+            worse = worse || rr[k] > 2.0 * best[k];
+            conv = conv && rr[k] <= tol;
+            stalled = stalled || (rr[k] > tol && rr[k] > 0.5 * prev[k]);
+            prev[k] = rr[k];
+        }
+        last_update = it;
+        if (!finite || worse || broke || (stalled && !conv)) {
+            fallback = true;
+            break;
+        }
+        bool improved = true;
+        for (int k = 0; k < NRHS; ++k) improved = improved && rr[k] <= best[k];
+        if (improved) {
+            RB_HIP(hipMemcpyAsync(xgood, x, xbytes, hipMemcpyDeviceToDevice, s));
+            for (int k = 0; k < NRHS; ++k) best[k] = rr[k];
+        }
+        if (conv) break;
+        // continue: a right-hand side the recursion called converged keeps iterating
+        bool rewrite = false;
+        for (int k = 0; k < NRHS; ++k) {
+            rmax[k] = rr[k];
+            if (hst[k].done_at != 0 && rr[k] > tol) {
+                hst[k].done_at = 0;
+                rewrite = true;
+            }
+        }
+        if (rewrite) RB_HIP(hipMemcpyAsync(w.st, hst, sizeof(KState) * kMaxRhs, hipMemcpyHostToDevice, s));
+    }
+    int total_it[kMaxRhs] = {0, 0, 0};
+    for (int k = 0; k < NRHS; ++k) total_it[k] = (it > 0) ? hst[k].iters : 0;
+    if (fallback) {
+        RB_HIP(hipMemcpyAsync(x, xgood, xbytes, hipMemcpyDeviceToDevice, s));
+        for (int k = 0; k < NRHS; ++k) rr[k] = best[k];
+    }
+    if (fallback && it < max_iter) {
+        const int left = max_iter - it;
+        KrylovResult fr;
+        RB_CHECK(bicgstab(ctx, n, q, col, val, dinv64, NRHS, b, x, tol, left, &fr, s));
+        conv = true;
+        for (int k = 0; k < NRHS; ++k) {
+            total_it[k] += fr.iters[k];
+            rr[k] = fr.relres[k];
+            conv = conv && fr.status[k] == RBFFD_OK;
+        }
+        ++nref;
+    }
+    for (int k = 0; k < NRHS; ++k) {
+        res->iters[k] = total_it[k];
+        res->status[k] = (rr[k] <= tol || (fallback && conv)) ? RBFFD_OK : RBFFD_E_NOCONV;
+        res->relres[k] = rr[k];
+    }
+    res->fp64_fallback = fallback;
+    if (refinements) *refinements = nref;
+    return RBFFD_OK;
+}
 
 int bicgstab_fp32_ir(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val, const float *val32,
                      const float *dinv32, const double *dinv64, int nrhs, const double *b, double *x, double tol,
                      int max_iter, KrylovResult *res, int *refinements, hipStream_t s)
 {
-    if (nrhs < 1 || nrhs > kMaxRhs) return fail(RBFFD_E_ARG, "nrhs must be 1..3");
-    const int64_t np = pad64(n);
-    Work w;
-    RB_CHECK(get_work<float>(ctx, np, nrhs, &w));
-    char *scr = nullptr;
-    const size_t rbytes = sizeof(double) * (2 * kMaxRhs * kMaxBlocks + kMaxRhs);
-    const size_t xbytes = sizeof(double) * n * nrhs;
-    RB_CHECK(workspace(ctx, WS_REFINE, rbytes + xbytes + sizeof(float) * np * nrhs * 2, (void **)&scr));
-    double *resid_dev = (double *)scr;
-    double *rout = resid_dev + 2 * kMaxRhs * kMaxBlocks;
-    double *xgood = (double *)(scr + rbytes);      // last iterate with a finite, improving residual
-    float *rb = (float *)(scr + rbytes + xbytes);
-    float *dx = rb + np * nrhs;
-    double *rr = nullptr;
-    RB_CHECK(host_scratch(ctx, kHostRefine, sizeof(double) * kMaxRhs, (void **)&rr));
-    const double inner_tol = std::max(tol, 1e-4);
-    int total_it[kMaxRhs] = {0, 0, 0};
-    int nref = 0;
-    const int nblk = grid_blocks(n);
-    const unsigned gb = (unsigned)((n + kBlock - 1) / kBlock);
-    bool converged = false, stalled = false;
-    double prev[kMaxRhs] = {0, 0, 0};
-    for (int sweep = 0; sweep < 200; ++sweep) {
-        // FP64 residual norm of the current iterate
-        hipLaunchKernelGGL(k_resid, dim3(nblk), dim3(kBlock), 0, s, n, q, nrhs, col, val, b, n, x, n, resid_dev);
-        hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(kBlock), 0, s, resid_dev, nblk, nrhs, rout);
-        RB_HIP(hipGetLastError());
-        RB_HIP(hipMemcpyAsync(rr, rout, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
-        RB_HIP(hipStreamSynchronize(s));
-        converged = true;
-        for (int k = 0; k < nrhs; ++k) converged = converged && rr[k] <= tol;
-        if (converged) break;
-        int left = max_iter;
-        for (int k = 0; k < nrhs; ++k) left = std::min(left, max_iter - total_it[k]);
-        if (left <= 0) break;
-        // a sweep that did not halve the FP64 residual (or went non-finite): FP32
-        // cannot resolve this system; return to the last good iterate and finish
-        // with FP64 sweeps
-        if (sweep > 0) {
-            for (int k = 0; k < nrhs; ++k) stalled = stalled || !(rr[k] <= 0.5 * prev[k]);
-        }
-        if (stalled) RB_HIP(hipMemcpyAsync(x, xgood, xbytes, hipMemcpyDeviceToDevice, s));
-        for (int k = 0; k < nrhs; ++k) prev[k] = rr[k];
-        if (stalled) {
-            KrylovResult fr;
-            RB_CHECK(bicgstab(ctx, n, q, col, val, dinv64, nrhs, b, x, tol, left, &fr, s));
-            for (int k = 0; k < nrhs; ++k) {
-                total_it[k] += fr.iters[k];
-                rr[k] = fr.relres[k];
-            }
-            ++nref;
-            converged = true;
-            for (int k = 0; k < nrhs; ++k) converged = converged && fr.status[k] == RBFFD_OK;
-            break;
-        }
-        RB_HIP(hipMemcpyAsync(xgood, x, xbytes, hipMemcpyDeviceToDevice, s));
-        left = std::min(left, kMaxInnerSweep);
-        // FP32 correction equation A d = b - A x from d = 0
-        hipLaunchKernelGGL(k_refine_res, dim3(gb), dim3(kBlock), 0, s, n, q, nrhs, col, val, b, n, x, n, rb, np);
-        hipLaunchKernelGGL(k_zero_f, dim3((unsigned)((np * nrhs + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, dx,
-                           np * nrhs);
-        RB_HIP(hipGetLastError());
-        KrylovResult ir;
-        if (nrhs == 1)
-            RB_CHECK((bicgstab_t<float, 1>(ctx, n, q, col, val32, dinv32, rb, np, dx, np, inner_tol, left, &ir, w, s)));
-        else if (nrhs == 2)
-            RB_CHECK((bicgstab_t<float, 2>(ctx, n, q, col, val32, dinv32, rb, np, dx, np, inner_tol, left, &ir, w, s)));
-        else
-            RB_CHECK((bicgstab_t<float, 3>(ctx, n, q, col, val32, dinv32, rb, np, dx, np, inner_tol, left, &ir, w, s)));
-        for (int k = 0; k < nrhs; ++k) total_it[k] += ir.iters[k];
-        hipLaunchKernelGGL(k_refine_add, dim3(gb), dim3(kBlock), 0, s, n, nrhs, x, n, dx, np);
-        RB_HIP(hipGetLastError());
-        ++nref;
+    switch (nrhs) {
+    case 1: return bicgstab_reliable<1>(ctx, n, q, col, val, val32, dinv32, dinv64, b, x, tol, max_iter, res,
+                                        refinements, s);
+    case 2: return bicgstab_reliable<2>(ctx, n, q, col, val, val32, dinv32, dinv64, b, x, tol, max_iter, res,
+                                        refinements, s);
+    case 3: return bicgstab_reliable<3>(ctx, n, q, col, val, val32, dinv32, dinv64, b, x, tol, max_iter, res,
+                                        refinements, s);
+    default: return fail(RBFFD_E_ARG, "nrhs must be 1..3");
     }
-    for (int k = 0; k < nrhs; ++k) {
-        res->iters[k] = total_it[k];
-        res->status[k] = (rr[k] <= tol || (stalled && converged)) ? RBFFD_OK : RBFFD_E_NOCONV;
-        res->relres[k] = rr[k];
-    }
-    res->fp64_fallback = stalled;
-    if (refinements) *refinements = nref;
-    return RBFFD_OK;
 }
 
 int residual_norms(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val, int nrhs,

@@ -421,7 +421,8 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
     }
     if (outer > o->max_outer) {
         outer = o->max_outer;
-        if (status == RBFFD_OK) status = RBFFD_E_NOCONV;
+        // tol_outer <= 0 asks for exactly max_outer iterations: not a failure
+        if (status == RBFFD_OK && o->tol_outer > 0.0) status = RBFFD_E_NOCONV;
     }
     // steady rate, then rotate the time levels
     hipLaunchKernelGGL(k_absdiff, dim3(nblk), dim3(kBlock), 0, s, n, dim, B.ur, u, B.part);

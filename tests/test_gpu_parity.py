@@ -140,6 +140,45 @@ def test_poisson_solve_mixed_precision(case, ctx, orc):
     assert err <= 1e-5
 
 
+def test_simple_step_mixed_precision(case, ctx, orc):
+    """The step with FP32 Krylov sweeps and FP64 reliable updates (momentum with
+    d right-hand sides, pressure correction) stays within 1e-5 of the FP64
+    oracle's fields."""
+    name, c, k, ops_o, s = case
+    if "flow" not in c.meta:
+        pytest.skip("no flow")
+    vel, p = W.flow_fields(c, 0.0)
+    nu = c.meta.get("nu", 0.025)
+    dt = 0.02
+    ubc_np, pbc_np = W.flow_fields(c, dt)
+    kw = dict(tol_outer=0.0, tol_krylov=1e-11, max_outer=2, max_krylov=40000)
+    uo, _, po, sto = orc.simple_step(ops_o, vel, vel, p, ubc_np, 1.0, nu, dt, alpha=orc.BDF2, p_bc=pbc_np, **kw)
+    if sto["status"] != 0:
+        pytest.xfail("the oracle's Krylov solves hit their limit on this system (ill-conditioned Neumann rows)")
+    s32 = R.rbffd_assemble(s.ctx, s.dcloud, s.nbr, s.w, k, precision=R.RBFFD_FP32_IR)
+    u = torch.tensor(vel, device="cuda")
+    up = torch.tensor(vel, device="cuda")
+    pg = torch.tensor(p, device="cuda")
+    st = R.simple_step(ctx, s32, u, up, pg, torch.tensor(ubc_np, device="cuda"), 1.0, nu, dt, R.BDF2,
+                       p_bc=torch.tensor(pbc_np, device="cuda"), precision=R.RBFFD_FP32_IR, **kw)
+    eu = _relinf(u.cpu().numpy(), uo)
+    ep = _relinf(pg.cpu().numpy(), po)
+    print(f"[step fp32] {name}: status {st['status']} mom {st['krylov_mom']} p {st['krylov_p']} "
+          f"du {eu:.2e} dp {ep:.2e}", flush=True)
+    assert eu <= 1e-5 and ep <= 1e-5
+
+
+def test_mixed_precision_zero_rhs(ctx):
+    """b = 0 gives x = 0 from any starting guess (mixed-precision path)."""
+    c = W.kovasznay_square(nx=12)
+    s = R.Solver(ctx, c, 3, precision=R.RBFFD_FP32_IR)
+    x = torch.ones(c.n, dtype=torch.float64, device="cuda")
+    st = R.poisson_solve(ctx, s.ops, torch.zeros(c.n, dtype=torch.float64, device="cuda"), x, tol=1e-10,
+                         max_iter=1000, precision=R.RBFFD_FP32_IR)
+    assert st["status"] == 0
+    assert float(x.abs().max()) == 0.0
+
+
 def test_courant_eigenvalue(case, ctx, orc):
     name, c, k, ops_o, s = case
     if "flow" not in c.meta:
