@@ -136,7 +136,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--max-outer", type=int, default=20)
-    ap.add_argument("--precision", choices=["fp64", "fp32ir"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "fp32ir", "fp32matrix"], default="fp64")
     ap.add_argument("--spmv-reps", type=int, default=200)
     ap.add_argument("--solve-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -157,7 +157,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     R.lib()
     dev = "cuda"
-    precision = R.RBFFD_FP64 if args.precision == "fp64" else R.RBFFD_FP32_IR
+    precision = {"fp64": R.RBFFD_FP64, "fp32ir": R.RBFFD_FP32_IR, "fp32matrix": R.RBFFD_FP32_MATRIX}[args.precision]
     k, co, rho, nu = WORKLOADS[args.workload]["k"], 10.0, 1.0, 0.01
     t0 = time.perf_counter()
     cloud = WORKLOADS[args.workload]["make"](W)
@@ -246,8 +246,10 @@ def main():
     solves64 = timed_solves(R.RBFFD_FP64, args.solve_reps)
     timed_solves(R.RBFFD_FP32_IR, 1)
     solves32 = timed_solves(R.RBFFD_FP32_IR, args.solve_reps)
+    timed_solves(R.RBFFD_FP32_MATRIX, 1)
+    solves32m = timed_solves(R.RBFFD_FP32_MATRIX, args.solve_reps)
     ops_mixed.free()
-    log(f"[bench] solves at 1e-6: fp64 {solves64}  fp32+refinement {solves32}")
+    log(f"[bench] solves at 1e-6: fp64 {solves64}  fp32 {solves32}  fp32 matrix {solves32m}")
 
     # ---- the benchmark step ---------------------------------------------------
     phase_s = {"stencils": 0.0, "assemble": 0.0, "time_step": 0.0}
@@ -307,7 +309,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if precision == R.RBFFD_FP64 else "f32+f64-refinement",
+        "dtype": {"fp64": "f64", "fp32ir": "f32 (f64 accumulation and refinement)",
+                  "fp32matrix": "f32 matrix, f64 vectors"}[args.precision],
         "data": "synthetic",
         "config": {
             "workload": WORKLOADS[args.workload]["text"].format(n=n, q=q, dt=dt) +
@@ -340,8 +343,12 @@ def main():
         "max_abs_err_u_vs_exact": max(errs),
         "converged_solves_1e-6": {
             "system": f"pressure-correction matrix of the same cloud, random right-hand side (seed 1), {args.solve_reps} solves each",
-            "fp64": solves64, "fp32_sweeps_fp64_refinement": solves32,
-            "speedup_vs_fp64": round(solves32["solves_per_s"] / solves64["solves_per_s"], 3),
+            "fp64": solves64,
+            "fp32_vectors_and_matrix": solves32,
+            "fp32_matrix_fp64_vectors": solves32m,
+            "speedup_vs_fp64": {"fp32_vectors_and_matrix": round(solves32["solves_per_s"] / solves64["solves_per_s"], 3),
+                                "fp32_matrix_fp64_vectors": round(solves32m["solves_per_s"] / solves64["solves_per_s"], 3)},
+            "note": "both mixed modes: FP64 row and dot accumulation, FP64 reliable residual updates",
         },
     }
     if not args.no_cpu_baseline:

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "librbffd.so")
 
 RBFFD_OK, RBFFD_E_ARG, RBFFD_E_OOM, RBFFD_E_SINGULAR = 0, -1, -2, -3
 RBFFD_E_NOCONV, RBFFD_E_BREAKDOWN, RBFFD_E_DEVICE = -4, -5, -6
-RBFFD_FP64, RBFFD_FP32_IR = 0, 1
+RBFFD_FP64, RBFFD_FP32_IR, RBFFD_FP32_MATRIX = 0, 1, 2
 STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_OOM", -3: "E_SINGULAR", -4: "E_NOCONV",
                 -5: "E_BREAKDOWN", -6: "E_DEVICE"}
 

@@ -201,7 +201,8 @@ int rbffd_assemble(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_stencil
     RB_CHECK(check_cloud(cloud));
     if (!cloud->kind || !cloud->normal) return fail(RBFFD_E_ARG, "cloud.kind or cloud.normal is NULL");
     if (cloud->pin < -1 || cloud->pin >= cloud->n) return fail(RBFFD_E_ARG, "pin out of range");
-    if (precision != RBFFD_FP64 && precision != RBFFD_FP32_IR) return fail(RBFFD_E_ARG, "unknown precision");
+    if (precision != RBFFD_FP64 && precision != RBFFD_FP32_IR && precision != RBFFD_FP32_MATRIX)
+        return fail(RBFFD_E_ARG, "unknown precision");
     int q, m, R;
     RB_CHECK(resolve_sizes(cloud->dim, opts, &q, &m, &R));
     if (q > cloud->n) return fail(RBFFD_E_ARG, "cloud size q exceeds the number of points");
@@ -267,9 +268,9 @@ int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, doubl
 {
     if (!ctx || !ops || !rhs || !x || !opts) return fail(RBFFD_E_ARG, "NULL argument");
     if (!(opts->tol >= 0.0) || opts->max_iter < 0) return fail(RBFFD_E_ARG, "bad Krylov options");
-    if (opts->precision != RBFFD_FP64 && opts->precision != RBFFD_FP32_IR)
+    if (opts->precision != RBFFD_FP64 && opts->precision != RBFFD_FP32_IR && opts->precision != RBFFD_FP32_MATRIX)
         return fail(RBFFD_E_ARG, "unknown precision");
-    if (opts->precision == RBFFD_FP32_IR && !ops->pval32)
+    if (opts->precision != RBFFD_FP64 && !ops->pval32)
         return fail(RBFFD_E_ARG, "operators were assembled without FP32 copies");
     RB_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)hip_stream;
@@ -280,8 +281,8 @@ int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, doubl
         st = bicgstab(ctx, ops->n, ops->q, ops->col, ops->pval, ops->pdinv, 1, rhs, x, opts->tol,
                       opts->max_iter, &res, s);
     else
-        st = bicgstab_fp32_ir(ctx, ops->n, ops->q, ops->col, ops->pval, ops->pval32, ops->pdinv32, ops->pdinv, 1,
-                              rhs, x, opts->tol, opts->max_iter, &res, &refine, s);
+        st = bicgstab_mixed(ctx, opts->precision, ops->n, ops->q, ops->col, ops->pval, ops->pval32, ops->pdinv32,
+                            ops->pdinv, 1, rhs, x, opts->tol, opts->max_iter, &res, &refine, s);
     if (st != RBFFD_OK) return st;
     double rr = 0.0;
     RB_CHECK(residual_norms(ctx, ops->n, ops->q, ops->col, ops->pval, 1, rhs, x, &rr, s));
@@ -310,9 +311,9 @@ int simple_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev,
         return fail(RBFFD_E_ARG, "bad BDF coefficients");
     if (opts->max_outer < 1 || opts->max_krylov < 1 || !(opts->tol_krylov >= 0.0) || !(opts->tol_outer >= 0.0))
         return fail(RBFFD_E_ARG, "bad iteration limits or tolerances");
-    if (opts->precision != RBFFD_FP64 && opts->precision != RBFFD_FP32_IR)
+    if (opts->precision != RBFFD_FP64 && opts->precision != RBFFD_FP32_IR && opts->precision != RBFFD_FP32_MATRIX)
         return fail(RBFFD_E_ARG, "unknown precision");
-    if (opts->precision == RBFFD_FP32_IR && !ops->pval32)
+    if (opts->precision != RBFFD_FP64 && !ops->pval32)
         return fail(RBFFD_E_ARG, "operators were assembled without FP32 copies");
     RB_HIP(hipSetDevice(ctx->device));
     rbffd_step_stats local{};

@@ -257,7 +257,7 @@ int assemble_ops(rbffd_ctx *ctx, const rbffd_cloud *cloud, int q, int k, int phs
     dev_free(ctx, flag, fbytes);
     RB_CHECK(st);
 
-    if (precision == RBFFD_FP32_IR) {
+    if (precision != RBFFD_FP64) {
         RB_CHECK(alloc_ops(ops, &ops->pval32, (size_t)nnz));
         RB_CHECK(alloc_ops(ops, &ops->pdinv32, (size_t)npad));
         RB_CHECK(alloc_ops(ops, &ops->mval32, (size_t)nnz));

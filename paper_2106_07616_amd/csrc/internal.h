@@ -207,9 +207,11 @@ struct KrylovResult {
 int bicgstab(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val,
              const double *dinv, int nrhs, const double *b, double *x, double tol, int max_iter,
              KrylovResult *res, hipStream_t s);
-int bicgstab_fp32_ir(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val,
-                     const float *val32, const float *dinv32, const double *dinv64, int nrhs, const double *b,
-                     double *x, double tol, int max_iter, KrylovResult *res, int *refinements, hipStream_t s);
+// FP32 matrix values with FP64 row accumulation and FP64 reliable updates;
+// precision RBFFD_FP32_IR keeps the Krylov vectors in FP32, RBFFD_FP32_MATRIX in FP64.
+int bicgstab_mixed(rbffd_ctx *ctx, int precision, int64_t n, int q, const int32_t *col, const double *val,
+                   const float *val32, const float *dinv32, const double *dinv64, int nrhs, const double *b, double *x,
+                   double tol, int max_iter, KrylovResult *res, int *refinements, hipStream_t s);
 int spmv(int64_t n, int q, const int32_t *col, const double *val, const double *x, double *y,
          hipStream_t s);
 int residual_norms(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val,

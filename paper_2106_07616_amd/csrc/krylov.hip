@@ -72,11 +72,11 @@ __device__ inline int64_t row_base(int64_t i, int q) { return ((i >> 6) * (int64
 // column order. The activity test sits outside the entry loop so the loop body
 // is branch-free and the compiler can keep several column/value/gather loads in
 // flight.
-template <typename T, int NRHS>
-__device__ inline void row_dot(int64_t i, int q, const int32_t *__restrict__ col, const T *__restrict__ val,
-                               const T *__restrict__ x, int64_t xs, const bool *act, double *acc)
+template <typename TM, typename TX, int NRHS>
+__device__ inline void row_dot(int64_t i, int q, const int32_t *__restrict__ col, const TM *__restrict__ val,
+                               const TX *__restrict__ x, int64_t xs, const bool *act, double *acc)
 {
-    const int64_t base = row_base<T>(i, q);
+    const int64_t base = row_base<TM>(i, q);
     bool all = true, any = false;
 #pragma unroll
     for (int r = 0; r < NRHS; ++r) {
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int64_t n, int q, const in
     if (i >= n) return;
     const bool act[1] = {true};
     double acc[1];
-    row_dot<T, 1>(i, q, col, val, x, 0, act, acc);
+    row_dot<T, T, 1>(i, q, col, val, x, 0, act, acc);
     y[i] = (T)acc[0];
 }
 
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kKB) void k_init(int64_t n, int64_t np, int q, cons
     for (int k = 0; k < NRHS; ++k) act[k] = true;
     for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kKB) {
         double ax[NRHS];
-        row_dot<T, NRHS>(i, q, col, val, x, xs, act, ax);
+        row_dot<T, T, NRHS>(i, q, col, val, x, xs, act, ax);
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
             const double bi = (double)b[k * bs + i];
@@ -309,9 +309,9 @@ __global__ __launch_bounds__(kKB) void k_p(int64_t n, int64_t np, const T *__res
 }
 
 // KV: v = A p-hat; partial r-hat.v
-template <typename T, int NRHS>
+template <typename T, typename TM, int NRHS>
 __global__ __launch_bounds__(kKB) void k_v(int64_t n, int64_t np, int q, const int32_t *__restrict__ col,
-                                              const T *__restrict__ val, const T *__restrict__ rh,
+                                              const TM *__restrict__ val, const T *__restrict__ rh,
                                               const T *__restrict__ ph, T *__restrict__ v, double *__restrict__ part,
                                               const KState *__restrict__ st, int phase)
 {
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(kKB) void k_v(int64_t n, int64_t np, int q, const i
     for (int k = 0; k < NRHS; ++k) srv[k] = 0.0;
     for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kKB) {
         double av[NRHS];
-        row_dot<T, NRHS>(i, q, col, val, ph, np, act, av);
+        row_dot<TM, T, NRHS>(i, q, col, val, ph, np, act, av);
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
             if (!act[k]) continue;
@@ -398,9 +398,9 @@ __global__ __launch_bounds__(kKB) void k_s(int64_t n, int64_t np, const T *__res
 }
 
 // KT: if ||s|| is small, x += alpha p-hat and stop; else t = A s-hat, partials t.s, t.t
-template <typename T, int NRHS>
+template <typename T, typename TM, int NRHS>
 __global__ __launch_bounds__(kKB) void k_t(int64_t n, int64_t np, int q, const int32_t *__restrict__ col,
-                                              const T *__restrict__ val, T *__restrict__ x, int64_t xs,
+                                              const TM *__restrict__ val, T *__restrict__ x, int64_t xs,
                                               const T *__restrict__ ph, const T *__restrict__ s,
                                               const T *__restrict__ sh, T *__restrict__ t, double *__restrict__ part,
                                               KState *__restrict__ st, int nblk, double tol2, int phase)
@@ -444,7 +444,7 @@ __global__ __launch_bounds__(kKB) void k_t(int64_t n, int64_t np, int q, const i
         for (int k = 0; k < NRHS; ++k)
             if (half[k]) x[k * xs + i] = (T)((double)x[k * xs + i] + alpha[k] * (double)ph[k * np + i]);
         double at[NRHS];
-        row_dot<T, NRHS>(i, q, col, val, sh, np, sp, at);
+        row_dot<TM, T, NRHS>(i, q, col, val, sh, np, sp, at);
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
             if (!sp[k]) continue;
@@ -542,7 +542,7 @@ __global__ __launch_bounds__(kBlock) void k_resid(int64_t n, int q, int nrhs, co
         const bool act[1] = {true};
         for (int64_t i = (int64_t)logical_block() * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
             double ax[1];
-            row_dot<double, 1>(i, q, col, val, x + k * xs, 0, act, ax);
+            row_dot<double, double, 1>(i, q, col, val, x + k * xs, 0, act, ax);
             const double ri = b[k * bs + i] - ax[0];
             srr += ri * ri;
             sbb += b[k * bs + i] * b[k * bs + i];
@@ -568,14 +568,14 @@ __global__ __launch_bounds__(kBlock) void k_resid_final(const double *__restrict
 
 // Reliable update of the mixed-precision solve, part 1: x (FP64) += d (FP32
 // correction accumulated since the last update), d = 0.
-__global__ void k_refine_add(int64_t n, int nrhs, double *__restrict__ x, int64_t xs, float *__restrict__ d,
-                             int64_t np)
+template <typename T>
+__global__ void k_refine_add(int64_t n, int nrhs, double *__restrict__ x, int64_t xs, T *__restrict__ d, int64_t np)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     for (int k = 0; k < nrhs; ++k) {
         x[k * xs + i] += (double)d[k * np + i];
-        d[k * np + i] = 0.0f;
+        d[k * np + i] = (T)0;
     }
 }
 
@@ -583,11 +583,11 @@ __global__ void k_refine_add(int64_t n, int nrhs, double *__restrict__ x, int64_
 // residual; partials r-hat.r and r.r for the FP32 iteration, and ||r||^2,
 // ||b||^2 of the FP64 residual for the host. With init set, r-hat = r and the
 // ||b||^2 partials of the iteration are written as well.
-template <int NRHS>
+template <typename T, int NRHS>
 __global__ __launch_bounds__(kKB) void k_rel_resid(int64_t n, int64_t np, int q, const int32_t *__restrict__ col,
                                                    const double *__restrict__ val, const double *__restrict__ b,
                                                    int64_t bs, const double *__restrict__ x, int64_t xs,
-                                                   float *__restrict__ r, float *__restrict__ rh, int init,
+                                                   T *__restrict__ r, T *__restrict__ rh, int init,
                                                    double *__restrict__ part, double *__restrict__ tpart)
 {
     __shared__ double lds[kKB / 64];
@@ -599,14 +599,14 @@ __global__ __launch_bounds__(kKB) void k_rel_resid(int64_t n, int64_t np, int q,
     for (int k = 0; k < NRHS; ++k) act[k] = true;
     for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kKB) {
         double ax[NRHS];
-        row_dot<double, NRHS>(i, q, col, val, x, xs, act, ax);
+        row_dot<double, double, NRHS>(i, q, col, val, x, xs, act, ax);
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
             const double bi = b[k * bs + i];
             const double ri = bi - ax[k];
-            const float rf = (float)ri;
+            const T rf = (T)ri;
             r[k * np + i] = rf;
-            float hf;
+            T hf;
             if (init) {
                 rh[k * np + i] = rf;
                 hf = rf;
@@ -635,10 +635,11 @@ __global__ __launch_bounds__(kKB) void k_rel_resid(int64_t n, int64_t np, int q,
     }
 }
 
-__global__ void k_zero_f(float *__restrict__ y, int64_t m)
+template <typename T>
+__global__ void k_zero(T *__restrict__ y, int64_t m)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < m) y[i] = 0.0f;
+    if (i < m) y[i] = (T)0;
 }
 
 inline int grid_blocks(int64_t n)
@@ -700,9 +701,9 @@ int bicgstab_t(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const T *va
         for (int c = 0; c < todo; ++c) {
             hipLaunchKernelGGL((k_p<T, NRHS>), g, bl, 0, s, n, np, dinv, x, xs, r, rh, ph, v, w.part, w.st, nblk, tol2,
                                ++phase);
-            hipLaunchKernelGGL((k_v<T, NRHS>), g, bl, 0, s, n, np, q, col, val, rh, ph, v, w.part, w.st, ++phase);
+            hipLaunchKernelGGL((k_v<T, T, NRHS>), g, bl, 0, s, n, np, q, col, val, rh, ph, v, w.part, w.st, ++phase);
             hipLaunchKernelGGL((k_s<T, NRHS>), g, bl, 0, s, n, np, dinv, r, v, sv, sh, w.part, w.st, nblk, ++phase);
-            hipLaunchKernelGGL((k_t<T, NRHS>), g, bl, 0, s, n, np, q, col, val, x, xs, ph, sv, sh, t, w.part, w.st, nblk,
+            hipLaunchKernelGGL((k_t<T, T, NRHS>), g, bl, 0, s, n, np, q, col, val, x, xs, ph, sv, sh, t, w.part, w.st, nblk,
                                tol2, ++phase);
             hipLaunchKernelGGL((k_x<T, NRHS>), g, bl, 0, s, n, np, x, xs, ph, sv, sh, t, r, rh, w.part, w.st, nblk,
                                ++phase);
@@ -793,23 +794,22 @@ int bicgstab(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double 
 constexpr double kRelDelta = 0.1;
 constexpr int kStallIters = 1000;   // forced update; less than 2x progress since the last one = stall
 
-template <int NRHS>
+template <typename T, int NRHS>
 static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val,
-                             const float *val32, const float *dinv32, const double *dinv64, const double *b,
-                             double *x, double tol, int max_iter, KrylovResult *res, int *refinements,
-                             hipStream_t s)
+                             const float *val32, const T *dinv, const double *dinv64, const double *b, double *x,
+                             double tol, int max_iter, KrylovResult *res, int *refinements, hipStream_t s)
 {
     const int64_t np = pad64(n);
     Work w;
-    RB_CHECK(get_work<float>(ctx, np, NRHS, &w));
+    RB_CHECK(get_work<T>(ctx, np, NRHS, &w));
     char *scr = nullptr;
     const size_t tbytes = sizeof(double) * (2 * kMaxRhs * kMaxBlocks + kMaxRhs);
     const size_t xbytes = sizeof(double) * n * NRHS;
-    RB_CHECK(workspace(ctx, WS_REFINE, tbytes + xbytes + sizeof(float) * np * NRHS, (void **)&scr));
+    RB_CHECK(workspace(ctx, WS_REFINE, tbytes + xbytes + sizeof(T) * np * NRHS, (void **)&scr));
     double *tpart = (double *)scr;
     double *rout = tpart + 2 * kMaxRhs * kMaxBlocks;
     double *xgood = (double *)(scr + tbytes);       // iterate with the lowest FP64 residual so far
-    float *d = (float *)(scr + tbytes + xbytes);    // FP32 correction since the last update
+    T *d = (T *)(scr + tbytes + xbytes);            // correction accumulated since the last update
     double *rr = nullptr;
     RB_CHECK(host_scratch(ctx, kHostRefine, sizeof(double) * kMaxRhs, (void **)&rr));
     KState *hst = nullptr;
@@ -818,13 +818,12 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, const int32_t *co
     const int nblk = krylov_blocks(n);
     const dim3 g(nblk), bl(kKB);
     const unsigned gb = (unsigned)((n + kBlock - 1) / kBlock);
-    float *r = (float *)w.r, *rh = (float *)w.rh, *ph = (float *)w.ph, *v = (float *)w.v, *sv = (float *)w.s,
-          *sh = (float *)w.sh, *t = (float *)w.t;
+    T *r = (T *)w.r, *rh = (T *)w.rh, *ph = (T *)w.ph, *v = (T *)w.v, *sv = (T *)w.s, *sh = (T *)w.sh, *t = (T *)w.t;
     const double tol2 = tol * tol;
 
     // true residual of x: replaces r (and r-hat when init), norms to the host
     auto true_residual = [&](int init) -> int {
-        hipLaunchKernelGGL((k_rel_resid<NRHS>), g, bl, 0, s, n, np, q, col, val, b, n, x, n, r, rh, init, w.part,
+        hipLaunchKernelGGL((k_rel_resid<T, NRHS>), g, bl, 0, s, n, np, q, col, val, b, n, x, n, r, rh, init, w.part,
                            tpart);
         hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(kBlock), 0, s, tpart, nblk, NRHS, rout);
         RB_HIP(hipGetLastError());
@@ -834,7 +833,7 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, const int32_t *co
     };
 
     RB_HIP(hipMemsetAsync(w.st, 0, sizeof(KState) * kMaxRhs, s));
-    hipLaunchKernelGGL(k_zero_f, dim3((unsigned)((np * NRHS + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, d,
+    hipLaunchKernelGGL(k_zero<T>, dim3((unsigned)((np * NRHS + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, d,
                        np * NRHS);
     RB_CHECK(true_residual(1));
     double best[NRHS], rmax[NRHS];
@@ -851,14 +850,14 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, const int32_t *co
     while (!conv && it < max_iter) {
         const int todo = std::min(chunk, max_iter - it);
         for (int c = 0; c < todo; ++c) {
-            hipLaunchKernelGGL((k_p<float, NRHS>), g, bl, 0, s, n, np, dinv32, d, np, r, rh, ph, v, w.part, w.st, nblk,
-                               tol2, ++phase);
-            hipLaunchKernelGGL((k_v<float, NRHS>), g, bl, 0, s, n, np, q, col, val32, rh, ph, v, w.part, w.st, ++phase);
-            hipLaunchKernelGGL((k_s<float, NRHS>), g, bl, 0, s, n, np, dinv32, r, v, sv, sh, w.part, w.st, nblk,
+            hipLaunchKernelGGL((k_p<T, NRHS>), g, bl, 0, s, n, np, dinv, d, np, r, rh, ph, v, w.part, w.st, nblk, tol2,
                                ++phase);
-            hipLaunchKernelGGL((k_t<float, NRHS>), g, bl, 0, s, n, np, q, col, val32, d, np, ph, sv, sh, t, w.part, w.st,
-                               nblk, tol2, ++phase);
-            hipLaunchKernelGGL((k_x<float, NRHS>), g, bl, 0, s, n, np, d, np, ph, sv, sh, t, r, rh, w.part, w.st, nblk,
+            hipLaunchKernelGGL((k_v<T, float, NRHS>), g, bl, 0, s, n, np, q, col, val32, rh, ph, v, w.part, w.st,
+                               ++phase);
+            hipLaunchKernelGGL((k_s<T, NRHS>), g, bl, 0, s, n, np, dinv, r, v, sv, sh, w.part, w.st, nblk, ++phase);
+            hipLaunchKernelGGL((k_t<T, float, NRHS>), g, bl, 0, s, n, np, q, col, val32, d, np, ph, sv, sh, t, w.part,
+                               w.st, nblk, tol2, ++phase);
+            hipLaunchKernelGGL((k_x<T, NRHS>), g, bl, 0, s, n, np, d, np, ph, sv, sh, t, r, rh, w.part, w.st, nblk,
                                ++phase);
         }
         it += todo;
@@ -878,7 +877,7 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, const int32_t *co
         }
         if (!update) continue;
         // reliable update
-        hipLaunchKernelGGL(k_refine_add, dim3(gb), dim3(kBlock), 0, s, n, NRHS, x, n, d, np);
+        hipLaunchKernelGGL(k_refine_add<T>, dim3(gb), dim3(kBlock), 0, s, n, NRHS, x, n, d, np);
         RB_CHECK(true_residual(0));
         ++nref;
         bool finite = true, worse = false, stalled = false;
@@ -941,19 +940,34 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, const int32_t *co
     return RBFFD_OK;
 }
 
-int bicgstab_fp32_ir(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val, const float *val32,
-                     const float *dinv32, const double *dinv64, int nrhs, const double *b, double *x, double tol,
-                     int max_iter, KrylovResult *res, int *refinements, hipStream_t s)
+int bicgstab_mixed(rbffd_ctx *ctx, int precision, int64_t n, int q, const int32_t *col, const double *val,
+                   const float *val32, const float *dinv32, const double *dinv64, int nrhs, const double *b, double *x,
+                   double tol, int max_iter, KrylovResult *res, int *refinements, hipStream_t s)
 {
-    switch (nrhs) {
-    case 1: return bicgstab_reliable<1>(ctx, n, q, col, val, val32, dinv32, dinv64, b, x, tol, max_iter, res,
-                                        refinements, s);
-    case 2: return bicgstab_reliable<2>(ctx, n, q, col, val, val32, dinv32, dinv64, b, x, tol, max_iter, res,
-                                        refinements, s);
-    case 3: return bicgstab_reliable<3>(ctx, n, q, col, val, val32, dinv32, dinv64, b, x, tol, max_iter, res,
-                                        refinements, s);
-    default: return fail(RBFFD_E_ARG, "nrhs must be 1..3");
+    if (nrhs < 1 || nrhs > kMaxRhs) return fail(RBFFD_E_ARG, "nrhs must be 1..3");
+    if (precision == RBFFD_FP32_IR) {
+        // FP32 vectors and preconditioner, FP32 matrix
+        switch (nrhs) {
+        case 1: return bicgstab_reliable<float, 1>(ctx, n, q, col, val, val32, dinv32, dinv64, b, x, tol, max_iter,
+                                                   res, refinements, s);
+        case 2: return bicgstab_reliable<float, 2>(ctx, n, q, col, val, val32, dinv32, dinv64, b, x, tol, max_iter,
+                                                   res, refinements, s);
+        default: return bicgstab_reliable<float, 3>(ctx, n, q, col, val, val32, dinv32, dinv64, b, x, tol, max_iter,
+                                                    res, refinements, s);
+        }
     }
+    if (precision == RBFFD_FP32_MATRIX) {
+        // FP64 vectors and preconditioner, FP32 matrix
+        switch (nrhs) {
+        case 1: return bicgstab_reliable<double, 1>(ctx, n, q, col, val, val32, dinv64, dinv64, b, x, tol, max_iter,
+                                                    res, refinements, s);
+        case 2: return bicgstab_reliable<double, 2>(ctx, n, q, col, val, val32, dinv64, dinv64, b, x, tol, max_iter,
+                                                    res, refinements, s);
+        default: return bicgstab_reliable<double, 3>(ctx, n, q, col, val, val32, dinv64, dinv64, b, x, tol,
+                                                     max_iter, res, refinements, s);
+        }
+    }
+    return fail(RBFFD_E_ARG, "unknown mixed precision mode");
 }
 
 int residual_norms(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val, int nrhs,

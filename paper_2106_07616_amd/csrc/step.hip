@@ -331,7 +331,7 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
     const int gn = (int)((n + kBlock - 1) / kBlock);
     const int gpad = (int)((ops->npad + kBlock - 1) / kBlock);
     const int nblk = blocks_for(n);
-    const bool fp32 = o->precision == RBFFD_FP32_IR;
+    const bool fp32 = o->precision != RBFFD_FP64;
 
     hipLaunchKernelGGL(k_start, dim3(gn), dim3(kBlock), 0, s, n, dim, ops->kind, u, u_bc, p, B.ur, B.pr);
     RB_HIP(hipGetLastError());
@@ -352,7 +352,7 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
         if (fp32) {
             RB_CHECK(launch_to_fp32(ops->mval, ops->mval32, vs, s));
             RB_CHECK(launch_to_fp32(ops->mdinv, ops->mdinv32, ops->npad, s));
-            RB_CHECK(bicgstab_fp32_ir(ctx, n, q, ops->col, ops->mval, ops->mval32, ops->mdinv32, ops->mdinv, dim, B.bm,
+            RB_CHECK(bicgstab_mixed(ctx, o->precision, n, q, ops->col, ops->mval, ops->mval32, ops->mdinv32, ops->mdinv, dim, B.bm,
                                       B.ut, o->tol_krylov, o->max_krylov, &km, nullptr, s));
         } else {
             RB_CHECK(bicgstab(ctx, n, q, ops->col, ops->mval, ops->mdinv, dim, B.bm, B.ut, o->tol_krylov, o->max_krylov,
@@ -373,7 +373,7 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
         RB_HIP(hipMemsetAsync(B.pc, 0, vec, s));
         KrylovResult kp;
         if (fp32)
-            RB_CHECK(bicgstab_fp32_ir(ctx, n, q, ops->col, ops->pval, ops->pval32, ops->pdinv32, ops->pdinv, 1, B.f,
+            RB_CHECK(bicgstab_mixed(ctx, o->precision, n, q, ops->col, ops->pval, ops->pval32, ops->pdinv32, ops->pdinv, 1, B.f,
                                       B.pc, o->tol_krylov, o->max_krylov, &kp, nullptr, s));
         else
             RB_CHECK(bicgstab(ctx, n, q, ops->col, ops->pval, ops->pdinv, 1, B.f, B.pc, o->tol_krylov, o->max_krylov,
