@@ -254,23 +254,26 @@ int launch_weights(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q,
     const long long init = LLONG_MAX;
     RB_HIP(hipMemcpyAsync(bad_dev, &init, sizeof(init), hipMemcpyHostToDevice, s));
     const dim3 grid((unsigned)n), block(64);
-    if (dim == 2) {
-        if (ns <= 32)
-            hipLaunchKernelGGL((weights_kernel<32, 2>), grid, block, 0, s, xyz, nbr, n, q, m, phs, w, bad_dev);
-        else if (ns <= 64)
-            hipLaunchKernelGGL((weights_kernel<64, 2>), grid, block, 0, s, xyz, nbr, n, q, m, phs, w, bad_dev);
-        else
-            return fail(RBFFD_E_ARG, "collocation systems larger than 64 are not supported");
-    } else {
-        if (ns <= 32)
-            hipLaunchKernelGGL((weights_kernel<32, 3>), grid, block, 0, s, xyz, nbr, n, q, m, phs, w, bad_dev);
-        else if (ns <= 64)
-            hipLaunchKernelGGL((weights_kernel<64, 3>), grid, block, 0, s, xyz, nbr, n, q, m, phs, w, bad_dev);
-        else
-            return fail(RBFFD_E_ARG, "collocation systems larger than 64 are not supported");
+    // the register row holds NSP + R doubles: NSP is the smallest instantiated
+    // size >= ns, so little work goes to padding columns
+#define RB_WEIGHTS(NSP_)                                                                                  \
+    if (ns <= NSP_) {                                                                                     \
+        if (dim == 2)                                                                                     \
+            hipLaunchKernelGGL((weights_kernel<NSP_, 2>), grid, block, 0, s, xyz, nbr, n, q, m, phs, w, bad_dev); \
+        else                                                                                              \
+            hipLaunchKernelGGL((weights_kernel<NSP_, 3>), grid, block, 0, s, xyz, nbr, n, q, m, phs, w, bad_dev); \
+        RB_HIP(hipGetLastError());                                                                        \
+        return RBFFD_OK;                                                                                  \
     }
-    RB_HIP(hipGetLastError());
-    return RBFFD_OK;
+    RB_WEIGHTS(16)
+    RB_WEIGHTS(24)
+    RB_WEIGHTS(32)
+    RB_WEIGHTS(40)
+    RB_WEIGHTS(48)
+    RB_WEIGHTS(56)
+    RB_WEIGHTS(64)
+#undef RB_WEIGHTS
+    return fail(RBFFD_E_ARG, "collocation systems larger than 64 are not supported");
 }
 
 }  // namespace rbffd

@@ -257,6 +257,22 @@ def test_polynomial_flow_step(case, ctx, orc, which):
     np.testing.assert_array_equal(up.cpu().numpy(), un)
 
 
+@pytest.mark.parametrize("dim,k,q,phs", [(2, 1, 6, 3), (2, 3, 28, 3), (2, 4, 40, 3), (2, 2, 20, 5), (3, 2, 26, 3),
+                                          (3, 3, 44, 5)])
+def test_weights_all_system_sizes(ctx, orc, dim, k, q, phs):
+    """Every register-row width of the weight kernel (systems of 9 to 64
+    unknowns, r^3 and r^5) against the oracle: clouds bit-exact, weights within
+    1e-10 row-relative."""
+    c = W.kovasznay_square(nx=14) if dim == 2 else W.scattered_cube(8, seed=5)
+    nbr, w, _ = R.rbffd_build_stencils(ctx, R.DeviceCloud.from_numpy(c), k, q, phs)
+    nbr_o = orc.knn(c.xyz, q)
+    np.testing.assert_array_equal(nbr.cpu().numpy(), nbr_o)
+    w_o = orc.weights(c.xyz, nbr_o, k, phs)
+    err = _rel_rows(w.cpu().numpy(), w_o)
+    print(f"[weights] dim {dim} k {k} q {q} r^{phs}: {err:.2e}", flush=True)
+    assert err <= 1e-10
+
+
 def test_determinism(ctx):
     c = W.kovasznay_square(nx=30)
     s = R.Solver(ctx, c, 3)
