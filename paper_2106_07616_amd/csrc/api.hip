@@ -227,7 +227,7 @@ int rbffd_ops_free(rbffd_ops *ops)
     rbffd_ctx *ctx = ops->ctx;
     if (ctx) (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    void *ptrs[] = {ops->kind, ops->normal, ops->col, ops->val, ops->pval, ops->pdinv, ops->pval32,
+    void *ptrs[] = {ops->kind, ops->normal, ops->col, ops->cbase, ops->col16, ops->val, ops->pval, ops->pdinv, ops->pval32,
                     ops->pdinv32, ops->mval, ops->mdinv, ops->mval32, ops->mdinv32, ops->bidx,
                     ops->bpos, ops->gcol, ops->gval, ops->gdinv};
     for (void *p : ptrs)
@@ -278,14 +278,14 @@ int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, doubl
     int refine = 0;
     int st;
     if (opts->precision == RBFFD_FP64)
-        st = bicgstab(ctx, ops->n, ops->q, ops->col, ops->pval, ops->pdinv, 1, rhs, x, opts->tol,
+        st = bicgstab(ctx, ops->n, ops->q, cols_of(ops), ops->pval, ops->pdinv, 1, rhs, x, opts->tol,
                       opts->max_iter, &res, s);
     else
-        st = bicgstab_mixed(ctx, opts->precision, ops->n, ops->q, ops->col, ops->pval, ops->pval32, ops->pdinv32,
+        st = bicgstab_mixed(ctx, opts->precision, ops->n, ops->q, cols_of(ops), ops->pval, ops->pval32, ops->pdinv32,
                             ops->pdinv, 1, rhs, x, opts->tol, opts->max_iter, &res, &refine, s);
     if (st != RBFFD_OK) return st;
     double rr = 0.0;
-    RB_CHECK(residual_norms(ctx, ops->n, ops->q, ops->col, ops->pval, 1, rhs, x, &rr, s));
+    RB_CHECK(residual_norms(ctx, ops->n, ops->q, cols_of(ops), ops->pval, 1, rhs, x, &rr, s));
     if (stats) {
         stats->iters = res.iters[0];
         stats->status = res.status[0];

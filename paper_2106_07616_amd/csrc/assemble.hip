@@ -8,6 +8,8 @@
 // per entry.
 #include <cmath>
 
+#include <climits>
+
 #include "internal.h"
 
 namespace rbffd {
@@ -164,6 +166,34 @@ __global__ void ell_to_csr(const int32_t *__restrict__ col, const double *__rest
     oval[(int64_t)R * n * q + e] = pval[slot];
 }
 
+// Per 64-row slice: the smallest column and, when the slice's columns span
+// fewer than 65536 indices, 16-bit offsets from it (one wavefront per slice).
+__global__ __launch_bounds__(64) void slice_offsets(const int32_t *__restrict__ col, int64_t n, int q,
+                                                    int32_t *__restrict__ cbase, uint16_t *__restrict__ col16)
+{
+    const int64_t sl = blockIdx.x;
+    const int64_t i = sl * 64 + threadIdx.x;
+    int32_t mn = INT32_MAX, mx = INT32_MIN;
+    if (i < n)
+        for (int a = 0; a < q; ++a) {
+            const int32_t c = col[ell_at(i, a, q)];
+            mn = min(mn, c);
+            mx = max(mx, c);
+        }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = min(mn, __shfl_xor(mn, o, 64));
+        mx = max(mx, __shfl_xor(mx, o, 64));
+    }
+    const bool narrow = mx >= mn && (int64_t)mx - (int64_t)mn < 65536;
+    if (threadIdx.x == 0) cbase[sl] = narrow ? mn : -1;
+    if (narrow && i < n)
+        for (int a = 0; a < q; ++a) {
+            const int64_t slot = ell_at(i, a, q);
+            col16[slot] = (uint16_t)(col[slot] - mn);
+        }
+}
+
 template <typename T>
 int alloc_ops(rbffd_ops *ops, T **p, size_t count)
 {
@@ -197,6 +227,8 @@ int assemble_ops(rbffd_ctx *ctx, const rbffd_cloud *cloud, int q, int k, int phs
     RB_CHECK(alloc_ops(ops, &ops->kind, (size_t)n));
     RB_CHECK(alloc_ops(ops, &ops->normal, (size_t)n * dim));
     RB_CHECK(alloc_ops(ops, &ops->col, (size_t)nnz));
+    RB_CHECK(alloc_ops(ops, &ops->cbase, (size_t)(npad / 64)));
+    RB_CHECK(alloc_ops(ops, &ops->col16, (size_t)nnz));
     RB_CHECK(alloc_ops(ops, &ops->val, (size_t)nnz * ops->R));
     RB_CHECK(alloc_ops(ops, &ops->pval, (size_t)nnz));
     RB_CHECK(alloc_ops(ops, &ops->pdinv, (size_t)npad));
@@ -208,6 +240,8 @@ int assemble_ops(rbffd_ctx *ctx, const rbffd_cloud *cloud, int q, int k, int phs
     const unsigned nslices = (unsigned)(npad / 64);
     hipLaunchKernelGGL(sort_rows, dim3(nslices), dim3(64), sizeof(int32_t) * 64 * (q + 1), s, nbr, w, n, q, ops->R,
                        ops->col, ops->val, nnz);
+    RB_HIP(hipGetLastError());
+    hipLaunchKernelGGL(slice_offsets, dim3(nslices), dim3(64), 0, s, ops->col, n, q, ops->cbase, ops->col16);
     RB_HIP(hipGetLastError());
     const unsigned gb = (unsigned)((npad + kBlock - 1) / kBlock);
     if (dim == 2)
@@ -292,7 +326,7 @@ int apply_op(rbffd_ctx *ctx, const rbffd_ops *ops, int which, const double *x, d
 {
     (void)ctx;
     const double *v = (which <= ops->dim) ? ops->val + (int64_t)which * ops->npad * ops->q : ops->pval;
-    return spmv(ops->n, ops->q, ops->col, v, x, y, s);
+    return spmv(ops->n, ops->q, cols_of(ops), v, x, y, s);
 }
 
 }  // namespace rbffd

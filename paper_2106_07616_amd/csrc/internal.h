@@ -110,6 +110,8 @@ struct rbffd_ops {
     double *normal = nullptr;           // [n][dim]
     // sliced-ELL operators
     int32_t *col = nullptr;             // [npad*q]
+    int32_t *cbase = nullptr;           // [npad/64] smallest column of each 64-row slice, -1 = wide slice
+    uint16_t *col16 = nullptr;          // [npad*q]  col - cbase on slices whose columns span < 65536
     double *val = nullptr;              // [R][npad*q]  d/dx, d/dy, (d/dz), Laplacian
     double *pval = nullptr;             // [npad*q]     pressure-correction matrix
     double *pdinv = nullptr;            // [npad]       1 / diag(P)
@@ -128,6 +130,19 @@ struct rbffd_ops {
 };
 
 namespace rbffd {
+
+// Column indices of a sliced-ELL matrix. Where a 64-row slice's columns span
+// fewer than 65536 indices (nearly all slices of a Morton-ordered cloud), the
+// kernels read 16-bit offsets from the slice's smallest column instead of
+// 32-bit indices. cbase == nullptr: 32-bit indices only.
+struct ColIdx {
+    const int32_t *col;
+    const int32_t *cbase;
+    const uint16_t *col16;
+};
+
+inline ColIdx cols_of(const rbffd_ops *ops) { return ColIdx{ops->col, ops->cbase, ops->col16}; }
+inline ColIdx cols_plain(const int32_t *col) { return ColIdx{col, nullptr, nullptr}; }
 
 // ---------------------------------------------------------------------------
 // device helpers
@@ -204,17 +219,17 @@ struct KrylovResult {
     double relres[kMaxRhs] = {0, 0, 0};
     bool fp64_fallback = false;   // FP32 sweeps stalled; finished in FP64
 };
-int bicgstab(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val,
+int bicgstab(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val,
              const double *dinv, int nrhs, const double *b, double *x, double tol, int max_iter,
              KrylovResult *res, hipStream_t s);
 // FP32 matrix values with FP64 row accumulation and FP64 reliable updates;
 // precision RBFFD_FP32_IR keeps the Krylov vectors in FP32, RBFFD_FP32_MATRIX in FP64.
-int bicgstab_mixed(rbffd_ctx *ctx, int precision, int64_t n, int q, const int32_t *col, const double *val,
+int bicgstab_mixed(rbffd_ctx *ctx, int precision, int64_t n, int q, ColIdx col, const double *val,
                    const float *val32, const float *dinv32, const double *dinv64, int nrhs, const double *b, double *x,
                    double tol, int max_iter, KrylovResult *res, int *refinements, hipStream_t s);
-int spmv(int64_t n, int q, const int32_t *col, const double *val, const double *x, double *y,
+int spmv(int64_t n, int q, ColIdx col, const double *val, const double *x, double *y,
          hipStream_t s);
-int residual_norms(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val,
+int residual_norms(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val,
                    int nrhs, const double *b, const double *x, double *relres_out, hipStream_t s);
 
 int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, double *p,

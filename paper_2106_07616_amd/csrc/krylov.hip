@@ -68,27 +68,25 @@ __device__ inline double *partial(double *base, int kind, int r) { return base +
 template <typename T>
 __device__ inline int64_t row_base(int64_t i, int q) { return ((i >> 6) * (int64_t)q) * 64 + (i & 63); }
 
+template <bool NARROW>
+__device__ inline int32_t col_at(const ColIdx &ci, int64_t slot, int32_t cb)
+{
+    if constexpr (NARROW)
+        return cb + (int32_t)ci.col16[slot];
+    else
+        return ci.col[slot];
+}
+
 // acc[r] = sum_a A[i,a] x_r[col] for the right-hand sides with act[r]; entries in
 // column order. The activity test sits outside the entry loop so the loop body
 // is branch-free and the compiler can keep several column/value/gather loads in
-// flight.
-template <typename TM, typename TX, int NRHS>
-__device__ inline void row_dot(int64_t i, int q, const int32_t *__restrict__ col, const TM *__restrict__ val,
-                               const TX *__restrict__ x, int64_t xs, const bool *act, double *acc)
+// flight. Rows accumulate in FP64 also for FP32 operands: Laplacian-like rows
+// cancel terms ~1/h^2 larger than their sum, and FP32 accumulation of that
+// cancellation makes FP32 BiCGSTAB diverge on fine clouds.
+template <bool NARROW, typename TM, typename TX, int NRHS>
+__device__ inline void row_dot_cols(int64_t base, int q, const ColIdx &ci, int32_t cb, const TM *__restrict__ val,
+                                    const TX *__restrict__ x, int64_t xs, const bool *act, bool all, double *acc)
 {
-    const int64_t base = row_base<TM>(i, q);
-    bool all = true, any = false;
-#pragma unroll
-    for (int r = 0; r < NRHS; ++r) {
-        all = all && act[r];
-        any = any || act[r];
-    }
-#pragma unroll
-    for (int r = 0; r < NRHS; ++r) acc[r] = 0.0;
-    if (!any) return;
-    // rows accumulate in FP64 also for FP32 operands: Laplacian-like rows cancel
-    // terms ~1/h^2 larger than their sum, and FP32 accumulation of that
-    // cancellation makes FP32 BiCGSTAB diverge on fine clouds
     if (all) {
         double s[NRHS];
 #pragma unroll
@@ -96,7 +94,7 @@ __device__ inline void row_dot(int64_t i, int q, const int32_t *__restrict__ col
 #pragma unroll 4
         for (int a = 0; a < q; ++a) {
             const int64_t slot = base + (int64_t)a * 64;
-            const int32_t c = col[slot];
+            const int32_t c = col_at<NARROW>(ci, slot, cb);
             const double v = (double)val[slot];
 #pragma unroll
             for (int r = 0; r < NRHS; ++r) s[r] = fma(v, (double)x[r * xs + c], s[r]);
@@ -111,17 +109,39 @@ __device__ inline void row_dot(int64_t i, int q, const int32_t *__restrict__ col
 #pragma unroll 4
         for (int a = 0; a < q; ++a) {
             const int64_t slot = base + (int64_t)a * 64;
-            s1 = fma((double)val[slot], (double)x[r * xs + col[slot]], s1);
+            s1 = fma((double)val[slot], (double)x[r * xs + col_at<NARROW>(ci, slot, cb)], s1);
         }
         acc[r] = s1;
     }
+}
+
+template <typename TM, typename TX, int NRHS>
+__device__ inline void row_dot(int64_t i, int q, const ColIdx &ci, const TM *__restrict__ val,
+                               const TX *__restrict__ x, int64_t xs, const bool *act, double *acc)
+{
+    const int64_t base = row_base<TM>(i, q);
+    bool all = true, any = false;
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) {
+        all = all && act[r];
+        any = any || act[r];
+    }
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) acc[r] = 0.0;
+    if (!any) return;
+    // one 64-row slice per wavefront: the branch is uniform across the wave
+    const int32_t cb = ci.cbase ? ci.cbase[i >> 6] : -1;
+    if (cb >= 0)
+        row_dot_cols<true, TM, TX, NRHS>(base, q, ci, cb, val, x, xs, act, all, acc);
+    else
+        row_dot_cols<false, TM, TX, NRHS>(base, q, ci, cb, val, x, xs, act, all, acc);
 }
 
 __device__ inline int logical_block() { return xcd_block(gridDim.x); }
 
 // ---- plain SpMV ------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void spmv_kernel(int64_t n, int q, const int32_t *__restrict__ col,
+__global__ __launch_bounds__(kBlock) void spmv_kernel(int64_t n, int q, ColIdx col,
                                                       const T *__restrict__ val, const T *__restrict__ x,
                                                       T *__restrict__ y)
 {
@@ -149,7 +169,7 @@ __device__ inline bool all_done(const KState *st, int phase)
 
 // r = b - A x, r-hat = r; partials r-hat.r, r.r, b.b
 template <typename T, int NRHS>
-__global__ __launch_bounds__(kKB) void k_init(int64_t n, int64_t np, int q, const int32_t *__restrict__ col,
+__global__ __launch_bounds__(kKB) void k_init(int64_t n, int64_t np, int q, ColIdx col,
                                                  const T *__restrict__ val, const T *__restrict__ b, int64_t bs,
                                                  const T *__restrict__ x, int64_t xs, T *__restrict__ r,
                                                  T *__restrict__ rh, double *__restrict__ part)
@@ -310,7 +330,7 @@ __global__ __launch_bounds__(kKB) void k_p(int64_t n, int64_t np, const T *__res
 
 // KV: v = A p-hat; partial r-hat.v
 template <typename T, typename TM, int NRHS>
-__global__ __launch_bounds__(kKB) void k_v(int64_t n, int64_t np, int q, const int32_t *__restrict__ col,
+__global__ __launch_bounds__(kKB) void k_v(int64_t n, int64_t np, int q, ColIdx col,
                                               const TM *__restrict__ val, const T *__restrict__ rh,
                                               const T *__restrict__ ph, T *__restrict__ v, double *__restrict__ part,
                                               const KState *__restrict__ st, int phase)
@@ -399,7 +419,7 @@ __global__ __launch_bounds__(kKB) void k_s(int64_t n, int64_t np, const T *__res
 
 // KT: if ||s|| is small, x += alpha p-hat and stop; else t = A s-hat, partials t.s, t.t
 template <typename T, typename TM, int NRHS>
-__global__ __launch_bounds__(kKB) void k_t(int64_t n, int64_t np, int q, const int32_t *__restrict__ col,
+__global__ __launch_bounds__(kKB) void k_t(int64_t n, int64_t np, int q, ColIdx col,
                                               const TM *__restrict__ val, T *__restrict__ x, int64_t xs,
                                               const T *__restrict__ ph, const T *__restrict__ s,
                                               const T *__restrict__ sh, T *__restrict__ t, double *__restrict__ part,
@@ -531,7 +551,7 @@ __global__ __launch_bounds__(kKB) void k_x(int64_t n, int64_t np, T *__restrict_
 }
 
 // ||b - A x||^2 and ||b||^2 per right-hand side (FP64), partials then one block
-__global__ __launch_bounds__(kBlock) void k_resid(int64_t n, int q, int nrhs, const int32_t *__restrict__ col,
+__global__ __launch_bounds__(kBlock) void k_resid(int64_t n, int q, int nrhs, ColIdx col,
                                                   const double *__restrict__ val, const double *__restrict__ b,
                                                   int64_t bs, const double *__restrict__ x, int64_t xs,
                                                   double *__restrict__ part)
@@ -584,7 +604,7 @@ __global__ void k_refine_add(int64_t n, int nrhs, double *__restrict__ x, int64_
 // ||b||^2 of the FP64 residual for the host. With init set, r-hat = r and the
 // ||b||^2 partials of the iteration are written as well.
 template <typename T, int NRHS>
-__global__ __launch_bounds__(kKB) void k_rel_resid(int64_t n, int64_t np, int q, const int32_t *__restrict__ col,
+__global__ __launch_bounds__(kKB) void k_rel_resid(int64_t n, int64_t np, int q, ColIdx col,
                                                    const double *__restrict__ val, const double *__restrict__ b,
                                                    int64_t bs, const double *__restrict__ x, int64_t xs,
                                                    T *__restrict__ r, T *__restrict__ rh, int init,
@@ -678,7 +698,7 @@ int get_work(rbffd_ctx *ctx, int64_t npad, int nrhs, Work *w)
 }
 
 template <typename T, int NRHS>
-int bicgstab_t(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const T *val, const T *dinv, const T *b,
+int bicgstab_t(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const T *val, const T *dinv, const T *b,
                int64_t bs, T *x, int64_t xs, double tol, int max_iter, KrylovResult *res, Work &w, hipStream_t s)
 {
     const int64_t np = pad64(n);
@@ -731,7 +751,7 @@ int bicgstab_t(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const T *va
 
 }  // namespace
 
-int spmv(int64_t n, int q, const int32_t *col, const double *val, const double *x, double *y, hipStream_t s)
+int spmv(int64_t n, int q, ColIdx col, const double *val, const double *x, double *y, hipStream_t s)
 {
     const int64_t nb = (n + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(spmv_kernel<double>, dim3((unsigned)nb), dim3(kBlock), 0, s, n, q, col, val, x, y);
@@ -739,7 +759,7 @@ int spmv(int64_t n, int q, const int32_t *col, const double *val, const double *
     return RBFFD_OK;
 }
 
-static int bicgstab_once(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val,
+static int bicgstab_once(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val,
                          const double *dinv, int nrhs, const double *b, double *x, double tol, int max_iter,
                          KrylovResult *res, hipStream_t s)
 {
@@ -755,7 +775,7 @@ static int bicgstab_once(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, c
 
 // BiCGSTAB with up to two restarts from the true residual: when the recursive
 // residual has met tol but ||b - A x|| exceeds 10 tol ||b||, iterate again from x.
-int bicgstab(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val, const double *dinv, int nrhs,
+int bicgstab(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, const double *dinv, int nrhs,
              const double *b, double *x, double tol, int max_iter, KrylovResult *res, hipStream_t s)
 {
     KrylovResult acc;
@@ -795,7 +815,7 @@ constexpr double kRelDelta = 0.1;
 constexpr int kStallIters = 1000;   // forced update; less than 2x progress since the last one = stall
 
 template <typename T, int NRHS>
-static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val,
+static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val,
                              const float *val32, const T *dinv, const double *dinv64, const double *b, double *x,
                              double tol, int max_iter, KrylovResult *res, int *refinements, hipStream_t s)
 {
@@ -940,7 +960,7 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, const int32_t *co
     return RBFFD_OK;
 }
 
-int bicgstab_mixed(rbffd_ctx *ctx, int precision, int64_t n, int q, const int32_t *col, const double *val,
+int bicgstab_mixed(rbffd_ctx *ctx, int precision, int64_t n, int q, ColIdx col, const double *val,
                    const float *val32, const float *dinv32, const double *dinv64, int nrhs, const double *b, double *x,
                    double tol, int max_iter, KrylovResult *res, int *refinements, hipStream_t s)
 {
@@ -970,7 +990,7 @@ int bicgstab_mixed(rbffd_ctx *ctx, int precision, int64_t n, int q, const int32_
     return fail(RBFFD_E_ARG, "unknown mixed precision mode");
 }
 
-int residual_norms(rbffd_ctx *ctx, int64_t n, int q, const int32_t *col, const double *val, int nrhs,
+int residual_norms(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, int nrhs,
                    const double *b, const double *x, double *relres_out, hipStream_t s)
 {
     const int nblk = grid_blocks(n);

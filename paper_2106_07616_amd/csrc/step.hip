@@ -352,10 +352,10 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
         if (fp32) {
             RB_CHECK(launch_to_fp32(ops->mval, ops->mval32, vs, s));
             RB_CHECK(launch_to_fp32(ops->mdinv, ops->mdinv32, ops->npad, s));
-            RB_CHECK(bicgstab_mixed(ctx, o->precision, n, q, ops->col, ops->mval, ops->mval32, ops->mdinv32, ops->mdinv, dim, B.bm,
+            RB_CHECK(bicgstab_mixed(ctx, o->precision, n, q, cols_of(ops), ops->mval, ops->mval32, ops->mdinv32, ops->mdinv, dim, B.bm,
                                       B.ut, o->tol_krylov, o->max_krylov, &km, nullptr, s));
         } else {
-            RB_CHECK(bicgstab(ctx, n, q, ops->col, ops->mval, ops->mdinv, dim, B.bm, B.ut, o->tol_krylov, o->max_krylov,
+            RB_CHECK(bicgstab(ctx, n, q, cols_of(ops), ops->mval, ops->mdinv, dim, B.bm, B.ut, o->tol_krylov, o->max_krylov,
                               &km, s));
         }
         for (int e = 0; e < dim; ++e) {
@@ -373,10 +373,10 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
         RB_HIP(hipMemsetAsync(B.pc, 0, vec, s));
         KrylovResult kp;
         if (fp32)
-            RB_CHECK(bicgstab_mixed(ctx, o->precision, n, q, ops->col, ops->pval, ops->pval32, ops->pdinv32, ops->pdinv, 1, B.f,
+            RB_CHECK(bicgstab_mixed(ctx, o->precision, n, q, cols_of(ops), ops->pval, ops->pval32, ops->pdinv32, ops->pdinv, 1, B.f,
                                       B.pc, o->tol_krylov, o->max_krylov, &kp, nullptr, s));
         else
-            RB_CHECK(bicgstab(ctx, n, q, ops->col, ops->pval, ops->pdinv, 1, B.f, B.pc, o->tol_krylov, o->max_krylov,
+            RB_CHECK(bicgstab(ctx, n, q, cols_of(ops), ops->pval, ops->pdinv, 1, B.f, B.pc, o->tol_krylov, o->max_krylov,
                               &kp, s));
         kit_p += kp.iters[0];
         if (kp.status[0] != RBFFD_OK && status == RBFFD_OK) status = kp.status[0];
@@ -396,7 +396,7 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
                                    dt, a1, a2, a3, B.bb, B.pb);
             RB_HIP(hipGetLastError());
             KrylovResult kb;
-            RB_CHECK(bicgstab(ctx, ops->nb, q, ops->gcol, ops->gval, ops->gdinv, 1, B.bb, B.pb, o->tol_krylov,
+            RB_CHECK(bicgstab(ctx, ops->nb, q, cols_plain(ops->gcol), ops->gval, ops->gdinv, 1, B.bb, B.pb, o->tol_krylov,
                               o->max_krylov, &kb, s));
             kit_b += kb.iters[0];
             if (kb.status[0] != RBFFD_OK && status == RBFFD_OK) status = kb.status[0];
@@ -467,7 +467,7 @@ int convdiff_lambda(rbffd_ctx *ctx, const rbffd_ops *ops, const double *u0, doub
     hipLaunchKernelGGL(k_sq_partial, dim3(nblk), dim3(kBlock), 0, s, n, y, part);
     hipLaunchKernelGGL(k_normalise, dim3(nblk), dim3(kBlock), 0, s, n, y, x, part, nblk, nrm);
     for (int it = 0; it < iters; ++it) {
-        RB_CHECK(spmv(n, q, ops->col, ops->mval, x, y, s));
+        RB_CHECK(spmv(n, q, cols_of(ops), ops->mval, x, y, s));
         hipLaunchKernelGGL(k_sq_partial, dim3(nblk), dim3(kBlock), 0, s, n, y, part);
         hipLaunchKernelGGL(k_normalise, dim3(nblk), dim3(kBlock), 0, s, n, y, x, part, nblk, nrm);
     }
