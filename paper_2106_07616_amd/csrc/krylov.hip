@@ -6,11 +6,19 @@
 // Every kernel streams the sliced-ELL matrix with one thread per row: entry a of
 // 64 consecutive rows is one contiguous run, so column indices and values are
 // read fully coalesced, and the gathered vector entries of Morton-ordered points
-// hit in cache. Each BiCGSTAB iteration is five kernels; the global dot
-// products are finished redundantly by every block of the consuming kernel
-// from per-block partials in a fixed order, so the scalars (alpha, beta, omega)
-// never travel to the host and the result is deterministic run to run. The
-// host only reads a small state record every few iterations to stop.
+// hit in cache. Each BiCGSTAB iteration is four kernels:
+//   KV  v = A p-hat, r-hat.v                 (convergence test on ||r|| first)
+//   KS  alpha; s = r - alpha v, s-hat = D^-1 s, s.s, r-hat.s
+//   KT  t = A s-hat, t.s, t.t, r-hat.t       (or x += alpha p-hat if ||s|| is small)
+//   KX  omega; x += alpha p-hat + omega s-hat; r = s - omega t; r.r; and the next
+//       search direction p-hat = D^-1 r + beta (p-hat - omega D^-1 v), with
+//       beta = (rho'/rho)(alpha/omega) and rho' = r-hat.r taken as
+//       r-hat.s - omega r-hat.t (the same inner product, by linearity), so the
+//       search-direction update needs no kernel of its own.
+// Global dot products are finished redundantly by every block of the consuming
+// kernel from per-block partials in a fixed order, so the scalars never travel
+// to the host and results are deterministic run to run. The host only reads a
+// small state record every few iterations to stop.
 #include <cmath>
 
 #include "internal.h"
@@ -22,14 +30,18 @@ namespace {
 // Per right-hand-side solver state. A kernel launch that finishes a solve
 // records its launch sequence number in done_at; blocks of that same launch keep
 // working (they may still owe updates of their rows), later launches skip.
+// Fields written by block 0 during a launch are read by other blocks only in
+// later launches.
 struct KState {
-    double rho_prev;  // r-hat . r of the previous iteration
-    double rho_cur;   // r-hat . r of this iteration (after a restart: r . r)
+    double rho;       // r-hat . r of the current iteration (set by KV)
+    double rho_next;  // r-hat . r of the next iteration (set by KX, taken over by the next KV)
     double alpha, omega;
     double rr, bb;    // ||r||^2 (recursive) at the start of the last iteration, ||b||^2
-    int done_at;  // 0 running, else sequence number of the launch that finished
-    int iters;    // completed iterations
-    int status;   // RBFFD_OK / RBFFD_E_BREAKDOWN
+    int done_at;      // 0 running, else sequence number of the launch that finished
+    int iters;        // completed iterations
+    int status;       // RBFFD_OK / RBFFD_E_BREAKDOWN
+    int restart;      // r-hat was reset to r: rho = r.r at the next KV
+    int refresh;      // r was replaced by a true residual: rho = r-hat.r at the next KV
     int pad;
 };
 
@@ -54,7 +66,7 @@ __device__ inline double kblock_sum(double v, double *lds)
 
 __device__ inline bool finished_before(const KState &s, int phase) { return s.done_at != 0 && s.done_at < phase; }
 
-enum { P_RHR = 0, P_RR, P_BB, P_RV, P_SS, P_TS, P_TT, P_COUNT };
+enum { P_RHR = 0, P_RR, P_BB, P_RV, P_SS, P_RS, P_TS, P_TT, P_RT, P_COUNT };
 
 struct Work {
     // vectors, [nrhs][npad] each
@@ -154,10 +166,6 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int64_t n, int q, ColIdx c
 }
 
 // ---- BiCGSTAB ---------------------------------------------------------------
-struct Scal {
-    double rhr[kMaxRhs], rr[kMaxRhs], bb[kMaxRhs];
-};
-
 template <int NRHS>
 __device__ inline bool all_done(const KState *st, int phase)
 {
@@ -167,44 +175,32 @@ __device__ inline bool all_done(const KState *st, int phase)
     return d;
 }
 
-// r = b - A x, r-hat = r; partials r-hat.r, r.r, b.b
-template <typename T, int NRHS>
-__global__ __launch_bounds__(kKB) void k_init(int64_t n, int64_t np, int q, ColIdx col,
-                                                 const T *__restrict__ val, const T *__restrict__ b, int64_t bs,
-                                                 const T *__restrict__ x, int64_t xs, T *__restrict__ r,
-                                                 T *__restrict__ rh, double *__restrict__ part)
+// Block sums of NV per-thread values, written as partial blk of NV arrays.
+template <int NV>
+__device__ inline void write_partials(const double *v, double *const *parts)
 {
-    __shared__ double lds[kKB / 64];
-    double srr[NRHS], sbb[NRHS];
+    __shared__ double red[NV][kKB / 64];
+    double w[NV];
 #pragma unroll
-    for (int k = 0; k < NRHS; ++k) srr[k] = sbb[k] = 0.0;
-    bool act[NRHS];
+    for (int m = 0; m < NV; ++m) w[m] = v[m];
 #pragma unroll
-    for (int k = 0; k < NRHS; ++k) act[k] = true;
-    for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kKB) {
-        double ax[NRHS];
-        row_dot<T, T, NRHS>(i, q, col, val, x, xs, act, ax);
+    for (int o = 32; o > 0; o >>= 1)
 #pragma unroll
-        for (int k = 0; k < NRHS; ++k) {
-            const double bi = (double)b[k * bs + i];
-            const T ri = (T)(bi - ax[k]);
-            r[k * np + i] = ri;
-            rh[k * np + i] = ri;
-            srr[k] += (double)ri * (double)ri;
-            sbb[k] += bi * bi;
+        for (int m = 0; m < NV; ++m) w[m] += __shfl_xor(w[m], o, 64);
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0)
+#pragma unroll
+        for (int m = 0; m < NV; ++m) red[m][wv] = w[m];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int m = 0; m < NV; ++m) {
+            double t = 0.0;
+#pragma unroll
+            for (int j = 0; j < kKB / 64; ++j) t += red[m][j];
+            parts[m][blockIdx.x] = t;
         }
-    }
-    const int blk = blockIdx.x;
-#pragma unroll
-    for (int k = 0; k < NRHS; ++k) {
-        const double a = kblock_sum(srr[k], lds);
-        const double c = kblock_sum(sbb[k], lds);
-        if (threadIdx.x == 0) {
-            partial(part, P_RHR, k)[blk] = a;
-            partial(part, P_RR, k)[blk] = a;
-            partial(part, P_BB, k)[blk] = c;
-        }
-    }
 }
 
 // Sums of NV partial arrays (np entries each) in a fixed order, identical in
@@ -247,128 +243,120 @@ __device__ inline void sum_partials_n(const double *const *parts, int np, double
     }
 }
 
-// Common prologue: sums of r-hat.r, r.r, b.b for every right-hand side.
-template <int NRHS>
-__device__ inline void prologue_rho(const double *part, int np, double *lds, Scal &sc)
-{
-    (void)lds;
-    const double *ps[3 * NRHS];
-    double out[3 * NRHS];
-#pragma unroll
-    for (int k = 0; k < NRHS; ++k) {
-        ps[3 * k + 0] = partial((double *)part, P_RHR, k);
-        ps[3 * k + 1] = partial((double *)part, P_RR, k);
-        ps[3 * k + 2] = partial((double *)part, P_BB, k);
-    }
-    sum_partials_n<3 * NRHS>(ps, np, out);
-#pragma unroll
-    for (int k = 0; k < NRHS; ++k) {
-        sc.rhr[k] = out[3 * k + 0];
-        sc.rr[k] = out[3 * k + 1];
-        sc.bb[k] = out[3 * k + 2];
-    }
-}
-
-__device__ inline bool want_restart(const KState &s, double rhr, double rr)
-{
-    return s.iters > 0 && (fabs(rhr) < 1e-300 || fabs(rhr) < 1e-30 * rr);
-}
-
-// KP: convergence test on r; p-hat = D^-1 r + beta (p-hat - omega D^-1 v)
+// r = b - A x, r-hat = r, p-hat = D^-1 r; partials r.r and b.b
 template <typename T, int NRHS>
-__global__ __launch_bounds__(kKB) void k_p(int64_t n, int64_t np, const T *__restrict__ dinv,
-                                              T *__restrict__ x, int64_t xs, T *__restrict__ r,
-                                              T *__restrict__ rh, T *__restrict__ ph, const T *__restrict__ v,
-                                              double *__restrict__ part, KState *__restrict__ st, int nblk_prev,
-                                              double tol2, int phase)
+__global__ __launch_bounds__(kKB) void k_init(int64_t n, int64_t np, int q, ColIdx col, const T *__restrict__ val,
+                                              const T *__restrict__ dinv, const T *__restrict__ b, int64_t bs,
+                                              const T *__restrict__ x, int64_t xs, T *__restrict__ r,
+                                              T *__restrict__ rh, T *__restrict__ ph, double *__restrict__ part)
 {
-    __shared__ double lds[kKB / 64];
-    // partial sums first: their loads overlap the state read, and finished
-    // solves only cost this prologue
-    Scal sc;
-    prologue_rho<NRHS>(part, nblk_prev, lds, sc);
-    if (all_done<NRHS>(st, phase)) return;
-    bool act[NRHS], zero[NRHS], restart[NRHS];
-    double beta[NRHS], om[NRHS];
+    double acc[2 * NRHS];
 #pragma unroll
-    for (int k = 0; k < NRHS; ++k) {
-        const KState s = st[k];
-        act[k] = !finished_before(s, phase);
-        zero[k] = act[k] && sc.bb[k] == 0.0;
-        const bool conv = act[k] && !zero[k] && sc.rr[k] <= tol2 * sc.bb[k];
-        restart[k] = want_restart(s, sc.rhr[k], sc.rr[k]);
-        beta[k] = (s.iters == 0 || restart[k]) ? 0.0 : (sc.rhr[k] / s.rho_prev) * (s.alpha / s.omega);
-        om[k] = s.omega;
-        if (act[k] && blockIdx.x == 0 && threadIdx.x == 0) {
-            st[k].rho_cur = restart[k] ? sc.rr[k] : sc.rhr[k];
-            st[k].rr = sc.rr[k];
-            st[k].bb = sc.bb[k];
-        }
-        if ((zero[k] || conv) && blockIdx.x == 0 && threadIdx.x == 0) {
-            st[k].done_at = phase;
-            st[k].status = RBFFD_OK;
-        }
-        if (conv) act[k] = false;
-    }
+    for (int k = 0; k < 2 * NRHS; ++k) acc[k] = 0.0;
+    bool act[NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) act[k] = true;
     for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kKB) {
+        double ax[NRHS];
+        row_dot<T, T, NRHS>(i, q, col, val, x, xs, act, ax);
         const T di = dinv[i];
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
-            if (!act[k]) continue;
-            if (zero[k]) {
-                x[k * xs + i] = 0;
-                continue;
-            }
-            const T ri = r[k * np + i];
-            if (restart[k]) rh[k * np + i] = ri;
-            const T pn = (beta[k] == 0.0) ? (T)(di * ri)
-                                          : (T)(di * ri + beta[k] * (ph[k * np + i] - om[k] * (di * v[k * np + i])));
-            ph[k * np + i] = pn;
+            const double bi = (double)b[k * bs + i];
+            const T ri = (T)(bi - ax[k]);
+            r[k * np + i] = ri;
+            rh[k * np + i] = ri;
+            ph[k * np + i] = di * ri;
+            acc[2 * k] += (double)ri * (double)ri;
+            acc[2 * k + 1] += bi * bi;
         }
     }
+    double *ps[2 * NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+        ps[2 * k] = partial(part, P_RR, k);
+        ps[2 * k + 1] = partial(part, P_BB, k);
+    }
+    write_partials<2 * NRHS>(acc, ps);
 }
 
-// KV: v = A p-hat; partial r-hat.v
+// KV: convergence test on ||r||; v = A p-hat; partial r-hat.v. With check_only
+// set, only the test runs (after the last permitted iteration).
 template <typename T, typename TM, int NRHS>
-__global__ __launch_bounds__(kKB) void k_v(int64_t n, int64_t np, int q, ColIdx col,
-                                              const TM *__restrict__ val, const T *__restrict__ rh,
-                                              const T *__restrict__ ph, T *__restrict__ v, double *__restrict__ part,
-                                              const KState *__restrict__ st, int phase)
+__global__ __launch_bounds__(kKB) void k_v(int64_t n, int64_t np, int q, ColIdx col, const TM *__restrict__ val,
+                                           const T *__restrict__ rh, const T *__restrict__ ph, T *__restrict__ v,
+                                           T *__restrict__ x, int64_t xs, double *__restrict__ part,
+                                           KState *__restrict__ st, int nblk, double tol2, int check_only, int phase)
 {
-    __shared__ double lds[kKB / 64];
-    if (all_done<NRHS>(st, phase)) return;
-    bool act[NRHS];
+    double sums[3 * NRHS];
+    {
+        const double *ps[3 * NRHS];
 #pragma unroll
-    for (int k = 0; k < NRHS; ++k) act[k] = !finished_before(st[k], phase);
+        for (int k = 0; k < NRHS; ++k) {
+            ps[3 * k] = partial(part, P_RR, k);
+            ps[3 * k + 1] = partial(part, P_BB, k);
+            ps[3 * k + 2] = partial(part, P_RHR, k);
+        }
+        sum_partials_n<3 * NRHS>(ps, nblk, sums);
+    }
+    if (all_done<NRHS>(st, phase)) return;
+    bool act[NRHS], zero[NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+        const KState s = st[k];
+        const double rr = sums[3 * k], bb = sums[3 * k + 1];
+        act[k] = !finished_before(s, phase);
+        zero[k] = act[k] && bb == 0.0;
+        const bool conv = act[k] && !zero[k] && rr <= tol2 * bb;
+        if (act[k] && blockIdx.x == 0 && threadIdx.x == 0) {
+            st[k].rr = rr;
+            st[k].bb = bb;
+            if (s.refresh)
+                st[k].rho = sums[3 * k + 2];
+            else if (s.iters == 0 || s.restart)
+                st[k].rho = rr;
+            else
+                st[k].rho = s.rho_next;
+            if (zero[k] || conv) {
+                st[k].done_at = phase;
+                st[k].status = RBFFD_OK;
+            }
+        }
+        if (conv || check_only) act[k] = false;
+    }
     double srv[NRHS];
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) srv[k] = 0.0;
     for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kKB) {
-        double av[NRHS];
-        row_dot<TM, T, NRHS>(i, q, col, val, ph, np, act, av);
+        bool sp[NRHS];
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
-            if (!act[k]) continue;
+            sp[k] = act[k] && !zero[k];
+            if (act[k] && zero[k]) x[k * xs + i] = (T)0;
+        }
+        double av[NRHS];
+        row_dot<TM, T, NRHS>(i, q, col, val, ph, np, sp, av);
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            if (!sp[k]) continue;
             const T vi = (T)av[k];
             v[k * np + i] = vi;
             srv[k] += (double)rh[k * np + i] * (double)vi;
         }
     }
+    double *ps[NRHS];
 #pragma unroll
-    for (int k = 0; k < NRHS; ++k) {
-        const double a = kblock_sum(srv[k], lds);
-        if (threadIdx.x == 0) partial(part, P_RV, k)[blockIdx.x] = a;
-    }
+    for (int k = 0; k < NRHS; ++k) ps[k] = partial(part, P_RV, k);
+    write_partials<NRHS>(srv, ps);
 }
 
-// KS: alpha = rho / r-hat.v; s = r - alpha v; s-hat = D^-1 s; partial s.s
+// KS: alpha = rho / r-hat.v; s = r - alpha v; s-hat = D^-1 s; partials s.s, r-hat.s
 template <typename T, int NRHS>
 __global__ __launch_bounds__(kKB) void k_s(int64_t n, int64_t np, const T *__restrict__ dinv,
-                                              const T *__restrict__ r, const T *__restrict__ v, T *__restrict__ s,
-                                              T *__restrict__ sh, double *__restrict__ part, KState *__restrict__ st,
-                                              int nblk, int phase)
+                                           const T *__restrict__ r, const T *__restrict__ rh, const T *__restrict__ v,
+                                           T *__restrict__ s, T *__restrict__ sh, double *__restrict__ part,
+                                           KState *__restrict__ st, int nblk, int phase)
 {
-    __shared__ double lds[kKB / 64];
     double rvs[NRHS];
     {
         const double *ps[NRHS];
@@ -383,12 +371,12 @@ __global__ __launch_bounds__(kKB) void k_s(int64_t n, int64_t np, const T *__res
     for (int k = 0; k < NRHS; ++k) {
         const KState stk = st[k];
         act[k] = !finished_before(stk, phase);
-        const double rho = stk.rho_cur;
         const double rv = rvs[k];
-        alpha[k] = (rv != 0.0) ? rho / rv : 0.0;
+        alpha[k] = (rv != 0.0) ? stk.rho / rv : 0.0;
         if (act[k] && blockIdx.x == 0 && threadIdx.x == 0) {
             st[k].alpha = alpha[k];
-            st[k].rho_prev = rho;
+            st[k].restart = 0;
+            st[k].refresh = 0;
             if (rv == 0.0) {
                 st[k].done_at = phase;
                 st[k].status = RBFFD_E_BREAKDOWN;
@@ -396,9 +384,9 @@ __global__ __launch_bounds__(kKB) void k_s(int64_t n, int64_t np, const T *__res
         }
         if (rv == 0.0) act[k] = false;
     }
-    double sss[NRHS];
+    double acc[2 * NRHS];
 #pragma unroll
-    for (int k = 0; k < NRHS; ++k) sss[k] = 0.0;
+    for (int k = 0; k < 2 * NRHS; ++k) acc[k] = 0.0;
     for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kKB) {
         const T di = dinv[i];
 #pragma unroll
@@ -407,58 +395,54 @@ __global__ __launch_bounds__(kKB) void k_s(int64_t n, int64_t np, const T *__res
             const T si = (T)((double)r[k * np + i] - alpha[k] * (double)v[k * np + i]);
             s[k * np + i] = si;
             sh[k * np + i] = di * si;
-            sss[k] += (double)si * (double)si;
+            acc[2 * k] += (double)si * (double)si;
+            acc[2 * k + 1] += (double)rh[k * np + i] * (double)si;
         }
     }
+    double *ps[2 * NRHS];
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) {
-        const double a = kblock_sum(sss[k], lds);
-        if (threadIdx.x == 0) partial(part, P_SS, k)[blockIdx.x] = a;
+        ps[2 * k] = partial(part, P_SS, k);
+        ps[2 * k + 1] = partial(part, P_RS, k);
     }
+    write_partials<2 * NRHS>(acc, ps);
 }
 
-// KT: if ||s|| is small, x += alpha p-hat and stop; else t = A s-hat, partials t.s, t.t
+// KT: if ||s|| is small, x += alpha p-hat and stop; else t = A s-hat and
+// partials t.s, t.t, r-hat.t
 template <typename T, typename TM, int NRHS>
-__global__ __launch_bounds__(kKB) void k_t(int64_t n, int64_t np, int q, ColIdx col,
-                                              const TM *__restrict__ val, T *__restrict__ x, int64_t xs,
-                                              const T *__restrict__ ph, const T *__restrict__ s,
-                                              const T *__restrict__ sh, T *__restrict__ t, double *__restrict__ part,
-                                              KState *__restrict__ st, int nblk, double tol2, int phase)
+__global__ __launch_bounds__(kKB) void k_t(int64_t n, int64_t np, int q, ColIdx col, const TM *__restrict__ val,
+                                           T *__restrict__ x, int64_t xs, const T *__restrict__ ph,
+                                           const T *__restrict__ s, const T *__restrict__ sh,
+                                           const T *__restrict__ rh, T *__restrict__ t, double *__restrict__ part,
+                                           KState *__restrict__ st, int nblk, double tol2, int phase)
 {
-    __shared__ double lds[kKB / 64];
-    bool act[NRHS], half[NRHS];
-    double alpha[NRHS];
-    double sums[2 * NRHS];
+    double ss[NRHS];
     {
-        const double *ps[2 * NRHS];
+        const double *ps[NRHS];
 #pragma unroll
-        for (int k = 0; k < NRHS; ++k) {
-            ps[2 * k] = partial(part, P_SS, k);
-            ps[2 * k + 1] = partial(part, P_BB, k);
-        }
-        sum_partials_n<2 * NRHS>(ps, nblk, sums);
+        for (int k = 0; k < NRHS; ++k) ps[k] = partial(part, P_SS, k);
+        sum_partials_n<NRHS>(ps, nblk, ss);
     }
     if (all_done<NRHS>(st, phase)) return;
+    bool act[NRHS], half[NRHS], sp[NRHS];
+    double alpha[NRHS];
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) {
         const KState stk = st[k];
         act[k] = !finished_before(stk, phase);
         alpha[k] = stk.alpha;
-        const double ss = sums[2 * k];
-        const double bb = sums[2 * k + 1];
-        half[k] = act[k] && ss <= tol2 * bb;
+        half[k] = act[k] && ss[k] <= tol2 * stk.bb;
+        sp[k] = act[k] && !half[k];
         if (half[k] && blockIdx.x == 0 && threadIdx.x == 0) {
             st[k].done_at = phase;
             st[k].status = RBFFD_OK;
             st[k].iters = stk.iters + 1;
         }
     }
-    bool sp[NRHS];
+    double acc[3 * NRHS];
 #pragma unroll
-    for (int k = 0; k < NRHS; ++k) sp[k] = act[k] && !half[k];
-    double sts[NRHS], stt[NRHS];
-#pragma unroll
-    for (int k = 0; k < NRHS; ++k) sts[k] = stt[k] = 0.0;
+    for (int k = 0; k < 3 * NRHS; ++k) acc[k] = 0.0;
     for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kKB) {
 #pragma unroll
         for (int k = 0; k < NRHS; ++k)
@@ -470,84 +454,92 @@ __global__ __launch_bounds__(kKB) void k_t(int64_t n, int64_t np, int q, ColIdx 
             if (!sp[k]) continue;
             const T ti = (T)at[k];
             t[k * np + i] = ti;
-            sts[k] += (double)ti * (double)s[k * np + i];
-            stt[k] += (double)ti * (double)ti;
+            acc[3 * k] += (double)ti * (double)s[k * np + i];
+            acc[3 * k + 1] += (double)ti * (double)ti;
+            acc[3 * k + 2] += (double)rh[k * np + i] * (double)ti;
         }
     }
+    double *ps[3 * NRHS];
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) {
-        const double a = kblock_sum(sts[k], lds);
-        const double c = kblock_sum(stt[k], lds);
-        if (threadIdx.x == 0) {
-            partial(part, P_TS, k)[blockIdx.x] = a;
-            partial(part, P_TT, k)[blockIdx.x] = c;
-        }
+        ps[3 * k] = partial(part, P_TS, k);
+        ps[3 * k + 1] = partial(part, P_TT, k);
+        ps[3 * k + 2] = partial(part, P_RT, k);
     }
+    write_partials<3 * NRHS>(acc, ps);
 }
 
-// KX: omega = t.s / t.t; x += alpha p-hat + omega s-hat; r = s - omega t; partials r-hat.r, r.r
+// KX: omega = t.s / t.t; x += alpha p-hat + omega s-hat; r = s - omega t;
+// rho' = r-hat.s - omega r-hat.t; restart (r-hat = r) when rho' has vanished
+// relative to s.s; p-hat = D^-1 r + beta (p-hat - omega D^-1 v); partial r.r
 template <typename T, int NRHS>
-__global__ __launch_bounds__(kKB) void k_x(int64_t n, int64_t np, T *__restrict__ x, int64_t xs,
-                                              const T *__restrict__ ph, const T *__restrict__ s,
-                                              const T *__restrict__ sh, const T *__restrict__ t, T *__restrict__ r,
-                                              const T *__restrict__ rh, double *__restrict__ part,
-                                              KState *__restrict__ st, int nblk, int phase)
+__global__ __launch_bounds__(kKB) void k_x(int64_t n, int64_t np, const T *__restrict__ dinv, T *__restrict__ x,
+                                           int64_t xs, T *__restrict__ ph, const T *__restrict__ s,
+                                           const T *__restrict__ sh, const T *__restrict__ t,
+                                           const T *__restrict__ v, T *__restrict__ r, T *__restrict__ rh,
+                                           double *__restrict__ part, KState *__restrict__ st, int nblk, int phase)
 {
-    __shared__ double lds[kKB / 64];
-    bool act[NRHS];
-    double alpha[NRHS], omega[NRHS];
-    double sums[2 * NRHS];
+    double sums[5 * NRHS];
     {
-        const double *ps[2 * NRHS];
+        const double *ps[5 * NRHS];
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
-            ps[2 * k] = partial(part, P_TS, k);
-            ps[2 * k + 1] = partial(part, P_TT, k);
+            ps[5 * k] = partial(part, P_TS, k);
+            ps[5 * k + 1] = partial(part, P_TT, k);
+            ps[5 * k + 2] = partial(part, P_RS, k);
+            ps[5 * k + 3] = partial(part, P_RT, k);
+            ps[5 * k + 4] = partial(part, P_SS, k);
         }
-        sum_partials_n<2 * NRHS>(ps, nblk, sums);
+        sum_partials_n<5 * NRHS>(ps, nblk, sums);
     }
     if (all_done<NRHS>(st, phase)) return;
+    bool act[NRHS], restart[NRHS];
+    double alpha[NRHS], omega[NRHS], beta[NRHS];
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) {
         const KState stk = st[k];
         act[k] = !finished_before(stk, phase);
         alpha[k] = stk.alpha;
-        const double ts = sums[2 * k];
-        const double tt = sums[2 * k + 1];
+        const double ts = sums[5 * k], tt = sums[5 * k + 1], rs = sums[5 * k + 2], rt = sums[5 * k + 3];
+        const double ssk = sums[5 * k + 4];
         omega[k] = (tt > 0.0) ? ts / tt : 0.0;
+        const double rho1 = rs - omega[k] * rt;
+        restart[k] = fabs(rho1) < 1e-300 || fabs(rho1) < 1e-30 * ssk;
+        beta[k] = (restart[k] || omega[k] == 0.0) ? 0.0 : (rho1 / stk.rho) * (alpha[k] / omega[k]);
         if (act[k] && blockIdx.x == 0 && threadIdx.x == 0) {
             st[k].omega = omega[k];
             st[k].iters = stk.iters + 1;
+            st[k].rho_next = rho1;
+            st[k].restart = restart[k];
             if (omega[k] == 0.0) {
                 st[k].done_at = phase;
                 st[k].status = RBFFD_E_BREAKDOWN;
             }
         }
     }
-    double srhr[NRHS], srr[NRHS];
+    double srr[NRHS];
 #pragma unroll
-    for (int k = 0; k < NRHS; ++k) srhr[k] = srr[k] = 0.0;
+    for (int k = 0; k < NRHS; ++k) srr[k] = 0.0;
     for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kKB) {
+        const T di = dinv[i];
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
             if (!act[k]) continue;
-            x[k * xs + i] = (T)((double)x[k * xs + i] + alpha[k] * (double)ph[k * np + i] +
-                                omega[k] * (double)sh[k * np + i]);
+            const T phi = ph[k * np + i];
+            x[k * xs + i] = (T)((double)x[k * xs + i] + alpha[k] * (double)phi + omega[k] * (double)sh[k * np + i]);
             const T ri = (T)((double)s[k * np + i] - omega[k] * (double)t[k * np + i]);
             r[k * np + i] = ri;
-            srhr[k] += (double)rh[k * np + i] * (double)ri;
+            if (restart[k]) rh[k * np + i] = ri;
+            const T pn = (beta[k] == 0.0) ? (T)(di * ri)
+                                          : (T)(di * ri + beta[k] * ((double)phi - omega[k] * (double)(di * v[k * np + i])));
+            ph[k * np + i] = pn;
             srr[k] += (double)ri * (double)ri;
         }
     }
+    double *ps[NRHS];
 #pragma unroll
-    for (int k = 0; k < NRHS; ++k) {
-        const double a = kblock_sum(srhr[k], lds);
-        const double c = kblock_sum(srr[k], lds);
-        if (threadIdx.x == 0) {
-            partial(part, P_RHR, k)[blockIdx.x] = a;
-            partial(part, P_RR, k)[blockIdx.x] = c;
-        }
-    }
+    for (int k = 0; k < NRHS; ++k) ps[k] = partial(part, P_RR, k);
+    write_partials<NRHS>(srr, ps);
 }
 
 // ||b - A x||^2 and ||b||^2 per right-hand side (FP64), partials then one block
@@ -601,14 +593,15 @@ __global__ void k_refine_add(int64_t n, int nrhs, double *__restrict__ x, int64_
 
 // Part 2: the true residual r = b - A x in FP64 replaces the FP32 recursive
 // residual; partials r-hat.r and r.r for the FP32 iteration, and ||r||^2,
-// ||b||^2 of the FP64 residual for the host. With init set, r-hat = r and the
-// ||b||^2 partials of the iteration are written as well.
+// ||b||^2 of the FP64 residual for the host. With init set, r-hat = r,
+// p-hat = D^-1 r and the ||b||^2 partials of the iteration are written as well.
 template <typename T, int NRHS>
 __global__ __launch_bounds__(kKB) void k_rel_resid(int64_t n, int64_t np, int q, ColIdx col,
                                                    const double *__restrict__ val, const double *__restrict__ b,
                                                    int64_t bs, const double *__restrict__ x, int64_t xs,
-                                                   T *__restrict__ r, T *__restrict__ rh, int init,
-                                                   double *__restrict__ part, double *__restrict__ tpart)
+                                                   const T *__restrict__ dinv, T *__restrict__ r, T *__restrict__ rh,
+                                                   T *__restrict__ ph, int init, double *__restrict__ part,
+                                                   double *__restrict__ tpart)
 {
     __shared__ double lds[kKB / 64];
     double rhr[NRHS], rr[NRHS], tr[NRHS], bb[NRHS];
@@ -629,6 +622,7 @@ __global__ __launch_bounds__(kKB) void k_rel_resid(int64_t n, int64_t np, int q,
             T hf;
             if (init) {
                 rh[k * np + i] = rf;
+                ph[k * np + i] = dinv[i] * rf;
                 hf = rf;
             } else {
                 hf = rh[k * np + i];
@@ -652,6 +646,22 @@ __global__ __launch_bounds__(kKB) void k_rel_resid(int64_t n, int64_t np, int q,
             tpart[(2 * k) * kMaxBlocks + blockIdx.x] = a3;
             tpart[(2 * k + 1) * kMaxBlocks + blockIdx.x] = a4;
         }
+    }
+}
+
+// r-hat = r and p-hat = D^-1 r for the right-hand sides in mask (a solve that
+// continues after its recursion had stopped)
+template <typename T>
+__global__ void k_dir_reset(int64_t n, int64_t np, int nrhs, unsigned mask, const T *__restrict__ dinv,
+                            const T *__restrict__ r, T *__restrict__ rh, T *__restrict__ ph)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 0; k < nrhs; ++k) {
+        if (!((mask >> k) & 1u)) continue;
+        const T ri = r[k * np + i];
+        rh[k * np + i] = ri;
+        ph[k * np + i] = dinv[i] * ri;
     }
 }
 
@@ -707,10 +717,7 @@ int bicgstab_t(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const T *val, const
     T *r = (T *)w.r, *rh = (T *)w.rh, *ph = (T *)w.ph, *v = (T *)w.v, *sv = (T *)w.s, *sh = (T *)w.sh, *t = (T *)w.t;
     const double tol2 = tol * tol;
     RB_HIP(hipMemsetAsync(w.st, 0, sizeof(KState) * kMaxRhs, s));
-    // p-hat and v start at zero (only read after the first iteration)
-    RB_HIP(hipMemsetAsync(ph, 0, sizeof(T) * np * NRHS, s));
-    RB_HIP(hipMemsetAsync(v, 0, sizeof(T) * np * NRHS, s));
-    hipLaunchKernelGGL((k_init<T, NRHS>), g, bl, 0, s, n, np, q, col, val, b, bs, x, xs, r, rh, w.part);
+    hipLaunchKernelGGL((k_init<T, NRHS>), g, bl, 0, s, n, np, q, col, val, dinv, b, bs, x, xs, r, rh, ph, w.part);
     RB_HIP(hipGetLastError());
     KState *hst = nullptr;
     RB_CHECK(host_scratch(ctx, kHostKrylov, sizeof(KState) * kMaxRhs, (void **)&hst));
@@ -719,21 +726,18 @@ int bicgstab_t(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const T *val, const
     while (!finished) {
         const int todo = std::min(chunk, max_iter - it);
         for (int c = 0; c < todo; ++c) {
-            hipLaunchKernelGGL((k_p<T, NRHS>), g, bl, 0, s, n, np, dinv, x, xs, r, rh, ph, v, w.part, w.st, nblk, tol2,
-                               ++phase);
-            hipLaunchKernelGGL((k_v<T, T, NRHS>), g, bl, 0, s, n, np, q, col, val, rh, ph, v, w.part, w.st, ++phase);
-            hipLaunchKernelGGL((k_s<T, NRHS>), g, bl, 0, s, n, np, dinv, r, v, sv, sh, w.part, w.st, nblk, ++phase);
-            hipLaunchKernelGGL((k_t<T, T, NRHS>), g, bl, 0, s, n, np, q, col, val, x, xs, ph, sv, sh, t, w.part, w.st, nblk,
-                               tol2, ++phase);
-            hipLaunchKernelGGL((k_x<T, NRHS>), g, bl, 0, s, n, np, x, xs, ph, sv, sh, t, r, rh, w.part, w.st, nblk,
-                               ++phase);
+            hipLaunchKernelGGL((k_v<T, T, NRHS>), g, bl, 0, s, n, np, q, col, val, rh, ph, v, x, xs, w.part, w.st, nblk,
+                               tol2, 0, ++phase);
+            hipLaunchKernelGGL((k_s<T, NRHS>), g, bl, 0, s, n, np, dinv, r, rh, v, sv, sh, w.part, w.st, nblk, ++phase);
+            hipLaunchKernelGGL((k_t<T, T, NRHS>), g, bl, 0, s, n, np, q, col, val, x, xs, ph, sv, sh, rh, t, w.part,
+                               w.st, nblk, tol2, ++phase);
+            hipLaunchKernelGGL((k_x<T, NRHS>), g, bl, 0, s, n, np, dinv, x, xs, ph, sv, sh, t, v, r, rh, w.part, w.st,
+                               nblk, ++phase);
         }
         it += std::max(todo, 0);
-        if (it >= max_iter) {
-            // final convergence test on the last residual
-            hipLaunchKernelGGL((k_p<T, NRHS>), g, bl, 0, s, n, np, dinv, x, xs, r, rh, ph, v, w.part, w.st, nblk, tol2,
-                               ++phase);
-        }
+        // convergence test on the last residual, so the host sees it now
+        hipLaunchKernelGGL((k_v<T, T, NRHS>), g, bl, 0, s, n, np, q, col, val, rh, ph, v, x, xs, w.part, w.st, nblk,
+                           tol2, 1, ++phase);
         RB_HIP(hipGetLastError());
         RB_HIP(hipMemcpyAsync(hst, w.st, sizeof(KState) * kMaxRhs, hipMemcpyDeviceToHost, s));
         RB_HIP(hipStreamSynchronize(s));
@@ -843,8 +847,8 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const
 
     // true residual of x: replaces r (and r-hat when init), norms to the host
     auto true_residual = [&](int init) -> int {
-        hipLaunchKernelGGL((k_rel_resid<T, NRHS>), g, bl, 0, s, n, np, q, col, val, b, n, x, n, r, rh, init, w.part,
-                           tpart);
+        hipLaunchKernelGGL((k_rel_resid<T, NRHS>), g, bl, 0, s, n, np, q, col, val, b, n, x, n, dinv, r, rh, ph, init,
+                           w.part, tpart);
         hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(kBlock), 0, s, tpart, nblk, NRHS, rout);
         RB_HIP(hipGetLastError());
         RB_HIP(hipMemcpyAsync(rr, rout, sizeof(double) * NRHS, hipMemcpyDeviceToHost, s));
@@ -870,17 +874,17 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const
     while (!conv && it < max_iter) {
         const int todo = std::min(chunk, max_iter - it);
         for (int c = 0; c < todo; ++c) {
-            hipLaunchKernelGGL((k_p<T, NRHS>), g, bl, 0, s, n, np, dinv, d, np, r, rh, ph, v, w.part, w.st, nblk, tol2,
-                               ++phase);
-            hipLaunchKernelGGL((k_v<T, float, NRHS>), g, bl, 0, s, n, np, q, col, val32, rh, ph, v, w.part, w.st,
-                               ++phase);
-            hipLaunchKernelGGL((k_s<T, NRHS>), g, bl, 0, s, n, np, dinv, r, v, sv, sh, w.part, w.st, nblk, ++phase);
-            hipLaunchKernelGGL((k_t<T, float, NRHS>), g, bl, 0, s, n, np, q, col, val32, d, np, ph, sv, sh, t, w.part,
-                               w.st, nblk, tol2, ++phase);
-            hipLaunchKernelGGL((k_x<T, NRHS>), g, bl, 0, s, n, np, d, np, ph, sv, sh, t, r, rh, w.part, w.st, nblk,
-                               ++phase);
+            hipLaunchKernelGGL((k_v<T, float, NRHS>), g, bl, 0, s, n, np, q, col, val32, rh, ph, v, d, np, w.part,
+                               w.st, nblk, tol2, 0, ++phase);
+            hipLaunchKernelGGL((k_s<T, NRHS>), g, bl, 0, s, n, np, dinv, r, rh, v, sv, sh, w.part, w.st, nblk, ++phase);
+            hipLaunchKernelGGL((k_t<T, float, NRHS>), g, bl, 0, s, n, np, q, col, val32, d, np, ph, sv, sh, rh, t,
+                               w.part, w.st, nblk, tol2, ++phase);
+            hipLaunchKernelGGL((k_x<T, NRHS>), g, bl, 0, s, n, np, dinv, d, np, ph, sv, sh, t, v, r, rh, w.part, w.st,
+                               nblk, ++phase);
         }
         it += todo;
+        hipLaunchKernelGGL((k_v<T, float, NRHS>), g, bl, 0, s, n, np, q, col, val32, rh, ph, v, d, np, w.part, w.st,
+                           nblk, tol2, 1, ++phase);
         chunk = std::min(chunk * 2, 32);
         RB_HIP(hipGetLastError());
         RB_HIP(hipMemcpyAsync(hst, w.st, sizeof(KState) * kMaxRhs, hipMemcpyDeviceToHost, s));
@@ -921,16 +925,23 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const
             for (int k = 0; k < NRHS; ++k) best[k] = rr[k];
         }
         if (conv) break;
-        // continue: a right-hand side the recursion called converged keeps iterating
-        bool rewrite = false;
+        // continue from the replaced residual: rho = r-hat.r at the next KV; a
+        // right-hand side whose recursion had stopped restarts its directions
+        unsigned mask = 0;
         for (int k = 0; k < NRHS; ++k) {
             rmax[k] = rr[k];
             if (hst[k].done_at != 0 && rr[k] > tol) {
                 hst[k].done_at = 0;
-                rewrite = true;
+                hst[k].restart = 1;
+                hst[k].refresh = 0;
+                mask |= 1u << k;
+            } else {
+                hst[k].refresh = 1;
             }
         }
-        if (rewrite) RB_HIP(hipMemcpyAsync(w.st, hst, sizeof(KState) * kMaxRhs, hipMemcpyHostToDevice, s));
+        if (mask)
+            hipLaunchKernelGGL(k_dir_reset<T>, dim3(gb), dim3(kBlock), 0, s, n, np, NRHS, mask, dinv, r, rh, ph);
+        RB_HIP(hipMemcpyAsync(w.st, hst, sizeof(KState) * kMaxRhs, hipMemcpyHostToDevice, s));
     }
     int total_it[kMaxRhs] = {0, 0, 0};
     for (int k = 0; k < NRHS; ++k) total_it[k] = (it > 0) ? hst[k].iters : 0;
