@@ -173,6 +173,25 @@ typedef struct {
 int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, double *x,
                   const rbffd_krylov_opts *opts, rbffd_krylov_stats *stats, void *hip_stream);
 
+/* (Sec. 3, "preconditioned BiCGSTAB"; the batched configuration of many
+ * independent clouds) Solve P_j x_j = rhs_j for `count` independent
+ * pressure-correction systems at once, each as poisson_solve would (right
+ * Jacobi BiCGSTAB, FP64, restarts from the true residual). Every kernel stage
+ * is one launch over all systems; each system owns a fixed range of thread
+ * blocks and its own reductions, so its result is bitwise the same alone or
+ * in any batch. Systems stop independently.
+ *   ops, rhs, x: HOST arrays of `count` pointers; rhs[j], x[j] device [n_j];
+ *                x[j] holds the initial guess on entry and the solution on
+ *                return
+ *   opts:        shared by all systems; precision must be RBFFD_FP64
+ *   stats:       host array of `count` records (may be NULL)
+ * Returns RBFFD_OK when every system converged, RBFFD_E_NOCONV or
+ * RBFFD_E_BREAKDOWN (the first failing code) otherwise; per-system outcomes
+ * are in stats. */
+int poisson_solve_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops, const double *const *rhs,
+                          double *const *x, const rbffd_krylov_opts *opts, rbffd_krylov_stats *stats,
+                          void *hip_stream);
+
 /* ---- time step ---------------------------------------------------------- */
 typedef struct {
     double rho, mu;         /* density and dynamic viscosity                         */

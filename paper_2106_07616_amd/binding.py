@@ -24,8 +24,8 @@ STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_OOM", -3: "E_SINGULAR", -4: "E_NOCO
 
 EXPORTED = ["rbffd_last_error", "rbffd_ctx_create", "rbffd_ctx_destroy", "rbffd_ctx_bytes_in_use",
             "rbffd_stencil_sizes", "rbffd_build_stencils", "rbffd_assemble", "rbffd_ops_free",
-            "rbffd_ops_info", "rbffd_ops_export_csr", "rbffd_apply", "poisson_solve", "simple_step",
-            "rbffd_convdiff_lambda"]
+            "rbffd_ops_info", "rbffd_ops_export_csr", "rbffd_apply", "poisson_solve", "poisson_solve_batched",
+            "simple_step", "rbffd_convdiff_lambda"]
 
 
 class RbffdError(RuntimeError):
@@ -82,6 +82,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.rbffd_ops_export_csr.argtypes = [P, P, P, P]
     L.rbffd_apply.argtypes = [P, P, I, P, P, P]
     L.poisson_solve.argtypes = [P, P, P, P, C.POINTER(KrylovOptsT), C.POINTER(KrylovStatsT), P]
+    L.poisson_solve_batched.argtypes = [P, I, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(KrylovOptsT),
+                                        C.POINTER(KrylovStatsT), P]
     L.simple_step.argtypes = [P, P, P, P, P, P, P, C.POINTER(StepOptsT), C.POINTER(StepStatsT), P]
     L.rbffd_convdiff_lambda.argtypes = [P, P, P, D, D, I, C.POINTER(D), P]
     return L
@@ -240,6 +242,22 @@ def poisson_solve(ctx: Context, ops: Operators, rhs: torch.Tensor, x: torch.Tens
     _check(st, allow=(RBFFD_E_NOCONV,) if allow_noconv else ())
     return dict(iters=s.iters, status=s.status, refinements=s.refinements, fp64_fallback=s.fp64_fallback,
                 relres=s.relres)
+
+
+def poisson_solve_batched(ctx: Context, ops: list, rhs: list, x: list, tol: float = 1e-10, max_iter: int = 5000,
+                          allow_noconv: bool = False):
+    """FP64 pressure-correction solves of several independent systems in one
+    batch; x[j] is updated in place. Returns one stats dict per system."""
+    m = len(ops)
+    if not (m == len(rhs) == len(x)) or m == 0:
+        raise ValueError("ops, rhs and x must be non-empty lists of the same length")
+    arr = C.c_void_p * m
+    o = KrylovOptsT(tol, max_iter, RBFFD_FP64)
+    stats = (KrylovStatsT * m)()
+    st = lib().poisson_solve_batched(ctx.handle, m, arr(*[op.handle for op in ops]), arr(*[_ptr(t) for t in rhs]),
+                                     arr(*[_ptr(t) for t in x]), C.byref(o), stats, _stream())
+    _check(st, allow=(RBFFD_E_NOCONV, RBFFD_E_BREAKDOWN) if allow_noconv else ())
+    return [dict(iters=s_.iters, status=s_.status, relres=s_.relres) for s_ in stats]
 
 
 BDF2 = (1.5, -2.0, 0.5)

@@ -3,6 +3,8 @@
 #include <cstring>
 #include <new>
 
+#include <vector>
+
 #include "internal.h"
 
 namespace rbffd {
@@ -51,7 +53,7 @@ int workspace(rbffd_ctx *ctx, int slot, size_t bytes, void **p)
     Buffer &b = ctx->ws[slot];
     if (b.bytes < bytes) {
         size_t grow = bytes + bytes / 4;
-        if (slot == WS_HOST_PINNED) {
+        if (slot == WS_HOST_PINNED || slot == WS_BATCH_HOST) {
             if (b.ptr) (void)hipHostFree(b.ptr);
             b.ptr = nullptr;
             b.bytes = 0;
@@ -144,7 +146,7 @@ int rbffd_ctx_destroy(rbffd_ctx *ctx)
     (void)hipDeviceSynchronize();
     for (int s = 0; s < WS_COUNT; ++s) {
         if (!ctx->ws[s].ptr) continue;
-        if (s == WS_HOST_PINNED)
+        if (s == WS_HOST_PINNED || s == WS_BATCH_HOST)
             (void)hipHostFree(ctx->ws[s].ptr);
         else
             dev_free(ctx, ctx->ws[s].ptr, ctx->ws[s].bytes);
@@ -296,6 +298,40 @@ int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, doubl
     if (res.status[0] != RBFFD_OK)
         return fail(res.status[0], "poisson_solve did not converge in " + std::to_string(res.iters[0]) +
                                        " iterations (relres " + std::to_string(rr) + ")");
+    return RBFFD_OK;
+}
+
+int poisson_solve_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops, const double *const *rhs,
+                          double *const *x, const rbffd_krylov_opts *opts, rbffd_krylov_stats *stats,
+                          void *hip_stream)
+{
+    if (!ctx || !ops || !rhs || !x || !opts) return fail(RBFFD_E_ARG, "NULL argument");
+    if (count < 1) return fail(RBFFD_E_ARG, "count must be >= 1");
+    if (!(opts->tol >= 0.0) || opts->max_iter < 0) return fail(RBFFD_E_ARG, "bad Krylov options");
+    if (opts->precision != RBFFD_FP64) return fail(RBFFD_E_ARG, "batched solves run in FP64");
+    std::vector<BatchSystem> sys((size_t)count);
+    for (int j = 0; j < count; ++j) {
+        if (!ops[j] || !rhs[j] || !x[j])
+            return fail(RBFFD_E_ARG, "NULL operator, right-hand side or solution of system " + std::to_string(j));
+        sys[j] = BatchSystem{ops[j]->n, ops[j]->q, cols_of(ops[j]), ops[j]->pval, ops[j]->pdinv, rhs[j], x[j]};
+    }
+    RB_HIP(hipSetDevice(ctx->device));
+    std::vector<int> iters((size_t)count), status((size_t)count);
+    std::vector<double> relres((size_t)count);
+    RB_CHECK(bicgstab_batched(ctx, count, sys.data(), opts->tol, opts->max_iter, iters.data(), status.data(),
+                              relres.data(), (hipStream_t)hip_stream));
+    int first = RBFFD_OK;
+    for (int j = 0; j < count; ++j) {
+        if (stats) {
+            stats[j].iters = iters[j];
+            stats[j].status = status[j];
+            stats[j].refinements = 0;
+            stats[j].fp64_fallback = 0;
+            stats[j].relres = relres[j];
+        }
+        if (status[j] != RBFFD_OK && first == RBFFD_OK) first = status[j];
+    }
+    if (first != RBFFD_OK) return fail(first, "a batched system did not converge");
     return RBFFD_OK;
 }
 

@@ -67,6 +67,9 @@ enum WorkSlot {
     WS_STEP,         // time-step fields
     WS_STEP2,        // boundary-pressure solve and step reductions
     WS_MISC,
+    WS_RESID,        // true-residual partials
+    WS_BATCH,        // batched solves: descriptors, block map, partials, states, vectors
+    WS_BATCH_HOST,   // batched solves: pinned host staging
     WS_HOST_PINNED,  // pinned host staging for small read-backs
     WS_COUNT
 };
@@ -227,6 +230,19 @@ int bicgstab(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val,
 int bicgstab_mixed(rbffd_ctx *ctx, int precision, int64_t n, int q, ColIdx col, const double *val,
                    const float *val32, const float *dinv32, const double *dinv64, int nrhs, const double *b, double *x,
                    double tol, int max_iter, KrylovResult *res, int *refinements, hipStream_t s);
+// One system of a batched solve (host description).
+struct BatchSystem {
+    int64_t n;
+    int q;
+    ColIdx col;
+    const double *val, *dinv, *b;
+    double *x;
+};
+// FP64 BiCGSTAB on many independent systems at once: every kernel stage is one
+// launch over all systems, each system owns a fixed range of blocks and its own
+// reductions, so its result does not depend on the other systems in the batch.
+int bicgstab_batched(rbffd_ctx *ctx, int count, const BatchSystem *sys, double tol, int max_iter, int *iters,
+                     int *status, double *relres, hipStream_t s);
 int spmv(int64_t n, int q, ColIdx col, const double *val, const double *x, double *y,
          hipStream_t s);
 int residual_norms(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val,

@@ -19,7 +19,9 @@
 // kernel from per-block partials in a fixed order, so the scalars never travel
 // to the host and results are deterministic run to run. The host only reads a
 // small state record every few iterations to stop.
+#include <climits>
 #include <cmath>
+#include <vector>
 
 #include "internal.h"
 
@@ -753,6 +755,242 @@ int bicgstab_t(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const T *val, const
     return RBFFD_OK;
 }
 
+// ---- batched BiCGSTAB (FP64, one right-hand side per system) ---------------
+// System j owns blocks [boff, boff + nblk); block b belongs to system bmap[b].
+// Partials live at part[kind * pstride + b], so every system reduces over its
+// own blocks in block order.
+struct BSys {
+    int64_t n, np;
+    int q, boff, nblk, pad;
+    ColIdx col;
+    const double *val, *dinv, *b;
+    double *x;
+    double *r, *rh, *ph, *v, *s, *sh, *t;
+};
+
+__device__ inline const double *bpart(const double *part, int kind, int pstride, int boff)
+{
+    return part + (int64_t)kind * pstride + boff;
+}
+
+__global__ __launch_bounds__(kKB) void kb_init(const BSys *__restrict__ sys, const int *__restrict__ bmap,
+                                               double *__restrict__ part, int pstride, const KState *__restrict__ st)
+{
+    const int j = bmap[blockIdx.x];
+    const BSys S = sys[j];
+    if (st[j].done_at != 0) return;
+    const int lb = blockIdx.x - S.boff;
+    double rr = 0.0, bb = 0.0;
+    const bool act[1] = {true};
+    for (int64_t i = (int64_t)lb * kKB + threadIdx.x; i < S.n; i += (int64_t)S.nblk * kKB) {
+        double ax[1];
+        row_dot<double, double, 1>(i, S.q, S.col, S.val, S.x, 0, act, ax);
+        const double bi = S.b[i];
+        const double ri = bi - ax[0];
+        S.r[i] = ri;
+        S.rh[i] = ri;
+        S.ph[i] = S.dinv[i] * ri;
+        rr += ri * ri;
+        bb += bi * bi;
+    }
+    const double acc[2] = {rr, bb};
+    double *ps[2] = {part + (int64_t)P_RR * pstride, part + (int64_t)P_BB * pstride};
+    write_partials<2>(acc, ps);
+}
+
+__global__ __launch_bounds__(kKB) void kb_v(const BSys *__restrict__ sys, const int *__restrict__ bmap,
+                                            double *__restrict__ part, int pstride, KState *__restrict__ st,
+                                            double tol2, int check_only, int phase)
+{
+    const int j = bmap[blockIdx.x];
+    const BSys S = sys[j];
+    double sums[2];
+    {
+        const double *ps[2] = {bpart(part, P_RR, pstride, S.boff), bpart(part, P_BB, pstride, S.boff)};
+        sum_partials_n<2>(ps, S.nblk, sums);
+    }
+    const KState k0 = st[j];
+    if (finished_before(k0, phase)) return;
+    const double rr = sums[0], bb = sums[1];
+    const bool zero = bb == 0.0;
+    const bool conv = !zero && rr <= tol2 * bb;
+    const bool lead = blockIdx.x == S.boff && threadIdx.x == 0;
+    if (lead) {
+        st[j].rr = rr;
+        st[j].bb = bb;
+        st[j].rho = (k0.iters == 0 || k0.restart) ? rr : k0.rho_next;
+        if (zero || conv) {
+            st[j].done_at = phase;
+            st[j].status = RBFFD_OK;
+        }
+    }
+    if (conv || (check_only && !zero)) return;
+    const int lb = blockIdx.x - S.boff;
+    double srv = 0.0;
+    const bool act[1] = {!zero};
+    for (int64_t i = (int64_t)lb * kKB + threadIdx.x; i < S.n; i += (int64_t)S.nblk * kKB) {
+        if (zero) {
+            S.x[i] = 0.0;
+            continue;
+        }
+        double av[1];
+        row_dot<double, double, 1>(i, S.q, S.col, S.val, S.ph, 0, act, av);
+        S.v[i] = av[0];
+        srv += S.rh[i] * av[0];
+    }
+    double *ps[1] = {part + (int64_t)P_RV * pstride};
+    write_partials<1>(&srv, ps);
+}
+
+__global__ __launch_bounds__(kKB) void kb_s(const BSys *__restrict__ sys, const int *__restrict__ bmap,
+                                            double *__restrict__ part, int pstride, KState *__restrict__ st, int phase)
+{
+    const int j = bmap[blockIdx.x];
+    const BSys S = sys[j];
+    double rv;
+    {
+        const double *ps[1] = {bpart(part, P_RV, pstride, S.boff)};
+        sum_partials_n<1>(ps, S.nblk, &rv);
+    }
+    const KState k0 = st[j];
+    if (finished_before(k0, phase)) return;
+    const double alpha = (rv != 0.0) ? k0.rho / rv : 0.0;
+    if (blockIdx.x == S.boff && threadIdx.x == 0) {
+        st[j].alpha = alpha;
+        st[j].restart = 0;
+        if (rv == 0.0) {
+            st[j].done_at = phase;
+            st[j].status = RBFFD_E_BREAKDOWN;
+        }
+    }
+    if (rv == 0.0) return;
+    const int lb = blockIdx.x - S.boff;
+    double acc[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)lb * kKB + threadIdx.x; i < S.n; i += (int64_t)S.nblk * kKB) {
+        const double si = S.r[i] - alpha * S.v[i];
+        S.s[i] = si;
+        S.sh[i] = S.dinv[i] * si;
+        acc[0] += si * si;
+        acc[1] += S.rh[i] * si;
+    }
+    double *ps[2] = {part + (int64_t)P_SS * pstride, part + (int64_t)P_RS * pstride};
+    write_partials<2>(acc, ps);
+}
+
+__global__ __launch_bounds__(kKB) void kb_t(const BSys *__restrict__ sys, const int *__restrict__ bmap,
+                                            double *__restrict__ part, int pstride, KState *__restrict__ st,
+                                            double tol2, int phase)
+{
+    const int j = bmap[blockIdx.x];
+    const BSys S = sys[j];
+    double ss;
+    {
+        const double *ps[1] = {bpart(part, P_SS, pstride, S.boff)};
+        sum_partials_n<1>(ps, S.nblk, &ss);
+    }
+    const KState k0 = st[j];
+    if (finished_before(k0, phase)) return;
+    const bool half = ss <= tol2 * k0.bb;
+    if (half && blockIdx.x == S.boff && threadIdx.x == 0) {
+        st[j].done_at = phase;
+        st[j].status = RBFFD_OK;
+        st[j].iters = k0.iters + 1;
+    }
+    const int lb = blockIdx.x - S.boff;
+    double acc[3] = {0.0, 0.0, 0.0};
+    const bool act[1] = {true};
+    for (int64_t i = (int64_t)lb * kKB + threadIdx.x; i < S.n; i += (int64_t)S.nblk * kKB) {
+        if (half) {
+            S.x[i] += k0.alpha * S.ph[i];
+            continue;
+        }
+        double at[1];
+        row_dot<double, double, 1>(i, S.q, S.col, S.val, S.sh, 0, act, at);
+        S.t[i] = at[0];
+        acc[0] += at[0] * S.s[i];
+        acc[1] += at[0] * at[0];
+        acc[2] += S.rh[i] * at[0];
+    }
+    if (half) return;
+    double *ps[3] = {part + (int64_t)P_TS * pstride, part + (int64_t)P_TT * pstride, part + (int64_t)P_RT * pstride};
+    write_partials<3>(acc, ps);
+}
+
+__global__ __launch_bounds__(kKB) void kb_x(const BSys *__restrict__ sys, const int *__restrict__ bmap,
+                                            double *__restrict__ part, int pstride, KState *__restrict__ st, int phase)
+{
+    const int j = bmap[blockIdx.x];
+    const BSys S = sys[j];
+    double sums[5];
+    {
+        const double *ps[5] = {bpart(part, P_TS, pstride, S.boff), bpart(part, P_TT, pstride, S.boff),
+                               bpart(part, P_RS, pstride, S.boff), bpart(part, P_RT, pstride, S.boff),
+                               bpart(part, P_SS, pstride, S.boff)};
+        sum_partials_n<5>(ps, S.nblk, sums);
+    }
+    const KState k0 = st[j];
+    if (finished_before(k0, phase)) return;
+    const double ts = sums[0], tt = sums[1], rs = sums[2], rt = sums[3], ssk = sums[4];
+    const double omega = (tt > 0.0) ? ts / tt : 0.0;
+    const double rho1 = rs - omega * rt;
+    const bool restart = fabs(rho1) < 1e-300 || fabs(rho1) < 1e-30 * ssk;
+    const double beta = (restart || omega == 0.0) ? 0.0 : (rho1 / k0.rho) * (k0.alpha / omega);
+    if (blockIdx.x == S.boff && threadIdx.x == 0) {
+        st[j].omega = omega;
+        st[j].iters = k0.iters + 1;
+        st[j].rho_next = rho1;
+        st[j].restart = restart;
+        if (omega == 0.0) {
+            st[j].done_at = phase;
+            st[j].status = RBFFD_E_BREAKDOWN;
+        }
+    }
+    const int lb = blockIdx.x - S.boff;
+    double srr = 0.0;
+    for (int64_t i = (int64_t)lb * kKB + threadIdx.x; i < S.n; i += (int64_t)S.nblk * kKB) {
+        const double di = S.dinv[i];
+        const double phi = S.ph[i];
+        S.x[i] += k0.alpha * phi + omega * S.sh[i];
+        const double ri = S.s[i] - omega * S.t[i];
+        S.r[i] = ri;
+        if (restart) S.rh[i] = ri;
+        S.ph[i] = (beta == 0.0) ? di * ri : di * ri + beta * (phi - omega * (di * S.v[i]));
+        srr += ri * ri;
+    }
+    double *ps[1] = {part + (int64_t)P_RR * pstride};
+    write_partials<1>(&srr, ps);
+}
+
+// true residual ||b - A x|| / ||b|| per system (||b - A x|| when b = 0)
+__global__ __launch_bounds__(kKB) void kb_resid(const BSys *__restrict__ sys, const int *__restrict__ bmap,
+                                                double *__restrict__ part, int pstride)
+{
+    const int j = bmap[blockIdx.x];
+    const BSys S = sys[j];
+    const int lb = blockIdx.x - S.boff;
+    double acc[2] = {0.0, 0.0};
+    const bool act[1] = {true};
+    for (int64_t i = (int64_t)lb * kKB + threadIdx.x; i < S.n; i += (int64_t)S.nblk * kKB) {
+        double ax[1];
+        row_dot<double, double, 1>(i, S.q, S.col, S.val, S.x, 0, act, ax);
+        const double ri = S.b[i] - ax[0];
+        acc[0] += ri * ri;
+        acc[1] += S.b[i] * S.b[i];
+    }
+    double *ps[2] = {part + (int64_t)P_TS * pstride, part + (int64_t)P_TT * pstride};
+    write_partials<2>(acc, ps);
+}
+
+__global__ __launch_bounds__(kKB) void kb_resid_final(const BSys *__restrict__ sys, const double *__restrict__ part,
+                                                      int pstride, double *__restrict__ out)
+{
+    const BSys S = sys[blockIdx.x];
+    double sums[2];
+    const double *ps[2] = {bpart(part, P_TS, pstride, S.boff), bpart(part, P_TT, pstride, S.boff)};
+    sum_partials_n<2>(ps, S.nblk, sums);
+    if (threadIdx.x == 0) out[blockIdx.x] = (sums[1] > 0.0) ? sqrt(sums[0] / sums[1]) : sqrt(sums[0]);
+}
+
 }  // namespace
 
 int spmv(int64_t n, int q, ColIdx col, const double *val, const double *x, double *y, hipStream_t s)
@@ -1006,14 +1244,149 @@ int residual_norms(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *v
 {
     const int nblk = grid_blocks(n);
     double *dev = nullptr;
-    RB_CHECK(dev_alloc(ctx, (void **)&dev, sizeof(double) * (2 * kMaxRhs * kMaxBlocks + kMaxRhs)));
+    RB_CHECK(workspace(ctx, WS_RESID, sizeof(double) * (2 * kMaxRhs * kMaxBlocks + kMaxRhs), (void **)&dev));
     double *out = dev + 2 * kMaxRhs * kMaxBlocks;
+    double *hout = nullptr;
+    RB_CHECK(host_scratch(ctx, kHostMisc, sizeof(double) * kMaxRhs, (void **)&hout));
     hipLaunchKernelGGL(k_resid, dim3(nblk), dim3(kBlock), 0, s, n, q, nrhs, col, val, b, n, x, n, dev);
     hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(kBlock), 0, s, dev, nblk, nrhs, out);
-    hipError_t e = hipMemcpyAsync(relres_out, out, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    dev_free(ctx, dev, sizeof(double) * (2 * kMaxRhs * kMaxBlocks + kMaxRhs));
-    if (e != hipSuccess) return hip_fail(e, "residual norm");
+    RB_HIP(hipGetLastError());
+    RB_HIP(hipMemcpyAsync(hout, out, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+    RB_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < nrhs; ++k) relres_out[k] = hout[k];
+    return RBFFD_OK;
+}
+
+
+int bicgstab_batched(rbffd_ctx *ctx, int count, const BatchSystem *sys, double tol, int max_iter, int *iters,
+                     int *status, double *relres, hipStream_t s)
+{
+    if (count < 1) return fail(RBFFD_E_ARG, "batch is empty");
+    // block ranges: the same for a system alone or in any batch
+    std::vector<int> boff(count), nblk(count);
+    int64_t total = 0, vec = 0;
+    for (int j = 0; j < count; ++j) {
+        int64_t b = (sys[j].n + kKB - 1) / kKB;
+        if (b > kKMaxBlocks) b = kKMaxBlocks;
+        nblk[j] = (int)std::max<int64_t>(1, b);
+        boff[j] = (int)total;
+        total += nblk[j];
+        vec += pad64(sys[j].n);
+    }
+    if (total > (int64_t)INT32_MAX / P_COUNT) return fail(RBFFD_E_ARG, "batch too large");
+    const int pstride = (int)total;
+    // device: descriptors | block map | states | partials | 7 vectors per system
+    const size_t dsz = sizeof(BSys) * count, msz = sizeof(int) * total, ssz = sizeof(KState) * count;
+    const size_t psz = sizeof(double) * P_COUNT * total, vsz = sizeof(double) * 7 * vec;
+    const size_t o1 = (dsz + 255) / 256 * 256, o2 = o1 + (msz + 255) / 256 * 256, o3 = o2 + (ssz + 255) / 256 * 256,
+                 o4 = o3 + (psz + 255) / 256 * 256, dtot = o4 + vsz + (size_t)count * sizeof(double) + 256;
+    char *dev = nullptr;
+    RB_CHECK(workspace(ctx, WS_BATCH, dtot, (void **)&dev));
+    BSys *dsys = (BSys *)dev;
+    int *dmap = (int *)(dev + o1);
+    KState *dst = (KState *)(dev + o2);
+    double *part = (double *)(dev + o3);
+    double *vecs = (double *)(dev + o4);
+    double *dout = vecs + 7 * vec;
+    // pinned host staging: descriptors | block map | states | residuals
+    const size_t htot = o3 + (size_t)count * sizeof(double) + 256;
+    char *host = nullptr;
+    RB_CHECK(workspace(ctx, WS_BATCH_HOST, htot, (void **)&host));
+    BSys *hsys = (BSys *)host;
+    int *hmap = (int *)(host + o1);
+    KState *hst = (KState *)(host + o2);
+    double *hout = (double *)(host + o3);
+    int64_t voff = 0;
+    for (int j = 0; j < count; ++j) {
+        BSys &B = hsys[j];
+        B.n = sys[j].n;
+        B.np = pad64(sys[j].n);
+        B.q = sys[j].q;
+        B.boff = boff[j];
+        B.nblk = nblk[j];
+        B.pad = 0;
+        B.col = sys[j].col;
+        B.val = sys[j].val;
+        B.dinv = sys[j].dinv;
+        B.b = sys[j].b;
+        B.x = sys[j].x;
+        double *base = vecs + 7 * voff;
+        B.r = base;
+        B.rh = base + B.np;
+        B.ph = base + 2 * B.np;
+        B.v = base + 3 * B.np;
+        B.s = base + 4 * B.np;
+        B.sh = base + 5 * B.np;
+        B.t = base + 6 * B.np;
+        voff += B.np;
+        for (int b = 0; b < nblk[j]; ++b) hmap[boff[j] + b] = j;
+    }
+    RB_HIP(hipMemcpyAsync(dsys, hsys, dsz, hipMemcpyHostToDevice, s));
+    RB_HIP(hipMemcpyAsync(dmap, hmap, msz, hipMemcpyHostToDevice, s));
+    const dim3 g((unsigned)total), bl(kKB);
+    const double tol2 = tol * tol;
+    std::vector<int> it_total(count, 0), good(count, 0);
+    for (int j = 0; j < count; ++j) status[j] = RBFFD_E_NOCONV;
+    int phase = 0;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        // systems already within 10 tol of their true residual stay finished
+        for (int j = 0; j < count; ++j) {
+            KState z{};
+            z.done_at = good[j] ? 1 : 0;
+            z.status = RBFFD_OK;
+            hst[j] = z;
+        }
+        RB_HIP(hipMemcpyAsync(dst, hst, ssz, hipMemcpyHostToDevice, s));
+        ++phase;   // 1: the "finished" stamp above precedes every later launch
+        hipLaunchKernelGGL(kb_init, g, bl, 0, s, dsys, dmap, part, pstride, dst);
+        int it = 0, chunk = 4;
+        int left = max_iter;
+        for (int j = 0; j < count; ++j)
+            if (!good[j]) left = std::min(left, max_iter - it_total[j]);
+        bool finished = left <= 0;
+        while (!finished) {
+            const int todo = std::min(chunk, left - it);
+            for (int c = 0; c < todo; ++c) {
+                hipLaunchKernelGGL(kb_v, g, bl, 0, s, dsys, dmap, part, pstride, dst, tol2, 0, ++phase);
+                hipLaunchKernelGGL(kb_s, g, bl, 0, s, dsys, dmap, part, pstride, dst, ++phase);
+                hipLaunchKernelGGL(kb_t, g, bl, 0, s, dsys, dmap, part, pstride, dst, tol2, ++phase);
+                hipLaunchKernelGGL(kb_x, g, bl, 0, s, dsys, dmap, part, pstride, dst, ++phase);
+            }
+            it += todo;
+            hipLaunchKernelGGL(kb_v, g, bl, 0, s, dsys, dmap, part, pstride, dst, tol2, 1, ++phase);
+            RB_HIP(hipGetLastError());
+            RB_HIP(hipMemcpyAsync(hst, dst, ssz, hipMemcpyDeviceToHost, s));
+            RB_HIP(hipStreamSynchronize(s));
+            bool done = true;
+            for (int j = 0; j < count; ++j) done = done && hst[j].done_at != 0;
+            finished = done || it >= left;
+            chunk = std::min(chunk * 2, 32);
+        }
+        hipLaunchKernelGGL(kb_resid, g, bl, 0, s, dsys, dmap, part, pstride);
+        hipLaunchKernelGGL(kb_resid_final, dim3((unsigned)count), bl, 0, s, dsys, part, pstride, dout);
+        RB_HIP(hipGetLastError());
+        RB_HIP(hipMemcpyAsync(hout, dout, sizeof(double) * count, hipMemcpyDeviceToHost, s));
+        RB_HIP(hipStreamSynchronize(s));
+        bool retry = false;
+        for (int j = 0; j < count; ++j) {
+            if (good[j]) continue;
+            it_total[j] += hst[j].iters;
+            relres[j] = hout[j];
+            const bool stopped = hst[j].done_at != 0;
+            status[j] = stopped ? hst[j].status : RBFFD_E_NOCONV;
+            if (stopped && status[j] == RBFFD_OK) {
+                if (hout[j] <= 10.0 * tol)
+                    good[j] = 1;
+                else
+                    retry = true;   // recursive residual drifted: iterate again from x
+            }
+        }
+        if (!retry) break;
+    }
+    for (int j = 0; j < count; ++j) {
+        iters[j] = it_total[j];
+        if (!good[j] && status[j] == RBFFD_OK) status[j] = RBFFD_E_NOCONV;
+    }
     return RBFFD_OK;
 }
 

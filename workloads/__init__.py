@@ -172,7 +172,9 @@ def morton_order(xyz: np.ndarray) -> np.ndarray:
 
 
 def _finish(dim, xyz, kind, normal, name, h, meta, centre, boundary_kind=DIRICHLET):
-    kind = np.where(kind != INTERIOR, boundary_kind, INTERIOR).astype(np.uint8)
+    if boundary_kind is not None:   # None: keep the kinds given per point
+        kind = np.where(kind != INTERIOR, boundary_kind, INTERIOR)
+    kind = kind.astype(np.uint8)
     order = morton_order(xyz)
     xyz = np.ascontiguousarray(xyz[order], dtype=np.float64)
     kind = np.ascontiguousarray(kind[order], dtype=np.uint8)
@@ -331,7 +333,7 @@ def beltrami_cube(n: int = 100, seed: int = 4, jitter: float = 0.2, nu: float = 
 
 
 def holed_square(n_target: int, seed: int, n_holes: int | None = None, Re: float = 40.0,
-                 jitter: float = 0.2) -> Cloud:
+                 jitter: float = 0.2, edge_kind: int = DIRICHLET) -> Cloud:
     """Unit square minus 0-4 circular holes (radius U(0.05, 0.15), centre in
     [r+0.05, 1-r-0.05]^2, kept 0.05 apart). Jittered lattice interior with spacing h
     chosen to approach n_target points; points inside a hole or within h/2 of it are
@@ -369,14 +371,15 @@ def holed_square(n_target: int, seed: int, n_holes: int | None = None, Re: float
     parts = [inter, bpts] + hp
     xyz = np.concatenate(parts)
     n_hole_pts = sum(len(p) for p in hp)
-    kind = np.concatenate([np.zeros(len(inter), np.uint8), np.ones(len(bpts) + n_hole_pts, np.uint8)])
+    kind = np.concatenate([np.zeros(len(inter), np.uint8), np.full(len(bpts), edge_kind, np.uint8),
+                           np.full(n_hole_pts, DIRICHLET, np.uint8)])
     normal = np.concatenate([np.zeros_like(inter), bnrm] + hn)
     on_hole = np.concatenate([np.zeros(len(inter) + len(bpts), bool), np.ones(n_hole_pts, bool)])
     return _finish(2, xyz, kind, normal, f"holed_{len(xyz)}_{seed}", h,
                    {"flow": "kovasznay_holes", "Re": Re, "nu": 1.0 / Re, "seed": seed,
                     "holes": [(float(c[0]), float(c[1]), float(r)) for c, r in holes],
                     "on_hole": on_hole},
-                   centre=(0.5, 0.5))
+                   centre=(0.5, 0.5), boundary_kind=None)
 
 
 def scattered_square(nx: int, seed: int = 7, jitter: float = 0.2, lo: float = 0.0,
