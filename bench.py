@@ -146,6 +146,102 @@ def cpu_baseline(args):
                       f"iterations, {pi} point-iters in {t:.2f} s"}
 
 
+def batch_bench(args):
+    """The batched configuration: independent holed-square clouds (0-4 holes,
+    prescribed pressure on the outer edges and the holes) with sizes
+    log-uniform over 500-50k points and degrees 2-5 (q = 2m), one converged
+    pressure-correction solve each at 1e-6 relative residual: one batched launch
+    sequence against the same solves one at a time (plain FP64 path)."""
+    import torch
+
+    import paper_2106_07616_amd as R
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    R.lib()
+    cfg = W.config_c3_sizes(args.batch_count)
+    t0 = time.perf_counter()
+    # p' = 0 on every boundary point (prescribed pressure): the homogeneous
+    # Neumann closure on the holes leaves many of these systems beyond plain
+    # Jacobi-BiCGSTAB
+    clouds = [(W.holed_square(nt, seed=sd, edge_kind=W.PRESCRIBED_PRESSURE, hole_kind=W.PRESCRIBED_PRESSURE), k)
+              for nt, sd, k in cfg]
+    log(f"[batch] {len(clouds)} clouds, {sum(c.n for c, _ in clouds)} points, generated in {time.perf_counter() - t0:.1f}s")
+    ctx = R.Context(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solvers = [R.Solver(ctx, c, k) for c, k in clouds]
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    npts = sum(c.n for c, _ in clouds)
+    rhs = [torch.tensor(np.random.default_rng(5000 + j).standard_normal(c.n), device="cuda")
+           for j, (c, _) in enumerate(clouds)]
+    tol = 1e-6
+
+    seq_status = []
+
+    def sequential():
+        lat, its = [], []
+        xs = []
+        seq_status.clear()
+        for sv, b in zip(solvers, rhs):
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            st = R.poisson_solve(ctx, sv.ops, b, x, tol=tol, max_iter=20000, allow_noconv=True)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - ta)
+            its.append(st["iters"])
+            seq_status.append(st["status"])
+            xs.append(x)
+        return lat, its, xs
+
+    def batched():
+        xs = [torch.zeros_like(b) for b in rhs]
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        st = R.poisson_solve_batched(ctx, [sv.ops for sv in solvers], rhs, xs, tol=tol, max_iter=20000,
+                                     allow_noconv=True)
+        torch.cuda.synchronize()
+        return time.perf_counter() - ta, st, xs
+
+    sequential()
+    lat, its, xseq = sequential()
+    batched()
+    t_batch, stb, xb = batched()
+    t_seq = sum(lat)
+    ok = [j for j, s_ in enumerate(stb) if s_["status"] == 0 and seq_status[j] == 0]
+    diff = max((float((xb[j] - xseq[j]).abs().max() / xseq[j].abs().max()) for j in ok), default=None)
+    bad = [(clouds[j][0].name, clouds[j][1], stb[j]["status"], stb[j]["relres"]) for j in range(len(stb))
+           if stb[j]["status"] != 0]
+    if bad:
+        log(f"[batch] systems that did not converge: {bad[:10]}")
+    point_iters = sum(c.n * s_["iters"] for (c, _), s_ in zip(clouds, stb))
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "metric": METRIC, "value": round(len(solvers) / t_batch, 3), "unit": "converged solves/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(t_batch * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{len(solvers)} holed-square clouds (seeds 1000+i), {npts} points in total, "
+                               f"500-50k points each, k=2..5, q=2m; one pressure-correction solve each at "
+                               f"relative residual {tol:g}, batched", "instances": len(solvers), "points": npts},
+        "batched": {"solves_per_s": round(len(solvers) / t_batch, 3), "wall_ms": round(t_batch * 1e3, 3),
+                    "M_point_iters_per_s": round(point_iters / t_batch / 1e6, 1),
+                    "converged": int(sum(s_["status"] == 0 for s_ in stb)),
+                    "max_true_relres": float(max(s_["relres"] for s_ in stb))},
+        "sequential_fp64": {"solves_per_s": round(len(solvers) / t_seq, 3), "wall_ms": round(t_seq * 1e3, 3),
+                            "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                            "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+                            "iters_median": int(np.median(its)),
+                            "converged": int(sum(st_ == 0 for st_ in seq_status))},
+        "speedup_batched_vs_sequential": round(t_seq / t_batch, 3),
+        "max_rel_diff_batched_vs_sequential": diff,
+        "stencils_and_assembly_ms": round(t_build * 1e3, 1),
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,7 +252,8 @@ def main():
     ap.add_argument("--spmv-reps", type=int, default=200)
     ap.add_argument("--solve-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="taylor_green")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch"], default="taylor_green")
+    ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--cpu-sample-r", type=float, default=0.02)
     ap.add_argument("--cpu-sample-cube", type=int, default=30)
     ap.add_argument("--spmv-only", action="store_true", help="run only the SpMV timing (for counter runs)")
@@ -164,6 +261,9 @@ def main():
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (pass --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        batch_bench(args)
+        return
 
     import torch
 

@@ -239,7 +239,7 @@ def poisson_solve(ctx: Context, ops: Operators, rhs: torch.Tensor, x: torch.Tens
     o = KrylovOptsT(tol, max_iter, precision)
     s = KrylovStatsT()
     st = lib().poisson_solve(ctx.handle, ops.handle, _ptr(rhs), _ptr(x), C.byref(o), C.byref(s), _stream())
-    _check(st, allow=(RBFFD_E_NOCONV,) if allow_noconv else ())
+    _check(st, allow=(RBFFD_E_NOCONV, RBFFD_E_BREAKDOWN) if allow_noconv else ())
     return dict(iters=s.iters, status=s.status, refinements=s.refinements, fp64_fallback=s.fp64_fallback,
                 relres=s.relres)
 

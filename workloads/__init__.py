@@ -333,7 +333,7 @@ def beltrami_cube(n: int = 100, seed: int = 4, jitter: float = 0.2, nu: float = 
 
 
 def holed_square(n_target: int, seed: int, n_holes: int | None = None, Re: float = 40.0,
-                 jitter: float = 0.2, edge_kind: int = DIRICHLET) -> Cloud:
+                 jitter: float = 0.2, edge_kind: int = DIRICHLET, hole_kind: int = DIRICHLET) -> Cloud:
     """Unit square minus 0-4 circular holes (radius U(0.05, 0.15), centre in
     [r+0.05, 1-r-0.05]^2, kept 0.05 apart). Jittered lattice interior with spacing h
     chosen to approach n_target points; points inside a hole or within h/2 of it are
@@ -372,7 +372,7 @@ def holed_square(n_target: int, seed: int, n_holes: int | None = None, Re: float
     xyz = np.concatenate(parts)
     n_hole_pts = sum(len(p) for p in hp)
     kind = np.concatenate([np.zeros(len(inter), np.uint8), np.full(len(bpts), edge_kind, np.uint8),
-                           np.full(n_hole_pts, DIRICHLET, np.uint8)])
+                           np.full(n_hole_pts, hole_kind, np.uint8)])
     normal = np.concatenate([np.zeros_like(inter), bnrm] + hn)
     on_hole = np.concatenate([np.zeros(len(inter) + len(bpts), bool), np.ones(n_hole_pts, bool)])
     return _finish(2, xyz, kind, normal, f"holed_{len(xyz)}_{seed}", h,
