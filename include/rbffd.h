@@ -192,6 +192,29 @@ int poisson_solve_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops
                           double *const *x, const rbffd_krylov_opts *opts, rbffd_krylov_stats *stats,
                           void *hip_stream);
 
+/* ---- continuous batching ------------------------------------------------ */
+/* (Sec. 3, applied to a stream of independent requests) A server keeps a
+ * running batch of FP64 pressure-correction solves. Solves submitted while
+ * others run join the batch at the next rbffd_server_run; finished ones leave
+ * it and are collected with rbffd_server_poll. Each solve behaves as
+ * poisson_solve (right-Jacobi BiCGSTAB, restarts from the true residual) and
+ * its result does not depend on which other solves share the batch.
+ * Work vectors (7 n doubles per solve) are charged to the context's HBM
+ * budget at submission: RBFFD_E_OOM means "retry after some solves finish".
+ * One server per context; calls on it must not overlap. */
+typedef struct rbffd_server rbffd_server;
+int rbffd_server_create(rbffd_ctx *ctx, rbffd_server **out);
+int rbffd_server_destroy(rbffd_server *sv);
+/* Queue a solve of P x = rhs (ops, rhs and x stay owned by the caller and must
+ * outlive the solve; x holds the initial guess). *ticket identifies it. */
+int rbffd_server_submit(rbffd_server *sv, const rbffd_ops *ops, const double *rhs, double *x, double tol,
+                        int max_iter, int64_t *ticket);
+/* Run up to `iterations` BiCGSTAB iterations on every queued or running solve
+ * (synchronous on the stream); *active receives the number still running. */
+int rbffd_server_run(rbffd_server *sv, int iterations, int *active, void *hip_stream);
+/* Collect up to `max` finished solves: tickets[] and stats[] (host arrays). */
+int rbffd_server_poll(rbffd_server *sv, int max, int64_t *tickets, rbffd_krylov_stats *stats, int *count);
+
 /* ---- time step ---------------------------------------------------------- */
 typedef struct {
     double rho, mu;         /* density and dynamic viscosity                         */

@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_OOM", -3: "E_SINGULAR", -4: "E_NOCO
 EXPORTED = ["rbffd_last_error", "rbffd_ctx_create", "rbffd_ctx_destroy", "rbffd_ctx_bytes_in_use",
             "rbffd_stencil_sizes", "rbffd_build_stencils", "rbffd_assemble", "rbffd_ops_free",
             "rbffd_ops_info", "rbffd_ops_export_csr", "rbffd_apply", "poisson_solve", "poisson_solve_batched",
-            "simple_step", "rbffd_convdiff_lambda"]
+            "rbffd_server_create", "rbffd_server_destroy", "rbffd_server_submit", "rbffd_server_run",
+            "rbffd_server_poll", "simple_step", "rbffd_convdiff_lambda"]
 
 
 class RbffdError(RuntimeError):
@@ -84,6 +85,11 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.poisson_solve.argtypes = [P, P, P, P, C.POINTER(KrylovOptsT), C.POINTER(KrylovStatsT), P]
     L.poisson_solve_batched.argtypes = [P, I, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(KrylovOptsT),
                                         C.POINTER(KrylovStatsT), P]
+    L.rbffd_server_create.argtypes = [P, C.POINTER(P)]
+    L.rbffd_server_destroy.argtypes = [P]
+    L.rbffd_server_submit.argtypes = [P, P, P, P, D, I, C.POINTER(I64)]
+    L.rbffd_server_run.argtypes = [P, I, C.POINTER(I), P]
+    L.rbffd_server_poll.argtypes = [P, I, C.POINTER(I64), C.POINTER(KrylovStatsT), C.POINTER(I)]
     L.simple_step.argtypes = [P, P, P, P, P, P, P, C.POINTER(StepOptsT), C.POINTER(StepStatsT), P]
     L.rbffd_convdiff_lambda.argtypes = [P, P, P, D, D, I, C.POINTER(D), P]
     return L
@@ -258,6 +264,45 @@ def poisson_solve_batched(ctx: Context, ops: list, rhs: list, x: list, tol: floa
                                      arr(*[_ptr(t) for t in x]), C.byref(o), stats, _stream())
     _check(st, allow=(RBFFD_E_NOCONV, RBFFD_E_BREAKDOWN) if allow_noconv else ())
     return [dict(iters=s_.iters, status=s_.status, relres=s_.relres) for s_ in stats]
+
+
+class Server:
+    """Continuous batching of FP64 pressure-correction solves (rbffd_server_*)."""
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        h = C.c_void_p()
+        _check(lib().rbffd_server_create(ctx.handle, C.byref(h)))
+        self.handle = h
+        self._keep = {}   # ticket -> tensors that must outlive the solve
+
+    def submit(self, ops: Operators, rhs: torch.Tensor, x: torch.Tensor, tol: float = 1e-6,
+               max_iter: int = 20000) -> int:
+        t = C.c_int64()
+        _check(lib().rbffd_server_submit(self.handle, ops.handle, _ptr(rhs), _ptr(x), tol, max_iter, C.byref(t)))
+        self._keep[t.value] = (ops, rhs, x)
+        return t.value
+
+    def run(self, iterations: int = 32) -> int:
+        a = C.c_int()
+        _check(lib().rbffd_server_run(self.handle, iterations, C.byref(a), _stream()))
+        return a.value
+
+    def poll(self, max_items: int = 1024):
+        tickets = (C.c_int64 * max_items)()
+        stats = (KrylovStatsT * max_items)()
+        cnt = C.c_int()
+        _check(lib().rbffd_server_poll(self.handle, max_items, tickets, stats, C.byref(cnt)))
+        out = []
+        for i in range(cnt.value):
+            self._keep.pop(tickets[i], None)
+            out.append((tickets[i], dict(iters=stats[i].iters, status=stats[i].status, relres=stats[i].relres)))
+        return out
+
+    def close(self):
+        if self.handle:
+            lib().rbffd_server_destroy(self.handle)
+            self.handle = None
 
 
 BDF2 = (1.5, -2.0, 0.5)

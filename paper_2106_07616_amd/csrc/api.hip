@@ -335,6 +335,62 @@ int poisson_solve_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops
     return RBFFD_OK;
 }
 
+struct rbffd_server {
+    rbffd_ctx *ctx;
+    rbffd::Server *impl;
+};
+
+int rbffd_server_create(rbffd_ctx *ctx, rbffd_server **out)
+{
+    if (!ctx || !out) return fail(RBFFD_E_ARG, "NULL argument");
+    rbffd::Server *impl = nullptr;
+    RB_CHECK(server_create(ctx, &impl));
+    *out = new rbffd_server{ctx, impl};
+    return RBFFD_OK;
+}
+
+int rbffd_server_destroy(rbffd_server *sv)
+{
+    if (!sv) return RBFFD_OK;
+    (void)hipSetDevice(sv->ctx->device);
+    server_destroy(sv->impl);
+    delete sv;
+    return RBFFD_OK;
+}
+
+int rbffd_server_submit(rbffd_server *sv, const rbffd_ops *ops, const double *rhs, double *x, double tol,
+                        int max_iter, int64_t *ticket)
+{
+    if (!sv || !ops || !rhs || !x || !ticket) return fail(RBFFD_E_ARG, "NULL argument");
+    if (!(tol >= 0.0) || max_iter < 1) return fail(RBFFD_E_ARG, "bad Krylov options");
+    RB_HIP(hipSetDevice(sv->ctx->device));
+    const BatchSystem sys{ops->n, ops->q, cols_of(ops), ops->pval, ops->pdinv, rhs, x};
+    return server_submit(sv->impl, sys, tol, max_iter, ticket);
+}
+
+int rbffd_server_run(rbffd_server *sv, int iterations, int *active, void *hip_stream)
+{
+    if (!sv || !active || iterations < 1) return fail(RBFFD_E_ARG, "bad argument");
+    RB_HIP(hipSetDevice(sv->ctx->device));
+    return server_run(sv->impl, iterations, active, (hipStream_t)hip_stream);
+}
+
+int rbffd_server_poll(rbffd_server *sv, int max, int64_t *tickets, rbffd_krylov_stats *stats, int *count)
+{
+    if (!sv || !tickets || !stats || !count || max < 0) return fail(RBFFD_E_ARG, "bad argument");
+    std::vector<int> iters((size_t)std::max(max, 1)), status((size_t)std::max(max, 1));
+    std::vector<double> relres((size_t)std::max(max, 1));
+    RB_CHECK(server_poll(sv->impl, max, tickets, iters.data(), status.data(), relres.data(), count));
+    for (int i = 0; i < *count; ++i) {
+        stats[i].iters = iters[i];
+        stats[i].status = status[i];
+        stats[i].refinements = 0;
+        stats[i].fp64_fallback = 0;
+        stats[i].relres = relres[i];
+    }
+    return RBFFD_OK;
+}
+
 int simple_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, double *p,
                 const double *u_bc, const double *p_bc, const rbffd_step_opts *opts,
                 rbffd_step_stats *stats, void *hip_stream)

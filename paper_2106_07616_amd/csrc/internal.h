@@ -243,6 +243,14 @@ struct BatchSystem {
 // reductions, so its result does not depend on the other systems in the batch.
 int bicgstab_batched(rbffd_ctx *ctx, int count, const BatchSystem *sys, double tol, int max_iter, int *iters,
                      int *status, double *relres, hipStream_t s);
+// Continuous batching of FP64 pressure-correction solves: systems join and
+// leave a running batch between chunks of iterations.
+struct Server;
+int server_create(rbffd_ctx *ctx, Server **out);
+void server_destroy(Server *sv);
+int server_submit(Server *sv, const BatchSystem &sys, double tol, int max_iter, int64_t *ticket);
+int server_run(Server *sv, int iterations, int *n_active, hipStream_t s);
+int server_poll(Server *sv, int max, int64_t *tickets, int *iters, int *status, double *relres, int *count);
 int spmv(int64_t n, int q, ColIdx col, const double *val, const double *x, double *y,
          hipStream_t s);
 int residual_norms(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val,

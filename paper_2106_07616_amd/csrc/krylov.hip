@@ -44,7 +44,8 @@ struct KState {
     int status;       // RBFFD_OK / RBFFD_E_BREAKDOWN
     int restart;      // r-hat was reset to r: rho = r.r at the next KV
     int refresh;      // r was replaced by a true residual: rho = r-hat.r at the next KV
-    int pad;
+    int fresh;        // batched systems: to be initialised by the next KB_INIT
+    int moved;        // batched systems: block range changed, ||r||^2 is in rr
 };
 
 // BiCGSTAB kernels run 512-thread blocks on at most 1024 blocks, so that a
@@ -762,6 +763,7 @@ int bicgstab_t(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const T *val, const
 struct BSys {
     int64_t n, np;
     int q, boff, nblk, pad;
+    double tol2;
     ColIdx col;
     const double *val, *dinv, *b;
     double *x;
@@ -778,7 +780,7 @@ __global__ __launch_bounds__(kKB) void kb_init(const BSys *__restrict__ sys, con
 {
     const int j = bmap[blockIdx.x];
     const BSys S = sys[j];
-    if (st[j].done_at != 0) return;
+    if (!st[j].fresh) return;
     const int lb = blockIdx.x - S.boff;
     double rr = 0.0, bb = 0.0;
     const bool act[1] = {true};
@@ -800,7 +802,7 @@ __global__ __launch_bounds__(kKB) void kb_init(const BSys *__restrict__ sys, con
 
 __global__ __launch_bounds__(kKB) void kb_v(const BSys *__restrict__ sys, const int *__restrict__ bmap,
                                             double *__restrict__ part, int pstride, KState *__restrict__ st,
-                                            double tol2, int check_only, int phase)
+                                            int check_only, int phase)
 {
     const int j = bmap[blockIdx.x];
     const BSys S = sys[j];
@@ -811,9 +813,12 @@ __global__ __launch_bounds__(kKB) void kb_v(const BSys *__restrict__ sys, const 
     }
     const KState k0 = st[j];
     if (finished_before(k0, phase)) return;
-    const double rr = sums[0], bb = sums[1];
+    // ||b||^2 is taken from the partials of KB_INIT once, then from the state;
+    // after a change of block ranges ||r||^2 also comes from the state
+    const double rr = k0.moved ? k0.rr : sums[0];
+    const double bb = (k0.iters == 0 && !k0.moved) ? sums[1] : k0.bb;
     const bool zero = bb == 0.0;
-    const bool conv = !zero && rr <= tol2 * bb;
+    const bool conv = !zero && rr <= S.tol2 * bb;
     const bool lead = blockIdx.x == S.boff && threadIdx.x == 0;
     if (lead) {
         st[j].rr = rr;
@@ -858,6 +863,8 @@ __global__ __launch_bounds__(kKB) void kb_s(const BSys *__restrict__ sys, const 
     if (blockIdx.x == S.boff && threadIdx.x == 0) {
         st[j].alpha = alpha;
         st[j].restart = 0;
+        st[j].fresh = 0;
+        st[j].moved = 0;
         if (rv == 0.0) {
             st[j].done_at = phase;
             st[j].status = RBFFD_E_BREAKDOWN;
@@ -878,8 +885,7 @@ __global__ __launch_bounds__(kKB) void kb_s(const BSys *__restrict__ sys, const 
 }
 
 __global__ __launch_bounds__(kKB) void kb_t(const BSys *__restrict__ sys, const int *__restrict__ bmap,
-                                            double *__restrict__ part, int pstride, KState *__restrict__ st,
-                                            double tol2, int phase)
+                                            double *__restrict__ part, int pstride, KState *__restrict__ st, int phase)
 {
     const int j = bmap[blockIdx.x];
     const BSys S = sys[j];
@@ -890,7 +896,7 @@ __global__ __launch_bounds__(kKB) void kb_t(const BSys *__restrict__ sys, const 
     }
     const KState k0 = st[j];
     if (finished_before(k0, phase)) return;
-    const bool half = ss <= tol2 * k0.bb;
+    const bool half = ss <= S.tol2 * k0.bb;
     if (half && blockIdx.x == S.boff && threadIdx.x == 0) {
         st[j].done_at = phase;
         st[j].status = RBFFD_OK;
@@ -1305,6 +1311,7 @@ int bicgstab_batched(rbffd_ctx *ctx, int count, const BatchSystem *sys, double t
         B.boff = boff[j];
         B.nblk = nblk[j];
         B.pad = 0;
+        B.tol2 = tol * tol;
         B.col = sys[j].col;
         B.val = sys[j].val;
         B.dinv = sys[j].dinv;
@@ -1324,7 +1331,6 @@ int bicgstab_batched(rbffd_ctx *ctx, int count, const BatchSystem *sys, double t
     RB_HIP(hipMemcpyAsync(dsys, hsys, dsz, hipMemcpyHostToDevice, s));
     RB_HIP(hipMemcpyAsync(dmap, hmap, msz, hipMemcpyHostToDevice, s));
     const dim3 g((unsigned)total), bl(kKB);
-    const double tol2 = tol * tol;
     std::vector<int> it_total(count, 0), good(count, 0);
     for (int j = 0; j < count; ++j) status[j] = RBFFD_E_NOCONV;
     int phase = 0;
@@ -1333,6 +1339,7 @@ int bicgstab_batched(rbffd_ctx *ctx, int count, const BatchSystem *sys, double t
         for (int j = 0; j < count; ++j) {
             KState z{};
             z.done_at = good[j] ? 1 : 0;
+            z.fresh = good[j] ? 0 : 1;
             z.status = RBFFD_OK;
             hst[j] = z;
         }
@@ -1347,13 +1354,13 @@ int bicgstab_batched(rbffd_ctx *ctx, int count, const BatchSystem *sys, double t
         while (!finished) {
             const int todo = std::min(chunk, left - it);
             for (int c = 0; c < todo; ++c) {
-                hipLaunchKernelGGL(kb_v, g, bl, 0, s, dsys, dmap, part, pstride, dst, tol2, 0, ++phase);
+                hipLaunchKernelGGL(kb_v, g, bl, 0, s, dsys, dmap, part, pstride, dst, 0, ++phase);
                 hipLaunchKernelGGL(kb_s, g, bl, 0, s, dsys, dmap, part, pstride, dst, ++phase);
-                hipLaunchKernelGGL(kb_t, g, bl, 0, s, dsys, dmap, part, pstride, dst, tol2, ++phase);
+                hipLaunchKernelGGL(kb_t, g, bl, 0, s, dsys, dmap, part, pstride, dst, ++phase);
                 hipLaunchKernelGGL(kb_x, g, bl, 0, s, dsys, dmap, part, pstride, dst, ++phase);
             }
             it += todo;
-            hipLaunchKernelGGL(kb_v, g, bl, 0, s, dsys, dmap, part, pstride, dst, tol2, 1, ++phase);
+            hipLaunchKernelGGL(kb_v, g, bl, 0, s, dsys, dmap, part, pstride, dst, 1, ++phase);
             RB_HIP(hipGetLastError());
             RB_HIP(hipMemcpyAsync(hst, dst, ssz, hipMemcpyDeviceToHost, s));
             RB_HIP(hipStreamSynchronize(s));
@@ -1387,6 +1394,264 @@ int bicgstab_batched(rbffd_ctx *ctx, int count, const BatchSystem *sys, double t
         iters[j] = it_total[j];
         if (!good[j] && status[j] == RBFFD_OK) status[j] = RBFFD_E_NOCONV;
     }
+    return RBFFD_OK;
+}
+
+
+// ---- continuous batching ------------------------------------------------------
+// Systems join and leave a running batch between chunks of iterations. Each
+// system keeps its own work vectors and state; when the set changes the block
+// ranges are rebuilt (a system's result does not depend on its range: its
+// reductions always run over its own blocks in order), states move with their
+// systems, and ||r||^2 of moved systems is taken from their state once.
+struct ServerSys {
+    int64_t ticket = 0;
+    BatchSystem sys{};
+    double tol = 0.0;
+    int max_iter = 0;
+    double *vec = nullptr;
+    size_t vbytes = 0;
+    KState st{};
+    int iters_done = 0;   // iterations of finished attempts
+    int attempts = 0;
+};
+
+struct Server {
+    rbffd_ctx *ctx = nullptr;
+    std::vector<ServerSys> active;
+    std::vector<ServerSys> finished;
+    std::vector<int> fin_status;
+    std::vector<double> fin_relres;
+    int64_t next_ticket = 1;
+    int phase = 0;
+    bool dirty = true;
+    // layout buffers
+    char *dev = nullptr;
+    size_t dev_bytes = 0;
+    char *host = nullptr;
+    size_t host_bytes = 0;
+    int total_blocks = 0;
+    BSys *dsys = nullptr;
+    int *dmap = nullptr;
+    KState *dst = nullptr;
+    double *part = nullptr, *dout = nullptr;
+    BSys *hsys = nullptr;
+    int *hmap = nullptr;
+    KState *hst = nullptr;
+    double *hout = nullptr;
+};
+
+int server_create(rbffd_ctx *ctx, Server **out)
+{
+    Server *sv = new Server();
+    sv->ctx = ctx;
+    *out = sv;
+    return RBFFD_OK;
+}
+
+void server_destroy(Server *sv)
+{
+    if (!sv) return;
+    (void)hipDeviceSynchronize();
+    for (auto &a : sv->active) dev_free(sv->ctx, a.vec, a.vbytes);
+    for (auto &a : sv->finished) dev_free(sv->ctx, a.vec, a.vbytes);
+    if (sv->dev) dev_free(sv->ctx, sv->dev, sv->dev_bytes);
+    if (sv->host) (void)hipHostFree(sv->host);
+    delete sv;
+}
+
+int server_submit(Server *sv, const BatchSystem &sys, double tol, int max_iter, int64_t *ticket)
+{
+    ServerSys a;
+    a.sys = sys;
+    a.tol = tol;
+    a.max_iter = max_iter;
+    a.vbytes = sizeof(double) * 7 * pad64(sys.n);
+    RB_CHECK(dev_alloc(sv->ctx, (void **)&a.vec, a.vbytes));
+    a.ticket = sv->next_ticket++;
+    a.st = KState{};
+    a.st.fresh = 1;
+    a.st.status = RBFFD_OK;
+    sv->active.push_back(a);
+    sv->dirty = true;
+    *ticket = a.ticket;
+    return RBFFD_OK;
+}
+
+static int server_layout(Server *sv, hipStream_t s)
+{
+    const int count = (int)sv->active.size();
+    int64_t total = 0;
+    std::vector<int> boff(count), nblk(count);
+    for (int j = 0; j < count; ++j) {
+        int64_t b = (sv->active[j].sys.n + kKB - 1) / kKB;
+        if (b > kKMaxBlocks) b = kKMaxBlocks;
+        nblk[j] = (int)std::max<int64_t>(1, b);
+        boff[j] = (int)total;
+        total += nblk[j];
+    }
+    if (total > (int64_t)INT32_MAX / P_COUNT) return fail(RBFFD_E_ARG, "batch too large");
+    const size_t dsz = sizeof(BSys) * count, msz = sizeof(int) * total, ssz = sizeof(KState) * count;
+    const size_t psz = sizeof(double) * P_COUNT * total;
+    const size_t o1 = (dsz + 255) / 256 * 256, o2 = o1 + (msz + 255) / 256 * 256, o3 = o2 + (ssz + 255) / 256 * 256,
+                 o4 = o3 + (psz + 255) / 256 * 256, dtot = o4 + sizeof(double) * count + 256;
+    if (sv->dev_bytes < dtot) {
+        RB_HIP(hipStreamSynchronize(s));
+        if (sv->dev) dev_free(sv->ctx, sv->dev, sv->dev_bytes);
+        sv->dev = nullptr;
+        sv->dev_bytes = 0;
+        RB_CHECK(dev_alloc(sv->ctx, (void **)&sv->dev, dtot + dtot / 4));
+        sv->dev_bytes = dtot + dtot / 4;
+    }
+    const size_t htot = o3 + sizeof(double) * count + 256;
+    if (sv->host_bytes < htot) {
+        RB_HIP(hipStreamSynchronize(s));
+        if (sv->host) (void)hipHostFree(sv->host);
+        sv->host = nullptr;
+        sv->host_bytes = 0;
+        RB_HIP(hipHostMalloc((void **)&sv->host, htot + htot / 4, hipHostMallocDefault));
+        sv->host_bytes = htot + htot / 4;
+    }
+    sv->dsys = (BSys *)sv->dev;
+    sv->dmap = (int *)(sv->dev + o1);
+    sv->dst = (KState *)(sv->dev + o2);
+    sv->part = (double *)(sv->dev + o3);
+    sv->dout = (double *)(sv->dev + o4);
+    sv->hsys = (BSys *)sv->host;
+    sv->hmap = (int *)(sv->host + o1);
+    sv->hst = (KState *)(sv->host + o2);
+    sv->hout = (double *)(sv->host + o3);
+    sv->total_blocks = (int)total;
+    for (int j = 0; j < count; ++j) {
+        ServerSys &a = sv->active[j];
+        BSys &B = sv->hsys[j];
+        B.n = a.sys.n;
+        B.np = pad64(a.sys.n);
+        B.q = a.sys.q;
+        B.boff = boff[j];
+        B.nblk = nblk[j];
+        B.pad = 0;
+        B.tol2 = a.tol * a.tol;
+        B.col = a.sys.col;
+        B.val = a.sys.val;
+        B.dinv = a.sys.dinv;
+        B.b = a.sys.b;
+        B.x = a.sys.x;
+        B.r = a.vec;
+        B.rh = a.vec + B.np;
+        B.ph = a.vec + 2 * B.np;
+        B.v = a.vec + 3 * B.np;
+        B.s = a.vec + 4 * B.np;
+        B.sh = a.vec + 5 * B.np;
+        B.t = a.vec + 6 * B.np;
+        for (int b = 0; b < nblk[j]; ++b) sv->hmap[boff[j] + b] = j;
+        KState k = a.st;
+        if (!k.fresh) k.moved = 1;
+        sv->hst[j] = k;
+    }
+    RB_HIP(hipMemcpyAsync(sv->dsys, sv->hsys, dsz, hipMemcpyHostToDevice, s));
+    RB_HIP(hipMemcpyAsync(sv->dmap, sv->hmap, msz, hipMemcpyHostToDevice, s));
+    RB_HIP(hipMemcpyAsync(sv->dst, sv->hst, ssz, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(kb_init, dim3((unsigned)total), dim3(kKB), 0, s, sv->dsys, sv->dmap, sv->part, (int)total,
+                       sv->dst);
+    RB_HIP(hipGetLastError());
+    sv->dirty = false;
+    return RBFFD_OK;
+}
+
+int server_run(Server *sv, int iterations, int *n_active, hipStream_t s)
+{
+    if (sv->active.empty()) {
+        *n_active = 0;
+        return RBFFD_OK;
+    }
+    if (sv->dirty) RB_CHECK(server_layout(sv, s));
+    const int count = (int)sv->active.size();
+    const int total = sv->total_blocks;
+    const dim3 g((unsigned)total), bl(kKB);
+    int budget = iterations;
+    for (auto &a : sv->active) budget = std::min(budget, a.max_iter - a.iters_done - a.st.iters);
+    budget = std::max(budget, 1);
+    int it = 0, chunk = 4;
+    bool all_done = false;
+    while (it < budget && !all_done) {
+        const int todo = std::min(chunk, budget - it);
+        for (int c = 0; c < todo; ++c) {
+            hipLaunchKernelGGL(kb_v, g, bl, 0, s, sv->dsys, sv->dmap, sv->part, total, sv->dst, 0, ++sv->phase);
+            hipLaunchKernelGGL(kb_s, g, bl, 0, s, sv->dsys, sv->dmap, sv->part, total, sv->dst, ++sv->phase);
+            hipLaunchKernelGGL(kb_t, g, bl, 0, s, sv->dsys, sv->dmap, sv->part, total, sv->dst, ++sv->phase);
+            hipLaunchKernelGGL(kb_x, g, bl, 0, s, sv->dsys, sv->dmap, sv->part, total, sv->dst, ++sv->phase);
+        }
+        it += todo;
+        hipLaunchKernelGGL(kb_v, g, bl, 0, s, sv->dsys, sv->dmap, sv->part, total, sv->dst, 1, ++sv->phase);
+        RB_HIP(hipGetLastError());
+        RB_HIP(hipMemcpyAsync(sv->hst, sv->dst, sizeof(KState) * count, hipMemcpyDeviceToHost, s));
+        RB_HIP(hipStreamSynchronize(s));
+        all_done = true;
+        for (int j = 0; j < count; ++j) all_done = all_done && sv->hst[j].done_at != 0;
+        chunk = std::min(chunk * 2, 32);
+    }
+    for (int j = 0; j < count; ++j) sv->active[j].st = sv->hst[j];
+    // systems that stopped or used their iterations: true residual
+    bool any = false;
+    for (auto &a : sv->active)
+        any = any || a.st.done_at != 0 || a.iters_done + a.st.iters >= a.max_iter;
+    if (any) {
+        hipLaunchKernelGGL(kb_resid, g, bl, 0, s, sv->dsys, sv->dmap, sv->part, total);
+        hipLaunchKernelGGL(kb_resid_final, dim3((unsigned)count), bl, 0, s, sv->dsys, sv->part, total, sv->dout);
+        RB_HIP(hipGetLastError());
+        RB_HIP(hipMemcpyAsync(sv->hout, sv->dout, sizeof(double) * count, hipMemcpyDeviceToHost, s));
+        RB_HIP(hipStreamSynchronize(s));
+        std::vector<ServerSys> keep;
+        for (int j = 0; j < count; ++j) {
+            ServerSys &a = sv->active[j];
+            const bool stopped = a.st.done_at != 0;
+            const bool out_of_iters = a.iters_done + a.st.iters >= a.max_iter;
+            if (!stopped && !out_of_iters) {
+                keep.push_back(a);
+                continue;
+            }
+            const double rel = sv->hout[j];
+            int status = stopped ? a.st.status : RBFFD_E_NOCONV;
+            if (stopped && status == RBFFD_OK && rel > 10.0 * a.tol && a.attempts < 2 && !out_of_iters) {
+                // the recursive residual drifted: iterate again from x
+                a.iters_done += a.st.iters;
+                a.attempts += 1;
+                a.st = KState{};
+                a.st.fresh = 1;
+                a.st.status = RBFFD_OK;
+                keep.push_back(a);
+                sv->dirty = true;
+                continue;
+            }
+            if (status == RBFFD_OK && rel > 10.0 * a.tol) status = RBFFD_E_NOCONV;
+            a.iters_done += a.st.iters;
+            dev_free(sv->ctx, a.vec, a.vbytes);
+            a.vec = nullptr;
+            sv->finished.push_back(a);
+            sv->fin_status.push_back(status);
+            sv->fin_relres.push_back(rel);
+            sv->dirty = true;
+        }
+        sv->active.swap(keep);
+    }
+    *n_active = (int)sv->active.size();
+    return RBFFD_OK;
+}
+
+int server_poll(Server *sv, int max, int64_t *tickets, int *iters, int *status, double *relres, int *count)
+{
+    const int m = std::min<int>(max, (int)sv->finished.size());
+    for (int i = 0; i < m; ++i) {
+        tickets[i] = sv->finished[i].ticket;
+        iters[i] = sv->finished[i].iters_done;
+        status[i] = sv->fin_status[i];
+        relres[i] = sv->fin_relres[i];
+    }
+    sv->finished.erase(sv->finished.begin(), sv->finished.begin() + m);
+    sv->fin_status.erase(sv->fin_status.begin(), sv->fin_status.begin() + m);
+    sv->fin_relres.erase(sv->fin_relres.begin(), sv->fin_relres.begin() + m);
+    *count = m;
     return RBFFD_OK;
 }
 

@@ -111,3 +111,40 @@ def test_batched_rejects_bad_arguments(ctx, batch):
     st = L.poisson_solve_batched(ctx.handle, 1, arr(batch[0][2].ops.handle), arr(R.binding._ptr(x)),
                                  arr(R.binding._ptr(x)), C.byref(o), None, R.binding._stream())
     assert st == -1
+
+
+def test_server_staggered_equals_alone(ctx, batch):
+    """Continuous batching: solves joining a running batch at different times
+    give bitwise the results of each solve alone."""
+    items = batch[:5]
+    alone, st_alone = [], []
+    for it in items:
+        x1, s1 = _solve(ctx, [it], 1e-10)
+        alone.append(x1[0])
+        st_alone.append(s1[0])
+    sv = R.Server(ctx)
+    xs, tickets = {}, {}
+    rhs = [torch.tensor(it[4], device="cuda") for it in items]
+    done = {}
+    for j, it in enumerate(items):
+        x = torch.zeros(it[1].n, dtype=torch.float64, device="cuda")
+        t = sv.submit(it[2].ops, rhs[j], x, tol=1e-10, max_iter=20000)
+        xs[t], tickets[t] = x, j
+        sv.run(8 + 5 * j)          # others keep running while the next one arrives
+        for t2, st in sv.poll():
+            done[t2] = st
+    while sv.run(32) > 0 or len(done) < len(items):
+        for t2, st in sv.poll():
+            done[t2] = st
+        if len(done) == len(items):
+            break
+    for t2, st in sv.poll():
+        done[t2] = st
+    sv.close()
+    assert len(done) == len(items)
+    for t, j in tickets.items():
+        print(f"[server] {items[j][0]}: iters {done[t]['iters']}/{st_alone[j]['iters']} status {done[t]['status']}",
+              flush=True)
+        assert done[t]["iters"] == st_alone[j]["iters"]
+        assert done[t]["status"] == st_alone[j]["status"]
+        np.testing.assert_array_equal(xs[t].cpu().numpy(), alone[j])
