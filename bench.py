@@ -242,6 +242,153 @@ def batch_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def serve_bench(args):
+    """The serving configuration: a Poisson-arrival stream of solve requests,
+    70% 2D (half Kovasznay squares, half holed squares, 2k-200k points) and 30%
+    3D Beltrami cubes (50k-500k points), degree 2-4 in 2D and 2-3 in 3D, q = 2m,
+    prescribed pressure on every boundary. A request is served when its
+    stencils and operators are built on the device and its pressure-correction
+    solve (random right-hand side) reaches 1e-6. The arrival rate is 0.7 x the
+    closed-loop rate of the one-at-a-time FP64 path; the same arrival sequence
+    is served with continuous batching (rbffd_server) and one at a time."""
+    import torch
+
+    import paper_2106_07616_amd as R
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    R.lib()
+    rng = np.random.default_rng(5)
+    reqs = []
+    for i in range(args.serve_requests):
+        u = rng.random()
+        if u < 0.7:
+            npts = int(round(np.exp(rng.uniform(np.log(2e3), np.log(2e5)))))
+            k = int(rng.integers(2, 5))
+            if rng.random() < 0.5:
+                c = W.kovasznay_square(nx=max(8, int(round(np.sqrt(npts)))), seed=5000 + i,
+                                       boundary_kind=W.PRESCRIBED_PRESSURE)
+            else:
+                c = W.holed_square(npts, seed=5000 + i, edge_kind=W.PRESCRIBED_PRESSURE,
+                                   hole_kind=W.PRESCRIBED_PRESSURE)
+        else:
+            npts = int(round(np.exp(rng.uniform(np.log(5e4), np.log(5e5)))))
+            k = int(rng.integers(2, 4))   # 3D k = 4 needs 105-unknown systems (beyond 64)
+            c = W.beltrami_cube(n=max(8, int(round(npts ** (1 / 3)))), seed=5000 + i)
+        reqs.append((c, k, np.random.default_rng(9000 + i).standard_normal(c.n)))
+    log(f"[serve] {len(reqs)} requests, {sum(r[0].n for r in reqs)} points")
+    budget = 32 << 30
+    ctx = R.Context(0, budget)
+    tol = 1e-6
+
+    def build(j):
+        c, k, b = reqs[j]
+        sv = R.Solver(ctx, c, k)
+        return sv, torch.tensor(b, device="cuda")
+
+    # closed-loop rate of the one-at-a-time path on the first requests
+    warm = min(args.serve_warmup, len(reqs))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(warm):
+        sv, b = build(j)
+        x = torch.zeros_like(b)
+        R.poisson_solve(ctx, sv.ops, b, x, tol=tol, max_iter=20000, allow_noconv=True)
+        sv.ops.free()
+    torch.cuda.synchronize()
+    closed_rate = warm / (time.perf_counter() - t0)
+    lam = 0.7 * closed_rate
+    arrivals = np.cumsum(np.random.default_rng(6).exponential(1.0 / lam, len(reqs)))
+    log(f"[serve] closed-loop one-at-a-time rate {closed_rate:.2f}/s, offered load {lam:.2f}/s")
+
+    def report(lat, fin, iters):
+        lat = np.array(lat[warm:]) * 1e3
+        span = max(fin[warm:]) - arrivals[warm]
+        return {"solves_per_s": round((len(reqs) - warm) / span, 3), "p50_ms": round(float(np.percentile(lat, 50)), 1),
+                "p99_ms": round(float(np.percentile(lat, 99)), 1), "mean_ms": round(float(lat.mean()), 1),
+                "M_point_iters_per_s": round(sum(reqs[j][0].n * iters[j] for j in range(warm, len(reqs))) /
+                                             span / 1e6, 1)}
+
+    # one at a time, FIFO
+    lat, fin, iters, conv = [0.0] * len(reqs), [0.0] * len(reqs), [0] * len(reqs), 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(len(reqs)):
+        now = time.perf_counter() - t0
+        if now < arrivals[j]:
+            time.sleep(arrivals[j] - now)
+        sv, b = build(j)
+        x = torch.zeros_like(b)
+        st = R.poisson_solve(ctx, sv.ops, b, x, tol=tol, max_iter=20000, allow_noconv=True)
+        torch.cuda.synchronize()
+        fin[j] = time.perf_counter() - t0
+        lat[j] = fin[j] - arrivals[j]
+        iters[j] = st["iters"]
+        conv += st["status"] == 0
+        sv.ops.free()
+    seq = report(lat, fin, iters)
+    seq["converged"] = int(conv)
+    log(f"[serve] one at a time: {seq}")
+
+    # continuous batching
+    server = R.Server(ctx)
+    lat, fin, iters, conv = [0.0] * len(reqs), [0.0] * len(reqs), [0] * len(reqs), 0
+    live = {}
+    nxt = 0
+    peak = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < len(reqs):
+        now = time.perf_counter() - t0
+        # admit every request that has arrived, while the HBM budget allows
+        while nxt < len(reqs) and arrivals[nxt] <= now:
+            try:
+                sv, b = build(nxt)
+                x = torch.zeros_like(b)
+                t = server.submit(sv.ops, b, x, tol=tol, max_iter=20000)
+            except R.RbffdError as e:
+                if e.code != -2:
+                    raise
+                break   # over budget: admit after some solves finish
+            live[t] = (nxt, sv)
+            nxt += 1
+            now = time.perf_counter() - t0
+        active = server.run(args.serve_chunk)
+        peak = max(peak, active)
+        for t, st in server.poll():
+            j, sv = live.pop(t)
+            fin[j] = time.perf_counter() - t0
+            lat[j] = fin[j] - arrivals[j]
+            iters[j] = st["iters"]
+            conv += st["status"] == 0
+            sv.ops.free()
+            done += 1
+        if active == 0 and nxt < len(reqs):
+            wait = arrivals[nxt] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+    server.close()
+    cb = report(lat, fin, iters)
+    cb["converged"] = int(conv)
+    cb["peak_concurrent_solves"] = int(peak)
+    log(f"[serve] continuous batching: {cb}")
+    out = {
+        "metric": METRIC, "value": cb["solves_per_s"], "unit": "converged solves/s", "n_gpus": 1,
+        "steps": len(reqs) - warm, "warmup": warm, "ms_per_step": cb["mean_ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"Poisson-arrival stream of {len(reqs)} solve requests (first {warm} excluded): 70% 2D "
+                               "Kovasznay/holed squares 2k-200k points, 30% 3D Beltrami cubes 50k-500k points, "
+                               "k=2-4 (3D 2-3), q=2m; stencils + operators + pressure-correction solve to 1e-6 per "
+                               f"request; offered load {lam:.2f}/s = 0.7 x one-at-a-time closed-loop rate; "
+                               "HBM budget 32 GiB", "requests": len(reqs)},
+        "continuous_batching": cb, "one_at_a_time_fp64": seq,
+        "p99_latency_ratio_one_at_a_time_over_batched": round(seq["p99_ms"] / cb["p99_ms"], 3),
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,7 +399,10 @@ def main():
     ap.add_argument("--spmv-reps", type=int, default=200)
     ap.add_argument("--solve-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch"], default="taylor_green")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch", "serve"], default="taylor_green")
+    ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-warmup", type=int, default=20)
+    ap.add_argument("--serve-chunk", type=int, default=16)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--cpu-sample-r", type=float, default=0.02)
     ap.add_argument("--cpu-sample-cube", type=int, default=30)
@@ -263,6 +413,9 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         batch_bench(args)
+        return
+    if args.workload == "serve":
+        serve_bench(args)
         return
 
     import torch
