@@ -83,7 +83,8 @@ WORKLOADS = {
     },
 }
 
-COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "spmv_pressure_tg250k_counters.txt")
+COUNTER_SUMMARY = {"taylor_green": os.path.join(ROOT, "profiles", "spmv_pressure_tg250k_counters.txt"),
+                   "beltrami": os.path.join(ROOT, "profiles", "spmv_pressure_beltrami1m_counters.txt")}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2106_07616_amd", "csrc", f) for f in ("krylov.hip", "internal.h")]
 
 
@@ -96,12 +97,12 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def counter_traffic():
+def counter_traffic(workload):
     """HBM bytes per SpMV launch from the committed counter summary (FETCH_SIZE and
     WRITE_SIZE scaled by the copy-kernel calibration), or None when the summary is
     missing or was taken from different kernel sources."""
     try:
-        with open(COUNTER_SUMMARY) as fh:
+        with open(COUNTER_SUMMARY[workload]) as fh:
             kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith("#"))
     except OSError:
         return None
@@ -597,7 +598,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(spmv_gbs / HBM_PEAK_GBS, 4),
-            "traffic": counter_traffic(),
+            "traffic": counter_traffic(args.workload),
             "bytes_per_launch": spmv_bytes(n, q, narrow),
             "index_bytes": f"{narrow:.4f} of rows with 2-byte column offsets, the rest 4-byte indices",
             "us_per_launch": round(spmv_ms * 1e3, 2),

@@ -139,11 +139,27 @@ int rbffd_ctx_create(rbffd_ctx **ctx, int hip_device, size_t hbm_budget_bytes)
     return RBFFD_OK;
 }
 
+struct rbffd_server {
+    rbffd_ctx *ctx;
+    rbffd::Server *impl;
+};
+
+static void release_ops_memory(rbffd_ops *ops);
+
 int rbffd_ctx_destroy(rbffd_ctx *ctx)
 {
     if (!ctx) return RBFFD_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    for (rbffd_server *sv : ctx->servers) {
+        server_destroy(sv->impl);
+        sv->impl = nullptr;
+        sv->ctx = nullptr;
+    }
+    for (rbffd_ops *ops : ctx->ops) {
+        release_ops_memory(ops);
+        ops->ctx = nullptr;
+    }
     for (int s = 0; s < WS_COUNT; ++s) {
         if (!ctx->ws[s].ptr) continue;
         if (s == WS_HOST_PINNED || s == WS_BATCH_HOST)
@@ -219,22 +235,37 @@ int rbffd_assemble(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_stencil
         rbffd_ops_free(ops);
         return fail(st, msg);
     }
+    ctx->ops.insert(ops);
     *out = ops;
     return RBFFD_OK;
+}
+
+// device memory of an operator object (the object itself stays)
+static void release_ops_memory(rbffd_ops *ops)
+{
+    void **ptrs[] = {(void **)&ops->kind,   (void **)&ops->normal, (void **)&ops->col,    (void **)&ops->cbase,
+                     (void **)&ops->col16,  (void **)&ops->val,    (void **)&ops->pval,   (void **)&ops->pdinv,
+                     (void **)&ops->pval32, (void **)&ops->pdinv32, (void **)&ops->mval, (void **)&ops->mdinv,
+                     (void **)&ops->mval32, (void **)&ops->mdinv32, (void **)&ops->bidx, (void **)&ops->bpos,
+                     (void **)&ops->gcol,   (void **)&ops->gval,   (void **)&ops->gdinv};
+    for (void **p : ptrs) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+    if (ops->ctx) ops->ctx->in_use -= ops->bytes;
+    ops->bytes = 0;
 }
 
 int rbffd_ops_free(rbffd_ops *ops)
 {
     if (!ops) return RBFFD_OK;
     rbffd_ctx *ctx = ops->ctx;
-    if (ctx) (void)hipSetDevice(ctx->device);
-    (void)hipDeviceSynchronize();
-    void *ptrs[] = {ops->kind, ops->normal, ops->col, ops->cbase, ops->col16, ops->val, ops->pval, ops->pdinv, ops->pval32,
-                    ops->pdinv32, ops->mval, ops->mdinv, ops->mval32, ops->mdinv32, ops->bidx,
-                    ops->bpos, ops->gcol, ops->gval, ops->gdinv};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
-    if (ctx) ctx->in_use -= ops->bytes;
+    if (ctx) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+        ctx->ops.erase(ops);
+        release_ops_memory(ops);
+    }
     delete ops;
     return RBFFD_OK;
 }
@@ -252,6 +283,7 @@ int rbffd_ops_info(const rbffd_ops *ops, int64_t *n, int *q, int *dim, int64_t *
 int rbffd_ops_export_csr(const rbffd_ops *ops, int32_t *col, double *val, void *hip_stream)
 {
     if (!ops || !col || !val) return fail(RBFFD_E_ARG, "NULL argument");
+    if (!ops->ctx) return fail(RBFFD_E_ARG, "the operators' context was destroyed");
     RB_HIP(hipSetDevice(ops->ctx->device));
     return export_csr(ops, col, val, (hipStream_t)hip_stream);
 }
@@ -260,6 +292,7 @@ int rbffd_apply(rbffd_ctx *ctx, const rbffd_ops *ops, int which, const double *x
                 void *hip_stream)
 {
     if (!ctx || !ops || !x || !y) return fail(RBFFD_E_ARG, "NULL argument");
+    if (!ops->ctx) return fail(RBFFD_E_ARG, "the operators' context was destroyed");
     if (which < 0 || which > ops->dim + 1) return fail(RBFFD_E_ARG, "operator index out of range");
     RB_HIP(hipSetDevice(ctx->device));
     return apply_op(ctx, ops, which, x, y, (hipStream_t)hip_stream);
@@ -269,6 +302,7 @@ int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, doubl
                   const rbffd_krylov_opts *opts, rbffd_krylov_stats *stats, void *hip_stream)
 {
     if (!ctx || !ops || !rhs || !x || !opts) return fail(RBFFD_E_ARG, "NULL argument");
+    if (!ops->ctx) return fail(RBFFD_E_ARG, "the operators' context was destroyed");
     if (!(opts->tol >= 0.0) || opts->max_iter < 0) return fail(RBFFD_E_ARG, "bad Krylov options");
     if (opts->precision != RBFFD_FP64 && opts->precision != RBFFD_FP32_IR && opts->precision != RBFFD_FP32_MATRIX)
         return fail(RBFFD_E_ARG, "unknown precision");
@@ -313,6 +347,7 @@ int poisson_solve_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops
     for (int j = 0; j < count; ++j) {
         if (!ops[j] || !rhs[j] || !x[j])
             return fail(RBFFD_E_ARG, "NULL operator, right-hand side or solution of system " + std::to_string(j));
+        if (!ops[j]->ctx) return fail(RBFFD_E_ARG, "the operators' context was destroyed");
         sys[j] = BatchSystem{ops[j]->n, ops[j]->q, cols_of(ops[j]), ops[j]->pval, ops[j]->pdinv, rhs[j], x[j]};
     }
     RB_HIP(hipSetDevice(ctx->device));
@@ -335,25 +370,24 @@ int poisson_solve_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops
     return RBFFD_OK;
 }
 
-struct rbffd_server {
-    rbffd_ctx *ctx;
-    rbffd::Server *impl;
-};
-
 int rbffd_server_create(rbffd_ctx *ctx, rbffd_server **out)
 {
     if (!ctx || !out) return fail(RBFFD_E_ARG, "NULL argument");
     rbffd::Server *impl = nullptr;
     RB_CHECK(server_create(ctx, &impl));
     *out = new rbffd_server{ctx, impl};
+    ctx->servers.insert(*out);
     return RBFFD_OK;
 }
 
 int rbffd_server_destroy(rbffd_server *sv)
 {
     if (!sv) return RBFFD_OK;
-    (void)hipSetDevice(sv->ctx->device);
-    server_destroy(sv->impl);
+    if (sv->ctx) {
+        (void)hipSetDevice(sv->ctx->device);
+        sv->ctx->servers.erase(sv);
+        server_destroy(sv->impl);
+    }
     delete sv;
     return RBFFD_OK;
 }
@@ -362,6 +396,8 @@ int rbffd_server_submit(rbffd_server *sv, const rbffd_ops *ops, const double *rh
                         int max_iter, int64_t *ticket)
 {
     if (!sv || !ops || !rhs || !x || !ticket) return fail(RBFFD_E_ARG, "NULL argument");
+    if (!sv->impl) return fail(RBFFD_E_ARG, "the server's context was destroyed");
+    if (!ops->ctx) return fail(RBFFD_E_ARG, "the operators' context was destroyed");
     if (!(tol >= 0.0) || max_iter < 1) return fail(RBFFD_E_ARG, "bad Krylov options");
     RB_HIP(hipSetDevice(sv->ctx->device));
     const BatchSystem sys{ops->n, ops->q, cols_of(ops), ops->pval, ops->pdinv, rhs, x};
@@ -371,6 +407,7 @@ int rbffd_server_submit(rbffd_server *sv, const rbffd_ops *ops, const double *rh
 int rbffd_server_run(rbffd_server *sv, int iterations, int *active, void *hip_stream)
 {
     if (!sv || !active || iterations < 1) return fail(RBFFD_E_ARG, "bad argument");
+    if (!sv->impl) return fail(RBFFD_E_ARG, "the server's context was destroyed");
     RB_HIP(hipSetDevice(sv->ctx->device));
     return server_run(sv->impl, iterations, active, (hipStream_t)hip_stream);
 }
@@ -378,6 +415,7 @@ int rbffd_server_run(rbffd_server *sv, int iterations, int *active, void *hip_st
 int rbffd_server_poll(rbffd_server *sv, int max, int64_t *tickets, rbffd_krylov_stats *stats, int *count)
 {
     if (!sv || !tickets || !stats || !count || max < 0) return fail(RBFFD_E_ARG, "bad argument");
+    if (!sv->impl) return fail(RBFFD_E_ARG, "the server's context was destroyed");
     std::vector<int> iters((size_t)std::max(max, 1)), status((size_t)std::max(max, 1));
     std::vector<double> relres((size_t)std::max(max, 1));
     RB_CHECK(server_poll(sv->impl, max, tickets, iters.data(), status.data(), relres.data(), count));
@@ -396,6 +434,7 @@ int simple_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev,
                 rbffd_step_stats *stats, void *hip_stream)
 {
     if (!ctx || !ops || !u || !u_prev || !p || !u_bc || !opts) return fail(RBFFD_E_ARG, "NULL argument");
+    if (!ops->ctx) return fail(RBFFD_E_ARG, "the operators' context was destroyed");
     if (ops->n_prescribed > 0 && !p_bc) return fail(RBFFD_E_ARG, "p_bc is required: the cloud has prescribed-pressure points");
     if (!(opts->rho > 0.0) || !(opts->mu >= 0.0) || !(opts->dt > 0.0) || !std::isfinite(opts->dt))
         return fail(RBFFD_E_ARG, "rho, mu, dt must be positive and finite");
@@ -417,6 +456,7 @@ int rbffd_convdiff_lambda(rbffd_ctx *ctx, const rbffd_ops *ops, const double *u0
                           double mu, int iters, double *lambda_out, void *hip_stream)
 {
     if (!ctx || !ops || !u0 || !lambda_out || iters < 1) return fail(RBFFD_E_ARG, "bad argument");
+    if (!ops->ctx) return fail(RBFFD_E_ARG, "the operators' context was destroyed");
     RB_HIP(hipSetDevice(ctx->device));
     return convdiff_lambda(ctx, ops, u0, rho, mu, iters, lambda_out, (hipStream_t)hip_stream);
 }

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <set>
 #include <string>
 
 #include "../../include/rbffd.h"
@@ -83,11 +84,16 @@ constexpr size_t kHostBytes = 4096;
 
 }  // namespace rbffd
 
+struct rbffd_server;
 struct rbffd_ctx {
     int device = 0;
     size_t budget = 0;        // 0 = unlimited
     size_t in_use = 0;
     rbffd::Buffer ws[rbffd::WS_COUNT];
+    // objects created under this context: destroying the context releases
+    // their device memory and leaves them orphaned (freeing them later is safe)
+    std::set<rbffd_ops *> ops;
+    std::set<rbffd_server *> servers;
 };
 
 namespace rbffd {
