@@ -314,3 +314,53 @@ def test_cloud_equal_to_whole_set(ctx, orc):
     np.testing.assert_array_equal(s.nbr.cpu().numpy(), ref)
     w = orc.weights(c.xyz, ref, 2)
     assert _rel_rows(s.w.cpu().numpy(), w) <= 1e-10
+
+
+def test_more_argument_errors(ctx):
+    """Argument checks run before any launch and return RBFFD_E_ARG."""
+    import ctypes as C
+    L = R.lib()
+    c = W.kovasznay_square(nx=6)
+    dc = R.DeviceCloud.from_numpy(c)
+    o = R.binding.StencilOptsT(3, 2, 0)
+    bad = C.c_int64(-1)
+    nbr = torch.empty((c.n, 12), dtype=torch.int32, device="cuda")
+    w = torch.empty((3, c.n, 12), dtype=torch.float64, device="cuda")
+    for cs in (R.binding.CloudT(2, 0, R.binding._ptr(dc.xyz), R.binding._ptr(dc.kind), R.binding._ptr(dc.normal), 0),
+               R.binding.CloudT(4, c.n, R.binding._ptr(dc.xyz), R.binding._ptr(dc.kind), R.binding._ptr(dc.normal), 0)):
+        st = L.rbffd_build_stencils(ctx.handle, C.byref(cs), C.byref(o), R.binding._ptr(nbr), R.binding._ptr(w),
+                                    C.byref(bad), R.binding._stream())
+        assert st == -1
+    with pytest.raises(R.RbffdError) as e:
+        R.rbffd_build_stencils(ctx, dc, 7)                       # degree > 6
+    assert e.value.code == -1
+    with pytest.raises(R.RbffdError):
+        R.rbffd_build_stencils(ctx, dc, 2, q=129)                # q > 128
+    cube = R.DeviceCloud.from_numpy(W.scattered_cube(5, seed=2))
+    with pytest.raises(R.RbffdError) as e:
+        R.rbffd_build_stencils(ctx, cube, 4)                     # 3D k=4: 105 unknowns > 64
+    assert e.value.code == -1
+    # prescribed-pressure points need p_bc
+    t = W.taylor_green_disk(r=0.3)
+    s = R.Solver(ctx, t, 2)
+    vel, p = W.flow_fields(t)
+    u = torch.tensor(vel, device="cuda")
+    with pytest.raises(R.RbffdError) as e:
+        R.simple_step(ctx, s.ops, u, u.clone(), torch.tensor(p, device="cuda"), u.clone(), 1.0, 0.01, 0.01)
+    assert e.value.code == -1
+    # mixed precision needs FP32 copies
+    b = torch.ones(t.n, dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    with pytest.raises(R.RbffdError) as e:
+        R.poisson_solve(ctx, s.ops, b, x, precision=R.RBFFD_FP32_IR)
+    assert e.value.code == -1
+
+
+def test_zero_iterations_report_noconv(ctx):
+    c = W.kovasznay_square(nx=8)
+    s = R.Solver(ctx, c, 2)
+    b = torch.ones(c.n, dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    st = R.poisson_solve(ctx, s.ops, b, x, tol=1e-10, max_iter=0, allow_noconv=True)
+    assert st["status"] == -4 and st["iters"] == 0
+    assert float(x.abs().max()) == 0.0
