@@ -399,6 +399,8 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32ir", "fp32matrix"], default="fp64")
     ap.add_argument("--spmv-reps", type=int, default=200)
     ap.add_argument("--solve-reps", type=int, default=5)
+    ap.add_argument("--mixed-step", action="store_true",
+                    help="also run the step with both mixed-precision modes and report per-field differences")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch", "serve"], default="taylor_green")
     ap.add_argument("--serve-requests", type=int, default=120)
@@ -625,6 +627,32 @@ def main():
             "note": "both mixed modes: FP64 row and dot accumulation, FP64 reliable residual updates",
         },
     }
+    if args.mixed_step:
+        # the same step with mixed-precision Krylov sweeps against the FP64 step:
+        # per-field relative difference (max over points / max of the FP64 field)
+        nbr, w, _ = R.rbffd_build_stencils(ctx, dcloud, k)
+        ops_m = R.rbffd_assemble(ctx, dcloud, nbr, w, k, precision=R.RBFFD_FP32_IR)
+        res = {}
+        for name, prec in (("fp64", R.RBFFD_FP64), ("fp32", R.RBFFD_FP32_IR), ("fp32matrix", R.RBFFD_FP32_MATRIX)):
+            u, up, p = u0.clone(), um1.clone(), pt0.clone()
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            st = R.simple_step(ctx, ops_m, u, up, p, ubc, rho, nu, dt, R.BDF2, tol_outer=1e-8, tol_krylov=1e-10,
+                               max_outer=args.max_outer, max_krylov=20000, precision=prec, p_bc=pbc)
+            torch.cuda.synchronize()
+            res[name] = (u, p, st, time.perf_counter() - ta)
+        u64, p64 = res["fp64"][0], res["fp64"][1]
+        fields = {}
+        for name in ("fp32", "fp32matrix"):
+            u, p, st, tm = res[name]
+            du = [float((u[e] - u64[e]).abs().max() / u64[e].abs().max()) for e in range(cloud.dim)]
+            dp = float((p - p64).abs().max() / p64.abs().max())
+            fields[name] = {"ms": round(tm * 1e3, 1), "outer_iters": st["outer_iters"],
+                            "krylov_iters": st["krylov_mom"] + st["krylov_p"],
+                            "rel_diff_vs_fp64": dict(zip("uvw"[:cloud.dim], du), p=dp)}
+        fields["fp64_ms"] = round(res["fp64"][3] * 1e3, 1)
+        out["mixed_precision_step"] = fields
+        ops_m.free()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args)
     ctx.close()
