@@ -412,7 +412,7 @@ def main():
     ap.add_argument("--spmv-only", action="store_true", help="run only the SpMV timing (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (pass --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU; runs on several GPUs are not supported (pass --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
         batch_bench(args)

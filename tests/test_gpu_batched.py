@@ -61,7 +61,7 @@ def test_batched_matches_oracle(ctx, orc, batch):
         if st_o != 0:
             continue
         # at 1e-12 the attainable accuracy of a Neumann system can stop the
-        # true residual just above the tolerance: judge the residual itself
+        # true residual just above the tolerance: check the residual itself
         assert sj["relres"] <= max(1e-9, 10 * rr_o)
         assert err <= 1e-8
 
