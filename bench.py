@@ -411,7 +411,8 @@ def main():
     ap.add_argument("--spmv-reps", type=int, default=200)
     ap.add_argument("--solve-reps", type=int, default=5)
     ap.add_argument("--mixed-step", action="store_true",
-                    help="also run the step with both mixed-precision modes and report per-field differences")
+                    help="also run the step with both mixed-precision modes and with the block-Jacobi "
+                         "pressure preconditioner, and report per-field differences")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch", "serve"], default="taylor_green")
     ap.add_argument("--serve-requests", type=int, default=120)
@@ -513,13 +514,14 @@ def main():
     # refinement, on the same pressure-correction system ----------------------
     ops_mixed = R.rbffd_assemble(ctx, dcloud, solver.nbr, solver.w, k, precision=R.RBFFD_FP32_IR)
 
-    def timed_solves(prec, reps):
+    def timed_solves(prec, reps, pc=R.RBFFD_PREC_JACOBI):
         lat, its, rel, fb = [], [], [], []
         for _ in range(reps):
             xs.zero_()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            st = R.poisson_solve(ctx, ops_mixed, rhs, xs, tol=1e-6, max_iter=20000, precision=prec, allow_noconv=True)
+            st = R.poisson_solve(ctx, ops_mixed, rhs, xs, tol=1e-6, max_iter=20000, precision=prec, allow_noconv=True,
+                                 preconditioner=pc)
             torch.cuda.synchronize()
             lat.append(time.perf_counter() - t0)
             its.append(st["iters"])
@@ -536,8 +538,11 @@ def main():
     solves32 = timed_solves(R.RBFFD_FP32_IR, args.solve_reps)
     timed_solves(R.RBFFD_FP32_MATRIX, 1)
     solves32m = timed_solves(R.RBFFD_FP32_MATRIX, args.solve_reps)
+    timed_solves(R.RBFFD_FP64, 1, R.RBFFD_PREC_BLOCK64)
+    solves64b = timed_solves(R.RBFFD_FP64, args.solve_reps, R.RBFFD_PREC_BLOCK64)
     ops_mixed.free()
-    log(f"[bench] solves at 1e-6: fp64 {solves64}  fp32 {solves32}  fp32 matrix {solves32m}")
+    log(f"[bench] solves at 1e-6: fp64 {solves64}  fp32 {solves32}  fp32 matrix {solves32m}  "
+        f"fp64 block-Jacobi {solves64b}")
 
     # ---- the benchmark step ---------------------------------------------------
     phase_s = {"stencils": 0.0, "assemble": 0.0, "time_step": 0.0}
@@ -635,9 +640,13 @@ def main():
             "fp64": solves64,
             "fp32_vectors_and_matrix": solves32,
             "fp32_matrix_fp64_vectors": solves32m,
+            "fp64_block_jacobi": solves64b,
             "speedup_vs_fp64": {"fp32_vectors_and_matrix": round(solves32["solves_per_s"] / solves64["solves_per_s"], 3),
-                                "fp32_matrix_fp64_vectors": round(solves32m["solves_per_s"] / solves64["solves_per_s"], 3)},
-            "note": "both mixed modes: FP64 row and dot accumulation, FP64 reliable residual updates",
+                                "fp32_matrix_fp64_vectors": round(solves32m["solves_per_s"] / solves64["solves_per_s"], 3),
+                                "fp64_block_jacobi": round(solves64b["solves_per_s"] / solves64["solves_per_s"], 3)},
+            "note": "both mixed modes: FP64 row and dot accumulation, FP64 reliable residual updates; "
+                    "fp64 and the mixed modes use the Jacobi preconditioner, fp64_block_jacobi the inverses "
+                    "of the 64x64 diagonal blocks",
         },
     }
     if args.mixed_step:
@@ -646,17 +655,21 @@ def main():
         nbr, w, _ = R.rbffd_build_stencils(ctx, dcloud, k)
         ops_m = R.rbffd_assemble(ctx, dcloud, nbr, w, k, precision=R.RBFFD_FP32_IR)
         res = {}
-        for name, prec in (("fp64", R.RBFFD_FP64), ("fp32", R.RBFFD_FP32_IR), ("fp32matrix", R.RBFFD_FP32_MATRIX)):
+        for name, prec, pc in (("fp64", R.RBFFD_FP64, R.RBFFD_PREC_JACOBI),
+                               ("fp32", R.RBFFD_FP32_IR, R.RBFFD_PREC_JACOBI),
+                               ("fp32matrix", R.RBFFD_FP32_MATRIX, R.RBFFD_PREC_JACOBI),
+                               ("fp64_block_jacobi", R.RBFFD_FP64, R.RBFFD_PREC_BLOCK64)):
             u, up, p = u0.clone(), um1.clone(), pt0.clone()
             torch.cuda.synchronize()
             ta = time.perf_counter()
             st = R.simple_step(ctx, ops_m, u, up, p, ubc, rho, nu, dt, R.BDF2, tol_outer=1e-8, tol_krylov=1e-10,
-                               max_outer=args.max_outer, max_krylov=20000, precision=prec, p_bc=pbc)
+                               max_outer=args.max_outer, max_krylov=20000, precision=prec, p_bc=pbc,
+                               preconditioner=pc)
             torch.cuda.synchronize()
             res[name] = (u, p, st, time.perf_counter() - ta)
         u64, p64 = res["fp64"][0], res["fp64"][1]
         fields = {}
-        for name in ("fp32", "fp32matrix"):
+        for name in ("fp32", "fp32matrix", "fp64_block_jacobi"):
             u, p, st, tm = res[name]
             du = [float((u[e] - u64[e]).abs().max() / u64[e].abs().max()) for e in range(cloud.dim)]
             dp = float((p - p64).abs().max() / p64.abs().max())

@@ -60,6 +60,12 @@ extern "C" {
                                    vectors: 1/3 fewer matrix bytes at q >= 20 with
                                    nearly the FP64 iteration count                      */
 
+/* ---- preconditioner of the pressure-correction solve ------------------- */
+#define RBFFD_PREC_JACOBI 0     /* diagonal (Jacobi), applied on the right               */
+#define RBFFD_PREC_BLOCK64 1    /* inverses of the 64 x 64 diagonal blocks of the 64-row
+                                   slices (Morton-compact patches of 64 points), applied
+                                   on the right; FP64 solves only                       */
+
 /* ---- point kinds ------------------------------------------------------- */
 #define RBFFD_INTERIOR 0
 #define RBFFD_DIRICHLET 1       /* prescribed velocity (wall, inlet); homogeneous Neumann
@@ -144,6 +150,11 @@ int rbffd_ops_info(const rbffd_ops *ops, int64_t *n, int *q, int *dim, int64_t *
  * columns ascending): col device [n][q] int32, val device [R+1][n][q] double
  * holding d/dx, d/dy, (d/dz), Laplacian and the pressure-correction matrix. */
 int rbffd_ops_export_csr(const rbffd_ops *ops, int32_t *col, double *val, void *hip_stream);
+/* The block-Jacobi preconditioner of the pressure-correction matrix: for each
+ * 64-row slice s, the inverse of its 64 x 64 diagonal block in FP32,
+ * column-major (entry (row l, column j) at out[s*4096 + j*64 + l]; padding rows
+ * of the last slice are identity rows). out: device [ceil(n/64) * 4096]. */
+int rbffd_ops_export_block_inverse(const rbffd_ops *ops, float *out, void *hip_stream);
 /* y = A x for operator `which` (0..dim-1: d/dx_e, dim: Laplacian, dim+1: the
  * pressure-correction matrix); x, y device [n]. Enqueued on the stream and not
  * synchronised (one kernel launch). */
@@ -155,6 +166,7 @@ typedef struct {
     double tol;             /* stop when ||b - A x||_2 <= tol ||b||_2 (recursive residual) */
     int max_iter;           /* BiCGSTAB iterations                                   */
     int precision;          /* RBFFD_FP64, RBFFD_FP32_IR or RBFFD_FP32_MATRIX        */
+    int preconditioner;     /* RBFFD_PREC_JACOBI or RBFFD_PREC_BLOCK64 (poisson_solve) */
 } rbffd_krylov_opts;
 
 typedef struct {
@@ -168,8 +180,9 @@ typedef struct {
 
 /* (Sec. 3, "preconditioned BiCGSTAB") Solve P x = rhs for the
  * pressure-correction matrix with BiCGSTAB, right-preconditioned by the
- * Jacobi diagonal. x holds the initial guess on entry and the solution on
- * return. rhs, x: device [n]. */
+ * Jacobi diagonal or (opts->preconditioner) by the 64x64 diagonal blocks.
+ * x holds the initial guess on entry and the solution on return.
+ * rhs, x: device [n]. */
 int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, double *x,
                   const rbffd_krylov_opts *opts, rbffd_krylov_stats *stats, void *hip_stream);
 
@@ -226,6 +239,9 @@ typedef struct {
     int max_outer;          /* outer iteration limit                                  */
     int max_krylov;         /* iteration limit of every Krylov solve                  */
     int precision;          /* RBFFD_FP64, RBFFD_FP32_IR or RBFFD_FP32_MATRIX        */
+    int preconditioner;     /* of the pressure-correction solve: RBFFD_PREC_JACOBI or
+                               RBFFD_PREC_BLOCK64 (with RBFFD_FP64); momentum and
+                               boundary-pressure solves use Jacobi                    */
 } rbffd_step_opts;
 
 typedef struct {

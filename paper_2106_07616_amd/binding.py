@@ -19,12 +19,13 @@ LIB_PATH = os.path.join(_HERE, "librbffd.so")
 RBFFD_OK, RBFFD_E_ARG, RBFFD_E_OOM, RBFFD_E_SINGULAR = 0, -1, -2, -3
 RBFFD_E_NOCONV, RBFFD_E_BREAKDOWN, RBFFD_E_DEVICE = -4, -5, -6
 RBFFD_FP64, RBFFD_FP32_IR, RBFFD_FP32_MATRIX = 0, 1, 2
+RBFFD_PREC_JACOBI, RBFFD_PREC_BLOCK64 = 0, 1
 STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_OOM", -3: "E_SINGULAR", -4: "E_NOCONV",
                 -5: "E_BREAKDOWN", -6: "E_DEVICE"}
 
 EXPORTED = ["rbffd_last_error", "rbffd_ctx_create", "rbffd_ctx_destroy", "rbffd_ctx_bytes_in_use",
             "rbffd_stencil_sizes", "rbffd_build_stencils", "rbffd_assemble", "rbffd_ops_free",
-            "rbffd_ops_info", "rbffd_ops_export_csr", "rbffd_apply", "poisson_solve", "poisson_solve_batched",
+            "rbffd_ops_info", "rbffd_ops_export_csr", "rbffd_ops_export_block_inverse", "rbffd_apply", "poisson_solve", "poisson_solve_batched",
             "rbffd_server_create", "rbffd_server_destroy", "rbffd_server_submit", "rbffd_server_run",
             "rbffd_server_poll", "simple_step", "rbffd_convdiff_lambda"]
 
@@ -45,7 +46,7 @@ class StencilOptsT(C.Structure):
 
 
 class KrylovOptsT(C.Structure):
-    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int)]
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int), ("preconditioner", C.c_int)]
 
 
 class KrylovStatsT(C.Structure):
@@ -56,7 +57,7 @@ class KrylovStatsT(C.Structure):
 class StepOptsT(C.Structure):
     _fields_ = [("rho", C.c_double), ("mu", C.c_double), ("dt", C.c_double), ("alpha", C.c_double * 3),
                 ("tol_outer", C.c_double), ("tol_krylov", C.c_double), ("max_outer", C.c_int),
-                ("max_krylov", C.c_int), ("precision", C.c_int)]
+                ("max_krylov", C.c_int), ("precision", C.c_int), ("preconditioner", C.c_int)]
 
 
 class StepStatsT(C.Structure):
@@ -81,6 +82,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.rbffd_ops_free.argtypes = [P]
     L.rbffd_ops_info.argtypes = [P, C.POINTER(I64), C.POINTER(I), C.POINTER(I), C.POINTER(I64)]
     L.rbffd_ops_export_csr.argtypes = [P, P, P, P]
+    L.rbffd_ops_export_block_inverse.argtypes = [P, P, P]
     L.rbffd_apply.argtypes = [P, P, I, P, P, P]
     L.poisson_solve.argtypes = [P, P, P, P, C.POINTER(KrylovOptsT), C.POINTER(KrylovStatsT), P]
     L.poisson_solve_batched.argtypes = [P, I, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(KrylovOptsT),
@@ -212,6 +214,13 @@ class Operators:
         _check(lib().rbffd_ops_export_csr(self.handle, _ptr(col), _ptr(val), _stream()))
         return col, val
 
+    def export_block_inverse(self):
+        """[ceil(n/64), 64 (column), 64 (row)] FP32 inverses of the diagonal blocks."""
+        nb = (self.n + 63) // 64
+        out = torch.empty((nb, 64, 64), dtype=torch.float32, device=self.cloud.xyz.device)
+        _check(lib().rbffd_ops_export_block_inverse(self.handle, _ptr(out), _stream()))
+        return out
+
     def apply(self, which: int, x: torch.Tensor) -> torch.Tensor:
         y = torch.empty_like(x)
         _check(lib().rbffd_apply(self.ctx.handle, self.handle, which, _ptr(x), _ptr(y), _stream()))
@@ -241,8 +250,9 @@ def rbffd_assemble(ctx: Context, cloud: DeviceCloud, nbr: torch.Tensor, w: torch
 
 
 def poisson_solve(ctx: Context, ops: Operators, rhs: torch.Tensor, x: torch.Tensor, tol: float = 1e-10,
-                  max_iter: int = 5000, precision: int = RBFFD_FP64, allow_noconv: bool = False):
-    o = KrylovOptsT(tol, max_iter, precision)
+                  max_iter: int = 5000, precision: int = RBFFD_FP64, allow_noconv: bool = False,
+                  preconditioner: int = RBFFD_PREC_JACOBI):
+    o = KrylovOptsT(tol, max_iter, precision, preconditioner)
     s = KrylovStatsT()
     st = lib().poisson_solve(ctx.handle, ops.handle, _ptr(rhs), _ptr(x), C.byref(o), C.byref(s), _stream())
     _check(st, allow=(RBFFD_E_NOCONV, RBFFD_E_BREAKDOWN) if allow_noconv else ())
@@ -258,7 +268,7 @@ def poisson_solve_batched(ctx: Context, ops: list, rhs: list, x: list, tol: floa
     if not (m == len(rhs) == len(x)) or m == 0:
         raise ValueError("ops, rhs and x must be non-empty lists of the same length")
     arr = C.c_void_p * m
-    o = KrylovOptsT(tol, max_iter, RBFFD_FP64)
+    o = KrylovOptsT(tol, max_iter, RBFFD_FP64, RBFFD_PREC_JACOBI)
     stats = (KrylovStatsT * m)()
     st = lib().poisson_solve_batched(ctx.handle, m, arr(*[op.handle for op in ops]), arr(*[_ptr(t) for t in rhs]),
                                      arr(*[_ptr(t) for t in x]), C.byref(o), stats, _stream())
@@ -312,11 +322,13 @@ BDF1 = (1.0, -1.0, 0.0)
 def simple_step(ctx: Context, ops: Operators, u: torch.Tensor, u_prev: torch.Tensor, p: torch.Tensor,
                 u_bc: torch.Tensor, rho: float, mu: float, dt: float, alpha=BDF2, tol_outer: float = 1e-6,
                 tol_krylov: float = 1e-10, max_outer: int = 50, max_krylov: int = 5000,
-                precision: int = RBFFD_FP64, p_bc: torch.Tensor | None = None):
+                precision: int = RBFFD_FP64, p_bc: torch.Tensor | None = None,
+                preconditioner: int = RBFFD_PREC_JACOBI):
     """One time step in place on u [dim, n], u_prev [dim, n], p [n]; returns stats.
     p_bc [n]: pressure at t^{n+1} on prescribed-pressure points. A limit reached
     (E_NOCONV) is reported in the stats, not raised."""
-    o = StepOptsT(rho, mu, dt, (C.c_double * 3)(*alpha), tol_outer, tol_krylov, max_outer, max_krylov, precision)
+    o = StepOptsT(rho, mu, dt, (C.c_double * 3)(*alpha), tol_outer, tol_krylov, max_outer, max_krylov, precision,
+                  preconditioner)
     s = StepStatsT()
     st = lib().simple_step(ctx.handle, ops.handle, _ptr(u), _ptr(u_prev), _ptr(p), _ptr(u_bc), _ptr(p_bc),
                            C.byref(o), C.byref(s), _stream())

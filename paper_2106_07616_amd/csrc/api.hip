@@ -244,7 +244,7 @@ int rbffd_assemble(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_stencil
 static void release_ops_memory(rbffd_ops *ops)
 {
     void **ptrs[] = {(void **)&ops->kind,   (void **)&ops->normal, (void **)&ops->col,    (void **)&ops->cbase,
-                     (void **)&ops->col16,  (void **)&ops->val,    (void **)&ops->pval,   (void **)&ops->pdinv,
+                     (void **)&ops->col16,  (void **)&ops->val,    (void **)&ops->pval,   (void **)&ops->pdinv, (void **)&ops->pbinv,
                      (void **)&ops->pval32, (void **)&ops->pdinv32, (void **)&ops->mval, (void **)&ops->mdinv,
                      (void **)&ops->mval32, (void **)&ops->mdinv32, (void **)&ops->bidx, (void **)&ops->bpos,
                      (void **)&ops->gcol,   (void **)&ops->gval,   (void **)&ops->gdinv};
@@ -288,6 +288,17 @@ int rbffd_ops_export_csr(const rbffd_ops *ops, int32_t *col, double *val, void *
     return export_csr(ops, col, val, (hipStream_t)hip_stream);
 }
 
+int rbffd_ops_export_block_inverse(const rbffd_ops *ops, float *out, void *hip_stream)
+{
+    if (!ops || !out) return fail(RBFFD_E_ARG, "NULL argument");
+    if (!ops->ctx) return fail(RBFFD_E_ARG, "the operators' context was destroyed");
+    RB_HIP(hipSetDevice(ops->ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    RB_HIP(hipMemcpyAsync(out, ops->pbinv, sizeof(float) * ops->npad * 64, hipMemcpyDeviceToDevice, s));
+    RB_HIP(hipStreamSynchronize(s));
+    return RBFFD_OK;
+}
+
 int rbffd_apply(rbffd_ctx *ctx, const rbffd_ops *ops, int which, const double *x, double *y,
                 void *hip_stream)
 {
@@ -313,7 +324,14 @@ int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, doubl
     KrylovResult res;
     int refine = 0;
     int st;
-    if (opts->precision == RBFFD_FP64)
+    if (opts->preconditioner != RBFFD_PREC_JACOBI && opts->preconditioner != RBFFD_PREC_BLOCK64)
+        return fail(RBFFD_E_ARG, "unknown preconditioner");
+    if (opts->preconditioner == RBFFD_PREC_BLOCK64 && opts->precision != RBFFD_FP64)
+        return fail(RBFFD_E_ARG, "the block preconditioner runs with RBFFD_FP64");
+    if (opts->preconditioner == RBFFD_PREC_BLOCK64)
+        st = bicgstab_block(ctx, ops->n, ops->q, cols_of(ops), ops->pval, ops->pbinv, rhs, x, opts->tol,
+                            opts->max_iter, &res, s);
+    else if (opts->precision == RBFFD_FP64)
         st = bicgstab(ctx, ops->n, ops->q, cols_of(ops), ops->pval, ops->pdinv, 1, rhs, x, opts->tol,
                       opts->max_iter, &res, s);
     else
@@ -446,6 +464,10 @@ int simple_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev,
         return fail(RBFFD_E_ARG, "unknown precision");
     if (opts->precision != RBFFD_FP64 && !ops->pval32)
         return fail(RBFFD_E_ARG, "operators were assembled without FP32 copies");
+    if (opts->preconditioner != RBFFD_PREC_JACOBI && opts->preconditioner != RBFFD_PREC_BLOCK64)
+        return fail(RBFFD_E_ARG, "unknown preconditioner");
+    if (opts->preconditioner == RBFFD_PREC_BLOCK64 && opts->precision != RBFFD_FP64)
+        return fail(RBFFD_E_ARG, "the block preconditioner runs with RBFFD_FP64");
     RB_HIP(hipSetDevice(ctx->device));
     rbffd_step_stats local{};
     int st = run_step(ctx, ops, u, u_prev, p, u_bc, p_bc, opts, stats ? stats : &local, (hipStream_t)hip_stream);

@@ -194,6 +194,77 @@ __global__ __launch_bounds__(64) void slice_offsets(const int32_t *__restrict__ 
         }
 }
 
+// Inverse of the 64x64 diagonal block of each 64-row slice of the
+// pressure-correction matrix (a block-Jacobi preconditioner whose blocks are
+// Morton-compact patches of 64 points): Gauss-Jordan elimination with partial
+// pivoting (largest |a|, ties to the lowest row) in LDS, one wavefront per
+// slice, one row per lane. Stored in FP32, column-major per block: entry
+// (row l, column j) at j*64 + l. Padding rows are identity rows. A block
+// whose pivot falls to 1e-13 max|block| or below keeps the Jacobi diagonal.
+__global__ __launch_bounds__(64) void block_inverse(const int32_t *__restrict__ col, const double *__restrict__ pval,
+                                                    int64_t n, int q, float *__restrict__ binv)
+{
+    __shared__ double A[64][65];
+    __shared__ double B[64][65];
+    const int l = threadIdx.x;
+    const int64_t sl = blockIdx.x;
+    const int64_t i = sl * 64 + l;
+    for (int j = 0; j < 64; ++j) {
+        A[l][j] = 0.0;
+        B[l][j] = (j == l) ? 1.0 : 0.0;
+    }
+    if (i < n) {
+        for (int a = 0; a < q; ++a) {
+            const int64_t slot = ell_at(i, a, q);
+            const int32_t c = col[slot];
+            if ((int64_t)(c >> 6) == sl) A[l][c & 63] += pval[slot];
+        }
+    } else {
+        A[l][l] = 1.0;
+    }
+    const double diag = A[l][l];
+    double amax = 0.0;
+    for (int j = 0; j < 64; ++j) amax = fmax(amax, fabs(A[l][j]));
+    amax = wave_max(amax);
+    __syncthreads();
+    bool singular = false;
+    for (int k = 0; k < 64; ++k) {
+        const double v = (l >= k) ? fabs(A[l][k]) : -1.0;
+        const double mx = wave_max(v);
+        if (!(mx > 1e-13 * amax)) {
+            singular = true;
+            break;
+        }
+        const uint64_t msk = __ballot(l >= k && v == mx);
+        const int p = msk ? (__ffsll((unsigned long long)msk) - 1) : k;
+        if (p != k) {
+            double t = A[k][l];
+            A[k][l] = A[p][l];
+            A[p][l] = t;
+            t = B[k][l];
+            B[k][l] = B[p][l];
+            B[p][l] = t;
+        }
+        __syncthreads();
+        const double inv = 1.0 / A[k][k];
+        __syncthreads();
+        A[k][l] *= inv;
+        B[k][l] *= inv;
+        __syncthreads();
+        if (l != k) {
+            const double f = A[l][k];
+            for (int j = 0; j < 64; ++j) {
+                A[l][j] -= f * A[k][j];
+                B[l][j] -= f * B[k][j];
+            }
+        }
+        __syncthreads();
+    }
+    float *out = binv + sl * 4096;
+    for (int j = 0; j < 64; ++j)
+        out[j * 64 + l] = singular ? ((j == l && diag != 0.0) ? (float)(1.0 / diag) : 0.0f) : (float)B[l][j];
+}
+
 template <typename T>
 int alloc_ops(rbffd_ops *ops, T **p, size_t count)
 {
@@ -250,6 +321,11 @@ int assemble_ops(rbffd_ctx *ctx, const rbffd_cloud *cloud, int q, int k, int phs
     else
         hipLaunchKernelGGL(poisson_rows<3>, dim3(gb), dim3(kBlock), 0, s, ops->col, ops->val, nnz, ops->kind,
                            ops->normal, ops->pin, n, q, ops->pval, ops->pdinv);
+    RB_HIP(hipGetLastError());
+
+    // block-Jacobi preconditioner of the pressure-correction matrix
+    RB_CHECK(alloc_ops(ops, &ops->pbinv, (size_t)npad * 64));
+    hipLaunchKernelGGL(block_inverse, dim3(nslices), dim3(64), 0, s, ops->col, ops->pval, n, q, ops->pbinv);
     RB_HIP(hipGetLastError());
 
     // boundary numbering

@@ -124,6 +124,8 @@ struct rbffd_ops {
     double *val = nullptr;              // [R][npad*q]  d/dx, d/dy, (d/dz), Laplacian
     double *pval = nullptr;             // [npad*q]     pressure-correction matrix
     double *pdinv = nullptr;            // [npad]       1 / diag(P)
+    float *pbinv = nullptr;             // [npad/64][64][64] inverse of each 64-row diagonal block of P
+                                        //              (FP32, column-major per block)
     float *pval32 = nullptr;            // [npad*q]     FP32 copy (RBFFD_FP32_IR)
     float *pdinv32 = nullptr;           // [npad]
     double *mval = nullptr;             // [npad*q]     momentum matrix (rebuilt per outer iteration)
@@ -228,6 +230,10 @@ struct KrylovResult {
     double relres[kMaxRhs] = {0, 0, 0};
     bool fp64_fallback = false;   // FP32 sweeps stalled; finished in FP64
 };
+// FP64 BiCGSTAB right-preconditioned by the inverses of the 64x64 diagonal
+// blocks of the 64-row slices (one right-hand side).
+int bicgstab_block(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, const float *binv,
+                   const double *b, double *x, double tol, int max_iter, KrylovResult *res, hipStream_t s);
 int bicgstab(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val,
              const double *dinv, int nrhs, const double *b, double *x, double tol, int max_iter,
              KrylovResult *res, hipStream_t s);

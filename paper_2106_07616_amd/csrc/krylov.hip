@@ -756,6 +756,144 @@ int bicgstab_t(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const T *val, const
     return RBFFD_OK;
 }
 
+// ---- BiCGSTAB with the block-Jacobi preconditioner (FP64, one right-hand side)
+// The preconditioner blocks are the 64-row slices, and a slice is one
+// wavefront, so z = M^-1 y is a wave-local 64x64 matrix-vector product: lane l
+// holds y_l, and z_l = sum_j Minv[l][j] y_j with y_j broadcast across the wave.
+// The row loops therefore run over whole slices (up to npad) so that every
+// lane takes part in the broadcasts; loads and stores stay within n.
+__device__ inline double bj_apply(const float *__restrict__ blk, double y, int lane)
+{
+    double z = 0.0;
+#pragma unroll 8
+    for (int j = 0; j < 64; ++j) z = fma((double)blk[j * 64 + lane], __shfl(y, j, 64), z);
+    return z;
+}
+
+// r = b - A x, r-hat = r, p = r, p-hat = M^-1 r; partials r.r and b.b
+__global__ __launch_bounds__(kKB) void kbj_init(int64_t n, int64_t np, int q, ColIdx col, const double *__restrict__ val,
+                                                const float *__restrict__ binv, const double *__restrict__ b,
+                                                const double *__restrict__ x, double *__restrict__ r,
+                                                double *__restrict__ rh, double *__restrict__ p,
+                                                double *__restrict__ ph, double *__restrict__ part)
+{
+    const int lane = threadIdx.x & 63;
+    double acc[2] = {0.0, 0.0};
+    const bool act[1] = {true};
+    for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < np; i += (int64_t)gridDim.x * kKB) {
+        double ri = 0.0;
+        if (i < n) {
+            double ax[1];
+            row_dot<double, double, 1>(i, q, col, val, x, 0, act, ax);
+            const double bi = b[i];
+            ri = bi - ax[0];
+            r[i] = ri;
+            rh[i] = ri;
+            p[i] = ri;
+            acc[0] += ri * ri;
+            acc[1] += bi * bi;
+        }
+        const double z = bj_apply(binv + (i >> 6) * 4096, ri, lane);
+        if (i < n) ph[i] = z;
+    }
+    double *ps[2] = {partial(part, P_RR, 0), partial(part, P_BB, 0)};
+    write_partials<2>(acc, ps);
+}
+
+// KS: alpha = rho / r-hat.v; s = r - alpha v; s-hat = M^-1 s; partials s.s, r-hat.s
+__global__ __launch_bounds__(kKB) void kbj_s(int64_t n, int64_t np, const float *__restrict__ binv,
+                                             const double *__restrict__ r, const double *__restrict__ rh,
+                                             const double *__restrict__ v, double *__restrict__ s,
+                                             double *__restrict__ sh, double *__restrict__ part, KState *__restrict__ st,
+                                             int nblk, int phase)
+{
+    double rv;
+    {
+        const double *ps[1] = {partial(part, P_RV, 0)};
+        sum_partials_n<1>(ps, nblk, &rv);
+    }
+    if (all_done<1>(st, phase)) return;
+    const KState stk = st[0];
+    const double alpha = (rv != 0.0) ? stk.rho / rv : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st[0].alpha = alpha;
+        st[0].restart = 0;
+        st[0].refresh = 0;
+        if (rv == 0.0) {
+            st[0].done_at = phase;
+            st[0].status = RBFFD_E_BREAKDOWN;
+        }
+    }
+    if (rv == 0.0) return;
+    const int lane = threadIdx.x & 63;
+    double acc[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < np; i += (int64_t)gridDim.x * kKB) {
+        double si = 0.0;
+        if (i < n) {
+            si = r[i] - alpha * v[i];
+            s[i] = si;
+            acc[0] += si * si;
+            acc[1] += rh[i] * si;
+        }
+        const double z = bj_apply(binv + (i >> 6) * 4096, si, lane);
+        if (i < n) sh[i] = z;
+    }
+    double *ps[2] = {partial(part, P_SS, 0), partial(part, P_RS, 0)};
+    write_partials<2>(acc, ps);
+}
+
+// KX: omega; x += alpha p-hat + omega s-hat; r = s - omega t; p = r + beta (p -
+// omega v); p-hat = M^-1 p; partial r.r (restart and beta as in k_x)
+__global__ __launch_bounds__(kKB) void kbj_x(int64_t n, int64_t np, const float *__restrict__ binv,
+                                             double *__restrict__ x, double *__restrict__ p, double *__restrict__ ph,
+                                             const double *__restrict__ s, const double *__restrict__ sh,
+                                             const double *__restrict__ t, const double *__restrict__ v,
+                                             double *__restrict__ r, double *__restrict__ rh,
+                                             double *__restrict__ part, KState *__restrict__ st, int nblk, int phase)
+{
+    double sums[5];
+    {
+        const double *ps[5] = {partial(part, P_TS, 0), partial(part, P_TT, 0), partial(part, P_RS, 0),
+                               partial(part, P_RT, 0), partial(part, P_SS, 0)};
+        sum_partials_n<5>(ps, nblk, sums);
+    }
+    if (all_done<1>(st, phase)) return;
+    const KState stk = st[0];
+    const double ts = sums[0], tt = sums[1], rs = sums[2], rt = sums[3], ssk = sums[4];
+    const double omega = (tt > 0.0) ? ts / tt : 0.0;
+    const double rho1 = rs - omega * rt;
+    const bool restart = fabs(rho1) < 1e-300 || fabs(rho1) < 1e-30 * ssk;
+    const double beta = (restart || omega == 0.0) ? 0.0 : (rho1 / stk.rho) * (stk.alpha / omega);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st[0].omega = omega;
+        st[0].iters = stk.iters + 1;
+        st[0].rho_next = rho1;
+        st[0].restart = restart;
+        if (omega == 0.0) {
+            st[0].done_at = phase;
+            st[0].status = RBFFD_E_BREAKDOWN;
+        }
+    }
+    const int lane = threadIdx.x & 63;
+    double srr = 0.0;
+    for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < np; i += (int64_t)gridDim.x * kKB) {
+        double pn = 0.0;
+        if (i < n) {
+            x[i] += stk.alpha * ph[i] + omega * sh[i];
+            const double ri = s[i] - omega * t[i];
+            r[i] = ri;
+            if (restart) rh[i] = ri;
+            pn = (beta == 0.0) ? ri : ri + beta * (p[i] - omega * v[i]);
+            p[i] = pn;
+            srr += ri * ri;
+        }
+        const double z = bj_apply(binv + (i >> 6) * 4096, pn, lane);
+        if (i < n) ph[i] = z;
+    }
+    double *ps[1] = {partial(part, P_RR, 0)};
+    write_partials<1>(&srr, ps);
+}
+
 // ---- batched BiCGSTAB (FP64, one right-hand side per system) ---------------
 // System j owns blocks [boff, boff + nblk); block b belongs to system bmap[b].
 // Partials live at part[kind * pstride + b], so every system reduces over its
@@ -1019,6 +1157,71 @@ static int bicgstab_once(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const dou
     case 3: return bicgstab_t<double, 3>(ctx, n, q, col, val, dinv, b, n, x, n, tol, max_iter, res, w, s);
     default: return fail(RBFFD_E_ARG, "nrhs must be 1..3");
     }
+}
+
+static int bicgstab_block_once(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, const float *binv,
+                               const double *b, double *x, double tol, int max_iter, KrylovResult *res,
+                               hipStream_t s)
+{
+    Work w;
+    RB_CHECK(get_work<double>(ctx, pad64(n), 1, &w));
+    double *pv = nullptr;   // unpreconditioned search direction
+    RB_CHECK(workspace(ctx, WS_MISC, sizeof(double) * pad64(n), (void **)&pv));
+    const int64_t np = pad64(n);
+    const int nblk = krylov_blocks(n);
+    const dim3 g(nblk), bl(kKB);
+    double *r = (double *)w.r, *rh = (double *)w.rh, *ph = (double *)w.ph, *v = (double *)w.v, *sv = (double *)w.s,
+           *sh = (double *)w.sh, *t = (double *)w.t;
+    const double tol2 = tol * tol;
+    RB_HIP(hipMemsetAsync(w.st, 0, sizeof(KState) * kMaxRhs, s));
+    hipLaunchKernelGGL(kbj_init, g, bl, 0, s, n, np, q, col, val, binv, b, x, r, rh, pv, ph, w.part);
+    RB_HIP(hipGetLastError());
+    KState *hst = nullptr;
+    RB_CHECK(host_scratch(ctx, kHostKrylov, sizeof(KState) * kMaxRhs, (void **)&hst));
+    int it = 0, chunk = 4, phase = 0;
+    bool finished = false;
+    while (!finished) {
+        const int todo = std::min(chunk, max_iter - it);
+        for (int c = 0; c < todo; ++c) {
+            hipLaunchKernelGGL((k_v<double, double, 1>), g, bl, 0, s, n, np, q, col, val, rh, ph, v, x, n, w.part,
+                               w.st, nblk, tol2, 0, ++phase);
+            hipLaunchKernelGGL(kbj_s, g, bl, 0, s, n, np, binv, r, rh, v, sv, sh, w.part, w.st, nblk, ++phase);
+            hipLaunchKernelGGL((k_t<double, double, 1>), g, bl, 0, s, n, np, q, col, val, x, n, ph, sv, sh, rh, t,
+                               w.part, w.st, nblk, tol2, ++phase);
+            hipLaunchKernelGGL(kbj_x, g, bl, 0, s, n, np, binv, x, pv, ph, sv, sh, t, v, r, rh, w.part, w.st, nblk,
+                               ++phase);
+        }
+        it += std::max(todo, 0);
+        hipLaunchKernelGGL((k_v<double, double, 1>), g, bl, 0, s, n, np, q, col, val, rh, ph, v, x, n, w.part, w.st,
+                           nblk, tol2, 1, ++phase);
+        RB_HIP(hipGetLastError());
+        RB_HIP(hipMemcpyAsync(hst, w.st, sizeof(KState) * kMaxRhs, hipMemcpyDeviceToHost, s));
+        RB_HIP(hipStreamSynchronize(s));
+        finished = hst[0].done_at != 0 || it >= max_iter;
+        chunk = std::min(chunk * 2, 32);
+    }
+    res->iters[0] = hst[0].iters;
+    res->status[0] = hst[0].done_at ? hst[0].status : RBFFD_E_NOCONV;
+    return RBFFD_OK;
+}
+
+int bicgstab_block(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, const float *binv,
+                   const double *b, double *x, double tol, int max_iter, KrylovResult *res, hipStream_t s)
+{
+    KrylovResult acc;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        const int left = max_iter - acc.iters[0];
+        KrylovResult r1;
+        RB_CHECK(bicgstab_block_once(ctx, n, q, col, val, binv, b, x, tol, std::max(left, 0), &r1, s));
+        acc.iters[0] += r1.iters[0];
+        acc.status[0] = r1.status[0];
+        double rr[kMaxRhs];
+        RB_CHECK(residual_norms(ctx, n, q, col, val, 1, b, x, rr, s));
+        acc.relres[0] = rr[0];
+        if (r1.status[0] != RBFFD_OK || left <= 0 || rr[0] <= 10.0 * tol) break;
+    }
+    *res = acc;
+    return RBFFD_OK;
 }
 
 // BiCGSTAB with up to two restarts from the true residual: when the recursive

@@ -372,7 +372,10 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
                                ops->pin, B.ut, mass, B.f);
         RB_HIP(hipMemsetAsync(B.pc, 0, vec, s));
         KrylovResult kp;
-        if (fp32)
+        if (o->preconditioner == RBFFD_PREC_BLOCK64)
+            RB_CHECK(bicgstab_block(ctx, n, q, cols_of(ops), ops->pval, ops->pbinv, B.f, B.pc, o->tol_krylov,
+                                    o->max_krylov, &kp, s));
+        else if (fp32)
             RB_CHECK(bicgstab_mixed(ctx, o->precision, n, q, cols_of(ops), ops->pval, ops->pval32, ops->pdinv32, ops->pdinv, 1, B.f,
                                       B.pc, o->tol_krylov, o->max_krylov, &kp, nullptr, s));
         else

@@ -105,7 +105,7 @@ def test_batched_rejects_bad_arguments(ctx, batch):
         R.poisson_solve_batched(ctx, [], [], [])
     L = R.lib()
     import ctypes as C
-    o = R.binding.KrylovOptsT(1e-8, 100, R.RBFFD_FP32_IR)
+    o = R.binding.KrylovOptsT(1e-8, 100, R.RBFFD_FP32_IR, 0)
     arr = C.c_void_p * 1
     x = torch.zeros(batch[0][1].n, dtype=torch.float64, device="cuda")
     st = L.poisson_solve_batched(ctx.handle, 1, arr(batch[0][2].ops.handle), arr(R.binding._ptr(x)),

@@ -364,3 +364,83 @@ def test_zero_iterations_report_noconv(ctx):
     st = R.poisson_solve(ctx, s.ops, b, x, tol=1e-10, max_iter=0, allow_noconv=True)
     assert st["status"] == -4 and st["iters"] == 0
     assert float(x.abs().max()) == 0.0
+
+
+def test_block_inverse_blocks(case):
+    """Each exported 64x64 block inverse times the diagonal block of the
+    pressure-correction matrix (from the exported CSR) is the identity, to FP32
+    accuracy scaled by the block's condition."""
+    name, c, k, ops_o, s = case
+    binv = s.ops.export_block_inverse().cpu().numpy().astype(np.float64)   # [nb, col j, row l]
+    col, val = s.ops.export_csr()
+    col = col.cpu().numpy()
+    pv = val[c.dim + 1].cpu().numpy()
+    n = c.n
+    worst = 0.0
+    for sl in range(binv.shape[0]):
+        lo = sl * 64
+        blk = np.eye(64)
+        for l in range(64):
+            i = lo + l
+            if i >= n:
+                continue
+            blk[l, :] = 0.0
+            for a in range(col.shape[1]):
+                j = col[i, a]
+                if lo <= j < lo + 64:
+                    blk[l, j - lo] = pv[i, a]
+        minv = binv[sl].T          # [row, col]
+        prod = minv @ blk
+        cond = np.linalg.cond(blk)
+        worst = max(worst, np.abs(prod - np.eye(64)).max() / max(cond, 1.0))
+    print(f"[block inverse] {name}: max |M^-1 B - I| / cond(B) = {worst:.1e}", flush=True)
+    assert worst <= 1e-5
+
+
+def test_poisson_block_preconditioner(case, ctx, orc):
+    """BiCGSTAB with the block-Jacobi preconditioner reaches the oracle's
+    solution in fewer iterations than Jacobi."""
+    name, c, k, ops_o, s = case
+    b = np.random.default_rng(3).standard_normal(c.n)
+    xo, _, rr_o, st_o = orc.bicgstab(ops_o.col, ops_o.pval, b, tol=1e-12, maxit=20000)
+    if st_o != 0:
+        pytest.xfail(f"the oracle's Jacobi-BiCGSTAB does not reach 1e-12 on this system (true relres {rr_o:.1e})")
+    bt = torch.tensor(b, device="cuda")
+    xj = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+    sj = R.poisson_solve(ctx, s.ops, bt, xj, tol=1e-10, max_iter=20000, allow_noconv=True)
+    xb = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+    sb = R.poisson_solve(ctx, s.ops, bt, xb, tol=1e-12, max_iter=20000, allow_noconv=True,
+                         preconditioner=R.RBFFD_PREC_BLOCK64)
+    xb2 = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+    sb2 = R.poisson_solve(ctx, s.ops, bt, xb2, tol=1e-10, max_iter=20000, allow_noconv=True,
+                          preconditioner=R.RBFFD_PREC_BLOCK64)
+    err = _relinf(xb.cpu().numpy(), xo)
+    print(f"[poisson block] {name}: iters at 1e-10 block {sb2['iters']} jacobi {sj['iters']}; at 1e-12 "
+          f"{sb['iters']} relres {sb['relres']:.1e} diff {err:.1e}", flush=True)
+    assert sb["relres"] <= max(1e-9, 10 * rr_o)
+    assert err <= 1e-8
+    assert sb2["iters"] <= sj["iters"]
+
+
+def test_simple_step_block_preconditioner(case, ctx, orc):
+    """The time step with the block-Jacobi pressure solve matches the oracle."""
+    name, c, k, ops_o, s = case
+    if "flow" not in c.meta:
+        pytest.skip("no flow")
+    vel, p = W.flow_fields(c, 0.0)
+    nu = c.meta.get("nu", 0.025)
+    dt = 0.02
+    ubc_np, pbc_np = W.flow_fields(c, dt)
+    kw = dict(tol_outer=0.0, tol_krylov=1e-13, max_outer=2, max_krylov=20000)
+    uo, _, po, sto = orc.simple_step(ops_o, vel, vel, p, ubc_np, 1.0, nu, dt, alpha=orc.BDF2, p_bc=pbc_np, **kw)
+    if sto["status"] != 0:
+        pytest.xfail("the oracle's Krylov solves hit their limit on this system (ill-conditioned Neumann rows)")
+    u = torch.tensor(vel, device="cuda")
+    pg = torch.tensor(p, device="cuda")
+    st = R.simple_step(ctx, s.ops, u, torch.tensor(vel, device="cuda"), pg, torch.tensor(ubc_np, device="cuda"),
+                       1.0, nu, dt, R.BDF2, p_bc=torch.tensor(pbc_np, device="cuda"),
+                       preconditioner=R.RBFFD_PREC_BLOCK64, **kw)
+    eu = _relinf(u.cpu().numpy(), uo)
+    ep = _relinf(pg.cpu().numpy(), po)
+    print(f"[step block] {name}: p iters {st['krylov_p']}/{sto['krylov_p']} du {eu:.1e} dp {ep:.1e}", flush=True)
+    assert eu <= 1e-8 and ep <= 1e-8
