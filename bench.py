@@ -197,12 +197,12 @@ def batch_bench(args):
             xs.append(x)
         return lat, its, xs
 
-    def batched():
+    def batched(pc=R.RBFFD_PREC_JACOBI):
         xs = [torch.zeros_like(b) for b in rhs]
         torch.cuda.synchronize()
         ta = time.perf_counter()
         st = R.poisson_solve_batched(ctx, [sv.ops for sv in solvers], rhs, xs, tol=tol, max_iter=20000,
-                                     allow_noconv=True)
+                                     allow_noconv=True, preconditioner=pc)
         torch.cuda.synchronize()
         return time.perf_counter() - ta, st, xs
 
@@ -210,6 +210,10 @@ def batch_bench(args):
     lat, its, xseq = sequential()
     batched()
     t_batch, stb, xb = batched()
+    batched(R.RBFFD_PREC_BLOCK64)
+    t_bj, stbj, xbj = batched(R.RBFFD_PREC_BLOCK64)
+    ok_bj = [j for j, s_ in enumerate(stbj) if s_["status"] == 0 and seq_status[j] == 0]
+    diff_bj = max((float((xbj[j] - xseq[j]).abs().max() / xseq[j].abs().max()) for j in ok_bj), default=None)
     t_seq = sum(lat)
     ok = [j for j, s_ in enumerate(stb) if s_["status"] == 0 and seq_status[j] == 0]
     diff = max((float((xb[j] - xseq[j]).abs().max() / xseq[j].abs().max()) for j in ok), default=None)
@@ -228,6 +232,7 @@ def batch_bench(args):
                                f"relative residual {tol:g}, batched", "instances": len(solvers), "points": npts},
         "batched": {"solves_per_s": round(len(solvers) / t_batch, 3), "wall_ms": round(t_batch * 1e3, 3),
                     "M_point_iters_per_s": round(point_iters / t_batch / 1e6, 1),
+                    "iters_median": int(np.median([s_["iters"] for s_ in stb])),
                     "converged": int(sum(s_["status"] == 0 for s_ in stb)),
                     "max_true_relres": float(max(s_["relres"] for s_ in stb))},
         "sequential_fp64": {"solves_per_s": round(len(solvers) / t_seq, 3), "wall_ms": round(t_seq * 1e3, 3),
@@ -235,7 +240,15 @@ def batch_bench(args):
                             "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
                             "iters_median": int(np.median(its)),
                             "converged": int(sum(st_ == 0 for st_ in seq_status))},
+        "batched_block_jacobi": {"solves_per_s": round(len(solvers) / t_bj, 3), "wall_ms": round(t_bj * 1e3, 3),
+                                 "M_point_iters_per_s": round(sum(c.n * s_["iters"] for (c, _), s_ in
+                                                                  zip(clouds, stbj)) / t_bj / 1e6, 1),
+                                 "iters_median": int(np.median([s_["iters"] for s_ in stbj])),
+                                 "converged": int(sum(s_["status"] == 0 for s_ in stbj)),
+                                 "max_true_relres": float(max(s_["relres"] for s_ in stbj)),
+                                 "max_rel_diff_vs_sequential": diff_bj},
         "speedup_batched_vs_sequential": round(t_seq / t_batch, 3),
+        "speedup_batched_block_jacobi_vs_sequential": round(t_seq / t_bj, 3),
         "max_rel_diff_batched_vs_sequential": diff,
         "stencils_and_assembly_ms": round(t_build * 1e3, 1),
     }
@@ -331,7 +344,36 @@ def serve_bench(args):
     seq["converged"] = int(conv)
     log(f"[serve] one at a time: {seq}")
 
-    # continuous batching
+    def continuous(pc):
+        return serve_continuous(args, R, ctx, reqs, arrivals, build, report, tol, pc)
+
+    cb = continuous(R.RBFFD_PREC_JACOBI)
+    log(f"[serve] continuous batching: {cb}")
+    cbj = continuous(R.RBFFD_PREC_BLOCK64)
+    log(f"[serve] continuous batching, block-Jacobi: {cbj}")
+    out = {
+        "metric": METRIC, "value": cb["solves_per_s"], "unit": "converged solves/s", "n_gpus": 1,
+        "steps": len(reqs) - warm, "warmup": warm, "ms_per_step": cb["mean_ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"Poisson-arrival stream of {len(reqs)} solve requests (first {warm} excluded): 70% 2D "
+                               "Kovasznay/holed squares 2k-200k points, 30% 3D Beltrami cubes 50k-500k points, "
+                               "k=2-4 (3D 2-3), q=2m; stencils + operators + pressure-correction solve to 1e-6 per "
+                               f"request; offered load {lam:.2f}/s = 0.7 x one-at-a-time closed-loop rate; "
+                               f"HBM budget 32 GiB; at most {args.serve_large_limit} solve(s) above "
+                               f"{args.serve_large_points} points in the batch at once", "requests": len(reqs)},
+        "continuous_batching": cb, "continuous_batching_block_jacobi": cbj, "one_at_a_time_fp64": seq,
+        "p99_latency_ratio_one_at_a_time_over_batched": round(seq["p99_ms"] / cb["p99_ms"], 3),
+        "p99_latency_ratio_one_at_a_time_over_batched_block_jacobi": round(seq["p99_ms"] / cbj["p99_ms"], 3),
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def serve_continuous(args, R, ctx, reqs, arrivals, build, report, tol, pc):
+    """Serve the arrival sequence with continuous batching (rbffd_server)."""
+    import torch
+
+    warm = min(args.serve_warmup, len(reqs))
     server = R.Server(ctx)
     lat, fin, iters, conv = [0.0] * len(reqs), [0.0] * len(reqs), [0] * len(reqs), 0
     live = {}
@@ -357,7 +399,7 @@ def serve_bench(args):
             try:
                 sv, b = build(j)
                 x = torch.zeros_like(b)
-                t = server.submit(sv.ops, b, x, tol=tol, max_iter=20000)
+                t = server.submit(sv.ops, b, x, tol=tol, max_iter=20000, preconditioner=pc)
             except R.RbffdError as e:
                 if e.code != -2:
                     raise
@@ -383,22 +425,7 @@ def serve_bench(args):
     cb = report(lat, fin, iters)
     cb["converged"] = int(conv)
     cb["peak_concurrent_solves"] = int(peak)
-    log(f"[serve] continuous batching: {cb}")
-    out = {
-        "metric": METRIC, "value": cb["solves_per_s"], "unit": "converged solves/s", "n_gpus": 1,
-        "steps": len(reqs) - warm, "warmup": warm, "ms_per_step": cb["mean_ms"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"Poisson-arrival stream of {len(reqs)} solve requests (first {warm} excluded): 70% 2D "
-                               "Kovasznay/holed squares 2k-200k points, 30% 3D Beltrami cubes 50k-500k points, "
-                               "k=2-4 (3D 2-3), q=2m; stencils + operators + pressure-correction solve to 1e-6 per "
-                               f"request; offered load {lam:.2f}/s = 0.7 x one-at-a-time closed-loop rate; "
-                               f"HBM budget 32 GiB; at most {args.serve_large_limit} solve(s) above "
-                               f"{args.serve_large_points} points in the batch at once", "requests": len(reqs)},
-        "continuous_batching": cb, "one_at_a_time_fp64": seq,
-        "p99_latency_ratio_one_at_a_time_over_batched": round(seq["p99_ms"] / cb["p99_ms"], 3),
-    }
-    ctx.close()
-    print(json.dumps(out), flush=True)
+    return cb
 
 
 def main():

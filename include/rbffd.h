@@ -166,7 +166,7 @@ typedef struct {
     double tol;             /* stop when ||b - A x||_2 <= tol ||b||_2 (recursive residual) */
     int max_iter;           /* BiCGSTAB iterations                                   */
     int precision;          /* RBFFD_FP64, RBFFD_FP32_IR or RBFFD_FP32_MATRIX        */
-    int preconditioner;     /* RBFFD_PREC_JACOBI or RBFFD_PREC_BLOCK64 (poisson_solve) */
+    int preconditioner;     /* RBFFD_PREC_JACOBI or RBFFD_PREC_BLOCK64 (FP64 only)   */
 } rbffd_krylov_opts;
 
 typedef struct {
@@ -188,15 +188,17 @@ int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, doubl
 
 /* (Sec. 3, "preconditioned BiCGSTAB"; the batched configuration of many
  * independent clouds) Solve P_j x_j = rhs_j for `count` independent
- * pressure-correction systems at once, each as poisson_solve would (right
- * Jacobi BiCGSTAB, FP64, restarts from the true residual). Every kernel stage
+ * pressure-correction systems at once, each as poisson_solve would (FP64
+ * BiCGSTAB, right-preconditioned by the Jacobi diagonal or the 64x64 diagonal
+ * blocks, restarts from the true residual). Every kernel stage
  * is one launch over all systems; each system owns a fixed range of thread
  * blocks and its own reductions, so its result is bitwise the same alone or
  * in any batch. Systems stop independently.
  *   ops, rhs, x: HOST arrays of `count` pointers; rhs[j], x[j] device [n_j];
  *                x[j] holds the initial guess on entry and the solution on
  *                return
- *   opts:        shared by all systems; precision must be RBFFD_FP64
+ *   opts:        shared by all systems; precision must be RBFFD_FP64,
+ *                preconditioner RBFFD_PREC_JACOBI or RBFFD_PREC_BLOCK64
  *   stats:       host array of `count` records (may be NULL)
  * Returns RBFFD_OK when every system converged, RBFFD_E_NOCONV or
  * RBFFD_E_BREAKDOWN (the first failing code) otherwise; per-system outcomes
@@ -210,18 +212,21 @@ int poisson_solve_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops
  * running batch of FP64 pressure-correction solves. Solves submitted while
  * others run join the batch at the next rbffd_server_run; finished ones leave
  * it and are collected with rbffd_server_poll. Each solve behaves as
- * poisson_solve (right-Jacobi BiCGSTAB, restarts from the true residual) and
- * its result does not depend on which other solves share the batch.
- * Work vectors (7 n doubles per solve) are charged to the context's HBM
+ * poisson_solve (FP64 BiCGSTAB with the Jacobi or block-Jacobi preconditioner,
+ * restarts from the true residual) and its result does not depend on which
+ * other solves share the batch.
+ * Work vectors (8 n doubles per solve) are charged to the context's HBM
  * budget at submission: RBFFD_E_OOM means "retry after some solves finish".
  * One server per context; calls on it must not overlap. */
 typedef struct rbffd_server rbffd_server;
 int rbffd_server_create(rbffd_ctx *ctx, rbffd_server **out);
 int rbffd_server_destroy(rbffd_server *sv);
 /* Queue a solve of P x = rhs (ops, rhs and x stay owned by the caller and must
- * outlive the solve; x holds the initial guess). *ticket identifies it. */
-int rbffd_server_submit(rbffd_server *sv, const rbffd_ops *ops, const double *rhs, double *x, double tol,
-                        int max_iter, int64_t *ticket);
+ * outlive the solve; x holds the initial guess). opts: tol, max_iter (>= 1),
+ * precision (RBFFD_FP64) and preconditioner, copied at submission.
+ * *ticket identifies the solve. */
+int rbffd_server_submit(rbffd_server *sv, const rbffd_ops *ops, const double *rhs, double *x,
+                        const rbffd_krylov_opts *opts, int64_t *ticket);
 /* Run up to `iterations` BiCGSTAB iterations on every queued or running solve
  * (synchronous on the stream); *active receives the number still running. */
 int rbffd_server_run(rbffd_server *sv, int iterations, int *active, void *hip_stream);

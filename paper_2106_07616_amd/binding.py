@@ -89,7 +89,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                         C.POINTER(KrylovStatsT), P]
     L.rbffd_server_create.argtypes = [P, C.POINTER(P)]
     L.rbffd_server_destroy.argtypes = [P]
-    L.rbffd_server_submit.argtypes = [P, P, P, P, D, I, C.POINTER(I64)]
+    L.rbffd_server_submit.argtypes = [P, P, P, P, C.POINTER(KrylovOptsT), C.POINTER(I64)]
     L.rbffd_server_run.argtypes = [P, I, C.POINTER(I), P]
     L.rbffd_server_poll.argtypes = [P, I, C.POINTER(I64), C.POINTER(KrylovStatsT), C.POINTER(I)]
     L.simple_step.argtypes = [P, P, P, P, P, P, P, C.POINTER(StepOptsT), C.POINTER(StepStatsT), P]
@@ -121,6 +121,18 @@ def _ptr(t: torch.Tensor | None):
     if not t.is_contiguous():
         raise ValueError("contiguous tensor expected")
     return C.c_void_p(t.data_ptr())
+
+
+def _f64(t: torch.Tensor | None, numel: int, what: str):
+    """Pointer to a contiguous FP64 device tensor of exactly `numel` entries:
+    the library takes raw pointers and trusts their extents."""
+    if t is None:
+        return None
+    if t.dtype != torch.float64:
+        raise ValueError(f"{what}: float64 tensor expected, got {t.dtype}")
+    if t.numel() != numel:
+        raise ValueError(f"{what}: {numel} entries expected, got {t.numel()}")
+    return _ptr(t)
 
 
 def _stream():
@@ -223,7 +235,7 @@ class Operators:
 
     def apply(self, which: int, x: torch.Tensor) -> torch.Tensor:
         y = torch.empty_like(x)
-        _check(lib().rbffd_apply(self.ctx.handle, self.handle, which, _ptr(x), _ptr(y), _stream()))
+        _check(lib().rbffd_apply(self.ctx.handle, self.handle, which, _f64(x, self.n, "x"), _ptr(y), _stream()))
         return y
 
     def free(self):
@@ -254,24 +266,27 @@ def poisson_solve(ctx: Context, ops: Operators, rhs: torch.Tensor, x: torch.Tens
                   preconditioner: int = RBFFD_PREC_JACOBI):
     o = KrylovOptsT(tol, max_iter, precision, preconditioner)
     s = KrylovStatsT()
-    st = lib().poisson_solve(ctx.handle, ops.handle, _ptr(rhs), _ptr(x), C.byref(o), C.byref(s), _stream())
+    st = lib().poisson_solve(ctx.handle, ops.handle, _f64(rhs, ops.n, "rhs"), _f64(x, ops.n, "x"), C.byref(o),
+                             C.byref(s), _stream())
     _check(st, allow=(RBFFD_E_NOCONV, RBFFD_E_BREAKDOWN) if allow_noconv else ())
     return dict(iters=s.iters, status=s.status, refinements=s.refinements, fp64_fallback=s.fp64_fallback,
                 relres=s.relres)
 
 
 def poisson_solve_batched(ctx: Context, ops: list, rhs: list, x: list, tol: float = 1e-10, max_iter: int = 5000,
-                          allow_noconv: bool = False):
+                          allow_noconv: bool = False, preconditioner: int = RBFFD_PREC_JACOBI):
     """FP64 pressure-correction solves of several independent systems in one
     batch; x[j] is updated in place. Returns one stats dict per system."""
     m = len(ops)
     if not (m == len(rhs) == len(x)) or m == 0:
         raise ValueError("ops, rhs and x must be non-empty lists of the same length")
     arr = C.c_void_p * m
-    o = KrylovOptsT(tol, max_iter, RBFFD_FP64, RBFFD_PREC_JACOBI)
+    o = KrylovOptsT(tol, max_iter, RBFFD_FP64, preconditioner)
     stats = (KrylovStatsT * m)()
-    st = lib().poisson_solve_batched(ctx.handle, m, arr(*[op.handle for op in ops]), arr(*[_ptr(t) for t in rhs]),
-                                     arr(*[_ptr(t) for t in x]), C.byref(o), stats, _stream())
+    rp = [_f64(t, op.n, f"rhs[{j}]") for j, (t, op) in enumerate(zip(rhs, ops))]
+    xp = [_f64(t, op.n, f"x[{j}]") for j, (t, op) in enumerate(zip(x, ops))]
+    st = lib().poisson_solve_batched(ctx.handle, m, arr(*[op.handle for op in ops]), arr(*rp), arr(*xp),
+                                     C.byref(o), stats, _stream())
     _check(st, allow=(RBFFD_E_NOCONV, RBFFD_E_BREAKDOWN) if allow_noconv else ())
     return [dict(iters=s_.iters, status=s_.status, relres=s_.relres) for s_ in stats]
 
@@ -287,9 +302,11 @@ class Server:
         self._keep = {}   # ticket -> tensors that must outlive the solve
 
     def submit(self, ops: Operators, rhs: torch.Tensor, x: torch.Tensor, tol: float = 1e-6,
-               max_iter: int = 20000) -> int:
+               max_iter: int = 20000, preconditioner: int = RBFFD_PREC_JACOBI) -> int:
         t = C.c_int64()
-        _check(lib().rbffd_server_submit(self.handle, ops.handle, _ptr(rhs), _ptr(x), tol, max_iter, C.byref(t)))
+        o = KrylovOptsT(tol, max_iter, RBFFD_FP64, preconditioner)
+        _check(lib().rbffd_server_submit(self.handle, ops.handle, _f64(rhs, ops.n, "rhs"), _f64(x, ops.n, "x"),
+                                         C.byref(o), C.byref(t)))
         self._keep[t.value] = (ops, rhs, x)
         return t.value
 
@@ -330,8 +347,9 @@ def simple_step(ctx: Context, ops: Operators, u: torch.Tensor, u_prev: torch.Ten
     o = StepOptsT(rho, mu, dt, (C.c_double * 3)(*alpha), tol_outer, tol_krylov, max_outer, max_krylov, precision,
                   preconditioner)
     s = StepStatsT()
-    st = lib().simple_step(ctx.handle, ops.handle, _ptr(u), _ptr(u_prev), _ptr(p), _ptr(u_bc), _ptr(p_bc),
-                           C.byref(o), C.byref(s), _stream())
+    dn = ops.dim * ops.n
+    st = lib().simple_step(ctx.handle, ops.handle, _f64(u, dn, "u"), _f64(u_prev, dn, "u_prev"), _f64(p, ops.n, "p"),
+                           _f64(u_bc, dn, "u_bc"), _f64(p_bc, ops.n, "p_bc"), C.byref(o), C.byref(s), _stream())
     _check(st, allow=(RBFFD_E_NOCONV,))
     return dict(outer_iters=s.outer_iters, krylov_mom=s.krylov_mom, krylov_p=s.krylov_p, krylov_b=s.krylov_b,
                 status=s.status, delta=s.delta, eps_steady=s.eps_steady)

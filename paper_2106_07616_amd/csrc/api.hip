@@ -361,12 +361,16 @@ int poisson_solve_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops
     if (count < 1) return fail(RBFFD_E_ARG, "count must be >= 1");
     if (!(opts->tol >= 0.0) || opts->max_iter < 0) return fail(RBFFD_E_ARG, "bad Krylov options");
     if (opts->precision != RBFFD_FP64) return fail(RBFFD_E_ARG, "batched solves run in FP64");
+    if (opts->preconditioner != RBFFD_PREC_JACOBI && opts->preconditioner != RBFFD_PREC_BLOCK64)
+        return fail(RBFFD_E_ARG, "unknown preconditioner");
+    const bool block = opts->preconditioner == RBFFD_PREC_BLOCK64;
     std::vector<BatchSystem> sys((size_t)count);
     for (int j = 0; j < count; ++j) {
         if (!ops[j] || !rhs[j] || !x[j])
             return fail(RBFFD_E_ARG, "NULL operator, right-hand side or solution of system " + std::to_string(j));
         if (!ops[j]->ctx) return fail(RBFFD_E_ARG, "the operators' context was destroyed");
-        sys[j] = BatchSystem{ops[j]->n, ops[j]->q, cols_of(ops[j]), ops[j]->pval, ops[j]->pdinv, rhs[j], x[j]};
+        sys[j] = BatchSystem{ops[j]->n, ops[j]->q, cols_of(ops[j]), ops[j]->pval, ops[j]->pdinv, rhs[j], x[j],
+                             block ? ops[j]->pbinv : nullptr};
     }
     RB_HIP(hipSetDevice(ctx->device));
     std::vector<int> iters((size_t)count), status((size_t)count);
@@ -410,16 +414,20 @@ int rbffd_server_destroy(rbffd_server *sv)
     return RBFFD_OK;
 }
 
-int rbffd_server_submit(rbffd_server *sv, const rbffd_ops *ops, const double *rhs, double *x, double tol,
-                        int max_iter, int64_t *ticket)
+int rbffd_server_submit(rbffd_server *sv, const rbffd_ops *ops, const double *rhs, double *x,
+                        const rbffd_krylov_opts *opts, int64_t *ticket)
 {
-    if (!sv || !ops || !rhs || !x || !ticket) return fail(RBFFD_E_ARG, "NULL argument");
+    if (!sv || !ops || !rhs || !x || !opts || !ticket) return fail(RBFFD_E_ARG, "NULL argument");
     if (!sv->impl) return fail(RBFFD_E_ARG, "the server's context was destroyed");
     if (!ops->ctx) return fail(RBFFD_E_ARG, "the operators' context was destroyed");
-    if (!(tol >= 0.0) || max_iter < 1) return fail(RBFFD_E_ARG, "bad Krylov options");
+    if (!(opts->tol >= 0.0) || opts->max_iter < 1) return fail(RBFFD_E_ARG, "bad Krylov options");
+    if (opts->precision != RBFFD_FP64) return fail(RBFFD_E_ARG, "served solves run in FP64");
+    if (opts->preconditioner != RBFFD_PREC_JACOBI && opts->preconditioner != RBFFD_PREC_BLOCK64)
+        return fail(RBFFD_E_ARG, "unknown preconditioner");
     RB_HIP(hipSetDevice(sv->ctx->device));
-    const BatchSystem sys{ops->n, ops->q, cols_of(ops), ops->pval, ops->pdinv, rhs, x};
-    return server_submit(sv->impl, sys, tol, max_iter, ticket);
+    const BatchSystem sys{ops->n, ops->q, cols_of(ops), ops->pval, ops->pdinv, rhs, x,
+                          opts->preconditioner == RBFFD_PREC_BLOCK64 ? ops->pbinv : nullptr};
+    return server_submit(sv->impl, sys, opts->tol, opts->max_iter, ticket);
 }
 
 int rbffd_server_run(rbffd_server *sv, int iterations, int *active, void *hip_stream)

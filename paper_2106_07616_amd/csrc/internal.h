@@ -249,6 +249,7 @@ struct BatchSystem {
     ColIdx col;
     const double *val, *dinv, *b;
     double *x;
+    const float *binv;   // block-Jacobi inverses, or nullptr for Jacobi
 };
 // FP64 BiCGSTAB on many independent systems at once: every kernel stage is one
 // launch over all systems, each system owns a fixed range of blocks and its own

@@ -897,16 +897,21 @@ __global__ __launch_bounds__(kKB) void kbj_x(int64_t n, int64_t np, const float 
 // ---- batched BiCGSTAB (FP64, one right-hand side per system) ---------------
 // System j owns blocks [boff, boff + nblk); block b belongs to system bmap[b].
 // Partials live at part[kind * pstride + b], so every system reduces over its
-// own blocks in block order.
+// own blocks in block order. A system with block inverses (binv) is
+// preconditioned by them and keeps its unpreconditioned direction in p; its
+// row loops run over whole 64-row slices (a block's first row and its stride
+// are multiples of 64, so each wavefront holds one slice).
 struct BSys {
     int64_t n, np;
     int q, boff, nblk, pad;
     double tol2;
     ColIdx col;
     const double *val, *dinv, *b;
+    const float *binv;
     double *x;
-    double *r, *rh, *ph, *v, *s, *sh, *t;
+    double *r, *rh, *ph, *v, *s, *sh, *t, *p;
 };
+constexpr int kBatchVecs = 8;   // work vectors per system: r r-hat p-hat v s s-hat t p
 
 __device__ inline const double *bpart(const double *part, int kind, int pstride, int boff)
 {
@@ -920,18 +925,31 @@ __global__ __launch_bounds__(kKB) void kb_init(const BSys *__restrict__ sys, con
     const BSys S = sys[j];
     if (!st[j].fresh) return;
     const int lb = blockIdx.x - S.boff;
+    const bool bj = S.binv != nullptr;
+    const int64_t lim = bj ? S.np : S.n;
+    const int lane = threadIdx.x & 63;
     double rr = 0.0, bb = 0.0;
     const bool act[1] = {true};
-    for (int64_t i = (int64_t)lb * kKB + threadIdx.x; i < S.n; i += (int64_t)S.nblk * kKB) {
-        double ax[1];
-        row_dot<double, double, 1>(i, S.q, S.col, S.val, S.x, 0, act, ax);
-        const double bi = S.b[i];
-        const double ri = bi - ax[0];
-        S.r[i] = ri;
-        S.rh[i] = ri;
-        S.ph[i] = S.dinv[i] * ri;
-        rr += ri * ri;
-        bb += bi * bi;
+    for (int64_t i = (int64_t)lb * kKB + threadIdx.x; i < lim; i += (int64_t)S.nblk * kKB) {
+        double ri = 0.0;
+        if (i < S.n) {
+            double ax[1];
+            row_dot<double, double, 1>(i, S.q, S.col, S.val, S.x, 0, act, ax);
+            const double bi = S.b[i];
+            ri = bi - ax[0];
+            S.r[i] = ri;
+            S.rh[i] = ri;
+            if (bj)
+                S.p[i] = ri;
+            else
+                S.ph[i] = S.dinv[i] * ri;
+            rr += ri * ri;
+            bb += bi * bi;
+        }
+        if (bj) {
+            const double z = bj_apply(S.binv + (i >> 6) * 4096, ri, lane);
+            if (i < S.n) S.ph[i] = z;
+        }
     }
     const double acc[2] = {rr, bb};
     double *ps[2] = {part + (int64_t)P_RR * pstride, part + (int64_t)P_BB * pstride};
@@ -1010,13 +1028,23 @@ __global__ __launch_bounds__(kKB) void kb_s(const BSys *__restrict__ sys, const 
     }
     if (rv == 0.0) return;
     const int lb = blockIdx.x - S.boff;
+    const bool bj = S.binv != nullptr;
+    const int64_t lim = bj ? S.np : S.n;
+    const int lane = threadIdx.x & 63;
     double acc[2] = {0.0, 0.0};
-    for (int64_t i = (int64_t)lb * kKB + threadIdx.x; i < S.n; i += (int64_t)S.nblk * kKB) {
-        const double si = S.r[i] - alpha * S.v[i];
-        S.s[i] = si;
-        S.sh[i] = S.dinv[i] * si;
-        acc[0] += si * si;
-        acc[1] += S.rh[i] * si;
+    for (int64_t i = (int64_t)lb * kKB + threadIdx.x; i < lim; i += (int64_t)S.nblk * kKB) {
+        double si = 0.0;
+        if (i < S.n) {
+            si = S.r[i] - alpha * S.v[i];
+            S.s[i] = si;
+            if (!bj) S.sh[i] = S.dinv[i] * si;
+            acc[0] += si * si;
+            acc[1] += S.rh[i] * si;
+        }
+        if (bj) {
+            const double z = bj_apply(S.binv + (i >> 6) * 4096, si, lane);
+            if (i < S.n) S.sh[i] = z;
+        }
     }
     double *ps[2] = {part + (int64_t)P_SS * pstride, part + (int64_t)P_RS * pstride};
     write_partials<2>(acc, ps);
@@ -1091,15 +1119,34 @@ __global__ __launch_bounds__(kKB) void kb_x(const BSys *__restrict__ sys, const 
     }
     const int lb = blockIdx.x - S.boff;
     double srr = 0.0;
-    for (int64_t i = (int64_t)lb * kKB + threadIdx.x; i < S.n; i += (int64_t)S.nblk * kKB) {
-        const double di = S.dinv[i];
-        const double phi = S.ph[i];
-        S.x[i] += k0.alpha * phi + omega * S.sh[i];
-        const double ri = S.s[i] - omega * S.t[i];
-        S.r[i] = ri;
-        if (restart) S.rh[i] = ri;
-        S.ph[i] = (beta == 0.0) ? di * ri : di * ri + beta * (phi - omega * (di * S.v[i]));
-        srr += ri * ri;
+    if (S.binv == nullptr) {
+        for (int64_t i = (int64_t)lb * kKB + threadIdx.x; i < S.n; i += (int64_t)S.nblk * kKB) {
+            const double di = S.dinv[i];
+            const double phi = S.ph[i];
+            S.x[i] += k0.alpha * phi + omega * S.sh[i];
+            const double ri = S.s[i] - omega * S.t[i];
+            S.r[i] = ri;
+            if (restart) S.rh[i] = ri;
+            S.ph[i] = (beta == 0.0) ? di * ri : di * ri + beta * (phi - omega * (di * S.v[i]));
+            srr += ri * ri;
+        }
+    } else {
+        // p = r + beta (p - omega v), p-hat = M^-1 p over whole slices
+        const int lane = threadIdx.x & 63;
+        for (int64_t i = (int64_t)lb * kKB + threadIdx.x; i < S.np; i += (int64_t)S.nblk * kKB) {
+            double pn = 0.0;
+            if (i < S.n) {
+                S.x[i] += k0.alpha * S.ph[i] + omega * S.sh[i];
+                const double ri = S.s[i] - omega * S.t[i];
+                S.r[i] = ri;
+                if (restart) S.rh[i] = ri;
+                pn = (beta == 0.0) ? ri : ri + beta * (S.p[i] - omega * S.v[i]);
+                S.p[i] = pn;
+                srr += ri * ri;
+            }
+            const double z = bj_apply(S.binv + (i >> 6) * 4096, pn, lane);
+            if (i < S.n) S.ph[i] = z;
+        }
     }
     double *ps[1] = {part + (int64_t)P_RR * pstride};
     write_partials<1>(&srr, ps);
@@ -1486,7 +1533,7 @@ int bicgstab_batched(rbffd_ctx *ctx, int count, const BatchSystem *sys, double t
     const int pstride = (int)total;
     // device: descriptors | block map | states | partials | 7 vectors per system
     const size_t dsz = sizeof(BSys) * count, msz = sizeof(int) * total, ssz = sizeof(KState) * count;
-    const size_t psz = sizeof(double) * P_COUNT * total, vsz = sizeof(double) * 7 * vec;
+    const size_t psz = sizeof(double) * P_COUNT * total, vsz = sizeof(double) * kBatchVecs * vec;
     const size_t o1 = (dsz + 255) / 256 * 256, o2 = o1 + (msz + 255) / 256 * 256, o3 = o2 + (ssz + 255) / 256 * 256,
                  o4 = o3 + (psz + 255) / 256 * 256, dtot = o4 + vsz + (size_t)count * sizeof(double) + 256;
     char *dev = nullptr;
@@ -1496,7 +1543,7 @@ int bicgstab_batched(rbffd_ctx *ctx, int count, const BatchSystem *sys, double t
     KState *dst = (KState *)(dev + o2);
     double *part = (double *)(dev + o3);
     double *vecs = (double *)(dev + o4);
-    double *dout = vecs + 7 * vec;
+    double *dout = vecs + kBatchVecs * vec;
     // pinned host staging: descriptors | block map | states | residuals
     const size_t htot = o3 + (size_t)count * sizeof(double) + 256;
     char *host = nullptr;
@@ -1518,9 +1565,10 @@ int bicgstab_batched(rbffd_ctx *ctx, int count, const BatchSystem *sys, double t
         B.col = sys[j].col;
         B.val = sys[j].val;
         B.dinv = sys[j].dinv;
+        B.binv = sys[j].binv;
         B.b = sys[j].b;
         B.x = sys[j].x;
-        double *base = vecs + 7 * voff;
+        double *base = vecs + kBatchVecs * voff;
         B.r = base;
         B.rh = base + B.np;
         B.ph = base + 2 * B.np;
@@ -1528,6 +1576,7 @@ int bicgstab_batched(rbffd_ctx *ctx, int count, const BatchSystem *sys, double t
         B.s = base + 4 * B.np;
         B.sh = base + 5 * B.np;
         B.t = base + 6 * B.np;
+        B.p = base + 7 * B.np;
         voff += B.np;
         for (int b = 0; b < nblk[j]; ++b) hmap[boff[j] + b] = j;
     }
@@ -1669,7 +1718,7 @@ int server_submit(Server *sv, const BatchSystem &sys, double tol, int max_iter, 
     a.sys = sys;
     a.tol = tol;
     a.max_iter = max_iter;
-    a.vbytes = sizeof(double) * 7 * pad64(sys.n);
+    a.vbytes = sizeof(double) * kBatchVecs * pad64(sys.n);
     RB_CHECK(dev_alloc(sv->ctx, (void **)&a.vec, a.vbytes));
     a.ticket = sv->next_ticket++;
     a.st = KState{};
@@ -1738,6 +1787,7 @@ static int server_layout(Server *sv, hipStream_t s)
         B.col = a.sys.col;
         B.val = a.sys.val;
         B.dinv = a.sys.dinv;
+        B.binv = a.sys.binv;
         B.b = a.sys.b;
         B.x = a.sys.x;
         B.r = a.vec;
@@ -1747,6 +1797,7 @@ static int server_layout(Server *sv, hipStream_t s)
         B.s = a.vec + 4 * B.np;
         B.sh = a.vec + 5 * B.np;
         B.t = a.vec + 6 * B.np;
+        B.p = a.vec + 7 * B.np;
         for (int b = 0; b < nblk[j]; ++b) sv->hmap[boff[j] + b] = j;
         KState k = a.st;
         if (!k.fresh) k.moved = 1;

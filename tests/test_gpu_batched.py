@@ -1,5 +1,6 @@
 """Batched pressure-correction solves through the C ABI: each system of a batch
-matches the FP64 oracle, and is bitwise the same alone and in the mix."""
+matches the FP64 oracle, and is bitwise the same alone and in the mix, with the
+Jacobi and with the block-Jacobi preconditioner."""
 import numpy as np
 import pytest
 
@@ -43,20 +44,24 @@ def batch(ctx, orc):
     return out
 
 
-def _solve(ctx, items, tol):
+PCS = {"jacobi": R.RBFFD_PREC_JACOBI, "block64": R.RBFFD_PREC_BLOCK64}
+
+
+def _solve(ctx, items, tol, pc=R.RBFFD_PREC_JACOBI):
     xs = [torch.zeros(it[1].n, dtype=torch.float64, device="cuda") for it in items]
     rhs = [torch.tensor(it[4], device="cuda") for it in items]
     st = R.poisson_solve_batched(ctx, [it[2].ops for it in items], rhs, xs, tol=tol, max_iter=20000,
-                                 allow_noconv=True)
+                                 allow_noconv=True, preconditioner=pc)
     return [x.cpu().numpy() for x in xs], st
 
 
-def test_batched_matches_oracle(ctx, orc, batch):
-    xs, st = _solve(ctx, batch, 1e-12)
+@pytest.mark.parametrize("pc", sorted(PCS))
+def test_batched_matches_oracle(ctx, orc, batch, pc):
+    xs, st = _solve(ctx, batch, 1e-12, PCS[pc])
     for (name, c, s, ops_o, b), x, sj in zip(batch, xs, st):
         xo, _, rr_o, st_o = orc.bicgstab(ops_o.col, ops_o.pval, b, tol=1e-12, maxit=20000)
         err = float(np.abs(x - xo).max() / np.abs(xo).max())
-        print(f"[batch] {name}: iters {sj['iters']} status {sj['status']} relres {sj['relres']:.1e} "
+        print(f"[batch {pc}] {name}: iters {sj['iters']} status {sj['status']} relres {sj['relres']:.1e} "
               f"oracle status {st_o} diff {err:.1e}", flush=True)
         if st_o != 0:
             continue
@@ -66,12 +71,25 @@ def test_batched_matches_oracle(ctx, orc, batch):
         assert err <= 1e-8
 
 
-def test_batched_alone_equals_in_mix(ctx, batch):
-    xs, st = _solve(ctx, batch, 1e-10)
+@pytest.mark.parametrize("pc", sorted(PCS))
+def test_batched_alone_equals_in_mix(ctx, batch, pc):
+    xs, st = _solve(ctx, batch, 1e-10, PCS[pc])
     for j, item in enumerate(batch):
-        x1, st1 = _solve(ctx, [item], 1e-10)
+        x1, st1 = _solve(ctx, [item], 1e-10, PCS[pc])
         assert st1[0]["iters"] == st[j]["iters"]
         np.testing.assert_array_equal(x1[0], xs[j])
+
+
+def test_batched_block_needs_fewer_iterations(ctx, batch):
+    """The block-Jacobi preconditioner takes no more iterations than Jacobi on
+    any system of the batch (fewer on the 2D ones)."""
+    _, sj = _solve(ctx, batch, 1e-10, R.RBFFD_PREC_JACOBI)
+    _, sb = _solve(ctx, batch, 1e-10, R.RBFFD_PREC_BLOCK64)
+    for it, a, b in zip(batch, sj, sb):
+        print(f"[batch] {it[0]}: iterations jacobi {a['iters']} block {b['iters']}", flush=True)
+        if a["status"] == 0:
+            assert b["status"] == 0 and b["iters"] <= a["iters"]
+    assert sum(b["iters"] for b in sb) < sum(a["iters"] for a in sj)
 
 
 def test_batched_zero_rhs_and_order(ctx, batch):
@@ -85,18 +103,20 @@ def test_batched_zero_rhs_and_order(ctx, batch):
         np.testing.assert_array_equal(a, b_)
 
 
-def test_batched_large_system_matches_single_solve(ctx):
+@pytest.mark.parametrize("pc", sorted(PCS))
+def test_batched_large_system_matches_single_solve(ctx, pc):
     """A system with more rows than 1024 blocks of 512 threads (rows looped per
     thread) agrees with the single-system solver."""
     c = W.beltrami_cube(n=82)
     s = R.Solver(ctx, c, 2)
     b = torch.tensor(np.random.default_rng(7).standard_normal(c.n), device="cuda")
     x1 = torch.zeros(c.n, dtype=torch.float64, device="cuda")
-    R.poisson_solve(ctx, s.ops, b, x1, tol=1e-10, max_iter=20000)
+    R.poisson_solve(ctx, s.ops, b, x1, tol=1e-10, max_iter=20000, preconditioner=PCS[pc])
     x2 = torch.zeros(c.n, dtype=torch.float64, device="cuda")
-    st = R.poisson_solve_batched(ctx, [s.ops], [b], [x2], tol=1e-10, max_iter=20000)
+    st = R.poisson_solve_batched(ctx, [s.ops], [b], [x2], tol=1e-10, max_iter=20000, preconditioner=PCS[pc])
     err = float((x1 - x2).abs().max() / x1.abs().max())
-    print(f"[batch] cube82 n={c.n}: iters {st[0]['iters']} relres {st[0]['relres']:.1e} diff {err:.1e}", flush=True)
+    print(f"[batch {pc}] cube82 n={c.n}: iters {st[0]['iters']} relres {st[0]['relres']:.1e} diff {err:.1e}",
+          flush=True)
     assert st[0]["status"] == 0 and err <= 1e-8
 
 
@@ -105,21 +125,26 @@ def test_batched_rejects_bad_arguments(ctx, batch):
         R.poisson_solve_batched(ctx, [], [], [])
     L = R.lib()
     import ctypes as C
-    o = R.binding.KrylovOptsT(1e-8, 100, R.RBFFD_FP32_IR, 0)
     arr = C.c_void_p * 1
     x = torch.zeros(batch[0][1].n, dtype=torch.float64, device="cuda")
-    st = L.poisson_solve_batched(ctx.handle, 1, arr(batch[0][2].ops.handle), arr(R.binding._ptr(x)),
-                                 arr(R.binding._ptr(x)), C.byref(o), None, R.binding._stream())
-    assert st == -1
+    for prec, pc in ((R.RBFFD_FP32_IR, 0), (R.RBFFD_FP64, 7)):     # mixed precision; unknown preconditioner
+        o = R.binding.KrylovOptsT(1e-8, 100, prec, pc)
+        st = L.poisson_solve_batched(ctx.handle, 1, arr(batch[0][2].ops.handle), arr(R.binding._ptr(x)),
+                                     arr(R.binding._ptr(x)), C.byref(o), None, R.binding._stream())
+        assert st == -1
+    with pytest.raises(ValueError):     # extents are checked before the call
+        R.poisson_solve_batched(ctx, [batch[0][2].ops], [x[:-1]], [x])
 
 
 def test_server_staggered_equals_alone(ctx, batch):
-    """Continuous batching: solves joining a running batch at different times
-    give bitwise the results of each solve alone."""
+    """Continuous batching: solves joining a running batch at different times,
+    alternately with the Jacobi and the block-Jacobi preconditioner, give
+    bitwise the results of each solve alone."""
     items = batch[:5]
+    pcs = [R.RBFFD_PREC_JACOBI if j % 2 == 0 else R.RBFFD_PREC_BLOCK64 for j in range(len(items))]
     alone, st_alone = [], []
-    for it in items:
-        x1, s1 = _solve(ctx, [it], 1e-10)
+    for it, pc in zip(items, pcs):
+        x1, s1 = _solve(ctx, [it], 1e-10, pc)
         alone.append(x1[0])
         st_alone.append(s1[0])
     sv = R.Server(ctx)
@@ -128,7 +153,7 @@ def test_server_staggered_equals_alone(ctx, batch):
     done = {}
     for j, it in enumerate(items):
         x = torch.zeros(it[1].n, dtype=torch.float64, device="cuda")
-        t = sv.submit(it[2].ops, rhs[j], x, tol=1e-10, max_iter=20000)
+        t = sv.submit(it[2].ops, rhs[j], x, tol=1e-10, max_iter=20000, preconditioner=pcs[j])
         xs[t], tickets[t] = x, j
         sv.run(8 + 5 * j)          # others keep running while the next one arrives
         for t2, st in sv.poll():
