@@ -567,9 +567,13 @@ def main():
     solves32m = timed_solves(R.RBFFD_FP32_MATRIX, args.solve_reps)
     timed_solves(R.RBFFD_FP64, 1, R.RBFFD_PREC_BLOCK64)
     solves64b = timed_solves(R.RBFFD_FP64, args.solve_reps, R.RBFFD_PREC_BLOCK64)
+    timed_solves(R.RBFFD_FP32_IR, 1, R.RBFFD_PREC_BLOCK64)
+    solves32b = timed_solves(R.RBFFD_FP32_IR, args.solve_reps, R.RBFFD_PREC_BLOCK64)
+    timed_solves(R.RBFFD_FP32_MATRIX, 1, R.RBFFD_PREC_BLOCK64)
+    solves32mb = timed_solves(R.RBFFD_FP32_MATRIX, args.solve_reps, R.RBFFD_PREC_BLOCK64)
     ops_mixed.free()
     log(f"[bench] solves at 1e-6: fp64 {solves64}  fp32 {solves32}  fp32 matrix {solves32m}  "
-        f"fp64 block-Jacobi {solves64b}")
+        f"fp64 block-Jacobi {solves64b}  fp32 block-Jacobi {solves32b}  fp32 matrix block-Jacobi {solves32mb}")
 
     # ---- the benchmark step ---------------------------------------------------
     phase_s = {"stencils": 0.0, "assemble": 0.0, "time_step": 0.0}
@@ -668,12 +672,15 @@ def main():
             "fp32_vectors_and_matrix": solves32,
             "fp32_matrix_fp64_vectors": solves32m,
             "fp64_block_jacobi": solves64b,
-            "speedup_vs_fp64": {"fp32_vectors_and_matrix": round(solves32["solves_per_s"] / solves64["solves_per_s"], 3),
-                                "fp32_matrix_fp64_vectors": round(solves32m["solves_per_s"] / solves64["solves_per_s"], 3),
-                                "fp64_block_jacobi": round(solves64b["solves_per_s"] / solves64["solves_per_s"], 3)},
+            "fp32_vectors_and_matrix_block_jacobi": solves32b,
+            "fp32_matrix_fp64_vectors_block_jacobi": solves32mb,
+            "speedup_vs_fp64": {k_: round(v_["solves_per_s"] / solves64["solves_per_s"], 3) for k_, v_ in (
+                ("fp32_vectors_and_matrix", solves32), ("fp32_matrix_fp64_vectors", solves32m),
+                ("fp64_block_jacobi", solves64b), ("fp32_vectors_and_matrix_block_jacobi", solves32b),
+                ("fp32_matrix_fp64_vectors_block_jacobi", solves32mb))},
             "note": "both mixed modes: FP64 row and dot accumulation, FP64 reliable residual updates; "
-                    "fp64 and the mixed modes use the Jacobi preconditioner, fp64_block_jacobi the inverses "
-                    "of the 64x64 diagonal blocks",
+                    "entries without a suffix use the Jacobi preconditioner, *_block_jacobi the FP32 inverses "
+                    "of the 64x64 diagonal blocks; speedups against fp64 with Jacobi",
         },
     }
     if args.mixed_step:
@@ -685,7 +692,8 @@ def main():
         for name, prec, pc in (("fp64", R.RBFFD_FP64, R.RBFFD_PREC_JACOBI),
                                ("fp32", R.RBFFD_FP32_IR, R.RBFFD_PREC_JACOBI),
                                ("fp32matrix", R.RBFFD_FP32_MATRIX, R.RBFFD_PREC_JACOBI),
-                               ("fp64_block_jacobi", R.RBFFD_FP64, R.RBFFD_PREC_BLOCK64)):
+                               ("fp64_block_jacobi", R.RBFFD_FP64, R.RBFFD_PREC_BLOCK64),
+                               ("fp32matrix_block_jacobi", R.RBFFD_FP32_MATRIX, R.RBFFD_PREC_BLOCK64)):
             u, up, p = u0.clone(), um1.clone(), pt0.clone()
             torch.cuda.synchronize()
             ta = time.perf_counter()
@@ -696,7 +704,7 @@ def main():
             res[name] = (u, p, st, time.perf_counter() - ta)
         u64, p64 = res["fp64"][0], res["fp64"][1]
         fields = {}
-        for name in ("fp32", "fp32matrix", "fp64_block_jacobi"):
+        for name in ("fp32", "fp32matrix", "fp64_block_jacobi", "fp32matrix_block_jacobi"):
             u, p, st, tm = res[name]
             du = [float((u[e] - u64[e]).abs().max() / u64[e].abs().max()) for e in range(cloud.dim)]
             dp = float((p - p64).abs().max() / p64.abs().max())

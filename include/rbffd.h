@@ -63,8 +63,10 @@ extern "C" {
 /* ---- preconditioner of the pressure-correction solve ------------------- */
 #define RBFFD_PREC_JACOBI 0     /* diagonal (Jacobi), applied on the right               */
 #define RBFFD_PREC_BLOCK64 1    /* inverses of the 64 x 64 diagonal blocks of the 64-row
-                                   slices (Morton-compact patches of 64 points), applied
-                                   on the right; FP64 solves only                       */
+                                   slices (Morton-compact patches of 64 points), stored
+                                   in FP32 and applied on the right with FP64
+                                   accumulation; any precision in poisson_solve and
+                                   simple_step, FP64 in batched and served solves       */
 
 /* ---- point kinds ------------------------------------------------------- */
 #define RBFFD_INTERIOR 0
@@ -166,7 +168,7 @@ typedef struct {
     double tol;             /* stop when ||b - A x||_2 <= tol ||b||_2 (recursive residual) */
     int max_iter;           /* BiCGSTAB iterations                                   */
     int precision;          /* RBFFD_FP64, RBFFD_FP32_IR or RBFFD_FP32_MATRIX        */
-    int preconditioner;     /* RBFFD_PREC_JACOBI or RBFFD_PREC_BLOCK64 (FP64 only)   */
+    int preconditioner;     /* RBFFD_PREC_JACOBI or RBFFD_PREC_BLOCK64               */
 } rbffd_krylov_opts;
 
 typedef struct {
@@ -245,8 +247,8 @@ typedef struct {
     int max_krylov;         /* iteration limit of every Krylov solve                  */
     int precision;          /* RBFFD_FP64, RBFFD_FP32_IR or RBFFD_FP32_MATRIX        */
     int preconditioner;     /* of the pressure-correction solve: RBFFD_PREC_JACOBI or
-                               RBFFD_PREC_BLOCK64 (with RBFFD_FP64); momentum and
-                               boundary-pressure solves use Jacobi                    */
+                               RBFFD_PREC_BLOCK64; momentum and boundary-pressure
+                               solves use Jacobi                                      */
 } rbffd_step_opts;
 
 typedef struct {

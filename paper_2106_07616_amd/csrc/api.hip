@@ -326,9 +326,8 @@ int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, doubl
     int st;
     if (opts->preconditioner != RBFFD_PREC_JACOBI && opts->preconditioner != RBFFD_PREC_BLOCK64)
         return fail(RBFFD_E_ARG, "unknown preconditioner");
-    if (opts->preconditioner == RBFFD_PREC_BLOCK64 && opts->precision != RBFFD_FP64)
-        return fail(RBFFD_E_ARG, "the block preconditioner runs with RBFFD_FP64");
-    if (opts->preconditioner == RBFFD_PREC_BLOCK64)
+    const bool block = opts->preconditioner == RBFFD_PREC_BLOCK64;
+    if (block && opts->precision == RBFFD_FP64)
         st = bicgstab_block(ctx, ops->n, ops->q, cols_of(ops), ops->pval, ops->pbinv, rhs, x, opts->tol,
                             opts->max_iter, &res, s);
     else if (opts->precision == RBFFD_FP64)
@@ -336,7 +335,8 @@ int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, doubl
                       opts->max_iter, &res, s);
     else
         st = bicgstab_mixed(ctx, opts->precision, ops->n, ops->q, cols_of(ops), ops->pval, ops->pval32, ops->pdinv32,
-                            ops->pdinv, 1, rhs, x, opts->tol, opts->max_iter, &res, &refine, s);
+                            ops->pdinv, block ? ops->pbinv : nullptr, 1, rhs, x, opts->tol, opts->max_iter, &res,
+                            &refine, s);
     if (st != RBFFD_OK) return st;
     double rr = 0.0;
     RB_CHECK(residual_norms(ctx, ops->n, ops->q, cols_of(ops), ops->pval, 1, rhs, x, &rr, s));
@@ -474,8 +474,6 @@ int simple_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev,
         return fail(RBFFD_E_ARG, "operators were assembled without FP32 copies");
     if (opts->preconditioner != RBFFD_PREC_JACOBI && opts->preconditioner != RBFFD_PREC_BLOCK64)
         return fail(RBFFD_E_ARG, "unknown preconditioner");
-    if (opts->preconditioner == RBFFD_PREC_BLOCK64 && opts->precision != RBFFD_FP64)
-        return fail(RBFFD_E_ARG, "the block preconditioner runs with RBFFD_FP64");
     RB_HIP(hipSetDevice(ctx->device));
     rbffd_step_stats local{};
     int st = run_step(ctx, ops, u, u_prev, p, u_bc, p_bc, opts, stats ? stats : &local, (hipStream_t)hip_stream);

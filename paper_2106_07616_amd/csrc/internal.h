@@ -239,9 +239,11 @@ int bicgstab(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val,
              KrylovResult *res, hipStream_t s);
 // FP32 matrix values with FP64 row accumulation and FP64 reliable updates;
 // precision RBFFD_FP32_IR keeps the Krylov vectors in FP32, RBFFD_FP32_MATRIX in FP64.
+// binv: block-Jacobi inverses (one right-hand side), or nullptr for Jacobi.
 int bicgstab_mixed(rbffd_ctx *ctx, int precision, int64_t n, int q, ColIdx col, const double *val,
-                   const float *val32, const float *dinv32, const double *dinv64, int nrhs, const double *b, double *x,
-                   double tol, int max_iter, KrylovResult *res, int *refinements, hipStream_t s);
+                   const float *val32, const float *dinv32, const double *dinv64, const float *binv, int nrhs,
+                   const double *b, double *x, double tol, int max_iter, KrylovResult *res, int *refinements,
+                   hipStream_t s);
 // One system of a batched solve (host description).
 struct BatchSystem {
     int64_t n;

@@ -801,10 +801,11 @@ __global__ __launch_bounds__(kKB) void kbj_init(int64_t n, int64_t np, int q, Co
 }
 
 // KS: alpha = rho / r-hat.v; s = r - alpha v; s-hat = M^-1 s; partials s.s, r-hat.s
+template <typename T>
 __global__ __launch_bounds__(kKB) void kbj_s(int64_t n, int64_t np, const float *__restrict__ binv,
-                                             const double *__restrict__ r, const double *__restrict__ rh,
-                                             const double *__restrict__ v, double *__restrict__ s,
-                                             double *__restrict__ sh, double *__restrict__ part, KState *__restrict__ st,
+                                             const T *__restrict__ r, const T *__restrict__ rh,
+                                             const T *__restrict__ v, T *__restrict__ s,
+                                             T *__restrict__ sh, double *__restrict__ part, KState *__restrict__ st,
                                              int nblk, int phase)
 {
     double rv;
@@ -830,13 +831,14 @@ __global__ __launch_bounds__(kKB) void kbj_s(int64_t n, int64_t np, const float 
     for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < np; i += (int64_t)gridDim.x * kKB) {
         double si = 0.0;
         if (i < n) {
-            si = r[i] - alpha * v[i];
-            s[i] = si;
+            const T sv = (T)((double)r[i] - alpha * (double)v[i]);
+            s[i] = sv;
+            si = (double)sv;
             acc[0] += si * si;
-            acc[1] += rh[i] * si;
+            acc[1] += (double)rh[i] * si;
         }
         const double z = bj_apply(binv + (i >> 6) * 4096, si, lane);
-        if (i < n) sh[i] = z;
+        if (i < n) sh[i] = (T)z;
     }
     double *ps[2] = {partial(part, P_SS, 0), partial(part, P_RS, 0)};
     write_partials<2>(acc, ps);
@@ -844,11 +846,12 @@ __global__ __launch_bounds__(kKB) void kbj_s(int64_t n, int64_t np, const float 
 
 // KX: omega; x += alpha p-hat + omega s-hat; r = s - omega t; p = r + beta (p -
 // omega v); p-hat = M^-1 p; partial r.r (restart and beta as in k_x)
+template <typename T>
 __global__ __launch_bounds__(kKB) void kbj_x(int64_t n, int64_t np, const float *__restrict__ binv,
-                                             double *__restrict__ x, double *__restrict__ p, double *__restrict__ ph,
-                                             const double *__restrict__ s, const double *__restrict__ sh,
-                                             const double *__restrict__ t, const double *__restrict__ v,
-                                             double *__restrict__ r, double *__restrict__ rh,
+                                             T *__restrict__ x, T *__restrict__ p, T *__restrict__ ph,
+                                             const T *__restrict__ s, const T *__restrict__ sh,
+                                             const T *__restrict__ t, const T *__restrict__ v,
+                                             T *__restrict__ r, T *__restrict__ rh,
                                              double *__restrict__ part, KState *__restrict__ st, int nblk, int phase)
 {
     double sums[5];
@@ -879,19 +882,96 @@ __global__ __launch_bounds__(kKB) void kbj_x(int64_t n, int64_t np, const float 
     for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < np; i += (int64_t)gridDim.x * kKB) {
         double pn = 0.0;
         if (i < n) {
-            x[i] += stk.alpha * ph[i] + omega * sh[i];
-            const double ri = s[i] - omega * t[i];
-            r[i] = ri;
-            if (restart) rh[i] = ri;
-            pn = (beta == 0.0) ? ri : ri + beta * (p[i] - omega * v[i]);
-            p[i] = pn;
+            x[i] = (T)((double)x[i] + (stk.alpha * (double)ph[i] + omega * (double)sh[i]));
+            const T rt = (T)((double)s[i] - omega * (double)t[i]);
+            const double ri = (double)rt;
+            r[i] = rt;
+            if (restart) rh[i] = rt;
+            const T pt = (beta == 0.0) ? rt : (T)(ri + beta * ((double)p[i] - omega * (double)v[i]));
+            p[i] = pt;
+            pn = (double)pt;
             srr += ri * ri;
         }
         const double z = bj_apply(binv + (i >> 6) * 4096, pn, lane);
-        if (i < n) ph[i] = z;
+        if (i < n) ph[i] = (T)z;
     }
     double *ps[1] = {partial(part, P_RR, 0)};
     write_partials<1>(&srr, ps);
+}
+
+// Reliable update with the block preconditioner (one right-hand side): the
+// FP64 residual r = b - A x replaces the recursive one; partials r-hat.r and
+// r.r for the iteration and ||r||^2, ||b||^2 for the host. With init set,
+// r-hat = p = r, p-hat = M^-1 r and the ||b||^2 partials are written as well.
+template <typename T>
+__global__ __launch_bounds__(kKB) void kbj_rel_resid(int64_t n, int64_t np, int q, ColIdx col,
+                                                     const double *__restrict__ val, const float *__restrict__ binv,
+                                                     const double *__restrict__ b, const double *__restrict__ x,
+                                                     T *__restrict__ r, T *__restrict__ rh, T *__restrict__ p,
+                                                     T *__restrict__ ph, int init, double *__restrict__ part,
+                                                     double *__restrict__ tpart)
+{
+    __shared__ double lds[kKB / 64];
+    const int lane = threadIdx.x & 63;
+    double rhr = 0.0, rr = 0.0, tr = 0.0, bb = 0.0;
+    const bool act[1] = {true};
+    for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < np; i += (int64_t)gridDim.x * kKB) {
+        double rf = 0.0;
+        if (i < n) {
+            double ax[1];
+            row_dot<double, double, 1>(i, q, col, val, x, n, act, ax);
+            const double bi = b[i];
+            const double ri = bi - ax[0];
+            const T rt = (T)ri;
+            rf = (double)rt;
+            r[i] = rt;
+            double hf = rf;
+            if (init) {
+                rh[i] = rt;
+                p[i] = rt;
+            } else {
+                hf = (double)rh[i];
+            }
+            rhr += hf * rf;
+            rr += rf * rf;
+            tr += ri * ri;
+            bb += bi * bi;
+        }
+        if (init) {
+            const double z = bj_apply(binv + (i >> 6) * 4096, rf, lane);
+            if (i < n) ph[i] = (T)z;
+        }
+    }
+    const double a1 = kblock_sum(rhr, lds);
+    const double a2 = kblock_sum(rr, lds);
+    const double a3 = kblock_sum(tr, lds);
+    const double a4 = kblock_sum(bb, lds);
+    if (threadIdx.x == 0) {
+        partial(part, P_RHR, 0)[blockIdx.x] = a1;
+        partial(part, P_RR, 0)[blockIdx.x] = a2;
+        if (init) partial(part, P_BB, 0)[blockIdx.x] = a4;
+        tpart[blockIdx.x] = a3;
+        tpart[kMaxBlocks + blockIdx.x] = a4;
+    }
+}
+
+// r-hat = p = r, p-hat = M^-1 r (a solve that continues after its recursion
+// had stopped); one thread per row, whole slices per wavefront
+template <typename T>
+__global__ void kbj_dir_reset(int64_t n, int64_t np, const float *__restrict__ binv, const T *__restrict__ r,
+                              T *__restrict__ rh, T *__restrict__ p, T *__restrict__ ph)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= np) return;   // np is a multiple of 64 and blockDim.x of 64: whole wavefronts leave
+    double ri = 0.0;
+    if (i < n) {
+        const T rt = r[i];
+        rh[i] = rt;
+        p[i] = rt;
+        ri = (double)rt;
+    }
+    const double z = bj_apply(binv + (i >> 6) * 4096, ri, threadIdx.x & 63);
+    if (i < n) ph[i] = (T)z;
 }
 
 // ---- batched BiCGSTAB (FP64, one right-hand side per system) ---------------
@@ -1232,11 +1312,11 @@ static int bicgstab_block_once(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, con
         for (int c = 0; c < todo; ++c) {
             hipLaunchKernelGGL((k_v<double, double, 1>), g, bl, 0, s, n, np, q, col, val, rh, ph, v, x, n, w.part,
                                w.st, nblk, tol2, 0, ++phase);
-            hipLaunchKernelGGL(kbj_s, g, bl, 0, s, n, np, binv, r, rh, v, sv, sh, w.part, w.st, nblk, ++phase);
+            hipLaunchKernelGGL(kbj_s<double>, g, bl, 0, s, n, np, binv, r, rh, v, sv, sh, w.part, w.st, nblk, ++phase);
             hipLaunchKernelGGL((k_t<double, double, 1>), g, bl, 0, s, n, np, q, col, val, x, n, ph, sv, sh, rh, t,
                                w.part, w.st, nblk, tol2, ++phase);
-            hipLaunchKernelGGL(kbj_x, g, bl, 0, s, n, np, binv, x, pv, ph, sv, sh, t, v, r, rh, w.part, w.st, nblk,
-                               ++phase);
+            hipLaunchKernelGGL(kbj_x<double>, g, bl, 0, s, n, np, binv, x, pv, ph, sv, sh, t, v, r, rh, w.part, w.st,
+                               nblk, ++phase);
         }
         it += std::max(todo, 0);
         hipLaunchKernelGGL((k_v<double, double, 1>), g, bl, 0, s, n, np, q, col, val, rh, ph, v, x, n, w.part, w.st,
@@ -1308,26 +1388,32 @@ int bicgstab(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, co
 // b - A x replaces the FP32 one, and the iteration continues in the same
 // Krylov space. The solve stops when the FP64 residual meets tol. If an update
 // finds a non-finite or growing FP64 residual, or FP32 BiCGSTAB breaks down,
-// the best iterate is restored and the solve finishes in FP64.
+// the best iterate is restored and the solve finishes in FP64. With block
+// inverses (binv, one right-hand side) the iteration is right-preconditioned by
+// them instead of the diagonal, and keeps its unpreconditioned direction p.
 constexpr double kRelDelta = 0.1;
 constexpr int kStallIters = 1000;   // forced update; less than 2x progress since the last one = stall
 
 template <typename T, int NRHS>
 static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val,
-                             const float *val32, const T *dinv, const double *dinv64, const double *b, double *x,
-                             double tol, int max_iter, KrylovResult *res, int *refinements, hipStream_t s)
+                             const float *val32, const T *dinv, const double *dinv64, const float *binv,
+                             const double *b, double *x, double tol, int max_iter, KrylovResult *res,
+                             int *refinements, hipStream_t s)
 {
+    if (binv && NRHS != 1) return fail(RBFFD_E_ARG, "the block preconditioner takes one right-hand side");
     const int64_t np = pad64(n);
     Work w;
     RB_CHECK(get_work<T>(ctx, np, NRHS, &w));
     char *scr = nullptr;
     const size_t tbytes = sizeof(double) * (2 * kMaxRhs * kMaxBlocks + kMaxRhs);
     const size_t xbytes = sizeof(double) * n * NRHS;
-    RB_CHECK(workspace(ctx, WS_REFINE, tbytes + xbytes + sizeof(T) * np * NRHS, (void **)&scr));
+    const size_t dbytes = sizeof(T) * np * NRHS;
+    RB_CHECK(workspace(ctx, WS_REFINE, tbytes + xbytes + dbytes + (binv ? dbytes : 0), (void **)&scr));
     double *tpart = (double *)scr;
     double *rout = tpart + 2 * kMaxRhs * kMaxBlocks;
     double *xgood = (double *)(scr + tbytes);       // iterate with the lowest FP64 residual so far
     T *d = (T *)(scr + tbytes + xbytes);            // correction accumulated since the last update
+    T *pv = binv ? (T *)(scr + tbytes + xbytes + dbytes) : nullptr;   // unpreconditioned direction
     double *rr = nullptr;
     RB_CHECK(host_scratch(ctx, kHostRefine, sizeof(double) * kMaxRhs, (void **)&rr));
     KState *hst = nullptr;
@@ -1341,8 +1427,12 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const
 
     // true residual of x: replaces r (and r-hat when init), norms to the host
     auto true_residual = [&](int init) -> int {
-        hipLaunchKernelGGL((k_rel_resid<T, NRHS>), g, bl, 0, s, n, np, q, col, val, b, n, x, n, dinv, r, rh, ph, init,
-                           w.part, tpart);
+        if (binv)
+            hipLaunchKernelGGL(kbj_rel_resid<T>, g, bl, 0, s, n, np, q, col, val, binv, b, x, r, rh, pv, ph, init,
+                               w.part, tpart);
+        else
+            hipLaunchKernelGGL((k_rel_resid<T, NRHS>), g, bl, 0, s, n, np, q, col, val, b, n, x, n, dinv, r, rh, ph,
+                               init, w.part, tpart);
         hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(kBlock), 0, s, tpart, nblk, NRHS, rout);
         RB_HIP(hipGetLastError());
         RB_HIP(hipMemcpyAsync(rr, rout, sizeof(double) * NRHS, hipMemcpyDeviceToHost, s));
@@ -1370,11 +1460,19 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const
         for (int c = 0; c < todo; ++c) {
             hipLaunchKernelGGL((k_v<T, float, NRHS>), g, bl, 0, s, n, np, q, col, val32, rh, ph, v, d, np, w.part,
                                w.st, nblk, tol2, 0, ++phase);
-            hipLaunchKernelGGL((k_s<T, NRHS>), g, bl, 0, s, n, np, dinv, r, rh, v, sv, sh, w.part, w.st, nblk, ++phase);
+            if (binv)
+                hipLaunchKernelGGL(kbj_s<T>, g, bl, 0, s, n, np, binv, r, rh, v, sv, sh, w.part, w.st, nblk, ++phase);
+            else
+                hipLaunchKernelGGL((k_s<T, NRHS>), g, bl, 0, s, n, np, dinv, r, rh, v, sv, sh, w.part, w.st, nblk,
+                                   ++phase);
             hipLaunchKernelGGL((k_t<T, float, NRHS>), g, bl, 0, s, n, np, q, col, val32, d, np, ph, sv, sh, rh, t,
                                w.part, w.st, nblk, tol2, ++phase);
-            hipLaunchKernelGGL((k_x<T, NRHS>), g, bl, 0, s, n, np, dinv, d, np, ph, sv, sh, t, v, r, rh, w.part, w.st,
-                               nblk, ++phase);
+            if (binv)
+                hipLaunchKernelGGL(kbj_x<T>, g, bl, 0, s, n, np, binv, d, pv, ph, sv, sh, t, v, r, rh, w.part, w.st,
+                                   nblk, ++phase);
+            else
+                hipLaunchKernelGGL((k_x<T, NRHS>), g, bl, 0, s, n, np, dinv, d, np, ph, sv, sh, t, v, r, rh, w.part,
+                                   w.st, nblk, ++phase);
         }
         it += todo;
         hipLaunchKernelGGL((k_v<T, float, NRHS>), g, bl, 0, s, n, np, q, col, val32, rh, ph, v, d, np, w.part, w.st,
@@ -1433,7 +1531,10 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const
                 hst[k].refresh = 1;
             }
         }
-        if (mask)
+        if (mask && binv)
+            hipLaunchKernelGGL(kbj_dir_reset<T>, dim3((unsigned)((np + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n,
+                               np, binv, r, rh, pv, ph);
+        else if (mask)
             hipLaunchKernelGGL(k_dir_reset<T>, dim3(gb), dim3(kBlock), 0, s, n, np, NRHS, mask, dinv, r, rh, ph);
         RB_HIP(hipMemcpyAsync(w.st, hst, sizeof(KState) * kMaxRhs, hipMemcpyHostToDevice, s));
     }
@@ -1446,7 +1547,10 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const
     if (fallback && it < max_iter) {
         const int left = max_iter - it;
         KrylovResult fr;
-        RB_CHECK(bicgstab(ctx, n, q, col, val, dinv64, NRHS, b, x, tol, left, &fr, s));
+        if (binv)
+            RB_CHECK(bicgstab_block(ctx, n, q, col, val, binv, b, x, tol, left, &fr, s));
+        else
+            RB_CHECK(bicgstab(ctx, n, q, col, val, dinv64, NRHS, b, x, tol, left, &fr, s));
         conv = true;
         for (int k = 0; k < NRHS; ++k) {
             total_it[k] += fr.iters[k];
@@ -1466,29 +1570,31 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const
 }
 
 int bicgstab_mixed(rbffd_ctx *ctx, int precision, int64_t n, int q, ColIdx col, const double *val,
-                   const float *val32, const float *dinv32, const double *dinv64, int nrhs, const double *b, double *x,
-                   double tol, int max_iter, KrylovResult *res, int *refinements, hipStream_t s)
+                   const float *val32, const float *dinv32, const double *dinv64, const float *binv, int nrhs,
+                   const double *b, double *x, double tol, int max_iter, KrylovResult *res, int *refinements,
+                   hipStream_t s)
 {
     if (nrhs < 1 || nrhs > kMaxRhs) return fail(RBFFD_E_ARG, "nrhs must be 1..3");
+    if (binv && nrhs != 1) return fail(RBFFD_E_ARG, "the block preconditioner takes one right-hand side");
     if (precision == RBFFD_FP32_IR) {
-        // FP32 vectors and preconditioner, FP32 matrix
+        // FP32 vectors and Jacobi diagonal, FP32 matrix
         switch (nrhs) {
-        case 1: return bicgstab_reliable<float, 1>(ctx, n, q, col, val, val32, dinv32, dinv64, b, x, tol, max_iter,
-                                                   res, refinements, s);
-        case 2: return bicgstab_reliable<float, 2>(ctx, n, q, col, val, val32, dinv32, dinv64, b, x, tol, max_iter,
-                                                   res, refinements, s);
-        default: return bicgstab_reliable<float, 3>(ctx, n, q, col, val, val32, dinv32, dinv64, b, x, tol, max_iter,
-                                                    res, refinements, s);
+        case 1: return bicgstab_reliable<float, 1>(ctx, n, q, col, val, val32, dinv32, dinv64, binv, b, x, tol,
+                                                   max_iter, res, refinements, s);
+        case 2: return bicgstab_reliable<float, 2>(ctx, n, q, col, val, val32, dinv32, dinv64, binv, b, x, tol,
+                                                   max_iter, res, refinements, s);
+        default: return bicgstab_reliable<float, 3>(ctx, n, q, col, val, val32, dinv32, dinv64, binv, b, x, tol,
+                                                    max_iter, res, refinements, s);
         }
     }
     if (precision == RBFFD_FP32_MATRIX) {
-        // FP64 vectors and preconditioner, FP32 matrix
+        // FP64 vectors and Jacobi diagonal, FP32 matrix
         switch (nrhs) {
-        case 1: return bicgstab_reliable<double, 1>(ctx, n, q, col, val, val32, dinv64, dinv64, b, x, tol, max_iter,
-                                                    res, refinements, s);
-        case 2: return bicgstab_reliable<double, 2>(ctx, n, q, col, val, val32, dinv64, dinv64, b, x, tol, max_iter,
-                                                    res, refinements, s);
-        default: return bicgstab_reliable<double, 3>(ctx, n, q, col, val, val32, dinv64, dinv64, b, x, tol,
+        case 1: return bicgstab_reliable<double, 1>(ctx, n, q, col, val, val32, dinv64, dinv64, binv, b, x, tol,
+                                                    max_iter, res, refinements, s);
+        case 2: return bicgstab_reliable<double, 2>(ctx, n, q, col, val, val32, dinv64, dinv64, binv, b, x, tol,
+                                                    max_iter, res, refinements, s);
+        default: return bicgstab_reliable<double, 3>(ctx, n, q, col, val, val32, dinv64, dinv64, binv, b, x, tol,
                                                      max_iter, res, refinements, s);
         }
     }

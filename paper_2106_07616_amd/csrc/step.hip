@@ -352,8 +352,9 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
         if (fp32) {
             RB_CHECK(launch_to_fp32(ops->mval, ops->mval32, vs, s));
             RB_CHECK(launch_to_fp32(ops->mdinv, ops->mdinv32, ops->npad, s));
-            RB_CHECK(bicgstab_mixed(ctx, o->precision, n, q, cols_of(ops), ops->mval, ops->mval32, ops->mdinv32, ops->mdinv, dim, B.bm,
-                                      B.ut, o->tol_krylov, o->max_krylov, &km, nullptr, s));
+            RB_CHECK(bicgstab_mixed(ctx, o->precision, n, q, cols_of(ops), ops->mval, ops->mval32, ops->mdinv32,
+                                    ops->mdinv, nullptr, dim, B.bm, B.ut, o->tol_krylov, o->max_krylov, &km, nullptr,
+                                    s));
         } else {
             RB_CHECK(bicgstab(ctx, n, q, cols_of(ops), ops->mval, ops->mdinv, dim, B.bm, B.ut, o->tol_krylov, o->max_krylov,
                               &km, s));
@@ -372,12 +373,14 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
                                ops->pin, B.ut, mass, B.f);
         RB_HIP(hipMemsetAsync(B.pc, 0, vec, s));
         KrylovResult kp;
-        if (o->preconditioner == RBFFD_PREC_BLOCK64)
+        const bool block = o->preconditioner == RBFFD_PREC_BLOCK64;
+        if (fp32)
+            RB_CHECK(bicgstab_mixed(ctx, o->precision, n, q, cols_of(ops), ops->pval, ops->pval32, ops->pdinv32,
+                                    ops->pdinv, block ? ops->pbinv : nullptr, 1, B.f, B.pc, o->tol_krylov,
+                                    o->max_krylov, &kp, nullptr, s));
+        else if (block)
             RB_CHECK(bicgstab_block(ctx, n, q, cols_of(ops), ops->pval, ops->pbinv, B.f, B.pc, o->tol_krylov,
                                     o->max_krylov, &kp, s));
-        else if (fp32)
-            RB_CHECK(bicgstab_mixed(ctx, o->precision, n, q, cols_of(ops), ops->pval, ops->pval32, ops->pdinv32, ops->pdinv, 1, B.f,
-                                      B.pc, o->tol_krylov, o->max_krylov, &kp, nullptr, s));
         else
             RB_CHECK(bicgstab(ctx, n, q, cols_of(ops), ops->pval, ops->pdinv, 1, B.f, B.pc, o->tol_krylov, o->max_krylov,
                               &kp, s));

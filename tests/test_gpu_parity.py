@@ -123,10 +123,12 @@ def test_poisson_solve_parity(case, ctx, orc):
 
 
 MIXED = {"fp32": R.RBFFD_FP32_IR, "fp32matrix": R.RBFFD_FP32_MATRIX}
+PCS = {"jacobi": R.RBFFD_PREC_JACOBI, "block64": R.RBFFD_PREC_BLOCK64}
 
 
+@pytest.mark.parametrize("pc", list(PCS))
 @pytest.mark.parametrize("mode", list(MIXED))
-def test_poisson_solve_mixed_precision(case, ctx, orc, mode):
+def test_poisson_solve_mixed_precision(case, ctx, orc, mode, pc):
     name, c, k, ops_o, s = case
     rng = np.random.default_rng(4)
     b = rng.standard_normal(c.n)
@@ -136,16 +138,17 @@ def test_poisson_solve_mixed_precision(case, ctx, orc, mode):
     s32 = R.rbffd_assemble(s.ctx, s.dcloud, s.nbr, s.w, k, precision=R.RBFFD_FP32_IR)
     xg = torch.zeros(c.n, dtype=torch.float64, device="cuda")
     stats = R.poisson_solve(ctx, s32, torch.tensor(b, device="cuda"), xg, tol=1e-10, max_iter=40000,
-                            precision=MIXED[mode], allow_noconv=True)
+                            precision=MIXED[mode], allow_noconv=True, preconditioner=PCS[pc])
     err = _relinf(xg.cpu().numpy(), xo)
-    print(f"[poisson {mode}] {name}: iters {stats['iters']} refinements {stats['refinements']} "
+    print(f"[poisson {mode} {pc}] {name}: iters {stats['iters']} refinements {stats['refinements']} "
           f"fp64 fallback {stats['fp64_fallback']} relres {stats['relres']:.2e} diff {err:.2e}", flush=True)
     assert stats["relres"] <= 1e-9
     assert err <= 1e-5
 
 
+@pytest.mark.parametrize("pc", list(PCS))
 @pytest.mark.parametrize("mode", list(MIXED))
-def test_simple_step_mixed_precision(case, ctx, orc, mode):
+def test_simple_step_mixed_precision(case, ctx, orc, mode, pc):
     """The step with FP32 Krylov sweeps and FP64 reliable updates (momentum with
     d right-hand sides, pressure correction) stays within 1e-5 of the FP64
     oracle's fields."""
@@ -165,22 +168,23 @@ def test_simple_step_mixed_precision(case, ctx, orc, mode):
     up = torch.tensor(vel, device="cuda")
     pg = torch.tensor(p, device="cuda")
     st = R.simple_step(ctx, s32, u, up, pg, torch.tensor(ubc_np, device="cuda"), 1.0, nu, dt, R.BDF2,
-                       p_bc=torch.tensor(pbc_np, device="cuda"), precision=MIXED[mode], **kw)
+                       p_bc=torch.tensor(pbc_np, device="cuda"), precision=MIXED[mode], preconditioner=PCS[pc], **kw)
     eu = _relinf(u.cpu().numpy(), uo)
     ep = _relinf(pg.cpu().numpy(), po)
-    print(f"[step {mode}] {name}: status {st['status']} mom {st['krylov_mom']} p {st['krylov_p']} "
+    print(f"[step {mode} {pc}] {name}: status {st['status']} mom {st['krylov_mom']} p {st['krylov_p']} "
           f"du {eu:.2e} dp {ep:.2e}", flush=True)
     assert eu <= 1e-5 and ep <= 1e-5
 
 
+@pytest.mark.parametrize("pc", list(PCS))
 @pytest.mark.parametrize("mode", list(MIXED))
-def test_mixed_precision_zero_rhs(ctx, mode):
+def test_mixed_precision_zero_rhs(ctx, mode, pc):
     """b = 0 gives x = 0 from any starting guess (mixed-precision paths)."""
     c = W.kovasznay_square(nx=12)
     s = R.Solver(ctx, c, 3, precision=MIXED[mode])
     x = torch.ones(c.n, dtype=torch.float64, device="cuda")
     st = R.poisson_solve(ctx, s.ops, torch.zeros(c.n, dtype=torch.float64, device="cuda"), x, tol=1e-10,
-                         max_iter=1000, precision=MIXED[mode])
+                         max_iter=1000, precision=MIXED[mode], preconditioner=PCS[pc])
     assert st["status"] == 0
     assert float(x.abs().max()) == 0.0
 
