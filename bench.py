@@ -259,7 +259,7 @@ def batch_bench(args):
 def serve_bench(args):
     """The serving configuration: a Poisson-arrival stream of solve requests,
     70% 2D (half Kovasznay squares, half holed squares, 2k-200k points) and 30%
-    3D Beltrami cubes (50k-500k points), degree 2-4 in 2D and 2-3 in 3D, q = 2m,
+    3D Beltrami cubes (50k-500k points), degree 2-4, q = 2m,
     prescribed pressure on every boundary. A request is served when its
     stencils and operators are built on the device and its pressure-correction
     solve (random right-hand side) reaches 1e-6. The arrival rate is 0.7 x the
@@ -287,7 +287,7 @@ def serve_bench(args):
                                    hole_kind=W.PRESCRIBED_PRESSURE)
         else:
             npts = int(round(np.exp(rng.uniform(np.log(5e4), np.log(5e5)))))
-            k = int(rng.integers(2, 4))   # 3D k = 4 needs 105-unknown systems (beyond 64)
+            k = int(rng.integers(2, 5))
             c = W.beltrami_cube(n=max(8, int(round(npts ** (1 / 3)))), seed=5000 + i)
         reqs.append((c, k, np.random.default_rng(9000 + i).standard_normal(c.n)))
     log(f"[serve] {len(reqs)} requests, {sum(r[0].n for r in reqs)} points")
@@ -357,7 +357,7 @@ def serve_bench(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"Poisson-arrival stream of {len(reqs)} solve requests (first {warm} excluded): 70% 2D "
                                "Kovasznay/holed squares 2k-200k points, 30% 3D Beltrami cubes 50k-500k points, "
-                               "k=2-4 (3D 2-3), q=2m; stencils + operators + pressure-correction solve to 1e-6 per "
+                               "k=2-4, q=2m; stencils + operators + pressure-correction solve to 1e-6 per "
                                f"request; offered load {lam:.2f}/s = 0.7 x one-at-a-time closed-loop rate; "
                                f"HBM budget 32 GiB; at most {args.serve_large_limit} solve(s) above "
                                f"{args.serve_large_points} points in the batch at once", "requests": len(reqs)},

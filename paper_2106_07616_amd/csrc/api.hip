@@ -192,7 +192,7 @@ int rbffd_build_stencils(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_s
     RB_CHECK(resolve_sizes(cloud->dim, opts, &q, &m, &R));
     if (q > cloud->n) return fail(RBFFD_E_ARG, "cloud size q exceeds the number of points");
     if (!nbr || !w) return fail(RBFFD_E_ARG, "nbr or w is NULL");
-    if (q + m > 64) return fail(RBFFD_E_ARG, "collocation systems larger than 64 (q + m) are not supported");
+    if (q + m > 128) return fail(RBFFD_E_ARG, "collocation systems larger than 128 (q + m) are not supported");
     RB_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)hip_stream;
     RB_CHECK(launch_knn(ctx, cloud->dim, cloud->n, cloud->xyz, q, nbr, s));

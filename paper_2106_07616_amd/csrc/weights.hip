@@ -10,7 +10,8 @@
 // of A^{-1} b_L.
 //
 // Layout on gfx950: one wavefront per system, lane r owns row r of [A | B] in
-// registers (ns <= 64). The pivot search is a wave max-reduction, the pivot row
+// registers (ns <= 64). Systems of 65-128 unknowns (2D degree 6, 3D degree 4)
+// take two wavefronts with the matrix in LDS: thread r still owns row r. The pivot search is a wave max-reduction, the pivot row
 // is broadcast lane-to-scalar with readlane, and the rank-1 update is one FP64
 // FMA per entry. On gfx950 the FP64 matrix-core rate equals the FP64 vector
 // rate, so the unblocked register LU runs against the same FP64 ceiling a
@@ -238,6 +239,185 @@ __global__ __launch_bounds__(64) void weights_kernel(const double *__restrict__ 
     if (singular && lane == 0) atomicMin((unsigned long long *)bad, (unsigned long long)i);
 }
 
+// Systems of 65-128 unknowns: one workgroup of 128 x kRowThreads threads per
+// system. [A | B] lives in LDS column-major (entry (t, j) at j*128 + t, up to
+// 132 KiB), so the lanes of a wavefront touch consecutive addresses. Row t is
+// shared by the threads (t, h), h < kRowThreads, each updating the columns
+// j = h mod kRowThreads; the threads with h = 0 (wavefronts 0 and 1) run the
+// pivot search and the back substitution. The arithmetic per entry is the
+// one-wavefront kernel's. A double-buffered LDS pair carries the two
+// wavefronts' pivot candidates, so one barrier per elimination step orders
+// every cross-row read.
+constexpr int kRowThreads = 8;
+
+template <int DIM>
+__global__ __launch_bounds__(128 * kRowThreads) void weights_kernel_lds(
+    const double *__restrict__ xyz, const int32_t *__restrict__ nbr, int64_t n, int q, int m, int phs,
+    double *__restrict__ w, int64_t *__restrict__ bad)
+{
+    constexpr int R = DIM + 1;
+    constexpr int NW = 128 * kRowThreads / 64;   // wavefronts per workgroup
+    extern __shared__ double A[];   // [ns + R][128]: columns 0..ns-1 the matrix, ns..ns+R-1 the right-hand sides
+    __shared__ double xs[kMaxQ * DIM];
+    __shared__ int exs[128 * 3];
+    __shared__ double red[2][2];
+    __shared__ int redi[2][2];
+    __shared__ double redm[NW];
+    __shared__ int prow_of[128];    // pivot row of each elimination step
+    const int tid = threadIdx.x;
+    const int t = tid & 127, h = tid >> 7;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int64_t i = blockIdx.x;
+    if (i >= n) return;
+    const int ns = q + m, nc = ns + R;
+#define RB_AT(ptr, j) (ptr)[(j) * 128]
+
+    double c[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) c[d] = xyz[i * DIM + d];
+    const int64_t jl = nbr[i * q + q - 1];
+    const double s = sqrt(sqdist_exact<DIM>(c, xyz + jl * DIM));
+    for (int a = tid; a < q; a += blockDim.x) {
+        const int64_t j = nbr[i * q + a];
+        for (int d = 0; d < DIM; ++d) xs[a * DIM + d] = (xyz[j * DIM + d] - c[d]) / s;
+    }
+    if (tid < m) {
+        int ex[3];
+        monomial_exponents<DIM>(tid, ex);
+        exs[tid * 3 + 0] = ex[0];
+        exs[tid * 3 + 1] = ex[1];
+        exs[tid * 3 + 2] = ex[2];
+    }
+    __syncthreads();
+
+    double *row = A + t;   // RB_AT(row, j): entry (t, j)
+    double amax = 0.0;
+    double mine[3] = {0, 0, 0};
+    int myex[3] = {0, 0, 0};
+    if (t < ns) {
+        if (t < q)
+            for (int d = 0; d < DIM; ++d) mine[d] = xs[t * DIM + d];
+        if (t >= q) {
+            myex[0] = exs[(t - q) * 3 + 0];
+            myex[1] = exs[(t - q) * 3 + 1];
+            myex[2] = exs[(t - q) * 3 + 2];
+        }
+        for (int b = h; b < ns; b += kRowThreads) {
+            double v = 0.0;
+            if (t < q) {
+                if (b < q) {
+                    const double r = sqrt(sqdist_exact<DIM>(mine, xs + b * DIM));
+                    v = (phs == 3) ? r * r * r : r * r * r * r * r;
+                } else {
+                    v = monomial<DIM>(exs + (b - q) * 3, mine);
+                }
+            } else if (b < q) {
+                v = monomial<DIM>(myex, xs + b * DIM);
+            }
+            RB_AT(row, b) = v;
+            amax = fmax(amax, fabs(v));
+        }
+        if (h == 0) {
+            double rhs[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) rhs[r] = 0.0;
+            if (t < q) {
+                double rr = 0.0;
+                for (int d = 0; d < DIM; ++d) rr = rr + mine[d] * mine[d];
+                const double r = sqrt(rr);
+                const double rp2 = (phs == 3) ? r : r * r * r;
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) rhs[d] = -(double)phs * rp2 * mine[d];
+                rhs[DIM] = (double)(phs * (phs + DIM - 2)) * rp2;
+            } else {
+                const int tot = myex[0] + myex[1] + myex[2];
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) {
+                    if (tot == 1 && myex[d] == 1) rhs[d] = 1.0;
+                    if (tot == 2 && myex[d] == 2) rhs[DIM] = 2.0;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) RB_AT(row, ns + r) = rhs[r];
+        }
+    }
+    amax = wave_max(amax);
+    if (lane == 0) redm[wv] = amax;
+    __syncthreads();
+    amax = 0.0;
+#pragma unroll
+    for (int u = 0; u < NW; ++u) amax = fmax(amax, redm[u]);
+
+    // LU with partial pivoting (largest |a|, ties to the lowest row); a row
+    // that has served as pivot keeps its U part and is no longer updated
+    bool active = t < ns;
+    int mystep = -1;
+    bool singular = false;
+    for (int k = 0; k < ns; ++k) {
+        const int buf = k & 1;
+        if (h == 0) {
+            const double v = active ? fabs(RB_AT(row, k)) : -1.0;
+            const double mx_w = wave_max(v);
+            const uint64_t msk = __ballot(active && v == mx_w);
+            if (lane == 0) {
+                red[buf][wv] = mx_w;
+                redi[buf][wv] = msk ? wv * 64 + (__ffsll((unsigned long long)msk) - 1) : INT_MAX;
+            }
+        }
+        __syncthreads();   // every row's step k-1 update and both candidates are visible
+        const double mx = fmax(red[buf][0], red[buf][1]);
+        const int p = (red[buf][0] >= red[buf][1]) ? redi[buf][0] : redi[buf][1];
+        if (!(mx > 1e-13 * amax)) singular = true;
+        if (t == p) {
+            active = false;
+            mystep = k;
+            if (h == 0) prow_of[k] = t;
+        }
+        const double *pr = A + p;
+        const double piv = singular ? 1.0 : RB_AT(pr, k);
+        if (active) {
+            // rw and pp are different rows (the pivot row is inactive)
+            double *__restrict__ rw = row;
+            const double *__restrict__ pp = pr;
+            const double l = RB_AT(rw, k) / piv;
+            int j = k + 1 + h;
+            for (; j + kRowThreads < nc; j += 2 * kRowThreads) {
+                const double p0 = RB_AT(pp, j), p1 = RB_AT(pp, j + kRowThreads);
+                const double r0 = RB_AT(rw, j), r1 = RB_AT(rw, j + kRowThreads);
+                RB_AT(rw, j) = fma(-l, p0, r0);
+                RB_AT(rw, j + kRowThreads) = fma(-l, p1, r1);
+            }
+            if (j < nc) RB_AT(rw, j) = fma(-l, RB_AT(pp, j), RB_AT(rw, j));
+        }
+    }
+
+    // back substitution by the h = 0 threads; thread c keeps unknown c
+    double xout[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) xout[r] = 0.0;
+    for (int k = ns - 1; k >= 0; --k) {
+        __syncthreads();   // the pivot row's right-hand sides are final for step k
+        if (h != 0) continue;
+        const double *pr = A + prow_of[k];
+        const double dgl = singular ? 1.0 : RB_AT(pr, k);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double xk = RB_AT(pr, ns + r) / dgl;
+            if (t == k) xout[r] = xk;
+            if (mystep >= 0 && mystep < k) RB_AT(row, ns + r) = fma(-RB_AT(row, k), xk, RB_AT(row, ns + r));
+        }
+    }
+#undef RB_AT
+
+    if (h == 0 && t < q) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double sc = (r < DIM) ? s : s * s;
+            w[(int64_t)r * n * q + i * q + t] = xout[r] / sc;
+        }
+    }
+    if (singular && tid == 0) atomicMin((unsigned long long *)bad, (unsigned long long)i);
+}
+
 }  // namespace
 
 int launch_weights(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q, const int32_t *nbr, int k,
@@ -273,7 +453,31 @@ int launch_weights(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q,
     RB_WEIGHTS(56)
     RB_WEIGHTS(64)
 #undef RB_WEIGHTS
-    return fail(RBFFD_E_ARG, "collocation systems larger than 64 are not supported");
+    if (ns <= 128) {
+        // systems of 65-128 unknowns: the matrix lives in LDS
+        const int R = dim + 1;
+        const size_t lds = sizeof(double) * (size_t)(ns + R) * 128;
+        int dev = 0, lim = 0;
+        RB_HIP(hipGetDevice(&dev));
+        RB_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        const size_t fixed = sizeof(double) * (kMaxQ * 3 + 4 + 2 * kRowThreads) + sizeof(int) * (128 * 3 + 4 + 128);
+        if (lds + fixed > (size_t)lim)
+            return fail(RBFFD_E_ARG, "collocation system needs " + std::to_string(lds + fixed) +
+                                         " bytes of LDS per workgroup; the device allows " + std::to_string(lim));
+        const dim3 block2(128 * kRowThreads);
+        if (dim == 2) {
+            RB_HIP(hipFuncSetAttribute((const void *)weights_kernel_lds<2>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL(weights_kernel_lds<2>, grid, block2, lds, s, xyz, nbr, n, q, m, phs, w, bad_dev);
+        } else {
+            RB_HIP(hipFuncSetAttribute((const void *)weights_kernel_lds<3>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL(weights_kernel_lds<3>, grid, block2, lds, s, xyz, nbr, n, q, m, phs, w, bad_dev);
+        }
+        RB_HIP(hipGetLastError());
+        return RBFFD_OK;
+    }
+    return fail(RBFFD_E_ARG, "collocation systems larger than 128 are not supported");
 }
 
 }  // namespace rbffd

@@ -51,6 +51,9 @@ CLOUDS = {
     # walls with Neumann p', and prescribed-pressure walls at degree 5
     "couette2080_k3": (lambda: W.couette_annulus(W.COUETTE_RADII[2080]), 3),
     "couette4033_pp_k5": (lambda: W.couette_annulus(W.COUETTE_RADII[4033], boundary_kind=W.PRESCRIBED_PRESSURE), 5),
+    # systems of 65-128 unknowns (two-wavefront weight kernel): 2D degree 6 and 3D degree 4
+    "couette2080_pp_k6": (lambda: W.couette_annulus(W.COUETTE_RADII[2080], boundary_kind=W.PRESCRIBED_PRESSURE), 6),
+    "cube9_k4": (lambda: W.beltrami_cube(n=9), 4),
 }
 
 
@@ -269,11 +272,12 @@ def test_polynomial_flow_step(case, ctx, orc, which):
 
 
 @pytest.mark.parametrize("dim,k,q,phs", [(2, 1, 6, 3), (2, 3, 28, 3), (2, 4, 40, 3), (2, 2, 20, 5), (3, 2, 26, 3),
-                                          (3, 3, 44, 5)])
+                                          (3, 3, 44, 5), (2, 6, 56, 3), (3, 4, 70, 3), (2, 5, 100, 5),
+                                          (3, 3, 65, 3)])
 def test_weights_all_system_sizes(ctx, orc, dim, k, q, phs):
-    """Every register-row width of the weight kernel (systems of 9 to 64
-    unknowns, r^3 and r^5) against the oracle: clouds bit-exact, weights within
-    1e-10 row-relative."""
+    """Every register-row width of the weight kernels (systems of 9 to 64
+    unknowns on one wavefront, 65 to 128 on two; r^3 and r^5) against the
+    oracle: clouds bit-exact, weights within 1e-10 row-relative."""
     c = W.kovasznay_square(nx=14) if dim == 2 else W.scattered_cube(8, seed=5)
     nbr, w, _ = R.rbffd_build_stencils(ctx, R.DeviceCloud.from_numpy(c), k, q, phs)
     nbr_o = orc.knn(c.xyz, q)
@@ -349,7 +353,7 @@ def test_more_argument_errors(ctx):
         R.rbffd_build_stencils(ctx, dc, 2, q=129)                # q > 128
     cube = R.DeviceCloud.from_numpy(W.scattered_cube(5, seed=2))
     with pytest.raises(R.RbffdError) as e:
-        R.rbffd_build_stencils(ctx, cube, 4)                     # 3D k=4: 105 unknowns > 64
+        R.rbffd_build_stencils(ctx, cube, 5)                     # 3D k=5: 168 unknowns > 128
     assert e.value.code == -1
     # prescribed-pressure points need p_bc
     t = W.taylor_green_disk(r=0.3)
