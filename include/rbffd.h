@@ -163,6 +163,26 @@ int rbffd_ops_export_block_inverse(const rbffd_ops *ops, float *out, void *hip_s
 int rbffd_apply(rbffd_ctx *ctx, const rbffd_ops *ops, int which, const double *x, double *y,
                 void *hip_stream);
 
+/* (Sec. 2, Eq. RBF_interp evaluated off the nodes; the centre-line profiles
+ * and sampled fields of Sec. 4) Interpolate fields given on the cloud's points
+ * at nq arbitrary points: each query point takes its q nearest cloud points in
+ * the order (squared distance, index), and the local PHS + polynomial
+ * interpolant of degree opts->poly_degree on them, centred at the query point
+ * and scaled by the distance to its farthest cloud point, is evaluated there.
+ *   qxyz:   device [nq][dim] query coordinates (any point; clouds of points
+ *           outside the bounding box are still exact but slower to find)
+ *   fields: device [nfield][n] values on the cloud (may be NULL if nfield = 0)
+ *   out:    device [nfield][nq] interpolated values (may be NULL if nfield = 0)
+ *   nbr_out, w_out: optional device [nq][q] int32 clouds and [nq][q] double
+ *           weights (out[f][j] = sum_a w[j][a] fields[f][nbr[j][a]]); NULL to
+ *           keep them internal
+ * Systems of up to 128 unknowns (q + m). Synchronises the stream. Returns
+ * RBFFD_E_SINGULAR (lowest query index in *bad_query) for a singular local
+ * system, RBFFD_E_ARG for bad sizes; nq = 0 is a no-op. */
+int rbffd_interpolate(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_stencil_opts *opts, int64_t nq,
+                      const double *qxyz, int nfield, const double *fields, double *out, int32_t *nbr_out,
+                      double *w_out, int64_t *bad_query, void *hip_stream);
+
 /* ---- Krylov solve ------------------------------------------------------- */
 typedef struct {
     double tol;             /* stop when ||b - A x||_2 <= tol ||b||_2 (recursive residual) */

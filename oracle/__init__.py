@@ -146,6 +146,41 @@ def weights(xyz, nbr, k, phs=3, queries=None, allow_singular=False):
     return w
 
 
+def knn_points(xyz, q, points):
+    """Brute-force q nearest cloud points of arbitrary points (Sec. 2 clouds):
+    order (squared distance, index), squared distance formed as
+    ((dx*dx + dy*dy) + dz*dz) with dx = x_j - x* in FP64 without fused
+    multiply-adds (numpy never fuses)."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    pts = np.asarray(points, dtype=np.float64).reshape(-1, xyz.shape[1])
+    out = np.zeros((len(pts), q), np.int32)
+    idx = np.arange(len(xyz))
+    for t, x in enumerate(pts):
+        d = xyz - x
+        d2 = d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]
+        if xyz.shape[1] == 3:
+            d2 = d2 + d[:, 2] * d[:, 2]
+        out[t] = np.lexsort((idx, d2))[:q]
+    return out
+
+
+def interpolate(xyz, k, points, fields, q=None, phs=3):
+    """Evaluate the local PHS + polynomial interpolant of each point's q-point
+    cloud (Sec. 2, Eq. RBF_interp) at arbitrary points: returns
+    (values[nfield, np], nbr[np, q], w[np, q])."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    dim = xyz.shape[1]
+    q = default_q(dim, k) if q is None else q
+    nbr = knn_points(xyz, q, points)
+    pts = np.asarray(points, dtype=np.float64).reshape(-1, dim)
+    w = np.zeros((len(pts), q))
+    for t in range(len(pts)):
+        w[t] = interp_weights(xyz, nbr[t], pts[t], k, phs)
+    f = np.asarray(fields, dtype=np.float64).reshape(-1, len(xyz))
+    vals = np.array([[w[t] @ fi[nbr[t]] for t in range(len(pts))] for fi in f])
+    return vals, nbr, w
+
+
 def interp_weights(xyz, cloud_idx, xstar, k, phs=3):
     xyz = _c(xyz, np.float64)
     cl = _c(cloud_idx, np.int32)

@@ -7,11 +7,13 @@ loop (Sec. 3.2: outer tolerance min(1e-4, dt * eps_s); Sec. 4.1: steady error).
 """
 from __future__ import annotations
 
-from .binding import (BDF1, BDF2, RBFFD_PREC_BLOCK64, RBFFD_PREC_JACOBI, RBFFD_FP32_IR, RBFFD_FP32_MATRIX, RBFFD_FP64, Context, DeviceCloud, Operators, RbffdError, Server,
-                      lib, poisson_solve, poisson_solve_batched, rbffd_assemble, rbffd_build_stencils, rbffd_convdiff_lambda,
+from .binding import (BDF1, BDF2, RBFFD_FP32_IR, RBFFD_FP32_MATRIX, RBFFD_FP64, RBFFD_PREC_BLOCK64, RBFFD_PREC_JACOBI,
+                      Context, DeviceCloud, Operators, RbffdError, Server, lib, poisson_solve, poisson_solve_batched,
+                      rbffd_assemble, rbffd_build_stencils, rbffd_convdiff_lambda, rbffd_interpolate,
                       rbffd_stencil_sizes, simple_step)
 from .driver import Solver, outer_tolerance
 
-__all__ = ["BDF1", "BDF2", "RBFFD_PREC_BLOCK64", "RBFFD_PREC_JACOBI", "RBFFD_FP32_IR", "RBFFD_FP32_MATRIX", "RBFFD_FP64", "Context", "DeviceCloud", "Operators", "RbffdError", "Server",
-           "lib", "poisson_solve", "poisson_solve_batched", "rbffd_assemble", "rbffd_build_stencils", "rbffd_convdiff_lambda",
+__all__ = ["BDF1", "BDF2", "RBFFD_FP32_IR", "RBFFD_FP32_MATRIX", "RBFFD_FP64", "RBFFD_PREC_BLOCK64", "RBFFD_PREC_JACOBI",
+           "Context", "DeviceCloud", "Operators", "RbffdError", "Server", "lib", "poisson_solve", "poisson_solve_batched",
+           "rbffd_assemble", "rbffd_build_stencils", "rbffd_convdiff_lambda", "rbffd_interpolate",
            "rbffd_stencil_sizes", "simple_step", "Solver", "outer_tolerance"]

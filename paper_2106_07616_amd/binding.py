@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_OOM", -3: "E_SINGULAR", -4: "E_NOCO
 
 EXPORTED = ["rbffd_last_error", "rbffd_ctx_create", "rbffd_ctx_destroy", "rbffd_ctx_bytes_in_use",
             "rbffd_stencil_sizes", "rbffd_build_stencils", "rbffd_assemble", "rbffd_ops_free",
-            "rbffd_ops_info", "rbffd_ops_export_csr", "rbffd_ops_export_block_inverse", "rbffd_apply", "poisson_solve", "poisson_solve_batched",
+            "rbffd_ops_info", "rbffd_ops_export_csr", "rbffd_ops_export_block_inverse", "rbffd_apply", "rbffd_interpolate", "poisson_solve",
+            "poisson_solve_batched",
             "rbffd_server_create", "rbffd_server_destroy", "rbffd_server_submit", "rbffd_server_run",
             "rbffd_server_poll", "simple_step", "rbffd_convdiff_lambda"]
 
@@ -84,6 +85,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.rbffd_ops_export_csr.argtypes = [P, P, P, P]
     L.rbffd_ops_export_block_inverse.argtypes = [P, P, P]
     L.rbffd_apply.argtypes = [P, P, I, P, P, P]
+    L.rbffd_interpolate.argtypes = [P, C.POINTER(CloudT), C.POINTER(StencilOptsT), I64, P, I, P, P, P, P,
+                                    C.POINTER(I64), P]
     L.poisson_solve.argtypes = [P, P, P, P, C.POINTER(KrylovOptsT), C.POINTER(KrylovStatsT), P]
     L.poisson_solve_batched.argtypes = [P, I, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(KrylovOptsT),
                                         C.POINTER(KrylovStatsT), P]
@@ -204,6 +207,37 @@ def rbffd_build_stencils(ctx: Context, cloud: DeviceCloud, poly_degree: int, q: 
     st = lib().rbffd_build_stencils(ctx.handle, C.byref(cs), C.byref(o), _ptr(nbr), _ptr(w), C.byref(bad), _stream())
     _check(st, allow=(RBFFD_E_SINGULAR,) if allow_singular else ())
     return nbr, w, bad.value
+
+
+def rbffd_interpolate(ctx: Context, cloud: DeviceCloud, poly_degree: int, qxyz: torch.Tensor,
+                      fields: torch.Tensor | None = None, q: int = 0, phs_power: int = 3,
+                      return_stencils: bool = False):
+    """Interpolated fields out[nfield, nq] at the query points qxyz[nq, dim]
+    from fields[nfield, n] on the cloud; with return_stencils, also the
+    clouds nbr[nq, q] and weights w[nq, q]."""
+    q, m, R = rbffd_stencil_sizes(cloud.dim, poly_degree, q, phs_power)
+    dev = cloud.xyz.device
+    if qxyz.dim() != 2 or qxyz.shape[1] != cloud.dim:
+        raise ValueError(f"qxyz must be [nq, {cloud.dim}]")
+    nq = qxyz.shape[0]
+    nf = 0
+    if fields is not None:
+        if fields.dim() == 1:
+            fields = fields.reshape(1, -1)
+        nf = fields.shape[0]
+        _f64(fields, nf * cloud.n, "fields")
+    out = torch.empty((nf, nq), dtype=torch.float64, device=dev) if nf else None
+    nbr = torch.empty((nq, q), dtype=torch.int32, device=dev) if return_stencils else None
+    w = torch.empty((nq, q), dtype=torch.float64, device=dev) if return_stencils else None
+    o = StencilOptsT(phs_power, poly_degree, q)
+    cs = cloud.struct()
+    bad = C.c_int64(-1)
+    _check(lib().rbffd_interpolate(ctx.handle, C.byref(cs), C.byref(o), nq, _f64(qxyz, nq * cloud.dim, "qxyz"), nf,
+                                   _ptr(fields) if nf else None, _ptr(out), _ptr(nbr), _ptr(w), C.byref(bad),
+                                   _stream()))
+    if return_stencils:
+        return out, nbr, w
+    return out
 
 
 class Operators:

@@ -309,6 +309,60 @@ int rbffd_apply(rbffd_ctx *ctx, const rbffd_ops *ops, int which, const double *x
     return apply_op(ctx, ops, which, x, y, (hipStream_t)hip_stream);
 }
 
+int rbffd_interpolate(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_stencil_opts *opts, int64_t nq,
+                      const double *qxyz, int nfield, const double *fields, double *out, int32_t *nbr_out,
+                      double *w_out, int64_t *bad_query, void *hip_stream)
+{
+    if (!ctx) return fail(RBFFD_E_ARG, "ctx is NULL");
+    if (bad_query) *bad_query = -1;
+    RB_CHECK(check_cloud(cloud));
+    int q, m, R;
+    RB_CHECK(resolve_sizes(cloud->dim, opts, &q, &m, &R));
+    if (q > cloud->n) return fail(RBFFD_E_ARG, "cloud size q exceeds the number of points");
+    if (q + m > 128) return fail(RBFFD_E_ARG, "collocation systems larger than 128 (q + m) are not supported");
+    if (nq < 0 || nfield < 0) return fail(RBFFD_E_ARG, "nq and nfield must be >= 0");
+    if (nq > INT32_MAX) return fail(RBFFD_E_ARG, "too many query points");
+    if (nq == 0) return RBFFD_OK;
+    if (!qxyz) return fail(RBFFD_E_ARG, "qxyz is NULL");
+    if (nfield > 0 && (!fields || !out)) return fail(RBFFD_E_ARG, "fields or out is NULL");
+    RB_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t nb = sizeof(int32_t) * nq * q, wb = sizeof(double) * nq * q;
+    int32_t *nbr = nbr_out;
+    double *w = w_out;
+    if (!nbr) RB_CHECK(dev_alloc(ctx, (void **)&nbr, nb));
+    if (!w) {
+        const int st = dev_alloc(ctx, (void **)&w, wb);
+        if (st != RBFFD_OK) {
+            if (!nbr_out) dev_free(ctx, nbr, nb);
+            return st;
+        }
+    }
+    int64_t *bad_dev = nullptr;
+    int64_t *hb = nullptr;
+    int st = workspace(ctx, WS_MISC, sizeof(int64_t), (void **)&bad_dev);
+    if (st == RBFFD_OK) st = host_scratch(ctx, kHostMisc, sizeof(int64_t), (void **)&hb);
+    if (st == RBFFD_OK) st = launch_knn_points(ctx, cloud->dim, cloud->n, cloud->xyz, nq, qxyz, q, nbr, s);
+    if (st == RBFFD_OK)
+        st = launch_interp(ctx, cloud->dim, cloud->n, cloud->xyz, nq, qxyz, q, nbr, opts->poly_degree,
+                           opts->phs_power, w, bad_dev, nfield, fields, out, s);
+    hipError_t e = hipSuccess;
+    if (st == RBFFD_OK) {
+        e = hipMemcpyAsync(hb, bad_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    } else {
+        (void)hipStreamSynchronize(s);
+    }
+    if (!w_out) dev_free(ctx, w, wb);
+    if (!nbr_out) dev_free(ctx, nbr, nb);
+    if (st != RBFFD_OK) return st;
+    if (e != hipSuccess) return hip_fail(e, "interpolation");
+    const int64_t bad = (*hb == INT64_MAX) ? -1 : *hb;
+    if (bad_query) *bad_query = bad;
+    if (bad >= 0) return fail(RBFFD_E_SINGULAR, "singular interpolation system at query " + std::to_string(bad));
+    return RBFFD_OK;
+}
+
 int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, double *x,
                   const rbffd_krylov_opts *opts, rbffd_krylov_stats *stats, void *hip_stream)
 {

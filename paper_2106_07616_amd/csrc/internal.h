@@ -212,6 +212,14 @@ int launch_knn(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q, int
                hipStream_t s);
 int launch_weights(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q, const int32_t *nbr,
                    int k, int phs, double *w, int64_t *bad_dev, hipStream_t s);
+// The q nearest cloud points of nq arbitrary query points.
+int launch_knn_points(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int64_t nq, const double *qxyz, int q,
+                      int32_t *nbr, hipStream_t s);
+// Interpolation weights at nq query points (clouds in nbr) and, when nfield > 0,
+// the interpolated fields: out[f][j] = sum_a w[j][a] fields[f][nbr[j][a]].
+int launch_interp(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int64_t nq, const double *qxyz, int q,
+                  const int32_t *nbr, int k, int phs, double *w, int64_t *bad_dev, int nfield, const double *fields,
+                  double *out, hipStream_t s);
 int assemble_ops(rbffd_ctx *ctx, const rbffd_cloud *cloud, int q, int k, int phs,
                  const int32_t *nbr, const double *w, int precision, rbffd_ops *ops, hipStream_t s);
 int export_csr(const rbffd_ops *ops, int32_t *col, double *val, hipStream_t s);

@@ -219,17 +219,17 @@ __device__ inline void scan_range(QueryState<DIM> &S, const double *xq, int32_t 
 }
 
 template <int DIM>
-__global__ __launch_bounds__(64) void knn_query(const double *__restrict__ xyz, const int32_t *__restrict__ cstart,
+__global__ __launch_bounds__(64) void knn_query(const double *__restrict__ qxyz, const int32_t *__restrict__ cstart,
                                                 const int32_t *__restrict__ sidx, const double *__restrict__ sxyz,
-                                                Grid g, int64_t n, int q, int32_t *__restrict__ nbr)
+                                                Grid g, int64_t nq, int q, int32_t *__restrict__ nbr)
 {
     __shared__ QueryState<DIM> S;
     const int64_t i = blockIdx.x;
-    if (i >= n) return;
+    if (i >= nq) return;
     double xq[3] = {0.0, 0.0, 0.0};
     int c[3] = {0, 0, 0};
     for (int d = 0; d < DIM; ++d) {
-        xq[d] = xyz[i * DIM + d];
+        xq[d] = qxyz[i * DIM + d];
         c[d] = cell_coord<DIM>(xq[d], g, d);
     }
     double csmin = g.cs[0];
@@ -358,6 +358,15 @@ int scan_exclusive(rbffd_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, h
 
 int launch_knn(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q, int32_t *nbr, hipStream_t s)
 {
+    return launch_knn_points(ctx, dim, n, xyz, n, xyz, q, nbr, s);
+}
+
+// The q nearest cloud points of each of nq query points (qxyz [nq][dim]); a
+// query outside the cloud's bounding box starts from the nearest cell and
+// widens its shells until the box covers the grid.
+int launch_knn_points(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int64_t nq, const double *qxyz, int q,
+                      int32_t *nbr, hipStream_t s)
+{
     // bounding box
     const int nbb = (int)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock);
     double *part = nullptr;
@@ -437,11 +446,11 @@ int launch_knn(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q, int
             hipLaunchKernelGGL(cell_scatter<3>, dim3(nb), dim3(kBlock), 0, s, xyz, n, cell_of, cstart, cursor, sidx, sxyz);
         e = hipGetLastError();
     }
-    if (e == hipSuccess && st == RBFFD_OK) {
+    if (e == hipSuccess && st == RBFFD_OK && nq > 0) {
         if (dim == 2)
-            hipLaunchKernelGGL(knn_query<2>, dim3((unsigned)n), dim3(64), 0, s, xyz, cstart, sidx, sxyz, g, n, q, nbr);
+            hipLaunchKernelGGL(knn_query<2>, dim3((unsigned)nq), dim3(64), 0, s, qxyz, cstart, sidx, sxyz, g, nq, q, nbr);
         else
-            hipLaunchKernelGGL(knn_query<3>, dim3((unsigned)n), dim3(64), 0, s, xyz, cstart, sidx, sxyz, g, n, q, nbr);
+            hipLaunchKernelGGL(knn_query<3>, dim3((unsigned)nq), dim3(64), 0, s, qxyz, cstart, sidx, sxyz, g, nq, q, nbr);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);

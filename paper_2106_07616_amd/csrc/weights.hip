@@ -248,14 +248,21 @@ __global__ __launch_bounds__(64) void weights_kernel(const double *__restrict__ 
 // one-wavefront kernel's. A double-buffered LDS pair carries the two
 // wavefronts' pivot candidates, so one barrier per elimination step orders
 // every cross-row read.
+//
+// With INTERP set the same kernel gives interpolation weights at off-node
+// points (evaluation of the local PHS + polynomial interpolant, Sec. 2, Eq.
+// RBF_interp): the system is centred at query point i (ctr[i]), scaled by the
+// distance to its farthest cloud point, and its one right-hand side is
+// [phi(|x_j - x*|); P(x*)], where only the constant monomial is nonzero at the
+// centre. Interpolation weights are scale-free, so they are stored unscaled.
 constexpr int kRowThreads = 8;
 
-template <int DIM>
+template <int DIM, bool INTERP>
 __global__ __launch_bounds__(128 * kRowThreads) void weights_kernel_lds(
-    const double *__restrict__ xyz, const int32_t *__restrict__ nbr, int64_t n, int q, int m, int phs,
-    double *__restrict__ w, int64_t *__restrict__ bad)
+    const double *__restrict__ xyz, const double *__restrict__ ctr, const int32_t *__restrict__ nbr, int64_t n,
+    int q, int m, int phs, double *__restrict__ w, int64_t *__restrict__ bad)
 {
-    constexpr int R = DIM + 1;
+    constexpr int R = INTERP ? 1 : DIM + 1;
     constexpr int NW = 128 * kRowThreads / 64;   // wavefronts per workgroup
     extern __shared__ double A[];   // [ns + R][128]: columns 0..ns-1 the matrix, ns..ns+R-1 the right-hand sides
     __shared__ double xs[kMaxQ * DIM];
@@ -273,7 +280,7 @@ __global__ __launch_bounds__(128 * kRowThreads) void weights_kernel_lds(
 #define RB_AT(ptr, j) (ptr)[(j) * 128]
 
     double c[3] = {0, 0, 0};
-    for (int d = 0; d < DIM; ++d) c[d] = xyz[i * DIM + d];
+    for (int d = 0; d < DIM; ++d) c[d] = ctr[i * DIM + d];
     const int64_t jl = nbr[i * q + q - 1];
     const double s = sqrt(sqdist_exact<DIM>(c, xyz + jl * DIM));
     for (int a = tid; a < q; a += blockDim.x) {
@@ -320,20 +327,29 @@ __global__ __launch_bounds__(128 * kRowThreads) void weights_kernel_lds(
             double rhs[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) rhs[r] = 0.0;
-            if (t < q) {
+            if (INTERP) {
+                if (t < q) {
+                    double rr = 0.0;
+                    for (int d = 0; d < DIM; ++d) rr = rr + mine[d] * mine[d];
+                    const double r = sqrt(rr);
+                    rhs[0] = (phs == 3) ? r * r * r : r * r * r * r * r;
+                } else {
+                    rhs[0] = (myex[0] + myex[1] + myex[2] == 0) ? 1.0 : 0.0;
+                }
+            } else if (t < q) {
                 double rr = 0.0;
                 for (int d = 0; d < DIM; ++d) rr = rr + mine[d] * mine[d];
                 const double r = sqrt(rr);
                 const double rp2 = (phs == 3) ? r : r * r * r;
 #pragma unroll
                 for (int d = 0; d < DIM; ++d) rhs[d] = -(double)phs * rp2 * mine[d];
-                rhs[DIM] = (double)(phs * (phs + DIM - 2)) * rp2;
+                rhs[R - 1] = (double)(phs * (phs + DIM - 2)) * rp2;
             } else {
                 const int tot = myex[0] + myex[1] + myex[2];
 #pragma unroll
                 for (int d = 0; d < DIM; ++d) {
                     if (tot == 1 && myex[d] == 1) rhs[d] = 1.0;
-                    if (tot == 2 && myex[d] == 2) rhs[DIM] = 2.0;
+                    if (tot == 2 && myex[d] == 2) rhs[R - 1] = 2.0;
                 }
             }
 #pragma unroll
@@ -411,11 +427,25 @@ __global__ __launch_bounds__(128 * kRowThreads) void weights_kernel_lds(
     if (h == 0 && t < q) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const double sc = (r < DIM) ? s : s * s;
+            const double sc = INTERP ? 1.0 : ((r < DIM) ? s : s * s);
             w[(int64_t)r * n * q + i * q + t] = xout[r] / sc;
         }
     }
     if (singular && tid == 0) atomicMin((unsigned long long *)bad, (unsigned long long)i);
+}
+
+// out[f][j] = sum_a w[j][a] field_f[nbr[j][a]], in cloud order a = 0..q-1
+__global__ __launch_bounds__(kBlock) void interp_apply(int64_t nq, int q, const int32_t *__restrict__ nbr,
+                                                       const double *__restrict__ w, int nfield, int64_t n,
+                                                       const double *__restrict__ fields, double *__restrict__ out)
+{
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= nq) return;
+    for (int f = 0; f < nfield; ++f) {
+        double acc = 0.0;
+        for (int a = 0; a < q; ++a) acc = fma(w[j * q + a], fields[(int64_t)f * n + nbr[j * q + a]], acc);
+        out[(int64_t)f * nq + j] = acc;
+    }
 }
 
 }  // namespace
@@ -466,18 +496,63 @@ int launch_weights(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q,
                                          " bytes of LDS per workgroup; the device allows " + std::to_string(lim));
         const dim3 block2(128 * kRowThreads);
         if (dim == 2) {
-            RB_HIP(hipFuncSetAttribute((const void *)weights_kernel_lds<2>,
+            RB_HIP(hipFuncSetAttribute((const void *)weights_kernel_lds<2, false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            hipLaunchKernelGGL(weights_kernel_lds<2>, grid, block2, lds, s, xyz, nbr, n, q, m, phs, w, bad_dev);
+            hipLaunchKernelGGL((weights_kernel_lds<2, false>), grid, block2, lds, s, xyz, xyz, nbr, n, q, m, phs, w,
+                               bad_dev);
         } else {
-            RB_HIP(hipFuncSetAttribute((const void *)weights_kernel_lds<3>,
+            RB_HIP(hipFuncSetAttribute((const void *)weights_kernel_lds<3, false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            hipLaunchKernelGGL(weights_kernel_lds<3>, grid, block2, lds, s, xyz, nbr, n, q, m, phs, w, bad_dev);
+            hipLaunchKernelGGL((weights_kernel_lds<3, false>), grid, block2, lds, s, xyz, xyz, nbr, n, q, m, phs, w,
+                               bad_dev);
         }
         RB_HIP(hipGetLastError());
         return RBFFD_OK;
     }
     return fail(RBFFD_E_ARG, "collocation systems larger than 128 are not supported");
+}
+
+int launch_interp(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int64_t nq, const double *qxyz, int q,
+                  const int32_t *nbr, int k, int phs, double *w, int64_t *bad_dev, int nfield, const double *fields,
+                  double *out, hipStream_t s)
+{
+    (void)ctx;
+    long mm = 1, den = 1;
+    for (int i = 1; i <= dim; ++i) {
+        mm *= (k + i);
+        den *= i;
+    }
+    const int m = (int)(mm / den);
+    const int ns = q + m;
+    if (ns > 128) return fail(RBFFD_E_ARG, "collocation systems larger than 128 are not supported");
+    const long long init = LLONG_MAX;
+    RB_HIP(hipMemcpyAsync(bad_dev, &init, sizeof(init), hipMemcpyHostToDevice, s));
+    if (nq == 0) return RBFFD_OK;
+    const size_t lds = sizeof(double) * (size_t)(ns + 1) * 128;
+    int dev = 0, lim = 0;
+    RB_HIP(hipGetDevice(&dev));
+    RB_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t fixed = sizeof(double) * (kMaxQ * 3 + 4 + 2 * kRowThreads) + sizeof(int) * (128 * 3 + 4 + 128);
+    if (lds + fixed > (size_t)lim) return fail(RBFFD_E_ARG, "interpolation system does not fit the device's LDS");
+    const dim3 grid((unsigned)nq), block(128 * kRowThreads);
+    if (dim == 2) {
+        RB_HIP(hipFuncSetAttribute((const void *)weights_kernel_lds<2, true>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL((weights_kernel_lds<2, true>), grid, block, lds, s, xyz, qxyz, nbr, nq, q, m, phs, w,
+                           bad_dev);
+    } else {
+        RB_HIP(hipFuncSetAttribute((const void *)weights_kernel_lds<3, true>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL((weights_kernel_lds<3, true>), grid, block, lds, s, xyz, qxyz, nbr, nq, q, m, phs, w,
+                           bad_dev);
+    }
+    RB_HIP(hipGetLastError());
+    if (nfield > 0) {
+        hipLaunchKernelGGL(interp_apply, dim3((unsigned)((nq + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, nq, q, nbr,
+                           w, nfield, n, fields, out);
+        RB_HIP(hipGetLastError());
+    }
+    return RBFFD_OK;
 }
 
 }  // namespace rbffd

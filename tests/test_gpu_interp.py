@@ -1,0 +1,127 @@
+"""Off-node interpolation through the C ABI (rbffd_interpolate) against the
+FP64 oracle: clouds bit-exact, weights within 1e-10 (row-relative), values
+within 1e-12 of the oracle's weights applied to the same fields; degree-k
+polynomials reproduced; a query on a node returns the nodal value."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2106_07616_amd as R  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = R.Context(0)
+    yield c
+    c.close()
+
+
+CASES = {
+    # the centre line of the Kovasznay square (the paper's profile plots)
+    "kovasznay40_k3": (lambda: W.kovasznay_square(nx=40), 3),
+    "tg_disk_k4": (lambda: W.taylor_green_disk(r=0.06), 4),
+    "couette2080_k6": (lambda: W.couette_annulus(W.COUETTE_RADII[2080]), 6),   # 84 unknowns
+    "cube9_k2": (lambda: W.beltrami_cube(n=9), 2),
+    "cube9_k4": (lambda: W.beltrami_cube(n=9), 4),                               # 105 unknowns
+}
+
+
+def _queries(c, rng):
+    lo, hi = c.xyz.min(0), c.xyz.max(0)
+    mid = 0.5 * (lo + hi)
+    line = np.repeat(mid[None, :], 100, axis=0)
+    line[:, 0] = np.linspace(lo[0] + 0.01 * (hi[0] - lo[0]), hi[0] - 0.01 * (hi[0] - lo[0]), 100)
+    if c.meta.get("flow") == "couette":   # the radial line y = 0, x in [r1, r2]
+        line[:, 1] = 0.0
+        line[:, 0] = np.linspace(0.51, 0.99, 100)
+    scat = lo + (hi - lo) * rng.uniform(0.05, 0.95, size=(60, c.dim))
+    if c.meta.get("flow") == "couette":
+        r = rng.uniform(0.52, 0.98, 60)
+        th = rng.uniform(0, 2 * np.pi, 60)
+        scat = np.stack([r * np.cos(th), r * np.sin(th)], axis=1)
+    return np.concatenate([line, scat, c.xyz[[3, c.n // 2]]])   # two queries on nodes
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_interpolation_parity(ctx, orc, name):
+    gen, k = CASES[name]
+    c = gen()
+    pts = _queries(c, np.random.default_rng(21))
+    vel, p = W.flow_fields(c) if "flow" in c.meta else (None, None)
+    fields = np.concatenate([vel, p[None, :]]) if vel is not None else np.sin(c.xyz[:, :1].T)
+    dc = R.DeviceCloud.from_numpy(c)
+    out, nbr, w = R.rbffd_interpolate(ctx, dc, k, torch.tensor(pts, device="cuda"),
+                                      torch.tensor(fields, device="cuda"), return_stencils=True)
+    vo, nbr_o, w_o = orc.interpolate(c.xyz, k, pts, fields)
+    np.testing.assert_array_equal(nbr.cpu().numpy(), nbr_o)
+    wg = w.cpu().numpy()
+    werr = float((np.abs(wg - w_o).max(1) / np.abs(w_o).max(1)).max())
+    og = out.cpu().numpy()
+    verr = float(np.abs(og - vo).max() / np.abs(vo).max())
+    print(f"[interp] {name}: nq={len(pts)} q={nbr.shape[1]} weights {werr:.1e} values {verr:.1e}", flush=True)
+    assert werr <= 1e-10
+    assert verr <= 1e-12
+    # queries on nodes return the nodal values
+    np.testing.assert_allclose(og[:, -2:], fields[:, [3, c.n // 2]], rtol=1e-10,
+                               atol=1e-12 * np.abs(fields).max())
+    # against the exact flow on the sampled points (discretization error only)
+    if vel is not None and c.meta.get("flow") != "taylor_green":
+        ue, pe = W.flow_fields(W.Cloud(dim=c.dim, xyz=pts, kind=np.zeros(len(pts), np.uint8),
+                                       normal=np.zeros_like(pts), pin=-1, meta=c.meta))
+        du = float(np.abs(og[:c.dim] - ue).max() / np.abs(ue).max())
+        print(f"[interp] {name}: max velocity error vs the closed form {du:.1e}", flush=True)
+        assert du <= 1e-3
+
+
+@pytest.mark.parametrize("dim,k", [(2, 3), (3, 3)])
+def test_interpolation_reproduces_polynomials(ctx, dim, k):
+    c = W.kovasznay_square(nx=20) if dim == 2 else W.scattered_cube(9, seed=5)
+    rng = np.random.default_rng(5)
+    lo, hi = c.xyz.min(0), c.xyz.max(0)
+    pts = lo + (hi - lo) * rng.uniform(0.0, 1.0, size=(200, dim))
+    import itertools
+    ex = [np.array(e) for e in itertools.product(range(k + 1), repeat=dim) if sum(e) <= k]
+    coef = rng.standard_normal(len(ex))
+    poly = lambda x: sum(cf * np.prod(x ** e, axis=1) for cf, e in zip(coef, ex))
+    out = R.rbffd_interpolate(ctx, R.DeviceCloud.from_numpy(c), k, torch.tensor(pts, device="cuda"),
+                              torch.tensor(poly(c.xyz), device="cuda"))
+    ref = poly(pts)
+    assert float(np.abs(out.cpu().numpy()[0] - ref).max()) <= 1e-9 * np.abs(ref).max()
+
+
+def test_interpolation_edge_cases(ctx):
+    c = W.kovasznay_square(nx=12)
+    dc = R.DeviceCloud.from_numpy(c)
+    f = torch.tensor(c.xyz[:, 0].copy(), device="cuda")
+    # no query points: a no-op
+    out = R.rbffd_interpolate(ctx, dc, 2, torch.zeros((0, 2), dtype=torch.float64, device="cuda"), f)
+    assert out.shape == (1, 0)
+    # weights only (no fields)
+    out, nbr, w = R.rbffd_interpolate(ctx, dc, 2, torch.tensor([[0.3, 0.4]], dtype=torch.float64, device="cuda"), None,
+                                      return_stencils=True)
+    assert out is None and abs(float(w.sum()) - 1.0) < 1e-12    # the constant is reproduced
+    # a query outside the cloud's bounding box still finds its exact neighbours
+    far = np.array([[3.0, -2.0]])
+    _, nbr, _ = R.rbffd_interpolate(ctx, dc, 2, torch.tensor(far, device="cuda"), None, return_stencils=True)
+    np.testing.assert_array_equal(nbr.cpu().numpy(), __import__("oracle").knn_points(c.xyz, nbr.shape[1], far))
+    # argument errors through the C ABI
+    import ctypes as C
+    L = R.lib()
+    o = R.binding.StencilOptsT(3, 2, 0)
+    cs = dc.struct()
+    bad = C.c_int64()
+    assert L.rbffd_interpolate(ctx.handle, C.byref(cs), C.byref(o), -1, None, 0, None, None, None, None,
+                               C.byref(bad), R.binding._stream()) == -1
+    q1 = torch.tensor([[0.3, 0.4]], dtype=torch.float64, device="cuda")
+    assert L.rbffd_interpolate(ctx.handle, C.byref(cs), C.byref(o), 1, R.binding._ptr(q1), 1, None, None, None,
+                               None, C.byref(bad), R.binding._stream()) == -1      # fields missing
+    o7 = R.binding.StencilOptsT(3, 7, 0)
+    assert L.rbffd_interpolate(ctx.handle, C.byref(cs), C.byref(o7), 1, R.binding._ptr(q1), 0, None, None, None,
+                               None, C.byref(bad), R.binding._stream()) == -1      # degree 7

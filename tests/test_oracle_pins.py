@@ -477,3 +477,38 @@ def test_courant_lambda_matches_dense_eigenvalues(orc, mu, scale):
     lam_ref = np.abs(np.linalg.eigvals(A)).max()
     assert abs(lam - lam_ref) <= 1e-3 * lam_ref, (lam, lam_ref)
     assert lam <= np.linalg.norm(A, 2) * (1 + 1e-12)
+
+
+def test_knn_points_matches_cloud_knn_and_kdtree(orc):
+    """Off-node neighbour search: at the cloud's own points it equals the C
+    search; at arbitrary points its distances equal a k-d tree's."""
+    from scipy.spatial import cKDTree
+    c = W.kovasznay_square(nx=14)
+    q = 20
+    np.testing.assert_array_equal(orc.knn_points(c.xyz, q, c.xyz[:50]), orc.knn(c.xyz, q)[:50])
+    pts = np.random.default_rng(8).uniform(-0.4, 1.4, size=(40, 2))
+    nb = orc.knn_points(c.xyz, q, pts)
+    d_tree, _ = cKDTree(c.xyz).query(pts, q)
+    d_ours = np.sqrt(((c.xyz[nb] - pts[:, None, :]) ** 2).sum(-1))
+    np.testing.assert_allclose(d_ours, d_tree, rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("dim,k", [(2, 3), (2, 6), (3, 2), (3, 4)])
+def test_interpolation_reproduces_polynomials_off_node(orc, dim, k):
+    """The interpolant of a degree-k polynomial is the polynomial itself at any
+    point (the appended monomials, Eq. RBF_constraint); at a node it returns
+    the nodal value of any field."""
+    c = W.kovasznay_square(nx=16) if dim == 2 else W.scattered_cube(9, seed=5)
+    rng = np.random.default_rng(9)
+    lo, hi = c.xyz.min(0), c.xyz.max(0)
+    pts = lo + (hi - lo) * rng.uniform(0.1, 0.9, size=(12, dim))
+    import itertools
+    ex = [e for e in itertools.product(range(k + 1), repeat=dim) if sum(e) <= k]
+    coef = rng.standard_normal(len(ex))
+    def poly(x):
+        return sum(cf * np.prod(x ** np.array(e), axis=1) for cf, e in zip(coef, ex))
+    vals, _, _ = orc.interpolate(c.xyz, k, pts, poly(c.xyz))
+    np.testing.assert_allclose(vals[0], poly(pts), rtol=1e-9, atol=1e-9 * np.abs(poly(pts)).max())
+    f = np.sin(3 * c.xyz[:, 0]) + c.xyz[:, 1] ** 2
+    v_node, _, _ = orc.interpolate(c.xyz, k, c.xyz[7:9], f)
+    np.testing.assert_allclose(v_node[0], f[7:9], rtol=1e-10, atol=1e-12)
