@@ -171,7 +171,7 @@ def batch_bench(args):
     ctx = R.Context(0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    solvers = [R.Solver(ctx, c, k) for c, k in clouds]
+    solvers = [R.Solver(ctx, c, k, precision=R.RBFFD_FP32_MATRIX) for c, k in clouds]   # FP64 + FP32 copies
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     npts = sum(c.n for c, _ in clouds)
@@ -197,12 +197,12 @@ def batch_bench(args):
             xs.append(x)
         return lat, its, xs
 
-    def batched(pc=R.RBFFD_PREC_JACOBI):
+    def batched(pc=R.RBFFD_PREC_JACOBI, precision=R.RBFFD_FP64):
         xs = [torch.zeros_like(b) for b in rhs]
         torch.cuda.synchronize()
         ta = time.perf_counter()
         st = R.poisson_solve_batched(ctx, [sv.ops for sv in solvers], rhs, xs, tol=tol, max_iter=20000,
-                                     allow_noconv=True, preconditioner=pc)
+                                     allow_noconv=True, preconditioner=pc, precision=precision)
         torch.cuda.synchronize()
         return time.perf_counter() - ta, st, xs
 
@@ -214,6 +214,10 @@ def batch_bench(args):
     t_bj, stbj, xbj = batched(R.RBFFD_PREC_BLOCK64)
     ok_bj = [j for j, s_ in enumerate(stbj) if s_["status"] == 0 and seq_status[j] == 0]
     diff_bj = max((float((xbj[j] - xseq[j]).abs().max() / xseq[j].abs().max()) for j in ok_bj), default=None)
+    batched(R.RBFFD_PREC_BLOCK64, R.RBFFD_FP32_MATRIX)
+    t_mx, stmx, xmx = batched(R.RBFFD_PREC_BLOCK64, R.RBFFD_FP32_MATRIX)
+    ok_mx = [j for j, s_ in enumerate(stmx) if s_["status"] == 0 and seq_status[j] == 0]
+    diff_mx = max((float((xmx[j] - xseq[j]).abs().max() / xseq[j].abs().max()) for j in ok_mx), default=None)
     t_seq = sum(lat)
     ok = [j for j, s_ in enumerate(stb) if s_["status"] == 0 and seq_status[j] == 0]
     diff = max((float((xb[j] - xseq[j]).abs().max() / xseq[j].abs().max()) for j in ok), default=None)
@@ -247,8 +251,16 @@ def batch_bench(args):
                                  "converged": int(sum(s_["status"] == 0 for s_ in stbj)),
                                  "max_true_relres": float(max(s_["relres"] for s_ in stbj)),
                                  "max_rel_diff_vs_sequential": diff_bj},
+        "batched_fp32_matrix_block_jacobi": {
+            "solves_per_s": round(len(solvers) / t_mx, 3), "wall_ms": round(t_mx * 1e3, 3),
+            "iters_median": int(np.median([s_["iters"] for s_ in stmx])),
+            "converged": int(sum(s_["status"] == 0 for s_ in stmx)),
+            "max_true_relres": float(max(s_["relres"] for s_ in stmx)),
+            "max_rel_diff_vs_sequential": diff_mx,
+            "note": "FP32 matrix values in the Krylov SpMVs, FP64 vectors, FP64 residual refinement"},
         "speedup_batched_vs_sequential": round(t_seq / t_batch, 3),
         "speedup_batched_block_jacobi_vs_sequential": round(t_seq / t_bj, 3),
+        "speedup_batched_fp32_matrix_block_jacobi_vs_sequential": round(t_seq / t_mx, 3),
         "max_rel_diff_batched_vs_sequential": diff,
         "stencils_and_assembly_ms": round(t_build * 1e3, 1),
     }
@@ -297,7 +309,7 @@ def serve_bench(args):
 
     def build(j):
         c, k, b = reqs[j]
-        sv = R.Solver(ctx, c, k)
+        sv = R.Solver(ctx, c, k, precision=R.RBFFD_FP32_MATRIX)   # FP64 operators plus FP32 copies
         return sv, torch.tensor(b, device="cuda")
 
     # closed-loop rate of the one-at-a-time path on the first requests
@@ -344,13 +356,15 @@ def serve_bench(args):
     seq["converged"] = int(conv)
     log(f"[serve] one at a time: {seq}")
 
-    def continuous(pc):
-        return serve_continuous(args, R, ctx, reqs, arrivals, build, report, tol, pc)
+    def continuous(pc, precision=R.RBFFD_FP64):
+        return serve_continuous(args, R, ctx, reqs, arrivals, build, report, tol, pc, precision)
 
     cb = continuous(R.RBFFD_PREC_JACOBI)
     log(f"[serve] continuous batching: {cb}")
     cbj = continuous(R.RBFFD_PREC_BLOCK64)
     log(f"[serve] continuous batching, block-Jacobi: {cbj}")
+    cbm = continuous(R.RBFFD_PREC_BLOCK64, R.RBFFD_FP32_MATRIX)
+    log(f"[serve] continuous batching, FP32 matrix + block-Jacobi: {cbm}")
     out = {
         "metric": METRIC, "value": cb["solves_per_s"], "unit": "converged solves/s", "n_gpus": 1,
         "steps": len(reqs) - warm, "warmup": warm, "ms_per_step": cb["mean_ms"], "higher_is_better": True,
@@ -361,15 +375,18 @@ def serve_bench(args):
                                f"request; offered load {lam:.2f}/s = 0.7 x one-at-a-time closed-loop rate; "
                                f"HBM budget 32 GiB; at most {args.serve_large_limit} solve(s) above "
                                f"{args.serve_large_points} points in the batch at once", "requests": len(reqs)},
-        "continuous_batching": cb, "continuous_batching_block_jacobi": cbj, "one_at_a_time_fp64": seq,
+        "continuous_batching": cb, "continuous_batching_block_jacobi": cbj,
+        "continuous_batching_fp32_matrix_block_jacobi": cbm, "one_at_a_time_fp64": seq,
         "p99_latency_ratio_one_at_a_time_over_batched": round(seq["p99_ms"] / cb["p99_ms"], 3),
         "p99_latency_ratio_one_at_a_time_over_batched_block_jacobi": round(seq["p99_ms"] / cbj["p99_ms"], 3),
+        "p99_latency_ratio_one_at_a_time_over_batched_fp32_matrix_block_jacobi": round(seq["p99_ms"] / cbm["p99_ms"],
+                                                                                       3),
     }
     ctx.close()
     print(json.dumps(out), flush=True)
 
 
-def serve_continuous(args, R, ctx, reqs, arrivals, build, report, tol, pc):
+def serve_continuous(args, R, ctx, reqs, arrivals, build, report, tol, pc, precision):
     """Serve the arrival sequence with continuous batching (rbffd_server)."""
     import torch
 
@@ -399,7 +416,7 @@ def serve_continuous(args, R, ctx, reqs, arrivals, build, report, tol, pc):
             try:
                 sv, b = build(j)
                 x = torch.zeros_like(b)
-                t = server.submit(sv.ops, b, x, tol=tol, max_iter=20000, preconditioner=pc)
+                t = server.submit(sv.ops, b, x, tol=tol, max_iter=20000, preconditioner=pc, precision=precision)
             except R.RbffdError as e:
                 if e.code != -2:
                     raise

@@ -66,7 +66,8 @@ extern "C" {
                                    slices (Morton-compact patches of 64 points), stored
                                    in FP32 and applied on the right with FP64
                                    accumulation; any precision in poisson_solve and
-                                   simple_step, FP64 in batched and served solves       */
+                                   simple_step, RBFFD_FP64 or RBFFD_FP32_MATRIX in
+                                   batched and served solves                            */
 
 /* ---- point kinds ------------------------------------------------------- */
 #define RBFFD_INTERIOR 0
@@ -219,8 +220,14 @@ int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, doubl
  *   ops, rhs, x: HOST arrays of `count` pointers; rhs[j], x[j] device [n_j];
  *                x[j] holds the initial guess on entry and the solution on
  *                return
- *   opts:        shared by all systems; precision must be RBFFD_FP64,
- *                preconditioner RBFFD_PREC_JACOBI or RBFFD_PREC_BLOCK64
+ *   opts:        shared by all systems; precision RBFFD_FP64 or
+ *                RBFFD_FP32_MATRIX (FP32 matrix values in the Krylov
+ *                SpMVs, FP64 vectors; every start and the final check use
+ *                the FP64 residual b - A x, and a system whose FP64 residual
+ *                exceeds 10 tol iterates again from x, at most three times:
+ *                iterative refinement; needs operators assembled with FP32
+ *                copies), preconditioner RBFFD_PREC_JACOBI or
+ *                RBFFD_PREC_BLOCK64
  *   stats:       host array of `count` records (may be NULL)
  * Returns RBFFD_OK when every system converged, RBFFD_E_NOCONV or
  * RBFFD_E_BREAKDOWN (the first failing code) otherwise; per-system outcomes
@@ -231,7 +238,8 @@ int poisson_solve_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops
 
 /* ---- continuous batching ------------------------------------------------ */
 /* (Sec. 3, applied to a stream of independent requests) A server keeps a
- * running batch of FP64 pressure-correction solves. Solves submitted while
+ * running batch of pressure-correction solves (FP64, or FP32 matrix values
+ * with FP64 vectors and residuals). Solves submitted while
  * others run join the batch at the next rbffd_server_run; finished ones leave
  * it and are collected with rbffd_server_poll. Each solve behaves as
  * poisson_solve (FP64 BiCGSTAB with the Jacobi or block-Jacobi preconditioner,
@@ -245,7 +253,8 @@ int rbffd_server_create(rbffd_ctx *ctx, rbffd_server **out);
 int rbffd_server_destroy(rbffd_server *sv);
 /* Queue a solve of P x = rhs (ops, rhs and x stay owned by the caller and must
  * outlive the solve; x holds the initial guess). opts: tol, max_iter (>= 1),
- * precision (RBFFD_FP64) and preconditioner, copied at submission.
+ * precision (RBFFD_FP64 or RBFFD_FP32_MATRIX, as in poisson_solve_batched)
+ * and preconditioner, copied at submission.
  * *ticket identifies the solve. */
 int rbffd_server_submit(rbffd_server *sv, const rbffd_ops *ops, const double *rhs, double *x,
                         const rbffd_krylov_opts *opts, int64_t *ticket);

@@ -308,14 +308,16 @@ def poisson_solve(ctx: Context, ops: Operators, rhs: torch.Tensor, x: torch.Tens
 
 
 def poisson_solve_batched(ctx: Context, ops: list, rhs: list, x: list, tol: float = 1e-10, max_iter: int = 5000,
-                          allow_noconv: bool = False, preconditioner: int = RBFFD_PREC_JACOBI):
-    """FP64 pressure-correction solves of several independent systems in one
-    batch; x[j] is updated in place. Returns one stats dict per system."""
+                          allow_noconv: bool = False, preconditioner: int = RBFFD_PREC_JACOBI,
+                          precision: int = RBFFD_FP64):
+    """Pressure-correction solves of several independent systems in one batch
+    (FP64, or FP32 matrix values with FP64 vectors and residuals); x[j] is
+    updated in place. Returns one stats dict per system."""
     m = len(ops)
     if not (m == len(rhs) == len(x)) or m == 0:
         raise ValueError("ops, rhs and x must be non-empty lists of the same length")
     arr = C.c_void_p * m
-    o = KrylovOptsT(tol, max_iter, RBFFD_FP64, preconditioner)
+    o = KrylovOptsT(tol, max_iter, precision, preconditioner)
     stats = (KrylovStatsT * m)()
     rp = [_f64(t, op.n, f"rhs[{j}]") for j, (t, op) in enumerate(zip(rhs, ops))]
     xp = [_f64(t, op.n, f"x[{j}]") for j, (t, op) in enumerate(zip(x, ops))]
@@ -336,9 +338,9 @@ class Server:
         self._keep = {}   # ticket -> tensors that must outlive the solve
 
     def submit(self, ops: Operators, rhs: torch.Tensor, x: torch.Tensor, tol: float = 1e-6,
-               max_iter: int = 20000, preconditioner: int = RBFFD_PREC_JACOBI) -> int:
+               max_iter: int = 20000, preconditioner: int = RBFFD_PREC_JACOBI, precision: int = RBFFD_FP64) -> int:
         t = C.c_int64()
-        o = KrylovOptsT(tol, max_iter, RBFFD_FP64, preconditioner)
+        o = KrylovOptsT(tol, max_iter, precision, preconditioner)
         _check(lib().rbffd_server_submit(self.handle, ops.handle, _f64(rhs, ops.n, "rhs"), _f64(x, ops.n, "x"),
                                          C.byref(o), C.byref(t)))
         self._keep[t.value] = (ops, rhs, x)

@@ -414,17 +414,21 @@ int poisson_solve_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops
     if (!ctx || !ops || !rhs || !x || !opts) return fail(RBFFD_E_ARG, "NULL argument");
     if (count < 1) return fail(RBFFD_E_ARG, "count must be >= 1");
     if (!(opts->tol >= 0.0) || opts->max_iter < 0) return fail(RBFFD_E_ARG, "bad Krylov options");
-    if (opts->precision != RBFFD_FP64) return fail(RBFFD_E_ARG, "batched solves run in FP64");
+    if (opts->precision != RBFFD_FP64 && opts->precision != RBFFD_FP32_MATRIX)
+        return fail(RBFFD_E_ARG, "batched solves run in RBFFD_FP64 or RBFFD_FP32_MATRIX");
     if (opts->preconditioner != RBFFD_PREC_JACOBI && opts->preconditioner != RBFFD_PREC_BLOCK64)
         return fail(RBFFD_E_ARG, "unknown preconditioner");
     const bool block = opts->preconditioner == RBFFD_PREC_BLOCK64;
+    const bool f32 = opts->precision == RBFFD_FP32_MATRIX;
     std::vector<BatchSystem> sys((size_t)count);
     for (int j = 0; j < count; ++j) {
         if (!ops[j] || !rhs[j] || !x[j])
             return fail(RBFFD_E_ARG, "NULL operator, right-hand side or solution of system " + std::to_string(j));
         if (!ops[j]->ctx) return fail(RBFFD_E_ARG, "the operators' context was destroyed");
+        if (f32 && !ops[j]->pval32)
+            return fail(RBFFD_E_ARG, "system " + std::to_string(j) + " was assembled without FP32 copies");
         sys[j] = BatchSystem{ops[j]->n, ops[j]->q, cols_of(ops[j]), ops[j]->pval, ops[j]->pdinv, rhs[j], x[j],
-                             block ? ops[j]->pbinv : nullptr};
+                             block ? ops[j]->pbinv : nullptr, f32 ? ops[j]->pval32 : nullptr};
     }
     RB_HIP(hipSetDevice(ctx->device));
     std::vector<int> iters((size_t)count), status((size_t)count);
@@ -475,12 +479,16 @@ int rbffd_server_submit(rbffd_server *sv, const rbffd_ops *ops, const double *rh
     if (!sv->impl) return fail(RBFFD_E_ARG, "the server's context was destroyed");
     if (!ops->ctx) return fail(RBFFD_E_ARG, "the operators' context was destroyed");
     if (!(opts->tol >= 0.0) || opts->max_iter < 1) return fail(RBFFD_E_ARG, "bad Krylov options");
-    if (opts->precision != RBFFD_FP64) return fail(RBFFD_E_ARG, "served solves run in FP64");
+    if (opts->precision != RBFFD_FP64 && opts->precision != RBFFD_FP32_MATRIX)
+        return fail(RBFFD_E_ARG, "served solves run in RBFFD_FP64 or RBFFD_FP32_MATRIX");
     if (opts->preconditioner != RBFFD_PREC_JACOBI && opts->preconditioner != RBFFD_PREC_BLOCK64)
         return fail(RBFFD_E_ARG, "unknown preconditioner");
+    const bool f32 = opts->precision == RBFFD_FP32_MATRIX;
+    if (f32 && !ops->pval32) return fail(RBFFD_E_ARG, "operators were assembled without FP32 copies");
     RB_HIP(hipSetDevice(sv->ctx->device));
     const BatchSystem sys{ops->n, ops->q, cols_of(ops), ops->pval, ops->pdinv, rhs, x,
-                          opts->preconditioner == RBFFD_PREC_BLOCK64 ? ops->pbinv : nullptr};
+                          opts->preconditioner == RBFFD_PREC_BLOCK64 ? ops->pbinv : nullptr,
+                          f32 ? ops->pval32 : nullptr};
     return server_submit(sv->impl, sys, opts->tol, opts->max_iter, ticket);
 }
 

@@ -259,7 +259,8 @@ struct BatchSystem {
     ColIdx col;
     const double *val, *dinv, *b;
     double *x;
-    const float *binv;   // block-Jacobi inverses, or nullptr for Jacobi
+    const float *binv;    // block-Jacobi inverses, or nullptr for Jacobi
+    const float *val32;   // FP32 matrix for the Krylov SpMVs (FP64 residuals), or nullptr
 };
 // FP64 BiCGSTAB on many independent systems at once: every kernel stage is one
 // launch over all systems, each system owns a fixed range of blocks and its own

@@ -987,6 +987,7 @@ struct BSys {
     double tol2;
     ColIdx col;
     const double *val, *dinv, *b;
+    const float *val32;   // FP32 matrix for the Krylov SpMVs, or nullptr (FP64)
     const float *binv;
     double *x;
     double *r, *rh, *ph, *v, *s, *sh, *t, *p;
@@ -1075,7 +1076,10 @@ __global__ __launch_bounds__(kKB) void kb_v(const BSys *__restrict__ sys, const 
             continue;
         }
         double av[1];
-        row_dot<double, double, 1>(i, S.q, S.col, S.val, S.ph, 0, act, av);
+        if (S.val32)
+            row_dot<float, double, 1>(i, S.q, S.col, S.val32, S.ph, 0, act, av);
+        else
+            row_dot<double, double, 1>(i, S.q, S.col, S.val, S.ph, 0, act, av);
         S.v[i] = av[0];
         srv += S.rh[i] * av[0];
     }
@@ -1157,7 +1161,10 @@ __global__ __launch_bounds__(kKB) void kb_t(const BSys *__restrict__ sys, const 
             continue;
         }
         double at[1];
-        row_dot<double, double, 1>(i, S.q, S.col, S.val, S.sh, 0, act, at);
+        if (S.val32)
+            row_dot<float, double, 1>(i, S.q, S.col, S.val32, S.sh, 0, act, at);
+        else
+            row_dot<double, double, 1>(i, S.q, S.col, S.val, S.sh, 0, act, at);
         S.t[i] = at[0];
         acc[0] += at[0] * S.s[i];
         acc[1] += at[0] * at[0];
@@ -1671,6 +1678,7 @@ int bicgstab_batched(rbffd_ctx *ctx, int count, const BatchSystem *sys, double t
         B.col = sys[j].col;
         B.val = sys[j].val;
         B.dinv = sys[j].dinv;
+        B.val32 = sys[j].val32;
         B.binv = sys[j].binv;
         B.b = sys[j].b;
         B.x = sys[j].x;
@@ -1893,6 +1901,7 @@ static int server_layout(Server *sv, hipStream_t s)
         B.col = a.sys.col;
         B.val = a.sys.val;
         B.dinv = a.sys.dinv;
+        B.val32 = a.sys.val32;
         B.binv = a.sys.binv;
         B.b = a.sys.b;
         B.x = a.sys.x;

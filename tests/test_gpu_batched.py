@@ -1,6 +1,7 @@
 """Batched pressure-correction solves through the C ABI: each system of a batch
 matches the FP64 oracle, and is bitwise the same alone and in the mix, with the
-Jacobi and with the block-Jacobi preconditioner."""
+Jacobi and with the block-Jacobi preconditioner, in FP64 and with FP32 matrix
+values refined by FP64 residuals."""
 import numpy as np
 import pytest
 
@@ -36,7 +37,7 @@ def batch(ctx, orc):
     out = []
     for j, (name, gen, k) in enumerate(SYSTEMS):
         c = gen()
-        s = R.Solver(ctx, c, k)
+        s = R.Solver(ctx, c, k, precision=R.RBFFD_FP32_MATRIX)   # FP64 operators plus FP32 copies
         ops_o = orc.build_operators(c, k)
         b = np.random.default_rng(100 + j).standard_normal(c.n)
         print(f"[batch] {name}: n={c.n} q={s.q}", flush=True)
@@ -47,12 +48,32 @@ def batch(ctx, orc):
 PCS = {"jacobi": R.RBFFD_PREC_JACOBI, "block64": R.RBFFD_PREC_BLOCK64}
 
 
-def _solve(ctx, items, tol, pc=R.RBFFD_PREC_JACOBI):
+def _solve(ctx, items, tol, pc=R.RBFFD_PREC_JACOBI, precision=R.RBFFD_FP64):
     xs = [torch.zeros(it[1].n, dtype=torch.float64, device="cuda") for it in items]
     rhs = [torch.tensor(it[4], device="cuda") for it in items]
     st = R.poisson_solve_batched(ctx, [it[2].ops for it in items], rhs, xs, tol=tol, max_iter=20000,
-                                 allow_noconv=True, preconditioner=pc)
+                                 allow_noconv=True, preconditioner=pc, precision=precision)
     return [x.cpu().numpy() for x in xs], st
+
+
+@pytest.mark.parametrize("pc", sorted(PCS))
+def test_batched_fp32_matrix_matches_oracle(ctx, orc, batch, pc):
+    """FP32 matrix values in the Krylov SpMVs, FP64 residual refinement: every
+    system reaches its FP64 residual tolerance and stays within the
+    reduced-precision bar (1e-5) of the oracle; alone equals in the mix."""
+    xs, st = _solve(ctx, batch, 1e-8, PCS[pc], R.RBFFD_FP32_MATRIX)
+    for (name, c, s, ops_o, b), x, sj in zip(batch, xs, st):
+        xo, _, rr_o, st_o = orc.bicgstab(ops_o.col, ops_o.pval, b, tol=1e-12, maxit=20000)
+        err = float(np.abs(x - xo).max() / np.abs(xo).max())
+        print(f"[batch fp32 matrix {pc}] {name}: iters {sj['iters']} status {sj['status']} "
+              f"relres {sj['relres']:.1e} diff {err:.1e}", flush=True)
+        if st_o != 0:
+            continue
+        assert sj["relres"] <= 1e-7
+        assert err <= 1e-5
+    x1, st1 = _solve(ctx, [batch[3]], 1e-8, PCS[pc], R.RBFFD_FP32_MATRIX)
+    assert st1[0]["iters"] == st[3]["iters"]
+    np.testing.assert_array_equal(x1[0], xs[3])
 
 
 @pytest.mark.parametrize("pc", sorted(PCS))
@@ -127,24 +148,37 @@ def test_batched_rejects_bad_arguments(ctx, batch):
     import ctypes as C
     arr = C.c_void_p * 1
     x = torch.zeros(batch[0][1].n, dtype=torch.float64, device="cuda")
-    for prec, pc in ((R.RBFFD_FP32_IR, 0), (R.RBFFD_FP64, 7)):     # mixed precision; unknown preconditioner
+    for prec, pc in ((R.RBFFD_FP32_IR, 0), (R.RBFFD_FP64, 7)):     # FP32 vectors; unknown preconditioner
         o = R.binding.KrylovOptsT(1e-8, 100, prec, pc)
         st = L.poisson_solve_batched(ctx.handle, 1, arr(batch[0][2].ops.handle), arr(R.binding._ptr(x)),
                                      arr(R.binding._ptr(x)), C.byref(o), None, R.binding._stream())
         assert st == -1
     with pytest.raises(ValueError):     # extents are checked before the call
         R.poisson_solve_batched(ctx, [batch[0][2].ops], [x[:-1]], [x])
+    # FP32 matrix values need operators assembled with FP32 copies
+    c = W.kovasznay_square(nx=8)
+    s64 = R.Solver(ctx, c, 2)
+    x8 = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+    o = R.binding.KrylovOptsT(1e-8, 100, R.RBFFD_FP32_MATRIX, 0)
+    assert L.poisson_solve_batched(ctx.handle, 1, arr(s64.ops.handle), arr(R.binding._ptr(x8)),
+                                   arr(R.binding._ptr(x8)), C.byref(o), None, R.binding._stream()) == -1
+    sv = R.Server(ctx)
+    with pytest.raises(R.RbffdError):
+        sv.submit(s64.ops, x8, x8.clone(), precision=R.RBFFD_FP32_MATRIX)
+    sv.close()
 
 
 def test_server_staggered_equals_alone(ctx, batch):
     """Continuous batching: solves joining a running batch at different times,
-    alternately with the Jacobi and the block-Jacobi preconditioner, give
-    bitwise the results of each solve alone."""
+    alternately with the Jacobi and the block-Jacobi preconditioner, two of
+    them with FP32 matrix values, give bitwise the results of each solve
+    alone."""
     items = batch[:5]
     pcs = [R.RBFFD_PREC_JACOBI if j % 2 == 0 else R.RBFFD_PREC_BLOCK64 for j in range(len(items))]
+    precs = [R.RBFFD_FP32_MATRIX if j in (1, 2) else R.RBFFD_FP64 for j in range(len(items))]
     alone, st_alone = [], []
-    for it, pc in zip(items, pcs):
-        x1, s1 = _solve(ctx, [it], 1e-10, pc)
+    for it, pc, pr in zip(items, pcs, precs):
+        x1, s1 = _solve(ctx, [it], 1e-10, pc, pr)
         alone.append(x1[0])
         st_alone.append(s1[0])
     sv = R.Server(ctx)
@@ -153,7 +187,7 @@ def test_server_staggered_equals_alone(ctx, batch):
     done = {}
     for j, it in enumerate(items):
         x = torch.zeros(it[1].n, dtype=torch.float64, device="cuda")
-        t = sv.submit(it[2].ops, rhs[j], x, tol=1e-10, max_iter=20000, preconditioner=pcs[j])
+        t = sv.submit(it[2].ops, rhs[j], x, tol=1e-10, max_iter=20000, preconditioner=pcs[j], precision=precs[j])
         xs[t], tickets[t] = x, j
         sv.run(8 + 5 * j)          # others keep running while the next one arrives
         for t2, st in sv.poll():
