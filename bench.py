@@ -696,7 +696,7 @@ def main():
                 ("fp64_block_jacobi", solves64b), ("fp32_vectors_and_matrix_block_jacobi", solves32b),
                 ("fp32_matrix_fp64_vectors_block_jacobi", solves32mb))},
             "note": "both mixed modes: FP64 row and dot accumulation, FP64 reliable residual updates; "
-                    "entries without a suffix use the Jacobi preconditioner, *_block_jacobi the FP32 inverses "
+                    "entries without a suffix use the Jacobi preconditioner, *_block_jacobi the FP16 inverses "
                     "of the 64x64 diagonal blocks; speedups against fp64 with Jacobi",
         },
     }

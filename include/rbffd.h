@@ -64,8 +64,8 @@ extern "C" {
 #define RBFFD_PREC_JACOBI 0     /* diagonal (Jacobi), applied on the right               */
 #define RBFFD_PREC_BLOCK64 1    /* inverses of the 64 x 64 diagonal blocks of the 64-row
                                    slices (Morton-compact patches of 64 points), stored
-                                   in FP32 and applied on the right with FP64
-                                   accumulation; any precision in poisson_solve and
+                                   in FP16 scaled per block and applied on the right
+                                   with FP64 accumulation; any precision in poisson_solve and
                                    simple_step, RBFFD_FP64 or RBFFD_FP32_MATRIX in
                                    batched and served solves                            */
 
@@ -154,7 +154,8 @@ int rbffd_ops_info(const rbffd_ops *ops, int64_t *n, int *q, int *dim, int64_t *
  * holding d/dx, d/dy, (d/dz), Laplacian and the pressure-correction matrix. */
 int rbffd_ops_export_csr(const rbffd_ops *ops, int32_t *col, double *val, void *hip_stream);
 /* The block-Jacobi preconditioner of the pressure-correction matrix: for each
- * 64-row slice s, the inverse of its 64 x 64 diagonal block in FP32,
+ * 64-row slice s, the inverse of its 64 x 64 diagonal block as the solver
+ * holds it (FP16 values times an FP32 per-block scale), expanded to FP32,
  * column-major (entry (row l, column j) at out[s*4096 + j*64 + l]; padding rows
  * of the last slice are identity rows). out: device [ceil(n/64) * 4096]. */
 int rbffd_ops_export_block_inverse(const rbffd_ops *ops, float *out, void *hip_stream);

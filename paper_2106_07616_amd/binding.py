@@ -261,7 +261,8 @@ class Operators:
         return col, val
 
     def export_block_inverse(self):
-        """[ceil(n/64), 64 (column), 64 (row)] FP32 inverses of the diagonal blocks."""
+        """[ceil(n/64), 64 (column), 64 (row)] inverses of the diagonal blocks
+        (the solver's FP16 values times their per-block scale, in FP32)."""
         nb = (self.n + 63) // 64
         out = torch.empty((nb, 64, 64), dtype=torch.float32, device=self.cloud.xyz.device)
         _check(lib().rbffd_ops_export_block_inverse(self.handle, _ptr(out), _stream()))

@@ -244,7 +244,7 @@ int rbffd_assemble(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_stencil
 static void release_ops_memory(rbffd_ops *ops)
 {
     void **ptrs[] = {(void **)&ops->kind,   (void **)&ops->normal, (void **)&ops->col,    (void **)&ops->cbase,
-                     (void **)&ops->col16,  (void **)&ops->val,    (void **)&ops->pval,   (void **)&ops->pdinv, (void **)&ops->pbinv,
+                     (void **)&ops->col16,  (void **)&ops->val,    (void **)&ops->pval,   (void **)&ops->pdinv, (void **)&ops->pbinv, (void **)&ops->pbscale,
                      (void **)&ops->pval32, (void **)&ops->pdinv32, (void **)&ops->mval, (void **)&ops->mdinv,
                      (void **)&ops->mval32, (void **)&ops->mdinv32, (void **)&ops->bidx, (void **)&ops->bpos,
                      (void **)&ops->gcol,   (void **)&ops->gval,   (void **)&ops->gdinv};
@@ -294,7 +294,7 @@ int rbffd_ops_export_block_inverse(const rbffd_ops *ops, float *out, void *hip_s
     if (!ops->ctx) return fail(RBFFD_E_ARG, "the operators' context was destroyed");
     RB_HIP(hipSetDevice(ops->ctx->device));
     hipStream_t s = (hipStream_t)hip_stream;
-    RB_HIP(hipMemcpyAsync(out, ops->pbinv, sizeof(float) * ops->npad * 64, hipMemcpyDeviceToDevice, s));
+    RB_CHECK(expand_block_inverse(ops, out, s));
     RB_HIP(hipStreamSynchronize(s));
     return RBFFD_OK;
 }
@@ -382,14 +382,14 @@ int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, doubl
         return fail(RBFFD_E_ARG, "unknown preconditioner");
     const bool block = opts->preconditioner == RBFFD_PREC_BLOCK64;
     if (block && opts->precision == RBFFD_FP64)
-        st = bicgstab_block(ctx, ops->n, ops->q, cols_of(ops), ops->pval, ops->pbinv, rhs, x, opts->tol,
+        st = bicgstab_block(ctx, ops->n, ops->q, cols_of(ops), ops->pval, binv_of(ops), rhs, x, opts->tol,
                             opts->max_iter, &res, s);
     else if (opts->precision == RBFFD_FP64)
         st = bicgstab(ctx, ops->n, ops->q, cols_of(ops), ops->pval, ops->pdinv, 1, rhs, x, opts->tol,
                       opts->max_iter, &res, s);
     else
         st = bicgstab_mixed(ctx, opts->precision, ops->n, ops->q, cols_of(ops), ops->pval, ops->pval32, ops->pdinv32,
-                            ops->pdinv, block ? ops->pbinv : nullptr, 1, rhs, x, opts->tol, opts->max_iter, &res,
+                            ops->pdinv, block ? binv_of(ops) : kNoBlockInv, 1, rhs, x, opts->tol, opts->max_iter, &res,
                             &refine, s);
     if (st != RBFFD_OK) return st;
     double rr = 0.0;
@@ -428,7 +428,7 @@ int poisson_solve_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops
         if (f32 && !ops[j]->pval32)
             return fail(RBFFD_E_ARG, "system " + std::to_string(j) + " was assembled without FP32 copies");
         sys[j] = BatchSystem{ops[j]->n, ops[j]->q, cols_of(ops[j]), ops[j]->pval, ops[j]->pdinv, rhs[j], x[j],
-                             block ? ops[j]->pbinv : nullptr, f32 ? ops[j]->pval32 : nullptr};
+                             block ? binv_of(ops[j]) : kNoBlockInv, f32 ? ops[j]->pval32 : nullptr};
     }
     RB_HIP(hipSetDevice(ctx->device));
     std::vector<int> iters((size_t)count), status((size_t)count);
@@ -487,7 +487,7 @@ int rbffd_server_submit(rbffd_server *sv, const rbffd_ops *ops, const double *rh
     if (f32 && !ops->pval32) return fail(RBFFD_E_ARG, "operators were assembled without FP32 copies");
     RB_HIP(hipSetDevice(sv->ctx->device));
     const BatchSystem sys{ops->n, ops->q, cols_of(ops), ops->pval, ops->pdinv, rhs, x,
-                          opts->preconditioner == RBFFD_PREC_BLOCK64 ? ops->pbinv : nullptr,
+                          opts->preconditioner == RBFFD_PREC_BLOCK64 ? binv_of(ops) : kNoBlockInv,
                           f32 ? ops->pval32 : nullptr};
     return server_submit(sv->impl, sys, opts->tol, opts->max_iter, ticket);
 }

@@ -198,11 +198,13 @@ __global__ __launch_bounds__(64) void slice_offsets(const int32_t *__restrict__ 
 // pressure-correction matrix (a block-Jacobi preconditioner whose blocks are
 // Morton-compact patches of 64 points): Gauss-Jordan elimination with partial
 // pivoting (largest |a|, ties to the lowest row) in LDS, one wavefront per
-// slice, one row per lane. Stored in FP32, column-major per block: entry
-// (row l, column j) at j*64 + l. Padding rows are identity rows. A block
-// whose pivot falls to 1e-13 max|block| or below keeps the Jacobi diagonal.
+// slice, one row per lane. Stored in FP16 divided by the inverse's largest
+// |entry| (kept in FP32 per block), column-major per block: entry (row l,
+// column j) at j*64 + l. Padding rows are identity rows. A block whose pivot
+// falls to 1e-13 max|block| or below keeps the Jacobi diagonal.
 __global__ __launch_bounds__(64) void block_inverse(const int32_t *__restrict__ col, const double *__restrict__ pval,
-                                                    int64_t n, int q, float *__restrict__ binv)
+                                                    int64_t n, int q, __half *__restrict__ binv,
+                                                    float *__restrict__ bscale)
 {
     __shared__ double A[64][65];
     __shared__ double B[64][65];
@@ -260,9 +262,27 @@ __global__ __launch_bounds__(64) void block_inverse(const int32_t *__restrict__ 
         }
         __syncthreads();
     }
-    float *out = binv + sl * 4096;
-    for (int j = 0; j < 64; ++j)
-        out[j * 64 + l] = singular ? ((j == l && diag != 0.0) ? (float)(1.0 / diag) : 0.0f) : (float)B[l][j];
+    double emax = 0.0;
+    for (int j = 0; j < 64; ++j) {
+        const double e = singular ? ((j == l && diag != 0.0) ? 1.0 / diag : 0.0) : B[l][j];
+        emax = fmax(emax, fabs(e));
+    }
+    emax = wave_max(emax);
+    const double sc = (emax > 0.0 && emax < 3.0e38) ? emax : 1.0;
+    __half *out = binv + sl * 4096;
+    for (int j = 0; j < 64; ++j) {
+        const double e = singular ? ((j == l && diag != 0.0) ? 1.0 / diag : 0.0) : B[l][j];
+        out[j * 64 + l] = __float2half((float)(e / sc));
+    }
+    if (l == 0) bscale[sl] = (float)sc;
+}
+
+// FP32 copy of the block inverses (value x scale), for export
+__global__ void expand_blocks(int64_t total, const __half *__restrict__ v, const float *__restrict__ sc,
+                              float *__restrict__ out)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e < total) out[e] = __half2float(v[e]) * sc[e >> 12];
 }
 
 template <typename T>
@@ -325,7 +345,9 @@ int assemble_ops(rbffd_ctx *ctx, const rbffd_cloud *cloud, int q, int k, int phs
 
     // block-Jacobi preconditioner of the pressure-correction matrix
     RB_CHECK(alloc_ops(ops, &ops->pbinv, (size_t)npad * 64));
-    hipLaunchKernelGGL(block_inverse, dim3(nslices), dim3(64), 0, s, ops->col, ops->pval, n, q, ops->pbinv);
+    RB_CHECK(alloc_ops(ops, &ops->pbscale, (size_t)nslices));
+    hipLaunchKernelGGL(block_inverse, dim3(nslices), dim3(64), 0, s, ops->col, ops->pval, n, q, ops->pbinv,
+                       ops->pbscale);
     RB_HIP(hipGetLastError());
 
     // boundary numbering
@@ -384,6 +406,15 @@ int assemble_ops(rbffd_ctx *ctx, const rbffd_cloud *cloud, int q, int k, int phs
 int launch_to_fp32(const double *x, float *y, int64_t m, hipStream_t s)
 {
     hipLaunchKernelGGL(to_fp32, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, x, y, m);
+    RB_HIP(hipGetLastError());
+    return RBFFD_OK;
+}
+
+int expand_block_inverse(const rbffd_ops *ops, float *out, hipStream_t s)
+{
+    const int64_t total = ops->npad * 64;
+    hipLaunchKernelGGL(expand_blocks, dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, total,
+                       ops->pbinv, ops->pbscale, out);
     RB_HIP(hipGetLastError());
     return RBFFD_OK;
 }

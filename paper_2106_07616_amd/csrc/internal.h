@@ -2,6 +2,7 @@
 // objects, device helpers, kernel launch wrappers. Not part of the C ABI.
 #pragma once
 
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -124,8 +125,9 @@ struct rbffd_ops {
     double *val = nullptr;              // [R][npad*q]  d/dx, d/dy, (d/dz), Laplacian
     double *pval = nullptr;             // [npad*q]     pressure-correction matrix
     double *pdinv = nullptr;            // [npad]       1 / diag(P)
-    float *pbinv = nullptr;             // [npad/64][64][64] inverse of each 64-row diagonal block of P
-                                        //              (FP32, column-major per block)
+    __half *pbinv = nullptr;            // [npad/64][64][64] inverse of each 64-row diagonal block of P
+                                        //              (FP16 divided by pbscale, column-major per block)
+    float *pbscale = nullptr;           // [npad/64]    largest |entry| of each block's inverse
     float *pval32 = nullptr;            // [npad*q]     FP32 copy (RBFFD_FP32_IR)
     float *pdinv32 = nullptr;           // [npad]
     double *mval = nullptr;             // [npad*q]     momentum matrix (rebuilt per outer iteration)
@@ -154,6 +156,17 @@ struct ColIdx {
 
 inline ColIdx cols_of(const rbffd_ops *ops) { return ColIdx{ops->col, ops->cbase, ops->col16}; }
 inline ColIdx cols_plain(const int32_t *col) { return ColIdx{col, nullptr, nullptr}; }
+
+// Block-Jacobi preconditioner: the inverse of each 64-row slice's diagonal
+// block in FP16, divided by the block's largest |entry| (scale), so every
+// stored value lies in [-1, 1]. val == nullptr: no block preconditioner.
+struct BlockInv {
+    const __half *val;
+    const float *scale;
+};
+
+inline BlockInv binv_of(const rbffd_ops *ops) { return BlockInv{ops->pbinv, ops->pbscale}; }
+constexpr BlockInv kNoBlockInv{nullptr, nullptr};
 
 // ---------------------------------------------------------------------------
 // device helpers
@@ -223,6 +236,8 @@ int launch_interp(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int64_t
 int assemble_ops(rbffd_ctx *ctx, const rbffd_cloud *cloud, int q, int k, int phs,
                  const int32_t *nbr, const double *w, int precision, rbffd_ops *ops, hipStream_t s);
 int export_csr(const rbffd_ops *ops, int32_t *col, double *val, hipStream_t s);
+// FP32 copy of the block-Jacobi inverses (FP16 value x block scale), out [npad*64]
+int expand_block_inverse(const rbffd_ops *ops, float *out, hipStream_t s);
 int apply_op(rbffd_ctx *ctx, const rbffd_ops *ops, int which, const double *x, double *y,
              hipStream_t s);
 
@@ -240,16 +255,16 @@ struct KrylovResult {
 };
 // FP64 BiCGSTAB right-preconditioned by the inverses of the 64x64 diagonal
 // blocks of the 64-row slices (one right-hand side).
-int bicgstab_block(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, const float *binv,
+int bicgstab_block(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, BlockInv binv,
                    const double *b, double *x, double tol, int max_iter, KrylovResult *res, hipStream_t s);
 int bicgstab(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val,
              const double *dinv, int nrhs, const double *b, double *x, double tol, int max_iter,
              KrylovResult *res, hipStream_t s);
 // FP32 matrix values with FP64 row accumulation and FP64 reliable updates;
 // precision RBFFD_FP32_IR keeps the Krylov vectors in FP32, RBFFD_FP32_MATRIX in FP64.
-// binv: block-Jacobi inverses (one right-hand side), or nullptr for Jacobi.
+// binv: block-Jacobi inverses (one right-hand side), or binv.val nullptr for Jacobi.
 int bicgstab_mixed(rbffd_ctx *ctx, int precision, int64_t n, int q, ColIdx col, const double *val,
-                   const float *val32, const float *dinv32, const double *dinv64, const float *binv, int nrhs,
+                   const float *val32, const float *dinv32, const double *dinv64, BlockInv binv, int nrhs,
                    const double *b, double *x, double tol, int max_iter, KrylovResult *res, int *refinements,
                    hipStream_t s);
 // One system of a batched solve (host description).
@@ -259,7 +274,7 @@ struct BatchSystem {
     ColIdx col;
     const double *val, *dinv, *b;
     double *x;
-    const float *binv;    // block-Jacobi inverses, or nullptr for Jacobi
+    BlockInv binv;        // block-Jacobi inverses (binv.val nullptr: Jacobi)
     const float *val32;   // FP32 matrix for the Krylov SpMVs (FP64 residuals), or nullptr
 };
 // FP64 BiCGSTAB on many independent systems at once: every kernel stage is one

@@ -762,17 +762,18 @@ int bicgstab_t(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const T *val, const
 // holds y_l, and z_l = sum_j Minv[l][j] y_j with y_j broadcast across the wave.
 // The row loops therefore run over whole slices (up to npad) so that every
 // lane takes part in the broadcasts; loads and stores stay within n.
-__device__ inline double bj_apply(const float *__restrict__ blk, double y, int lane)
+__device__ inline double bj_apply(const BlockInv &bi, int64_t slice, double y, int lane)
 {
+    const __half *__restrict__ blk = bi.val + slice * 4096;
     double z = 0.0;
 #pragma unroll 8
-    for (int j = 0; j < 64; ++j) z = fma((double)blk[j * 64 + lane], __shfl(y, j, 64), z);
-    return z;
+    for (int j = 0; j < 64; ++j) z = fma((double)__half2float(blk[j * 64 + lane]), __shfl(y, j, 64), z);
+    return z * (double)bi.scale[slice];
 }
 
 // r = b - A x, r-hat = r, p = r, p-hat = M^-1 r; partials r.r and b.b
 __global__ __launch_bounds__(kKB) void kbj_init(int64_t n, int64_t np, int q, ColIdx col, const double *__restrict__ val,
-                                                const float *__restrict__ binv, const double *__restrict__ b,
+                                                BlockInv binv, const double *__restrict__ b,
                                                 const double *__restrict__ x, double *__restrict__ r,
                                                 double *__restrict__ rh, double *__restrict__ p,
                                                 double *__restrict__ ph, double *__restrict__ part)
@@ -793,7 +794,7 @@ __global__ __launch_bounds__(kKB) void kbj_init(int64_t n, int64_t np, int q, Co
             acc[0] += ri * ri;
             acc[1] += bi * bi;
         }
-        const double z = bj_apply(binv + (i >> 6) * 4096, ri, lane);
+        const double z = bj_apply(binv, i >> 6, ri, lane);
         if (i < n) ph[i] = z;
     }
     double *ps[2] = {partial(part, P_RR, 0), partial(part, P_BB, 0)};
@@ -802,7 +803,7 @@ __global__ __launch_bounds__(kKB) void kbj_init(int64_t n, int64_t np, int q, Co
 
 // KS: alpha = rho / r-hat.v; s = r - alpha v; s-hat = M^-1 s; partials s.s, r-hat.s
 template <typename T>
-__global__ __launch_bounds__(kKB) void kbj_s(int64_t n, int64_t np, const float *__restrict__ binv,
+__global__ __launch_bounds__(kKB) void kbj_s(int64_t n, int64_t np, BlockInv binv,
                                              const T *__restrict__ r, const T *__restrict__ rh,
                                              const T *__restrict__ v, T *__restrict__ s,
                                              T *__restrict__ sh, double *__restrict__ part, KState *__restrict__ st,
@@ -837,7 +838,7 @@ __global__ __launch_bounds__(kKB) void kbj_s(int64_t n, int64_t np, const float 
             acc[0] += si * si;
             acc[1] += (double)rh[i] * si;
         }
-        const double z = bj_apply(binv + (i >> 6) * 4096, si, lane);
+        const double z = bj_apply(binv, i >> 6, si, lane);
         if (i < n) sh[i] = (T)z;
     }
     double *ps[2] = {partial(part, P_SS, 0), partial(part, P_RS, 0)};
@@ -847,7 +848,7 @@ __global__ __launch_bounds__(kKB) void kbj_s(int64_t n, int64_t np, const float 
 // KX: omega; x += alpha p-hat + omega s-hat; r = s - omega t; p = r + beta (p -
 // omega v); p-hat = M^-1 p; partial r.r (restart and beta as in k_x)
 template <typename T>
-__global__ __launch_bounds__(kKB) void kbj_x(int64_t n, int64_t np, const float *__restrict__ binv,
+__global__ __launch_bounds__(kKB) void kbj_x(int64_t n, int64_t np, BlockInv binv,
                                              T *__restrict__ x, T *__restrict__ p, T *__restrict__ ph,
                                              const T *__restrict__ s, const T *__restrict__ sh,
                                              const T *__restrict__ t, const T *__restrict__ v,
@@ -892,7 +893,7 @@ __global__ __launch_bounds__(kKB) void kbj_x(int64_t n, int64_t np, const float 
             pn = (double)pt;
             srr += ri * ri;
         }
-        const double z = bj_apply(binv + (i >> 6) * 4096, pn, lane);
+        const double z = bj_apply(binv, i >> 6, pn, lane);
         if (i < n) ph[i] = (T)z;
     }
     double *ps[1] = {partial(part, P_RR, 0)};
@@ -905,7 +906,7 @@ __global__ __launch_bounds__(kKB) void kbj_x(int64_t n, int64_t np, const float 
 // r-hat = p = r, p-hat = M^-1 r and the ||b||^2 partials are written as well.
 template <typename T>
 __global__ __launch_bounds__(kKB) void kbj_rel_resid(int64_t n, int64_t np, int q, ColIdx col,
-                                                     const double *__restrict__ val, const float *__restrict__ binv,
+                                                     const double *__restrict__ val, BlockInv binv,
                                                      const double *__restrict__ b, const double *__restrict__ x,
                                                      T *__restrict__ r, T *__restrict__ rh, T *__restrict__ p,
                                                      T *__restrict__ ph, int init, double *__restrict__ part,
@@ -938,7 +939,7 @@ __global__ __launch_bounds__(kKB) void kbj_rel_resid(int64_t n, int64_t np, int 
             bb += bi * bi;
         }
         if (init) {
-            const double z = bj_apply(binv + (i >> 6) * 4096, rf, lane);
+            const double z = bj_apply(binv, i >> 6, rf, lane);
             if (i < n) ph[i] = (T)z;
         }
     }
@@ -958,7 +959,7 @@ __global__ __launch_bounds__(kKB) void kbj_rel_resid(int64_t n, int64_t np, int 
 // r-hat = p = r, p-hat = M^-1 r (a solve that continues after its recursion
 // had stopped); one thread per row, whole slices per wavefront
 template <typename T>
-__global__ void kbj_dir_reset(int64_t n, int64_t np, const float *__restrict__ binv, const T *__restrict__ r,
+__global__ void kbj_dir_reset(int64_t n, int64_t np, BlockInv binv, const T *__restrict__ r,
                               T *__restrict__ rh, T *__restrict__ p, T *__restrict__ ph)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -970,7 +971,7 @@ __global__ void kbj_dir_reset(int64_t n, int64_t np, const float *__restrict__ b
         p[i] = rt;
         ri = (double)rt;
     }
-    const double z = bj_apply(binv + (i >> 6) * 4096, ri, threadIdx.x & 63);
+    const double z = bj_apply(binv, i >> 6, ri, threadIdx.x & 63);
     if (i < n) ph[i] = (T)z;
 }
 
@@ -988,7 +989,7 @@ struct BSys {
     ColIdx col;
     const double *val, *dinv, *b;
     const float *val32;   // FP32 matrix for the Krylov SpMVs, or nullptr (FP64)
-    const float *binv;
+    BlockInv binv;        // block-Jacobi inverses (binv.val nullptr: Jacobi)
     double *x;
     double *r, *rh, *ph, *v, *s, *sh, *t, *p;
 };
@@ -1006,7 +1007,7 @@ __global__ __launch_bounds__(kKB) void kb_init(const BSys *__restrict__ sys, con
     const BSys S = sys[j];
     if (!st[j].fresh) return;
     const int lb = blockIdx.x - S.boff;
-    const bool bj = S.binv != nullptr;
+    const bool bj = S.binv.val != nullptr;
     const int64_t lim = bj ? S.np : S.n;
     const int lane = threadIdx.x & 63;
     double rr = 0.0, bb = 0.0;
@@ -1028,7 +1029,7 @@ __global__ __launch_bounds__(kKB) void kb_init(const BSys *__restrict__ sys, con
             bb += bi * bi;
         }
         if (bj) {
-            const double z = bj_apply(S.binv + (i >> 6) * 4096, ri, lane);
+            const double z = bj_apply(S.binv, i >> 6, ri, lane);
             if (i < S.n) S.ph[i] = z;
         }
     }
@@ -1112,7 +1113,7 @@ __global__ __launch_bounds__(kKB) void kb_s(const BSys *__restrict__ sys, const 
     }
     if (rv == 0.0) return;
     const int lb = blockIdx.x - S.boff;
-    const bool bj = S.binv != nullptr;
+    const bool bj = S.binv.val != nullptr;
     const int64_t lim = bj ? S.np : S.n;
     const int lane = threadIdx.x & 63;
     double acc[2] = {0.0, 0.0};
@@ -1126,7 +1127,7 @@ __global__ __launch_bounds__(kKB) void kb_s(const BSys *__restrict__ sys, const 
             acc[1] += S.rh[i] * si;
         }
         if (bj) {
-            const double z = bj_apply(S.binv + (i >> 6) * 4096, si, lane);
+            const double z = bj_apply(S.binv, i >> 6, si, lane);
             if (i < S.n) S.sh[i] = z;
         }
     }
@@ -1206,7 +1207,7 @@ __global__ __launch_bounds__(kKB) void kb_x(const BSys *__restrict__ sys, const 
     }
     const int lb = blockIdx.x - S.boff;
     double srr = 0.0;
-    if (S.binv == nullptr) {
+    if (S.binv.val == nullptr) {
         for (int64_t i = (int64_t)lb * kKB + threadIdx.x; i < S.n; i += (int64_t)S.nblk * kKB) {
             const double di = S.dinv[i];
             const double phi = S.ph[i];
@@ -1231,7 +1232,7 @@ __global__ __launch_bounds__(kKB) void kb_x(const BSys *__restrict__ sys, const 
                 S.p[i] = pn;
                 srr += ri * ri;
             }
-            const double z = bj_apply(S.binv + (i >> 6) * 4096, pn, lane);
+            const double z = bj_apply(S.binv, i >> 6, pn, lane);
             if (i < S.n) S.ph[i] = z;
         }
     }
@@ -1293,7 +1294,7 @@ static int bicgstab_once(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const dou
     }
 }
 
-static int bicgstab_block_once(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, const float *binv,
+static int bicgstab_block_once(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, BlockInv binv,
                                const double *b, double *x, double tol, int max_iter, KrylovResult *res,
                                hipStream_t s)
 {
@@ -1339,7 +1340,7 @@ static int bicgstab_block_once(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, con
     return RBFFD_OK;
 }
 
-int bicgstab_block(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, const float *binv,
+int bicgstab_block(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, BlockInv binv,
                    const double *b, double *x, double tol, int max_iter, KrylovResult *res, hipStream_t s)
 {
     KrylovResult acc;
@@ -1403,11 +1404,11 @@ constexpr int kStallIters = 1000;   // forced update; less than 2x progress sinc
 
 template <typename T, int NRHS>
 static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val,
-                             const float *val32, const T *dinv, const double *dinv64, const float *binv,
+                             const float *val32, const T *dinv, const double *dinv64, BlockInv binv,
                              const double *b, double *x, double tol, int max_iter, KrylovResult *res,
                              int *refinements, hipStream_t s)
 {
-    if (binv && NRHS != 1) return fail(RBFFD_E_ARG, "the block preconditioner takes one right-hand side");
+    if (binv.val && NRHS != 1) return fail(RBFFD_E_ARG, "the block preconditioner takes one right-hand side");
     const int64_t np = pad64(n);
     Work w;
     RB_CHECK(get_work<T>(ctx, np, NRHS, &w));
@@ -1415,12 +1416,12 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const
     const size_t tbytes = sizeof(double) * (2 * kMaxRhs * kMaxBlocks + kMaxRhs);
     const size_t xbytes = sizeof(double) * n * NRHS;
     const size_t dbytes = sizeof(T) * np * NRHS;
-    RB_CHECK(workspace(ctx, WS_REFINE, tbytes + xbytes + dbytes + (binv ? dbytes : 0), (void **)&scr));
+    RB_CHECK(workspace(ctx, WS_REFINE, tbytes + xbytes + dbytes + (binv.val ? dbytes : 0), (void **)&scr));
     double *tpart = (double *)scr;
     double *rout = tpart + 2 * kMaxRhs * kMaxBlocks;
     double *xgood = (double *)(scr + tbytes);       // iterate with the lowest FP64 residual so far
     T *d = (T *)(scr + tbytes + xbytes);            // correction accumulated since the last update
-    T *pv = binv ? (T *)(scr + tbytes + xbytes + dbytes) : nullptr;   // unpreconditioned direction
+    T *pv = binv.val ? (T *)(scr + tbytes + xbytes + dbytes) : nullptr;   // unpreconditioned direction
     double *rr = nullptr;
     RB_CHECK(host_scratch(ctx, kHostRefine, sizeof(double) * kMaxRhs, (void **)&rr));
     KState *hst = nullptr;
@@ -1434,7 +1435,7 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const
 
     // true residual of x: replaces r (and r-hat when init), norms to the host
     auto true_residual = [&](int init) -> int {
-        if (binv)
+        if (binv.val)
             hipLaunchKernelGGL(kbj_rel_resid<T>, g, bl, 0, s, n, np, q, col, val, binv, b, x, r, rh, pv, ph, init,
                                w.part, tpart);
         else
@@ -1467,14 +1468,14 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const
         for (int c = 0; c < todo; ++c) {
             hipLaunchKernelGGL((k_v<T, float, NRHS>), g, bl, 0, s, n, np, q, col, val32, rh, ph, v, d, np, w.part,
                                w.st, nblk, tol2, 0, ++phase);
-            if (binv)
+            if (binv.val)
                 hipLaunchKernelGGL(kbj_s<T>, g, bl, 0, s, n, np, binv, r, rh, v, sv, sh, w.part, w.st, nblk, ++phase);
             else
                 hipLaunchKernelGGL((k_s<T, NRHS>), g, bl, 0, s, n, np, dinv, r, rh, v, sv, sh, w.part, w.st, nblk,
                                    ++phase);
             hipLaunchKernelGGL((k_t<T, float, NRHS>), g, bl, 0, s, n, np, q, col, val32, d, np, ph, sv, sh, rh, t,
                                w.part, w.st, nblk, tol2, ++phase);
-            if (binv)
+            if (binv.val)
                 hipLaunchKernelGGL(kbj_x<T>, g, bl, 0, s, n, np, binv, d, pv, ph, sv, sh, t, v, r, rh, w.part, w.st,
                                    nblk, ++phase);
             else
@@ -1538,7 +1539,7 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const
                 hst[k].refresh = 1;
             }
         }
-        if (mask && binv)
+        if (mask && binv.val)
             hipLaunchKernelGGL(kbj_dir_reset<T>, dim3((unsigned)((np + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n,
                                np, binv, r, rh, pv, ph);
         else if (mask)
@@ -1554,7 +1555,7 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const
     if (fallback && it < max_iter) {
         const int left = max_iter - it;
         KrylovResult fr;
-        if (binv)
+        if (binv.val)
             RB_CHECK(bicgstab_block(ctx, n, q, col, val, binv, b, x, tol, left, &fr, s));
         else
             RB_CHECK(bicgstab(ctx, n, q, col, val, dinv64, NRHS, b, x, tol, left, &fr, s));
@@ -1577,12 +1578,12 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const
 }
 
 int bicgstab_mixed(rbffd_ctx *ctx, int precision, int64_t n, int q, ColIdx col, const double *val,
-                   const float *val32, const float *dinv32, const double *dinv64, const float *binv, int nrhs,
+                   const float *val32, const float *dinv32, const double *dinv64, BlockInv binv, int nrhs,
                    const double *b, double *x, double tol, int max_iter, KrylovResult *res, int *refinements,
                    hipStream_t s)
 {
     if (nrhs < 1 || nrhs > kMaxRhs) return fail(RBFFD_E_ARG, "nrhs must be 1..3");
-    if (binv && nrhs != 1) return fail(RBFFD_E_ARG, "the block preconditioner takes one right-hand side");
+    if (binv.val && nrhs != 1) return fail(RBFFD_E_ARG, "the block preconditioner takes one right-hand side");
     if (precision == RBFFD_FP32_IR) {
         // FP32 vectors and Jacobi diagonal, FP32 matrix
         switch (nrhs) {

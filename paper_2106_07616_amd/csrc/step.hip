@@ -353,8 +353,8 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
             RB_CHECK(launch_to_fp32(ops->mval, ops->mval32, vs, s));
             RB_CHECK(launch_to_fp32(ops->mdinv, ops->mdinv32, ops->npad, s));
             RB_CHECK(bicgstab_mixed(ctx, o->precision, n, q, cols_of(ops), ops->mval, ops->mval32, ops->mdinv32,
-                                    ops->mdinv, nullptr, dim, B.bm, B.ut, o->tol_krylov, o->max_krylov, &km, nullptr,
-                                    s));
+                                    ops->mdinv, kNoBlockInv, dim, B.bm, B.ut, o->tol_krylov, o->max_krylov, &km,
+                                    nullptr, s));
         } else {
             RB_CHECK(bicgstab(ctx, n, q, cols_of(ops), ops->mval, ops->mdinv, dim, B.bm, B.ut, o->tol_krylov, o->max_krylov,
                               &km, s));
@@ -376,10 +376,10 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
         const bool block = o->preconditioner == RBFFD_PREC_BLOCK64;
         if (fp32)
             RB_CHECK(bicgstab_mixed(ctx, o->precision, n, q, cols_of(ops), ops->pval, ops->pval32, ops->pdinv32,
-                                    ops->pdinv, block ? ops->pbinv : nullptr, 1, B.f, B.pc, o->tol_krylov,
+                                    ops->pdinv, block ? binv_of(ops) : kNoBlockInv, 1, B.f, B.pc, o->tol_krylov,
                                     o->max_krylov, &kp, nullptr, s));
         else if (block)
-            RB_CHECK(bicgstab_block(ctx, n, q, cols_of(ops), ops->pval, ops->pbinv, B.f, B.pc, o->tol_krylov,
+            RB_CHECK(bicgstab_block(ctx, n, q, cols_of(ops), ops->pval, binv_of(ops), B.f, B.pc, o->tol_krylov,
                                     o->max_krylov, &kp, s));
         else
             RB_CHECK(bicgstab(ctx, n, q, cols_of(ops), ops->pval, ops->pdinv, 1, B.f, B.pc, o->tol_krylov, o->max_krylov,

@@ -382,9 +382,10 @@ def test_zero_iterations_report_noconv(ctx):
 
 
 def test_block_inverse_blocks(case):
-    """Each exported 64x64 block inverse times the diagonal block of the
-    pressure-correction matrix (from the exported CSR) is the identity, to FP32
-    accuracy scaled by the block's condition."""
+    """Each exported 64x64 block inverse equals numpy's FP64 inverse of the
+    diagonal block of the pressure-correction matrix (from the exported CSR)
+    to FP16 storage accuracy: half an FP16 unit of the block's largest entry
+    (2^-11 relative), plus FP64 rounding amplified by the block's condition."""
     name, c, k, ops_o, s = case
     binv = s.ops.export_block_inverse().cpu().numpy().astype(np.float64)   # [nb, col j, row l]
     col, val = s.ops.export_csr()
@@ -404,12 +405,11 @@ def test_block_inverse_blocks(case):
                 j = col[i, a]
                 if lo <= j < lo + 64:
                     blk[l, j - lo] = pv[i, a]
-        minv = binv[sl].T          # [row, col]
-        prod = minv @ blk
-        cond = np.linalg.cond(blk)
-        worst = max(worst, np.abs(prod - np.eye(64)).max() / max(cond, 1.0))
-    print(f"[block inverse] {name}: max |M^-1 B - I| / cond(B) = {worst:.1e}", flush=True)
-    assert worst <= 1e-5
+        ref = np.linalg.inv(blk)
+        bound = (2.0 ** -11 + 1e-6 + 1e-14 * np.linalg.cond(blk)) * np.abs(ref).max()
+        worst = max(worst, np.abs(binv[sl].T - ref).max() / bound)
+    print(f"[block inverse] {name}: max |stored - inv| / bound = {worst:.2f}", flush=True)
+    assert worst <= 1.0
 
 
 def test_poisson_block_preconditioner(case, ctx, orc):
