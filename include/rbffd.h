@@ -76,6 +76,9 @@ extern "C" {
                                    normal momentum equation (Sec. 3.1)                  */
 #define RBFFD_PRESCRIBED_PRESSURE 2 /* prescribed velocity and prescribed pressure; the
                                    pressure correction is zero there (Sec. 3.1)          */
+#define RBFFD_OUTLET 3          /* outlet with prescribed pressure (p' = 0, pressure from
+                                   p_bc) and zero normal derivative of every velocity
+                                   component (Sec. 3.1); needs the outward normal        */
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *rbffd_last_error(void);
@@ -97,7 +100,7 @@ typedef struct {
     int dim;                /* 2 or 3                                                */
     int64_t n;              /* number of points, 1 <= n < 2^31                       */
     const double *xyz;      /* device [n][dim]; no two points may coincide           */
-    const uint8_t *kind;    /* device [n]: RBFFD_INTERIOR / _DIRICHLET / _PRESCRIBED_PRESSURE */
+    const uint8_t *kind;    /* device [n]: RBFFD_INTERIOR / _DIRICHLET / _PRESCRIBED_PRESSURE / _OUTLET */
     const double *normal;   /* device [n][dim]: unit outward normal (boundary points) */
     int64_t pin;            /* interior point whose pressure correction is 0, or -1
                                (none; needed only when no prescribed-pressure point
@@ -137,8 +140,8 @@ typedef struct rbffd_ops rbffd_ops;
  * column into a sparse matrix with exactly q entries per row, carry the R
  * weight sets along, and build the pressure-correction matrix: the Laplacian
  * row at interior points, N . grad at velocity-Dirichlet boundary points
- * (homogeneous Neumann), the identity row (p' = 0) at prescribed-pressure points
- * and at the pin. `precision` selects
+ * (homogeneous Neumann), the identity row (p' = 0) at prescribed-pressure and
+ * outlet points and at the pin. `precision` selects
  * whether FP32 copies for the mixed-precision modes are made (any value other
  * than RBFFD_FP64). The cloud arrays are copied;
  * nbr and w may be freed afterwards. *out is library-owned: free it with
@@ -292,19 +295,21 @@ typedef struct {
 } rbffd_step_stats;
 
 /* (Sec. 3 and the step list of Sec. 3.2) One BDF time step: starting from
- * u^r = u^n (Dirichlet values of t^{n+1} on boundary points) and p^r = p^n,
- * repeat  momentum solves for u~ (Eqs. u:tilde, v:tilde) -> pressure
- * correction (Eq. pressure poisson) -> interior p += p' -> boundary pressure
- * (Eq. normal momentum on velocity-Dirichlet points, solved for their block
- * with the other pressures fixed; the given value on prescribed-pressure
- * points) -> u = u~ - dt/(rho alpha1) grad p' on interior points -> Delta,
- * until Delta < tol_outer or max_outer.
+ * u^r = u^n (Dirichlet values of t^{n+1} on velocity-prescribed points) and
+ * p^r = p^n, repeat  momentum solves for u~ (Eqs. u:tilde, v:tilde; outlet
+ * rows N . grad u = 0) -> pressure correction (Eq. pressure poisson) ->
+ * interior p += p' -> boundary pressure (Eq. normal momentum on
+ * velocity-Dirichlet points, solved for their block with the other pressures
+ * fixed; the given value on prescribed-pressure and outlet points) ->
+ * u = u~ - dt/(rho alpha1) grad p' on interior points -> Delta, until
+ * Delta < tol_outer or max_outer.
  *   u:      device [dim][n] in: u^n,     out: u^{n+1}
  *   u_prev: device [dim][n] in: u^{n-1}, out: u^n
  *   p:      device [n]      in: p^n,     out: p^{n+1}
- *   u_bc:   device [dim][n] Dirichlet velocity at t^{n+1} (read on boundary rows)
- *   p_bc:   device [n] pressure at t^{n+1} (read on prescribed-pressure rows;
- *           may be NULL when the cloud has none)
+ *   u_bc:   device [dim][n] Dirichlet velocity at t^{n+1} (read on
+ *           velocity-prescribed rows)
+ *   p_bc:   device [n] pressure at t^{n+1} (read on prescribed-pressure and
+ *           outlet rows; may be NULL when the cloud has none)
  * Returns RBFFD_OK, or RBFFD_E_NOCONV when the outer or a Krylov iteration hit
  * its limit (fields hold the last iterate). */
 int simple_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, double *p,

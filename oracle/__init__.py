@@ -308,7 +308,7 @@ def simple_step(ops: Operators, u, u_prev, p, u_bc, rho, mu, dt, alpha=BDF2,
                    tol_outer, tol_krylov, max_outer, max_krylov)
     st = _StepStats()
     pbc = None if p_bc is None else _c(p_bc, np.float64).reshape(n)
-    if pbc is None and (cl.kind == 2).any():
+    if pbc is None and ((cl.kind == 2) | (cl.kind == 3)).any():
         raise ValueError("p_bc is required on clouds with prescribed-pressure points")
     lib().orc_simple_step(C.byref(cfg), _p(u), _p(up), _p(p), _p(ubc), _p(pbc), C.byref(st))
     stats = dict(outer_iters=st.outer_iters, krylov_mom=st.krylov_mom, krylov_p=st.krylov_p,

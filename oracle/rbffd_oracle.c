@@ -552,7 +552,8 @@ int orc_bicgstab(int64_t n, int q, const int32_t *col, const double *val, const 
 /* ---------------------------------------------------------------------- */
 /* Rows: the PHS Laplacian at interior points, the outward normal derivative
  * (homogeneous Neumann, N . grad p' = 0) at velocity-Dirichlet boundary points
- * (kind 1), p' = 0 at prescribed-pressure boundary points (kind 2), and p' = 0
+ * (kind 1), p' = 0 at prescribed-pressure boundary points (kind 2) and at
+ * outlets (kind 3: prescribed pressure, zero normal velocity gradient), and p' = 0
  * at the pinned interior point (pin >= 0), which removes the constant null
  * space when every boundary is of kind 1. Same sparsity as the operators. */
 int orc_poisson_values(int dim, int64_t n, int q, const uint8_t *kind, const double *normal,
@@ -563,7 +564,7 @@ int orc_poisson_values(int dim, int64_t n, int q, const uint8_t *kind, const dou
         for (int a = 0; a < q; ++a) {
             int64_t e = i * q + a;
             double v;
-            if (i == pin || kind[i] == 2) {
+            if (i == pin || kind[i] == 2 || kind[i] == 3) {
                 /* pinned point, or prescribed-pressure boundary: p' = 0 */
                 v = (col[e] == i) ? 1.0 : 0.0;
             } else if (kind[i] == 0) {
@@ -654,14 +655,25 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
     int status = ORC_OK, kit_m = 0, kit_p = 0, kit_b = 0, outer = 0;
     double delta = 0.0;
     /* step 1: the iterate starts from the old time level, with the Dirichlet
-     * values of the new time level on boundary points */
+     * values of the new time level on velocity-prescribed points (kinds 1, 2) */
     for (int e = 0; e < dim; ++e)
-        for (int64_t i = 0; i < n; ++i) ur[e * n + i] = (c->kind[i] != 0) ? u_bc[e * n + i] : u[e * n + i];
+        for (int64_t i = 0; i < n; ++i)
+            ur[e * n + i] = (c->kind[i] == 1 || c->kind[i] == 2) ? u_bc[e * n + i] : u[e * n + i];
     memcpy(pr, p, sizeof(double) * n);
 
     for (outer = 1; outer <= c->max_outer; ++outer) {
         /* step 2: momentum matrix and right-hand sides (Eqs. u:tilde, v:tilde) */
         for (int64_t i = 0; i < n; ++i) {
+            if (c->kind[i] == 3) {
+                /* outlet (Sec. 3.1): N . grad u_e = 0 for every component */
+                for (int a = 0; a < q; ++a) {
+                    double v = 0.0;
+                    for (int d = 0; d < dim; ++d) v = v + c->normal[i * dim + d] * c->val[d * nnz + i * q + a];
+                    mval[i * q + a] = v;
+                }
+                for (int e = 0; e < dim; ++e) bm[e * n + i] = 0.0;
+                continue;
+            }
             if (c->kind[i] != 0) {
                 for (int a = 0; a < q; ++a) mval[i * q + a] = (c->col[i * q + a] == i) ? 1.0 : 0.0;
                 for (int e = 0; e < dim; ++e) bm[e * n + i] = u_bc[e * n + i];
@@ -712,9 +724,9 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
             if (s != ORC_OK) status = s;
         }
         /* step 4: interior pressure correction (Eq. p:correction); prescribed
-         * pressure on kind-2 points */
+         * pressure on kind-2 and outlet (kind-3) points */
         for (int64_t i = 0; i < n; ++i)
-            pa[i] = (c->kind[i] == 0) ? pr[i] + pc[i] : (c->kind[i] == 2 ? p_bc[i] : pr[i]);
+            pa[i] = (c->kind[i] == 0) ? pr[i] + pc[i] : ((c->kind[i] == 2 || c->kind[i] == 3) ? p_bc[i] : pr[i]);
         /* step 5: boundary pressure from the normal momentum equation (Eq. normal
          * momentum), evaluated with u-tilde (the newest velocity at this step)
          * and solved for the whole boundary block with the corrected interior

@@ -74,7 +74,7 @@ __global__ void poisson_rows(const int32_t *__restrict__ col, const double *__re
         const int64_t slot = ell_at(i, a, q);
         const int32_t c = col[slot];
         double v;
-        if (i == pin || kd == RBFFD_PRESCRIBED_PRESSURE) {
+        if (i == pin || kd == RBFFD_PRESCRIBED_PRESSURE || kd == RBFFD_OUTLET) {
             v = (c == i) ? 1.0 : 0.0;
         } else if (kd == RBFFD_INTERIOR) {
             v = val[DIM * vstride + slot];
@@ -94,7 +94,7 @@ __global__ void boundary_flags(const uint8_t *__restrict__ kind, int64_t n, int3
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) {
         flag[i] = kind[i] == RBFFD_DIRICHLET;
-        flag2[i] = kind[i] == RBFFD_PRESCRIBED_PRESSURE;
+        flag2[i] = kind[i] == RBFFD_PRESCRIBED_PRESSURE || kind[i] == RBFFD_OUTLET;
     }
 }
 

@@ -26,14 +26,14 @@ inline int blocks_for(int64_t n)
     return (int)std::max<int64_t>(1, b);
 }
 
-// u^r = u^n with the Dirichlet values of t^{n+1} on boundary points; p^r = p^n
+// u^r = u^n with the Dirichlet values of t^{n+1} on velocity-prescribed points; p^r = p^n
 __global__ void k_start(int64_t n, int dim, const uint8_t *__restrict__ kind, const double *__restrict__ u,
                         const double *__restrict__ ubc, const double *__restrict__ p, double *__restrict__ ur,
                         double *__restrict__ pr)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const bool b = kind[i] != RBFFD_INTERIOR;
+    const bool b = kind[i] == RBFFD_DIRICHLET || kind[i] == RBFFD_PRESCRIBED_PRESSURE;
     for (int e = 0; e < dim; ++e) ur[e * n + i] = b ? ubc[e * n + i] : u[e * n + i];
     pr[i] = p[i];
 }
@@ -41,13 +41,16 @@ __global__ void k_start(int64_t n, int dim, const uint8_t *__restrict__ kind, co
 // Momentum matrix (Eqs. u:tilde, v:tilde, with u^r linearising advection):
 //   interior:  M_ij = rho a1/dt d_ij + rho sum_e u^r_e,i D_e,ij - mu L_ij
 //              b_e,i = -rho (a2 u^n_e,i + a3 u^{n-1}_e,i)/dt - (D_e p^r)_i
-//   boundary:  identity row, b_e,i = u_bc,e,i
+//   velocity-prescribed boundary:  identity row, b_e,i = u_bc,e,i
+//   outlet:    zero normal derivative of every component (Sec. 3.1),
+//              M_ij = sum_d N_d D_d,ij, b_e,i = 0
 // With `cd` set it writes instead C = -rho (u . grad) + mu L on interior rows and
 // zero rows on the boundary (the convection-diffusion operator of Sec. 3.2).
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_momentum(int64_t n, int q, const int32_t *__restrict__ col,
                                                      const double *__restrict__ val, int64_t vs,
-                                                     const uint8_t *__restrict__ kind, const double *__restrict__ ur,
+                                                     const uint8_t *__restrict__ kind,
+                                                     const double *__restrict__ normal, const double *__restrict__ ur,
                                                      const double *__restrict__ un, const double *__restrict__ up,
                                                      const double *__restrict__ ubc, const double *__restrict__ pr,
                                                      double rho, double mu, double dt, double a1, double a2, double a3,
@@ -60,6 +63,19 @@ __global__ __launch_bounds__(kBlock) void k_momentum(int64_t n, int q, const int
     if (i >= n) {
         for (int a = 0; a < q; ++a) mval[base + (int64_t)a * 64] = 0.0;
         mdinv[i] = 0.0;
+        return;
+    }
+    if (kind[i] == RBFFD_OUTLET && !cd) {
+        double diag = 0.0;
+        for (int a = 0; a < q; ++a) {
+            const int64_t slot = base + (int64_t)a * 64;
+            double v = 0.0;
+            for (int d = 0; d < DIM; ++d) v = fma(normal[i * DIM + d], val[d * vs + slot], v);
+            mval[slot] = v;
+            if (col[slot] == i) diag += v;
+        }
+        mdinv[i] = (diag != 0.0) ? 1.0 / diag : 1.0;
+        for (int e = 0; e < DIM; ++e) bm[e * n + i] = 0.0;
         return;
     }
     if (kind[i] != RBFFD_INTERIOR) {
@@ -134,7 +150,8 @@ __global__ void k_p_interior(int64_t n, const uint8_t *__restrict__ kind, const 
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int kd = kind[i];
-    pa[i] = (kd == RBFFD_INTERIOR) ? pr[i] + pc[i] : (kd == RBFFD_PRESCRIBED_PRESSURE ? pbc[i] : pr[i]);
+    pa[i] = (kd == RBFFD_INTERIOR) ? pr[i] + pc[i]
+                                   : ((kd == RBFFD_PRESCRIBED_PRESSURE || kd == RBFFD_OUTLET) ? pbc[i] : pr[i]);
 }
 
 // Boundary-pressure right-hand side (Eq. normal momentum) for boundary row b:
@@ -342,10 +359,12 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
         // step 2: momentum matrix, right-hand sides, and the solves from u^r
         if (dim == 2)
             hipLaunchKernelGGL(k_momentum<2>, dim3(gpad), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs, ops->kind,
-                               B.ur, u, u_prev, u_bc, B.pr, rho, mu, dt, a1, a2, a3, 0, ops->mval, ops->mdinv, B.bm);
+                               ops->normal, B.ur, u, u_prev, u_bc, B.pr, rho, mu, dt, a1, a2, a3, 0, ops->mval,
+                               ops->mdinv, B.bm);
         else
             hipLaunchKernelGGL(k_momentum<3>, dim3(gpad), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs, ops->kind,
-                               B.ur, u, u_prev, u_bc, B.pr, rho, mu, dt, a1, a2, a3, 0, ops->mval, ops->mdinv, B.bm);
+                               ops->normal, B.ur, u, u_prev, u_bc, B.pr, rho, mu, dt, a1, a2, a3, 0, ops->mval,
+                               ops->mdinv, B.bm);
         RB_HIP(hipGetLastError());
         RB_HIP(hipMemcpyAsync(B.ut, B.ur, vec * dim, hipMemcpyDeviceToDevice, s));
         KrylovResult km;
@@ -464,11 +483,11 @@ int convdiff_lambda(rbffd_ctx *ctx, const rbffd_ops *ops, const double *u0, doub
     const int gn = (int)((n + kBlock - 1) / kBlock);
     const int nblk = blocks_for(n);
     if (dim == 2)
-        hipLaunchKernelGGL(k_momentum<2>, dim3(gpad), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs, ops->kind, u0,
-                           u0, u0, u0, u0, rho, mu, 1.0, 0.0, 0.0, 0.0, 1, ops->mval, ops->mdinv, y);
+        hipLaunchKernelGGL(k_momentum<2>, dim3(gpad), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs, ops->kind,
+                           ops->normal, u0, u0, u0, u0, u0, rho, mu, 1.0, 0.0, 0.0, 0.0, 1, ops->mval, ops->mdinv, y);
     else
-        hipLaunchKernelGGL(k_momentum<3>, dim3(gpad), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs, ops->kind, u0,
-                           u0, u0, u0, u0, rho, mu, 1.0, 0.0, 0.0, 0.0, 1, ops->mval, ops->mdinv, y);
+        hipLaunchKernelGGL(k_momentum<3>, dim3(gpad), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs, ops->kind,
+                           ops->normal, u0, u0, u0, u0, u0, rho, mu, 1.0, 0.0, 0.0, 0.0, 1, ops->mval, ops->mdinv, y);
     hipLaunchKernelGGL(k_pow_start, dim3(gn), dim3(kBlock), 0, s, n, y);
     hipLaunchKernelGGL(k_sq_partial, dim3(nblk), dim3(kBlock), 0, s, n, y, part);
     hipLaunchKernelGGL(k_normalise, dim3(nblk), dim3(kBlock), 0, s, n, y, x, part, nblk, nrm);

@@ -88,6 +88,12 @@ def test_couette_closed_form():
     assert abs((pn[2] - pn[3]) - dp) < 1e-13
     # walls: |v| = omega r1 on r = r1, 0 on r = r2
     assert abs(np.hypot(un[0], vn[0]) - 1.0) < 1e-14 and abs(np.hypot(un[1], vn[1])) < 1e-14
+    # plane Poiseuille flow (the outlet workload)
+    U, mu = s.Integer(1), s.Rational(1, 100)
+    _check_ns2(s, x, y, t, 4 * U * y * (1 - y), s.Integer(0) * x, -8 * mu * U * x, mu,
+               pts=[(0.3, 0.2, 0.0), (2.5, 0.7, 0.0)])
+    up, vp, pp = W.poiseuille(np.array([0.3]), np.array([0.2]), 1.0, 0.01)
+    assert abs(up[0] - 4 * 0.2 * 0.8) < 1e-15 and vp[0] == 0.0 and abs(pp[0] + 8 * 0.01 * 0.3) < 1e-15
 
 
 def _check_ns2(s, x, y, t, u, v, p, nu, pts=((0.2, 0.3, 0.1), (-0.4, 1.2, 0.7), (1.1, -0.3, 2.0))):
@@ -512,3 +518,27 @@ def test_interpolation_reproduces_polynomials_off_node(orc, dim, k):
     f = np.sin(3 * c.xyz[:, 0]) + c.xyz[:, 1] ** 2
     v_node, _, _ = orc.interpolate(c.xyz, k, c.xyz[7:9], f)
     np.testing.assert_allclose(v_node[0], f[7:9], rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_poiseuille_outlet_is_a_fixed_point(orc, k):
+    """Plane Poiseuille flow is quadratic, so PHS operators with degree >= 2
+    polynomials reproduce it exactly: started from it, one BDF2 step with an
+    outlet (zero normal velocity gradient, prescribed pressure; Sec. 3.1)
+    returns it to solver accuracy. The step must not read u_bc on outlet points
+    nor p_bc elsewhere: both are set to garbage there."""
+    c = W.poiseuille_channel()
+    ops = orc.build_operators(c, k)
+    vel, p = W.flow_fields(c)
+    out = c.kind == W.OUTLET
+    ubc = np.where(out[None, :], 123.0, vel)
+    pbc = np.where(out, p, -77.0)
+    u1, _, p1, st = orc.simple_step(ops, vel, vel, p, ubc, 1.0, c.meta["nu"], 0.05, alpha=orc.BDF2, p_bc=pbc,
+                                    tol_outer=1e-13, tol_krylov=1e-14, max_outer=3, max_krylov=20000)
+    assert np.abs(u1 - vel).max() <= 1e-10, np.abs(u1 - vel).max()
+    assert np.abs(p1 - p).max() <= 1e-10 * np.abs(p).max(), np.abs(p1 - p).max()
+    # a wrong outlet row shows: a uniform shift of the outlet pressure moves the flow
+    _, _, p2, _ = orc.simple_step(ops, vel, vel, p, ubc, 1.0, c.meta["nu"], 0.05, alpha=orc.BDF2,
+                                  p_bc=pbc + 0.01 * out, tol_outer=1e-13, tol_krylov=1e-14, max_outer=3,
+                                  max_krylov=20000)
+    assert np.abs(p2 - p).max() > 1e-3

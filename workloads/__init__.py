@@ -24,6 +24,7 @@ import numpy as np
 INTERIOR = 0
 DIRICHLET = 1
 PRESCRIBED_PRESSURE = 2
+OUTLET = 3          # prescribed pressure, zero normal derivative of the velocity
 
 
 @dataclass
@@ -110,6 +111,16 @@ def couette(x, y, r1=0.5, r2=1.0, omega=2.0):
     return u, v, p
 
 
+def poiseuille(x, y, U=1.0, mu=0.01):
+    """Plane Poiseuille flow in the channel 0 <= y <= 1 (rho = 1): u = 4U y(1-y),
+    v = 0, p = -8 mu U x. Fully developed, so every outlet x = const has a zero
+    normal velocity gradient."""
+    u = 4.0 * U * y * (1.0 - y)
+    v = np.zeros_like(u)
+    p = -8.0 * mu * U * x
+    return u, v, p
+
+
 def flow_fields(cloud: Cloud, t: float = 0.0):
     """Exact (velocity[dim, n], pressure[n]) of the cloud's flow at time t."""
     x = cloud.xyz
@@ -123,6 +134,9 @@ def flow_fields(cloud: Cloud, t: float = 0.0):
     elif flow == "beltrami":
         u, v, w, p = beltrami(x[:, 0], x[:, 1], x[:, 2], t, nu=cloud.meta.get("nu", 0.01))
         vel = np.stack([u, v, w])
+    elif flow == "poiseuille":
+        u, v, p = poiseuille(x[:, 0], x[:, 1], cloud.meta.get("U", 1.0), cloud.meta["nu"])
+        vel = np.stack([u, v])
     elif flow == "couette":
         u, v, p = couette(x[:, 0], x[:, 1], cloud.meta["r1"], cloud.meta["r2"], cloud.meta["omega"])
         vel = np.stack([u, v])
@@ -216,7 +230,7 @@ def _finish(dim, xyz, kind, normal, name, h, meta, centre, boundary_kind=DIRICHL
     d2 = ((xyz - np.asarray(centre)) ** 2).sum(axis=1)
     d2 = np.where(kind == INTERIOR, d2, np.inf)
     pin = int(np.lexsort((np.arange(len(d2)), d2))[0])
-    if (kind == PRESCRIBED_PRESSURE).any():
+    if ((kind == PRESCRIBED_PRESSURE) | (kind == OUTLET)).any():
         pin = -1   # the prescribed boundary pressure fixes the pressure level
     return Cloud(dim=dim, xyz=xyz, kind=kind, normal=normal, pin=pin, name=name, h=h, meta=meta)
 
@@ -325,6 +339,36 @@ def taylor_green_disk(r: float = TG_RADIUS_250K, seed: int = 2, nu: float = 0.01
     return _finish(2, xyz, kind, normal, f"taylor_green_{len(xyz)}", r,
                    {"flow": "taylor_green", "nu": nu, "seed": seed},
                    centre=(np.pi, np.pi), boundary_kind=boundary_kind)
+
+
+def poiseuille_channel(nx: int = 48, ny: int = 16, length: float = 3.0, seed: int = 13, jitter: float = 0.2,
+                       nu: float = 0.01) -> Cloud:
+    """Channel [0, length] x [0, 1] for plane Poiseuille flow: a jittered
+    cell-centred nx-by-ny lattice, Dirichlet velocity on the inlet x = 0 and the
+    walls y = 0, 1 (corners included, with their wall normals), and an outlet
+    (kind OUTLET, outward normal +x) on x = length between the walls."""
+    rng = np.random.default_rng(seed)
+    hx, hy = length / nx, 1.0 / ny
+    gx = (np.arange(nx) + 0.5) * hx
+    gy = (np.arange(ny) + 0.5) * hy
+    X, Y = np.meshgrid(gx, gy, indexing="ij")
+    inter = np.stack([X.ravel(), Y.ravel()], axis=1)
+    inter = inter + np.stack([rng.uniform(-jitter * hx, jitter * hx, len(inter)),
+                              rng.uniform(-jitter * hy, jitter * hy, len(inter))], axis=1)
+    wx = np.arange(nx + 1) * hx                      # wall points, corners included
+    walls = np.concatenate([np.stack([wx, np.zeros_like(wx)], 1), np.stack([wx, np.ones_like(wx)], 1)])
+    wn = np.concatenate([np.tile([0.0, -1.0], (nx + 1, 1)), np.tile([0.0, 1.0], (nx + 1, 1))])
+    ey = gy                                           # inlet and outlet points between the walls
+    inlet = np.stack([np.zeros_like(ey), ey], 1)
+    outlet = np.stack([np.full_like(ey, length), ey], 1)
+    xyz = np.concatenate([inter, walls, inlet, outlet])
+    kind = np.concatenate([np.zeros(len(inter), np.uint8), np.full(len(walls), DIRICHLET, np.uint8),
+                           np.full(len(inlet), DIRICHLET, np.uint8), np.full(len(outlet), OUTLET, np.uint8)])
+    normal = np.concatenate([np.zeros_like(inter), wn, np.tile([-1.0, 0.0], (len(inlet), 1)),
+                             np.tile([1.0, 0.0], (len(outlet), 1))])
+    return _finish(2, xyz, kind, normal, f"poiseuille_{len(xyz)}", min(hx, hy),
+                   {"flow": "poiseuille", "U": 1.0, "nu": nu, "seed": seed},
+                   centre=(length / 2, 0.5), boundary_kind=None)
 
 
 # Poisson-disk radii giving the three point counts of the Couette study (2080,
