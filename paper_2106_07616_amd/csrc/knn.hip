@@ -70,8 +70,10 @@ __global__ __launch_bounds__(kBlock) void bbox_partial(const double *__restrict_
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
         for (int d = 0; d < DIM; ++d) {
             double v = xyz[i * DIM + d];
-            mn[d] = fmin(mn[d], v);
-            mx[d] = fmax(mx[d], v);
+            // fmin/fmax skip NaN: a NaN coordinate widens the box to +-infinity
+            // instead, so the host's finiteness check sees it
+            mn[d] = (v != v) ? -INFINITY : fmin(mn[d], v);
+            mx[d] = (v != v) ? INFINITY : fmax(mx[d], v);
         }
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     for (int d = 0; d < DIM; ++d) {
@@ -367,6 +369,25 @@ int launch_knn(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q, int
 int launch_knn_points(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int64_t nq, const double *qxyz, int q,
                       int32_t *nbr, hipStream_t s)
 {
+    if (qxyz != xyz && nq > 0) {
+        // query coordinates must be finite (their bounding box is)
+        const int nbq = (int)std::min<int64_t>(1024, (nq + kBlock - 1) / kBlock);
+        double *qpart = nullptr;
+        RB_CHECK(dev_alloc(ctx, (void **)&qpart, sizeof(double) * (nbq * 6 + 6)));
+        double *qbb = qpart + nbq * 6;
+        if (dim == 2)
+            hipLaunchKernelGGL(bbox_partial<2>, dim3(nbq), dim3(kBlock), 0, s, qxyz, nq, qpart);
+        else
+            hipLaunchKernelGGL(bbox_partial<3>, dim3(nbq), dim3(kBlock), 0, s, qxyz, nq, qpart);
+        hipLaunchKernelGGL(bbox_final, dim3(1), dim3(64), 0, s, qpart, nbq, qbb);
+        double hq[6];
+        hipError_t eq = hipMemcpyAsync(hq, qbb, sizeof(hq), hipMemcpyDeviceToHost, s);
+        if (eq == hipSuccess) eq = hipStreamSynchronize(s);
+        dev_free(ctx, qpart, sizeof(double) * (nbq * 6 + 6));
+        if (eq != hipSuccess) return hip_fail(eq, "query bounding box");
+        for (int d = 0; d < dim; ++d)
+            if (!std::isfinite(hq[d]) || !std::isfinite(hq[3 + d])) return fail(RBFFD_E_ARG, "non-finite query coordinates");
+    }
     // bounding box
     const int nbb = (int)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock);
     double *part = nullptr;

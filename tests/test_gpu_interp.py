@@ -122,6 +122,11 @@ def test_interpolation_edge_cases(ctx):
     q1 = torch.tensor([[0.3, 0.4]], dtype=torch.float64, device="cuda")
     assert L.rbffd_interpolate(ctx.handle, C.byref(cs), C.byref(o), 1, R.binding._ptr(q1), 1, None, None, None,
                                None, C.byref(bad), R.binding._stream()) == -1      # fields missing
+    # non-finite query coordinates are rejected before any search
+    for bad_q in (np.nan, np.inf):
+        qn = torch.tensor([[0.3, bad_q]], dtype=torch.float64, device="cuda")
+        assert L.rbffd_interpolate(ctx.handle, C.byref(cs), C.byref(o), 1, R.binding._ptr(qn), 0, None, None, None,
+                                   None, C.byref(bad), R.binding._stream()) == -1
     o7 = R.binding.StencilOptsT(3, 7, 0)
     assert L.rbffd_interpolate(ctx.handle, C.byref(cs), C.byref(o7), 1, R.binding._ptr(q1), 0, None, None, None,
                                None, C.byref(bad), R.binding._stream()) == -1      # degree 7

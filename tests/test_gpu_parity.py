@@ -336,6 +336,17 @@ def test_cloud_equal_to_whole_set(ctx, orc):
     assert _rel_rows(s.w.cpu().numpy(), w) <= 1e-10
 
 
+def test_non_finite_coordinates_rejected(ctx):
+    """A NaN or infinite coordinate is reported as RBFFD_E_ARG before the
+    neighbour search (its bounding box is not finite)."""
+    for bad in (np.nan, np.inf):
+        c = W.kovasznay_square(nx=6)
+        c.xyz[5, 1] = bad
+        with pytest.raises(R.RbffdError) as e:
+            R.rbffd_build_stencils(ctx, R.DeviceCloud.from_numpy(c), 2)
+        assert e.value.code == -1
+
+
 def test_more_argument_errors(ctx):
     """Argument checks run before any launch and return RBFFD_E_ARG."""
     import ctypes as C
