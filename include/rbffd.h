@@ -79,6 +79,12 @@ extern "C" {
 #define RBFFD_OUTLET 3          /* outlet with prescribed pressure (p' = 0, pressure from
                                    p_bc) and zero normal derivative of every velocity
                                    component (Sec. 3.1); needs the outward normal        */
+#define RBFFD_SYMMETRY 4        /* symmetry plane normal to a coordinate axis (Sec. 3.1):
+                                   zero normal velocity, zero normal derivative of the
+                                   tangential velocity; homogeneous Neumann p' and the
+                                   pressure from the normal momentum equation, as at
+                                   velocity-Dirichlet points. The normal must be a
+                                   coordinate unit vector                                */
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *rbffd_last_error(void);
@@ -100,7 +106,8 @@ typedef struct {
     int dim;                /* 2 or 3                                                */
     int64_t n;              /* number of points, 1 <= n < 2^31                       */
     const double *xyz;      /* device [n][dim]; no two points may coincide           */
-    const uint8_t *kind;    /* device [n]: RBFFD_INTERIOR / _DIRICHLET / _PRESCRIBED_PRESSURE / _OUTLET */
+    const uint8_t *kind;    /* device [n]: RBFFD_INTERIOR / _DIRICHLET / _PRESCRIBED_PRESSURE / _OUTLET /
+                               _SYMMETRY */
     const double *normal;   /* device [n][dim]: unit outward normal (boundary points) */
     int64_t pin;            /* interior point whose pressure correction is 0, or -1
                                (none; needed only when no prescribed-pressure point
@@ -139,9 +146,10 @@ typedef struct rbffd_ops rbffd_ops;
 /* (Sec. 2 closing remark, Eq. pressure poisson, Sec. 3.1) Sort each cloud by
  * column into a sparse matrix with exactly q entries per row, carry the R
  * weight sets along, and build the pressure-correction matrix: the Laplacian
- * row at interior points, N . grad at velocity-Dirichlet boundary points
+ * row at interior points, N . grad at velocity-Dirichlet and symmetry points
  * (homogeneous Neumann), the identity row (p' = 0) at prescribed-pressure and
- * outlet points and at the pin. `precision` selects
+ * outlet points and at the pin. RBFFD_E_ARG if a symmetry point's normal is
+ * not a coordinate unit vector. `precision` selects
  * whether FP32 copies for the mixed-precision modes are made (any value other
  * than RBFFD_FP64). The cloud arrays are copied;
  * nbr and w may be freed afterwards. *out is library-owned: free it with

@@ -629,8 +629,10 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
     double *f = (double *)malloc(sizeof(double) * n);
     double *bm = (double *)malloc(sizeof(double) * dim * n);
     double *mval = (double *)malloc(sizeof(double) * nnz);
-    int64_t nb = 0;   /* velocity-Dirichlet (kind 1) points: pressure from normal momentum */
-    for (int64_t i = 0; i < n; ++i) nb += (c->kind[i] == 1);
+    /* velocity-Dirichlet (kind 1) and symmetry (kind 4) points: homogeneous
+     * Neumann p' and the pressure from the normal momentum equation */
+    int64_t nb = 0;
+    for (int64_t i = 0; i < n; ++i) nb += (c->kind[i] == 1 || c->kind[i] == 4);
     int64_t *bidx = (int64_t *)malloc(sizeof(int64_t) * (nb + 1));
     int64_t *bpos = (int64_t *)malloc(sizeof(int64_t) * n);
     int32_t *gcol = (int32_t *)malloc(sizeof(int32_t) * (nb * q + 1));
@@ -638,8 +640,8 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
     double *bb = (double *)malloc(sizeof(double) * (nb + 1));
     double *pb = (double *)malloc(sizeof(double) * (nb + 1));
     for (int64_t i = 0, b = 0; i < n; ++i) {
-        bpos[i] = (c->kind[i] == 1) ? b : -1;
-        if (c->kind[i] == 1) bidx[b++] = i;
+        bpos[i] = (c->kind[i] == 1 || c->kind[i] == 4) ? b : -1;
+        if (c->kind[i] == 1 || c->kind[i] == 4) bidx[b++] = i;
     }
     /* block of the normal-derivative rows over kind-1 points: columns of the
      * other points are moved to the right-hand side (zero value, own column) */
@@ -647,8 +649,9 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
         const int64_t i = bidx[b];
         for (int a = 0; a < q; ++a) {
             int64_t k = i * q + a, j = c->col[k];
-            gcol[b * q + a] = (c->kind[j] == 1) ? (int32_t)bpos[j] : (int32_t)b;
-            gval[b * q + a] = (c->kind[j] == 1) ? c->pval[k] : 0.0;
+            const int in_block = (c->kind[j] == 1 || c->kind[j] == 4);
+            gcol[b * q + a] = in_block ? (int32_t)bpos[j] : (int32_t)b;
+            gval[b * q + a] = in_block ? c->pval[k] : 0.0;
         }
     }
 
@@ -664,8 +667,10 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
     for (outer = 1; outer <= c->max_outer; ++outer) {
         /* step 2: momentum matrix and right-hand sides (Eqs. u:tilde, v:tilde) */
         for (int64_t i = 0; i < n; ++i) {
-            if (c->kind[i] == 3) {
-                /* outlet (Sec. 3.1): N . grad u_e = 0 for every component */
+            if (c->kind[i] == 3 || c->kind[i] == 4) {
+                /* outlet and symmetry (Sec. 3.1): N . grad u_e = 0; on a
+                 * symmetry point the normal component is set to u = 0 below,
+                 * component by component */
                 for (int a = 0; a < q; ++a) {
                     double v = 0.0;
                     for (int d = 0; d < dim; ++d) v = v + c->normal[i * dim + d] * c->val[d * nnz + i * q + a];
@@ -696,6 +701,21 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
         /* momentum solves, one per velocity component, started from u^r */
         for (int e = 0; e < dim; ++e) {
             int its = 0;
+            /* symmetry points: u_e = 0 where e is the plane's normal axis,
+             * N . grad u_e = 0 otherwise (right-hand side 0 on both) */
+            for (int64_t i = 0; i < n; ++i) {
+                if (c->kind[i] != 4) continue;
+                const int normal_axis = fabs(c->normal[i * dim + e]) == 1.0;
+                for (int a = 0; a < q; ++a) {
+                    double v = 0.0;
+                    if (normal_axis) {
+                        v = (c->col[i * q + a] == i) ? 1.0 : 0.0;
+                    } else {
+                        for (int d = 0; d < dim; ++d) v = v + c->normal[i * dim + d] * c->val[d * nnz + i * q + a];
+                    }
+                    mval[i * q + a] = v;
+                }
+            }
             memcpy(ut + e * n, ur + e * n, sizeof(double) * n);
             int s = orc_bicgstab(n, q, c->col, mval, bm + e * n, ut + e * n, c->tol_krylov, c->max_krylov, &its, NULL);
             kit_m += its;
@@ -749,7 +769,7 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
             }
             for (int a = 0; a < q; ++a) {
                 int64_t k = i * q + a, j = c->col[k];
-                if (c->kind[j] == 1) continue;
+                if (c->kind[j] == 1 || c->kind[j] == 4) continue;
                 rhs = rhs - c->pval[k] * pa[j];
             }
             bb[b] = rhs;
@@ -761,7 +781,7 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
             kit_b += its;
             if (s != ORC_OK) status = s;
         }
-        for (int64_t i = 0; i < n; ++i) pr[i] = (c->kind[i] == 1) ? pb[bpos[i]] : pa[i];
+        for (int64_t i = 0; i < n; ++i) pr[i] = (c->kind[i] == 1 || c->kind[i] == 4) ? pb[bpos[i]] : pa[i];
         /* step 6: velocity correction (Eqs. u:correction, v:correction) */
         const double coef = dt / (rho * a1);
         for (int e = 0; e < dim; ++e)

@@ -9,6 +9,7 @@
 #include <cmath>
 
 #include <climits>
+#include <vector>
 
 #include "internal.h"
 
@@ -93,7 +94,7 @@ __global__ void boundary_flags(const uint8_t *__restrict__ kind, int64_t n, int3
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) {
-        flag[i] = kind[i] == RBFFD_DIRICHLET;
+        flag[i] = neumann_p(kind[i]);
         flag2[i] = kind[i] == RBFFD_PRESCRIBED_PRESSURE || kind[i] == RBFFD_OUTLET;
     }
 }
@@ -103,7 +104,7 @@ __global__ void boundary_index(const uint8_t *__restrict__ kind, const int32_t *
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    if (kind[i] == RBFFD_DIRICHLET) {
+    if (neumann_p(kind[i])) {
         bidx[pos[i]] = (int32_t)i;
         bpos[i] = pos[i];
     } else {
@@ -111,7 +112,7 @@ __global__ void boundary_index(const uint8_t *__restrict__ kind, const int32_t *
     }
 }
 
-// Block of the normal-derivative rows over velocity-Dirichlet points: entries of
+// Block of the normal-derivative rows over velocity-Dirichlet and symmetry points: entries of
 // the other columns are kept as explicit zeros on the row's own (block-local)
 // column, so every row keeps q entries.
 __global__ void boundary_block(const int32_t *__restrict__ col, const double *__restrict__ pval,
@@ -134,7 +135,7 @@ __global__ void boundary_block(const int32_t *__restrict__ col, const double *__
     for (int a = 0; a < q; ++a) {
         const int64_t si = ell_at(i, a, q), sb = ell_at(b, a, q);
         const int32_t j = col[si];
-        if (kind[j] == RBFFD_DIRICHLET) {
+        if (neumann_p(kind[j])) {
             gcol[sb] = bpos[j];
             gval[sb] = pval[si];
             if (bpos[j] == b) diag += pval[si];
@@ -327,6 +328,33 @@ int assemble_ops(rbffd_ctx *ctx, const rbffd_cloud *cloud, int q, int k, int phs
     RB_CHECK(alloc_ops(ops, &ops->mdinv, (size_t)npad * kMaxRhs));
     RB_HIP(hipMemcpyAsync(ops->kind, cloud->kind, n, hipMemcpyDeviceToDevice, s));
     RB_HIP(hipMemcpyAsync(ops->normal, cloud->normal, sizeof(double) * n * dim, hipMemcpyDeviceToDevice, s));
+    {
+        // symmetry points: count them, and check that each normal is a
+        // coordinate unit vector (their rows differ per velocity component)
+        std::vector<uint8_t> hk((size_t)n);
+        RB_HIP(hipMemcpyAsync(hk.data(), cloud->kind, (size_t)n, hipMemcpyDeviceToHost, s));
+        RB_HIP(hipStreamSynchronize(s));
+        int64_t nsym = 0;
+        for (uint8_t v : hk) nsym += (v == RBFFD_SYMMETRY);
+        ops->n_symmetry = nsym;
+        if (nsym > 0) {
+            std::vector<double> hn((size_t)n * dim);
+            RB_HIP(hipMemcpyAsync(hn.data(), cloud->normal, sizeof(double) * n * dim, hipMemcpyDeviceToHost, s));
+            RB_HIP(hipStreamSynchronize(s));
+            for (int64_t i = 0; i < n; ++i) {
+                if (hk[i] != RBFFD_SYMMETRY) continue;
+                int ones = 0, zeros = 0;
+                for (int d = 0; d < dim; ++d) {
+                    const double a = std::fabs(hn[i * dim + d]);
+                    ones += (a == 1.0);
+                    zeros += (a == 0.0);
+                }
+                if (ones != 1 || zeros != dim - 1)
+                    return fail(RBFFD_E_ARG, "symmetry point " + std::to_string(i) +
+                                                 ": the normal is not a coordinate unit vector");
+            }
+        }
+    }
 
     const unsigned nslices = (unsigned)(npad / 64);
     hipLaunchKernelGGL(sort_rows, dim3(nslices), dim3(64), sizeof(int32_t) * 64 * (q + 1), s, nbr, w, n, q, ops->R,

@@ -112,7 +112,8 @@ struct rbffd_ops {
     int dim = 2, q = 0, R = 3, k = 0, phs = 3;
     int64_t n = 0, npad = 0, pin = 0;
     int64_t nb = 0, nbpad = 0;          // velocity-Dirichlet boundary points (normal momentum block)
-    int64_t n_prescribed = 0;           // prescribed-pressure points
+    int64_t n_prescribed = 0;           // prescribed-pressure and outlet points
+    int64_t n_symmetry = 0;             // symmetry-plane points (momentum solved per component)
     int precision = RBFFD_FP64;
     size_t bytes = 0;                   // device bytes charged to ctx
     // cloud copies
@@ -166,6 +167,10 @@ struct BlockInv {
 };
 
 inline BlockInv binv_of(const rbffd_ops *ops) { return BlockInv{ops->pbinv, ops->pbscale}; }
+
+// Points whose pressure correction has a homogeneous Neumann row and whose
+// pressure comes from the normal momentum equation (Sec. 3.1).
+__host__ __device__ inline bool neumann_p(int kd) { return kd == RBFFD_DIRICHLET || kd == RBFFD_SYMMETRY; }
 constexpr BlockInv kNoBlockInv{nullptr, nullptr};
 
 // ---------------------------------------------------------------------------

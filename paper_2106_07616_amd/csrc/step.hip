@@ -42,8 +42,9 @@ __global__ void k_start(int64_t n, int dim, const uint8_t *__restrict__ kind, co
 //   interior:  M_ij = rho a1/dt d_ij + rho sum_e u^r_e,i D_e,ij - mu L_ij
 //              b_e,i = -rho (a2 u^n_e,i + a3 u^{n-1}_e,i)/dt - (D_e p^r)_i
 //   velocity-prescribed boundary:  identity row, b_e,i = u_bc,e,i
-//   outlet:    zero normal derivative of every component (Sec. 3.1),
-//              M_ij = sum_d N_d D_d,ij, b_e,i = 0
+//   outlet and symmetry:  zero normal derivative (Sec. 3.1),
+//              M_ij = sum_d N_d D_d,ij, b_e,i = 0 (the normal component of a
+//              symmetry point is switched to u = 0 per solve by k_sym_rows)
 // With `cd` set it writes instead C = -rho (u . grad) + mu L on interior rows and
 // zero rows on the boundary (the convection-diffusion operator of Sec. 3.2).
 template <int DIM>
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(kBlock) void k_momentum(int64_t n, int q, const int
         mdinv[i] = 0.0;
         return;
     }
-    if (kind[i] == RBFFD_OUTLET && !cd) {
+    if ((kind[i] == RBFFD_OUTLET || kind[i] == RBFFD_SYMMETRY) && !cd) {
         double diag = 0.0;
         for (int a = 0; a < q; ++a) {
             const int64_t slot = base + (int64_t)a * 64;
@@ -114,6 +115,34 @@ __global__ __launch_bounds__(kBlock) void k_momentum(int64_t n, int q, const int
     mdinv[i] = (diag != 0.0) ? 1.0 / diag : 1.0;
     if (!cd)
         for (int e = 0; e < DIM; ++e) bm[e * n + i] = -rho * (a2 * un[e * n + i] + a3 * up[e * n + i]) / dt - g[e];
+}
+
+// Symmetry rows of the momentum matrix for velocity component e (Sec. 3.1):
+// u_e = 0 where e is the normal axis of the point's plane, N . grad u_e = 0
+// otherwise. The right-hand side stays 0 on both.
+template <int DIM>
+__global__ void k_sym_rows(int64_t n, int q, const int32_t *__restrict__ col, const double *__restrict__ val,
+                           int64_t vs, const uint8_t *__restrict__ kind, const double *__restrict__ normal, int e,
+                           double *__restrict__ mval, double *__restrict__ mdinv)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n || kind[i] != RBFFD_SYMMETRY) return;
+    const int64_t base = ((i >> 6) * (int64_t)q) * 64 + (i & 63);
+    const bool normal_axis = fabs(normal[i * DIM + e]) == 1.0;
+    double diag = 0.0;
+    for (int a = 0; a < q; ++a) {
+        const int64_t slot = base + (int64_t)a * 64;
+        double v;
+        if (normal_axis) {
+            v = (col[slot] == i) ? 1.0 : 0.0;
+        } else {
+            v = 0.0;
+            for (int d = 0; d < DIM; ++d) v = fma(normal[i * DIM + d], val[d * vs + slot], v);
+        }
+        mval[slot] = v;
+        if (col[slot] == i) diag += v;
+    }
+    mdinv[i] = (diag != 0.0) ? 1.0 / diag : 1.0;
 }
 
 // f_i = (rho a1 / dt) sum_e (D_e u~_e)_i on interior rows other than the pin; 0 elsewhere
@@ -186,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_boundary_rhs(int64_t n, int64_t nb, 
             for (int g = 0; g < DIM; ++g) grad[g][c] = fma(val[g * vs + slot], uj, grad[g][c]);
             lap[c] = fma(val[DIM * vs + slot], uj, lap[c]);
         }
-        if (kind[j] != RBFFD_DIRICHLET) off = fma(pval[slot], pa[j], off);
+        if (!neumann_p(kind[j])) off = fma(pval[slot], pa[j], off);
     }
     double rhs = 0.0;
     for (int c = 0; c < DIM; ++c) {
@@ -205,7 +234,7 @@ __global__ void k_p_scatter(int64_t n, const uint8_t *__restrict__ kind, const i
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    pr[i] = (kind[i] == RBFFD_DIRICHLET) ? pb[bpos[i]] : pa[i];
+    pr[i] = neumann_p(kind[i]) ? pb[bpos[i]] : pa[i];
 }
 
 // u^{r+1} = u~ - coef D p' on interior points (Eqs. u:correction, v:correction),
@@ -367,20 +396,36 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
                                ops->mdinv, B.bm);
         RB_HIP(hipGetLastError());
         RB_HIP(hipMemcpyAsync(B.ut, B.ur, vec * dim, hipMemcpyDeviceToDevice, s));
-        KrylovResult km;
-        if (fp32) {
-            RB_CHECK(launch_to_fp32(ops->mval, ops->mval32, vs, s));
-            RB_CHECK(launch_to_fp32(ops->mdinv, ops->mdinv32, ops->npad, s));
-            RB_CHECK(bicgstab_mixed(ctx, o->precision, n, q, cols_of(ops), ops->mval, ops->mval32, ops->mdinv32,
-                                    ops->mdinv, kNoBlockInv, dim, B.bm, B.ut, o->tol_krylov, o->max_krylov, &km,
-                                    nullptr, s));
-        } else {
-            RB_CHECK(bicgstab(ctx, n, q, cols_of(ops), ops->mval, ops->mdinv, dim, B.bm, B.ut, o->tol_krylov, o->max_krylov,
-                              &km, s));
-        }
-        for (int e = 0; e < dim; ++e) {
-            kit_m += km.iters[e];
-            if (km.status[e] != RBFFD_OK && status == RBFFD_OK) status = km.status[e];
+        // the d components share one matrix, unless symmetry rows differ between them
+        const int groups = ops->n_symmetry > 0 ? dim : 1;
+        const int nrhs = ops->n_symmetry > 0 ? 1 : dim;
+        for (int g = 0; g < groups; ++g) {
+            if (ops->n_symmetry > 0) {
+                if (dim == 2)
+                    hipLaunchKernelGGL(k_sym_rows<2>, dim3(gn), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs,
+                                       ops->kind, ops->normal, g, ops->mval, ops->mdinv);
+                else
+                    hipLaunchKernelGGL(k_sym_rows<3>, dim3(gn), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs,
+                                       ops->kind, ops->normal, g, ops->mval, ops->mdinv);
+                RB_HIP(hipGetLastError());
+            }
+            const double *bg = B.bm + (int64_t)g * n;
+            double *xg = B.ut + (int64_t)g * n;
+            KrylovResult km;
+            if (fp32) {
+                RB_CHECK(launch_to_fp32(ops->mval, ops->mval32, vs, s));
+                RB_CHECK(launch_to_fp32(ops->mdinv, ops->mdinv32, ops->npad, s));
+                RB_CHECK(bicgstab_mixed(ctx, o->precision, n, q, cols_of(ops), ops->mval, ops->mval32, ops->mdinv32,
+                                        ops->mdinv, kNoBlockInv, nrhs, bg, xg, o->tol_krylov, o->max_krylov, &km,
+                                        nullptr, s));
+            } else {
+                RB_CHECK(bicgstab(ctx, n, q, cols_of(ops), ops->mval, ops->mdinv, nrhs, bg, xg, o->tol_krylov,
+                                  o->max_krylov, &km, s));
+            }
+            for (int e = 0; e < nrhs; ++e) {
+                kit_m += km.iters[e];
+                if (km.status[e] != RBFFD_OK && status == RBFFD_OK) status = km.status[e];
+            }
         }
         // step 3: pressure correction from p' = 0
         const double mass = rho * a1 / dt;

@@ -56,6 +56,8 @@ CLOUDS = {
     "cube9_k4": (lambda: W.beltrami_cube(n=9), 4),
     # a channel with an outlet (zero normal velocity gradient, prescribed pressure)
     "channel_outlet_k3": (lambda: W.poiseuille_channel(), 3),
+    # Kovasznay flow between its symmetry lines (symmetry points, per-component momentum rows)
+    "kovasznay_strip_k3": (lambda: W.kovasznay_strip(), 3),
 }
 
 
@@ -249,6 +251,8 @@ def test_polynomial_flow_step(case, ctx, orc, which):
     name, c, k, ops_o, s = case
     if which == "stagnation" and (c.kind == W.OUTLET).any():
         pytest.skip("the stagnation flow has a nonzero normal velocity gradient on the outlet")
+    if (c.kind == W.SYMMETRY).any():
+        pytest.skip("these flows break the symmetry conditions of the cloud's planes")
     rho, mu, dt, t = 1.3, 0.05, 0.05, 0.3
     un, pn = W.polynomial_flow(c.xyz, t, which, rho)
     um, _ = W.polynomial_flow(c.xyz, t - dt, which, rho)
@@ -502,3 +506,40 @@ def test_poiseuille_outlet_fixed_point(ctx, orc, k):
     assert np.abs(ug - vel).max() <= 1e-10
     assert np.abs(pgn - p).max() <= 1e-10 * np.abs(p).max()
     assert np.abs(ug - uo).max() <= 1e-10 and np.abs(pgn - po).max() <= 1e-10 * np.abs(p).max()
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_symmetry_plane_fixed_point(ctx, orc, k):
+    """The stagnation flow with its symmetry line y = 0 is a fixed point of the
+    step (quadratic fields), on the GPU as in the oracle; u_bc on the symmetry
+    points is garbage and must not be read."""
+    c = W.symmetric_square()
+    s = R.Solver(ctx, c, k)
+    ops_o = orc.build_operators(c, k)
+    vel, p = W.flow_fields(c)
+    sym = c.kind == W.SYMMETRY
+    ubc = np.where(sym[None, :], 55.0, vel)
+    kw = dict(tol_outer=1e-13, tol_krylov=1e-14, max_outer=3, max_krylov=20000)
+    uo, _, po, sto = orc.simple_step(ops_o, vel, vel, p, ubc, 1.0, c.meta["nu"], 0.05, alpha=orc.BDF2, **kw)
+    u = torch.tensor(vel, device="cuda")
+    pg = torch.tensor(p, device="cuda")
+    st = R.simple_step(ctx, s.ops, u, torch.tensor(vel, device="cuda"), pg, torch.tensor(ubc, device="cuda"), 1.0,
+                       c.meta["nu"], 0.05, R.BDF2, **kw)
+    ug, pgn = u.cpu().numpy(), pg.cpu().numpy()
+    print(f"[symmetry] k={k}: |u - exact| {np.abs(ug - vel).max():.1e} |p - exact| {np.abs(pgn - p).max():.1e} "
+          f"|u - oracle| {np.abs(ug - uo).max():.1e} momentum iterations {st['krylov_mom']}/{sto['krylov_mom']}",
+          flush=True)
+    assert np.abs(ug - vel).max() <= 1e-10
+    assert np.abs(pgn - p).max() <= 1e-9
+    assert np.abs(ug - uo).max() <= 1e-10 and np.abs(pgn - po).max() <= 1e-9
+
+
+def test_symmetry_normal_must_be_a_coordinate_axis(ctx):
+    c = W.kovasznay_strip(nx=10, ny=4)
+    sym = np.where(c.kind == W.SYMMETRY)[0]
+    c.normal[sym[0]] = [0.6, -0.8]
+    dc = R.DeviceCloud.from_numpy(c)
+    nbr, w, _ = R.rbffd_build_stencils(ctx, dc, 2)
+    with pytest.raises(R.RbffdError) as e:
+        R.rbffd_assemble(ctx, dc, nbr, w, 2)
+    assert e.value.code == -1

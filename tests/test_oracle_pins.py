@@ -542,3 +542,37 @@ def test_poiseuille_outlet_is_a_fixed_point(orc, k):
                                   p_bc=pbc + 0.01 * out, tol_outer=1e-13, tol_krylov=1e-14, max_outer=3,
                                   max_krylov=20000)
     assert np.abs(p2 - p).max() > 1e-3
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_symmetry_plane_keeps_the_stagnation_flow(orc, k):
+    """The stagnation flow u = (x, -y), p = -|u|^2/2 has the symmetry line
+    y = 0 (v = 0, du/dy = 0; Sec. 3.1 symmetry conditions). Quadratic, so with
+    degree >= 2 one BDF2 step returns it to solver accuracy; u_bc on the
+    symmetry points is garbage and must not be read."""
+    c = W.symmetric_square()
+    ops = orc.build_operators(c, k)
+    vel, p = W.flow_fields(c)
+    sym = c.kind == W.SYMMETRY
+    ubc = np.where(sym[None, :], 55.0, vel)
+    u1, _, p1, st = orc.simple_step(ops, vel, vel, p, ubc, 1.0, c.meta["nu"], 0.05, alpha=orc.BDF2,
+                                    tol_outer=1e-13, tol_krylov=1e-14, max_outer=3, max_krylov=20000)
+    assert np.abs(u1 - vel).max() <= 1e-10, np.abs(u1 - vel).max()
+    assert np.abs(p1 - p).max() <= 1e-9, np.abs(p1 - p).max()
+    # the symmetry rows matter: imposing u_bc there instead would move the flow
+    assert np.abs(ubc - vel).max() > 1.0
+
+
+def test_symmetry_strip_keeps_kovasznay_flow(orc):
+    """Kovasznay flow between its symmetry lines y = 0 and y = 0.5: started
+    from the exact state, one outer iteration moves the velocity only by the
+    discretization error, which shrinks with h."""
+    changes = []
+    for nx, ny in ((20, 5), (40, 10)):
+        c = W.kovasznay_strip(nx=nx, ny=ny)
+        ops = orc.build_operators(c, 3)
+        vel, p = W.flow_fields(c)
+        u1, _, _, st = orc.simple_step(ops, vel, vel, p, vel, 1.0, 1.0 / 40, 0.01, alpha=orc.BDF2,
+                                       tol_outer=0.0, tol_krylov=1e-12, max_outer=1, max_krylov=20000)
+        changes.append(np.abs(u1 - vel).mean())
+    assert changes[1] < changes[0] / 2 and changes[1] < 2e-3, changes

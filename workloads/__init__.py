@@ -25,6 +25,7 @@ INTERIOR = 0
 DIRICHLET = 1
 PRESCRIBED_PRESSURE = 2
 OUTLET = 3          # prescribed pressure, zero normal derivative of the velocity
+SYMMETRY = 4        # symmetry plane normal to a coordinate axis
 
 
 @dataclass
@@ -137,6 +138,8 @@ def flow_fields(cloud: Cloud, t: float = 0.0):
     elif flow == "poiseuille":
         u, v, p = poiseuille(x[:, 0], x[:, 1], cloud.meta.get("U", 1.0), cloud.meta["nu"])
         vel = np.stack([u, v])
+    elif flow == "stagnation":
+        vel, p = polynomial_flow(x, t, "stagnation", 1.0)
     elif flow == "couette":
         u, v, p = couette(x[:, 0], x[:, 1], cloud.meta["r1"], cloud.meta["r2"], cloud.meta["omega"])
         vel = np.stack([u, v])
@@ -339,6 +342,63 @@ def taylor_green_disk(r: float = TG_RADIUS_250K, seed: int = 2, nu: float = 0.01
     return _finish(2, xyz, kind, normal, f"taylor_green_{len(xyz)}", r,
                    {"flow": "taylor_green", "nu": nu, "seed": seed},
                    centre=(np.pi, np.pi), boundary_kind=boundary_kind)
+
+
+def _edge_points(x0, y0, x1, y1, count, nrm, include_end=False):
+    """count evenly spaced points from (x0, y0) towards (x1, y1) (the end point
+    only with include_end), all with normal nrm."""
+    s = np.arange(count + (1 if include_end else 0)) / count
+    pts = np.stack([x0 + (x1 - x0) * s, y0 + (y1 - y0) * s], axis=1)
+    return pts, np.tile(np.asarray(nrm, dtype=np.float64), (len(pts), 1))
+
+
+def symmetric_square(nx: int = 16, seed: int = 17, jitter: float = 0.2) -> Cloud:
+    """Unit square for the stagnation flow u = (x, -y): a symmetry plane on
+    y = 0 (normal (0, -1), corners excluded) and velocity-Dirichlet points on the
+    other three edges (corners included)."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / nx
+    g = (np.arange(nx) + 0.5) * h
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    inter = np.stack([X.ravel(), Y.ravel()], axis=1) + rng.uniform(-jitter * h, jitter * h, size=(nx * nx, 2))
+    sym, sym_n = _edge_points(h, 0.0, 1.0, 0.0, nx - 1, (0.0, -1.0))     # x = h .. 1-h
+    sym = sym[: nx - 1]
+    sym_n = sym_n[: nx - 1]
+    right, rn = _edge_points(1.0, 0.0, 1.0, 1.0, nx, (1.0, 0.0))
+    top, tn = _edge_points(1.0, 1.0, 0.0, 1.0, nx, (0.0, 1.0))
+    left, ln = _edge_points(0.0, 1.0, 0.0, 0.0, nx, (-1.0, 0.0))
+    xyz = np.concatenate([inter, sym, right, top, left])
+    kind = np.concatenate([np.zeros(len(inter), np.uint8), np.full(len(sym), SYMMETRY, np.uint8),
+                           np.full(len(right) + len(top) + len(left), DIRICHLET, np.uint8)])
+    normal = np.concatenate([np.zeros_like(inter), sym_n, rn, tn, ln])
+    return _finish(2, xyz, kind, normal, f"symmetric_square_{len(xyz)}", h, {"flow": "stagnation", "nu": 0.05},
+                   centre=(0.5, 0.5), boundary_kind=None)
+
+
+def kovasznay_strip(nx: int = 40, ny: int = 10, seed: int = 19, jitter: float = 0.2, Re: float = 40.0) -> Cloud:
+    """Kovasznay flow on [-0.5, 1.5] x [0, 0.5]: both y = 0 and y = 0.5 are
+    symmetry lines of the flow (v = 0, du/dy = 0), so they carry symmetry
+    points (corners excluded); inlet and outlet edges are velocity-Dirichlet."""
+    rng = np.random.default_rng(seed)
+    hx, hy = 2.0 / nx, 0.5 / ny
+    gx = -0.5 + (np.arange(nx) + 0.5) * hx
+    gy = (np.arange(ny) + 0.5) * hy
+    X, Y = np.meshgrid(gx, gy, indexing="ij")
+    inter = np.stack([X.ravel(), Y.ravel()], axis=1)
+    inter = inter + np.stack([rng.uniform(-jitter * hx, jitter * hx, len(inter)),
+                              rng.uniform(-jitter * hy, jitter * hy, len(inter))], axis=1)
+    bot, bn = _edge_points(-0.5 + hx, 0.0, 1.5, 0.0, nx - 1, (0.0, -1.0))
+    top, tn = _edge_points(1.5 - hx, 0.5, -0.5, 0.5, nx - 1, (0.0, 1.0))
+    bot, bn, top, tn = bot[: nx - 1], bn[: nx - 1], top[: nx - 1], tn[: nx - 1]
+    inl, iln = _edge_points(-0.5, 0.5, -0.5, 0.0, ny, (-1.0, 0.0), include_end=True)
+    outl, oln = _edge_points(1.5, 0.0, 1.5, 0.5, ny, (1.0, 0.0), include_end=True)
+    xyz = np.concatenate([inter, bot, top, inl, outl])
+    kind = np.concatenate([np.zeros(len(inter), np.uint8), np.full(len(bot) + len(top), SYMMETRY, np.uint8),
+                           np.full(len(inl) + len(outl), DIRICHLET, np.uint8)])
+    normal = np.concatenate([np.zeros_like(inter), bn, tn, iln, oln])
+    return _finish(2, xyz, kind, normal, f"kovasznay_strip_{len(xyz)}", min(hx, hy),
+                   {"flow": "kovasznay", "Re": Re, "nu": 1.0 / Re, "seed": seed},
+                   centre=(0.5, 0.25), boundary_kind=None)
 
 
 def poiseuille_channel(nx: int = 48, ny: int = 16, length: float = 3.0, seed: int = 13, jitter: float = 0.2,
