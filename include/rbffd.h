@@ -112,6 +112,11 @@ typedef struct {
     int64_t pin;            /* interior point whose pressure correction is 0, or -1
                                (none; needed only when no prescribed-pressure point
                                fixes the pressure level)                             */
+    double period[3];       /* > 0: the cloud wraps along that axis with this period
+                               (Sec. 3.1, periodic boundaries): point j also stands
+                               at x_j +- period e_d, and clouds near one face take
+                               points from the other. The points' extent along the
+                               axis must be below the period. 0: not periodic        */
 } rbffd_cloud;
 
 typedef struct {

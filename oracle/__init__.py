@@ -259,10 +259,50 @@ class Operators:
     pval: np.ndarray      # (n, q) pressure-correction matrix
 
 
+def periodic_images(xyz, period):
+    """The points followed by all their images x_j + m L e (m in {-1, 0, 1}
+    along each periodic axis, not all 0), image coordinates formed as x + L or
+    x - L; returns (coordinates, index of the point each row is an image of)."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    n, dim = xyz.shape
+    rows, owner = [xyz], [np.arange(n)]
+    for a in (-1, 0, 1):
+        for b in (-1, 0, 1):
+            for c in (-1, 0, 1):
+                m = (a, b, c)
+                if m == (0, 0, 0) or any(m[d] != 0 and (d >= dim or not period[d] > 0) for d in range(3)):
+                    continue
+                y = xyz.copy()
+                for d in range(dim):
+                    if m[d] > 0:
+                        y[:, d] = xyz[:, d] + period[d]
+                    elif m[d] < 0:
+                        y[:, d] = xyz[:, d] - period[d]
+                rows.append(y)
+                owner.append(np.arange(n))
+    return np.concatenate(rows), np.concatenate(owner)
+
+
 def build_operators(cloud, k, q=None, phs=3) -> Operators:
+    """Clouds, weights and operators (Sec. 2). A periodic cloud (Sec. 3.1)
+    takes its clouds among all images of its points, by brute force; the
+    weights use the images' coordinates and the clouds are then written with
+    the indices of the points the images stand for."""
     q = default_q(cloud.dim, k) if q is None else q
-    nbr = knn(cloud.xyz, q)
-    w = weights(cloud.xyz, nbr, k, phs)
+    period = tuple(getattr(cloud, "period", (0.0, 0.0, 0.0)))
+    if any(p > 0 for p in period[:cloud.dim]):
+        n = cloud.n
+        imgs, owner = periodic_images(cloud.xyz, period)
+        nb_img = knn_points(imgs, q, cloud.xyz)
+        full = np.zeros((len(imgs), q), np.int32)
+        full[:n] = nb_img
+        w = weights(imgs, full, k, phs, queries=np.arange(n))
+        nbr = owner[nb_img].astype(np.int32)
+        if any(len(set(r)) != q for r in nbr):
+            raise ValueError("a cloud holds two images of one point: period too small for q")
+    else:
+        nbr = knn(cloud.xyz, q)
+        w = weights(cloud.xyz, nbr, k, phs)
     col, val = csr(nbr, w)
     pv = poisson_values(cloud, col, val)
     return Operators(cloud, k, q, phs, nbr, w, col, val, pv)

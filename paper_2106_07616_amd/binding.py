@@ -39,7 +39,7 @@ class RbffdError(RuntimeError):
 
 class CloudT(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int64), ("xyz", C.c_void_p), ("kind", C.c_void_p),
-                ("normal", C.c_void_p), ("pin", C.c_int64)]
+                ("normal", C.c_void_p), ("pin", C.c_int64), ("period", C.c_double * 3)]
 
 
 class StencilOptsT(C.Structure):
@@ -174,6 +174,7 @@ class DeviceCloud:
     kind: torch.Tensor     # [n] uint8
     normal: torch.Tensor   # [n, dim] float64
     pin: int
+    period: tuple = (0.0, 0.0, 0.0)   # > 0: periodic along that axis
 
     @staticmethod
     def from_numpy(cloud, device="cuda"):
@@ -181,10 +182,11 @@ class DeviceCloud:
                            torch.as_tensor(cloud.xyz, dtype=torch.float64, device=device).contiguous(),
                            torch.as_tensor(cloud.kind, dtype=torch.uint8, device=device).contiguous(),
                            torch.as_tensor(cloud.normal, dtype=torch.float64, device=device).contiguous(),
-                           int(cloud.pin))
+                           int(cloud.pin), tuple(float(v) for v in getattr(cloud, "period", (0.0, 0.0, 0.0))))
 
     def struct(self) -> CloudT:
-        return CloudT(self.dim, self.n, _ptr(self.xyz), _ptr(self.kind), _ptr(self.normal), self.pin)
+        return CloudT(self.dim, self.n, _ptr(self.xyz), _ptr(self.kind), _ptr(self.normal), self.pin,
+                      (C.c_double * 3)(*self.period))
 
 
 def rbffd_stencil_sizes(dim: int, poly_degree: int, q: int = 0, phs_power: int = 3):

@@ -1,4 +1,6 @@
 // C ABI entry points, context and error handling.
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -88,7 +90,150 @@ static int check_cloud(const rbffd_cloud *c)
     if (c->dim != 2 && c->dim != 3) return fail(RBFFD_E_ARG, "dim must be 2 or 3");
     if (c->n < 1 || c->n >= (int64_t(1) << 31)) return fail(RBFFD_E_ARG, "n out of range");
     if (!c->xyz) return fail(RBFFD_E_ARG, "cloud.xyz is NULL");
+    for (int d = 0; d < 3; ++d) {
+        if (!(c->period[d] >= 0.0) || !std::isfinite(c->period[d]))
+            return fail(RBFFD_E_ARG, "cloud.period must be finite and >= 0");
+        if (d >= c->dim && c->period[d] != 0.0) return fail(RBFFD_E_ARG, "cloud.period set beyond dim");
+    }
     return RBFFD_OK;
+}
+
+static bool is_periodic(const rbffd_cloud *c)
+{
+    for (int d = 0; d < c->dim; ++d)
+        if (c->period[d] > 0.0) return true;
+    return false;
+}
+
+// Stencils of a cloud that wraps along its periodic axes (Sec. 3.1): ghost
+// images x_j +- period e_d of the points within a band of each periodic face
+// are appended, the neighbour search and the weights run on the augmented
+// points (the images' own coordinates: clouds near one face take points from
+// the other), and neighbour indices are mapped back to the points they are
+// images of. The band starts at twice the radius that holds q points at the
+// mean density and doubles until every point's q-th neighbour lies within it,
+// which makes the search exact.
+static int stencils_periodic(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_stencil_opts *opts, int q,
+                             int32_t *nbr, double *w, int64_t *bad_point, hipStream_t s)
+{
+    const int dim = cloud->dim;
+    const int64_t n = cloud->n;
+    std::vector<double> x((size_t)n * dim);
+    RB_HIP(hipMemcpyAsync(x.data(), cloud->xyz, sizeof(double) * n * dim, hipMemcpyDeviceToHost, s));
+    RB_HIP(hipStreamSynchronize(s));
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int d = 0; d < dim; ++d) {
+        lo[d] = INFINITY;
+        hi[d] = -INFINITY;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < dim; ++d) {
+            const double v = x[i * dim + d];
+            if (!std::isfinite(v)) return fail(RBFFD_E_ARG, "non-finite coordinates");
+            lo[d] = std::min(lo[d], v);
+            hi[d] = std::max(hi[d], v);
+        }
+    const double *L = cloud->period;
+    double vol = 1.0;
+    for (int d = 0; d < dim; ++d) {
+        if (L[d] > 0.0 && !(hi[d] - lo[d] < L[d]))
+            return fail(RBFFD_E_ARG, "the cloud's extent along a periodic axis is not below its period");
+        vol *= (L[d] > 0.0) ? L[d] : std::max(hi[d] - lo[d], 1e-300);
+    }
+    const double pi = 3.14159265358979323846;
+    double band = 2.0 * ((dim == 2) ? std::sqrt(q * vol / (pi * (double)n))
+                                    : std::cbrt(3.0 * q * vol / (4.0 * pi * (double)n)));
+    // shift vectors m in {-1, 0, 1}^dim, nonzero only along periodic axes
+    std::vector<std::array<int, 3>> shifts;
+    for (int a = -1; a <= 1; ++a)
+        for (int b = -1; b <= 1; ++b)
+            for (int c = -1; c <= 1; ++c) {
+                const int m[3] = {a, b, c};
+                bool ok = !(a == 0 && b == 0 && c == 0);
+                for (int d = 0; d < 3; ++d)
+                    if (m[d] != 0 && (d >= dim || !(L[d] > 0.0))) ok = false;
+                if (ok) shifts.push_back({a, b, c});
+            }
+    int64_t *bad_dev = nullptr;
+    RB_CHECK(workspace(ctx, WS_MISC, sizeof(int64_t), (void **)&bad_dev));
+    int64_t *hb = nullptr;
+    RB_CHECK(host_scratch(ctx, kHostMisc, sizeof(int64_t), (void **)&hb));
+    std::vector<int32_t> hn((size_t)n * q);
+    for (int attempt = 0; attempt < 12; ++attempt, band *= 2.0) {
+        std::vector<double> aug(x);
+        std::vector<int32_t> owner((size_t)n);
+        for (int64_t i = 0; i < n; ++i) owner[i] = (int32_t)i;
+        for (const auto &m : shifts)
+            for (int64_t j = 0; j < n; ++j) {
+                double y[3];
+                bool keep = true;
+                for (int d = 0; d < dim; ++d) {
+                    const double v = x[j * dim + d];
+                    y[d] = (m[d] > 0) ? v + L[d] : ((m[d] < 0) ? v - L[d] : v);
+                    if (L[d] > 0.0 && (y[d] < lo[d] - band || y[d] > hi[d] + band)) keep = false;
+                }
+                if (!keep) continue;
+                for (int d = 0; d < dim; ++d) aug.push_back(y[d]);
+                owner.push_back((int32_t)j);
+            }
+        const int64_t naug = (int64_t)owner.size();
+        if (naug >= (int64_t(1) << 31)) return fail(RBFFD_E_ARG, "too many periodic images");
+        double *aug_dev = nullptr;
+        const size_t abytes = sizeof(double) * naug * dim;
+        RB_CHECK(dev_alloc(ctx, (void **)&aug_dev, abytes));
+        int st = RBFFD_OK;
+        hipError_t e = hipMemcpyAsync(aug_dev, aug.data(), abytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) st = hip_fail(e, "periodic images");
+        if (st == RBFFD_OK) st = launch_knn_points(ctx, dim, naug, aug_dev, n, aug_dev, q, nbr, s);
+        if (st == RBFFD_OK) {
+            e = hipMemcpyAsync(hn.data(), nbr, sizeof(int32_t) * n * q, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) st = hip_fail(e, "periodic neighbours");
+        }
+        bool inside = true;
+        for (int64_t i = 0; st == RBFFD_OK && i < n && inside; ++i) {
+            const int64_t j = hn[i * q + q - 1];
+            double d2 = 0.0;
+            for (int d = 0; d < dim; ++d) {
+                const double dd = aug[j * dim + d] - x[i * dim + d];
+                d2 += dd * dd;
+            }
+            inside = std::sqrt(d2) <= band;
+        }
+        if (st == RBFFD_OK && !inside) {
+            dev_free(ctx, aug_dev, abytes);
+            continue;   // a q-th neighbour beyond the band: widen it
+        }
+        if (st == RBFFD_OK)
+            st = launch_weights(ctx, dim, n, aug_dev, q, nbr, opts->poly_degree, opts->phs_power, w, bad_dev, s);
+        if (st == RBFFD_OK) {
+            e = hipMemcpyAsync(hb, bad_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) st = hip_fail(e, "periodic weights");
+        }
+        (void)hipStreamSynchronize(s);
+        dev_free(ctx, aug_dev, abytes);
+        RB_CHECK(st);
+        // neighbour indices back to the points they are images of; a point may
+        // appear in a cloud only once
+        std::vector<int32_t> row((size_t)q);
+        for (int64_t i = 0; i < n; ++i) {
+            for (int a = 0; a < q; ++a) row[a] = owner[hn[i * q + a]];
+            std::vector<int32_t> sorted(row);
+            std::sort(sorted.begin(), sorted.end());
+            if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+                return fail(RBFFD_E_ARG, "point " + std::to_string(i) +
+                                             ": its cloud holds two images of one point (period too small for q)");
+            for (int a = 0; a < q; ++a) hn[i * q + a] = row[a];
+        }
+        RB_HIP(hipMemcpyAsync(nbr, hn.data(), sizeof(int32_t) * n * q, hipMemcpyHostToDevice, s));
+        RB_HIP(hipStreamSynchronize(s));
+        const int64_t bad = (*hb == INT64_MAX) ? -1 : *hb;
+        if (bad_point) *bad_point = bad;
+        if (bad >= 0) return fail(RBFFD_E_SINGULAR, "singular collocation system at point " + std::to_string(bad));
+        return RBFFD_OK;
+    }
+    return fail(RBFFD_E_ARG, "no band of periodic images holds every cloud");
 }
 
 static int binom(int a, int b)
@@ -195,6 +340,8 @@ int rbffd_build_stencils(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_s
     if (q + m > 128) return fail(RBFFD_E_ARG, "collocation systems larger than 128 (q + m) are not supported");
     RB_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)hip_stream;
+    if (bad_point) *bad_point = -1;
+    if (is_periodic(cloud)) return stencils_periodic(ctx, cloud, opts, q, nbr, w, bad_point, s);
     RB_CHECK(launch_knn(ctx, cloud->dim, cloud->n, cloud->xyz, q, nbr, s));
     int64_t *bad_dev = nullptr;
     RB_CHECK(workspace(ctx, WS_MISC, sizeof(int64_t), (void **)&bad_dev));
@@ -320,6 +467,7 @@ int rbffd_interpolate(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_sten
     RB_CHECK(resolve_sizes(cloud->dim, opts, &q, &m, &R));
     if (q > cloud->n) return fail(RBFFD_E_ARG, "cloud size q exceeds the number of points");
     if (q + m > 128) return fail(RBFFD_E_ARG, "collocation systems larger than 128 (q + m) are not supported");
+    if (is_periodic(cloud)) return fail(RBFFD_E_ARG, "interpolation on periodic clouds is not supported");
     if (nq < 0 || nfield < 0) return fail(RBFFD_E_ARG, "nq and nfield must be >= 0");
     if (nq > INT32_MAX) return fail(RBFFD_E_ARG, "too many query points");
     if (nq == 0) return RBFFD_OK;

@@ -576,3 +576,36 @@ def test_symmetry_strip_keeps_kovasznay_flow(orc):
                                        tol_outer=0.0, tol_krylov=1e-12, max_outer=1, max_krylov=20000)
         changes.append(np.abs(u1 - vel).mean())
     assert changes[1] < changes[0] / 2 and changes[1] < 2e-3, changes
+
+
+def test_periodic_clouds_wrap_the_seam(orc):
+    """A periodic cloud (Sec. 3.1) takes its neighbours across the seam: its
+    neighbour distances equal scipy's periodic k-d tree's, and derivative
+    errors near the seam match those inside, falling at orders k (gradient)
+    and k - 1 (Laplacian), band -0.7."""
+    from scipy.spatial import cKDTree
+    c = W.taylor_green_periodic(nx=24)
+    ops = orc.build_operators(c, 4)
+    L = 2 * np.pi
+    dt_tree, _ = cKDTree(c.xyz, boxsize=L).query(c.xyz, ops.q)
+    imgs, owner = orc.periodic_images(c.xyz, c.period)
+    nb_img = orc.knn_points(imgs, ops.q, c.xyz)
+    d_ours = np.sqrt(((imgs[nb_img] - c.xyz[:, None, :]) ** 2).sum(-1))
+    np.testing.assert_allclose(d_ours, dt_tree, rtol=1e-12, atol=1e-13)
+    np.testing.assert_array_equal(owner[nb_img], ops.nbr)
+    k = 4
+    hs, eg, el, ratio = [], [], [], []
+    for nx in (24, 36, 54):
+        c = W.taylor_green_periodic(nx=nx)
+        ops = orc.build_operators(c, k)
+        x, y = c.xyz[:, 0], c.xyz[:, 1]
+        f = np.sin(x) * np.cos(2 * y)
+        d = orc.apply_ops(ops.col, ops.val, f)
+        ex = np.abs(d[0] - np.cos(x) * np.cos(2 * y))
+        near = (x < 3 * c.h) | (x > L - 3 * c.h) | (y < 3 * c.h) | (y > L - 3 * c.h)
+        hs.append(c.h)
+        eg.append(ex.mean())
+        el.append(np.abs(d[2] + 5 * f).mean())
+        ratio.append(ex[near].max() / ex[~near].max())
+    assert _fit_slope(hs, eg) >= k - 0.7 and _fit_slope(hs, el) >= k - 1 - 0.7
+    assert max(ratio) < 2.0, ratio

@@ -38,6 +38,7 @@ class Cloud:
     name: str = ""
     h: float = 0.0           # nominal point spacing of the generator
     meta: dict = field(default_factory=dict)
+    period: tuple = (0.0, 0.0, 0.0)   # > 0: the cloud wraps along that axis
 
     @property
     def n(self) -> int:
@@ -218,7 +219,7 @@ def morton_order(xyz: np.ndarray) -> np.ndarray:
     return np.argsort(code, kind="stable")
 
 
-def _finish(dim, xyz, kind, normal, name, h, meta, centre, boundary_kind=DIRICHLET):
+def _finish(dim, xyz, kind, normal, name, h, meta, centre, boundary_kind=DIRICHLET, period=(0.0, 0.0, 0.0)):
     if boundary_kind is not None:   # None: keep the kinds given per point
         kind = np.where(kind != INTERIOR, boundary_kind, INTERIOR)
     kind = kind.astype(np.uint8)
@@ -235,7 +236,8 @@ def _finish(dim, xyz, kind, normal, name, h, meta, centre, boundary_kind=DIRICHL
     pin = int(np.lexsort((np.arange(len(d2)), d2))[0])
     if ((kind == PRESCRIBED_PRESSURE) | (kind == OUTLET)).any():
         pin = -1   # the prescribed boundary pressure fixes the pressure level
-    return Cloud(dim=dim, xyz=xyz, kind=kind, normal=normal, pin=pin, name=name, h=h, meta=meta)
+    return Cloud(dim=dim, xyz=xyz, kind=kind, normal=normal, pin=pin, name=name, h=h, meta=meta,
+                 period=tuple(period))
 
 
 def _square_perimeter(lo, hi, per_edge):
@@ -399,6 +401,22 @@ def kovasznay_strip(nx: int = 40, ny: int = 10, seed: int = 19, jitter: float = 
     return _finish(2, xyz, kind, normal, f"kovasznay_strip_{len(xyz)}", min(hx, hy),
                    {"flow": "kovasznay", "Re": Re, "nu": 1.0 / Re, "seed": seed},
                    centre=(0.5, 0.25), boundary_kind=None)
+
+
+def taylor_green_periodic(nx: int = 48, seed: int = 23, jitter: float = 0.2, nu: float = 0.01) -> Cloud:
+    """The Taylor-Green vortex on the periodic square [0, 2 pi)^2 (period 2 pi
+    in x and y, no boundary points): a cell-centred nx-by-nx lattice, each
+    coordinate jittered by U(-jitter h, jitter h)."""
+    rng = np.random.default_rng(seed)
+    L = 2.0 * np.pi
+    h = L / nx
+    g = (np.arange(nx) + 0.5) * h
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    xyz = np.stack([X.ravel(), Y.ravel()], axis=1) + rng.uniform(-jitter * h, jitter * h, size=(nx * nx, 2))
+    kind = np.zeros(len(xyz), np.uint8)
+    return _finish(2, xyz, kind, np.zeros_like(xyz), f"taylor_green_periodic_{len(xyz)}", h,
+                   {"flow": "taylor_green", "nu": nu, "seed": seed}, centre=(np.pi, np.pi), boundary_kind=None,
+                   period=(L, L, 0.0))
 
 
 def poiseuille_channel(nx: int = 48, ny: int = 16, length: float = 3.0, seed: int = 13, jitter: float = 0.2,
