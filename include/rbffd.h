@@ -295,6 +295,11 @@ typedef struct {
     int preconditioner;     /* of the pressure-correction solve: RBFFD_PREC_JACOBI or
                                RBFFD_PREC_BLOCK64; momentum and boundary-pressure
                                solves use Jacobi                                      */
+    double force[3];        /* constant body force per unit volume added to the
+                               momentum equations (and to the normal momentum
+                               equation of the boundary pressure): the mean
+                               pressure gradient that drives a periodic channel
+                               (Sec. 4, Eq. bellow dp_dx); 0 for none                 */
 } rbffd_step_opts;
 
 typedef struct {

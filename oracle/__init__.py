@@ -315,7 +315,7 @@ class _StepCfg(C.Structure):
                 ("rho", C.c_double), ("mu", C.c_double), ("dt", C.c_double),
                 ("alpha", C.c_double * 3),
                 ("tol_outer", C.c_double), ("tol_krylov", C.c_double),
-                ("max_outer", C.c_int), ("max_krylov", C.c_int)]
+                ("max_outer", C.c_int), ("max_krylov", C.c_int), ("force", C.c_double * 3)]
 
 
 class _StepStats(C.Structure):
@@ -329,9 +329,10 @@ BDF1 = (1.0, -1.0, 0.0)
 
 
 def simple_step(ops: Operators, u, u_prev, p, u_bc, rho, mu, dt, alpha=BDF2,
-                tol_outer=1e-6, tol_krylov=1e-10, max_outer=50, max_krylov=5000, p_bc=None):
+                tol_outer=1e-6, tol_krylov=1e-10, max_outer=50, max_krylov=5000, p_bc=None, force=(0.0, 0.0, 0.0)):
     """One time step; returns (u_new, u_n, p_new, stats dict). Inputs are not modified.
-    p_bc: pressure at t^{n+1} on prescribed-pressure (kind 2) points."""
+    p_bc: pressure at t^{n+1} on prescribed-pressure (kind 2) and outlet points.
+    force: constant body force per unit volume (a mean pressure gradient)."""
     cl = ops.cloud
     n, dim = cl.n, cl.dim
     u = np.array(u, dtype=np.float64, copy=True).reshape(dim, n)
@@ -345,7 +346,8 @@ def simple_step(ops: Operators, u, u_prev, p, u_bc, rho, mu, dt, alpha=BDF2,
     pv = _c(ops.pval, np.float64)
     cfg = _StepCfg(dim, ops.q, n, _p(kind).value, _p(nrm).value, int(cl.pin), _p(col).value,
                    _p(val).value, _p(pv).value, rho, mu, dt, (C.c_double * 3)(*alpha),
-                   tol_outer, tol_krylov, max_outer, max_krylov)
+                   tol_outer, tol_krylov, max_outer, max_krylov,
+                   (C.c_double * 3)(*(tuple(force) + (0.0,) * (3 - len(force)))))
     st = _StepStats()
     pbc = None if p_bc is None else _c(p_bc, np.float64).reshape(n)
     if pbc is None and ((cl.kind == 2) | (cl.kind == 3)).any():

@@ -597,6 +597,7 @@ typedef struct {
     double alpha[3];
     double tol_outer, tol_krylov;
     int max_outer, max_krylov;
+    double force[3];      /* constant body force per unit volume (mean pressure gradient) */
 } orc_step_cfg;
 
 typedef struct {
@@ -695,7 +696,7 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
             for (int e = 0; e < dim; ++e) {
                 double g = 0.0;
                 for (int a = 0; a < q; ++a) g = g + c->val[e * nnz + i * q + a] * pr[c->col[i * q + a]];
-                bm[e * n + i] = -rho * (a2 * u[e * n + i] + a3 * u_prev[e * n + i]) / dt - g;
+                bm[e * n + i] = -rho * (a2 * u[e * n + i] + a3 * u_prev[e * n + i]) / dt - g + c->force[e];
             }
         }
         /* momentum solves, one per velocity component, started from u^r */
@@ -764,7 +765,7 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
                 }
                 double lap = 0.0;
                 for (int a = 0; a < q; ++a) lap = lap + c->val[dim * nnz + i * q + a] * ut[e * n + c->col[i * q + a]];
-                double comp = -dudt - rho * adv + mu * lap;
+                double comp = -dudt - rho * adv + mu * lap + c->force[e];
                 rhs = rhs + c->normal[i * dim + e] * comp;
             }
             for (int a = 0; a < q; ++a) {

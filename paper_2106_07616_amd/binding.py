@@ -58,7 +58,8 @@ class KrylovStatsT(C.Structure):
 class StepOptsT(C.Structure):
     _fields_ = [("rho", C.c_double), ("mu", C.c_double), ("dt", C.c_double), ("alpha", C.c_double * 3),
                 ("tol_outer", C.c_double), ("tol_krylov", C.c_double), ("max_outer", C.c_int),
-                ("max_krylov", C.c_int), ("precision", C.c_int), ("preconditioner", C.c_int)]
+                ("max_krylov", C.c_int), ("precision", C.c_int), ("preconditioner", C.c_int),
+                ("force", C.c_double * 3)]
 
 
 class StepStatsT(C.Structure):
@@ -379,12 +380,12 @@ def simple_step(ctx: Context, ops: Operators, u: torch.Tensor, u_prev: torch.Ten
                 u_bc: torch.Tensor, rho: float, mu: float, dt: float, alpha=BDF2, tol_outer: float = 1e-6,
                 tol_krylov: float = 1e-10, max_outer: int = 50, max_krylov: int = 5000,
                 precision: int = RBFFD_FP64, p_bc: torch.Tensor | None = None,
-                preconditioner: int = RBFFD_PREC_JACOBI):
+                preconditioner: int = RBFFD_PREC_JACOBI, force=(0.0, 0.0, 0.0)):
     """One time step in place on u [dim, n], u_prev [dim, n], p [n]; returns stats.
     p_bc [n]: pressure at t^{n+1} on prescribed-pressure points. A limit reached
     (E_NOCONV) is reported in the stats, not raised."""
     o = StepOptsT(rho, mu, dt, (C.c_double * 3)(*alpha), tol_outer, tol_krylov, max_outer, max_krylov, precision,
-                  preconditioner)
+                  preconditioner, (C.c_double * 3)(*(tuple(force) + (0.0,) * (3 - len(force)))))
     s = StepStatsT()
     dn = ops.dim * ops.n
     st = lib().simple_step(ctx.handle, ops.handle, _f64(u, dn, "u"), _f64(u_prev, dn, "u_prev"), _f64(p, ops.n, "p"),

@@ -674,6 +674,8 @@ int simple_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev,
     if (ops->n_prescribed > 0 && !p_bc) return fail(RBFFD_E_ARG, "p_bc is required: the cloud has prescribed-pressure points");
     if (!(opts->rho > 0.0) || !(opts->mu >= 0.0) || !(opts->dt > 0.0) || !std::isfinite(opts->dt))
         return fail(RBFFD_E_ARG, "rho, mu, dt must be positive and finite");
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(opts->force[d])) return fail(RBFFD_E_ARG, "the body force must be finite");
     if (!(opts->alpha[0] != 0.0) || !std::isfinite(opts->alpha[1]) || !std::isfinite(opts->alpha[2]))
         return fail(RBFFD_E_ARG, "bad BDF coefficients");
     if (opts->max_outer < 1 || opts->max_krylov < 1 || !(opts->tol_krylov >= 0.0) || !(opts->tol_outer >= 0.0))

@@ -26,6 +26,12 @@ inline int blocks_for(int64_t n)
     return (int)std::max<int64_t>(1, b);
 }
 
+// constant body force per unit volume (the mean pressure gradient of a periodic
+// channel), passed by value
+struct Force3 {
+    double v[3];
+};
+
 // u^r = u^n with the Dirichlet values of t^{n+1} on velocity-prescribed points; p^r = p^n
 __global__ void k_start(int64_t n, int dim, const uint8_t *__restrict__ kind, const double *__restrict__ u,
                         const double *__restrict__ ubc, const double *__restrict__ p, double *__restrict__ ur,
@@ -55,8 +61,8 @@ __global__ __launch_bounds__(kBlock) void k_momentum(int64_t n, int q, const int
                                                      const double *__restrict__ un, const double *__restrict__ up,
                                                      const double *__restrict__ ubc, const double *__restrict__ pr,
                                                      double rho, double mu, double dt, double a1, double a2, double a3,
-                                                     int cd, double *__restrict__ mval, double *__restrict__ mdinv,
-                                                     double *__restrict__ bm)
+                                                     Force3 f, int cd, double *__restrict__ mval,
+                                                     double *__restrict__ mdinv, double *__restrict__ bm)
 {
     const int64_t i = (int64_t)lb() * kBlock + threadIdx.x;
     if (i >= pad64(n)) return;
@@ -114,7 +120,8 @@ __global__ __launch_bounds__(kBlock) void k_momentum(int64_t n, int q, const int
     }
     mdinv[i] = (diag != 0.0) ? 1.0 / diag : 1.0;
     if (!cd)
-        for (int e = 0; e < DIM; ++e) bm[e * n + i] = -rho * (a2 * un[e * n + i] + a3 * up[e * n + i]) / dt - g[e];
+        for (int e = 0; e < DIM; ++e)
+            bm[e * n + i] = -rho * (a2 * un[e * n + i] + a3 * up[e * n + i]) / dt - g[e] + f.v[e];
 }
 
 // Symmetry rows of the momentum matrix for velocity component e (Sec. 3.1):
@@ -196,7 +203,8 @@ __global__ __launch_bounds__(kBlock) void k_boundary_rhs(int64_t n, int64_t nb, 
                                                          const double *__restrict__ un, const double *__restrict__ up,
                                                          const double *__restrict__ pa, const double *__restrict__ pr,
                                                          double rho, double mu, double dt, double a1, double a2,
-                                                         double a3, double *__restrict__ bb, double *__restrict__ pb)
+                                                         double a3, Force3 f, double *__restrict__ bb,
+                                                         double *__restrict__ pb)
 {
     const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (b >= nb) return;
@@ -222,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_boundary_rhs(int64_t n, int64_t nb, 
         const double dudt = rho * (a1 * ut[c * n + i] + a2 * un[c * n + i] + a3 * up[c * n + i]) / dt;
         double adv = 0.0;
         for (int g = 0; g < DIM; ++g) adv = adv + ut[g * n + i] * grad[g][c];
-        const double comp = -dudt - rho * adv + mu * lap[c];
+        const double comp = -dudt - rho * adv + mu * lap[c] + f.v[c];
         rhs = rhs + normal[i * DIM + c] * comp;
     }
     bb[b] = rhs - off;
@@ -374,6 +382,7 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
 
     const double rho = o->rho, mu = o->mu, dt = o->dt;
     const double a1 = o->alpha[0], a2 = o->alpha[1], a3 = o->alpha[2];
+    const Force3 force{{o->force[0], o->force[1], o->force[2]}};
     const int gn = (int)((n + kBlock - 1) / kBlock);
     const int gpad = (int)((ops->npad + kBlock - 1) / kBlock);
     const int nblk = blocks_for(n);
@@ -388,11 +397,11 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
         // step 2: momentum matrix, right-hand sides, and the solves from u^r
         if (dim == 2)
             hipLaunchKernelGGL(k_momentum<2>, dim3(gpad), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs, ops->kind,
-                               ops->normal, B.ur, u, u_prev, u_bc, B.pr, rho, mu, dt, a1, a2, a3, 0, ops->mval,
+                               ops->normal, B.ur, u, u_prev, u_bc, B.pr, rho, mu, dt, a1, a2, a3, force, 0, ops->mval,
                                ops->mdinv, B.bm);
         else
             hipLaunchKernelGGL(k_momentum<3>, dim3(gpad), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs, ops->kind,
-                               ops->normal, B.ur, u, u_prev, u_bc, B.pr, rho, mu, dt, a1, a2, a3, 0, ops->mval,
+                               ops->normal, B.ur, u, u_prev, u_bc, B.pr, rho, mu, dt, a1, a2, a3, force, 0, ops->mval,
                                ops->mdinv, B.bm);
         RB_HIP(hipGetLastError());
         RB_HIP(hipMemcpyAsync(B.ut, B.ur, vec * dim, hipMemcpyDeviceToDevice, s));
@@ -459,11 +468,11 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
             if (dim == 2)
                 hipLaunchKernelGGL(k_boundary_rhs<2>, dim3(gb), dim3(kBlock), 0, s, n, ops->nb, q, ops->col, ops->val, vs,
                                    ops->pval, ops->kind, ops->normal, ops->bidx, B.ut, u, u_prev, B.pa, B.pr, rho, mu,
-                                   dt, a1, a2, a3, B.bb, B.pb);
+                                   dt, a1, a2, a3, force, B.bb, B.pb);
             else
                 hipLaunchKernelGGL(k_boundary_rhs<3>, dim3(gb), dim3(kBlock), 0, s, n, ops->nb, q, ops->col, ops->val, vs,
                                    ops->pval, ops->kind, ops->normal, ops->bidx, B.ut, u, u_prev, B.pa, B.pr, rho, mu,
-                                   dt, a1, a2, a3, B.bb, B.pb);
+                                   dt, a1, a2, a3, force, B.bb, B.pb);
             RB_HIP(hipGetLastError());
             KrylovResult kb;
             RB_CHECK(bicgstab(ctx, ops->nb, q, cols_plain(ops->gcol), ops->gval, ops->gdinv, 1, B.bb, B.pb, o->tol_krylov,
@@ -529,10 +538,12 @@ int convdiff_lambda(rbffd_ctx *ctx, const rbffd_ops *ops, const double *u0, doub
     const int nblk = blocks_for(n);
     if (dim == 2)
         hipLaunchKernelGGL(k_momentum<2>, dim3(gpad), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs, ops->kind,
-                           ops->normal, u0, u0, u0, u0, u0, rho, mu, 1.0, 0.0, 0.0, 0.0, 1, ops->mval, ops->mdinv, y);
+                           ops->normal, u0, u0, u0, u0, u0, rho, mu, 1.0, 0.0, 0.0, 0.0, Force3{}, 1, ops->mval,
+                           ops->mdinv, y);
     else
         hipLaunchKernelGGL(k_momentum<3>, dim3(gpad), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs, ops->kind,
-                           ops->normal, u0, u0, u0, u0, u0, rho, mu, 1.0, 0.0, 0.0, 0.0, 1, ops->mval, ops->mdinv, y);
+                           ops->normal, u0, u0, u0, u0, u0, rho, mu, 1.0, 0.0, 0.0, 0.0, Force3{}, 1, ops->mval,
+                           ops->mdinv, y);
     hipLaunchKernelGGL(k_pow_start, dim3(gn), dim3(kBlock), 0, s, n, y);
     hipLaunchKernelGGL(k_sq_partial, dim3(nblk), dim3(kBlock), 0, s, n, y, part);
     hipLaunchKernelGGL(k_normalise, dim3(nblk), dim3(kBlock), 0, s, n, y, x, part, nblk, nrm);

@@ -547,3 +547,25 @@ def test_symmetry_normal_must_be_a_coordinate_axis(ctx):
     with pytest.raises(R.RbffdError) as e:
         R.rbffd_assemble(ctx, dc, nbr, w, 2)
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_forced_periodic_channel_fixed_point(ctx, orc, k):
+    """A periodic channel driven by a body force holds Poiseuille flow at
+    constant pressure, on the GPU as in the oracle (quadratic fields)."""
+    c = W.periodic_channel()
+    s = R.Solver(ctx, c, k)
+    ops_o = orc.build_operators(c, k)
+    vel, p = W.flow_fields(c)
+    kw = dict(tol_outer=1e-13, tol_krylov=1e-14, max_outer=3, max_krylov=20000)
+    uo, _, po, sto = orc.simple_step(ops_o, vel, vel, p, vel, 1.0, c.meta["nu"], 0.05, alpha=orc.BDF2,
+                                     force=c.meta["force"], **kw)
+    u = torch.tensor(vel, device="cuda")
+    pg = torch.tensor(p, device="cuda")
+    R.simple_step(ctx, s.ops, u, torch.tensor(vel, device="cuda"), pg, torch.tensor(vel, device="cuda"), 1.0,
+                  c.meta["nu"], 0.05, R.BDF2, force=c.meta["force"], **kw)
+    ug, pgn = u.cpu().numpy(), pg.cpu().numpy()
+    print(f"[forced channel] k={k}: |u - exact| {np.abs(ug - vel).max():.1e} |p| {np.abs(pgn).max():.1e} "
+          f"|u - oracle| {np.abs(ug - uo).max():.1e}", flush=True)
+    assert np.abs(ug - vel).max() <= 1e-10 and np.abs(pgn - p).max() <= 1e-10
+    assert np.abs(ug - uo).max() <= 1e-10 and np.abs(pgn - po).max() <= 1e-10

@@ -609,3 +609,21 @@ def test_periodic_clouds_wrap_the_seam(orc):
         ratio.append(ex[near].max() / ex[~near].max())
     assert _fit_slope(hs, eg) >= k - 0.7 and _fit_slope(hs, el) >= k - 1 - 0.7
     assert max(ratio) < 2.0, ratio
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_forced_periodic_channel_is_a_fixed_point(orc, k):
+    """A channel periodic in x, driven by the body force 8 nu U e_x (the mean
+    pressure gradient of a periodic channel, Sec. 4, Eq. bellow dp_dx), holds
+    Poiseuille flow at constant pressure exactly (quadratic fields, k >= 2).
+    Without the force the flow decays: the term is used."""
+    c = W.periodic_channel()
+    ops = orc.build_operators(c, k)
+    vel, p = W.flow_fields(c)
+    kw = dict(tol_outer=1e-13, tol_krylov=1e-14, max_outer=3, max_krylov=20000)
+    u1, _, p1, st = orc.simple_step(ops, vel, vel, p, vel, 1.0, c.meta["nu"], 0.05, alpha=orc.BDF2,
+                                    force=c.meta["force"], **kw)
+    assert np.abs(u1 - vel).max() <= 1e-10, np.abs(u1 - vel).max()
+    assert np.abs(p1 - p).max() <= 1e-10, np.abs(p1 - p).max()
+    u0, _, _, _ = orc.simple_step(ops, vel, vel, p, vel, 1.0, c.meta["nu"], 0.05, alpha=orc.BDF2, **kw)
+    assert np.abs(u0 - vel).max() > 1e-4

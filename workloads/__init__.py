@@ -136,6 +136,10 @@ def flow_fields(cloud: Cloud, t: float = 0.0):
     elif flow == "beltrami":
         u, v, w, p = beltrami(x[:, 0], x[:, 1], x[:, 2], t, nu=cloud.meta.get("nu", 0.01))
         vel = np.stack([u, v, w])
+    elif flow == "poiseuille_forced":
+        u, v, _ = poiseuille(x[:, 0], x[:, 1], cloud.meta.get("U", 1.0), cloud.meta["nu"])
+        p = np.zeros_like(u)
+        vel = np.stack([u, v])
     elif flow == "poiseuille":
         u, v, p = poiseuille(x[:, 0], x[:, 1], cloud.meta.get("U", 1.0), cloud.meta["nu"])
         vel = np.stack([u, v])
@@ -401,6 +405,30 @@ def kovasznay_strip(nx: int = 40, ny: int = 10, seed: int = 19, jitter: float = 
     return _finish(2, xyz, kind, normal, f"kovasznay_strip_{len(xyz)}", min(hx, hy),
                    {"flow": "kovasznay", "Re": Re, "nu": 1.0 / Re, "seed": seed},
                    centre=(0.5, 0.25), boundary_kind=None)
+
+
+def periodic_channel(nx: int = 32, ny: int = 16, length: float = 2.0, seed: int = 29, jitter: float = 0.2,
+                     nu: float = 0.01, U: float = 1.0) -> Cloud:
+    """Channel periodic in x (period `length`) between walls y = 0 and y = 1,
+    for Poiseuille flow driven by the body force 8 nu U e_x instead of a
+    pressure gradient (meta["force"]); the pressure is then constant. A
+    jittered cell-centred lattice and wall points at the cell centres of x."""
+    rng = np.random.default_rng(seed)
+    hx, hy = length / nx, 1.0 / ny
+    gx = (np.arange(nx) + 0.5) * hx
+    gy = (np.arange(ny) + 0.5) * hy
+    X, Y = np.meshgrid(gx, gy, indexing="ij")
+    inter = np.stack([X.ravel(), Y.ravel()], axis=1)
+    inter = inter + np.stack([rng.uniform(-jitter * hx, jitter * hx, len(inter)),
+                              rng.uniform(-jitter * hy, jitter * hy, len(inter))], axis=1)
+    walls = np.concatenate([np.stack([gx, np.zeros_like(gx)], 1), np.stack([gx, np.ones_like(gx)], 1)])
+    wn = np.concatenate([np.tile([0.0, -1.0], (nx, 1)), np.tile([0.0, 1.0], (nx, 1))])
+    xyz = np.concatenate([inter, walls])
+    kind = np.concatenate([np.zeros(len(inter), np.uint8), np.full(len(walls), DIRICHLET, np.uint8)])
+    normal = np.concatenate([np.zeros_like(inter), wn])
+    return _finish(2, xyz, kind, normal, f"periodic_channel_{len(xyz)}", min(hx, hy),
+                   {"flow": "poiseuille_forced", "U": U, "nu": nu, "seed": seed, "force": (8.0 * nu * U, 0.0, 0.0)},
+                   centre=(length / 2, 0.5), boundary_kind=None, period=(length, 0.0, 0.0))
 
 
 def taylor_green_periodic(nx: int = 48, seed: int = 23, jitter: float = 0.2, nu: float = 0.01) -> Cloud:
