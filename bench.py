@@ -661,7 +661,9 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "spmv_kernel<double> (sliced-ELL SpMV, pressure-correction matrix)",
+            # the library unrolls the row loop by 3 for widths divisible by 3 and not by 4
+            "kernel": f"spmv_kernel<double, {3 if q % 3 == 0 and q % 4 else 4}> (sliced-ELL SpMV, "
+                      "pressure-correction matrix)",
             "achieved": round(spmv_gbs, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
