@@ -11,6 +11,8 @@ Function-to-paper map (Shahane & Vanka, arXiv 2106.07616):
   weights            -> Sec. 2, Eqs. RBF_interp, RBF_constraint, RBF_interp_mat_vec,
                         RBF_interp_L ... RBF_interp_mat_vec_L_solve (centre row of B1)
   interp_weights     -> Eq. RBF_interp evaluated away from the nodes
+  cylinder_forces    -> Sec. 4, Eqs. cylinder forces, cylinder stress and cylinder
+                        lift drag (surface stresses, Simpson's rule, C_D and C_L)
   csr                -> Sec. 2 closing remark: B1 precomputed and stored
   poisson_values     -> Eq. pressure poisson with the Sec. 3.1 boundary conditions
   bicgstab           -> Sec. 3 "preconditioned BiCGSTAB" (right Jacobi)
@@ -23,6 +25,7 @@ Function-to-paper map (Shahane & Vanka, arXiv 2106.07616):
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 import threading
@@ -422,3 +425,56 @@ def run_transient(ops: Operators, u0, p0, bc_fn, rho, mu, dt, nsteps, tol_outer=
                                    p_bc=None if pbc_fn is None else pbc_fn(t_next))
         hist.append(st)
     return u, p, hist
+
+
+def cylinder_forces(ops: Operators, u, p, centre, diameter, mu, nsurf=360, rho=None, u_ref=None):
+    """Force per unit length on a circular cylinder in a 2D flow (Sec. 4, Eqs.
+    cylinder forces and cylinder stress), in the order the paper takes it:
+
+    1. strain rates at the nodes from the cloud's d/dx and d/dy operators;
+    2. pressure and strain rates interpolated (Eq. RBF_interp off the nodes,
+       with the operators' k, q and PHS power) to nsurf uniform points
+       x_j = centre + (D/2)(cos t_j, sin t_j), t_j = 2 pi j / nsurf;
+    3. sigma = -p I + mu (grad u + grad u^T) there, and the traction
+       sigma . (cos t, sin t), the normal pointing from the cylinder into the
+       fluid;
+    4. F = (D/2) * integral over t in [0, 2 pi] of the traction, by the
+       composite Simpson rule over the nsurf panels of the closed curve
+       (nsurf even).
+
+    With rho and u_ref, also C_D, C_L = F / (rho u_ref^2 D / 2) (Eq. cylinder
+    lift drag). Returns (F[2], traction[2, nsurf]) or (F, traction, C[2])."""
+    cloud = ops.cloud
+    if cloud.dim != 2:
+        raise ValueError("cylinder forces are defined for 2D clouds")
+    if nsurf < 4 or nsurf % 2:
+        raise ValueError("nsurf must be even and at least 4")
+    n = cloud.n
+    u = np.asarray(u, dtype=np.float64).reshape(2, n)
+    p = np.asarray(p, dtype=np.float64).reshape(n)
+    grads = [spmv(ops.col, ops.val[d], u[comp]) for comp in range(2) for d in range(2)]   # ux, uy, vx, vy
+    r = 0.5 * diameter
+    cs = [math.cos(2.0 * math.pi * j / nsurf) for j in range(nsurf)]
+    sn = [math.sin(2.0 * math.pi * j / nsurf) for j in range(nsurf)]
+    pts = np.array([[centre[0] + r * cs[j], centre[1] + r * sn[j]] for j in range(nsurf)])
+    vals, _, _ = interpolate(cloud.xyz, ops.k, pts, np.stack([p] + grads), q=ops.q, phs=ops.phs)
+    trac = np.zeros((2, nsurf))
+    for j in range(nsurf):
+        pj, ux, uy, vx, vy = vals[:, j]
+        sxx = -pj + 2.0 * mu * ux
+        syy = -pj + 2.0 * mu * vy
+        sxy = mu * (uy + vx)
+        trac[0, j] = sxx * cs[j] + sxy * sn[j]
+        trac[1, j] = sxy * cs[j] + syy * sn[j]
+    # the closed curve's end point repeats its start: even points weigh 2h/3,
+    # odd points 4h/3
+    h = 2.0 * math.pi / nsurf
+    force = np.zeros(2)
+    for d in range(2):
+        acc = 0.0
+        for j in range(nsurf):
+            acc += (4.0 if j % 2 else 2.0) * trac[d, j]
+        force[d] = r * (h / 3.0) * acc
+    if rho is None or u_ref is None:
+        return force, trac
+    return force, trac, force / (0.5 * rho * u_ref * u_ref * diameter)

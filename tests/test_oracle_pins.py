@@ -4,6 +4,7 @@ Each test checks the oracle against something other than itself: values printed
 in the paper, closed forms, exact polynomial reproduction, library routines on
 the same inputs, brute force, invariances and convergence orders.
 """
+import math
 import os
 
 import numpy as np
@@ -627,3 +628,118 @@ def test_forced_periodic_channel_is_a_fixed_point(orc, k):
     assert np.abs(p1 - p).max() <= 1e-10, np.abs(p1 - p).max()
     u0, _, _, _ = orc.simple_step(ops, vel, vel, p, vel, 1.0, c.meta["nu"], 0.05, alpha=orc.BDF2, **kw)
     assert np.abs(u0 - vel).max() > 1e-4
+
+
+# ---- drag and lift on a cylinder (Sec. 4, Eqs. cylinder forces, cylinder stress) ----
+_CUBIC = [(0, 0), (1, 0), (0, 1), (2, 0), (1, 1), (0, 2), (3, 0), (2, 1), (1, 2), (0, 3)]
+
+
+def _poly(coef, ex, X, Y, dx=0, dy=0):
+    """sum_c coef_c d^dx/dX d^dy/dY (X^i Y^j), differentiated term by term."""
+    t = 0.0
+    for cf, (i, j) in zip(coef, ex):
+        if i < dx or j < dy:
+            continue
+        f = (math.factorial(i) // math.factorial(i - dx)) * (math.factorial(j) // math.factorial(j - dy))
+        t = t + cf * f * X ** (i - dx) * Y ** (j - dy)
+    return t
+
+
+def _cubic_case(seed=5, n=3000):
+    c = W.holed_square(n, seed=seed, n_holes=1)
+    cx, cy, r = c.meta["holes"][0]
+    rng = np.random.default_rng(3)
+    a, b, g = rng.standard_normal(10), rng.standard_normal(10), rng.standard_normal(6)
+    X, Y = c.xyz[:, 0] - 0.5, c.xyz[:, 1] - 0.5
+    u = np.stack([_poly(a, _CUBIC, X, Y), _poly(b, _CUBIC, X, Y)])
+    p = _poly(g, _CUBIC[:6], X, Y)
+    return c, (cx, cy, r), (a, b, g), u, p
+
+
+def _exact_traction(coefs, centre, r, mu, th):
+    a, b, g = coefs
+    X, Y = centre[0] - 0.5 + r * np.cos(th), centre[1] - 0.5 + r * np.sin(th)
+    P = _poly(g, _CUBIC[:6], X, Y)
+    ux, uy = _poly(a, _CUBIC, X, Y, 1, 0), _poly(a, _CUBIC, X, Y, 0, 1)
+    vx, vy = _poly(b, _CUBIC, X, Y, 1, 0), _poly(b, _CUBIC, X, Y, 0, 1)
+    sxx, syy, sxy = -P + 2 * mu * ux, -P + 2 * mu * vy, mu * (uy + vx)
+    return np.stack([sxx * np.cos(th) + sxy * np.sin(th), sxy * np.cos(th) + syy * np.sin(th)])
+
+
+@pytest.mark.parametrize("k", [3, 4])
+def test_cylinder_force_divergence_theorem(orc, k):
+    """Cubic velocity, quadratic pressure: the derivative operators and the
+    interpolation reproduce them exactly (k >= 3), Simpson's rule integrates
+    the resulting trigonometric polynomial exactly, and by the divergence
+    theorem the force is pi R^2 (div sigma)(centre), div sigma being linear.
+    A pure pressure p = -G x gives (G pi R^2, 0). C_D, C_L scale F by
+    rho U^2 D / 2."""
+    c, (cx, cy, r), (a, b, g), u, p = _cubic_case()
+    ops = orc.build_operators(c, k)
+    mu = 0.7
+    F, trac, coef = orc.cylinder_forces(ops, u, p, (cx, cy), 2 * r, mu, 360, rho=1.3, u_ref=0.9)
+    X0, Y0 = cx - 0.5, cy - 0.5
+    div = np.array([
+        -_poly(g, _CUBIC[:6], X0, Y0, 1, 0) + 2 * mu * _poly(a, _CUBIC, X0, Y0, 2, 0)
+        + mu * (_poly(a, _CUBIC, X0, Y0, 0, 2) + _poly(b, _CUBIC, X0, Y0, 1, 1)),
+        -_poly(g, _CUBIC[:6], X0, Y0, 0, 1) + 2 * mu * _poly(b, _CUBIC, X0, Y0, 0, 2)
+        + mu * (_poly(a, _CUBIC, X0, Y0, 1, 1) + _poly(b, _CUBIC, X0, Y0, 2, 0))])
+    np.testing.assert_allclose(F, math.pi * r * r * div, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(coef, F / (0.5 * 1.3 * 0.9 ** 2 * 2 * r), rtol=1e-15)
+    th = 2 * np.pi * np.arange(360) / 360
+    np.testing.assert_allclose(trac, _exact_traction((a, b, g), (cx, cy), r, mu, th), rtol=0, atol=1e-10)
+    G = 1.7
+    Fp, _ = orc.cylinder_forces(ops, np.zeros_like(u), -G * c.xyz[:, 0], (cx, cy), 2 * r, mu, 360)
+    np.testing.assert_allclose(Fp, [G * math.pi * r * r, 0.0], rtol=0, atol=1e-12)
+
+
+def test_cylinder_force_simpson_rule(orc):
+    """The quadrature is the composite Simpson rule of the closed curve, not
+    the trapezoidal rule: with 6 panels its value is Richardson's
+    (4 T_6 - T_3) / 3 of the trapezoidal sums of the exact traction, which the
+    degree-3 content of the integrand sets apart from the exact integral."""
+    c, (cx, cy, r), coefs, u, p = _cubic_case()
+    ops = orc.build_operators(c, 3)
+    mu = 0.7
+
+    def trap(N):
+        th = 2 * np.pi * np.arange(N) / N
+        return r * (2 * np.pi / N) * _exact_traction(coefs, (cx, cy), r, mu, th).sum(axis=1)
+
+    F6, _ = orc.cylinder_forces(ops, u, p, (cx, cy), 2 * r, mu, 6)
+    np.testing.assert_allclose(F6, (4 * trap(6) - trap(3)) / 3, rtol=0, atol=1e-12)
+    assert np.abs(F6 - trap(360)).max() > 1e-3
+    with pytest.raises(ValueError):
+        orc.cylinder_forces(ops, u, p, (cx, cy), 2 * r, mu, 7)
+
+
+def test_cylinder_force_kovasznay_converges(orc):
+    """Kovasznay flow past a hole: the force approaches the exact surface
+    integral (exact fields, central-difference strain rates, 4096-point
+    trapezoidal rule) at the order of the operators."""
+    Re = 40.0
+    mu = 1.0 / Re
+
+    def fields(x, y):
+        return W.kovasznay(x, y, Re)
+
+    def exact(cx, cy, r, N=4096, e=1e-6):
+        th = 2 * np.pi * np.arange(N) / N
+        X, Y = cx + r * np.cos(th), cy + r * np.sin(th)
+        _, _, P = fields(X, Y)
+        d = [(np.array(fields(X + e, Y)[i]) - fields(X - e, Y)[i]) / (2 * e) for i in (0, 1)]
+        dy = [(np.array(fields(X, Y + e)[i]) - fields(X, Y - e)[i]) / (2 * e) for i in (0, 1)]
+        sxx, syy, sxy = -P + 2 * mu * d[0], -P + 2 * mu * dy[1], mu * (dy[0] + d[1])
+        return r * (2 * np.pi / N) * np.array([(sxx * np.cos(th) + sxy * np.sin(th)).sum(),
+                                               (sxy * np.cos(th) + syy * np.sin(th)).sum()])
+    errs = {}
+    for nt in (3000, 12000):
+        c = W.holed_square(nt, seed=5, n_holes=1)
+        cx, cy, r = c.meta["holes"][0]
+        Fe = exact(cx, cy, r)
+        u, v, p = fields(c.xyz[:, 0], c.xyz[:, 1])
+        for k in (3, 4):
+            F, _ = orc.cylinder_forces(orc.build_operators(c, k), np.stack([u, v]), p, (cx, cy), 2 * r, mu)
+            errs[nt, k] = np.abs(F - Fe).max() / np.abs(Fe).max()
+    assert errs[3000, 3] < 3e-4 and errs[3000, 4] < 3e-6, errs
+    assert errs[12000, 3] < errs[3000, 3] / 4, errs
