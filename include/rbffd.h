@@ -201,6 +201,41 @@ int rbffd_interpolate(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_sten
                       const double *qxyz, int nfield, const double *fields, double *out, int32_t *nbr_out,
                       double *w_out, int64_t *bad_query, void *hip_stream);
 
+/* (Sec. 4, Eqs. cylinder forces, cylinder stress and cylinder lift drag) Force
+ * per unit length on a circular cylinder in a 2D flow, from its surface
+ * stresses:
+ *   1. the strain rates du/dx, du/dy, dv/dx, dv/dy at the nodes, by the
+ *      operators' d/dx and d/dy;
+ *   2. the pressure and the strain rates interpolated, as rbffd_interpolate
+ *      does with the operators' degree, cloud size and PHS power, to nsurf
+ *      uniform points x_j = centre + (D/2)(cos t_j, sin t_j),
+ *      t_j = 2 pi j / nsurf (cos and sin of the host C library);
+ *   3. sigma = -p I + mu (grad u + grad u^T) there, and the traction
+ *      sigma . (cos t_j, sin t_j), the normal pointing from the cylinder into
+ *      the fluid;
+ *   4. F = (D/2) * integral over t in [0, 2 pi] of the traction, by the
+ *      composite Simpson rule over the nsurf panels of the closed curve.
+ *   cloud, ops:   a 2D, non-periodic cloud and its operators (same n)
+ *   u:            device [2][n] velocity; p: device [n] pressure
+ *   centre:       host [2]; diameter D > 0; mu the dynamic viscosity
+ *   nsurf:        even, 4 .. 1048576 (the paper uses 360)
+ *   force:        host [2] out: F_x, F_y
+ *   coef:         optional host [2] out: C_D, C_L = F / (rho u_ref^2 D / 2),
+ *                 with rho > 0 and u_ref != 0; NULL to skip
+ *   traction:     optional device [2][nsurf] out: the traction at each point
+ *   bad_query:    optional host out: the surface point whose interpolation
+ *                 system was singular, else -1
+ * The surface may cross the cloud anywhere: its points take the q nearest
+ * cloud points wherever they lie. Allocates device scratch for the five
+ * fields at the nodes, synchronises the stream. RBFFD_E_ARG for 3D or
+ * periodic clouds, mismatched sizes, odd or out-of-range nsurf, a
+ * non-positive or non-finite diameter; RBFFD_E_SINGULAR for a singular
+ * interpolation system. */
+int rbffd_cylinder_forces(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_ops *ops, const double *u,
+                          const double *p, const double *centre, double diameter, double mu, int nsurf, double rho,
+                          double u_ref, double *force, double *coef, double *traction, int64_t *bad_query,
+                          void *hip_stream);
+
 /* ---- Krylov solve ------------------------------------------------------- */
 typedef struct {
     double tol;             /* stop when ||b - A x||_2 <= tol ||b||_2 (recursive residual) */

@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_OOM", -3: "E_SINGULAR", -4: "E_NOCO
 
 EXPORTED = ["rbffd_last_error", "rbffd_ctx_create", "rbffd_ctx_destroy", "rbffd_ctx_bytes_in_use",
             "rbffd_stencil_sizes", "rbffd_build_stencils", "rbffd_assemble", "rbffd_ops_free",
-            "rbffd_ops_info", "rbffd_ops_export_csr", "rbffd_ops_export_block_inverse", "rbffd_apply", "rbffd_interpolate", "poisson_solve",
+            "rbffd_ops_info", "rbffd_ops_export_csr", "rbffd_ops_export_block_inverse", "rbffd_apply", "rbffd_interpolate", "rbffd_cylinder_forces", "poisson_solve",
             "poisson_solve_batched",
             "rbffd_server_create", "rbffd_server_destroy", "rbffd_server_submit", "rbffd_server_run",
             "rbffd_server_poll", "simple_step", "rbffd_convdiff_lambda"]
@@ -88,6 +88,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.rbffd_apply.argtypes = [P, P, I, P, P, P]
     L.rbffd_interpolate.argtypes = [P, C.POINTER(CloudT), C.POINTER(StencilOptsT), I64, P, I, P, P, P, P,
                                     C.POINTER(I64), P]
+    L.rbffd_cylinder_forces.argtypes = [P, C.POINTER(CloudT), P, P, P, C.POINTER(D), D, D, I, D, D, C.POINTER(D),
+                                        C.POINTER(D), P, C.POINTER(I64), P]
     L.poisson_solve.argtypes = [P, P, P, P, C.POINTER(KrylovOptsT), C.POINTER(KrylovStatsT), P]
     L.poisson_solve_batched.argtypes = [P, I, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(KrylovOptsT),
                                         C.POINTER(KrylovStatsT), P]
@@ -241,6 +243,31 @@ def rbffd_interpolate(ctx: Context, cloud: DeviceCloud, poly_degree: int, qxyz: 
     if return_stencils:
         return out, nbr, w
     return out
+
+
+def rbffd_cylinder_forces(ctx: Context, cloud: DeviceCloud, ops: "Operators", u: torch.Tensor, p: torch.Tensor,
+                          centre, diameter: float, mu: float, nsurf: int = 360, rho: float | None = None,
+                          u_ref: float | None = None, return_traction: bool = False):
+    """Force per unit length (F_x, F_y) on a circular cylinder of a 2D flow
+    from its surface stresses; with rho and u_ref also (C_D, C_L); with
+    return_traction also the traction [2, nsurf] at the surface points.
+    u: [2, n] velocity, p: [n] pressure on the cloud."""
+    n = cloud.n
+    f = (C.c_double * 2)()
+    cf = (C.c_double * 2)() if (rho is not None and u_ref is not None) else None
+    tr = torch.empty((2, nsurf), dtype=torch.float64, device=cloud.xyz.device) if return_traction else None
+    cen = (C.c_double * 2)(float(centre[0]), float(centre[1]))
+    cs = cloud.struct()
+    bad = C.c_int64(-1)
+    _check(lib().rbffd_cylinder_forces(ctx.handle, C.byref(cs), ops.handle, _f64(u, 2 * n, "u"), _f64(p, n, "p"), cen,
+                                       float(diameter), float(mu), int(nsurf), float(rho or 0.0), float(u_ref or 0.0),
+                                       f, cf, _ptr(tr), C.byref(bad), _stream()))
+    out = [[f[0], f[1]]]
+    if cf is not None:
+        out.append([cf[0], cf[1]])
+    if return_traction:
+        out.append(tr)
+    return out[0] if len(out) == 1 else tuple(out)
 
 
 class Operators:

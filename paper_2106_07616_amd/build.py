@@ -9,7 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librbffd.so")
-SOURCES = ["api.hip", "knn.hip", "weights.hip", "assemble.hip", "krylov.hip", "step.hip"]
+SOURCES = ["api.hip", "knn.hip", "weights.hip", "assemble.hip", "krylov.hip", "step.hip", "forces.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          # no packed FP32 instructions (see the design notes)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

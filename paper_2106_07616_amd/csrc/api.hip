@@ -511,6 +511,105 @@ int rbffd_interpolate(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_sten
     return RBFFD_OK;
 }
 
+// most surface points of one force evaluation
+static constexpr int kMaxSurface = 1 << 20;
+
+int rbffd_cylinder_forces(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_ops *ops, const double *u,
+                          const double *p, const double *centre, double diameter, double mu, int nsurf, double rho,
+                          double u_ref, double *force, double *coef, double *traction, int64_t *bad_query,
+                          void *hip_stream)
+{
+    if (bad_query) *bad_query = -1;
+    if (!ctx || !ops || !u || !p || !centre || !force) return fail(RBFFD_E_ARG, "NULL argument");
+    if (!ops->ctx) return fail(RBFFD_E_ARG, "the operators' context was destroyed");
+    RB_CHECK(check_cloud(cloud));
+    if (cloud->dim != 2 || ops->dim != 2) return fail(RBFFD_E_ARG, "cylinder forces are defined for 2D clouds");
+    if (cloud->n != ops->n) return fail(RBFFD_E_ARG, "the cloud and the operators differ in size");
+    if (is_periodic(cloud)) return fail(RBFFD_E_ARG, "interpolation on periodic clouds is not supported");
+    if (nsurf < 4 || (nsurf & 1) || nsurf > kMaxSurface)
+        return fail(RBFFD_E_ARG, "nsurf must be even, at least 4 and at most " + std::to_string(kMaxSurface));
+    if (!(diameter > 0.0) || !std::isfinite(diameter) || !std::isfinite(centre[0]) || !std::isfinite(centre[1]) ||
+        !std::isfinite(mu))
+        return fail(RBFFD_E_ARG, "the centre, diameter and viscosity must be finite, the diameter positive");
+    if (coef && !(rho > 0.0 && std::isfinite(rho) && u_ref != 0.0 && std::isfinite(u_ref)))
+        return fail(RBFFD_E_ARG, "coefficients need a positive density and a nonzero reference speed");
+    const int q = ops->q, k = ops->k, phs = ops->phs;
+    const int m = (k + 1) * (k + 2) / 2;
+    if (q + m > 128) return fail(RBFFD_E_ARG, "collocation systems larger than 128 (q + m) are not supported");
+    RB_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t n = ops->n, ns = nsurf;
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t b_fld = up(sizeof(double) * 5 * n), b_q = up(sizeof(double) * 2 * ns),
+                 b_cs = up(sizeof(double) * 2 * ns), b_fs = up(sizeof(double) * 5 * ns),
+                 b_nbr = up(sizeof(int32_t) * ns * q), b_w = up(sizeof(double) * ns * q),
+                 b_res = up(sizeof(double) * 2 + sizeof(int64_t));
+    const size_t total = b_fld + b_q + b_cs + b_fs + b_nbr + b_w + b_res;
+    char *base = nullptr;
+    RB_CHECK(dev_alloc(ctx, (void **)&base, total));
+    double *fld = (double *)base;
+    double *qxyz = (double *)(base + b_fld);
+    double *cs = (double *)(base + b_fld + b_q);
+    double *fs = (double *)(base + b_fld + b_q + b_cs);
+    int32_t *nbr = (int32_t *)(base + b_fld + b_q + b_cs + b_fs);
+    double *w = (double *)(base + b_fld + b_q + b_cs + b_fs + b_nbr);
+    double *res = (double *)(base + b_fld + b_q + b_cs + b_fs + b_nbr + b_w);
+    int64_t *bad_dev = (int64_t *)(res + 2);
+    // uniform surface points t_j = 2 pi j / nsurf (host cos and sin)
+    const double r = 0.5 * diameter;
+    std::vector<double> hq(2 * ns), hcs(2 * ns);
+    for (int64_t j = 0; j < ns; ++j) {
+        const double t = 2.0 * M_PI * (double)j / (double)nsurf;
+        const double c = std::cos(t), sn = std::sin(t);
+        const double dx = r * c, dy = r * sn;
+        hq[2 * j] = centre[0] + dx;
+        hq[2 * j + 1] = centre[1] + dy;
+        hcs[j] = c;
+        hcs[ns + j] = sn;
+    }
+    const double h = 2.0 * M_PI / (double)nsurf;
+    double *hres = nullptr;
+    int st = host_scratch(ctx, kHostMisc, sizeof(double) * 3, (void **)&hres);
+    hipError_t e = hipSuccess;
+    if (st == RBFFD_OK) e = hipMemcpyAsync(qxyz, hq.data(), sizeof(double) * 2 * ns, hipMemcpyHostToDevice, s);
+    if (st == RBFFD_OK && e == hipSuccess)
+        e = hipMemcpyAsync(cs, hcs.data(), sizeof(double) * 2 * ns, hipMemcpyHostToDevice, s);
+    if (st == RBFFD_OK && e == hipSuccess) e = hipMemcpyAsync(fld, p, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) st = hip_fail(e, "cylinder forces");
+    // strain rates at the nodes: du/dx, du/dy, dv/dx, dv/dy
+    if (st == RBFFD_OK) st = apply_op(ctx, ops, 0, u, fld + n, s);
+    if (st == RBFFD_OK) st = apply_op(ctx, ops, 1, u, fld + 2 * n, s);
+    if (st == RBFFD_OK) st = apply_op(ctx, ops, 0, u + n, fld + 3 * n, s);
+    if (st == RBFFD_OK) st = apply_op(ctx, ops, 1, u + n, fld + 4 * n, s);
+    // pressure and strain rates at the surface points
+    if (st == RBFFD_OK) st = launch_knn_points(ctx, 2, n, cloud->xyz, ns, qxyz, q, nbr, s);
+    if (st == RBFFD_OK) st = launch_interp(ctx, 2, n, cloud->xyz, ns, qxyz, q, nbr, k, phs, w, bad_dev, 5, fld, fs, s);
+    if (st == RBFFD_OK) st = launch_surface_traction(nsurf, fs, cs, mu, r * (h / 3.0), traction, res, s);
+    if (st == RBFFD_OK) {
+        e = hipMemcpyAsync(hres, res, sizeof(double) * 2 + sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    } else {
+        (void)hipStreamSynchronize(s);
+    }
+    dev_free(ctx, base, total);
+    if (st != RBFFD_OK) return st;
+    if (e != hipSuccess) return hip_fail(e, "cylinder forces");
+    int64_t bad = 0;
+    std::memcpy(&bad, hres + 2, sizeof(bad));
+    if (bad != INT64_MAX) {
+        if (bad_query) *bad_query = bad;
+        return fail(RBFFD_E_SINGULAR, "singular interpolation system at surface point " + std::to_string(bad));
+    }
+    force[0] = hres[0];
+    force[1] = hres[1];
+    if (coef) {
+        const double den = 0.5 * rho * u_ref * u_ref * diameter;
+        coef[0] = force[0] / den;
+        coef[1] = force[1] / den;
+    }
+    return RBFFD_OK;
+}
+
 int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, double *x,
                   const rbffd_krylov_opts *opts, rbffd_krylov_stats *stats, void *hip_stream)
 {

@@ -38,6 +38,14 @@ class Solver:
     def dim(self) -> int:
         return self.dcloud.dim
 
+    def cylinder_forces(self, u: torch.Tensor, p: torch.Tensor, centre, diameter: float, mu: float,
+                        nsurf: int = 360, rho: float | None = None, u_ref: float | None = None,
+                        return_traction: bool = False):
+        """Force (and with rho, u_ref the drag and lift coefficients) on a
+        circular cylinder of this 2D cloud; see B.rbffd_cylinder_forces."""
+        return B.rbffd_cylinder_forces(self.ctx, self.dcloud, self.ops, u.contiguous(), p.contiguous(), centre, diameter,
+                                       mu, nsurf, rho, u_ref, return_traction)
+
     def dt_from_courant(self, u0: torch.Tensor, co: float, rho: float, mu: float, iters: int = 200) -> float:
         lam = B.rbffd_convdiff_lambda(self.ctx, self.ops, u0.contiguous(), rho, mu, iters)
         return 2.0 * co / lam
