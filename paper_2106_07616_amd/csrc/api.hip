@@ -7,6 +7,7 @@
 
 #include <vector>
 
+#include "forces.h"
 #include "internal.h"
 
 namespace rbffd {

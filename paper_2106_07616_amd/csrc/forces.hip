@@ -10,7 +10,7 @@
 //
 // The work is a few hundred points: one block of kBlock threads, with a
 // fixed-order block sum so that the result is the same run to run.
-#include "internal.h"
+#include "forces.h"
 
 namespace rbffd {
 

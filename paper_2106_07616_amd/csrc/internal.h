@@ -238,11 +238,6 @@ int launch_knn_points(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int
 int launch_interp(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int64_t nq, const double *qxyz, int q,
                   const int32_t *nbr, int k, int phs, double *w, int64_t *bad_dev, int nfield, const double *fields,
                   double *out, hipStream_t s);
-// Traction sigma . n at ns surface points from fld [5][ns] (p, du/dx, du/dy,
-// dv/dx, dv/dy) and cs [2][ns] (cos t, sin t); force [2] = scale times the
-// Simpson sum of the traction (weights 2, 4, 2, 4, ...); trac [2][ns] optional.
-int launch_surface_traction(int ns, const double *fld, const double *cs, double mu, double scale, double *trac,
-                            double *force, hipStream_t s);
 int assemble_ops(rbffd_ctx *ctx, const rbffd_cloud *cloud, int q, int k, int phs,
                  const int32_t *nbr, const double *w, int precision, rbffd_ops *ops, hipStream_t s);
 int export_csr(const rbffd_ops *ops, int32_t *col, double *val, hipStream_t s);
