@@ -147,6 +147,75 @@ def cpu_baseline(args):
                       f"iterations, {pi} point-iters in {t:.2f} s"}
 
 
+FP64_PEAK_TFLOPS = 78.6
+
+
+def post_bench(args):
+    """Post-processing on a 252k-point square with one circular hole, k = 4
+    (q = 30): rbffd_interpolate of u, v, p at 1M scattered points, and
+    rbffd_cylinder_forces at 360 surface points (Sec. 4)."""
+    import torch
+
+    import paper_2106_07616_amd as R
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    R.lib()
+    k, nq, reps = 4, 1_000_000, 5
+    cloud = W.holed_square(250_000, seed=5, n_holes=1)
+    cx, cy, rad = cloud.meta["holes"][0]
+    ctx = R.Context(0)
+    solver = R.Solver(ctx, cloud, k)
+    q, m, _ = R.rbffd_stencil_sizes(2, k)
+    u, v, p = W.kovasznay(cloud.xyz[:, 0], cloud.xyz[:, 1], cloud.meta["Re"])
+    vel = torch.tensor(np.stack([u, v]), device="cuda")
+    pt = torch.tensor(p, device="cuda")
+    fields = torch.tensor(np.stack([u, v, p]), device="cuda")
+    # query points in the fluid: a point deep inside the hole would see only
+    # the hole's circle, on which the degree-k polynomials are not unisolvent
+    cand = np.random.default_rng(6).uniform(0.0, 1.0, size=(2 * nq, 2))
+    cand = cand[np.hypot(cand[:, 0] - cx, cand[:, 1] - cy) > rad]
+    qx = torch.tensor(cand[:nq], device="cuda")
+    log(f"[post] cloud n={cloud.n} q={q} m={m}; {nq} query points")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            t.append(time.perf_counter() - t0)
+        return float(np.median(t))
+
+    t_int = timed(lambda: R.rbffd_interpolate(ctx, solver.dcloud, k, qx, fields))
+    mu = 1.0 / cloud.meta["Re"]
+    t_f = timed(lambda: solver.cylinder_forces(vel, pt, (cx, cy), 2 * rad, mu, 360, rho=1.0, u_ref=1.0))
+    F, cf = solver.cylinder_forces(vel, pt, (cx, cy), 2 * rad, mu, 360, rho=1.0, u_ref=1.0)
+    ns = q + m
+    flops = 2.0 / 3.0 * ns ** 3 + 2.0 * ns * ns   # LU of the saddle system + one solve, per query
+    tflops = nq * flops / t_int / 1e12
+    log(f"[post] interpolate: {t_int * 1e3:.1f} ms for {nq} points; forces: {t_f * 1e3:.2f} ms, F={F} C={cf}")
+    print(json.dumps({
+        "metric": "interpolated query points/s (3 fields) and cylinder force evaluations/s",
+        "value": round(nq / t_int, 1), "unit": "query points/s", "n_gpus": 1, "steps": reps, "warmup": 1,
+        "ms_per_step": round(t_int * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"unit square with one circular hole (centre ({cx:.4f}, {cy:.4f}), radius {rad:.4f}), "
+                               f"{cloud.n} points, PHS r^3 + degree-{k} polynomials, q={q}; Kovasznay fields; "
+                               f"{nq} uniform random query points in the fluid; forces on the hole at 360 surface points",
+                   "n_points": cloud.n, "q": q, "poly_degree": k},
+        "cylinder_forces": {"ms_per_eval": round(t_f * 1e3, 3), "evals_per_s": round(1.0 / t_f, 1), "nsurf": 360,
+                            "force": F, "coef": cf},
+        "roofline": {"bound": "alu", "kernel": "whole rbffd_interpolate call (kNN + weights + sampling)",
+                     "achieved": round(tflops, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tflops / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                     "flops_per_query": flops},
+    }))
+    ctx.close()
+
+
 def batch_bench(args):
     """The batched configuration: independent holed-square clouds (0-4 holes,
     prescribed pressure on the outer edges and the holes) with sizes
@@ -458,7 +527,7 @@ def main():
                     help="also run the step with both mixed-precision modes and with the block-Jacobi "
                          "pressure preconditioner, and report per-field differences")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch", "serve"], default="taylor_green")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch", "serve", "post"], default="taylor_green")
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--serve-warmup", type=int, default=20)
     ap.add_argument("--serve-chunk", type=int, default=16)
@@ -477,6 +546,9 @@ def main():
         return
     if args.workload == "serve":
         serve_bench(args)
+        return
+    if args.workload == "post":
+        post_bench(args)
         return
 
     import torch

@@ -93,12 +93,15 @@ __device__ inline void monomial_exponents(int alpha, int *ex)
     }
 }
 
-template <int NSP, int DIM>
-__global__ __launch_bounds__(64) void weights_kernel(const double *__restrict__ xyz, const int32_t *__restrict__ nbr,
-                                                     int64_t n, int q, int m, int phs, double *__restrict__ w,
-                                                     int64_t *__restrict__ bad)
+// With INTERP set, the kernel gives interpolation weights at off-node points
+// instead, as the LDS kernel below does in that mode: centre ctr[i], scale the
+// distance to the farthest cloud point, one right-hand side, unscaled weights.
+template <int NSP, int DIM, bool INTERP>
+__global__ __launch_bounds__(64) void weights_kernel(const double *__restrict__ xyz, const double *__restrict__ ctr,
+                                                     const int32_t *__restrict__ nbr, int64_t n, int q, int m, int phs,
+                                                     double *__restrict__ w, int64_t *__restrict__ bad)
 {
-    constexpr int R = DIM + 1;
+    constexpr int R = INTERP ? 1 : DIM + 1;
     constexpr int NC = NSP + R;
     __shared__ double xs[kMaxQ * DIM];
     __shared__ int exs[64 * 3];
@@ -109,7 +112,7 @@ __global__ __launch_bounds__(64) void weights_kernel(const double *__restrict__ 
 
     // centre and scale: s = distance to the q-th neighbour
     double c[3] = {0, 0, 0};
-    for (int d = 0; d < DIM; ++d) c[d] = xyz[i * DIM + d];
+    for (int d = 0; d < DIM; ++d) c[d] = ctr[i * DIM + d];
     const int64_t jl = nbr[i * q + q - 1];
     const double s = sqrt(sqdist_exact<DIM>(c, xyz + jl * DIM));
     for (int a = lane; a < q; a += 64) {
@@ -156,20 +159,30 @@ __global__ __launch_bounds__(64) void weights_kernel(const double *__restrict__ 
         double rhs[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) rhs[r] = 0.0;
-        if (lane < q) {
+        if constexpr (INTERP) {
+            // phi(|x_lane - x*|) and the monomials at the centre x*
+            if (lane < q) {
+                double rr = 0.0;
+                for (int d = 0; d < DIM; ++d) rr = rr + mine[d] * mine[d];
+                const double r = sqrt(rr);
+                rhs[0] = (phs == 3) ? r * r * r : r * r * r * r * r;
+            } else if (lane < ns) {
+                rhs[0] = (myex[0] + myex[1] + myex[2] == 0) ? 1.0 : 0.0;
+            }
+        } else if (lane < q) {
             double rr = 0.0;
             for (int d = 0; d < DIM; ++d) rr = rr + mine[d] * mine[d];
             const double r = sqrt(rr);
             const double rp2 = (phs == 3) ? r : r * r * r;
 #pragma unroll
             for (int d = 0; d < DIM; ++d) rhs[d] = -(double)phs * rp2 * mine[d];
-            rhs[DIM] = (double)(phs * (phs + DIM - 2)) * rp2;
+            rhs[R - 1] = (double)(phs * (phs + DIM - 2)) * rp2;
         } else if (lane < ns) {
             const int tot = myex[0] + myex[1] + myex[2];
 #pragma unroll
             for (int d = 0; d < DIM; ++d) {
                 if (tot == 1 && myex[d] == 1) rhs[d] = 1.0;
-                if (tot == 2 && myex[d] == 2) rhs[DIM] = 2.0;
+                if (tot == 2 && myex[d] == 2) rhs[R - 1] = 2.0;
             }
         }
 #pragma unroll
@@ -232,8 +245,8 @@ __global__ __launch_bounds__(64) void weights_kernel(const double *__restrict__ 
     if (lane < q) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const double sc = (r < DIM) ? s : s * s;
-            w[(int64_t)r * n * q + i * q + lane] = xout[r] / sc;
+            const double sc = INTERP ? 1.0 : ((r < DIM) ? s : s * s);
+            w[(int64_t)r * n * q + i * q + lane] = INTERP ? xout[r] : xout[r] / sc;
         }
     }
     if (singular && lane == 0) atomicMin((unsigned long long *)bad, (unsigned long long)i);
@@ -469,9 +482,11 @@ int launch_weights(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q,
 #define RB_WEIGHTS(NSP_)                                                                                  \
     if (ns <= NSP_) {                                                                                     \
         if (dim == 2)                                                                                     \
-            hipLaunchKernelGGL((weights_kernel<NSP_, 2>), grid, block, 0, s, xyz, nbr, n, q, m, phs, w, bad_dev); \
+            hipLaunchKernelGGL((weights_kernel<NSP_, 2, false>), grid, block, 0, s, xyz, xyz, nbr, n, q, m, phs, w,   \
+                               bad_dev);                                                                  \
         else                                                                                              \
-            hipLaunchKernelGGL((weights_kernel<NSP_, 3>), grid, block, 0, s, xyz, nbr, n, q, m, phs, w, bad_dev); \
+            hipLaunchKernelGGL((weights_kernel<NSP_, 3, false>), grid, block, 0, s, xyz, xyz, nbr, n, q, m, phs, w,   \
+                               bad_dev);                                                                  \
         RB_HIP(hipGetLastError());                                                                        \
         return RBFFD_OK;                                                                                  \
     }
@@ -528,23 +543,48 @@ int launch_interp(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int64_t
     const long long init = LLONG_MAX;
     RB_HIP(hipMemcpyAsync(bad_dev, &init, sizeof(init), hipMemcpyHostToDevice, s));
     if (nq == 0) return RBFFD_OK;
-    const size_t lds = sizeof(double) * (size_t)(ns + 1) * 128;
-    int dev = 0, lim = 0;
-    RB_HIP(hipGetDevice(&dev));
-    RB_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const size_t fixed = sizeof(double) * (kMaxQ * 3 + 4 + 2 * kRowThreads) + sizeof(int) * (128 * 3 + 4 + 128);
-    if (lds + fixed > (size_t)lim) return fail(RBFFD_E_ARG, "interpolation system does not fit the device's LDS");
-    const dim3 grid((unsigned)nq), block(128 * kRowThreads);
-    if (dim == 2) {
-        RB_HIP(hipFuncSetAttribute((const void *)weights_kernel_lds<2, true>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL((weights_kernel_lds<2, true>), grid, block, lds, s, xyz, qxyz, nbr, nq, q, m, phs, w,
-                           bad_dev);
-    } else {
-        RB_HIP(hipFuncSetAttribute((const void *)weights_kernel_lds<3, true>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL((weights_kernel_lds<3, true>), grid, block, lds, s, xyz, qxyz, nbr, nq, q, m, phs, w,
-                           bad_dev);
+    // up to 64 unknowns: one wavefront per query point, the row in registers
+    bool launched = false;
+    const dim3 grid1((unsigned)nq), block1(64);
+#define RB_INTERP(NSP_)                                                                                   \
+    if (!launched && ns <= NSP_) {                                                                        \
+        if (dim == 2)                                                                                     \
+            hipLaunchKernelGGL((weights_kernel<NSP_, 2, true>), grid1, block1, 0, s, xyz, qxyz, nbr, nq, q, m, phs, \
+                               w, bad_dev);                                                               \
+        else                                                                                              \
+            hipLaunchKernelGGL((weights_kernel<NSP_, 3, true>), grid1, block1, 0, s, xyz, qxyz, nbr, nq, q, m, phs, \
+                               w, bad_dev);                                                               \
+        launched = true;                                                                                  \
+    }
+    RB_INTERP(16)
+    RB_INTERP(24)
+    RB_INTERP(32)
+    RB_INTERP(40)
+    RB_INTERP(48)
+    RB_INTERP(56)
+    RB_INTERP(64)
+#undef RB_INTERP
+    if (!launched) {
+        // 65-128 unknowns: one workgroup per query point, the matrix in LDS
+        const size_t lds = sizeof(double) * (size_t)(ns + 1) * 128;
+        int dev = 0, lim = 0;
+        RB_HIP(hipGetDevice(&dev));
+        RB_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        const size_t fixed =
+            sizeof(double) * (kMaxQ * 3 + 4 + 2 * kRowThreads) + sizeof(int) * (128 * 3 + 4 + 128);
+        if (lds + fixed > (size_t)lim) return fail(RBFFD_E_ARG, "interpolation system does not fit the device's LDS");
+        const dim3 grid((unsigned)nq), block(128 * kRowThreads);
+        if (dim == 2) {
+            RB_HIP(hipFuncSetAttribute((const void *)weights_kernel_lds<2, true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL((weights_kernel_lds<2, true>), grid, block, lds, s, xyz, qxyz, nbr, nq, q, m, phs, w,
+                               bad_dev);
+        } else {
+            RB_HIP(hipFuncSetAttribute((const void *)weights_kernel_lds<3, true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL((weights_kernel_lds<3, true>), grid, block, lds, s, xyz, qxyz, nbr, nq, q, m, phs, w,
+                               bad_dev);
+        }
     }
     RB_HIP(hipGetLastError());
     if (nfield > 0) {
