@@ -70,7 +70,7 @@ def lib():
             L.orc_csr.argtypes = [i64, C.c_int, P, C.c_int, P, P, P]
             L.orc_spmv.argtypes = [i64, C.c_int, P, P, P, P]
             L.orc_spmv.restype = None
-            L.orc_poisson_values.argtypes = [C.c_int, i64, C.c_int, P, P, i64, P, P, P]
+            L.orc_poisson_values.argtypes = [C.c_int, i64, C.c_int, P, P, i64, P, P, P, P]
             L.orc_bicgstab.argtypes = [i64, C.c_int, P, P, P, P, C.c_double, C.c_int, P, P]
             L.orc_simple_step.argtypes = [P, P, P, P, P, P, P]
             L.orc_convdiff_lambda.argtypes = [C.c_int, i64, C.c_int, P, P, P, P, C.c_double, C.c_double, C.c_int]
@@ -223,16 +223,20 @@ def apply_ops(col, val, x):
     return np.stack([spmv(col, val[r], x) for r in range(val.shape[0])])
 
 
-def poisson_values(cloud, col, val):
+def poisson_values(cloud, col, val, rows=None):
     """Pressure-correction matrix: Laplacian rows inside, N . grad rows on
-    velocity-Dirichlet boundary points, identity at the pinned point."""
+    velocity-Dirichlet boundary points, identity at the pinned point and at
+    prescribed-pressure points. With rows (the global indices of the given
+    rows), cloud.kind and cloud.normal hold just those rows and cloud.pin
+    stays a global index."""
     col = _c(col, np.int32)
     val = _c(val, np.float64)
     n, q = col.shape
     kind = _c(cloud.kind, np.uint8)
     nrm = _c(cloud.normal, np.float64)
+    ri = None if rows is None else _c(rows, np.int64)
     pv = np.zeros((n, q))
-    lib().orc_poisson_values(cloud.dim, n, q, _p(kind), _p(nrm), int(cloud.pin), _p(col), _p(val), _p(pv))
+    lib().orc_poisson_values(cloud.dim, n, q, _p(kind), _p(nrm), int(cloud.pin), _p(col), _p(val), _p(ri), _p(pv))
     return pv
 
 

@@ -557,16 +557,18 @@ int orc_bicgstab(int64_t n, int q, const int32_t *col, const double *val, const 
  * at the pinned interior point (pin >= 0), which removes the constant null
  * space when every boundary is of kind 1. Same sparsity as the operators. */
 int orc_poisson_values(int dim, int64_t n, int q, const uint8_t *kind, const double *normal,
-                       int64_t pin, const int32_t *col, const double *val, double *pval)
+                       int64_t pin, const int32_t *col, const double *val, const int64_t *rows, double *pval)
 {
     const int64_t nnz = n * q;
     for (int64_t i = 0; i < n; ++i) {
+        /* the point row i stands for: itself, or rows[i] for a subset of rows */
+        const int64_t g = rows ? rows[i] : i;
         for (int a = 0; a < q; ++a) {
             int64_t e = i * q + a;
             double v;
-            if (i == pin || kind[i] == 2 || kind[i] == 3) {
+            if (g == pin || kind[i] == 2 || kind[i] == 3) {
                 /* pinned point, or prescribed-pressure boundary: p' = 0 */
-                v = (col[e] == i) ? 1.0 : 0.0;
+                v = (col[e] == g) ? 1.0 : 0.0;
             } else if (kind[i] == 0) {
                 v = val[(int64_t)dim * nnz + e];
             } else {

@@ -1,0 +1,137 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py times:
+the 250,120-point Taylor-Green disk (k = 4) and the 1.06M-point Beltrami cube
+(k = 3). The oracle recomputes sampled rows one by one: interior rows, boundary
+rows, the first rows and the ragged last slice. Clouds are compared bit for
+bit, and weights, operator rows and SpMV outputs to 1e-10. Properties that hold
+at any size check the rest: the Krylov residual on the oracle's own rows, and
+an exact quadratic flow as a fixed point of one time step."""
+import types
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import bench  # noqa: E402
+import paper_2106_07616_amd as R  # noqa: E402
+
+WORKLOADS = ["taylor_green", "beltrami"]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = R.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module", params=WORKLOADS)
+def full(request, ctx, orc):
+    name = request.param
+    k = bench.WORKLOADS[name]["k"]
+    c = bench.WORKLOADS[name]["make"](W)
+    print(f"[full] {name}: n={c.n} k={k}", flush=True)
+    s = R.Solver(ctx, c, k)
+    q = s.q
+    rng = np.random.default_rng(11)
+    inner = np.flatnonzero(c.kind == W.INTERIOR)
+    bnd = np.flatnonzero(c.kind != W.INTERIOR)
+    samples = np.unique(np.concatenate([rng.choice(inner, 160, replace=False), rng.choice(bnd, 64, replace=False),
+                                        np.arange(8), np.arange(c.n - 70, c.n)]))
+    nbr_o = orc.knn(c.xyz, q, queries=samples)
+    full_nbr = np.zeros((c.n, q), np.int32)
+    full_nbr[samples] = nbr_o
+    w_o = orc.weights(c.xyz, full_nbr, k, queries=samples)
+    del full_nbr
+    col_o, val_o = orc.csr(nbr_o, w_o)
+    sub = types.SimpleNamespace(dim=c.dim, kind=c.kind[samples], normal=c.normal[samples], pin=c.pin)
+    pv_o = orc.poisson_values(sub, col_o, val_o, rows=samples)
+    torch.cuda.synchronize()
+    return name, c, k, s, samples, nbr_o, w_o, col_o, val_o, pv_o
+
+
+def _rowrel(a, b):
+    return float((np.abs(a - b).max(axis=-1) / np.maximum(np.abs(b).max(axis=-1), 1e-300)).max())
+
+
+def test_fullsize_stencils_and_rows(full):
+    """Sampled clouds bit-exact; weights and every operator row (d/dx, d/dy,
+    (d/dz), Laplacian, pressure correction) within 1e-10 row-relative."""
+    name, c, k, s, samples, nbr_o, w_o, col_o, val_o, pv_o = full
+    idx = torch.tensor(samples, device="cuda")
+    np.testing.assert_array_equal(s.nbr[idx].cpu().numpy(), nbr_o)
+    w_g = s.w[:, idx].cpu().numpy()
+    ew = _rowrel(w_g, w_o)
+    col, val = s.ops.export_csr()
+    col_g, val_g = col[idx].cpu().numpy(), val[:, idx].cpu().numpy()
+    del col, val
+    np.testing.assert_array_equal(col_g, col_o)
+    ev = _rowrel(val_g[:c.dim + 1], val_o)
+    ep = _rowrel(val_g[c.dim + 1], pv_o)
+    print(f"[full] {name}: {len(samples)} sampled rows, weights {ew:.1e}, operators {ev:.1e}, pressure rows {ep:.1e}",
+          flush=True)
+    assert ew <= 1e-10 and ev <= 1e-10 and ep <= 1e-10
+
+
+def test_fullsize_spmv(full):
+    """The benchmark's SpMV (pressure-correction matrix, the field bench.py
+    applies) at the sampled rows, against the oracle's rows: within 1e-10 of
+    sum |a_ij x_j|."""
+    name, c, k, s, samples, nbr_o, w_o, col_o, val_o, pv_o = full
+    x = np.sin(c.xyz[:, 0]) * np.cos(c.xyz[:, 1])
+    y = s.ops.apply(c.dim + 1, torch.tensor(x, device="cuda")).cpu().numpy()
+    yo = (pv_o * x[col_o]).sum(axis=1)
+    scale = (np.abs(pv_o) * np.abs(x[col_o])).sum(axis=1)
+    diff = np.abs(y[samples] - yo)
+    err = float((diff / np.maximum(scale, 1e-300)).max())   # an identity row where x = 0 has scale 0
+    print(f"[full] {name}: SpMV at {len(samples)} rows, error {err:.1e} of sum |a x|", flush=True)
+    assert (diff <= 1e-10 * scale).all()
+
+
+def test_fullsize_poisson_residual(full, ctx):
+    """BiCGSTAB on the full pressure-correction system (bench.py's right-hand
+    side): the returned true residual meets the tolerance, and at the sampled
+    rows the residual computed from the oracle's rows is within that bound."""
+    name, c, k, s, samples, nbr_o, w_o, col_o, val_o, pv_o = full
+    b = np.random.default_rng(1).standard_normal(c.n)
+    x = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+    tol = 1e-8
+    st = R.poisson_solve(ctx, s.ops, torch.tensor(b, device="cuda"), x, tol=tol, max_iter=20000)
+    xg = x.cpu().numpy()
+    r = b[samples] - (pv_o * xg[col_o]).sum(axis=1)
+    slack = 1e-10 * (np.abs(pv_o) * np.abs(xg[col_o])).sum(axis=1)
+    bn = float(np.linalg.norm(b))
+    print(f"[full] {name}: {st['iters']} iterations, relres {st['relres']:.1e}, sampled |r|max "
+          f"{np.abs(r).max() / bn:.1e} of |b|", flush=True)
+    assert st["status"] == 0 and st["relres"] <= tol
+    assert (np.abs(r) <= tol * bn + slack).all()
+
+
+def test_fullsize_step_fixed_point(full, ctx):
+    """One BDF2 step from the exact stagnation flow (quadratic in space, linear
+    in time, so k >= 2 differentiates it exactly) lands on the exact state at
+    t^{n+1} on the full cloud."""
+    name, c, k, s, samples, nbr_o, w_o, col_o, val_o, pv_o = full
+    rho, mu, dt, t = 1.3, 0.05, 0.05, 0.3
+    un, pn = W.polynomial_flow(c.xyz, t, "stagnation", rho)
+    um, _ = W.polynomial_flow(c.xyz, t - dt, "stagnation", rho)
+    ue, pe = W.polynomial_flow(c.xyz, t + dt, "stagnation", rho)
+    u = torch.tensor(un, device="cuda")
+    up = torch.tensor(um, device="cuda")
+    pg = torch.tensor(pn, device="cuda")
+    has_pbc = bool(((c.kind == W.PRESCRIBED_PRESSURE) | (c.kind == W.OUTLET)).any())
+    st = R.simple_step(ctx, s.ops, u, up, pg, torch.tensor(ue, device="cuda"), rho, mu, dt, R.BDF2,
+                       tol_outer=1e-12, tol_krylov=1e-12, max_outer=3, max_krylov=20000,
+                       p_bc=torch.tensor(pe, device="cuda") if has_pbc else None)
+    ug, pgn = u.cpu().numpy(), pg.cpu().numpy()
+    su, sp_ = max(1.0, np.abs(ue).max()), max(1.0, np.abs(pe).max())
+    du, dp = np.abs(ug - ue).max() / su, np.abs(pgn - pe).max() / sp_
+    print(f"[full] {name}: stagnation step, outer {st['outer_iters']} status {st['status']} du {du:.1e} dp {dp:.1e}",
+          flush=True)
+    assert du <= 1e-8 and dp <= 1e-7
