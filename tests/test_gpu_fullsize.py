@@ -94,20 +94,34 @@ def test_fullsize_spmv(full):
     assert (diff <= 1e-10 * scale).all()
 
 
-def test_fullsize_poisson_residual(full, ctx):
+SOLVES = {"fp64_jacobi": ("RBFFD_FP64", "RBFFD_PREC_JACOBI"), "fp64_block": ("RBFFD_FP64", "RBFFD_PREC_BLOCK64"),
+          "fp32_matrix_block": ("RBFFD_FP32_MATRIX", "RBFFD_PREC_BLOCK64"),
+          "fp32_vectors_jacobi": ("RBFFD_FP32_IR", "RBFFD_PREC_JACOBI")}
+
+
+@pytest.mark.parametrize("mode", sorted(SOLVES))
+def test_fullsize_poisson_residual(full, ctx, mode):
     """BiCGSTAB on the full pressure-correction system (bench.py's right-hand
-    side): the returned true residual meets the tolerance, and at the sampled
-    rows the residual computed from the oracle's rows is within that bound."""
+    side), in FP64 and in both mixed-precision modes (operators with FP32
+    copies, as bench.py assembles them), with the Jacobi and the block-Jacobi
+    preconditioner: the returned true residual meets the tolerance, and at the
+    sampled rows the residual computed from the oracle's rows is within that
+    bound."""
     name, c, k, s, samples, nbr_o, w_o, col_o, val_o, pv_o = full
+    prec, pc = (getattr(R, a) for a in SOLVES[mode])
     b = np.random.default_rng(1).standard_normal(c.n)
     x = torch.zeros(c.n, dtype=torch.float64, device="cuda")
     tol = 1e-8
-    st = R.poisson_solve(ctx, s.ops, torch.tensor(b, device="cuda"), x, tol=tol, max_iter=20000)
+    ops = s.ops if prec == R.RBFFD_FP64 else R.rbffd_assemble(ctx, s.dcloud, s.nbr, s.w, k, precision=R.RBFFD_FP32_IR)
+    st = R.poisson_solve(ctx, ops, torch.tensor(b, device="cuda"), x, tol=tol, max_iter=20000, precision=prec,
+                         preconditioner=pc)
+    if ops is not s.ops:
+        ops.free()
     xg = x.cpu().numpy()
     r = b[samples] - (pv_o * xg[col_o]).sum(axis=1)
     slack = 1e-10 * (np.abs(pv_o) * np.abs(xg[col_o])).sum(axis=1)
     bn = float(np.linalg.norm(b))
-    print(f"[full] {name}: {st['iters']} iterations, relres {st['relres']:.1e}, sampled |r|max "
+    print(f"[full] {name} {mode}: {st['iters']} iterations, relres {st['relres']:.1e}, sampled |r|max "
           f"{np.abs(r).max() / bn:.1e} of |b|", flush=True)
     assert st["status"] == 0 and st["relres"] <= tol
     assert (np.abs(r) <= tol * bn + slack).all()
