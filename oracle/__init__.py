@@ -167,18 +167,53 @@ def knn_points(xyz, q, points):
     return out
 
 
-def interpolate(xyz, k, points, fields, q=None, phs=3):
+def wrap_points(xyz, points, period):
+    """Query points moved into the cloud's periodic box: along a periodic axis
+    of period L, a coordinate outside [lo, lo + L) (lo the cloud's smallest) is
+    replaced by lo + r, r = fmod(x - lo, L) taken into [0, L); coordinates
+    inside are kept as they are."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    pts = np.array(points, dtype=np.float64).reshape(-1, xyz.shape[1])
+    for d in range(xyz.shape[1]):
+        L = period[d]
+        if not L > 0:
+            continue
+        lo = float(xyz[:, d].min())
+        for t in range(len(pts)):
+            x = float(pts[t, d])
+            if x < lo or x >= lo + L:
+                r = math.fmod(x - lo, L)
+                if r < 0:
+                    r += L
+                pts[t, d] = lo + r
+    return pts
+
+
+def interpolate(xyz, k, points, fields, q=None, phs=3, period=None):
     """Evaluate the local PHS + polynomial interpolant of each point's q-point
     cloud (Sec. 2, Eq. RBF_interp) at arbitrary points: returns
-    (values[nfield, np], nbr[np, q], w[np, q])."""
+    (values[nfield, np], nbr[np, q], w[np, q]). With a period (Sec. 3.1
+    periodic boundaries) the points are wrapped into the periodic box
+    (wrap_points), each takes its cloud among all images of the cloud's
+    points (periodic_images), the weights use the images' coordinates, and
+    the cloud is written with the indices of the points the images stand for."""
     xyz = np.asarray(xyz, dtype=np.float64)
     dim = xyz.shape[1]
     q = default_q(dim, k) if q is None else q
-    nbr = knn_points(xyz, q, points)
-    pts = np.asarray(points, dtype=np.float64).reshape(-1, dim)
+    periodic = period is not None and any(p > 0 for p in period[:dim])
+    if periodic:
+        pts = wrap_points(xyz, points, period)
+        src, owner = periodic_images(xyz, period)
+    else:
+        pts = np.asarray(points, dtype=np.float64).reshape(-1, dim)
+        src, owner = xyz, np.arange(len(xyz))
+    nbr = knn_points(src, q, pts)
     w = np.zeros((len(pts), q))
     for t in range(len(pts)):
-        w[t] = interp_weights(xyz, nbr[t], pts[t], k, phs)
+        w[t] = interp_weights(src, nbr[t], pts[t], k, phs)
+    nbr = owner[nbr].astype(np.int32)
+    if periodic and any(len(set(r)) != q for r in nbr):
+        raise ValueError("a cloud holds two images of one point: period too small for q")
     f = np.asarray(fields, dtype=np.float64).reshape(-1, len(xyz))
     vals = np.array([[w[t] @ fi[nbr[t]] for t in range(len(pts))] for fi in f])
     return vals, nbr, w

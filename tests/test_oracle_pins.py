@@ -743,3 +743,61 @@ def test_cylinder_force_kovasznay_converges(orc):
             errs[nt, k] = np.abs(F - Fe).max() / np.abs(Fe).max()
     assert errs[3000, 3] < 3e-4 and errs[3000, 4] < 3e-6, errs
     assert errs[12000, 3] < errs[3000, 3] / 4, errs
+
+
+# ---- interpolation on periodic clouds (Sec. 2 off the nodes, Sec. 3.1 periodic) ----
+def _periodic_queries(c, rng, m=120):
+    L = c.period[0]
+    h = c.h
+    near = rng.uniform(0, L, size=(m, 2))
+    near[: m // 2, 0] = rng.choice([-1, 1], m // 2) * rng.uniform(0, h, m // 2) % L   # within h of the x seam
+    near[m // 2:, 1] = rng.choice([-1, 1], m - m // 2) * rng.uniform(0, h, m - m // 2) % L
+    inner = rng.uniform(0.3 * L, 0.7 * L, size=(m, 2))
+    return near, inner
+
+
+def test_periodic_interpolation_clouds_and_exactness(orc):
+    """The clouds of query points near the seams are the q nearest by
+    minimum-image distance (scipy's periodic k-d tree, independent code);
+    constants are reproduced at any point, and a query on a node returns the
+    nodal value."""
+    from scipy.spatial import cKDTree
+    c = W.taylor_green_periodic(nx=24)
+    L = c.period[0]
+    k = 3
+    rng = np.random.default_rng(2)
+    near, _ = _periodic_queries(c, rng)
+    ones = np.ones(c.n)
+    f = np.sin(c.xyz[:, 0]) * np.cos(c.xyz[:, 1])
+    vals, nbr, w = orc.interpolate(c.xyz, k, near, [ones, f], period=c.period)
+    q = nbr.shape[1]
+    d_tree, _ = cKDTree(c.xyz, boxsize=L).query(near, q)
+    dd = np.abs(c.xyz[nbr] - near[:, None, :])
+    dd = np.minimum(dd, L - dd)
+    d_ours = np.sort(np.sqrt((dd ** 2).sum(-1)), axis=1)
+    np.testing.assert_allclose(d_ours, d_tree, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(vals[0], 1.0, rtol=0, atol=1e-12)
+    nodes = c.xyz[rng.choice(c.n, 20, replace=False)]
+    vn, _, _ = orc.interpolate(c.xyz, k, nodes, [f], period=c.period)
+    fn = np.sin(nodes[:, 0]) * np.cos(nodes[:, 1])
+    np.testing.assert_allclose(vn[0], fn, rtol=0, atol=1e-12)
+
+
+def test_periodic_interpolation_seams_and_shifts(orc):
+    """A smooth periodic field is interpolated as accurately next to the seams
+    as inside (error ratio < 3), and queries moved by a period (outside the
+    box) give the same values."""
+    c = W.taylor_green_periodic(nx=32)
+    L = c.period[0]
+    k = 4
+    rng = np.random.default_rng(4)
+    near, inner = _periodic_queries(c, rng)
+    f = np.sin(c.xyz[:, 0]) * np.cos(2 * c.xyz[:, 1])
+    ex = lambda P: np.sin(P[:, 0]) * np.cos(2 * P[:, 1])     # noqa: E731
+    vn, _, _ = orc.interpolate(c.xyz, k, near, [f], period=c.period)
+    vi, _, _ = orc.interpolate(c.xyz, k, inner, [f], period=c.period)
+    en, ei = np.abs(vn[0] - ex(near)).max(), np.abs(vi[0] - ex(inner)).max()
+    assert en < 3 * ei and en < 1e-4, (en, ei)
+    shifted = near + np.array([L, -L]) * rng.choice([0, 1], size=(len(near), 2))
+    vs, _, _ = orc.interpolate(c.xyz, k, shifted, [f], period=c.period)
+    np.testing.assert_allclose(vs[0], vn[0], rtol=0, atol=1e-12)
