@@ -194,6 +194,12 @@ int rbffd_apply(rbffd_ctx *ctx, const rbffd_ops *ops, int which, const double *x
  *   nbr_out, w_out: optional device [nq][q] int32 clouds and [nq][q] double
  *           weights (out[f][j] = sum_a w[j][a] fields[f][nbr[j][a]]); NULL to
  *           keep them internal
+ * On a periodic cloud (Sec. 3.1), a query coordinate outside [lo, lo + L)
+ * along a periodic axis (lo the cloud's smallest coordinate there) is first
+ * wrapped to lo + r, r = fmod(x - lo, L) taken into [0, L); the query takes
+ * its q nearest among the points and their periodic images, the weights use
+ * the images' coordinates, and nbr_out names the points the images stand for
+ * (RBFFD_E_ARG if a cloud would hold two images of one point).
  * Systems of up to 128 unknowns (q + m). Synchronises the stream. Returns
  * RBFFD_E_SINGULAR (lowest query index in *bad_query) for a singular local
  * system, RBFFD_E_ARG for bad sizes; nq = 0 is a no-op. */

@@ -114,69 +114,106 @@ static bool is_periodic(const rbffd_cloud *c)
 // images of. The band starts at twice the radius that holds q points at the
 // mean density and doubles until every point's q-th neighbour lies within it,
 // which makes the search exact.
+// The periodic box of a cloud: its coordinates on the host, their bounds, a
+// first band width (twice the radius holding q points at the mean density)
+// and the shift vectors m in {-1, 0, 1}^dim, nonzero only along periodic axes.
+struct PeriodicBox {
+    int dim = 2;
+    int64_t n = 0;
+    const double *L = nullptr;
+    std::vector<double> x;
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    double band = 0.0;
+    std::vector<std::array<int, 3>> shifts;
+};
+
+static int periodic_box(const rbffd_cloud *cloud, int q, hipStream_t s, PeriodicBox *b)
+{
+    const int dim = cloud->dim;
+    const int64_t n = cloud->n;
+    b->dim = dim;
+    b->n = n;
+    b->L = cloud->period;
+    b->x.resize((size_t)n * dim);
+    RB_HIP(hipMemcpyAsync(b->x.data(), cloud->xyz, sizeof(double) * n * dim, hipMemcpyDeviceToHost, s));
+    RB_HIP(hipStreamSynchronize(s));
+    for (int d = 0; d < dim; ++d) {
+        b->lo[d] = INFINITY;
+        b->hi[d] = -INFINITY;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < dim; ++d) {
+            const double v = b->x[i * dim + d];
+            if (!std::isfinite(v)) return fail(RBFFD_E_ARG, "non-finite coordinates");
+            b->lo[d] = std::min(b->lo[d], v);
+            b->hi[d] = std::max(b->hi[d], v);
+        }
+    const double *L = b->L;
+    double vol = 1.0;
+    for (int d = 0; d < dim; ++d) {
+        if (L[d] > 0.0 && !(b->hi[d] - b->lo[d] < L[d]))
+            return fail(RBFFD_E_ARG, "the cloud's extent along a periodic axis is not below its period");
+        vol *= (L[d] > 0.0) ? L[d] : std::max(b->hi[d] - b->lo[d], 1e-300);
+    }
+    const double pi = 3.14159265358979323846;
+    b->band = 2.0 * ((dim == 2) ? std::sqrt(q * vol / (pi * (double)n))
+                                : std::cbrt(3.0 * q * vol / (4.0 * pi * (double)n)));
+    b->shifts.clear();
+    for (int a = -1; a <= 1; ++a)
+        for (int bb = -1; bb <= 1; ++bb)
+            for (int c = -1; c <= 1; ++c) {
+                const int m[3] = {a, bb, c};
+                bool ok = !(a == 0 && bb == 0 && c == 0);
+                for (int d = 0; d < 3; ++d)
+                    if (m[d] != 0 && (d >= dim || !(L[d] > 0.0))) ok = false;
+                if (ok) b->shifts.push_back({a, bb, c});
+            }
+    return RBFFD_OK;
+}
+
+// The points followed by their images x_j + m L (coordinates formed as x + L
+// or x - L) that lie within `band` of the box along every periodic axis;
+// owner[r] is the point row r stands for.
+static void periodic_images(const PeriodicBox &b, double band, std::vector<double> &aug, std::vector<int32_t> &owner)
+{
+    const int dim = b.dim;
+    const double *L = b.L;
+    aug = b.x;
+    owner.resize((size_t)b.n);
+    for (int64_t i = 0; i < b.n; ++i) owner[i] = (int32_t)i;
+    for (const auto &m : b.shifts)
+        for (int64_t j = 0; j < b.n; ++j) {
+            double y[3];
+            bool keep = true;
+            for (int d = 0; d < dim; ++d) {
+                const double v = b.x[j * dim + d];
+                y[d] = (m[d] > 0) ? v + L[d] : ((m[d] < 0) ? v - L[d] : v);
+                if (L[d] > 0.0 && (y[d] < b.lo[d] - band || y[d] > b.hi[d] + band)) keep = false;
+            }
+            if (!keep) continue;
+            for (int d = 0; d < dim; ++d) aug.push_back(y[d]);
+            owner.push_back((int32_t)j);
+        }
+}
+
 static int stencils_periodic(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_stencil_opts *opts, int q,
                              int32_t *nbr, double *w, int64_t *bad_point, hipStream_t s)
 {
     const int dim = cloud->dim;
     const int64_t n = cloud->n;
-    std::vector<double> x((size_t)n * dim);
-    RB_HIP(hipMemcpyAsync(x.data(), cloud->xyz, sizeof(double) * n * dim, hipMemcpyDeviceToHost, s));
-    RB_HIP(hipStreamSynchronize(s));
-    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-    for (int d = 0; d < dim; ++d) {
-        lo[d] = INFINITY;
-        hi[d] = -INFINITY;
-    }
-    for (int64_t i = 0; i < n; ++i)
-        for (int d = 0; d < dim; ++d) {
-            const double v = x[i * dim + d];
-            if (!std::isfinite(v)) return fail(RBFFD_E_ARG, "non-finite coordinates");
-            lo[d] = std::min(lo[d], v);
-            hi[d] = std::max(hi[d], v);
-        }
-    const double *L = cloud->period;
-    double vol = 1.0;
-    for (int d = 0; d < dim; ++d) {
-        if (L[d] > 0.0 && !(hi[d] - lo[d] < L[d]))
-            return fail(RBFFD_E_ARG, "the cloud's extent along a periodic axis is not below its period");
-        vol *= (L[d] > 0.0) ? L[d] : std::max(hi[d] - lo[d], 1e-300);
-    }
-    const double pi = 3.14159265358979323846;
-    double band = 2.0 * ((dim == 2) ? std::sqrt(q * vol / (pi * (double)n))
-                                    : std::cbrt(3.0 * q * vol / (4.0 * pi * (double)n)));
-    // shift vectors m in {-1, 0, 1}^dim, nonzero only along periodic axes
-    std::vector<std::array<int, 3>> shifts;
-    for (int a = -1; a <= 1; ++a)
-        for (int b = -1; b <= 1; ++b)
-            for (int c = -1; c <= 1; ++c) {
-                const int m[3] = {a, b, c};
-                bool ok = !(a == 0 && b == 0 && c == 0);
-                for (int d = 0; d < 3; ++d)
-                    if (m[d] != 0 && (d >= dim || !(L[d] > 0.0))) ok = false;
-                if (ok) shifts.push_back({a, b, c});
-            }
+    PeriodicBox box;
+    RB_CHECK(periodic_box(cloud, q, s, &box));
+    const std::vector<double> &x = box.x;
+    double band = box.band;
     int64_t *bad_dev = nullptr;
     RB_CHECK(workspace(ctx, WS_MISC, sizeof(int64_t), (void **)&bad_dev));
     int64_t *hb = nullptr;
     RB_CHECK(host_scratch(ctx, kHostMisc, sizeof(int64_t), (void **)&hb));
     std::vector<int32_t> hn((size_t)n * q);
     for (int attempt = 0; attempt < 12; ++attempt, band *= 2.0) {
-        std::vector<double> aug(x);
-        std::vector<int32_t> owner((size_t)n);
-        for (int64_t i = 0; i < n; ++i) owner[i] = (int32_t)i;
-        for (const auto &m : shifts)
-            for (int64_t j = 0; j < n; ++j) {
-                double y[3];
-                bool keep = true;
-                for (int d = 0; d < dim; ++d) {
-                    const double v = x[j * dim + d];
-                    y[d] = (m[d] > 0) ? v + L[d] : ((m[d] < 0) ? v - L[d] : v);
-                    if (L[d] > 0.0 && (y[d] < lo[d] - band || y[d] > hi[d] + band)) keep = false;
-                }
-                if (!keep) continue;
-                for (int d = 0; d < dim; ++d) aug.push_back(y[d]);
-                owner.push_back((int32_t)j);
-            }
+        std::vector<double> aug;
+        std::vector<int32_t> owner;
+        periodic_images(box, band, aug, owner);
         const int64_t naug = (int64_t)owner.size();
         if (naug >= (int64_t(1) << 31)) return fail(RBFFD_E_ARG, "too many periodic images");
         double *aug_dev = nullptr;
@@ -457,6 +494,125 @@ int rbffd_apply(rbffd_ctx *ctx, const rbffd_ops *ops, int which, const double *x
     return apply_op(ctx, ops, which, x, y, (hipStream_t)hip_stream);
 }
 
+// Interpolation on a periodic cloud (Sec. 2 off the nodes, Sec. 3.1 periodic
+// boundaries). Query coordinates outside [lo, lo + L) along a periodic axis
+// are wrapped to lo + r, r = fmod(x - lo, L) taken into [0, L). Each query
+// takes its q nearest among the points and their images within a band of the
+// box; the band widens until every q-th neighbour lies closer than the band
+// less the query's own distance outside the box, so no image left out can be
+// nearer. Weights use the images' coordinates; the clouds are then written
+// with the indices of the points the images stand for, and the fields are
+// sampled through them.
+static int interpolate_periodic(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_stencil_opts *opts, int q,
+                                int64_t nq, const double *qxyz, int nfield, const double *fields, double *out,
+                                int32_t *nbr, double *w, int64_t *bad_query, hipStream_t s)
+{
+    const int dim = cloud->dim;
+    const int64_t n = cloud->n;
+    PeriodicBox box;
+    RB_CHECK(periodic_box(cloud, q, s, &box));
+    const double *L = cloud->period;
+    std::vector<double> hq((size_t)nq * dim);
+    RB_HIP(hipMemcpyAsync(hq.data(), qxyz, sizeof(double) * nq * dim, hipMemcpyDeviceToHost, s));
+    RB_HIP(hipStreamSynchronize(s));
+    std::vector<double> outside((size_t)nq, 0.0);   // largest distance of a query outside the box along an axis
+    for (int64_t t = 0; t < nq; ++t)
+        for (int d = 0; d < dim; ++d) {
+            double &v = hq[t * dim + d];
+            if (!std::isfinite(v)) return fail(RBFFD_E_ARG, "non-finite query coordinates");
+            if (!(L[d] > 0.0)) continue;
+            if (v < box.lo[d] || v >= box.lo[d] + L[d]) {
+                double r = std::fmod(v - box.lo[d], L[d]);
+                if (r < 0.0) r += L[d];
+                v = box.lo[d] + r;
+            }
+            outside[t] = std::max(outside[t], std::max(box.lo[d] - v, v - box.hi[d]));
+        }
+    const size_t qbytes = sizeof(double) * nq * dim;
+    double *qdev = nullptr;
+    RB_CHECK(dev_alloc(ctx, (void **)&qdev, qbytes));
+    int64_t *bad_dev = nullptr, *hb = nullptr;
+    int st = workspace(ctx, WS_MISC, sizeof(int64_t), (void **)&bad_dev);
+    if (st == RBFFD_OK) st = host_scratch(ctx, kHostMisc, sizeof(int64_t), (void **)&hb);
+    hipError_t e = hipSuccess;
+    if (st == RBFFD_OK) {
+        e = hipMemcpyAsync(qdev, hq.data(), qbytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) st = hip_fail(e, "periodic queries");
+    }
+    std::vector<int32_t> hn((size_t)nq * q);
+    double band = box.band;
+    bool done = false;
+    for (int attempt = 0; st == RBFFD_OK && !done && attempt < 12; ++attempt, band *= 2.0) {
+        std::vector<double> aug;
+        std::vector<int32_t> owner;
+        periodic_images(box, band, aug, owner);
+        const int64_t naug = (int64_t)owner.size();
+        if (naug >= (int64_t(1) << 31)) {
+            st = fail(RBFFD_E_ARG, "too many periodic images");
+            break;
+        }
+        double *aug_dev = nullptr;
+        const size_t abytes = sizeof(double) * naug * dim;
+        st = dev_alloc(ctx, (void **)&aug_dev, abytes);
+        if (st != RBFFD_OK) break;
+        e = hipMemcpyAsync(aug_dev, aug.data(), abytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) st = hip_fail(e, "periodic images");
+        if (st == RBFFD_OK) st = launch_knn_points(ctx, dim, naug, aug_dev, nq, qdev, q, nbr, s);
+        if (st == RBFFD_OK) {
+            e = hipMemcpyAsync(hn.data(), nbr, sizeof(int32_t) * nq * q, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) st = hip_fail(e, "periodic neighbours");
+        }
+        bool inside = true;
+        for (int64_t t = 0; st == RBFFD_OK && t < nq && inside; ++t) {
+            const int64_t j = hn[t * q + q - 1];
+            double d2 = 0.0;
+            for (int d = 0; d < dim; ++d) {
+                const double dd = aug[j * dim + d] - hq[t * dim + d];
+                d2 += dd * dd;
+            }
+            inside = std::sqrt(d2) <= band - outside[t];
+        }
+        if (st == RBFFD_OK && inside) {
+            done = true;
+            st = launch_interp(ctx, dim, naug, aug_dev, nq, qdev, q, nbr, opts->poly_degree, opts->phs_power, w,
+                               bad_dev, 0, nullptr, nullptr, s);
+            if (st == RBFFD_OK) {
+                e = hipMemcpyAsync(hb, bad_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess) e = hipStreamSynchronize(s);
+                if (e != hipSuccess) st = hip_fail(e, "periodic interpolation weights");
+            }
+            // image indices back to the points they stand for; a point may
+            // appear in a cloud only once
+            std::vector<int32_t> row((size_t)q);
+            for (int64_t t = 0; st == RBFFD_OK && t < nq; ++t) {
+                for (int a = 0; a < q; ++a) row[a] = owner[hn[t * q + a]];
+                std::vector<int32_t> sorted(row);
+                std::sort(sorted.begin(), sorted.end());
+                if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+                    st = fail(RBFFD_E_ARG, "query " + std::to_string(t) +
+                                               ": its cloud holds two images of one point (period too small for q)");
+                for (int a = 0; a < q; ++a) hn[t * q + a] = row[a];
+            }
+        }
+        (void)hipStreamSynchronize(s);
+        dev_free(ctx, aug_dev, abytes);
+    }
+    if (st == RBFFD_OK && !done) st = fail(RBFFD_E_ARG, "no band of periodic images holds every cloud");
+    if (st == RBFFD_OK) {
+        e = hipMemcpyAsync(nbr, hn.data(), sizeof(int32_t) * nq * q, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) st = hip_fail(e, "periodic clouds");
+    }
+    const int64_t bad = (st == RBFFD_OK && *hb != INT64_MAX) ? *hb : -1;
+    if (st == RBFFD_OK && bad < 0) st = launch_interp_apply(nq, q, nbr, w, nfield, n, fields, out, s);
+    (void)hipStreamSynchronize(s);
+    dev_free(ctx, qdev, qbytes);
+    RB_CHECK(st);
+    if (bad_query) *bad_query = bad;
+    if (bad >= 0) return fail(RBFFD_E_SINGULAR, "singular interpolation system at query " + std::to_string(bad));
+    return RBFFD_OK;
+}
+
 int rbffd_interpolate(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_stencil_opts *opts, int64_t nq,
                       const double *qxyz, int nfield, const double *fields, double *out, int32_t *nbr_out,
                       double *w_out, int64_t *bad_query, void *hip_stream)
@@ -468,7 +624,6 @@ int rbffd_interpolate(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_sten
     RB_CHECK(resolve_sizes(cloud->dim, opts, &q, &m, &R));
     if (q > cloud->n) return fail(RBFFD_E_ARG, "cloud size q exceeds the number of points");
     if (q + m > 128) return fail(RBFFD_E_ARG, "collocation systems larger than 128 (q + m) are not supported");
-    if (is_periodic(cloud)) return fail(RBFFD_E_ARG, "interpolation on periodic clouds is not supported");
     if (nq < 0 || nfield < 0) return fail(RBFFD_E_ARG, "nq and nfield must be >= 0");
     if (nq > INT32_MAX) return fail(RBFFD_E_ARG, "too many query points");
     if (nq == 0) return RBFFD_OK;
@@ -491,6 +646,12 @@ int rbffd_interpolate(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_sten
     int64_t *hb = nullptr;
     int st = workspace(ctx, WS_MISC, sizeof(int64_t), (void **)&bad_dev);
     if (st == RBFFD_OK) st = host_scratch(ctx, kHostMisc, sizeof(int64_t), (void **)&hb);
+    if (st == RBFFD_OK && is_periodic(cloud)) {
+        st = interpolate_periodic(ctx, cloud, opts, q, nq, qxyz, nfield, fields, out, nbr, w, bad_query, s);
+        if (!w_out) dev_free(ctx, w, wb);
+        if (!nbr_out) dev_free(ctx, nbr, nb);
+        return st;
+    }
     if (st == RBFFD_OK) st = launch_knn_points(ctx, cloud->dim, cloud->n, cloud->xyz, nq, qxyz, q, nbr, s);
     if (st == RBFFD_OK)
         st = launch_interp(ctx, cloud->dim, cloud->n, cloud->xyz, nq, qxyz, q, nbr, opts->poly_degree,
@@ -526,7 +687,7 @@ int rbffd_cylinder_forces(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_
     RB_CHECK(check_cloud(cloud));
     if (cloud->dim != 2 || ops->dim != 2) return fail(RBFFD_E_ARG, "cylinder forces are defined for 2D clouds");
     if (cloud->n != ops->n) return fail(RBFFD_E_ARG, "the cloud and the operators differ in size");
-    if (is_periodic(cloud)) return fail(RBFFD_E_ARG, "interpolation on periodic clouds is not supported");
+    if (is_periodic(cloud)) return fail(RBFFD_E_ARG, "cylinder forces on periodic clouds are not supported");
     if (nsurf < 4 || (nsurf & 1) || nsurf > kMaxSurface)
         return fail(RBFFD_E_ARG, "nsurf must be even, at least 4 and at most " + std::to_string(kMaxSurface));
     if (!(diameter > 0.0) || !std::isfinite(diameter) || !std::isfinite(centre[0]) || !std::isfinite(centre[1]) ||

@@ -238,6 +238,9 @@ int launch_knn_points(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int
 int launch_interp(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int64_t nq, const double *qxyz, int q,
                   const int32_t *nbr, int k, int phs, double *w, int64_t *bad_dev, int nfield, const double *fields,
                   double *out, hipStream_t s);
+// out[f][j] = sum_a w[j][a] fields[f][nbr[j][a]] for nq points (fields [nfield][n]).
+int launch_interp_apply(int64_t nq, int q, const int32_t *nbr, const double *w, int nfield, int64_t n,
+                        const double *fields, double *out, hipStream_t s);
 int assemble_ops(rbffd_ctx *ctx, const rbffd_cloud *cloud, int q, int k, int phs,
                  const int32_t *nbr, const double *w, int precision, rbffd_ops *ops, hipStream_t s);
 int export_csr(const rbffd_ops *ops, int32_t *col, double *val, hipStream_t s);

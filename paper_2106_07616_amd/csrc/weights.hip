@@ -587,11 +587,16 @@ int launch_interp(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int64_t
         }
     }
     RB_HIP(hipGetLastError());
-    if (nfield > 0) {
-        hipLaunchKernelGGL(interp_apply, dim3((unsigned)((nq + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, nq, q, nbr,
-                           w, nfield, n, fields, out);
-        RB_HIP(hipGetLastError());
-    }
+    return launch_interp_apply(nq, q, nbr, w, nfield, n, fields, out, s);
+}
+
+int launch_interp_apply(int64_t nq, int q, const int32_t *nbr, const double *w, int nfield, int64_t n,
+                        const double *fields, double *out, hipStream_t s)
+{
+    if (nfield <= 0 || nq == 0) return RBFFD_OK;
+    hipLaunchKernelGGL(interp_apply, dim3((unsigned)((nq + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, nq, q, nbr, w,
+                       nfield, n, fields, out);
+    RB_HIP(hipGetLastError());
     return RBFFD_OK;
 }
 

@@ -130,3 +130,31 @@ def test_interpolation_edge_cases(ctx):
     o7 = R.binding.StencilOptsT(3, 7, 0)
     assert L.rbffd_interpolate(ctx.handle, C.byref(cs), C.byref(o7), 1, R.binding._ptr(q1), 0, None, None, None,
                                None, C.byref(bad), R.binding._stream()) == -1      # degree 7
+
+
+@pytest.mark.parametrize("k", [4, 6])
+def test_periodic_interpolation_matches_oracle(ctx, orc, k):
+    """Interpolation on the periodic Taylor-Green square at points next to the
+    seams and a period outside the box: clouds bit-exact with the oracle's
+    (which searches all images), weights within 1e-10, values within 1e-12;
+    k = 6 takes the 84-unknown LDS kernel."""
+    c = W.taylor_green_periodic()
+    L = c.period[0]
+    rng = np.random.default_rng(8)
+    m = 200
+    pts = rng.uniform(0, L, size=(m, 2))
+    pts[: m // 2, 0] = rng.uniform(-c.h, c.h, m // 2) % L           # next to the x seam
+    pts[m // 2:, 1] = rng.uniform(-c.h, c.h, m - m // 2) % L
+    pts[::7] += np.array([L, -L])                                   # outside the box
+    f = np.stack([np.sin(c.xyz[:, 0]) * np.cos(c.xyz[:, 1]), np.cos(2 * c.xyz[:, 0])])
+    vo, nbr_o, w_o = orc.interpolate(c.xyz, k, pts, f, period=c.period)
+    dc = R.DeviceCloud.from_numpy(c, "cuda")
+    out, nbr, w = R.rbffd_interpolate(ctx, dc, k, torch.tensor(pts, device="cuda"), torch.tensor(f, device="cuda"),
+                                      return_stencils=True)
+    nbr, w, out = nbr.cpu().numpy(), w.cpu().numpy(), out.cpu().numpy()
+    ew = float((np.abs(w - w_o).max(1) / np.abs(w_o).max(1)).max())
+    ev = float(np.abs(out - vo).max())
+    ex = np.abs(out[0] - np.sin(pts[:, 0]) * np.cos(pts[:, 1])).max()
+    print(f"[interp] periodic k={k}: weights {ew:.1e}, values {ev:.1e}, error vs the exact field {ex:.1e}", flush=True)
+    np.testing.assert_array_equal(nbr, nbr_o)
+    assert ew <= 1e-10 and ev <= 1e-12
