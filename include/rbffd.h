@@ -221,7 +221,7 @@ int rbffd_interpolate(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_sten
  *      the fluid;
  *   4. F = (D/2) * integral over t in [0, 2 pi] of the traction, by the
  *      composite Simpson rule over the nsurf panels of the closed curve.
- *   cloud, ops:   a 2D, non-periodic cloud and its operators (same n)
+ *   cloud, ops:   a 2D cloud and its operators (same n)
  *   u:            device [2][n] velocity; p: device [n] pressure
  *   centre:       host [2]; diameter D > 0; mu the dynamic viscosity
  *   nsurf:        even, 4 .. 1048576 (the paper uses 360)
@@ -233,8 +233,10 @@ int rbffd_interpolate(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_sten
  *                 system was singular, else -1
  * The surface may cross the cloud anywhere: its points take the q nearest
  * cloud points wherever they lie. Allocates device scratch for the five
- * fields at the nodes, synchronises the stream. RBFFD_E_ARG for 3D or
- * periodic clouds, mismatched sizes, odd or out-of-range nsurf, a
+ * fields at the nodes, synchronises the stream. On a periodic cloud the
+ * surface points are interpolated as rbffd_interpolate does there (a periodic
+ * array of cylinders). RBFFD_E_ARG for 3D clouds, mismatched sizes, odd or
+ * out-of-range nsurf, a
  * non-positive or non-finite diameter; RBFFD_E_SINGULAR for a singular
  * interpolation system. */
 int rbffd_cylinder_forces(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_ops *ops, const double *u,

@@ -472,7 +472,8 @@ def cylinder_forces(ops: Operators, u, p, centre, diameter, mu, nsurf=360, rho=N
 
     1. strain rates at the nodes from the cloud's d/dx and d/dy operators;
     2. pressure and strain rates interpolated (Eq. RBF_interp off the nodes,
-       with the operators' k, q and PHS power) to nsurf uniform points
+       with the operators' k, q and PHS power; on a periodic cloud as
+       interpolate does there) to nsurf uniform points
        x_j = centre + (D/2)(cos t_j, sin t_j), t_j = 2 pi j / nsurf;
     3. sigma = -p I + mu (grad u + grad u^T) there, and the traction
        sigma . (cos t, sin t), the normal pointing from the cylinder into the
@@ -496,7 +497,8 @@ def cylinder_forces(ops: Operators, u, p, centre, diameter, mu, nsurf=360, rho=N
     cs = [math.cos(2.0 * math.pi * j / nsurf) for j in range(nsurf)]
     sn = [math.sin(2.0 * math.pi * j / nsurf) for j in range(nsurf)]
     pts = np.array([[centre[0] + r * cs[j], centre[1] + r * sn[j]] for j in range(nsurf)])
-    vals, _, _ = interpolate(cloud.xyz, ops.k, pts, np.stack([p] + grads), q=ops.q, phs=ops.phs)
+    vals, _, _ = interpolate(cloud.xyz, ops.k, pts, np.stack([p] + grads), q=ops.q, phs=ops.phs,
+                             period=getattr(cloud, "period", None))
     trac = np.zeros((2, nsurf))
     for j in range(nsurf):
         pj, ux, uy, vx, vy = vals[:, j]

@@ -687,7 +687,6 @@ int rbffd_cylinder_forces(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_
     RB_CHECK(check_cloud(cloud));
     if (cloud->dim != 2 || ops->dim != 2) return fail(RBFFD_E_ARG, "cylinder forces are defined for 2D clouds");
     if (cloud->n != ops->n) return fail(RBFFD_E_ARG, "the cloud and the operators differ in size");
-    if (is_periodic(cloud)) return fail(RBFFD_E_ARG, "cylinder forces on periodic clouds are not supported");
     if (nsurf < 4 || (nsurf & 1) || nsurf > kMaxSurface)
         return fail(RBFFD_E_ARG, "nsurf must be even, at least 4 and at most " + std::to_string(kMaxSurface));
     if (!(diameter > 0.0) || !std::isfinite(diameter) || !std::isfinite(centre[0]) || !std::isfinite(centre[1]) ||
@@ -743,9 +742,20 @@ int rbffd_cylinder_forces(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_
     if (st == RBFFD_OK) st = apply_op(ctx, ops, 1, u, fld + 2 * n, s);
     if (st == RBFFD_OK) st = apply_op(ctx, ops, 0, u + n, fld + 3 * n, s);
     if (st == RBFFD_OK) st = apply_op(ctx, ops, 1, u + n, fld + 4 * n, s);
-    // pressure and strain rates at the surface points
-    if (st == RBFFD_OK) st = launch_knn_points(ctx, 2, n, cloud->xyz, ns, qxyz, q, nbr, s);
-    if (st == RBFFD_OK) st = launch_interp(ctx, 2, n, cloud->xyz, ns, qxyz, q, nbr, k, phs, w, bad_dev, 5, fld, fs, s);
+    // pressure and strain rates at the surface points (a periodic cloud takes
+    // the periodic interpolation, which reports a singular system itself)
+    const bool periodic = is_periodic(cloud);
+    if (st == RBFFD_OK && periodic) {
+        rbffd_stencil_opts o;
+        o.phs_power = phs;
+        o.poly_degree = k;
+        o.q = q;
+        st = interpolate_periodic(ctx, cloud, &o, q, ns, qxyz, 5, fld, fs, nbr, w, bad_query, s);
+    } else {
+        if (st == RBFFD_OK) st = launch_knn_points(ctx, 2, n, cloud->xyz, ns, qxyz, q, nbr, s);
+        if (st == RBFFD_OK)
+            st = launch_interp(ctx, 2, n, cloud->xyz, ns, qxyz, q, nbr, k, phs, w, bad_dev, 5, fld, fs, s);
+    }
     if (st == RBFFD_OK) st = launch_surface_traction(nsurf, fs, cs, mu, r * (h / 3.0), traction, res, s);
     if (st == RBFFD_OK) {
         e = hipMemcpyAsync(hres, res, sizeof(double) * 2 + sizeof(int64_t), hipMemcpyDeviceToHost, s);
@@ -756,8 +766,8 @@ int rbffd_cylinder_forces(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_
     dev_free(ctx, base, total);
     if (st != RBFFD_OK) return st;
     if (e != hipSuccess) return hip_fail(e, "cylinder forces");
-    int64_t bad = 0;
-    std::memcpy(&bad, hres + 2, sizeof(bad));
+    int64_t bad = INT64_MAX;
+    if (!periodic) std::memcpy(&bad, hres + 2, sizeof(bad));
     if (bad != INT64_MAX) {
         if (bad_query) *bad_query = bad;
         return fail(RBFFD_E_SINGULAR, "singular interpolation system at surface point " + std::to_string(bad));

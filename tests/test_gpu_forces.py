@@ -1,6 +1,6 @@
 """Drag and lift on a circular cylinder through the C ABI
 (rbffd_cylinder_forces) against the FP64 oracle: force, coefficients and the
-traction at every surface point. At any size, cubic velocity and quadratic
+traction at every surface point, also in a periodic cylinder array. At any size, cubic velocity and quadratic
 pressure fields give the divergence-theorem force pi R^2 (div sigma)(centre)."""
 import math
 
@@ -115,8 +115,26 @@ def test_cylinder_forces_reject_bad_arguments(ctx):
     with pytest.raises(R.RbffdError):
         s3.cylinder_forces(torch.zeros((2, cube.n), dtype=torch.float64, device="cuda"),
                            torch.zeros(cube.n, dtype=torch.float64, device="cuda"), (0.5, 0.5), 0.2, 0.01)
-    per = W.taylor_green_periodic()
-    sp = R.Solver(ctx, per, 2)
-    with pytest.raises(R.RbffdError):
-        sp.cylinder_forces(torch.zeros((2, per.n), dtype=torch.float64, device="cuda"),
-                           torch.zeros(per.n, dtype=torch.float64, device="cuda"), (1.0, 1.0), 0.5, 0.01)
+
+
+@pytest.mark.parametrize("k", [3, 5])
+def test_cylinder_forces_periodic_cell(ctx, orc, k):
+    """One cell of a periodic cylinder array, with a smooth periodic flow: the
+    force and the traction match the oracle's (1e-10 and 1e-9 of the traction
+    scale)."""
+    c = W.periodic_cylinder_cell()
+    cx, cy, r = c.meta["holes"][0]
+    x, y = 2 * np.pi * c.xyz[:, 0], 2 * np.pi * c.xyz[:, 1]
+    vel = np.stack([np.sin(x) * np.cos(y), -np.cos(x) * np.sin(y)])
+    p = 0.25 * (np.cos(2 * x) + np.cos(2 * y))
+    mu = 0.05
+    Fo, tro = orc.cylinder_forces(orc.build_operators(c, k), vel, p, (cx, cy), 2 * r, mu, 360)
+    s = R.Solver(ctx, c, k)
+    F, tr = s.cylinder_forces(torch.tensor(vel, device="cuda"), torch.tensor(p, device="cuda"), (cx, cy), 2 * r, mu,
+                              360, return_traction=True)
+    tr = tr.cpu().numpy()
+    scale = np.abs(tro).max()
+    print(f"[forces] periodic cell k={k}: F gpu {F} oracle {Fo}; traction diff {np.abs(tr - tro).max() / scale:.1e}",
+          flush=True)
+    assert np.abs(tr - tro).max() <= 1e-9 * scale
+    assert np.abs(np.array(F) - Fo).max() <= 1e-10 * scale * 2 * math.pi * r

@@ -801,3 +801,26 @@ def test_periodic_interpolation_seams_and_shifts(orc):
     shifted = near + np.array([L, -L]) * rng.choice([0, 1], size=(len(near), 2))
     vs, _, _ = orc.interpolate(c.xyz, k, shifted, [f], period=c.period)
     np.testing.assert_allclose(vs[0], vn[0], rtol=0, atol=1e-12)
+
+
+def test_cylinder_force_periodic_cell(orc):
+    """One cell of a periodic cylinder array: near the cylinder no cloud
+    reaches a seam, so cubic velocity and quadratic pressure are still
+    reproduced there and the force is the divergence-theorem value
+    pi R^2 (div sigma)(centre)."""
+    c = W.periodic_cylinder_cell()
+    cx, cy, r = c.meta["holes"][0]
+    rng = np.random.default_rng(3)
+    a, b, g = rng.standard_normal(10), rng.standard_normal(10), rng.standard_normal(6)
+    X, Y = c.xyz[:, 0] - 0.5, c.xyz[:, 1] - 0.5
+    u = np.stack([_poly(a, _CUBIC, X, Y), _poly(b, _CUBIC, X, Y)])
+    p = _poly(g, _CUBIC[:6], X, Y)
+    mu = 0.7
+    F, _ = orc.cylinder_forces(orc.build_operators(c, 3), u, p, (cx, cy), 2 * r, mu, 360)
+    X0, Y0 = cx - 0.5, cy - 0.5
+    div = np.array([
+        -_poly(g, _CUBIC[:6], X0, Y0, 1, 0) + 2 * mu * _poly(a, _CUBIC, X0, Y0, 2, 0)
+        + mu * (_poly(a, _CUBIC, X0, Y0, 0, 2) + _poly(b, _CUBIC, X0, Y0, 1, 1)),
+        -_poly(g, _CUBIC[:6], X0, Y0, 0, 1) + 2 * mu * _poly(b, _CUBIC, X0, Y0, 0, 2)
+        + mu * (_poly(a, _CUBIC, X0, Y0, 1, 1) + _poly(b, _CUBIC, X0, Y0, 2, 0))])
+    np.testing.assert_allclose(F, math.pi * r * r * div, rtol=0, atol=1e-11)

@@ -596,6 +596,29 @@ def holed_square(n_target: int, seed: int, n_holes: int | None = None, Re: float
                    centre=(0.5, 0.5), boundary_kind=None)
 
 
+def periodic_cylinder_cell(nx: int = 48, radius: float = 0.2, seed: int = 31, jitter: float = 0.2) -> Cloud:
+    """One cell of a periodic array of cylinders: the unit square, periodic in
+    x and y, minus a circle of the given radius at (0.5, 0.5). A cell-centred
+    nx-by-nx lattice jittered by U(-jitter h, jitter h), points within h/2 of
+    the circle removed, the circle carrying points at spacing ~h with normals
+    pointing into it (out of the fluid), no-slip there."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / nx
+    g = (np.arange(nx) + 0.5) * h
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    inter = np.stack([X.ravel(), Y.ravel()], axis=1) + rng.uniform(-jitter * h, jitter * h, size=(nx * nx, 2))
+    inter = inter[np.hypot(inter[:, 0] - 0.5, inter[:, 1] - 0.5) > radius + h / 2]
+    m = max(8, int(round(2 * np.pi * radius / h)))
+    th = np.arange(m) * (2 * np.pi / m)
+    circ = np.stack([0.5 + radius * np.cos(th), 0.5 + radius * np.sin(th)], axis=1)
+    xyz = np.concatenate([inter, circ])
+    kind = np.concatenate([np.zeros(len(inter), np.uint8), np.full(m, DIRICHLET, np.uint8)])
+    normal = np.concatenate([np.zeros_like(inter), -np.stack([np.cos(th), np.sin(th)], axis=1)])
+    return _finish(2, xyz, kind, normal, f"periodic_cylinder_{len(xyz)}", h,
+                   {"seed": seed, "holes": [(0.5, 0.5, float(radius))]}, centre=(0.0, 0.0), boundary_kind=None,
+                   period=(1.0, 1.0, 0.0))
+
+
 def scattered_square(nx: int, seed: int = 7, jitter: float = 0.2, lo: float = 0.0,
                      hi: float = 1.0) -> Cloud:
     """A jittered nx-by-nx lattice on [lo, hi]^2 with boundary points (no flow attached);
