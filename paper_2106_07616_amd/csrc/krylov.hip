@@ -48,10 +48,12 @@ struct KState {
     int moved;        // batched systems: block range changed, ||r||^2 is in rr
 };
 
-// BiCGSTAB kernels run 512-thread blocks on at most 1024 blocks, so that a
-// consumer kernel re-reduces at most 1024 partials per dot product.
+// BiCGSTAB kernels run 512-thread blocks on at most 512 blocks (two per CU),
+// so that a consumer kernel re-reduces at most 512 partials per dot product;
+// larger systems loop over rows. Measured at 1.06M rows: 258 us per iteration
+// with 512 blocks, 272 us with 1024, 282 us with 256.
 constexpr int kKB = 512;
-constexpr int kKMaxBlocks = 1024;
+constexpr int kKMaxBlocks = 512;
 static_assert(kKMaxBlocks <= kMaxBlocks, "partial arrays hold kMaxBlocks entries");
 
 __device__ inline double kblock_sum(double v, double *lds)
@@ -220,7 +222,7 @@ template <int NV>
 __device__ inline void sum_partials_n(const double *const *parts, int np, double *out)
 {
     __shared__ double red[NV][kKB / 64];
-    constexpr int kPer = kKMaxBlocks / kKB;
+    constexpr int kPer = (kKMaxBlocks + kKB - 1) / kKB;
     double ld[NV][kPer];
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
