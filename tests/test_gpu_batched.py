@@ -126,8 +126,9 @@ def test_batched_zero_rhs_and_order(ctx, batch):
 
 @pytest.mark.parametrize("pc", sorted(PCS))
 def test_batched_large_system_matches_single_solve(ctx, pc):
-    """A system with more rows than 1024 blocks of 512 threads (rows looped per
-    thread) agrees with the single-system solver."""
+    """A system with more rows than the BiCGSTAB grid has threads (512 blocks of
+    512 threads; rows looped per thread) agrees with the single-system
+    solver."""
     c = W.beltrami_cube(n=82)
     s = R.Solver(ctx, c, 2)
     b = torch.tensor(np.random.default_rng(7).standard_normal(c.n), device="cuda")
