@@ -60,9 +60,12 @@ def narrow_fraction(col, n, q):
 
 
 def bicgstab_iter_bytes(n, q, narrow=0.0):
-    """Algorithmic bytes of one FP64 BiCGSTAB iteration: two SpMVs and the fused
-    vector sweeps (p-update 4 vectors, v-dot 3, s-update 5, t-dots 3, x/r-update 8)."""
-    return 2 * spmv_bytes(n, q, narrow) + n * 8 * (4 + 2 + 5 + 2 + 8)
+    """Algorithmic bytes of one FP64 BiCGSTAB iteration: two SpMVs (their operand
+    read and result write included) and the vectors the four kernels move
+    besides: k_v reads r-hat (1); k_s reads r, v, r-hat, D^-1 and writes s,
+    s-hat (6); k_t reads s, r-hat (2); k_x reads x, p-hat, s, t, v, D^-1 and
+    writes x, r, p-hat (9)."""
+    return 2 * spmv_bytes(n, q, narrow) + n * 8 * (1 + 6 + 2 + 9)
 
 
 # the benchmark step's workload: the 2D Taylor-Green vortex on ~250k Poisson-disk

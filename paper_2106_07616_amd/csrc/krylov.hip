@@ -484,11 +484,13 @@ __global__ __launch_bounds__(kKB) void k_t(int64_t n, int64_t np, int q, ColIdx 
 
 // KX: omega = t.s / t.t; x += alpha p-hat + omega s-hat; r = s - omega t;
 // rho' = r-hat.s - omega r-hat.t; restart (r-hat = r) when rho' has vanished
-// relative to s.s; p-hat = D^-1 r + beta (p-hat - omega D^-1 v); partial r.r
+// relative to s.s; p-hat = D^-1 r + beta (p-hat - omega D^-1 v); partial r.r.
+// s-hat is formed again from s and D^-1, as KS formed it (the same rounded
+// product), which saves reading it back.
 template <typename T, int NRHS>
 __global__ __launch_bounds__(kKB) void k_x(int64_t n, int64_t np, const T *__restrict__ dinv, T *__restrict__ x,
                                            int64_t xs, T *__restrict__ ph, const T *__restrict__ s,
-                                           const T *__restrict__ sh, const T *__restrict__ t,
+                                           const T *__restrict__ t,
                                            const T *__restrict__ v, T *__restrict__ r, T *__restrict__ rh,
                                            double *__restrict__ part, KState *__restrict__ st, int nblk, int phase)
 {
@@ -539,8 +541,10 @@ __global__ __launch_bounds__(kKB) void k_x(int64_t n, int64_t np, const T *__res
         for (int k = 0; k < NRHS; ++k) {
             if (!act[k]) continue;
             const T phi = ph[k * np + i];
-            x[k * xs + i] = (T)((double)x[k * xs + i] + alpha[k] * (double)phi + omega[k] * (double)sh[k * np + i]);
-            const T ri = (T)((double)s[k * np + i] - omega[k] * (double)t[k * np + i]);
+            const T si = s[k * np + i];
+            const T shi = di * si;
+            x[k * xs + i] = (T)((double)x[k * xs + i] + alpha[k] * (double)phi + omega[k] * (double)shi);
+            const T ri = (T)((double)si - omega[k] * (double)t[k * np + i]);
             r[k * np + i] = ri;
             if (restart[k]) rh[k * np + i] = ri;
             const T pn = (beta[k] == 0.0) ? (T)(di * ri)
@@ -746,7 +750,7 @@ int bicgstab_t(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const T *val, const
             hipLaunchKernelGGL((k_s<T, NRHS>), g, bl, 0, s, n, np, dinv, r, rh, v, sv, sh, w.part, w.st, nblk, ++phase);
             hipLaunchKernelGGL(kt, g, bl, 0, s, n, np, q, col, val, x, xs, ph, sv, sh, rh, t, w.part,
                                w.st, nblk, tol2, ++phase);
-            hipLaunchKernelGGL((k_x<T, NRHS>), g, bl, 0, s, n, np, dinv, x, xs, ph, sv, sh, t, v, r, rh, w.part, w.st,
+            hipLaunchKernelGGL((k_x<T, NRHS>), g, bl, 0, s, n, np, dinv, x, xs, ph, sv, t, v, r, rh, w.part, w.st,
                                nblk, ++phase);
         }
         it += std::max(todo, 0);
@@ -1496,7 +1500,7 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const
                 hipLaunchKernelGGL(kbj_x<T>, g, bl, 0, s, n, np, binv, d, pv, ph, sv, sh, t, v, r, rh, w.part, w.st,
                                    nblk, ++phase);
             else
-                hipLaunchKernelGGL((k_x<T, NRHS>), g, bl, 0, s, n, np, dinv, d, np, ph, sv, sh, t, v, r, rh, w.part,
+                hipLaunchKernelGGL((k_x<T, NRHS>), g, bl, 0, s, n, np, dinv, d, np, ph, sv, t, v, r, rh, w.part,
                                    w.st, nblk, ++phase);
         }
         it += todo;
