@@ -704,20 +704,50 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
         /* momentum solves, one per velocity component, started from u^r */
         for (int e = 0; e < dim; ++e) {
             int its = 0;
-            /* symmetry points: u_e = 0 where e is the plane's normal axis,
-             * N . grad u_e = 0 otherwise (right-hand side 0 on both) */
+            /* symmetry points (Sec. 3.1: no flow through the plane, no normal
+             * derivative of the tangential velocity). With the plane's unit
+             * normal n, component s (largest |n_s|, lowest index on ties)
+             * takes u . n = 0 as n_s u_s = -sum_{d != s} n_d u_d; every other
+             * component a takes the tangent t_a = e_a - n_a n, i.e.
+             * (1 - n_a^2) N.grad u_a = sum_{d != a} n_a n_d N.grad u_d. The
+             * other components enter at the outer iterate u^r, so both hold
+             * once the outer iteration has converged. A normal along an axis
+             * gives u_s = 0 and N.grad u_a = 0, right-hand sides 0. */
             for (int64_t i = 0; i < n; ++i) {
                 if (c->kind[i] != 4) continue;
-                const int normal_axis = fabs(c->normal[i * dim + e]) == 1.0;
+                const double *nv = c->normal + i * dim;
+                int sc = 0;
+                for (int d = 1; d < dim; ++d)
+                    if (fabs(nv[d]) > fabs(nv[sc])) sc = d;
+                const int axis = fabs(nv[sc]) == 1.0;
+                const double scale = (e == sc) ? (axis ? 1.0 : nv[sc]) : (axis ? 1.0 : 1.0 - nv[e] * nv[e]);
                 for (int a = 0; a < q; ++a) {
                     double v = 0.0;
-                    if (normal_axis) {
-                        v = (c->col[i * q + a] == i) ? 1.0 : 0.0;
+                    if (e == sc) {
+                        v = (c->col[i * q + a] == i) ? scale : 0.0;
                     } else {
-                        for (int d = 0; d < dim; ++d) v = v + c->normal[i * dim + d] * c->val[d * nnz + i * q + a];
+                        for (int d = 0; d < dim; ++d) v = v + nv[d] * c->val[d * nnz + i * q + a];
+                        v = scale * v;
                     }
                     mval[i * q + a] = v;
                 }
+                double r = 0.0;
+                if (!axis && e == sc) {
+                    for (int d = 0; d < dim; ++d)
+                        if (d != sc) r = r - nv[d] * ur[d * n + i];
+                } else if (!axis) {
+                    for (int d = 0; d < dim; ++d) {
+                        if (d == e) continue;
+                        double g = 0.0;   /* (N . grad u_d)(x_i) at the iterate */
+                        for (int a = 0; a < q; ++a) {
+                            double w = 0.0;
+                            for (int cc = 0; cc < dim; ++cc) w = w + nv[cc] * c->val[cc * nnz + i * q + a];
+                            g = g + w * ur[d * n + c->col[i * q + a]];
+                        }
+                        r = r + nv[e] * nv[d] * g;
+                    }
+                }
+                bm[e * n + i] = r;
             }
             memcpy(ut + e * n, ur + e * n, sizeof(double) * n);
             int s = orc_bicgstab(n, q, c->col, mval, bm + e * n, ut + e * n, c->tol_krylov, c->max_krylov, &its, NULL);

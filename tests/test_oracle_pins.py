@@ -824,3 +824,37 @@ def test_cylinder_force_periodic_cell(orc):
         -_poly(g, _CUBIC[:6], X0, Y0, 0, 1) + 2 * mu * _poly(b, _CUBIC, X0, Y0, 0, 2)
         + mu * (_poly(a, _CUBIC, X0, Y0, 1, 1) + _poly(b, _CUBIC, X0, Y0, 2, 0))])
     np.testing.assert_allclose(F, math.pi * r * r * div, rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_inclined_symmetry_plane_keeps_the_stagnation_flow(orc, k):
+    """The stagnation-flow square turned by 0.5 rad: its symmetry line is off
+    the axes, so both velocity components are nonzero there and the two
+    conditions (u . n = 0, no normal derivative of the tangential velocity)
+    couple them. One BDF2 step from the exact (quadratic) flow returns it to
+    solver accuracy; u_bc on the symmetry points is garbage and unread."""
+    c = W.rotated(W.symmetric_square(), 0.5)
+    ops = orc.build_operators(c, k)
+    vel, p = W.flow_fields(c)
+    sym = c.kind == W.SYMMETRY
+    assert (np.abs(vel[:, sym]) > 1e-3).all()
+    ubc = np.where(sym[None, :], 55.0, vel)
+    u1, _, p1, st = orc.simple_step(ops, vel, vel, p, ubc, 1.0, c.meta["nu"], 0.05, alpha=orc.BDF2,
+                                    tol_outer=1e-13, tol_krylov=1e-14, max_outer=3, max_krylov=20000)
+    assert np.abs(u1 - vel).max() <= 1e-10, np.abs(u1 - vel).max()
+    assert np.abs(p1 - p).max() <= 1e-9, np.abs(p1 - p).max()
+
+
+def test_inclined_symmetry_strip_keeps_kovasznay_flow(orc):
+    """Kovasznay flow between its symmetry lines, the strip turned by 0.3 rad:
+    from the exact state one outer iteration moves the velocity only by the
+    discretization error, which shrinks with h (as on the unturned strip)."""
+    changes = []
+    for nx, ny in ((20, 5), (40, 10)):
+        c = W.rotated(W.kovasznay_strip(nx=nx, ny=ny), 0.3)
+        ops = orc.build_operators(c, 3)
+        vel, p = W.flow_fields(c)
+        u1, _, _, st = orc.simple_step(ops, vel, vel, p, vel, 1.0, 1.0 / 40, 0.01, alpha=orc.BDF2,
+                                       tol_outer=0.0, tol_krylov=1e-12, max_outer=1, max_krylov=20000)
+        changes.append(np.abs(u1 - vel).mean())
+    assert changes[1] < changes[0] / 2 and changes[1] < 2e-3, changes

@@ -124,7 +124,17 @@ def poiseuille(x, y, U=1.0, mu=0.01):
 
 
 def flow_fields(cloud: Cloud, t: float = 0.0):
-    """Exact (velocity[dim, n], pressure[n]) of the cloud's flow at time t."""
+    """Exact (velocity[dim, n], pressure[n]) of the cloud's flow at time t. A
+    rotated cloud (rotated()) carries the rotated flow: R u(R^T x), p(R^T x)."""
+    ang = cloud.meta.get("rotation")
+    if ang is not None:
+        c, s = np.cos(ang), np.sin(ang)
+        rot = np.array([[c, -s], [s, c]])
+        meta = {k: v for k, v in cloud.meta.items() if k != "rotation"}
+        base = Cloud(dim=2, xyz=cloud.xyz @ rot, kind=cloud.kind, normal=cloud.normal @ rot, pin=cloud.pin,
+                     name=cloud.name, h=cloud.h, meta=meta, period=cloud.period)
+        vel, p = flow_fields(base, t)
+        return np.ascontiguousarray(rot @ vel), p
     x = cloud.xyz
     flow = cloud.meta.get("flow")
     if flow == "kovasznay":
@@ -617,6 +627,21 @@ def periodic_cylinder_cell(nx: int = 48, radius: float = 0.2, seed: int = 31, ji
     return _finish(2, xyz, kind, normal, f"periodic_cylinder_{len(xyz)}", h,
                    {"seed": seed, "holes": [(0.5, 0.5, float(radius))]}, centre=(0.0, 0.0), boundary_kind=None,
                    period=(1.0, 1.0, 0.0))
+
+
+def rotated(cloud: Cloud, angle: float) -> Cloud:
+    """A 2D cloud turned by `angle` (radians) about the origin: coordinates and
+    normals rotated, kinds kept, the pressure pin moved with its point. Its
+    symmetry planes then lie off the coordinate axes, and flow_fields gives
+    the rotated flow."""
+    c, s = np.cos(angle), np.sin(angle)
+    rot = np.array([[c, -s], [s, c]])
+    xyz = cloud.xyz @ rot.T
+    normal = cloud.normal @ rot.T
+    centre = tuple(xyz[cloud.pin]) if cloud.pin >= 0 else (0.0, 0.0)
+    meta = dict(cloud.meta)
+    meta["rotation"] = float(angle)
+    return _finish(2, xyz, cloud.kind, normal, f"{cloud.name}_rot", cloud.h, meta, centre=centre, boundary_kind=None)
 
 
 def scattered_square(nx: int, seed: int = 7, jitter: float = 0.2, lo: float = 0.0,
