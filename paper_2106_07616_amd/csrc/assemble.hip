@@ -329,8 +329,8 @@ int assemble_ops(rbffd_ctx *ctx, const rbffd_cloud *cloud, int q, int k, int phs
     RB_HIP(hipMemcpyAsync(ops->kind, cloud->kind, n, hipMemcpyDeviceToDevice, s));
     RB_HIP(hipMemcpyAsync(ops->normal, cloud->normal, sizeof(double) * n * dim, hipMemcpyDeviceToDevice, s));
     {
-        // symmetry points: count them, and check that each normal is a
-        // coordinate unit vector (their rows differ per velocity component)
+        // symmetry points: count them, and check that each normal has unit
+        // length (their rows differ per velocity component)
         std::vector<uint8_t> hk((size_t)n);
         RB_HIP(hipMemcpyAsync(hk.data(), cloud->kind, (size_t)n, hipMemcpyDeviceToHost, s));
         RB_HIP(hipStreamSynchronize(s));
@@ -343,15 +343,11 @@ int assemble_ops(rbffd_ctx *ctx, const rbffd_cloud *cloud, int q, int k, int phs
             RB_HIP(hipStreamSynchronize(s));
             for (int64_t i = 0; i < n; ++i) {
                 if (hk[i] != RBFFD_SYMMETRY) continue;
-                int ones = 0, zeros = 0;
-                for (int d = 0; d < dim; ++d) {
-                    const double a = std::fabs(hn[i * dim + d]);
-                    ones += (a == 1.0);
-                    zeros += (a == 0.0);
-                }
-                if (ones != 1 || zeros != dim - 1)
+                double len2 = 0.0;
+                for (int d = 0; d < dim; ++d) len2 += hn[i * dim + d] * hn[i * dim + d];
+                if (!(std::fabs(len2 - 1.0) <= 1e-12))
                     return fail(RBFFD_E_ARG, "symmetry point " + std::to_string(i) +
-                                                 ": the normal is not a coordinate unit vector");
+                                                 ": the normal is not a unit vector");
             }
         }
     }

@@ -127,6 +127,24 @@ __global__ __launch_bounds__(kBlock) void k_momentum(int64_t n, int q, const int
 // Symmetry rows of the momentum matrix for velocity component e (Sec. 3.1):
 // u_e = 0 where e is the normal axis of the point's plane, N . grad u_e = 0
 // otherwise. The right-hand side stays 0 on both.
+// The component that carries u . n = 0 at a symmetry point: the largest |n_s|,
+// the lowest index on ties.
+template <int DIM>
+__device__ inline int sym_component(const double *nv)
+{
+    int sc = 0;
+#pragma unroll
+    for (int d = 1; d < DIM; ++d)
+        if (fabs(nv[d]) > fabs(nv[sc])) sc = d;
+    return sc;
+}
+
+// Momentum rows of component e at symmetry points (Sec. 3.1: no flow through
+// the plane, no normal derivative of the tangential velocity). With the unit
+// normal n, component s takes u . n = 0 as the row n_s u_s; every other
+// component a takes the tangent t_a = e_a - n_a n as the row
+// (1 - n_a^2) N.grad u_a. A normal along an axis gives u_s = 0 and N.grad u_a
+// = 0 (unit scale). The other components enter the right-hand side (k_sym_rhs).
 template <int DIM>
 __global__ void k_sym_rows(int64_t n, int q, const int32_t *__restrict__ col, const double *__restrict__ val,
                            int64_t vs, const uint8_t *__restrict__ kind, const double *__restrict__ normal, int e,
@@ -135,21 +153,60 @@ __global__ void k_sym_rows(int64_t n, int q, const int32_t *__restrict__ col, co
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n || kind[i] != RBFFD_SYMMETRY) return;
     const int64_t base = ((i >> 6) * (int64_t)q) * 64 + (i & 63);
-    const bool normal_axis = fabs(normal[i * DIM + e]) == 1.0;
+    const double *nv = normal + i * DIM;
+    const int sc = sym_component<DIM>(nv);
+    const bool axis = fabs(nv[sc]) == 1.0;
+    const double scale = (e == sc) ? (axis ? 1.0 : nv[sc]) : (axis ? 1.0 : 1.0 - nv[e] * nv[e]);
     double diag = 0.0;
     for (int a = 0; a < q; ++a) {
         const int64_t slot = base + (int64_t)a * 64;
         double v;
-        if (normal_axis) {
-            v = (col[slot] == i) ? 1.0 : 0.0;
+        if (e == sc) {
+            v = (col[slot] == i) ? scale : 0.0;
         } else {
             v = 0.0;
-            for (int d = 0; d < DIM; ++d) v = fma(normal[i * DIM + d], val[d * vs + slot], v);
+            for (int d = 0; d < DIM; ++d) v = fma(nv[d], val[d * vs + slot], v);
+            v = scale * v;
         }
         mval[slot] = v;
         if (col[slot] == i) diag += v;
     }
     mdinv[i] = (diag != 0.0) ? 1.0 / diag : 1.0;
+}
+
+// Right-hand side of component e at symmetry points with a normal off the
+// axes: -sum_{d != s} n_d u_d for the normal component s, and
+// sum_{d != e} n_e n_d (N.grad u_d) for a tangential one, the other
+// components at the outer iterate ur [DIM][n]. Axis normals keep 0.
+template <int DIM>
+__global__ void k_sym_rhs(int64_t n, int q, const int32_t *__restrict__ col, const double *__restrict__ val,
+                          int64_t vs, const uint8_t *__restrict__ kind, const double *__restrict__ normal,
+                          const double *__restrict__ ur, int e, double *__restrict__ b)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n || kind[i] != RBFFD_SYMMETRY) return;
+    const double *nv = normal + i * DIM;
+    const int sc = sym_component<DIM>(nv);
+    if (fabs(nv[sc]) == 1.0) return;
+    double r = 0.0;
+    if (e == sc) {
+        for (int d = 0; d < DIM; ++d)
+            if (d != sc) r = r - nv[d] * ur[d * n + i];
+    } else {
+        const int64_t base = ((i >> 6) * (int64_t)q) * 64 + (i & 63);
+        for (int d = 0; d < DIM; ++d) {
+            if (d == e) continue;
+            double g = 0.0;   // (N . grad u_d)(x_i) at the iterate
+            for (int a = 0; a < q; ++a) {
+                const int64_t slot = base + (int64_t)a * 64;
+                double w = 0.0;
+                for (int c = 0; c < DIM; ++c) w = fma(nv[c], val[c * vs + slot], w);
+                g = fma(w, ur[d * n + col[slot]], g);
+            }
+            r = r + nv[e] * nv[d] * g;
+        }
+    }
+    b[i] = r;
 }
 
 // f_i = (rho a1 / dt) sum_e (D_e u~_e)_i on interior rows other than the pin; 0 elsewhere
@@ -410,12 +467,17 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
         const int nrhs = ops->n_symmetry > 0 ? 1 : dim;
         for (int g = 0; g < groups; ++g) {
             if (ops->n_symmetry > 0) {
-                if (dim == 2)
+                if (dim == 2) {
                     hipLaunchKernelGGL(k_sym_rows<2>, dim3(gn), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs,
                                        ops->kind, ops->normal, g, ops->mval, ops->mdinv);
-                else
+                    hipLaunchKernelGGL(k_sym_rhs<2>, dim3(gn), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs,
+                                       ops->kind, ops->normal, B.ur, g, B.bm + (int64_t)g * n);
+                } else {
                     hipLaunchKernelGGL(k_sym_rows<3>, dim3(gn), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs,
                                        ops->kind, ops->normal, g, ops->mval, ops->mdinv);
+                    hipLaunchKernelGGL(k_sym_rhs<3>, dim3(gn), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs,
+                                       ops->kind, ops->normal, B.ur, g, B.bm + (int64_t)g * n);
+                }
                 RB_HIP(hipGetLastError());
             }
             const double *bg = B.bm + (int64_t)g * n;

@@ -58,6 +58,8 @@ CLOUDS = {
     "channel_outlet_k3": (lambda: W.poiseuille_channel(), 3),
     # Kovasznay flow between its symmetry lines (symmetry points, per-component momentum rows)
     "kovasznay_strip_k3": (lambda: W.kovasznay_strip(), 3),
+    # the same strip turned by 0.3 rad: symmetry lines off the axes
+    "kovasznay_strip_rot_k3": (lambda: W.rotated(W.kovasznay_strip(), 0.3), 3),
     # the fully periodic Taylor-Green square (clouds across the seams, no boundary)
     "tg_periodic_k4": (lambda: W.taylor_green_periodic(), 4),
 }
@@ -512,12 +514,14 @@ def test_poiseuille_outlet_fixed_point(ctx, orc, k):
     assert np.abs(ug - uo).max() <= 1e-10 and np.abs(pgn - po).max() <= 1e-10 * np.abs(p).max()
 
 
+@pytest.mark.parametrize("angle", [0.0, 0.5])
 @pytest.mark.parametrize("k", [2, 3])
-def test_symmetry_plane_fixed_point(ctx, orc, k):
+def test_symmetry_plane_fixed_point(ctx, orc, k, angle):
     """The stagnation flow with its symmetry line y = 0 is a fixed point of the
-    step (quadratic fields), on the GPU as in the oracle; u_bc on the symmetry
-    points is garbage and must not be read."""
-    c = W.symmetric_square()
+    step (quadratic fields), on the GPU as in the oracle, also with the square
+    turned by 0.5 rad (the line off the axes, both components coupled there);
+    u_bc on the symmetry points is garbage and must not be read."""
+    c = W.symmetric_square() if angle == 0.0 else W.rotated(W.symmetric_square(), angle)
     s = R.Solver(ctx, c, k)
     ops_o = orc.build_operators(c, k)
     vel, p = W.flow_fields(c)
@@ -530,7 +534,7 @@ def test_symmetry_plane_fixed_point(ctx, orc, k):
     st = R.simple_step(ctx, s.ops, u, torch.tensor(vel, device="cuda"), pg, torch.tensor(ubc, device="cuda"), 1.0,
                        c.meta["nu"], 0.05, R.BDF2, **kw)
     ug, pgn = u.cpu().numpy(), pg.cpu().numpy()
-    print(f"[symmetry] k={k}: |u - exact| {np.abs(ug - vel).max():.1e} |p - exact| {np.abs(pgn - p).max():.1e} "
+    print(f"[symmetry] k={k} angle={angle}: |u - exact| {np.abs(ug - vel).max():.1e} |p - exact| {np.abs(pgn - p).max():.1e} "
           f"|u - oracle| {np.abs(ug - uo).max():.1e} momentum iterations {st['krylov_mom']}/{sto['krylov_mom']}",
           flush=True)
     assert np.abs(ug - vel).max() <= 1e-10
@@ -538,12 +542,16 @@ def test_symmetry_plane_fixed_point(ctx, orc, k):
     assert np.abs(ug - uo).max() <= 1e-10 and np.abs(pgn - po).max() <= 1e-9
 
 
-def test_symmetry_normal_must_be_a_coordinate_axis(ctx):
+def test_symmetry_normal_must_be_a_unit_vector(ctx):
+    """Symmetry normals may point anywhere but must have unit length."""
     c = W.kovasznay_strip(nx=10, ny=4)
     sym = np.where(c.kind == W.SYMMETRY)[0]
     c.normal[sym[0]] = [0.6, -0.8]
     dc = R.DeviceCloud.from_numpy(c)
     nbr, w, _ = R.rbffd_build_stencils(ctx, dc, 2)
+    R.rbffd_assemble(ctx, dc, nbr, w, 2).free()
+    c.normal[sym[0]] = [0.6, -0.7]
+    dc = R.DeviceCloud.from_numpy(c)
     with pytest.raises(R.RbffdError) as e:
         R.rbffd_assemble(ctx, dc, nbr, w, 2)
     assert e.value.code == -1
