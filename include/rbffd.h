@@ -79,12 +79,13 @@ extern "C" {
 #define RBFFD_OUTLET 3          /* outlet with prescribed pressure (p' = 0, pressure from
                                    p_bc) and zero normal derivative of every velocity
                                    component (Sec. 3.1); needs the outward normal        */
-#define RBFFD_SYMMETRY 4        /* symmetry plane normal to a coordinate axis (Sec. 3.1):
-                                   zero normal velocity, zero normal derivative of the
-                                   tangential velocity; homogeneous Neumann p' and the
-                                   pressure from the normal momentum equation, as at
-                                   velocity-Dirichlet points. The normal must be a
-                                   coordinate unit vector                                */
+#define RBFFD_SYMMETRY 4        /* symmetry plane (Sec. 3.1), at any angle: zero normal
+                                   velocity, zero normal derivative of the tangential
+                                   velocity; homogeneous Neumann p' and the pressure
+                                   from the normal momentum equation, as at
+                                   velocity-Dirichlet points. The normal must have unit
+                                   length; off the axes the components' conditions are
+                                   coupled through the outer iteration               */
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *rbffd_last_error(void);
@@ -154,7 +155,7 @@ typedef struct rbffd_ops rbffd_ops;
  * row at interior points, N . grad at velocity-Dirichlet and symmetry points
  * (homogeneous Neumann), the identity row (p' = 0) at prescribed-pressure and
  * outlet points and at the pin. RBFFD_E_ARG if a symmetry point's normal is
- * not a coordinate unit vector. `precision` selects
+ * not of unit length (within 1e-12). `precision` selects
  * whether FP32 copies for the mixed-precision modes are made (any value other
  * than RBFFD_FP64). The cloud arrays are copied;
  * nbr and w may be freed afterwards. *out is library-owned: free it with
