@@ -542,6 +542,36 @@ def test_symmetry_plane_fixed_point(ctx, orc, k, angle):
     assert np.abs(ug - uo).max() <= 1e-10 and np.abs(pgn - po).max() <= 1e-9
 
 
+@pytest.mark.parametrize("angle", [0.0, 0.4])
+def test_symmetry_plane_3d_fixed_point(ctx, orc, angle):
+    """The 3D stagnation flow with its symmetry plane z = 0 (prescribed pressure
+    on the other faces), also with the cube turned by 0.4 rad about (1, 1, 0)
+    (three nonzero normal components): a fixed point of the step on the GPU as
+    in the oracle."""
+    c = W.symmetric_cube()
+    if angle:
+        c = W.rotated(c, angle, axis=(1.0, 1.0, 0.0))
+    k = 2
+    s = R.Solver(ctx, c, k)
+    ops_o = orc.build_operators(c, k)
+    vel, p = W.flow_fields(c)
+    sym = c.kind == W.SYMMETRY
+    ubc = np.where(sym[None, :], 55.0, vel)
+    kw = dict(tol_outer=1e-13, tol_krylov=1e-14, max_outer=3, max_krylov=20000)
+    uo, _, po, sto = orc.simple_step(ops_o, vel, vel, p, ubc, 1.0, c.meta["nu"], 0.05, alpha=orc.BDF2, p_bc=p, **kw)
+    u = torch.tensor(vel, device="cuda")
+    pg = torch.tensor(p, device="cuda")
+    st = R.simple_step(ctx, s.ops, u, torch.tensor(vel, device="cuda"), pg, torch.tensor(ubc, device="cuda"), 1.0,
+                       c.meta["nu"], 0.05, R.BDF2, p_bc=torch.tensor(p, device="cuda"), **kw)
+    assert sto["status"] == 0 and st["status"] == 0
+    ug, pgn = u.cpu().numpy(), pg.cpu().numpy()
+    print(f"[symmetry] 3D angle={angle}: |u - exact| {np.abs(ug - vel).max():.1e} |p - exact| "
+          f"{np.abs(pgn - p).max():.1e} |u - oracle| {np.abs(ug - uo).max():.1e}", flush=True)
+    assert np.abs(ug - vel).max() <= 1e-10
+    assert np.abs(pgn - p).max() <= 1e-9
+    assert np.abs(ug - uo).max() <= 1e-10 and np.abs(pgn - po).max() <= 1e-9
+
+
 def test_symmetry_normal_must_be_a_unit_vector(ctx):
     """Symmetry normals may point anywhere but must have unit length."""
     c = W.kovasznay_strip(nx=10, ny=4)

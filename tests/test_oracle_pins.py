@@ -858,3 +858,24 @@ def test_inclined_symmetry_strip_keeps_kovasznay_flow(orc):
                                        tol_outer=0.0, tol_krylov=1e-12, max_outer=1, max_krylov=20000)
         changes.append(np.abs(u1 - vel).mean())
     assert changes[1] < changes[0] / 2 and changes[1] < 2e-3, changes
+
+
+@pytest.mark.parametrize("angle", [0.0, 0.4])
+def test_symmetry_plane_3d_keeps_the_stagnation_flow(orc, angle):
+    """The 3D stagnation flow u = (x, y, -2z) with its symmetry plane z = 0,
+    also with the cube turned by 0.4 rad about (1, 1, 0): the plane's normal
+    then has three nonzero components, one normal and two tangential
+    conditions couple all three velocity components. One BDF2 step from the
+    exact (quadratic) flow returns it to solver accuracy."""
+    c = W.symmetric_cube()
+    if angle:
+        c = W.rotated(c, angle, axis=(1.0, 1.0, 0.0))
+    ops = orc.build_operators(c, 2)
+    vel, p = W.flow_fields(c)
+    sym = c.kind == W.SYMMETRY
+    ubc = np.where(sym[None, :], 55.0, vel)
+    u1, _, p1, st = orc.simple_step(ops, vel, vel, p, ubc, 1.0, c.meta["nu"], 0.05, alpha=orc.BDF2, p_bc=p,
+                                    tol_outer=1e-13, tol_krylov=1e-14, max_outer=3, max_krylov=20000)
+    assert st["status"] == 0
+    assert np.abs(u1 - vel).max() <= 1e-10, np.abs(u1 - vel).max()
+    assert np.abs(p1 - p).max() <= 1e-9, np.abs(p1 - p).max()

@@ -126,12 +126,10 @@ def poiseuille(x, y, U=1.0, mu=0.01):
 def flow_fields(cloud: Cloud, t: float = 0.0):
     """Exact (velocity[dim, n], pressure[n]) of the cloud's flow at time t. A
     rotated cloud (rotated()) carries the rotated flow: R u(R^T x), p(R^T x)."""
-    ang = cloud.meta.get("rotation")
-    if ang is not None:
-        c, s = np.cos(ang), np.sin(ang)
-        rot = np.array([[c, -s], [s, c]])
+    if cloud.meta.get("rotation") is not None:
+        rot = np.asarray(cloud.meta["rotation"], dtype=np.float64)
         meta = {k: v for k, v in cloud.meta.items() if k != "rotation"}
-        base = Cloud(dim=2, xyz=cloud.xyz @ rot, kind=cloud.kind, normal=cloud.normal @ rot, pin=cloud.pin,
+        base = Cloud(dim=cloud.dim, xyz=cloud.xyz @ rot, kind=cloud.kind, normal=cloud.normal @ rot, pin=cloud.pin,
                      name=cloud.name, h=cloud.h, meta=meta, period=cloud.period)
         vel, p = flow_fields(base, t)
         return np.ascontiguousarray(rot @ vel), p
@@ -629,19 +627,69 @@ def periodic_cylinder_cell(nx: int = 48, radius: float = 0.2, seed: int = 31, ji
                    period=(1.0, 1.0, 0.0))
 
 
-def rotated(cloud: Cloud, angle: float) -> Cloud:
-    """A 2D cloud turned by `angle` (radians) about the origin: coordinates and
+def rotated(cloud: Cloud, angle: float, axis=(0.0, 0.0, 1.0)) -> Cloud:
+    """A cloud turned by `angle` (radians) about the origin (2D) or about
+    `axis` through the origin (3D, Rodrigues' formula): coordinates and
     normals rotated, kinds kept, the pressure pin moved with its point. Its
     symmetry planes then lie off the coordinate axes, and flow_fields gives
     the rotated flow."""
     c, s = np.cos(angle), np.sin(angle)
-    rot = np.array([[c, -s], [s, c]])
+    if cloud.dim == 2:
+        rot = np.array([[c, -s], [s, c]])
+    else:
+        k = np.asarray(axis, dtype=np.float64) / np.linalg.norm(axis)
+        K = np.array([[0.0, -k[2], k[1]], [k[2], 0.0, -k[0]], [-k[1], k[0], 0.0]])
+        rot = np.eye(3) + s * K + (1.0 - c) * (K @ K)
     xyz = cloud.xyz @ rot.T
     normal = cloud.normal @ rot.T
-    centre = tuple(xyz[cloud.pin]) if cloud.pin >= 0 else (0.0, 0.0)
+    centre = tuple(xyz[cloud.pin]) if cloud.pin >= 0 else (0.0,) * cloud.dim
     meta = dict(cloud.meta)
-    meta["rotation"] = float(angle)
-    return _finish(2, xyz, cloud.kind, normal, f"{cloud.name}_rot", cloud.h, meta, centre=centre, boundary_kind=None)
+    meta["rotation"] = rot.tolist()
+    return _finish(cloud.dim, xyz, cloud.kind, normal, f"{cloud.name}_rot", cloud.h, meta, centre=centre,
+                   boundary_kind=None)
+
+
+def symmetric_cube(n: int = 7, seed: int = 37, jitter: float = 0.2, face_kind: int = PRESCRIBED_PRESSURE) -> Cloud:
+    """Unit cube for the 3D stagnation flow u = (x, y, -2z): a symmetry plane on
+    z = 0 (normal (0, 0, -1), its edges excluded) and points of `face_kind` on
+    the other five faces (edges included): by default prescribed pressure, so
+    that p' is fixed there and the step's pressure system stays well posed
+    when its right-hand side is rounding noise."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    g = (np.arange(n) + 0.5) * h
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    inter = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1) + rng.uniform(-jitter * h, jitter * h,
+                                                                              size=(n ** 3, 3))
+    f = np.linspace(0.0, 1.0, n + 1)
+    A, B = np.meshgrid(f, f, indexing="ij")
+    A, B = A.ravel(), B.ravel()
+    inner = (A > 0) & (A < 1) & (B > 0) & (B < 1)
+    sym = np.stack([A[inner], B[inner], np.zeros(inner.sum())], axis=1)
+    faces, fn = [], []
+    seen = set()
+    for ax in range(3):
+        for val in (0.0, 1.0):
+            if ax == 2 and val == 0.0:
+                continue
+            for a, b in zip(A, B):
+                pt = [a, b]
+                pt.insert(ax, val)
+                key = tuple(np.round(pt, 12))
+                if key in seen:   # edges and corners shared by two or three faces
+                    continue
+                seen.add(key)
+                faces.append(pt)
+                nv = [0.0, 0.0, 0.0]
+                nv[ax] = 1.0 if val == 1.0 else -1.0
+                fn.append(nv)
+    faces, fn = np.array(faces), np.array(fn)
+    xyz = np.concatenate([inter, sym, faces])
+    kind = np.concatenate([np.zeros(len(inter), np.uint8), np.full(len(sym), SYMMETRY, np.uint8),
+                           np.full(len(faces), face_kind, np.uint8)])
+    normal = np.concatenate([np.zeros_like(inter), np.tile([0.0, 0.0, -1.0], (len(sym), 1)), fn])
+    return _finish(3, xyz, kind, normal, f"symmetric_cube_{len(xyz)}", h, {"flow": "stagnation", "nu": 0.05},
+                   centre=(0.5, 0.5, 0.5), boundary_kind=None)
 
 
 def scattered_square(nx: int, seed: int = 7, jitter: float = 0.2, lo: float = 0.0,
