@@ -216,26 +216,34 @@ __device__ inline void write_partials(const double *v, double *const *parts)
         }
 }
 
+// Partials each thread loads per array: thread t holds entries t, t + kKB, ...
+constexpr int kPartPer = (kKMaxBlocks + kKB - 1) / kKB;
+
 // Sums of NV partial arrays (np entries each) in a fixed order, identical in
-// every block: all loads are issued before any add, then one block reduction.
+// every block, in two phases: the loads, then one block reduction. A kernel may
+// issue its own row loads between the two, so that waiting for the partials
+// does not also wait for those rows.
 template <int NV>
-__device__ inline void sum_partials_n(const double *const *parts, int np, double *out)
+__device__ inline void load_partials_n(const double *const *parts, int np, double (&ld)[NV][kPartPer])
 {
-    __shared__ double red[NV][kKB / 64];
-    constexpr int kPer = (kKMaxBlocks + kKB - 1) / kKB;
-    double ld[NV][kPer];
 #pragma unroll
-    for (int j = 0; j < kPer; ++j) {
+    for (int j = 0; j < kPartPer; ++j) {
         const int i = threadIdx.x + j * kKB;
 #pragma unroll
         for (int m = 0; m < NV; ++m) ld[m][j] = (i < np) ? parts[m][i] : 0.0;
     }
+}
+
+template <int NV>
+__device__ inline void reduce_partials_n(const double (&ld)[NV][kPartPer], double *out)
+{
+    __shared__ double red[NV][kKB / 64];
     double v[NV];
 #pragma unroll
     for (int m = 0; m < NV; ++m) {
         v[m] = 0.0;
 #pragma unroll
-        for (int j = 0; j < kPer; ++j) v[m] += ld[m][j];
+        for (int j = 0; j < kPartPer; ++j) v[m] += ld[m][j];
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1)
@@ -254,6 +262,14 @@ __device__ inline void sum_partials_n(const double *const *parts, int np, double
         for (int j = 0; j < kKB / 64; ++j) t += red[m][j];
         out[m] = t;
     }
+}
+
+template <int NV>
+__device__ inline void sum_partials_n(const double *const *parts, int np, double *out)
+{
+    double ld[NV][kPartPer];
+    load_partials_n<NV>(parts, np, ld);
+    reduce_partials_n<NV>(ld, out);
 }
 
 // r = b - A x, r-hat = r, p-hat = D^-1 r; partials r.r and b.b
@@ -370,13 +386,29 @@ __global__ __launch_bounds__(kKB) void k_s(int64_t n, int64_t np, const T *__res
                                            T *__restrict__ s, T *__restrict__ sh, double *__restrict__ part,
                                            KState *__restrict__ st, int nblk, int phase)
 {
-    double rvs[NRHS];
+    double ld[NRHS][kPartPer];
     {
         const double *ps[NRHS];
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) ps[k] = partial(part, P_RV, k);
-        sum_partials_n<NRHS>(ps, nblk, rvs);
+        load_partials_n<NRHS>(ps, nblk, ld);
     }
+    // the first row's operands, requested after the partials: the wait for the
+    // partials leaves them in flight through the reduction
+    const int64_t i0 = (int64_t)logical_block() * kKB + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kKB;
+    T d0 = (T)0, r0[NRHS], v0[NRHS], rh0[NRHS];
+    if (i0 < n) {
+        d0 = dinv[i0];
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            r0[k] = r[k * np + i0];
+            v0[k] = v[k * np + i0];
+            rh0[k] = rh[k * np + i0];
+        }
+    }
+    double rvs[NRHS];
+    reduce_partials_n<NRHS>(ld, rvs);
     if (all_done<NRHS>(st, phase)) return;
     bool act[NRHS];
     double alpha[NRHS];
@@ -400,16 +432,20 @@ __global__ __launch_bounds__(kKB) void k_s(int64_t n, int64_t np, const T *__res
     double acc[2 * NRHS];
 #pragma unroll
     for (int k = 0; k < 2 * NRHS; ++k) acc[k] = 0.0;
-    for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kKB) {
-        const T di = dinv[i];
+    for (int64_t i = i0; i < n; i += stride) {
+        const bool first = i == i0;
+        const T di = first ? d0 : dinv[i];
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
             if (!act[k]) continue;
-            const T si = (T)((double)r[k * np + i] - alpha[k] * (double)v[k * np + i]);
+            const T ri = first ? r0[k] : r[k * np + i];
+            const T vi = first ? v0[k] : v[k * np + i];
+            const T rhi = first ? rh0[k] : rh[k * np + i];
+            const T si = (T)((double)ri - alpha[k] * (double)vi);
             s[k * np + i] = si;
             sh[k * np + i] = di * si;
             acc[2 * k] += (double)si * (double)si;
-            acc[2 * k + 1] += (double)rh[k * np + i] * (double)si;
+            acc[2 * k + 1] += (double)rhi * (double)si;
         }
     }
     double *ps[2 * NRHS];
@@ -494,7 +530,7 @@ __global__ __launch_bounds__(kKB) void k_x(int64_t n, int64_t np, const T *__res
                                            const T *__restrict__ v, T *__restrict__ r, T *__restrict__ rh,
                                            double *__restrict__ part, KState *__restrict__ st, int nblk, int phase)
 {
-    double sums[5 * NRHS];
+    double ld[5 * NRHS][kPartPer];
     {
         const double *ps[5 * NRHS];
 #pragma unroll
@@ -505,8 +541,25 @@ __global__ __launch_bounds__(kKB) void k_x(int64_t n, int64_t np, const T *__res
             ps[5 * k + 3] = partial(part, P_RT, k);
             ps[5 * k + 4] = partial(part, P_SS, k);
         }
-        sum_partials_n<5 * NRHS>(ps, nblk, sums);
+        load_partials_n<5 * NRHS>(ps, nblk, ld);
     }
+    // the first row's operands, requested after the partials (as in k_s)
+    const int64_t i0 = (int64_t)logical_block() * kKB + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kKB;
+    T d0 = (T)0, x0[NRHS], ph0[NRHS], s0[NRHS], t0[NRHS], v0[NRHS];
+    if (i0 < n) {
+        d0 = dinv[i0];
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            x0[k] = x[k * xs + i0];
+            ph0[k] = ph[k * np + i0];
+            s0[k] = s[k * np + i0];
+            t0[k] = t[k * np + i0];
+            v0[k] = v[k * np + i0];
+        }
+    }
+    double sums[5 * NRHS];
+    reduce_partials_n<5 * NRHS>(ld, sums);
     if (all_done<NRHS>(st, phase)) return;
     bool act[NRHS], restart[NRHS];
     double alpha[NRHS], omega[NRHS], beta[NRHS];
@@ -535,20 +588,23 @@ __global__ __launch_bounds__(kKB) void k_x(int64_t n, int64_t np, const T *__res
     double srr[NRHS];
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) srr[k] = 0.0;
-    for (int64_t i = (int64_t)logical_block() * kKB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kKB) {
-        const T di = dinv[i];
+    for (int64_t i = i0; i < n; i += stride) {
+        const bool first = i == i0;
+        const T di = first ? d0 : dinv[i];
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
             if (!act[k]) continue;
-            const T phi = ph[k * np + i];
-            const T si = s[k * np + i];
+            const T phi = first ? ph0[k] : ph[k * np + i];
+            const T si = first ? s0[k] : s[k * np + i];
+            const T xi = first ? x0[k] : x[k * xs + i];
+            const T ti = first ? t0[k] : t[k * np + i];
             const T shi = di * si;
-            x[k * xs + i] = (T)((double)x[k * xs + i] + alpha[k] * (double)phi + omega[k] * (double)shi);
-            const T ri = (T)((double)si - omega[k] * (double)t[k * np + i]);
+            x[k * xs + i] = (T)((double)xi + alpha[k] * (double)phi + omega[k] * (double)shi);
+            const T ri = (T)((double)si - omega[k] * (double)ti);
             r[k * np + i] = ri;
             if (restart[k]) rh[k * np + i] = ri;
             const T pn = (beta[k] == 0.0) ? (T)(di * ri)
-                                          : (T)(di * ri + beta[k] * ((double)phi - omega[k] * (double)(di * v[k * np + i])));
+                                          : (T)(di * ri + beta[k] * ((double)phi - omega[k] * (double)(di * (first ? v0[k] : v[k * np + i]))));
             ph[k * np + i] = pn;
             srr[k] += (double)ri * (double)ri;
         }
