@@ -160,3 +160,43 @@ def test_fullsize_step_fixed_point(full, ctx):
     print(f"[full] {name}: stagnation step, outer {st['outer_iters']} status {st['status']} du {du:.1e} dp {dp:.1e}",
           flush=True)
     assert du <= 1e-8 and dp <= 1e-7
+
+
+def test_fullsize_post_processing(ctx, orc):
+    """The post-processing workload (bench.py --workload post): 1M query points
+    on the 252k-point square with one hole, k = 4. At 300 sampled queries the
+    oracle's clouds equal the GPU's bit for bit, its weights agree to 1e-10
+    row-relative and the sampled values to 1e-12; the cylinder force at 360
+    surface points agrees with the oracle's to 1e-10 of the traction scale."""
+    import math
+    c = W.holed_square(250_000, seed=5, n_holes=1)
+    cx, cy, rad = c.meta["holes"][0]
+    k, nq = 4, 1_000_000
+    cand = np.random.default_rng(6).uniform(0.0, 1.0, size=(2 * nq, 2))
+    pts = cand[np.hypot(cand[:, 0] - cx, cand[:, 1] - cy) > rad][:nq]
+    u, v, p = W.kovasznay(c.xyz[:, 0], c.xyz[:, 1], c.meta["Re"])
+    f = np.stack([u, v, p])
+    print(f"[full] post: n={c.n}, {nq} queries", flush=True)
+    dc = R.DeviceCloud.from_numpy(c, "cuda")
+    out, nbr, w = R.rbffd_interpolate(ctx, dc, k, torch.tensor(pts, device="cuda"), torch.tensor(f, device="cuda"),
+                                      return_stencils=True)
+    sel = np.unique(np.concatenate([np.random.default_rng(12).choice(nq, 296, replace=False),
+                                    np.arange(2), np.arange(nq - 2, nq)]))
+    idx = torch.tensor(sel, device="cuda")
+    nbr_g, w_g, out_g = nbr[idx].cpu().numpy(), w[idx].cpu().numpy(), out[:, idx].cpu().numpy()
+    del out, nbr, w
+    vo, nbr_o, w_o = orc.interpolate(c.xyz, k, pts[sel], f)
+    ew = float((np.abs(w_g - w_o).max(1) / np.abs(w_o).max(1)).max())
+    ev = float(np.abs(out_g - vo).max())
+    print(f"[full] post: {len(sel)} sampled queries, weights {ew:.1e}, values {ev:.1e}", flush=True)
+    np.testing.assert_array_equal(nbr_g, nbr_o)
+    assert ew <= 1e-10 and ev <= 1e-12
+    s = R.Solver(ctx, dc, k)
+    mu = 1.0 / c.meta["Re"]
+    F, tr = s.cylinder_forces(torch.tensor(np.stack([u, v]), device="cuda"), torch.tensor(p, device="cuda"),
+                              (cx, cy), 2 * rad, mu, 360, return_traction=True)
+    Fo, tro = orc.cylinder_forces(orc.build_operators(c, k), np.stack([u, v]), p, (cx, cy), 2 * rad, mu, 360)
+    scale = np.abs(tro).max()
+    print(f"[full] post: F gpu {F} oracle {Fo}; traction diff {np.abs(tr.cpu().numpy() - tro).max() / scale:.1e}",
+          flush=True)
+    assert np.abs(np.array(F) - Fo).max() <= 1e-10 * scale * 2 * math.pi * rad
