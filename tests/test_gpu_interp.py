@@ -158,3 +158,20 @@ def test_periodic_interpolation_matches_oracle(ctx, orc, k):
     print(f"[interp] periodic k={k}: weights {ew:.1e}, values {ev:.1e}, error vs the exact field {ex:.1e}", flush=True)
     np.testing.assert_array_equal(nbr, nbr_o)
     assert ew <= 1e-10 and ev <= 1e-12
+
+
+def test_periodic_interpolation_period_too_small(ctx, orc):
+    """A period too small for the cloud size (36 points, q = 34): a query's
+    cloud would hold two images of one point. The library refuses with
+    RBFFD_E_ARG, as the oracle refuses; q = 32 is accepted by both."""
+    c = W.taylor_green_periodic(nx=6)
+    pts = np.array([[0.1, 0.1], [3.0, 3.0]])
+    with pytest.raises(ValueError):
+        orc.interpolate(c.xyz, 3, pts, [np.ones(c.n)], q=34, period=c.period)
+    dc = R.DeviceCloud.from_numpy(c, "cuda")
+    ones = torch.ones((1, c.n), dtype=torch.float64, device="cuda")
+    with pytest.raises(R.RbffdError) as e:
+        R.rbffd_interpolate(ctx, dc, 3, torch.tensor(pts, device="cuda"), ones, q=34)
+    assert e.value.code == -1
+    out = R.rbffd_interpolate(ctx, dc, 3, torch.tensor(pts, device="cuda"), ones, q=32)
+    np.testing.assert_allclose(out.cpu().numpy(), 1.0, rtol=0, atol=1e-12)
