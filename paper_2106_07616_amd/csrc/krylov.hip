@@ -179,6 +179,16 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int64_t n, int q, ColIdx c
 }
 
 // ---- BiCGSTAB ---------------------------------------------------------------
+// The state records, read at a kernel's start: their loads then overlap the
+// partial loads. A field block 0 writes during a launch is read by other
+// blocks only in later launches, so the early copy is the current value.
+template <int NRHS>
+__device__ inline void load_states(const KState *st, KState *out)
+{
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) out[r] = st[r];
+}
+
 template <int NRHS>
 __device__ inline bool all_done(const KState *st, int phase)
 {
@@ -317,6 +327,8 @@ __global__ __launch_bounds__(kKB) void k_v(int64_t n, int64_t np, int q, ColIdx 
                                            T *__restrict__ x, int64_t xs, double *__restrict__ part,
                                            KState *__restrict__ st, int nblk, double tol2, int check_only, int phase)
 {
+    KState st0[NRHS];
+    load_states<NRHS>(st, st0);
     double sums[3 * NRHS];
     {
         const double *ps[3 * NRHS];
@@ -328,11 +340,11 @@ __global__ __launch_bounds__(kKB) void k_v(int64_t n, int64_t np, int q, ColIdx 
         }
         sum_partials_n<3 * NRHS>(ps, nblk, sums);
     }
-    if (all_done<NRHS>(st, phase)) return;
+    if (all_done<NRHS>(st0, phase)) return;
     bool act[NRHS], zero[NRHS];
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) {
-        const KState s = st[k];
+        const KState s = st0[k];
         const double rr = sums[3 * k], bb = sums[3 * k + 1];
         act[k] = !finished_before(s, phase);
         zero[k] = act[k] && bb == 0.0;
@@ -386,6 +398,8 @@ __global__ __launch_bounds__(kKB) void k_s(int64_t n, int64_t np, const T *__res
                                            T *__restrict__ s, T *__restrict__ sh, double *__restrict__ part,
                                            KState *__restrict__ st, int nblk, int phase)
 {
+    KState st0[NRHS];
+    load_states<NRHS>(st, st0);
     double ld[NRHS][kPartPer];
     {
         const double *ps[NRHS];
@@ -409,12 +423,12 @@ __global__ __launch_bounds__(kKB) void k_s(int64_t n, int64_t np, const T *__res
     }
     double rvs[NRHS];
     reduce_partials_n<NRHS>(ld, rvs);
-    if (all_done<NRHS>(st, phase)) return;
+    if (all_done<NRHS>(st0, phase)) return;
     bool act[NRHS];
     double alpha[NRHS];
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) {
-        const KState stk = st[k];
+        const KState stk = st0[k];
         act[k] = !finished_before(stk, phase);
         const double rv = rvs[k];
         alpha[k] = (rv != 0.0) ? stk.rho / rv : 0.0;
@@ -466,6 +480,8 @@ __global__ __launch_bounds__(kKB) void k_t(int64_t n, int64_t np, int q, ColIdx 
                                            const T *__restrict__ rh, T *__restrict__ t, double *__restrict__ part,
                                            KState *__restrict__ st, int nblk, double tol2, int phase)
 {
+    KState st0[NRHS];
+    load_states<NRHS>(st, st0);
     double ss[NRHS];
     {
         const double *ps[NRHS];
@@ -473,12 +489,12 @@ __global__ __launch_bounds__(kKB) void k_t(int64_t n, int64_t np, int q, ColIdx 
         for (int k = 0; k < NRHS; ++k) ps[k] = partial(part, P_SS, k);
         sum_partials_n<NRHS>(ps, nblk, ss);
     }
-    if (all_done<NRHS>(st, phase)) return;
+    if (all_done<NRHS>(st0, phase)) return;
     bool act[NRHS], half[NRHS], sp[NRHS];
     double alpha[NRHS];
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) {
-        const KState stk = st[k];
+        const KState stk = st0[k];
         act[k] = !finished_before(stk, phase);
         alpha[k] = stk.alpha;
         half[k] = act[k] && ss[k] <= tol2 * stk.bb;
@@ -530,6 +546,8 @@ __global__ __launch_bounds__(kKB) void k_x(int64_t n, int64_t np, const T *__res
                                            const T *__restrict__ v, T *__restrict__ r, T *__restrict__ rh,
                                            double *__restrict__ part, KState *__restrict__ st, int nblk, int phase)
 {
+    KState st0[NRHS];
+    load_states<NRHS>(st, st0);
     double ld[5 * NRHS][kPartPer];
     {
         const double *ps[5 * NRHS];
@@ -560,12 +578,12 @@ __global__ __launch_bounds__(kKB) void k_x(int64_t n, int64_t np, const T *__res
     }
     double sums[5 * NRHS];
     reduce_partials_n<5 * NRHS>(ld, sums);
-    if (all_done<NRHS>(st, phase)) return;
+    if (all_done<NRHS>(st0, phase)) return;
     bool act[NRHS], restart[NRHS];
     double alpha[NRHS], omega[NRHS], beta[NRHS];
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) {
-        const KState stk = st[k];
+        const KState stk = st0[k];
         act[k] = !finished_before(stk, phase);
         alpha[k] = stk.alpha;
         const double ts = sums[5 * k], tt = sums[5 * k + 1], rs = sums[5 * k + 2], rt = sums[5 * k + 3];
