@@ -899,13 +899,15 @@ __global__ __launch_bounds__(kKB) void kbj_s(int64_t n, int64_t np, BlockInv bin
                                              T *__restrict__ sh, double *__restrict__ part, KState *__restrict__ st,
                                              int nblk, int phase)
 {
+    KState st0[1];
+    load_states<1>(st, st0);
     double rv;
     {
         const double *ps[1] = {partial(part, P_RV, 0)};
         sum_partials_n<1>(ps, nblk, &rv);
     }
-    if (all_done<1>(st, phase)) return;
-    const KState stk = st[0];
+    if (all_done<1>(st0, phase)) return;
+    const KState stk = st0[0];
     const double alpha = (rv != 0.0) ? stk.rho / rv : 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st[0].alpha = alpha;
@@ -945,14 +947,16 @@ __global__ __launch_bounds__(kKB) void kbj_x(int64_t n, int64_t np, BlockInv bin
                                              T *__restrict__ r, T *__restrict__ rh,
                                              double *__restrict__ part, KState *__restrict__ st, int nblk, int phase)
 {
+    KState st0[1];
+    load_states<1>(st, st0);
     double sums[5];
     {
         const double *ps[5] = {partial(part, P_TS, 0), partial(part, P_TT, 0), partial(part, P_RS, 0),
                                partial(part, P_RT, 0), partial(part, P_SS, 0)};
         sum_partials_n<5>(ps, nblk, sums);
     }
-    if (all_done<1>(st, phase)) return;
-    const KState stk = st[0];
+    if (all_done<1>(st0, phase)) return;
+    const KState stk = st0[0];
     const double ts = sums[0], tt = sums[1], rs = sums[2], rt = sums[3], ssk = sums[4];
     const double omega = (tt > 0.0) ? ts / tt : 0.0;
     const double rho1 = rs - omega * rt;
@@ -1183,12 +1187,12 @@ __global__ __launch_bounds__(kKB) void kb_s(const BSys *__restrict__ sys, const 
 {
     const int j = bmap[blockIdx.x];
     const BSys S = sys[j];
+    const KState k0 = st[j];   // loaded early: overlaps the partial loads
     double rv;
     {
         const double *ps[1] = {bpart(part, P_RV, pstride, S.boff)};
         sum_partials_n<1>(ps, S.nblk, &rv);
     }
-    const KState k0 = st[j];
     if (finished_before(k0, phase)) return;
     const double alpha = (rv != 0.0) ? k0.rho / rv : 0.0;
     if (blockIdx.x == S.boff && threadIdx.x == 0) {
@@ -1230,12 +1234,12 @@ __global__ __launch_bounds__(kKB) void kb_t(const BSys *__restrict__ sys, const 
 {
     const int j = bmap[blockIdx.x];
     const BSys S = sys[j];
+    const KState k0 = st[j];   // loaded early: overlaps the partial loads
     double ss;
     {
         const double *ps[1] = {bpart(part, P_SS, pstride, S.boff)};
         sum_partials_n<1>(ps, S.nblk, &ss);
     }
-    const KState k0 = st[j];
     if (finished_before(k0, phase)) return;
     const bool half = ss <= S.tol2 * k0.bb;
     if (half && blockIdx.x == S.boff && threadIdx.x == 0) {
@@ -1271,6 +1275,7 @@ __global__ __launch_bounds__(kKB) void kb_x(const BSys *__restrict__ sys, const 
 {
     const int j = bmap[blockIdx.x];
     const BSys S = sys[j];
+    const KState k0 = st[j];   // loaded early: overlaps the partial loads
     double sums[5];
     {
         const double *ps[5] = {bpart(part, P_TS, pstride, S.boff), bpart(part, P_TT, pstride, S.boff),
@@ -1278,7 +1283,6 @@ __global__ __launch_bounds__(kKB) void kb_x(const BSys *__restrict__ sys, const 
                                bpart(part, P_SS, pstride, S.boff)};
         sum_partials_n<5>(ps, S.nblk, sums);
     }
-    const KState k0 = st[j];
     if (finished_before(k0, phase)) return;
     const double ts = sums[0], tt = sums[1], rs = sums[2], rt = sums[3], ssk = sums[4];
     const double omega = (tt > 0.0) ? ts / tt : 0.0;
