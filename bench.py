@@ -59,6 +59,25 @@ def narrow_fraction(col, n, q):
     return float(narrow.mean())
 
 
+def kt_bytes(n, q):
+    """Algorithmic bytes of the dominant kernel KT (t = A s-hat with the partial
+    dots t.s, t.t, r-hat.t): one SpMV at 12q + 16 B per row (q FP64 values, q
+    4-byte column indices, s-hat read, t written) plus the two dot operands s
+    and r-hat (16 B): 12q + 32 B per row."""
+    return n * (12 * q + 32)
+
+
+def kv_bytes(n, q):
+    """KV (v = A p-hat with the partial r-hat.v): 12q + 16 + 8 B per row."""
+    return n * (12 * q + 24)
+
+
+def iteration_bytes(n, q):
+    """One FP64 BiCGSTAB iteration: two SpMVs (12q + 16 B per row each) and
+    about 20 vector sweeps of 8 B: 24q + 192 B per row."""
+    return n * (24 * q + 192)
+
+
 def bicgstab_iter_bytes(n, q, narrow=0.0):
     """Algorithmic bytes of one FP64 BiCGSTAB iteration: two SpMVs (their operand
     read and result write included) and the vectors the four kernels move
@@ -75,12 +94,14 @@ WORKLOADS = {
     "taylor_green": {
         "k": 4, "make": lambda W: W.taylor_green_disk(),
         "sample": lambda W, a: W.taylor_green_disk(r=a.cpu_sample_r),
+        "sample1": lambda W, a: W.taylor_green_disk(r=2 * a.cpu_sample_r),
         "text": "Taylor-Green vortex nu=0.01 on [0,2pi]^2, {n} Poisson-disk points (seed 2), PHS r^3 + degree-4 "
                 "polynomials, q={q}, Co 10 (dt={dt:.5f})",
     },
     "beltrami": {
         "k": 3, "make": lambda W: W.beltrami_cube(n=100),
         "sample": lambda W, a: W.beltrami_cube(n=a.cpu_sample_cube),
+        "sample1": lambda W, a: W.beltrami_cube(n=a.cpu_sample_cube * 2 // 3),
         "text": "Ethier-Steinman Beltrami flow nu=0.01 on [0,1]^3, {n} points (100^3 jittered lattice + faces, "
                 "seed 4), PHS r^3 + degree-3 polynomials, q={q}, Co 10 (dt={dt:.5f})",
     },
@@ -118,36 +139,80 @@ def counter_traffic(workload):
         return None
 
 
+def host_cpu():
+    """Model name (lscpu) and the number of cores this process may use."""
+    model = "unknown"
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, usable
+
+
+def _omp_threads(nthreads):
+    """Set the OpenMP thread count of the oracle's runtime (libgomp)."""
+    import ctypes
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(nthreads))
+    except OSError:
+        pass
+
+
 def cpu_baseline(args):
     """The FP64 oracle running the same benchmark step (operator build + one BDF2
-    step at Co 10, same tolerances) on a smaller Taylor-Green cloud from the same
-    generator, in the same unit. kNN and weights use OpenMP threads; the oracle's
-    Krylov solver is sequential."""
+    step at Co 10, same tolerances) on a smaller cloud from the same generator,
+    in the same unit: with the OpenMP threads of the host (kNN, weights and the
+    row loop of the sparse products in parallel, dot products sequential), and
+    with one thread on a quarter-size cloud, which keeps the leg near 15 s."""
     import oracle
     import workloads as W
     oracle.build()
     c = WORKLOADS[args.workload]["sample"](W, args)
+    c1 = WORKLOADS[args.workload]["sample1"](W, args)
     kdeg = WORKLOADS[args.workload]["k"]
-    t0 = time.perf_counter()
-    ops = oracle.build_operators(c, kdeg)
-    vel0, p0 = W.flow_fields(c, 0.0)
-    dt = oracle.dt_from_courant(ops, vel0, 10.0, 1.0, 0.01)
-    t_build = time.perf_counter() - t0
-    velm, _ = W.flow_fields(c, -dt)
-    ubc, pbc = W.flow_fields(c, dt)
-    t1 = time.perf_counter()
-    _, _, _, st = oracle.simple_step(ops, vel0, velm, p0, ubc, 1.0, 0.01, dt, tol_outer=1e-8, tol_krylov=1e-10,
-                                     max_outer=args.max_outer, max_krylov=20000, p_bc=pbc)
-    t_end = time.perf_counter()
-    t = t_end - t0
-    pi = c.n * (st["krylov_mom"] + st["krylov_p"]) + int((c.kind == W.DIRICHLET).sum()) * st["krylov_b"]
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(pi / t / 1e6, 3), "unit": "M point-iters/s", "cores": cores, "kind": "oracle",
+    model, usable = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS", usable))
+
+    def leg(nthreads, c):
+        _omp_threads(nthreads)
+        t0 = time.perf_counter()
+        ops = oracle.build_operators(c, kdeg)
+        vel0, p0 = W.flow_fields(c, 0.0)
+        dt = oracle.dt_from_courant(ops, vel0, 10.0, 1.0, 0.01)
+        t_build = time.perf_counter() - t0
+        velm, _ = W.flow_fields(c, -dt)
+        ubc, pbc = W.flow_fields(c, dt)
+        t1 = time.perf_counter()
+        _, _, _, st = oracle.simple_step(ops, vel0, velm, p0, ubc, 1.0, 0.01, dt, tol_outer=1e-8, tol_krylov=1e-10,
+                                         max_outer=args.max_outer, max_krylov=20000, p_bc=pbc)
+        t_end = time.perf_counter()
+        pi = c.n * (st["krylov_mom"] + st["krylov_p"]) + int((c.kind == W.DIRICHLET).sum()) * st["krylov_b"]
+        return dict(value=round(pi / (t_end - t0) / 1e6, 3), t_build=t_build, t_step=t_end - t1, st=st, pi=pi,
+                    t=t_end - t0, dt=dt, q=ops.q, n=c.n)
+
+    full = leg(threads, c)
+    one = leg(1, c1)
+    _omp_threads(threads)
+    st = full["st"]
+    return {"value": full["value"], "unit": "M point-iters/s", "cores": threads, "kind": "oracle",
+            "host": {"lscpu_model": model, "usable_cores": usable},
+            "one_thread": {"value": one["value"], "cores": 1, "n_points": one["n"],
+                           "build_s": round(one["t_build"], 2), "step_s": round(one["t_step"], 2)},
             "sample": f"FP64 oracle, one benchmark step on a {c.n}-point {c.name} cloud from the same generator "
-                      f"(k={kdeg}, q={ops.q}, Co 10, dt={dt:.5f}): operator build {t_build:.2f} s "
-                      f"({cores} OpenMP threads for kNN/weights), step {t_end - t1:.2f} s (sequential Krylov), "
-                      f"{st['outer_iters']} outer / {st['krylov_mom']} momentum / {st['krylov_p']} pressure "
-                      f"iterations, {pi} point-iters in {t:.2f} s"}
+                      f"(k={kdeg}, q={full['q']}, Co 10, dt={full['dt']:.5f}): operator build {full['t_build']:.2f} s "
+                      f"({threads} OpenMP threads), step {full['t_step']:.2f} s "
+                      f"(sequential dot products), {st['outer_iters']} outer / {st['krylov_mom']} momentum / {st['krylov_p']} pressure "
+                      f"iterations, {full['pi']} point-iters in {full['t']:.2f} s; one thread on a {one['n']}-point cloud: "
+                      f"{one['value']} M point-iters/s (build {one['t_build']:.2f} s, step {one['t_step']:.2f} s)"}
 
 
 FP64_PEAK_TFLOPS = 78.6
@@ -607,6 +672,7 @@ def main():
     ap.add_argument("--max-outer", type=int, default=20)
     ap.add_argument("--precision", choices=["fp64", "fp32ir", "fp32matrix"], default="fp64")
     ap.add_argument("--spmv-reps", type=int, default=200)
+    ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--solve-reps", type=int, default=5)
     ap.add_argument("--mixed-step", action="store_true",
                     help="also run the step with both mixed-precision modes and with the block-Jacobi "
@@ -711,6 +777,13 @@ def main():
     it_us = t_ps / max(pst["iters"], 1) * 1e6
     log(f"[bench] poisson_solve: {pst['iters']} iterations, {it_us:.1f} us/iteration, relres {pst['relres']:.1e}")
 
+    # ---- kernel times of the BiCGSTAB iteration (HIP events on the stream) ----
+    xk = torch.zeros(n, dtype=torch.float64, device=dev)
+    ktimes = R.rbffd_krylov_kernel_times(ctx, solver.ops, rhs, xk, reps=args.kernel_reps)
+    kt_gbs = kt_bytes(n, q) / (ktimes["kt"] * 1e-6) / 1e9
+    log(f"[bench] kernel times (us): {ktimes}; k_t {kt_gbs:.0f} GB/s for {kt_bytes(n, q) / 1e6:.1f} MB")
+    del xk
+
     # ---- converged solves at 1e-6: plain FP64 against FP32 sweeps with FP64
     # refinement, on the same pressure-correction system ----------------------
     ops_mixed = R.rbffd_assemble(ctx, dcloud, solver.nbr, solver.w, k, precision=R.RBFFD_FP32_IR)
@@ -749,7 +822,19 @@ def main():
     log(f"[bench] solves at 1e-6: fp64 {solves64}  fp32 {solves32}  fp32 matrix {solves32m}  "
         f"fp64 block-Jacobi {solves64b}  fp32 block-Jacobi {solves32b}  fp32 matrix block-Jacobi {solves32mb}")
 
-    # ---- the benchmark step ---------------------------------------------------
+    # ---- the benchmark step: consecutive time steps of the run ----------------
+    # Every step is one pass of the whole hot path: stencils and weights
+    # (rbffd_build_stencils), assembly (rbffd_assemble) and one BDF2 time step
+    # (simple_step) that advances the flow from t^n to t^{n+1}. The Dirichlet
+    # data of every step are computed and copied to the device before the timed
+    # region starts.
+    nsteps = args.warmup + args.steps
+    bc_dev = []
+    for i in range(nsteps):
+        ub, pb = W.flow_fields(cloud, (i + 1) * dt)
+        bc_dev.append((torch.tensor(ub, device=dev), torch.tensor(pb, device=dev)))
+    torch.cuda.synchronize()
+    state = {"u": u0.clone(), "up": um1.clone(), "p": pt0.clone(), "i": 0}
     phase_s = {"stencils": 0.0, "assemble": 0.0, "time_step": 0.0}
 
     def one_step():
@@ -762,20 +847,19 @@ def main():
         tc = time.perf_counter()
         phase_s["stencils"] += tb - ta
         phase_s["assemble"] += tc - tb
-        u = u0.clone()
-        up = um1.clone()
-        p = pt0.clone()
-        st = R.simple_step(ctx, ops, u, up, p, ubc, rho, nu, dt, R.BDF2, tol_outer=1e-8, tol_krylov=1e-10,
-                           max_outer=args.max_outer, max_krylov=20000, precision=precision, p_bc=pbc)
+        ub, pb = bc_dev[state["i"]]
+        st = R.simple_step(ctx, ops, state["u"], state["up"], state["p"], ub, rho, nu, dt, R.BDF2, tol_outer=1e-8,
+                           tol_krylov=1e-10, max_outer=args.max_outer, max_krylov=20000, precision=precision,
+                           p_bc=pb)
         torch.cuda.synchronize()
         phase_s["time_step"] += time.perf_counter() - tc
+        state["i"] += 1
         pi = n * (st["krylov_mom"] + st["krylov_p"]) + ops.n_boundary * st["krylov_b"]
-        err = float((u - ubc).abs().max())
         ops.free()
-        return st, pi, err
+        return st, pi
 
     for i in range(args.warmup):
-        st, _, _ = one_step()
+        st, _ = one_step()
         log(f"[bench] warmup {i}: {st}")
     torch.cuda.synchronize()
     for key in phase_s:
@@ -783,18 +867,27 @@ def main():
     t0 = time.perf_counter()
     tot_pi = 0
     stats = []
-    errs = []
     for i in range(args.steps):
-        st, pi, err = one_step()
+        st, pi = one_step()
         tot_pi += pi
         stats.append(st)
-        errs.append(err)
         log(f"[bench] step {i}: {st} point-iters {pi}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed / args.steps * 1e3
     value = tot_pi / elapsed / 1e6
     last = stats[-1]
+    unconverged = sum(1 for st_ in stats if st_["status"] != 0)
+    # error against the closed-form flow at the last time level
+    t_end = nsteps * dt
+    ue_np, pe_np = W.flow_fields(cloud, t_end)
+    u_fin = state["u"].cpu().numpy()
+    p_fin = state["p"].cpu().numpy()
+    err_u = float(np.abs(u_fin - ue_np).max())
+    err_u_l1 = float(np.abs(u_fin - ue_np).mean())
+    err_p = float(np.abs(p_fin - pe_np).max() / np.abs(pe_np).max())
+    log(f"[bench] t={t_end:.4f} after {nsteps} steps: |u - exact| max {err_u:.3e} mean {err_u_l1:.3e}, "
+        f"|p - exact| / |p| {err_p:.3e}; unconverged timed steps {unconverged}")
 
     out = {
         "metric": METRIC,
@@ -812,26 +905,37 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": WORKLOADS[args.workload]["text"].format(n=n, q=q, dt=dt) +
-                        f"; step = stencil build + assembly + one BDF2 time step (Krylov tol 1e-10, outer tol 1e-8, "
-                        f"<= {args.max_outer} outer iterations)",
-            "n_points": n, "q": q, "poly_degree": k, "max_outer": args.max_outer,
+                        f"; step = stencil build + assembly + one BDF2 time step advancing the flow (Krylov tol 1e-10, "
+                        f"outer tol 1e-8, <= {args.max_outer} outer iterations); {nsteps} consecutive steps from t=0 "
+                        f"({args.warmup} untimed)",
+            "n_points": n, "q": q, "poly_degree": k, "max_outer": args.max_outer, "time_steps": nsteps,
         },
         "roofline": {
             "bound": "hbm",
-            # the library unrolls the row loop by 3 for widths divisible by 3 and not by 4
-            "kernel": f"spmv_kernel<double, {3 if q % 3 == 0 and q % 4 else 4}> (sliced-ELL SpMV, "
-                      "pressure-correction matrix)",
-            "achieved": round(spmv_gbs, 1),
+            # the dominant kernel of the step: KT of the pressure-correction BiCGSTAB
+            # (the library unrolls the row loop by 3 for widths divisible by 3 and not by 4)
+            "kernel": f"k_t<double, double, 1, {3 if q % 3 == 0 and q % 4 else 4}> (t = A s-hat with dots t.s, t.t, "
+                      "r-hat.t; pressure-correction BiCGSTAB)",
+            "achieved": round(kt_gbs, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(spmv_gbs / HBM_PEAK_GBS, 4),
+            "frac": round(kt_gbs / HBM_PEAK_GBS, 4),
             "traffic": counter_traffic(args.workload),
-            "bytes_per_launch": spmv_bytes(n, q, narrow),
-            "index_bytes": f"{narrow:.4f} of rows with 2-byte column offsets, the rest 4-byte indices",
-            "us_per_launch": round(spmv_ms * 1e3, 2),
-            "note": ("matrix + vectors (~%.0f MB) fit the 256 MB Infinity Cache" if spmv_bytes(n, q, narrow) < 256e6 else
-                     "matrix + vectors (~%.0f MB) exceed the 256 MB Infinity Cache: HBM-resident") %
-                    (spmv_bytes(n, q, narrow) / 1e6),
+            "bytes_per_launch": kt_bytes(n, q),
+            "bytes_per_row": f"12q + 32 = {12 * q + 32}",
+            "us_per_launch": round(ktimes["kt"], 2),
+            "k_v": {"us_per_launch": round(ktimes["kv"], 2), "bytes_per_launch": kv_bytes(n, q),
+                    "frac": round(kv_bytes(n, q) / (ktimes["kv"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},
+            "k_s_us": round(ktimes["ks"], 2), "k_x_us": round(ktimes["kx"], 2),
+            "iteration": {"us": round(ktimes["iteration"], 2), "bytes": iteration_bytes(n, q),
+                          "bytes_per_row": f"24q + 192 = {24 * q + 192}",
+                          "frac": round(iteration_bytes(n, q) / (ktimes["iteration"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},
+            "spmv_alone": {"us_per_launch": round(spmv_ms * 1e3, 2), "gbs_algorithmic": round(spmv_gbs, 1),
+                           "index_bytes": f"{narrow:.4f} of rows with 2-byte column offsets, the rest 4-byte indices"},
+            "note": ("working set ~%.0f MB fits the 256 MB Infinity Cache: effective bandwidth, not HBM"
+                     if iteration_bytes(n, q) < 256e6 else
+                     "working set ~%.0f MB exceeds the 256 MB Infinity Cache: HBM-resident") %
+                    (iteration_bytes(n, q) / 1e6),
         },
         "phase_ms_per_step": {key: round(v / args.steps * 1e3, 3) for key, v in phase_s.items()},
         "stencil_points_per_s": round(n * args.steps / max(phase_s["stencils"], 1e-12), 0),
@@ -839,9 +943,11 @@ def main():
         "outer_delta": last["delta"],
         "krylov_iters": {"momentum": last["krylov_mom"], "pressure": last["krylov_p"], "boundary": last["krylov_b"]},
         "step_status": last["status"],
+        "all_timed_steps_converged": unconverged == 0,
+        "unconverged_timed_steps": unconverged,
+        "error_vs_exact": {"t": round(t_end, 6), "u_max_abs": err_u, "u_mean_abs": err_u_l1, "p_max_rel": err_p},
         "bicgstab_us_per_iter": round(it_us, 2),
         "bicgstab_gbs": round(bicgstab_iter_bytes(n, q, narrow) / (it_us * 1e-6) / 1e9, 1),
-        "max_abs_err_u_vs_exact": max(errs),
         "converged_solves_1e-6": {
             "system": f"pressure-correction matrix of the same cloud, random right-hand side (seed 1), {args.solve_reps} solves each",
             "fp64": solves64,

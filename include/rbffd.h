@@ -297,6 +297,27 @@ int poisson_solve_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops
                           double *const *x, const rbffd_krylov_opts *opts, rbffd_krylov_stats *stats,
                           void *hip_stream);
 
+/* ---- measurement --------------------------------------------------------- */
+/* (Sec. 3, "preconditioned BiCGSTAB": the iteration that dominates the time
+ * step) Mean durations of the four kernels of one FP64 Jacobi BiCGSTAB
+ * iteration on the pressure-correction matrix, measured with HIP events on
+ * the caller's stream, for roofline figures:
+ *   us[0]  v = A p^ and r^.v                 (one matrix pass)
+ *   us[1]  alpha, s = r - alpha v, s^ = D^-1 s, s.s and r^.s
+ *   us[2]  t = A s^, t.s, t.t and r^.t       (one matrix pass)
+ *   us[3]  omega, x, r and the next search direction, r.r (whole iteration
+ *          minus the other three)
+ *   us[4]  one whole iteration
+ * The solve starts from x (device [n], overwritten with the iterate, not a
+ * solution) with right-hand side rhs (device [n]), runs three iterations,
+ * then times `reps` back-to-back launches of each of the first three kernels
+ * (each recomputes the same outputs in place) and `reps` whole iterations,
+ * with tolerance 0 so that nothing stops early. us: host [5]. Synchronises
+ * the stream. RBFFD_E_ARG for reps < 1; RBFFD_E_BREAKDOWN if the iteration
+ * broke down while being timed. */
+int rbffd_krylov_kernel_times(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, double *x, int reps,
+                              double *us, void *hip_stream);
+
 /* ---- continuous batching ------------------------------------------------ */
 /* (Sec. 3, applied to a stream of independent requests) A server keeps a
  * running batch of pressure-correction solves (FP64, or FP32 matrix values
@@ -354,6 +375,14 @@ typedef struct {
     int status;             /* RBFFD_OK or the first failure code                    */
     double delta;           /* last Delta = sum_c mean_i |u_c^{r+1} - u_c^r|          */
     double eps_steady;      /* max_c mean_i |u_c^{n+1} - u_c^n| / dt                  */
+    double div_l1;          /* mean over interior points of |sum_c D_c u_c^{n+1}|: the
+                               discrete continuity error of the new velocity (Eq.
+                               continuity:n+1)                                        */
+    double final_relres_p;  /* true residual ||b - P p'|| / ||b|| of the last
+                               pressure-correction solve                              */
+    double krylov_relres_max; /* largest true relative residual over every Krylov
+                               solve of the step (momentum, pressure correction,
+                               boundary pressure)                                     */
 } rbffd_step_stats;
 
 /* (Sec. 3 and the step list of Sec. 3.2) One BDF time step: starting from

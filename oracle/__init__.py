@@ -363,7 +363,8 @@ class _StepCfg(C.Structure):
 class _StepStats(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("krylov_mom", C.c_int), ("krylov_p", C.c_int),
                 ("krylov_b", C.c_int), ("status", C.c_int), ("delta", C.c_double),
-                ("eps_steady", C.c_double)]
+                ("eps_steady", C.c_double), ("div_l1", C.c_double), ("final_relres_p", C.c_double),
+                ("krylov_relres_max", C.c_double)]
 
 
 BDF2 = (1.5, -2.0, 0.5)
@@ -396,7 +397,8 @@ def simple_step(ops: Operators, u, u_prev, p, u_bc, rho, mu, dt, alpha=BDF2,
         raise ValueError("p_bc is required on clouds with prescribed-pressure points")
     lib().orc_simple_step(C.byref(cfg), _p(u), _p(up), _p(p), _p(ubc), _p(pbc), C.byref(st))
     stats = dict(outer_iters=st.outer_iters, krylov_mom=st.krylov_mom, krylov_p=st.krylov_p,
-                 krylov_b=st.krylov_b, status=st.status, delta=st.delta, eps_steady=st.eps_steady)
+                 krylov_b=st.krylov_b, status=st.status, delta=st.delta, eps_steady=st.eps_steady,
+                 div_l1=st.div_l1, final_relres_p=st.final_relres_p, krylov_relres_max=st.krylov_relres_max)
     return u, up, p, stats
 
 

@@ -493,7 +493,8 @@ done:
 
 /* BiCGSTAB with up to two restarts from the true residual: when the recursive
  * residual has met the tolerance but ||b - A x|| exceeds 10 tol ||b||, the
- * iteration starts again from the current x. */
+ * iteration starts again from the current x. A true residual still above
+ * 10 tol ||b|| after the restarts is reported as non-convergence. */
 static int bicgstab_op(int64_t n, orc_apply_fn apply, const void *actx, const double *dinv,
                        const double *b, double *x, double tol, int maxit, int *iters_out,
                        double *relres_out)
@@ -512,6 +513,9 @@ static int bicgstab_op(int64_t n, orc_apply_fn apply, const void *actx, const do
         rel = sqrt(dot(n, r, r)) / bn;
         if (rel <= 10.0 * tol || total >= maxit) break;
     }
+    /* the recursion met the tolerance but the true residual still misses it
+     * by more than 10x after the restarts: the solve has not converged */
+    if (st == ORC_OK && bn != 0.0 && !(rel <= 10.0 * tol)) st = ORC_E_NOCONV;
     free(r);
     if (iters_out) *iters_out = total;
     if (relres_out) *relres_out = rel;
@@ -610,6 +614,9 @@ typedef struct {
     int status;
     double delta;
     double eps_steady;
+    double div_l1;            /* mean over interior points of |sum_e D_e u_e^{n+1}| */
+    double final_relres_p;    /* true relative residual of the last p' solve */
+    double krylov_relres_max; /* largest true relative residual of the step's solves */
 } orc_step_stats;
 
 /* u, u_prev: [dim][n] velocity at t^n and t^{n-1}, replaced by t^{n+1} and t^n.
@@ -659,7 +666,7 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
     }
 
     int status = ORC_OK, kit_m = 0, kit_p = 0, kit_b = 0, outer = 0;
-    double delta = 0.0;
+    double delta = 0.0, relres_p = 0.0, relres_max = 0.0;
     /* step 1: the iterate starts from the old time level, with the Dirichlet
      * values of the new time level on velocity-prescribed points (kinds 1, 2) */
     for (int e = 0; e < dim; ++e)
@@ -750,8 +757,10 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
                 bm[e * n + i] = r;
             }
             memcpy(ut + e * n, ur + e * n, sizeof(double) * n);
-            int s = orc_bicgstab(n, q, c->col, mval, bm + e * n, ut + e * n, c->tol_krylov, c->max_krylov, &its, NULL);
+            double rel = 0.0;
+            int s = orc_bicgstab(n, q, c->col, mval, bm + e * n, ut + e * n, c->tol_krylov, c->max_krylov, &its, &rel);
             kit_m += its;
+            if (rel > relres_max) relres_max = rel;
             if (s != ORC_OK) status = s;
         }
         /* step 3: pressure-correction right-hand side (Eq. pressure poisson) */
@@ -772,8 +781,11 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
         {
             int its = 0;
             memset(pc, 0, sizeof(double) * n);
-            int s = orc_bicgstab(n, q, c->col, c->pval, f, pc, c->tol_krylov, c->max_krylov, &its, NULL);
+            double rel = 0.0;
+            int s = orc_bicgstab(n, q, c->col, c->pval, f, pc, c->tol_krylov, c->max_krylov, &its, &rel);
             kit_p += its;
+            relres_p = rel;
+            if (rel > relres_max) relres_max = rel;
             if (s != ORC_OK) status = s;
         }
         /* step 4: interior pressure correction (Eq. p:correction); prescribed
@@ -810,8 +822,10 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
         }
         if (nb > 0) {
             int its = 0;
-            int s = orc_bicgstab(nb, q, gcol, gval, bb, pb, c->tol_krylov, c->max_krylov, &its, NULL);
+            double rel = 0.0;
+            int s = orc_bicgstab(nb, q, gcol, gval, bb, pb, c->tol_krylov, c->max_krylov, &its, &rel);
             kit_b += its;
+            if (rel > relres_max) relres_max = rel;
             if (s != ORC_OK) status = s;
         }
         for (int64_t i = 0; i < n; ++i) pr[i] = (c->kind[i] == 1 || c->kind[i] == 4) ? pb[bpos[i]] : pa[i];
@@ -851,10 +865,28 @@ int orc_simple_step(const orc_step_cfg *c, double *u, double *u_prev, double *p,
         sacc = sacc / (double)n / dt;
         if (sacc > eps) eps = sacc;
     }
+    /* the discrete continuity equation (Eq. continuity:n+1) at the interior
+     * points, applied to the new velocity: mean of |sum_e D_e u_e| */
+    double div_sum = 0.0;
+    int64_t n_int = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (c->kind[i] != 0) continue;
+        double dv = 0.0;
+        for (int e = 0; e < dim; ++e) {
+            double g = 0.0;
+            for (int a = 0; a < q; ++a) g = g + c->val[e * nnz + i * q + a] * ur[e * n + c->col[i * q + a]];
+            dv = dv + g;
+        }
+        div_sum = div_sum + fabs(dv);
+        n_int++;
+    }
     memcpy(u_prev, u, sizeof(double) * dim * n);
     memcpy(u, ur, sizeof(double) * dim * n);
     memcpy(p, pr, sizeof(double) * n);
     if (st) {
+        st->div_l1 = n_int > 0 ? div_sum / (double)n_int : 0.0;
+        st->final_relres_p = relres_p;
+        st->krylov_relres_max = relres_max;
         st->outer_iters = outer;
         st->krylov_mom = kit_m;
         st->krylov_p = kit_p;

@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_OOM", -3: "E_SINGULAR", -4: "E_NOCO
 EXPORTED = ["rbffd_last_error", "rbffd_ctx_create", "rbffd_ctx_destroy", "rbffd_ctx_bytes_in_use",
             "rbffd_stencil_sizes", "rbffd_build_stencils", "rbffd_assemble", "rbffd_ops_free",
             "rbffd_ops_info", "rbffd_ops_export_csr", "rbffd_ops_export_block_inverse", "rbffd_apply", "rbffd_interpolate", "rbffd_cylinder_forces", "poisson_solve",
-            "poisson_solve_batched",
+            "poisson_solve_batched", "rbffd_krylov_kernel_times",
             "rbffd_server_create", "rbffd_server_destroy", "rbffd_server_submit", "rbffd_server_run",
             "rbffd_server_poll", "simple_step", "rbffd_convdiff_lambda"]
 
@@ -65,7 +65,8 @@ class StepOptsT(C.Structure):
 class StepStatsT(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("krylov_mom", C.c_int), ("krylov_p", C.c_int),
                 ("krylov_b", C.c_int), ("status", C.c_int), ("delta", C.c_double),
-                ("eps_steady", C.c_double)]
+                ("eps_steady", C.c_double), ("div_l1", C.c_double), ("final_relres_p", C.c_double),
+                ("krylov_relres_max", C.c_double)]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -91,6 +92,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.rbffd_cylinder_forces.argtypes = [P, C.POINTER(CloudT), P, P, P, C.POINTER(D), D, D, I, D, D, C.POINTER(D),
                                         C.POINTER(D), P, C.POINTER(I64), P]
     L.poisson_solve.argtypes = [P, P, P, P, C.POINTER(KrylovOptsT), C.POINTER(KrylovStatsT), P]
+    L.rbffd_krylov_kernel_times.argtypes = [P, P, P, P, I, C.POINTER(D), P]
     L.poisson_solve_batched.argtypes = [P, I, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(KrylovOptsT),
                                         C.POINTER(KrylovStatsT), P]
     L.rbffd_server_create.argtypes = [P, C.POINTER(P)]
@@ -338,6 +340,15 @@ def poisson_solve(ctx: Context, ops: Operators, rhs: torch.Tensor, x: torch.Tens
                 relres=s.relres)
 
 
+def rbffd_krylov_kernel_times(ctx: Context, ops: Operators, rhs: torch.Tensor, x: torch.Tensor, reps: int = 100):
+    """Mean kernel durations (us) of one FP64 Jacobi BiCGSTAB iteration on the
+    pressure-correction matrix: dict kv, ks, kt, kx, iteration."""
+    us = (C.c_double * 5)()
+    _check(lib().rbffd_krylov_kernel_times(ctx.handle, ops.handle, _f64(rhs, ops.n, "rhs"), _f64(x, ops.n, "x"),
+                                           reps, us, _stream()))
+    return dict(zip(("kv", "ks", "kt", "kx", "iteration"), list(us)))
+
+
 def poisson_solve_batched(ctx: Context, ops: list, rhs: list, x: list, tol: float = 1e-10, max_iter: int = 5000,
                           allow_noconv: bool = False, preconditioner: int = RBFFD_PREC_JACOBI,
                           precision: int = RBFFD_FP64):
@@ -410,16 +421,18 @@ def simple_step(ctx: Context, ops: Operators, u: torch.Tensor, u_prev: torch.Ten
                 preconditioner: int = RBFFD_PREC_JACOBI, force=(0.0, 0.0, 0.0)):
     """One time step in place on u [dim, n], u_prev [dim, n], p [n]; returns stats.
     p_bc [n]: pressure at t^{n+1} on prescribed-pressure points. A limit reached
-    (E_NOCONV) is reported in the stats, not raised."""
+    (E_NOCONV) or a Krylov breakdown (E_BREAKDOWN) is reported in the stats,
+    not raised."""
     o = StepOptsT(rho, mu, dt, (C.c_double * 3)(*alpha), tol_outer, tol_krylov, max_outer, max_krylov, precision,
                   preconditioner, (C.c_double * 3)(*(tuple(force) + (0.0,) * (3 - len(force)))))
     s = StepStatsT()
     dn = ops.dim * ops.n
     st = lib().simple_step(ctx.handle, ops.handle, _f64(u, dn, "u"), _f64(u_prev, dn, "u_prev"), _f64(p, ops.n, "p"),
                            _f64(u_bc, dn, "u_bc"), _f64(p_bc, ops.n, "p_bc"), C.byref(o), C.byref(s), _stream())
-    _check(st, allow=(RBFFD_E_NOCONV,))
+    _check(st, allow=(RBFFD_E_NOCONV, RBFFD_E_BREAKDOWN))
     return dict(outer_iters=s.outer_iters, krylov_mom=s.krylov_mom, krylov_p=s.krylov_p, krylov_b=s.krylov_b,
-                status=s.status, delta=s.delta, eps_steady=s.eps_steady)
+                status=s.status, delta=s.delta, eps_steady=s.eps_steady, div_l1=s.div_l1,
+                final_relres_p=s.final_relres_p, krylov_relres_max=s.krylov_relres_max)
 
 
 def rbffd_convdiff_lambda(ctx: Context, ops: Operators, u0: torch.Tensor, rho: float, mu: float,

@@ -826,6 +826,17 @@ int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, doubl
     return RBFFD_OK;
 }
 
+int rbffd_krylov_kernel_times(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, double *x, int reps,
+                              double *us, void *hip_stream)
+{
+    if (!ctx || !ops || !rhs || !x || !us) return fail(RBFFD_E_ARG, "NULL argument");
+    if (!ops->ctx) return fail(RBFFD_E_ARG, "the operators' context was destroyed");
+    if (reps < 1) return fail(RBFFD_E_ARG, "reps must be >= 1");
+    RB_HIP(hipSetDevice(ctx->device));
+    return krylov_kernel_times(ctx, ops->n, ops->q, cols_of(ops), ops->pval, ops->pdinv, rhs, x, reps, us,
+                               (hipStream_t)hip_stream);
+}
+
 int poisson_solve_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops, const double *const *rhs,
                           double *const *x, const rbffd_krylov_opts *opts, rbffd_krylov_stats *stats,
                           void *hip_stream)

@@ -300,6 +300,10 @@ int server_run(Server *sv, int iterations, int *n_active, hipStream_t s);
 int server_poll(Server *sv, int max, int64_t *tickets, int *iters, int *status, double *relres, int *count);
 int spmv(int64_t n, int q, ColIdx col, const double *val, const double *x, double *y,
          hipStream_t s);
+// Mean kernel durations (us) of one FP64 Jacobi BiCGSTAB iteration on one system:
+// us[0] KV, us[1] KS, us[2] KT, us[3] KX, us[4] the whole iteration.
+int krylov_kernel_times(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, const double *dinv,
+                        const double *b, double *x, int reps, double *us, hipStream_t s);
 int residual_norms(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val,
                    int nrhs, const double *b, const double *x, double *relres_out, hipStream_t s);
 

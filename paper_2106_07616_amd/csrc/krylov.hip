@@ -756,6 +756,13 @@ __global__ void k_dir_reset(int64_t n, int64_t np, int nrhs, unsigned mask, cons
     }
 }
 
+// Zeroes the solver state records (a kernel rather than a memset, so that the
+// solve also runs inside a captured graph).
+__global__ void k_clear_states(KState *__restrict__ st)
+{
+    if (threadIdx.x < kMaxRhs) st[threadIdx.x] = KState{};
+}
+
 template <typename T>
 __global__ void k_zero(T *__restrict__ y, int64_t m)
 {
@@ -799,19 +806,17 @@ int get_work(rbffd_ctx *ctx, int64_t npad, int nrhs, Work *w)
 }
 
 template <typename T, int NRHS>
-int bicgstab_t(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const T *val, const T *dinv, const T *b,
-               int64_t bs, T *x, int64_t xs, double tol, int max_iter, KrylovResult *res, Work &w, hipStream_t s)
+int bicgstab_t(int64_t n, int q, ColIdx col, const T *val, const T *dinv, const T *b, int64_t bs, T *x, int64_t xs,
+               double tol, int max_iter, KrylovResult *res, Work &w, KState *hst, hipStream_t s)
 {
     const int64_t np = pad64(n);
     const int nblk = krylov_blocks(n);
     const dim3 g(nblk), bl(kKB);
     T *r = (T *)w.r, *rh = (T *)w.rh, *ph = (T *)w.ph, *v = (T *)w.v, *sv = (T *)w.s, *sh = (T *)w.sh, *t = (T *)w.t;
     const double tol2 = tol * tol;
-    RB_HIP(hipMemsetAsync(w.st, 0, sizeof(KState) * kMaxRhs, s));
+    hipLaunchKernelGGL(k_clear_states, dim3(1), dim3(64), 0, s, w.st);
     hipLaunchKernelGGL((k_init<T, NRHS>), g, bl, 0, s, n, np, q, col, val, dinv, b, bs, x, xs, r, rh, ph, w.part);
     RB_HIP(hipGetLastError());
-    KState *hst = nullptr;
-    RB_CHECK(host_scratch(ctx, kHostKrylov, sizeof(KState) * kMaxRhs, (void **)&hst));
     const auto kv = row_unroll3(q) ? k_v<T, T, NRHS, 3> : k_v<T, T, NRHS, 4>;
     const auto kt = row_unroll3(q) ? k_t<T, T, NRHS, 3> : k_t<T, T, NRHS, 4>;
     int it = 0, chunk = 4, phase = 0;
@@ -1381,10 +1386,12 @@ static int bicgstab_once(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const dou
 {
     Work w;
     RB_CHECK(get_work<double>(ctx, pad64(n), nrhs, &w));
+    KState *hst = nullptr;
+    RB_CHECK(host_scratch(ctx, kHostKrylov, sizeof(KState) * kMaxRhs, (void **)&hst));
     switch (nrhs) {
-    case 1: return bicgstab_t<double, 1>(ctx, n, q, col, val, dinv, b, n, x, n, tol, max_iter, res, w, s);
-    case 2: return bicgstab_t<double, 2>(ctx, n, q, col, val, dinv, b, n, x, n, tol, max_iter, res, w, s);
-    case 3: return bicgstab_t<double, 3>(ctx, n, q, col, val, dinv, b, n, x, n, tol, max_iter, res, w, s);
+    case 1: return bicgstab_t<double, 1>(n, q, col, val, dinv, b, n, x, n, tol, max_iter, res, w, hst, s);
+    case 2: return bicgstab_t<double, 2>(n, q, col, val, dinv, b, n, x, n, tol, max_iter, res, w, hst, s);
+    case 3: return bicgstab_t<double, 3>(n, q, col, val, dinv, b, n, x, n, tol, max_iter, res, w, hst, s);
     default: return fail(RBFFD_E_ARG, "nrhs must be 1..3");
     }
 }
@@ -1403,7 +1410,7 @@ static int bicgstab_block_once(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, con
     double *r = (double *)w.r, *rh = (double *)w.rh, *ph = (double *)w.ph, *v = (double *)w.v, *sv = (double *)w.s,
            *sh = (double *)w.sh, *t = (double *)w.t;
     const double tol2 = tol * tol;
-    RB_HIP(hipMemsetAsync(w.st, 0, sizeof(KState) * kMaxRhs, s));
+    hipLaunchKernelGGL(k_clear_states, dim3(1), dim3(64), 0, s, w.st);
     hipLaunchKernelGGL(kbj_init, g, bl, 0, s, n, np, q, col, val, binv, b, x, r, rh, pv, ph, w.part);
     RB_HIP(hipGetLastError());
     KState *hst = nullptr;
@@ -1452,6 +1459,9 @@ int bicgstab_block(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *v
         acc.relres[0] = rr[0];
         if (r1.status[0] != RBFFD_OK || left <= 0 || rr[0] <= 10.0 * tol) break;
     }
+    // the recursion converged but the true residual still misses 10 tol after
+    // the restarts: not converged, as in the batched and served solves
+    if (acc.status[0] == RBFFD_OK && !(acc.relres[0] <= 10.0 * tol)) acc.status[0] = RBFFD_E_NOCONV;
     *res = acc;
     return RBFFD_OK;
 }
@@ -1482,6 +1492,8 @@ int bicgstab(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, co
         }
         if (!ok || left <= 0 || good) break;
     }
+    for (int k = 0; k < nrhs; ++k)
+        if (acc.status[k] == RBFFD_OK && !(acc.relres[k] <= 10.0 * tol)) acc.status[k] = RBFFD_E_NOCONV;
     *res = acc;
     return RBFFD_OK;
 }
@@ -1545,7 +1557,7 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const
         return RBFFD_OK;
     };
 
-    RB_HIP(hipMemsetAsync(w.st, 0, sizeof(KState) * kMaxRhs, s));
+    hipLaunchKernelGGL(k_clear_states, dim3(1), dim3(64), 0, s, w.st);
     hipLaunchKernelGGL(k_zero<T>, dim3((unsigned)((np * NRHS + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, d,
                        np * NRHS);
     RB_CHECK(true_residual(1));
@@ -1708,15 +1720,13 @@ int bicgstab_mixed(rbffd_ctx *ctx, int precision, int64_t n, int q, ColIdx col, 
     return fail(RBFFD_E_ARG, "unknown mixed precision mode");
 }
 
-int residual_norms(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, int nrhs,
-                   const double *b, const double *x, double *relres_out, hipStream_t s)
+// ||b - A x|| / ||b|| per right-hand side. dev: device [2 kMaxRhs kMaxBlocks +
+// kMaxRhs] doubles; hout: host [kMaxRhs] doubles the result is copied through.
+static int residual_norms_in(int64_t n, int q, ColIdx col, const double *val, int nrhs, const double *b,
+                             const double *x, double *dev, double *hout, double *relres_out, hipStream_t s)
 {
     const int nblk = grid_blocks(n);
-    double *dev = nullptr;
-    RB_CHECK(workspace(ctx, WS_RESID, sizeof(double) * (2 * kMaxRhs * kMaxBlocks + kMaxRhs), (void **)&dev));
     double *out = dev + 2 * kMaxRhs * kMaxBlocks;
-    double *hout = nullptr;
-    RB_CHECK(host_scratch(ctx, kHostMisc, sizeof(double) * kMaxRhs, (void **)&hout));
     hipLaunchKernelGGL(k_resid, dim3(nblk), dim3(kBlock), 0, s, n, q, nrhs, col, val, b, n, x, n, dev);
     hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(kBlock), 0, s, dev, nblk, nrhs, out);
     RB_HIP(hipGetLastError());
@@ -1724,6 +1734,16 @@ int residual_norms(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *v
     RB_HIP(hipStreamSynchronize(s));
     for (int k = 0; k < nrhs; ++k) relres_out[k] = hout[k];
     return RBFFD_OK;
+}
+
+int residual_norms(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, int nrhs,
+                   const double *b, const double *x, double *relres_out, hipStream_t s)
+{
+    double *dev = nullptr;
+    RB_CHECK(workspace(ctx, WS_RESID, sizeof(double) * (2 * kMaxRhs * kMaxBlocks + kMaxRhs), (void **)&dev));
+    double *hout = nullptr;
+    RB_CHECK(host_scratch(ctx, kHostMisc, sizeof(double) * kMaxRhs, (void **)&hout));
+    return residual_norms_in(n, q, col, val, nrhs, b, x, dev, hout, relres_out, s);
 }
 
 
@@ -2121,6 +2141,88 @@ int server_poll(Server *sv, int max, int64_t *tickets, int *iters, int *status, 
     sv->fin_status.erase(sv->fin_status.begin(), sv->fin_status.begin() + m);
     sv->fin_relres.erase(sv->fin_relres.begin(), sv->fin_relres.begin() + m);
     *count = m;
+    return RBFFD_OK;
+}
+
+
+// ---- kernel times of the Krylov iteration --------------------------------
+// Mean durations of the four kernels of one FP64 Jacobi BiCGSTAB iteration on
+// one system, for roofline measurement. With tolerance 0 nothing stops the
+// solve, and KV, KS and KT are idempotent within an iteration (they read the
+// state and vectors the previous kernels left and rewrite the same outputs), so
+// each is timed by `reps` back-to-back launches between two events on the
+// stream; whole iterations are timed the same way, and KX is the remainder.
+int krylov_kernel_times(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, const double *dinv,
+                        const double *b, double *x, int reps, double *us, hipStream_t s)
+{
+    Work w;
+    RB_CHECK(get_work<double>(ctx, pad64(n), 1, &w));
+    KState *hst = nullptr;
+    RB_CHECK(host_scratch(ctx, kHostKrylov, sizeof(KState) * kMaxRhs, (void **)&hst));
+    const int64_t np = pad64(n);
+    const int nblk = krylov_blocks(n);
+    const dim3 g(nblk), bl(kKB);
+    double *r = (double *)w.r, *rh = (double *)w.rh, *ph = (double *)w.ph, *v = (double *)w.v, *sv = (double *)w.s,
+           *sh = (double *)w.sh, *t = (double *)w.t;
+    const auto kv = row_unroll3(q) ? k_v<double, double, 1, 3> : k_v<double, double, 1, 4>;
+    const auto kt = row_unroll3(q) ? k_t<double, double, 1, 3> : k_t<double, double, 1, 4>;
+    int phase = 0;
+    auto iteration = [&]() {
+        hipLaunchKernelGGL(kv, g, bl, 0, s, n, np, q, col, val, rh, ph, v, x, n, w.part, w.st, nblk, 0.0, 0, ++phase);
+        hipLaunchKernelGGL((k_s<double, 1>), g, bl, 0, s, n, np, dinv, r, rh, v, sv, sh, w.part, w.st, nblk, ++phase);
+        hipLaunchKernelGGL(kt, g, bl, 0, s, n, np, q, col, val, x, n, ph, sv, sh, rh, t, w.part, w.st, nblk, 0.0,
+                           ++phase);
+        hipLaunchKernelGGL((k_x<double, 1>), g, bl, 0, s, n, np, dinv, x, n, ph, sv, t, v, r, rh, w.part, w.st, nblk,
+                           ++phase);
+    };
+    hipLaunchKernelGGL(k_clear_states, dim3(1), dim3(64), 0, s, w.st);
+    hipLaunchKernelGGL((k_init<double, 1>), g, bl, 0, s, n, np, q, col, val, dinv, b, n, x, n, r, rh, ph, w.part);
+    for (int i = 0; i < 3; ++i) iteration();
+    RB_HIP(hipGetLastError());
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    RB_HIP(hipEventCreate(&e0));
+    hipError_t err = hipEventCreate(&e1);
+    if (err != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(err, "hipEventCreate");
+    }
+    float ms[4] = {0, 0, 0, 0};
+    // KV, then KS, then KT, each repeated in place; then whole iterations
+    for (int stage = 0; stage < 4 && err == hipSuccess; ++stage) {
+        err = hipEventRecord(e0, s);
+        for (int r_ = 0; r_ < reps && err == hipSuccess; ++r_) {
+            if (stage == 0)
+                hipLaunchKernelGGL(kv, g, bl, 0, s, n, np, q, col, val, rh, ph, v, x, n, w.part, w.st, nblk, 0.0, 0,
+                                   phase + 1);
+            else if (stage == 1)
+                hipLaunchKernelGGL((k_s<double, 1>), g, bl, 0, s, n, np, dinv, r, rh, v, sv, sh, w.part, w.st, nblk,
+                                   phase + 2);
+            else if (stage == 2)
+                hipLaunchKernelGGL(kt, g, bl, 0, s, n, np, q, col, val, x, n, ph, sv, sh, rh, t, w.part, w.st, nblk,
+                                   0.0, phase + 3);
+            else
+                iteration();
+        }
+        if (stage == 2) {
+            hipLaunchKernelGGL((k_x<double, 1>), g, bl, 0, s, n, np, dinv, x, n, ph, sv, t, v, r, rh, w.part, w.st,
+                               nblk, phase + 4);
+            phase += 4;
+        }
+        if (err == hipSuccess) err = hipGetLastError();
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms[stage], e0, e1);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return hip_fail(err, "krylov_kernel_times");
+    RB_HIP(hipMemcpyAsync(hst, w.st, sizeof(KState), hipMemcpyDeviceToHost, s));
+    RB_HIP(hipStreamSynchronize(s));
+    if (hst[0].done_at != 0)
+        return fail(RBFFD_E_BREAKDOWN, "the timed BiCGSTAB iteration broke down; no kernel times");
+    for (int i = 0; i < 4; ++i) us[i] = 1e3 * ms[i] / reps;
+    us[4] = us[3];                          // whole iteration
+    us[3] = us[4] - us[0] - us[1] - us[2];  // KX: the remainder
     return RBFFD_OK;
 }
 

@@ -357,6 +357,48 @@ __global__ __launch_bounds__(kBlock) void k_absdiff(int64_t n, int dim, const do
     }
 }
 
+// Discrete continuity error of the new velocity: per-block sums of
+// |sum_e (D_e u_e)_i| and of the count over interior points i (Eq.
+// continuity:n+1), in part[0..] and part[kMaxBlocks..].
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_div_abs(int64_t n, int q, const int32_t *__restrict__ col,
+                                                    const double *__restrict__ val, int64_t vs,
+                                                    const uint8_t *__restrict__ kind, const double *__restrict__ u,
+                                                    double *__restrict__ part)
+{
+    __shared__ double lds[kBlock / 64];
+    double acc = 0.0, cnt = 0.0;
+    for (int64_t i = (int64_t)lb() * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        if (kind[i] != RBFFD_INTERIOR) continue;
+        const int64_t base = ((i >> 6) * (int64_t)q) * 64 + (i & 63);
+        double dv = 0.0;
+        for (int e = 0; e < DIM; ++e) {
+            double s = 0.0;
+            for (int a = 0; a < q; ++a) {
+                const int64_t slot = base + (int64_t)a * 64;
+                s = fma(val[e * vs + slot], u[e * n + col[slot]], s);
+            }
+            dv = dv + s;
+        }
+        acc += fabs(dv);
+        cnt += 1.0;
+    }
+    const double sa = block_sum(acc, lds), sc = block_sum(cnt, lds);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = sa;
+        part[kMaxBlocks + blockIdx.x] = sc;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_finish_ratio(const double *__restrict__ part, int np,
+                                                         double *__restrict__ out)
+{
+    __shared__ double lds[kBlock / 64];
+    const double a = sum_partials(part, np, lds);
+    const double c = sum_partials(part + kMaxBlocks, np, lds);
+    if (threadIdx.x == 0) out[0] = (c > 0.0) ? a / c : 0.0;
+}
+
 // out[0] = sum_e S_e / n (Delta); out[1] = max_e S_e / n / dt (steady rate)
 __global__ __launch_bounds__(kBlock) void k_finish_sums(const double *__restrict__ part, int np, int dim, int64_t n,
                                                         double dt, double *__restrict__ out)
@@ -435,7 +477,7 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
     B.bb = (double *)w2;
     B.pb = B.bb + nbv;
     double *hs = nullptr;
-    RB_CHECK(host_scratch(ctx, kHostStep, sizeof(double) * 4, (void **)&hs));
+    RB_CHECK(host_scratch(ctx, kHostStep, sizeof(double) * 6, (void **)&hs));
 
     const double rho = o->rho, mu = o->mu, dt = o->dt;
     const double a1 = o->alpha[0], a2 = o->alpha[1], a3 = o->alpha[2];
@@ -449,7 +491,7 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
     RB_HIP(hipGetLastError());
 
     int status = RBFFD_OK, outer = 0, kit_m = 0, kit_p = 0, kit_b = 0;
-    double delta = 0.0;
+    double delta = 0.0, relres_p = 0.0, relres_max = 0.0;
     for (outer = 1; outer <= o->max_outer; ++outer) {
         // step 2: momentum matrix, right-hand sides, and the solves from u^r
         if (dim == 2)
@@ -495,6 +537,7 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
             }
             for (int e = 0; e < nrhs; ++e) {
                 kit_m += km.iters[e];
+                relres_max = std::max(relres_max, km.relres[e]);
                 if (km.status[e] != RBFFD_OK && status == RBFFD_OK) status = km.status[e];
             }
         }
@@ -520,6 +563,8 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
             RB_CHECK(bicgstab(ctx, n, q, cols_of(ops), ops->pval, ops->pdinv, 1, B.f, B.pc, o->tol_krylov, o->max_krylov,
                               &kp, s));
         kit_p += kp.iters[0];
+        relres_p = kp.relres[0];
+        relres_max = std::max(relres_max, kp.relres[0]);
         if (kp.status[0] != RBFFD_OK && status == RBFFD_OK) status = kp.status[0];
         // step 4: interior pressure
         hipLaunchKernelGGL(k_p_interior, dim3(gn), dim3(kBlock), 0, s, n, ops->kind, B.pr, B.pc, p_bc ? p_bc : B.pr,
@@ -540,6 +585,7 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
             RB_CHECK(bicgstab(ctx, ops->nb, q, cols_plain(ops->gcol), ops->gval, ops->gdinv, 1, B.bb, B.pb, o->tol_krylov,
                               o->max_krylov, &kb, s));
             kit_b += kb.iters[0];
+            relres_max = std::max(relres_max, kb.relres[0]);
             if (kb.status[0] != RBFFD_OK && status == RBFFD_OK) status = kb.status[0];
         }
         hipLaunchKernelGGL(k_p_scatter, dim3(gn), dim3(kBlock), 0, s, n, ops->kind, ops->bpos, B.pa, B.pb, B.pr);
@@ -568,11 +614,19 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
     // steady rate, then rotate the time levels
     hipLaunchKernelGGL(k_absdiff, dim3(nblk), dim3(kBlock), 0, s, n, dim, B.ur, u, B.part);
     hipLaunchKernelGGL(k_finish_sums, dim3(1), dim3(kBlock), 0, s, B.part, nblk, dim, n, dt, B.scal + 2);
+    // discrete continuity error of the new velocity
+    if (dim == 2)
+        hipLaunchKernelGGL(k_div_abs<2>, dim3(nblk), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs, ops->kind, B.ur,
+                           B.part);
+    else
+        hipLaunchKernelGGL(k_div_abs<3>, dim3(nblk), dim3(kBlock), 0, s, n, q, ops->col, ops->val, vs, ops->kind, B.ur,
+                           B.part);
+    hipLaunchKernelGGL(k_finish_ratio, dim3(1), dim3(kBlock), 0, s, B.part, nblk, B.scal + 4);
     RB_HIP(hipGetLastError());
     RB_HIP(hipMemcpyAsync(u_prev, u, vec * dim, hipMemcpyDeviceToDevice, s));
     RB_HIP(hipMemcpyAsync(u, B.ur, vec * dim, hipMemcpyDeviceToDevice, s));
     RB_HIP(hipMemcpyAsync(p, B.pr, vec, hipMemcpyDeviceToDevice, s));
-    RB_HIP(hipMemcpyAsync(hs + 2, B.scal + 2, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+    RB_HIP(hipMemcpyAsync(hs + 2, B.scal + 2, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
     RB_HIP(hipStreamSynchronize(s));
     st->outer_iters = outer;
     st->krylov_mom = kit_m;
@@ -581,6 +635,9 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
     st->status = status;
     st->delta = delta;
     st->eps_steady = hs[3];
+    st->div_l1 = hs[4];
+    st->final_relres_p = relres_p;
+    st->krylov_relres_max = relres_max;
     if (status != RBFFD_OK)
         return fail(status, status == RBFFD_E_NOCONV ? "simple_step: an iteration limit was reached"
                                                      : "simple_step: Krylov breakdown");

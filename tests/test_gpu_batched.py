@@ -67,7 +67,7 @@ def test_batched_fp32_matrix_matches_oracle(ctx, orc, batch, pc):
         err = float(np.abs(x - xo).max() / np.abs(xo).max())
         print(f"[batch fp32 matrix {pc}] {name}: iters {sj['iters']} status {sj['status']} "
               f"relres {sj['relres']:.1e} diff {err:.1e}", flush=True)
-        if st_o != 0:
+        if rr_o > 1e-9:   # the oracle stopped above its parity floor: no reference
             continue
         assert sj["relres"] <= 1e-7
         assert err <= 1e-5
@@ -84,7 +84,7 @@ def test_batched_matches_oracle(ctx, orc, batch, pc):
         err = float(np.abs(x - xo).max() / np.abs(xo).max())
         print(f"[batch {pc}] {name}: iters {sj['iters']} status {sj['status']} relres {sj['relres']:.1e} "
               f"oracle status {st_o} diff {err:.1e}", flush=True)
-        if st_o != 0:
+        if rr_o > 1e-9:   # the oracle stopped above its parity floor: no reference
             continue
         # at 1e-12 the attainable accuracy of a Neumann system can stop the
         # true residual just above the tolerance: check the residual itself
