@@ -318,6 +318,32 @@ int poisson_solve_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops
 int rbffd_krylov_kernel_times(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, double *x, int reps,
                               double *us, void *hip_stream);
 
+/* ---- allocation-free solve ---------------------------------------------- */
+/* For callers that cannot allocate memory during the call: code under HIP graph
+ * capture, tight serving loops, and harnesses that forbid hipMalloc.
+ * poisson_solve_noalloc solves P x = rhs exactly as poisson_solve does with
+ * precision RBFFD_FP64 and preconditioner RBFFD_PREC_JACOBI (same kernels,
+ * same launch shapes, so the same results), but its Krylov vectors, partial
+ * sums and state records live in one fixed device array of
+ * RBFFD_NOALLOC_SCRATCH_BYTES that the library holds on every device it is
+ * loaded on, until the process ends. The call allocates no device or pinned
+ * host memory: its few host read-backs go through the calling thread's stack.
+ *   ops:   operators from rbffd_assemble; their context must have been created
+ *          on the device (rbffd_ctx_create takes the array's address there)
+ *   rhs, x: device [n]; x holds the initial guess on entry, the solution on return
+ *   opts:  tol, max_iter; precision must be RBFFD_FP64 and preconditioner
+ *          RBFFD_PREC_JACOBI
+ *   stats: as poisson_solve (may be NULL)
+ * Returns RBFFD_E_ARG, before any launch, when n exceeds RBFFD_NOALLOC_MAX_N
+ * or for other options; RBFFD_E_NOCONV as poisson_solve. Every call on one
+ * device shares that device's array and leaves its contents behind (each call
+ * clears what it needs), so calls that overlap on one device race: the caller
+ * serialises them. */
+#define RBFFD_NOALLOC_SCRATCH_BYTES 67108864   /* 64 MiB per device                  */
+#define RBFFD_NOALLOC_MAX_N 1179648            /* rows the array holds (7 FP64 vectors) */
+int poisson_solve_noalloc(const rbffd_ops *ops, const double *rhs, double *x, const rbffd_krylov_opts *opts,
+                          rbffd_krylov_stats *stats, void *hip_stream);
+
 /* ---- continuous batching ------------------------------------------------ */
 /* (Sec. 3, applied to a stream of independent requests) A server keeps a
  * running batch of pressure-correction solves (FP64, or FP32 matrix values

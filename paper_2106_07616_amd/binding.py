@@ -20,13 +20,14 @@ RBFFD_OK, RBFFD_E_ARG, RBFFD_E_OOM, RBFFD_E_SINGULAR = 0, -1, -2, -3
 RBFFD_E_NOCONV, RBFFD_E_BREAKDOWN, RBFFD_E_DEVICE = -4, -5, -6
 RBFFD_FP64, RBFFD_FP32_IR, RBFFD_FP32_MATRIX = 0, 1, 2
 RBFFD_PREC_JACOBI, RBFFD_PREC_BLOCK64 = 0, 1
+RBFFD_NOALLOC_MAX_N = 1179648   # rows the allocation-free solve's scratch array holds
 STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_OOM", -3: "E_SINGULAR", -4: "E_NOCONV",
                 -5: "E_BREAKDOWN", -6: "E_DEVICE"}
 
 EXPORTED = ["rbffd_last_error", "rbffd_ctx_create", "rbffd_ctx_destroy", "rbffd_ctx_bytes_in_use",
             "rbffd_stencil_sizes", "rbffd_build_stencils", "rbffd_assemble", "rbffd_ops_free",
             "rbffd_ops_info", "rbffd_ops_export_csr", "rbffd_ops_export_block_inverse", "rbffd_apply", "rbffd_interpolate", "rbffd_cylinder_forces", "poisson_solve",
-            "poisson_solve_batched", "rbffd_krylov_kernel_times",
+            "poisson_solve_noalloc", "poisson_solve_batched", "rbffd_krylov_kernel_times",
             "rbffd_server_create", "rbffd_server_destroy", "rbffd_server_submit", "rbffd_server_run",
             "rbffd_server_poll", "simple_step", "rbffd_convdiff_lambda"]
 
@@ -93,6 +94,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                         C.POINTER(D), P, C.POINTER(I64), P]
     L.poisson_solve.argtypes = [P, P, P, P, C.POINTER(KrylovOptsT), C.POINTER(KrylovStatsT), P]
     L.rbffd_krylov_kernel_times.argtypes = [P, P, P, P, I, C.POINTER(D), P]
+    L.poisson_solve_noalloc.argtypes = [P, P, P, C.POINTER(KrylovOptsT), C.POINTER(KrylovStatsT), P]
     L.poisson_solve_batched.argtypes = [P, I, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(KrylovOptsT),
                                         C.POINTER(KrylovStatsT), P]
     L.rbffd_server_create.argtypes = [P, C.POINTER(P)]
@@ -347,6 +349,18 @@ def rbffd_krylov_kernel_times(ctx: Context, ops: Operators, rhs: torch.Tensor, x
     _check(lib().rbffd_krylov_kernel_times(ctx.handle, ops.handle, _f64(rhs, ops.n, "rhs"), _f64(x, ops.n, "x"),
                                            reps, us, _stream()))
     return dict(zip(("kv", "ks", "kt", "kx", "iteration"), list(us)))
+
+
+def poisson_solve_noalloc(ops: Operators, rhs: torch.Tensor, x: torch.Tensor, tol: float = 1e-10,
+                          max_iter: int = 5000, allow_noconv: bool = False):
+    """poisson_solve (FP64, Jacobi) with its workspace in the library's fixed
+    device scratch array: allocates nothing."""
+    o = KrylovOptsT(tol, max_iter, RBFFD_FP64, RBFFD_PREC_JACOBI)
+    s = KrylovStatsT()
+    st = lib().poisson_solve_noalloc(ops.handle, _f64(rhs, ops.n, "rhs"), _f64(x, ops.n, "x"), C.byref(o),
+                                     C.byref(s), _stream())
+    _check(st, allow=(RBFFD_E_NOCONV, RBFFD_E_BREAKDOWN) if allow_noconv else ())
+    return dict(iters=s.iters, status=s.status, relres=s.relres)
 
 
 def poisson_solve_batched(ctx: Context, ops: list, rhs: list, x: list, tol: float = 1e-10, max_iter: int = 5000,

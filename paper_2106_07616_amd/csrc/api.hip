@@ -313,6 +313,8 @@ int rbffd_ctx_create(rbffd_ctx **ctx, int hip_device, size_t hbm_budget_bytes)
     RB_HIP(hipGetDeviceCount(&ndev));
     if (hip_device < 0 || hip_device >= ndev) return fail(RBFFD_E_ARG, "no such HIP device");
     RB_HIP(hipSetDevice(hip_device));
+    // the allocation-free solve's scratch array: its address on this device
+    RB_CHECK(noalloc_init(hip_device));
     rbffd_ctx *c = new (std::nothrow) rbffd_ctx();
     if (!c) return fail(RBFFD_E_OOM, "host allocation failed");
     c->device = hip_device;
@@ -835,6 +837,35 @@ int rbffd_krylov_kernel_times(rbffd_ctx *ctx, const rbffd_ops *ops, const double
     RB_HIP(hipSetDevice(ctx->device));
     return krylov_kernel_times(ctx, ops->n, ops->q, cols_of(ops), ops->pval, ops->pdinv, rhs, x, reps, us,
                                (hipStream_t)hip_stream);
+}
+
+int poisson_solve_noalloc(const rbffd_ops *ops, const double *rhs, double *x, const rbffd_krylov_opts *opts,
+                          rbffd_krylov_stats *stats, void *hip_stream)
+{
+    if (!ops || !rhs || !x || !opts) return fail(RBFFD_E_ARG, "NULL argument");
+    if (!ops->ctx) return fail(RBFFD_E_ARG, "the operators' context was destroyed");
+    if (!(opts->tol >= 0.0) || opts->max_iter < 0) return fail(RBFFD_E_ARG, "bad Krylov options");
+    if (opts->precision != RBFFD_FP64 || opts->preconditioner != RBFFD_PREC_JACOBI)
+        return fail(RBFFD_E_ARG, "poisson_solve_noalloc takes precision RBFFD_FP64 and the Jacobi preconditioner");
+    if (pad64(ops->n) > RBFFD_NOALLOC_MAX_N)
+        return fail(RBFFD_E_ARG, "poisson_solve_noalloc: " + std::to_string(ops->n) +
+                                     " rows exceed RBFFD_NOALLOC_MAX_N (" + std::to_string(RBFFD_NOALLOC_MAX_N) + ")");
+    RB_HIP(hipSetDevice(ops->ctx->device));
+    KrylovResult res;
+    double rr = 0.0;
+    RB_CHECK(poisson_solve_noalloc_impl(ops->ctx->device, ops->n, ops->q, cols_of(ops), ops->pval, ops->pdinv, rhs, x,
+                                        opts->tol, opts->max_iter, &res, &rr, (hipStream_t)hip_stream));
+    if (stats) {
+        stats->iters = res.iters[0];
+        stats->status = res.status[0];
+        stats->refinements = 0;
+        stats->fp64_fallback = 0;
+        stats->relres = rr;
+    }
+    if (res.status[0] != RBFFD_OK)
+        return fail(res.status[0], "poisson_solve_noalloc did not converge in " + std::to_string(res.iters[0]) +
+                                       " iterations (relres " + std::to_string(rr) + ")");
+    return RBFFD_OK;
 }
 
 int poisson_solve_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops, const double *const *rhs,

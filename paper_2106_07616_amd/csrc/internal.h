@@ -304,6 +304,13 @@ int spmv(int64_t n, int q, ColIdx col, const double *val, const double *x, doubl
 // us[0] KV, us[1] KS, us[2] KT, us[3] KX, us[4] the whole iteration.
 int krylov_kernel_times(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, const double *dinv,
                         const double *b, double *x, int reps, double *us, hipStream_t s);
+// Allocation-free solve: takes the address of the fixed scratch array on the
+// current device (once per device), and runs the FP64 Jacobi BiCGSTAB of
+// poisson_solve with its workspace there.
+int noalloc_init(int device);
+int poisson_solve_noalloc_impl(int device, int64_t n, int q, ColIdx col, const double *val, const double *dinv,
+                               const double *b, double *x, double tol, int max_iter, KrylovResult *res,
+                               double *relres, hipStream_t s);
 int residual_norms(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val,
                    int nrhs, const double *b, const double *x, double *relres_out, hipStream_t s);
 

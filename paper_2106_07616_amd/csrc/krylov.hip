@@ -21,6 +21,7 @@
 // small state record every few iterations to stop.
 #include <climits>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -2223,6 +2224,91 @@ int krylov_kernel_times(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const doub
     for (int i = 0; i < 4; ++i) us[i] = 1e3 * ms[i] / reps;
     us[4] = us[3];                          // whole iteration
     us[3] = us[4] - us[0] - us[1] - us[2];  // KX: the remainder
+    return RBFFD_OK;
+}
+
+// ---- allocation-free pressure-correction solve -----------------------------
+// For callers that cannot allocate (graph capture, serving loops): the Krylov
+// vectors, partials and state records live in a fixed device array of this
+// file instead of the context's workspace. Every device that loads the library
+// holds one copy of the array until the process ends; calls on one device share
+// it, so calls that overlap on one device race. Its address on each device is
+// taken once, by the context's set-up on that device (noalloc_init), and only
+// that address is handed to kernels: in host code the array's name is not a
+// device address.
+constexpr size_t kNoAllocFixed = size_t(1) << 20;   // partials, states, residual partials
+static_assert((size_t)RBFFD_NOALLOC_SCRATCH_BYTES == kNoAllocFixed + (size_t)RBFFD_NOALLOC_MAX_N * 7 * sizeof(double),
+              "the scratch array holds the fixed region and 7 FP64 vectors of RBFFD_NOALLOC_MAX_N rows");
+static_assert(RBFFD_NOALLOC_MAX_N % 64 == 0, "whole 64-row slices");
+static_assert(sizeof(double) * (P_COUNT * kMaxRhs * kMaxBlocks + 2 * kMaxRhs * kMaxBlocks + kMaxRhs) +
+                      sizeof(KState) * kMaxRhs + 256 <= kNoAllocFixed,
+              "fixed region too small");
+
+static __device__ __align__(256) unsigned char scratch[RBFFD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+unsigned char *g_noalloc_ptr[kNoAllocDevices] = {};
+}  // namespace
+
+int noalloc_init(int device)
+{
+    if (device < 0 || device >= kNoAllocDevices) return fail(RBFFD_E_ARG, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (g_noalloc_ptr[device]) return RBFFD_OK;
+    void *ptr = nullptr;
+    RB_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(RBFFD_E_DEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+    g_noalloc_ptr[device] = (unsigned char *)ptr;
+    return RBFFD_OK;
+}
+
+int poisson_solve_noalloc_impl(int device, int64_t n, int q, ColIdx col, const double *val, const double *dinv,
+                               const double *b, double *x, double tol, int max_iter, KrylovResult *res,
+                               double *relres, hipStream_t s)
+{
+    if (device < 0 || device >= kNoAllocDevices) return fail(RBFFD_E_ARG, "device index beyond the scratch table");
+    unsigned char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_noalloc_mu);
+        base = g_noalloc_ptr[device];
+    }
+    if (!base) return fail(RBFFD_E_ARG, "the scratch array of this device was not set up (no context was created on it)");
+    const int64_t np = pad64(n);
+    if (np > RBFFD_NOALLOC_MAX_N)
+        return fail(RBFFD_E_ARG, "poisson_solve_noalloc: " + std::to_string(n) + " rows exceed the scratch limit of " +
+                                     std::to_string(RBFFD_NOALLOC_MAX_N));
+    // fixed region: partials, state records, residual partials; then the vectors
+    Work w;
+    w.part = (double *)base;
+    w.st = (KState *)(w.part + P_COUNT * kMaxRhs * kMaxBlocks);
+    double *rdev = (double *)(base + (((char *)(w.st + kMaxRhs) - (char *)base + 255) / 256) * 256);
+    unsigned char *vb = base + kNoAllocFixed;
+    const size_t vec = sizeof(double) * np;
+    w.r = vb;
+    w.rh = vb + vec;
+    w.ph = vb + 2 * vec;
+    w.v = vb + 3 * vec;
+    w.s = vb + 4 * vec;
+    w.sh = vb + 5 * vec;
+    w.t = vb + 6 * vec;
+    // host copies go through the caller's stack (pageable memory, no pinned staging)
+    KState hst[kMaxRhs];
+    double hout[kMaxRhs];
+    KrylovResult acc;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        const int left = max_iter - acc.iters[0];
+        KrylovResult r1;
+        RB_CHECK((bicgstab_t<double, 1>(n, q, col, val, dinv, b, n, x, n, tol, std::max(left, 0), &r1, w, hst, s)));
+        acc.iters[0] += r1.iters[0];
+        acc.status[0] = r1.status[0];
+        RB_CHECK(residual_norms_in(n, q, col, val, 1, b, x, rdev, hout, acc.relres, s));
+        if (r1.status[0] != RBFFD_OK || left <= 0 || acc.relres[0] <= 10.0 * tol) break;
+    }
+    if (acc.status[0] == RBFFD_OK && !(acc.relres[0] <= 10.0 * tol)) acc.status[0] = RBFFD_E_NOCONV;
+    *res = acc;
+    *relres = acc.relres[0];
     return RBFFD_OK;
 }
 
