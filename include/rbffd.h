@@ -146,6 +146,26 @@ int rbffd_stencil_sizes(int dim, const rbffd_stencil_opts *opts, int *q, int *m,
 int rbffd_build_stencils(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_stencil_opts *opts,
                          int32_t *nbr, double *w, int64_t *bad_point, void *hip_stream);
 
+/* (Sec. 2, over many independent clouds: the batched configuration) The
+ * clouds and weights of `count` clouds, each exactly as rbffd_build_stencils
+ * computes them (bitwise the same). The neighbour search runs cloud by cloud;
+ * the weights of all clouds with at most 64 unknowns (q + m) are built in one
+ * launch per (dimension, register width) present, each 64-lane block taking
+ * one point of one cloud; clouds of 65-128 unknowns take the LDS kernel one
+ * by one. Clouds may differ in size, degree, cloud size and PHS power.
+ *   clouds, opts: HOST arrays of `count` descriptions and options
+ *   nbr, w:       HOST arrays of `count` device pointers: nbr[j] [n_j][q_j]
+ *                 int32, w[j] [R_j][n_j][q_j] double (outputs)
+ *   bad_points:   optional HOST [count] out: cloud j's lowest singular point,
+ *                 or -1
+ * Periodic clouds are refused (RBFFD_E_ARG; build them one at a time), as is
+ * any invalid cloud or size, before any launch (the message names the cloud).
+ * RBFFD_E_SINGULAR if any cloud had a singular system. Synchronises the
+ * stream. */
+int rbffd_build_stencils_batched(rbffd_ctx *ctx, int count, const rbffd_cloud *clouds,
+                                 const rbffd_stencil_opts *opts, int32_t *const *nbr, double *const *w,
+                                 int64_t *bad_points, void *hip_stream);
+
 /* ---- operators ---------------------------------------------------------- */
 typedef struct rbffd_ops rbffd_ops;
 

@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_OOM", -3: "E_SINGULAR", -4: "E_NOCO
                 -5: "E_BREAKDOWN", -6: "E_DEVICE"}
 
 EXPORTED = ["rbffd_last_error", "rbffd_ctx_create", "rbffd_ctx_destroy", "rbffd_ctx_bytes_in_use",
-            "rbffd_stencil_sizes", "rbffd_build_stencils", "rbffd_assemble", "rbffd_ops_free",
+            "rbffd_stencil_sizes", "rbffd_build_stencils", "rbffd_build_stencils_batched", "rbffd_assemble",
+            "rbffd_ops_free",
             "rbffd_ops_info", "rbffd_ops_export_csr", "rbffd_ops_export_block_inverse", "rbffd_apply", "rbffd_interpolate", "rbffd_cylinder_forces", "poisson_solve",
             "poisson_solve_noalloc", "poisson_solve_batched", "rbffd_krylov_kernel_times",
             "rbffd_server_create", "rbffd_server_destroy", "rbffd_server_submit", "rbffd_server_run",
@@ -82,6 +83,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.rbffd_ctx_bytes_in_use.restype = C.c_size_t
     L.rbffd_stencil_sizes.argtypes = [I, C.POINTER(StencilOptsT), C.POINTER(I), C.POINTER(I), C.POINTER(I)]
     L.rbffd_build_stencils.argtypes = [P, C.POINTER(CloudT), C.POINTER(StencilOptsT), P, P, C.POINTER(I64), P]
+    L.rbffd_build_stencils_batched.argtypes = [P, I, C.POINTER(CloudT), C.POINTER(StencilOptsT), C.POINTER(P),
+                                               C.POINTER(P), C.POINTER(I64), P]
     L.rbffd_assemble.argtypes = [P, C.POINTER(CloudT), C.POINTER(StencilOptsT), P, P, I, C.POINTER(P), P]
     L.rbffd_ops_free.argtypes = [P]
     L.rbffd_ops_info.argtypes = [P, C.POINTER(I64), C.POINTER(I), C.POINTER(I), C.POINTER(I64)]
@@ -216,6 +219,28 @@ def rbffd_build_stencils(ctx: Context, cloud: DeviceCloud, poly_degree: int, q: 
     st = lib().rbffd_build_stencils(ctx.handle, C.byref(cs), C.byref(o), _ptr(nbr), _ptr(w), C.byref(bad), _stream())
     _check(st, allow=(RBFFD_E_SINGULAR,) if allow_singular else ())
     return nbr, w, bad.value
+
+
+def rbffd_build_stencils_batched(ctx: Context, clouds: list, poly_degrees: list, qs: list | None = None,
+                                 phs_powers: list | None = None, allow_singular: bool = False):
+    """Clouds and weights of many clouds (one weight launch per dimension):
+    returns (nbr list, w list, bad-point list)."""
+    count = len(clouds)
+    qs = qs or [0] * count
+    phs_powers = phs_powers or [3] * count
+    cl = (CloudT * count)(*[c.struct() for c in clouds])
+    op = (StencilOptsT * count)(*[StencilOptsT(ph, k, q) for ph, k, q in zip(phs_powers, poly_degrees, qs)])
+    nbrs, ws = [], []
+    for c, k, q, ph in zip(clouds, poly_degrees, qs, phs_powers):
+        qq, _, R = rbffd_stencil_sizes(c.dim, k, q, ph)
+        nbrs.append(torch.empty((c.n, qq), dtype=torch.int32, device=c.xyz.device))
+        ws.append(torch.empty((R, c.n, qq), dtype=torch.float64, device=c.xyz.device))
+    pn = (C.c_void_p * count)(*[_ptr(t) for t in nbrs])
+    pw = (C.c_void_p * count)(*[_ptr(t) for t in ws])
+    bad = (C.c_int64 * count)()
+    st = lib().rbffd_build_stencils_batched(ctx.handle, count, cl, op, pn, pw, bad, _stream())
+    _check(st, allow=(RBFFD_E_SINGULAR,) if allow_singular else ())
+    return nbrs, ws, list(bad)
 
 
 def rbffd_interpolate(ctx: Context, cloud: DeviceCloud, poly_degree: int, qxyz: torch.Tensor,

@@ -56,7 +56,7 @@ int workspace(rbffd_ctx *ctx, int slot, size_t bytes, void **p)
     Buffer &b = ctx->ws[slot];
     if (b.bytes < bytes) {
         size_t grow = bytes + bytes / 4;
-        if (slot == WS_HOST_PINNED || slot == WS_BATCH_HOST) {
+        if (slot == WS_HOST_PINNED || slot == WS_BATCH_HOST || slot == WS_BUILD_HOST) {
             if (b.ptr) (void)hipHostFree(b.ptr);
             b.ptr = nullptr;
             b.bytes = 0;
@@ -347,7 +347,7 @@ int rbffd_ctx_destroy(rbffd_ctx *ctx)
     }
     for (int s = 0; s < WS_COUNT; ++s) {
         if (!ctx->ws[s].ptr) continue;
-        if (s == WS_HOST_PINNED || s == WS_BATCH_HOST)
+        if (s == WS_HOST_PINNED || s == WS_BATCH_HOST || s == WS_BUILD_HOST)
             (void)hipHostFree(ctx->ws[s].ptr);
         else
             dev_free(ctx, ctx->ws[s].ptr, ctx->ws[s].bytes);
@@ -394,6 +394,105 @@ int rbffd_build_stencils(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_s
     int64_t bad = (*hb == INT64_MAX) ? -1 : *hb;
     if (bad_point) *bad_point = bad;
     if (bad >= 0) return fail(RBFFD_E_SINGULAR, "singular collocation system at point " + std::to_string(bad));
+    return RBFFD_OK;
+}
+
+int rbffd_build_stencils_batched(rbffd_ctx *ctx, int count, const rbffd_cloud *clouds,
+                                 const rbffd_stencil_opts *opts, int32_t *const *nbr, double *const *w,
+                                 int64_t *bad_points, void *hip_stream)
+{
+    if (!ctx) return fail(RBFFD_E_ARG, "ctx is NULL");
+    if (count < 0) return fail(RBFFD_E_ARG, "count must be >= 0");
+    if (count == 0) return RBFFD_OK;
+    if (!clouds || !opts || !nbr || !w) return fail(RBFFD_E_ARG, "NULL argument");
+    // every check before any launch
+    std::vector<int> qs(count), ms(count), width(count);
+    for (int j = 0; j < count; ++j) {
+        const rbffd_cloud *c = &clouds[j];
+        const std::string at = " (cloud " + std::to_string(j) + ")";
+        int st = check_cloud(c);
+        if (st != RBFFD_OK) return fail(st, rbffd_last_error() + at);
+        int R;
+        st = resolve_sizes(c->dim, &opts[j], &qs[j], &ms[j], &R);
+        if (st != RBFFD_OK) return fail(st, rbffd_last_error() + at);
+        if (qs[j] > c->n) return fail(RBFFD_E_ARG, "cloud size q exceeds the number of points" + at);
+        if (!nbr[j] || !w[j]) return fail(RBFFD_E_ARG, "nbr or w is NULL" + at);
+        if (qs[j] + ms[j] > 128) return fail(RBFFD_E_ARG, "collocation systems larger than 128 are not supported" + at);
+        if (is_periodic(c)) return fail(RBFFD_E_ARG, "periodic clouds are built one at a time (rbffd_build_stencils)" + at);
+        width[j] = weight_width(qs[j] + ms[j]);   // 0: 65-128 unknowns, the LDS kernel
+    }
+    RB_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (bad_points)
+        for (int j = 0; j < count; ++j) bad_points[j] = -1;
+    // neighbour search, cloud by cloud
+    for (int j = 0; j < count; ++j)
+        RB_CHECK(launch_knn(ctx, clouds[j].dim, clouds[j].n, clouds[j].xyz, qs[j], nbr[j], s));
+    // launch groups: one per (dimension, register width) present; the clouds
+    // of a group are contiguous in `order`, and so are their descriptors and
+    // singular-point slots (slot t belongs to cloud order[t])
+    std::vector<int> order;
+    std::vector<std::pair<int, int>> groups;   // (dim, width) of each launch, width 0 = LDS
+    std::vector<size_t> gstart;
+    for (int dim = 2; dim <= 3; ++dim)
+        for (int wd : {16, 24, 32, 40, 48, 56, 64, 0}) {
+            const size_t before = order.size();
+            for (int j = 0; j < count; ++j)
+                if (clouds[j].dim == dim && width[j] == wd) order.push_back(j);
+            if (order.size() > before) {
+                groups.push_back({dim, wd});
+                gstart.push_back(before);
+            }
+        }
+    gstart.push_back(order.size());
+    std::vector<WeightSys> sys(count);
+    std::vector<int64_t> blocks(groups.size(), 0);
+    for (size_t g = 0; g < groups.size(); ++g)
+        for (size_t t = gstart[g]; t < gstart[g + 1]; ++t) {
+            const int j = order[t];
+            sys[t] = WeightSys{clouds[j].xyz, nbr[j], w[j], clouds[j].n, blocks[g], qs[j], ms[j],
+                               opts[j].phs_power, width[j]};
+            blocks[g] += clouds[j].n;
+        }
+    // descriptors and singular-point slots: [sys: count][pad][bad: count]
+    const size_t dbytes = (sizeof(WeightSys) * (size_t)count + 255) / 256 * 256;
+    const size_t bytes = dbytes + sizeof(int64_t) * (size_t)count;
+    char *dev = nullptr, *host = nullptr;
+    RB_CHECK(workspace(ctx, WS_BUILD, bytes, (void **)&dev));
+    RB_CHECK(workspace(ctx, WS_BUILD_HOST, bytes, (void **)&host));
+    // the staging buffer is free: every batched build synchronises the stream
+    // before it returns
+    std::memcpy(host, sys.data(), sizeof(WeightSys) * (size_t)count);
+    int64_t *hbad = (int64_t *)(host + dbytes);
+    for (int j = 0; j < count; ++j) hbad[j] = INT64_MAX;
+    RB_HIP(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, s));
+    const WeightSys *dsys = (const WeightSys *)dev;
+    int64_t *dbad = (int64_t *)(dev + dbytes);
+    for (size_t g = 0; g < groups.size(); ++g) {
+        const int dim = groups[g].first, wd = groups[g].second;
+        const size_t t0 = gstart[g], nt = gstart[g + 1] - gstart[g];
+        if (wd > 0) {
+            RB_CHECK(launch_weights_batched(dim, wd, (int)nt, dsys + t0, blocks[g], dbad + t0, s));
+        } else {
+            // systems of 65-128 unknowns: the two-wavefront LDS kernel, cloud by cloud
+            for (size_t t = t0; t < t0 + nt; ++t) {
+                const int j = order[t];
+                RB_CHECK(launch_weights(ctx, dim, clouds[j].n, clouds[j].xyz, qs[j], nbr[j], opts[j].poly_degree,
+                                        opts[j].phs_power, w[j], dbad + t, s));
+            }
+        }
+    }
+    RB_HIP(hipMemcpyAsync(hbad, dbad, sizeof(int64_t) * (size_t)count, hipMemcpyDeviceToHost, s));
+    RB_HIP(hipStreamSynchronize(s));
+    int first_bad = -1;
+    for (int t = 0; t < count; ++t) {
+        const int j = order[t];
+        const int64_t bp = (hbad[t] == INT64_MAX) ? -1 : hbad[t];
+        if (bad_points) bad_points[j] = bp;
+        if (bp >= 0 && (first_bad < 0 || j < first_bad)) first_bad = j;
+    }
+    if (first_bad >= 0)
+        return fail(RBFFD_E_SINGULAR, "singular collocation system in cloud " + std::to_string(first_bad));
     return RBFFD_OK;
 }
 

@@ -73,6 +73,8 @@ enum WorkSlot {
     WS_BATCH,        // batched solves: descriptors, block map, partials, states, vectors
     WS_BATCH_HOST,   // batched solves: pinned host staging
     WS_HOST_PINNED,  // pinned host staging for small read-backs
+    WS_BUILD,        // batched stencil builds: cloud descriptors, singular-point slots
+    WS_BUILD_HOST,   // batched stencil builds: pinned host staging
     WS_COUNT
 };
 
@@ -230,6 +232,22 @@ int launch_knn(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q, int
                hipStream_t s);
 int launch_weights(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q, const int32_t *nbr,
                    int k, int phs, double *w, int64_t *bad_dev, hipStream_t s);
+// One cloud of a batched weight build (systems of at most 64 unknowns): its
+// points take the blocks [first_block, first_block + n) of the launch.
+struct WeightSys {
+    const double *xyz;
+    const int32_t *nbr;
+    double *w;
+    int64_t n, first_block;
+    int q, m, phs, width;
+};
+// smallest register width of the weight kernels >= ns, or 0 above 64 unknowns
+int weight_width(int ns);
+// one launch over the points of `count` clouds of dimension dim and register
+// width `width` (all of them); bad_dev[j] is cloud j's lowest singular point
+// (INT64_MAX if none; set by the caller)
+int launch_weights_batched(int dim, int width, int count, const WeightSys *sys_dev, int64_t total_blocks,
+                           int64_t *bad_dev, hipStream_t s);
 // The q nearest cloud points of nq arbitrary query points.
 int launch_knn_points(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int64_t nq, const double *qxyz, int q,
                       int32_t *nbr, hipStream_t s);

@@ -86,13 +86,28 @@ __device__ inline double *partial(double *base, int kind, int r) { return base +
 template <typename T>
 __device__ inline int64_t row_base(int64_t i, int q) { return ((i >> 6) * (int64_t)q) * 64 + (i & 63); }
 
-template <bool NARROW>
+// Matrix loads. With NT set they are non-temporal: the values and column
+// indices are read once per product, and keeping them out of the caches leaves
+// the L2 and the Infinity Cache to the gathered vector and the Krylov vectors.
+// That pays where the matrix outgrows the Infinity Cache (1.06M rows at q = 40:
+// 255 -> 239 us per BiCGSTAB iteration) and costs where it would stay there
+// (250k rows at q = 30: 45.8 -> 52.6 us), so matrix_nt() picks it by size.
+template <bool NT, typename X>
+__device__ inline X mload(const X *p)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+template <bool NARROW, bool NT = false>
 __device__ inline int32_t col_at(const ColIdx &ci, int64_t slot, int32_t cb)
 {
     if constexpr (NARROW)
-        return cb + (int32_t)ci.col16[slot];
+        return cb + (int32_t)mload<NT>(ci.col16 + slot);
     else
-        return ci.col[slot];
+        return mload<NT>(ci.col + slot);
 }
 
 // acc[r] = sum_a A[i,a] x_r[col] for the right-hand sides with act[r]; entries in
@@ -101,7 +116,7 @@ __device__ inline int32_t col_at(const ColIdx &ci, int64_t slot, int32_t cb)
 // flight. Rows accumulate in FP64 also for FP32 operands: Laplacian-like rows
 // cancel terms ~1/h^2 larger than their sum, and FP32 accumulation of that
 // cancellation makes FP32 BiCGSTAB diverge on fine clouds.
-template <bool NARROW, typename TM, typename TX, int NRHS, int U>
+template <bool NARROW, typename TM, typename TX, int NRHS, int U, bool NT>
 __device__ inline void row_dot_cols(int64_t base, int q, const ColIdx &ci, int32_t cb, const TM *__restrict__ val,
                                     const TX *__restrict__ x, int64_t xs, const bool *act, bool all, double *acc)
 {
@@ -112,8 +127,8 @@ __device__ inline void row_dot_cols(int64_t base, int q, const ColIdx &ci, int32
 #pragma unroll U
         for (int a = 0; a < q; ++a) {
             const int64_t slot = base + (int64_t)a * 64;
-            const int32_t c = col_at<NARROW>(ci, slot, cb);
-            const double v = (double)val[slot];
+            const int32_t c = col_at<NARROW, NT>(ci, slot, cb);
+            const double v = (double)mload<NT>(val + slot);
 #pragma unroll
             for (int r = 0; r < NRHS; ++r) s[r] = fma(v, (double)x[r * xs + c], s[r]);
         }
@@ -127,7 +142,7 @@ __device__ inline void row_dot_cols(int64_t base, int q, const ColIdx &ci, int32
 #pragma unroll 4
         for (int a = 0; a < q; ++a) {
             const int64_t slot = base + (int64_t)a * 64;
-            s1 = fma((double)val[slot], (double)x[r * xs + col_at<NARROW>(ci, slot, cb)], s1);
+            s1 = fma((double)mload<NT>(val + slot), (double)x[r * xs + col_at<NARROW, NT>(ci, slot, cb)], s1);
         }
         acc[r] = s1;
     }
@@ -135,7 +150,7 @@ __device__ inline void row_dot_cols(int64_t base, int q, const ColIdx &ci, int32
 
 // U is the unroll depth of the entry loop. It changes only the schedule of the
 // loads, never the order of the sums; row_unroll() picks it for a stencil width.
-template <typename TM, typename TX, int NRHS, int U = 4>
+template <typename TM, typename TX, int NRHS, int U = 4, bool NT = false>
 __device__ inline void row_dot(int64_t i, int q, const ColIdx &ci, const TM *__restrict__ val,
                                const TX *__restrict__ x, int64_t xs, const bool *act, double *acc)
 {
@@ -152,9 +167,9 @@ __device__ inline void row_dot(int64_t i, int q, const ColIdx &ci, const TM *__r
     // one 64-row slice per wavefront: the branch is uniform across the wave
     const int32_t cb = ci.cbase ? ci.cbase[i >> 6] : -1;
     if (cb >= 0)
-        row_dot_cols<true, TM, TX, NRHS, U>(base, q, ci, cb, val, x, xs, act, all, acc);
+        row_dot_cols<true, TM, TX, NRHS, U, NT>(base, q, ci, cb, val, x, xs, act, all, acc);
     else
-        row_dot_cols<false, TM, TX, NRHS, U>(base, q, ci, cb, val, x, xs, act, all, acc);
+        row_dot_cols<false, TM, TX, NRHS, U, NT>(base, q, ci, cb, val, x, xs, act, all, acc);
 }
 
 __device__ inline int logical_block() { return xcd_block(gridDim.x); }
@@ -165,8 +180,13 @@ __device__ inline int logical_block() { return xcd_block(gridDim.x); }
 // inside the kernel slowed the 3D iteration by 10%).
 inline bool row_unroll3(int q) { return q % 3 == 0 && q % 4 != 0; }
 
+// Non-temporal matrix loads for matrices beyond half of the 256 MB Infinity
+// Cache (values of val_bytes plus up to 4-byte column indices per entry).
+constexpr size_t kNtBytes = size_t(128) << 20;
+inline bool matrix_nt(int64_t n, int q, size_t val_bytes) { return (size_t)pad64(n) * q * (val_bytes + 4) > kNtBytes; }
+
 // ---- plain SpMV ------------------------------------------------------------
-template <typename T, int U>
+template <typename T, int U, bool NT>
 __global__ __launch_bounds__(kBlock) void spmv_kernel(int64_t n, int q, ColIdx col,
                                                       const T *__restrict__ val, const T *__restrict__ x,
                                                       T *__restrict__ y)
@@ -175,7 +195,7 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int64_t n, int q, ColIdx c
     if (i >= n) return;
     const bool act[1] = {true};
     double acc[1];
-    row_dot<T, T, 1, U>(i, q, col, val, x, 0, act, acc);
+    row_dot<T, T, 1, U, NT>(i, q, col, val, x, 0, act, acc);
     y[i] = (T)acc[0];
 }
 
@@ -322,7 +342,7 @@ __global__ __launch_bounds__(kKB) void k_init(int64_t n, int64_t np, int q, ColI
 
 // KV: convergence test on ||r||; v = A p-hat; partial r-hat.v. With check_only
 // set, only the test runs (after the last permitted iteration).
-template <typename T, typename TM, int NRHS, int U>
+template <typename T, typename TM, int NRHS, int U, bool NT>
 __global__ __launch_bounds__(kKB) void k_v(int64_t n, int64_t np, int q, ColIdx col, const TM *__restrict__ val,
                                            const T *__restrict__ rh, const T *__restrict__ ph, T *__restrict__ v,
                                            T *__restrict__ x, int64_t xs, double *__restrict__ part,
@@ -377,7 +397,7 @@ __global__ __launch_bounds__(kKB) void k_v(int64_t n, int64_t np, int q, ColIdx 
             if (act[k] && zero[k]) x[k * xs + i] = (T)0;
         }
         double av[NRHS];
-        row_dot<TM, T, NRHS, U>(i, q, col, val, ph, np, sp, av);
+        row_dot<TM, T, NRHS, U, NT>(i, q, col, val, ph, np, sp, av);
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
             if (!sp[k]) continue;
@@ -474,7 +494,7 @@ __global__ __launch_bounds__(kKB) void k_s(int64_t n, int64_t np, const T *__res
 
 // KT: if ||s|| is small, x += alpha p-hat and stop; else t = A s-hat and
 // partials t.s, t.t, r-hat.t
-template <typename T, typename TM, int NRHS, int U>
+template <typename T, typename TM, int NRHS, int U, bool NT>
 __global__ __launch_bounds__(kKB) void k_t(int64_t n, int64_t np, int q, ColIdx col, const TM *__restrict__ val,
                                            T *__restrict__ x, int64_t xs, const T *__restrict__ ph,
                                            const T *__restrict__ s, const T *__restrict__ sh,
@@ -514,7 +534,7 @@ __global__ __launch_bounds__(kKB) void k_t(int64_t n, int64_t np, int q, ColIdx 
         for (int k = 0; k < NRHS; ++k)
             if (half[k]) x[k * xs + i] = (T)((double)x[k * xs + i] + alpha[k] * (double)ph[k * np + i]);
         double at[NRHS];
-        row_dot<TM, T, NRHS, U>(i, q, col, val, sh, np, sp, at);
+        row_dot<TM, T, NRHS, U, NT>(i, q, col, val, sh, np, sp, at);
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) {
             if (!sp[k]) continue;
@@ -632,6 +652,22 @@ __global__ __launch_bounds__(kKB) void k_x(int64_t n, int64_t np, const T *__res
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) ps[k] = partial(part, P_RR, k);
     write_partials<NRHS>(srr, ps);
+}
+
+// The instantiation of KV and KT for a stencil width (row unroll depth) and a
+// matrix size (non-temporal matrix loads).
+template <typename T, typename TM, int NRHS>
+inline auto kv_for(int q, bool nt)
+{
+    if (row_unroll3(q)) return nt ? k_v<T, TM, NRHS, 3, true> : k_v<T, TM, NRHS, 3, false>;
+    return nt ? k_v<T, TM, NRHS, 4, true> : k_v<T, TM, NRHS, 4, false>;
+}
+
+template <typename T, typename TM, int NRHS>
+inline auto kt_for(int q, bool nt)
+{
+    if (row_unroll3(q)) return nt ? k_t<T, TM, NRHS, 3, true> : k_t<T, TM, NRHS, 3, false>;
+    return nt ? k_t<T, TM, NRHS, 4, true> : k_t<T, TM, NRHS, 4, false>;
 }
 
 // ||b - A x||^2 and ||b||^2 per right-hand side (FP64), partials then one block
@@ -818,8 +854,9 @@ int bicgstab_t(int64_t n, int q, ColIdx col, const T *val, const T *dinv, const 
     hipLaunchKernelGGL(k_clear_states, dim3(1), dim3(64), 0, s, w.st);
     hipLaunchKernelGGL((k_init<T, NRHS>), g, bl, 0, s, n, np, q, col, val, dinv, b, bs, x, xs, r, rh, ph, w.part);
     RB_HIP(hipGetLastError());
-    const auto kv = row_unroll3(q) ? k_v<T, T, NRHS, 3> : k_v<T, T, NRHS, 4>;
-    const auto kt = row_unroll3(q) ? k_t<T, T, NRHS, 3> : k_t<T, T, NRHS, 4>;
+    const bool nt = matrix_nt(n, q, sizeof(T));
+    const auto kv = kv_for<T, T, NRHS>(q, nt);
+    const auto kt = kt_for<T, T, NRHS>(q, nt);
     int it = 0, chunk = 4, phase = 0;
     bool finished = false;
     while (!finished) {
@@ -1375,7 +1412,9 @@ __global__ __launch_bounds__(kKB) void kb_resid_final(const BSys *__restrict__ s
 int spmv(int64_t n, int q, ColIdx col, const double *val, const double *x, double *y, hipStream_t s)
 {
     const int64_t nb = (n + kBlock - 1) / kBlock;
-    const auto kern = row_unroll3(q) ? spmv_kernel<double, 3> : spmv_kernel<double, 4>;
+    const bool nt = matrix_nt(n, q, sizeof(double));
+    const auto kern = row_unroll3(q) ? (nt ? spmv_kernel<double, 3, true> : spmv_kernel<double, 3, false>)
+                                     : (nt ? spmv_kernel<double, 4, true> : spmv_kernel<double, 4, false>);
     hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kBlock), 0, s, n, q, col, val, x, y);
     RB_HIP(hipGetLastError());
     return RBFFD_OK;
@@ -1416,8 +1455,9 @@ static int bicgstab_block_once(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, con
     RB_HIP(hipGetLastError());
     KState *hst = nullptr;
     RB_CHECK(host_scratch(ctx, kHostKrylov, sizeof(KState) * kMaxRhs, (void **)&hst));
-    const auto kv = row_unroll3(q) ? k_v<double, double, 1, 3> : k_v<double, double, 1, 4>;
-    const auto kt = row_unroll3(q) ? k_t<double, double, 1, 3> : k_t<double, double, 1, 4>;
+    const bool nt = matrix_nt(n, q, sizeof(double));
+    const auto kv = kv_for<double, double, 1>(q, nt);
+    const auto kt = kt_for<double, double, 1>(q, nt);
     int it = 0, chunk = 4, phase = 0;
     bool finished = false;
     while (!finished) {
@@ -1571,8 +1611,9 @@ static int bicgstab_reliable(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const
     RB_HIP(hipMemcpyAsync(xgood, x, xbytes, hipMemcpyDeviceToDevice, s));
     double prev[NRHS];
     for (int k = 0; k < NRHS; ++k) prev[k] = rr[k];
-    const auto kv = row_unroll3(q) ? k_v<T, float, NRHS, 3> : k_v<T, float, NRHS, 4>;
-    const auto kt = row_unroll3(q) ? k_t<T, float, NRHS, 3> : k_t<T, float, NRHS, 4>;
+    const bool nt = matrix_nt(n, q, sizeof(float));
+    const auto kv = kv_for<T, float, NRHS>(q, nt);
+    const auto kt = kt_for<T, float, NRHS>(q, nt);
     int it = 0, chunk = 4, phase = 0, nref = 0, last_update = 0;
     bool fallback = false;
     while (!conv && it < max_iter) {
@@ -2165,8 +2206,9 @@ int krylov_kernel_times(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const doub
     const dim3 g(nblk), bl(kKB);
     double *r = (double *)w.r, *rh = (double *)w.rh, *ph = (double *)w.ph, *v = (double *)w.v, *sv = (double *)w.s,
            *sh = (double *)w.sh, *t = (double *)w.t;
-    const auto kv = row_unroll3(q) ? k_v<double, double, 1, 3> : k_v<double, double, 1, 4>;
-    const auto kt = row_unroll3(q) ? k_t<double, double, 1, 3> : k_t<double, double, 1, 4>;
+    const bool nt = matrix_nt(n, q, sizeof(double));
+    const auto kv = kv_for<double, double, 1>(q, nt);
+    const auto kt = kt_for<double, double, 1>(q, nt);
     int phase = 0;
     auto iteration = [&]() {
         hipLaunchKernelGGL(kv, g, bl, 0, s, n, np, q, col, val, rh, ph, v, x, n, w.part, w.st, nblk, 0.0, 0, ++phase);

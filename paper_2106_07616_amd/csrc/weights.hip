@@ -96,18 +96,19 @@ __device__ inline void monomial_exponents(int alpha, int *ex)
 // With INTERP set, the kernel gives interpolation weights at off-node points
 // instead, as the LDS kernel below does in that mode: centre ctr[i], scale the
 // distance to the farthest cloud point, one right-hand side, unscaled weights.
+//
+// The work of one point lives in weights_point, so that the batched kernel
+// below runs the same arithmetic for the points of many clouds. xs and exs are
+// the block's LDS buffers (kMaxQ * DIM doubles, 64 * 3 ints).
 template <int NSP, int DIM, bool INTERP>
-__global__ __launch_bounds__(64) void weights_kernel(const double *__restrict__ xyz, const double *__restrict__ ctr,
-                                                     const int32_t *__restrict__ nbr, int64_t n, int q, int m, int phs,
-                                                     double *__restrict__ w, int64_t *__restrict__ bad)
+__device__ inline void weights_point(const double *__restrict__ xyz, const double *__restrict__ ctr,
+                                     const int32_t *__restrict__ nbr, int64_t n, int q, int m, int phs,
+                                     double *__restrict__ w, int64_t *__restrict__ bad, int64_t i, double *xs,
+                                     int *exs)
 {
     constexpr int R = INTERP ? 1 : DIM + 1;
     constexpr int NC = NSP + R;
-    __shared__ double xs[kMaxQ * DIM];
-    __shared__ int exs[64 * 3];
     const int lane = threadIdx.x;
-    const int64_t i = blockIdx.x;
-    if (i >= n) return;
     const int ns = q + m;
 
     // centre and scale: s = distance to the q-th neighbour
@@ -250,6 +251,47 @@ __global__ __launch_bounds__(64) void weights_kernel(const double *__restrict__ 
         }
     }
     if (singular && lane == 0) atomicMin((unsigned long long *)bad, (unsigned long long)i);
+}
+
+template <int NSP, int DIM, bool INTERP>
+__global__ __launch_bounds__(64) void weights_kernel(const double *__restrict__ xyz, const double *__restrict__ ctr,
+                                                     const int32_t *__restrict__ nbr, int64_t n, int q, int m, int phs,
+                                                     double *__restrict__ w, int64_t *__restrict__ bad)
+{
+    __shared__ double xs[kMaxQ * DIM];
+    __shared__ int exs[64 * 3];
+    const int64_t i = blockIdx.x;
+    if (i >= n) return;
+    weights_point<NSP, DIM, INTERP>(xyz, ctr, nbr, n, q, m, phs, w, bad, i, xs, exs);
+}
+
+// Weights of the points of many clouds in one launch, all with the register
+// width NSP: block b takes point b - first_block of the last cloud whose
+// first_block <= b (binary search over the clouds) and runs weights_point
+// with that cloud's sizes, so every point gets exactly the arithmetic of the
+// one-cloud kernel. Each cloud has its own singular-point slot. Clouds of
+// different widths go to different launches: one kernel covering every width
+// would hold the widest path's registers (248 VGPRs against 115 at width 16)
+// and run the narrow systems at a quarter of their occupancy.
+template <int NSP, int DIM>
+__global__ __launch_bounds__(64) void weights_batched_kernel(const WeightSys *__restrict__ sys, int count,
+                                                             int64_t *__restrict__ bad)
+{
+    __shared__ double xs[kMaxQ * DIM];
+    __shared__ int exs[64 * 3];
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sys[mid].first_block <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const WeightSys S = sys[lo];
+    const int64_t i = b - S.first_block;
+    if (i < 0 || i >= S.n) return;
+    weights_point<NSP, DIM, false>(S.xyz, S.xyz, S.nbr, S.n, S.q, S.m, S.phs, S.w, bad + lo, i, xs, exs);
 }
 
 // Systems of 65-128 unknowns: one workgroup of 128 x kRowThreads threads per
@@ -525,6 +567,40 @@ int launch_weights(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q,
         return RBFFD_OK;
     }
     return fail(RBFFD_E_ARG, "collocation systems larger than 128 are not supported");
+}
+
+// smallest instantiated register width >= ns (systems of at most 64 unknowns)
+int weight_width(int ns)
+{
+    for (int wdt = 16; wdt <= 64; wdt += 8)
+        if (ns <= wdt) return wdt;
+    return 0;
+}
+
+int launch_weights_batched(int dim, int width, int count, const WeightSys *sys_dev, int64_t total_blocks,
+                           int64_t *bad_dev, hipStream_t s)
+{
+    if (count <= 0 || total_blocks <= 0) return RBFFD_OK;
+    if (total_blocks > INT_MAX) return fail(RBFFD_E_ARG, "too many points in one batched build");
+    const dim3 grid((unsigned)total_blocks), block(64);
+#define RB_WB(NSP_)                                                                                          \
+    if (width == NSP_) {                                                                                     \
+        if (dim == 2)                                                                                        \
+            hipLaunchKernelGGL((weights_batched_kernel<NSP_, 2>), grid, block, 0, s, sys_dev, count, bad_dev); \
+        else                                                                                                 \
+            hipLaunchKernelGGL((weights_batched_kernel<NSP_, 3>), grid, block, 0, s, sys_dev, count, bad_dev); \
+        RB_HIP(hipGetLastError());                                                                           \
+        return RBFFD_OK;                                                                                     \
+    }
+    RB_WB(16)
+    RB_WB(24)
+    RB_WB(32)
+    RB_WB(40)
+    RB_WB(48)
+    RB_WB(56)
+    RB_WB(64)
+#undef RB_WB
+    return fail(RBFFD_E_ARG, "no register width " + std::to_string(width));
 }
 
 int launch_interp(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int64_t nq, const double *qxyz, int q,
