@@ -141,8 +141,10 @@ int rbffd_stencil_sizes(int dim, const rbffd_stencil_opts *opts, int *q, int *m,
  *   w:   device [R][n][q] double out, weights in cloud order
  *   bad_point: host out (may be NULL): lowest index of a singular stencil or -1
  * Returns RBFFD_E_SINGULAR if any stencil was singular (w is then undefined for
- * that point), RBFFD_E_ARG for duplicate points is NOT detected here: the
- * caller guarantees distinct points. */
+ * that point). Coincident points are an input error: RBFFD_E_ARG, the message
+ * naming the lowest point whose cloud holds a point at distance 0 (checked on
+ * the coordinates as given; periodic clouds are not checked for points that
+ * coincide modulo the period). */
 int rbffd_build_stencils(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_stencil_opts *opts,
                          int32_t *nbr, double *w, int64_t *bad_point, void *hip_stream);
 

@@ -383,14 +383,17 @@ int rbffd_build_stencils(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_s
     if (bad_point) *bad_point = -1;
     if (is_periodic(cloud)) return stencils_periodic(ctx, cloud, opts, q, nbr, w, bad_point, s);
     RB_CHECK(launch_knn(ctx, cloud->dim, cloud->n, cloud->xyz, q, nbr, s));
-    int64_t *bad_dev = nullptr;
-    RB_CHECK(workspace(ctx, WS_MISC, sizeof(int64_t), (void **)&bad_dev));
+    int64_t *bad_dev = nullptr;   // [0] singular stencil, [1] duplicate point
+    RB_CHECK(workspace(ctx, WS_MISC, 2 * sizeof(int64_t), (void **)&bad_dev));
+    RB_CHECK(launch_dup_check(cloud->dim, cloud->n, cloud->xyz, q, nbr, bad_dev + 1, s));
     RB_CHECK(launch_weights(ctx, cloud->dim, cloud->n, cloud->xyz, q, nbr, opts->poly_degree,
                             opts->phs_power, w, bad_dev, s));
     int64_t *hb = nullptr;
-    RB_CHECK(host_scratch(ctx, kHostMisc, sizeof(int64_t), (void **)&hb));
-    RB_HIP(hipMemcpyAsync(hb, bad_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    RB_CHECK(host_scratch(ctx, kHostMisc, 2 * sizeof(int64_t), (void **)&hb));
+    RB_HIP(hipMemcpyAsync(hb, bad_dev, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     RB_HIP(hipStreamSynchronize(s));
+    if (hb[1] != INT64_MAX)
+        return fail(RBFFD_E_ARG, "duplicate points: point " + std::to_string(hb[1]) + " coincides with another point");
     int64_t bad = (*hb == INT64_MAX) ? -1 : *hb;
     if (bad_point) *bad_point = bad;
     if (bad >= 0) return fail(RBFFD_E_SINGULAR, "singular collocation system at point " + std::to_string(bad));
@@ -454,9 +457,10 @@ int rbffd_build_stencils_batched(rbffd_ctx *ctx, int count, const rbffd_cloud *c
                                opts[j].phs_power, width[j]};
             blocks[g] += clouds[j].n;
         }
-    // descriptors and singular-point slots: [sys: count][pad][bad: count]
+    // descriptors, singular-point and duplicate-point slots:
+    // [sys: count][pad][bad: count][dup: count]
     const size_t dbytes = (sizeof(WeightSys) * (size_t)count + 255) / 256 * 256;
-    const size_t bytes = dbytes + sizeof(int64_t) * (size_t)count;
+    const size_t bytes = dbytes + 2 * sizeof(int64_t) * (size_t)count;
     char *dev = nullptr, *host = nullptr;
     RB_CHECK(workspace(ctx, WS_BUILD, bytes, (void **)&dev));
     RB_CHECK(workspace(ctx, WS_BUILD_HOST, bytes, (void **)&host));
@@ -468,6 +472,9 @@ int rbffd_build_stencils_batched(rbffd_ctx *ctx, int count, const rbffd_cloud *c
     RB_HIP(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, s));
     const WeightSys *dsys = (const WeightSys *)dev;
     int64_t *dbad = (int64_t *)(dev + dbytes);
+    int64_t *ddup = dbad + count;
+    for (int j = 0; j < count; ++j)
+        RB_CHECK(launch_dup_check(clouds[j].dim, clouds[j].n, clouds[j].xyz, qs[j], nbr[j], ddup + j, s));
     for (size_t g = 0; g < groups.size(); ++g) {
         const int dim = groups[g].first, wd = groups[g].second;
         const size_t t0 = gstart[g], nt = gstart[g + 1] - gstart[g];
@@ -482,8 +489,12 @@ int rbffd_build_stencils_batched(rbffd_ctx *ctx, int count, const rbffd_cloud *c
             }
         }
     }
-    RB_HIP(hipMemcpyAsync(hbad, dbad, sizeof(int64_t) * (size_t)count, hipMemcpyDeviceToHost, s));
+    RB_HIP(hipMemcpyAsync(hbad, dbad, 2 * sizeof(int64_t) * (size_t)count, hipMemcpyDeviceToHost, s));
     RB_HIP(hipStreamSynchronize(s));
+    for (int j = 0; j < count; ++j)
+        if (hbad[count + j] != INT64_MAX)
+            return fail(RBFFD_E_ARG, "duplicate points: point " + std::to_string(hbad[count + j]) + " of cloud " +
+                                         std::to_string(j) + " coincides with another point");
     int first_bad = -1;
     for (int t = 0; t < count; ++t) {
         const int j = order[t];

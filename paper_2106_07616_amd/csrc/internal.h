@@ -228,6 +228,10 @@ __device__ inline int xcd_block(int nblocks)
 // ---------------------------------------------------------------------------
 // launch wrappers (defined in the .hip files)
 // ---------------------------------------------------------------------------
+// Lowest point whose cloud shows a coincident point (INT64_MAX when none), in
+// device memory at *first.
+int launch_dup_check(int dim, int64_t n, const double *xyz, int q, const int32_t *nbr, int64_t *first,
+                     hipStream_t s);
 int launch_knn(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q, int32_t *nbr,
                hipStream_t s);
 int launch_weights(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q, const int32_t *nbr,

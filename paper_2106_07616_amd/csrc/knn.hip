@@ -358,6 +358,37 @@ int scan_exclusive(rbffd_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, h
     return st;
 }
 
+// Duplicate points (an input error). A point that coincides with another has
+// that point at squared distance 0 among its two nearest, since clouds are in
+// (d^2, index) order, so the first two entries of each cloud decide it: the
+// first entry is another point, or the second lies at distance 0. The lowest
+// such point goes to *first (which the launcher sets to INT64_MAX first).
+template <int DIM>
+__global__ void dup_check_kernel(const double *__restrict__ xyz, const int32_t *__restrict__ nbr, int64_t n, int q,
+                                 unsigned long long *__restrict__ first)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j0 = nbr[i * q];
+    bool dup = j0 != i;
+    if (!dup && q > 1) dup = sqdist_exact<DIM>(xyz + i * DIM, xyz + (int64_t)nbr[i * q + 1] * DIM) == 0.0;
+    if (dup) atomicMin(first, (unsigned long long)i);
+}
+
+int launch_dup_check(int dim, int64_t n, const double *xyz, int q, const int32_t *nbr, int64_t *first, hipStream_t s)
+{
+    const long long init = LLONG_MAX;
+    RB_HIP(hipMemcpyAsync(first, &init, sizeof(init), hipMemcpyHostToDevice, s));
+    if (n <= 0) return RBFFD_OK;
+    const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
+    if (dim == 2)
+        hipLaunchKernelGGL(dup_check_kernel<2>, grid, block, 0, s, xyz, nbr, n, q, (unsigned long long *)first);
+    else
+        hipLaunchKernelGGL(dup_check_kernel<3>, grid, block, 0, s, xyz, nbr, n, q, (unsigned long long *)first);
+    RB_HIP(hipGetLastError());
+    return RBFFD_OK;
+}
+
 int launch_knn(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q, int32_t *nbr, hipStream_t s)
 {
     return launch_knn_points(ctx, dim, n, xyz, n, xyz, q, nbr, s);

@@ -557,7 +557,7 @@ __global__ __launch_bounds__(kKB) void k_t(int64_t n, int64_t np, int q, ColIdx 
 
 // KX: omega = t.s / t.t; x += alpha p-hat + omega s-hat; r = s - omega t;
 // rho' = r-hat.s - omega r-hat.t; restart (r-hat = r) when rho' has vanished
-// relative to s.s; p-hat = D^-1 r + beta (p-hat - omega D^-1 v); partial r.r.
+// relative to r.r (both by linearity from the dots of s and t); p-hat = D^-1 r + beta (p-hat - omega D^-1 v); partial r.r.
 // s-hat is formed again from s and D^-1, as KS formed it (the same rounded
 // product), which saves reading it back.
 template <typename T, int NRHS>
@@ -611,7 +611,9 @@ __global__ __launch_bounds__(kKB) void k_x(int64_t n, int64_t np, const T *__res
         const double ssk = sums[5 * k + 4];
         omega[k] = (tt > 0.0) ? ts / tt : 0.0;
         const double rho1 = rs - omega[k] * rt;
-        restart[k] = fabs(rho1) < 1e-300 || fabs(rho1) < 1e-30 * ssk;
+        // ||r||^2 of the new residual r = s - omega t, by linearity
+        const double rrk = fmax(ssk - 2.0 * omega[k] * ts + omega[k] * omega[k] * tt, 0.0);
+        restart[k] = fabs(rho1) < 1e-300 || fabs(rho1) < 1e-30 * rrk;
         beta[k] = (restart[k] || omega[k] == 0.0) ? 0.0 : (rho1 / stk.rho) * (alpha[k] / omega[k]);
         if (act[k] && blockIdx.x == 0 && threadIdx.x == 0) {
             st[k].omega = omega[k];
@@ -1003,7 +1005,8 @@ __global__ __launch_bounds__(kKB) void kbj_x(int64_t n, int64_t np, BlockInv bin
     const double ts = sums[0], tt = sums[1], rs = sums[2], rt = sums[3], ssk = sums[4];
     const double omega = (tt > 0.0) ? ts / tt : 0.0;
     const double rho1 = rs - omega * rt;
-    const bool restart = fabs(rho1) < 1e-300 || fabs(rho1) < 1e-30 * ssk;
+    const double rrk = fmax(ssk - 2.0 * omega * ts + omega * omega * tt, 0.0);   // ||s - omega t||^2
+    const bool restart = fabs(rho1) < 1e-300 || fabs(rho1) < 1e-30 * rrk;
     const double beta = (restart || omega == 0.0) ? 0.0 : (rho1 / stk.rho) * (stk.alpha / omega);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st[0].omega = omega;
@@ -1330,7 +1333,8 @@ __global__ __launch_bounds__(kKB) void kb_x(const BSys *__restrict__ sys, const 
     const double ts = sums[0], tt = sums[1], rs = sums[2], rt = sums[3], ssk = sums[4];
     const double omega = (tt > 0.0) ? ts / tt : 0.0;
     const double rho1 = rs - omega * rt;
-    const bool restart = fabs(rho1) < 1e-300 || fabs(rho1) < 1e-30 * ssk;
+    const double rrk = fmax(ssk - 2.0 * omega * ts + omega * omega * tt, 0.0);   // ||s - omega t||^2
+    const bool restart = fabs(rho1) < 1e-300 || fabs(rho1) < 1e-30 * rrk;
     const double beta = (restart || omega == 0.0) ? 0.0 : (rho1 / k0.rho) * (k0.alpha / omega);
     if (blockIdx.x == S.boff && threadIdx.x == 0) {
         st[j].omega = omega;

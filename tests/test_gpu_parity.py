@@ -682,3 +682,25 @@ def test_forced_periodic_channel_fixed_point(ctx, orc, k):
           f"|u - oracle| {np.abs(ug - uo).max():.1e}", flush=True)
     assert np.abs(ug - vel).max() <= 1e-10 and np.abs(pgn - p).max() <= 1e-10
     assert np.abs(ug - uo).max() <= 1e-10 and np.abs(pgn - po).max() <= 1e-10
+
+
+@pytest.mark.gpu
+def test_duplicate_points_are_an_argument_error(ctx, orc):
+    """Coincident points are an input error (E_ARG naming the lowest point
+    whose cloud holds a coincident point), as in the oracle's neighbour
+    search; the batched build reports them per cloud. The same cloud without
+    the copy builds."""
+    import dataclasses
+    c = W.kovasznay_square(nx=8)
+    xyz = c.xyz.copy()
+    xyz[17] = xyz[5]
+    dup = dataclasses.replace(c, xyz=xyz)
+    with pytest.raises(ValueError):
+        orc.knn(dup.xyz, 20)
+    with pytest.raises(R.RbffdError) as e:
+        R.rbffd_build_stencils(ctx, R.DeviceCloud.from_numpy(dup), 3)
+    assert e.value.code == -1 and "point 5" in str(e.value)
+    with pytest.raises(R.RbffdError) as e:
+        R.rbffd_build_stencils_batched(ctx, [R.DeviceCloud.from_numpy(c), R.DeviceCloud.from_numpy(dup)], [3, 3])
+    assert e.value.code == -1 and "cloud 1" in str(e.value)
+    R.rbffd_build_stencils(ctx, R.DeviceCloud.from_numpy(c), 3)

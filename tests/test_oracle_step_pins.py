@@ -235,3 +235,73 @@ def test_outer_iteration_linearisation(orc, kind):
         assert c.kind[np.argmax(v)] == W.DIRICHLET
     else:
         assert 0.9 < rad < 1.1
+
+
+def _outer_jacobian_variant(c, ops, rho, mu, dt, a1, base, pop):
+    """Pressure-to-pressure Jacobian of one outer iteration, linearised about a
+    frozen advecting velocity `base`, under two alternative readings studied
+    for velocity walls:
+      - the p' operator is either the PHS Laplacian (`pop` = "lap", Eq.
+        pressure poisson discretised directly) or the discrete divergence of
+        the interior-corrected gradient (`pop` = "divgrad": imposing the
+        discrete continuity equation on the corrected velocity, as the
+        equation is derived in Sec. 3);
+      - the wall pressure comes from the normal momentum block (Eq. normal
+        momentum) with its right-hand side taken from time level n, so that
+        within the step it follows the interior pressure only.
+    Homogeneous Neumann p' rows at the walls and the pin row as in the
+    oracle."""
+    n, d = c.n, c.dim
+    D = [_dense(ops.col, ops.val[e]) for e in range(d)]
+    L = _dense(ops.col, ops.val[d])
+    inner = c.kind == W.INTERIOR
+    b = np.where(~inner)[0]
+    A = rho * a1 / dt * np.eye(n) - mu * L + rho * sum(base[f][:, None] * D[f] for f in range(d))
+    A[~inner] = 0.0
+    A[b, b] = 1.0
+    Ainv = np.linalg.inv(A)
+    Gi = []
+    for e in range(d):
+        G = D[e].copy()
+        G[~inner] = 0.0
+        Gi.append(G)
+    F = rho * a1 / dt * sum(D[e] @ (-Ainv @ Gi[e]) for e in range(d))
+    F[~inner] = 0.0
+    P = L.copy() if pop == "lap" else sum(D[e] @ Gi[e] for e in range(d))
+    Nd = sum(c.normal[:, e][:, None] * D[e] for e in range(d))
+    P[b] = Nd[b]
+    P[c.pin] = 0.0
+    P[c.pin, c.pin] = 1.0
+    F[c.pin] = 0.0
+    J = np.eye(n) + np.linalg.solve(P, F)
+    Po = Nd[b].copy()
+    Po[:, b] = 0.0
+    J[b] = np.linalg.solve(Nd[np.ix_(b, b)], -Po @ J)
+    return J
+
+
+def test_outer_iteration_alternative_readings(orc):
+    """The alternative readings for velocity walls, on the same 741-point
+    annulus (k = 3) with the advection of the exact Couette flow: with the
+    PHS Laplacian as the p' operator the iteration diverges at every Courant
+    number; with the divergence of the interior-corrected gradient and a
+    time-level-n wall pressure it contracts at Co 1 but not at Co 8 (the
+    paper's setting), where its largest eigenvalue besides the pressure
+    level's exceeds 1. None of the readings therefore gives the paper's
+    converged Co 8-12 Couette march."""
+    c = W.couette_annulus(0.05)
+    ops = orc.build_operators(c, 3)
+    vel, _ = W.flow_fields(c)
+    nu = c.meta["nu"]
+    lam = orc.convdiff_lambda(ops, vel, 1.0, nu)
+    rad = {}
+    for co in (1.0, 8.0):
+        for pop in ("lap", "divgrad"):
+            J = _outer_jacobian_variant(c, ops, 1.0, nu, 2 * co / lam, 1.5, vel, pop)
+            ev = np.linalg.eigvals(J)
+            ev = ev[np.abs(ev - 1.0) > 1e-7]   # the pressure level: p' leaves it unchanged
+            rad[(co, pop)] = float(np.abs(ev).max())
+    print("[outer] spectral radii", {k: round(v, 3) for k, v in rad.items()})
+    assert rad[(1.0, "lap")] > 1.5 and rad[(8.0, "lap")] > 1.5
+    assert rad[(1.0, "divgrad")] < 0.9
+    assert rad[(8.0, "divgrad")] > 1.02
