@@ -9,13 +9,19 @@
 // symmetric, the centre row of B1 = [L Phi  L P] A^{-1} is the first q entries
 // of A^{-1} b_L.
 //
-// Layout on gfx950: one wavefront per system, lane r owns row r of [A | B] in
-// registers (ns <= 64). Systems of 65-128 unknowns (2D degree 6, 3D degree 4)
-// take two wavefronts with the matrix in LDS: thread r still owns row r. The pivot search is a wave max-reduction, the pivot row
-// is broadcast lane-to-scalar with readlane, and the rank-1 update is one FP64
-// FMA per entry. On gfx950 the FP64 matrix-core rate equals the FP64 vector
-// rate, so the unblocked register LU runs against the same FP64 ceiling a
-// blocked MFMA factorisation would, without its panel/broadcast overheads.
+// Layout on gfx950, by system size:
+//  - up to 64 unknowns: one wavefront per system, lane r owns row r of [A | B]
+//    in registers; the pivot search is a DPP wave max-reduction, the pivot row
+//    is broadcast lane-to-scalar with readlane, and the rank-1 update is one
+//    FP64 FMA per entry (LU, then back substitution);
+//  - 65-128 unknowns (2D degree 6, 3D degree 4): four wavefronts per system,
+//    the matrix in LDS in MFMA tiles, blocked Gauss-Jordan in panels of four
+//    columns whose rank-4 updates run on v_mfma_f64_16x16x4 (below). Where
+//    that layout does not fit the workgroup's LDS (128 unknowns with four
+//    right-hand sides), an unblocked LDS kernel takes the system.
+// On gfx950 the FP64 matrix-core rate equals the FP64 vector rate: the MFMA
+// path pays by replacing per-entry LDS traffic and broadcasts with one
+// instruction per 16 x 16 tile, not by a higher ceiling.
 #include <cfloat>
 #include <climits>
 #include <cmath>
@@ -31,6 +37,41 @@ __device__ inline double readlane_d(double v, int lane)
     int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
     int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
     return __hiloint2double(hi, lo);
+}
+
+// Wave maximum through DPP within rows of 16 lanes, then the four row maxima.
+__device__ inline double dpp_max_step(double v, int ctrl_sel)
+{
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    int lo2, hi2;
+    switch (ctrl_sel) {
+    case 0:   // quad_perm [1, 0, 3, 2]
+        lo2 = __builtin_amdgcn_update_dpp(lo, lo, 0xB1, 0xF, 0xF, false);
+        hi2 = __builtin_amdgcn_update_dpp(hi, hi, 0xB1, 0xF, 0xF, false);
+        break;
+    case 1:   // quad_perm [2, 3, 0, 1]
+        lo2 = __builtin_amdgcn_update_dpp(lo, lo, 0x4E, 0xF, 0xF, false);
+        hi2 = __builtin_amdgcn_update_dpp(hi, hi, 0x4E, 0xF, 0xF, false);
+        break;
+    case 2:   // row_half_mirror
+        lo2 = __builtin_amdgcn_update_dpp(lo, lo, 0x141, 0xF, 0xF, false);
+        hi2 = __builtin_amdgcn_update_dpp(hi, hi, 0x141, 0xF, 0xF, false);
+        break;
+    default:  // row_mirror
+        lo2 = __builtin_amdgcn_update_dpp(lo, lo, 0x140, 0xF, 0xF, false);
+        hi2 = __builtin_amdgcn_update_dpp(hi, hi, 0x140, 0xF, 0xF, false);
+        break;
+    }
+    return fmax(v, __hiloint2double(hi2, lo2));
+}
+
+__device__ inline double wave_max_dpp(double v)
+{
+    v = dpp_max_step(v, 0);
+    v = dpp_max_step(v, 1);
+    v = dpp_max_step(v, 2);
+    v = dpp_max_step(v, 3);
+    return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
 }
 
 template <int DIM>
@@ -194,7 +235,7 @@ __device__ inline void weights_point(const double *__restrict__ xyz, const doubl
     double amax = 0.0;
 #pragma unroll
     for (int b = 0; b < NSP; ++b) amax = fmax(amax, fabs(a_[b]));
-    amax = wave_max(amax);
+    amax = wave_max_dpp(amax);
     bool active = lane < ns;
     int mystep = -1;
     bool singular = false;
@@ -202,7 +243,7 @@ __device__ inline void weights_point(const double *__restrict__ xyz, const doubl
     for (int k = 0; k < NSP; ++k) {
         if (k < ns) {
             const double v = active ? fabs(a_[k]) : -1.0;
-            const double mx = wave_max(v);
+            const double mx = wave_max_dpp(v);
             const uint64_t msk = __ballot(active && v == mx);
             const int p = msk ? (__ffsll((unsigned long long)msk) - 1) : 0;
             if (!(mx > 1e-13 * amax)) singular = true;
@@ -489,6 +530,332 @@ __global__ __launch_bounds__(128 * kRowThreads) void weights_kernel_lds(
     if (singular && tid == 0) atomicMin((unsigned long long *)bad, (unsigned long long)i);
 }
 
+// ---- blocked Gauss-Jordan with FP64 MFMA trailing updates ------------------
+//
+// The same saddle systems, solved by Gauss-Jordan elimination with partial
+// pivoting in panels of four columns. A panel is factored by one wavefront
+// (pivot search, multipliers, updates of the panel's own columns); the rest of
+// the augmented matrix then takes the panel's rank-4 update, one
+// v_mfma_f64_16x16x4 per 16 x 16 tile. Rows never move: a row that has served
+// as pivot stays where it is, and Gauss-Jordan eliminates each pivot column
+// from every other row, including earlier pivot rows, so the matrix ends as a
+// permuted diagonal and no back substitution follows; unknown k is the pivot
+// row's right-hand side over its pivot. The pivot rule is that of the LU
+// kernels above (largest |a| among rows not yet pivots, ties to the lowest row;
+// singular below 1e-13 max|A|).
+//
+// The matrix lives in LDS tile by tile in the MFMA accumulator layout, so a
+// tile's C operand is two 16-byte reads per lane without bank conflicts.
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// LDS slot of entry (i, j): tile (i / 16, j / 16) holds 256 doubles; within a
+// tile, lane 16 * (i % 4) + j % 16 keeps rows 4 v + l / 16 at v = (i % 16) / 4
+// (the 16x16x4 FP64 MFMA's C/D layout on gfx950: column l % 16, rows
+// l / 16, 4 + l / 16, 8 + l / 16, 12 + l / 16 in its four registers).
+__device__ inline int gj_slot(int i, int j, int tc)
+{
+    return ((((i >> 4) * tc + (j >> 4)) * 64 + 16 * (i & 3) + (j & 15)) << 2) + ((i & 15) >> 2);
+}
+
+// The same maximum with the cross-row steps as DPP row broadcasts (rows 1
+// and 3 take lane 15 of the row before, then rows 2 and 3 take lane 31), so
+// that lane 63 holds it: one readlane instead of four.
+__device__ inline double dpp_bcast_max(double v, int sel)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    int lo2, hi2;
+    if (sel == 0) {   // row_bcast:15 into rows 1 and 3
+        lo2 = __builtin_amdgcn_update_dpp(lo, lo, 0x142, 0xA, 0xF, false);
+        hi2 = __builtin_amdgcn_update_dpp(hi, hi, 0x142, 0xA, 0xF, false);
+    } else {          // row_bcast:31 into rows 2 and 3
+        lo2 = __builtin_amdgcn_update_dpp(lo, lo, 0x143, 0xC, 0xF, false);
+        hi2 = __builtin_amdgcn_update_dpp(hi, hi, 0x143, 0xC, 0xF, false);
+    }
+    return fmax(v, __hiloint2double(hi2, lo2));
+}
+
+__device__ inline double wave_max_bcast(double v)
+{
+    v = dpp_max_step(v, 0);
+    v = dpp_max_step(v, 1);
+    v = dpp_max_step(v, 2);
+    v = dpp_max_step(v, 3);
+    v = dpp_bcast_max(v, 0);
+    v = dpp_bcast_max(v, 1);
+    return readlane_d(v, 63);
+}
+
+// Entry (i, j) of the augmented system [A | B] of a point: rows and columns
+// beyond ns (and beyond ns + R) are zero padding. xs holds the scaled cloud
+// (q x DIM), exs the monomial exponents.
+template <int DIM, bool INTERP>
+__device__ inline double gj_entry(int i, int j, int q, int ns, int phs, const double *xs, const int *exs)
+{
+    constexpr int R = INTERP ? 1 : DIM + 1;
+    if (i >= ns || j >= ns + R) return 0.0;
+    if (j < ns) {
+        if (i < q) {
+            if (j < q) {
+                const double r = sqrt(sqdist_exact<DIM>(xs + i * DIM, xs + j * DIM));
+                return (phs == 3) ? r * r * r : r * r * r * r * r;
+            }
+            return monomial<DIM>(exs + (j - q) * 3, xs + i * DIM);
+        }
+        if (j < q) return monomial<DIM>(exs + (i - q) * 3, xs + j * DIM);
+        return 0.0;
+    }
+    const int r = j - ns;
+    if (INTERP) {
+        if (i < q) {
+            double rr = 0.0;
+            for (int d = 0; d < DIM; ++d) rr = rr + xs[i * DIM + d] * xs[i * DIM + d];
+            const double rad = sqrt(rr);
+            return (phs == 3) ? rad * rad * rad : rad * rad * rad * rad * rad;
+        }
+        const int *ex = exs + (i - q) * 3;
+        return (ex[0] + ex[1] + ex[2] == 0) ? 1.0 : 0.0;
+    }
+    if (i < q) {
+        double rr = 0.0;
+        for (int d = 0; d < DIM; ++d) rr = rr + xs[i * DIM + d] * xs[i * DIM + d];
+        const double rad = sqrt(rr);
+        const double rp2 = (phs == 3) ? rad : rad * rad * rad;
+        if (r < DIM) return -(double)phs * rp2 * xs[i * DIM + r];
+        return (double)(phs * (phs + DIM - 2)) * rp2;
+    }
+    const int *ex = exs + (i - q) * 3;
+    const int tot = ex[0] + ex[1] + ex[2];
+    if (r < DIM) return (tot == 1 && ex[r] == 1) ? 1.0 : 0.0;
+    int two = 0;
+    for (int d = 0; d < DIM; ++d) two += (ex[d] == 2);
+    return (tot == 2 && two == 1) ? 2.0 : 0.0;
+}
+
+// LDS bytes of one system: matrix tiles, two panels' multipliers, pivots,
+// two panels' pivot-row multipliers, the scaled cloud.
+__host__ __device__ inline size_t gj_lds_bytes(int q, int ns, int nc, int dim)
+{
+    const int tr = (ns + 15) >> 4, tc = (nc + 15) >> 4;
+    return sizeof(double) * ((size_t)tr * tc * 256 + 2 * (size_t)tr * 64 + (size_t)ns + 32 + (size_t)q * dim);
+}
+
+// Factor the panel of columns c0 .. c0 + np - 1 (np <= 4; wavefront 0): rows
+// lane + 64 h in registers, pivot by the rule above, every row but the pivot
+// eliminates the column from the panel's later columns. Writes -L to Lbuf in the
+// MFMA A layout, the pivot rows' multipliers for earlier panel columns to lpb,
+// and the pivot rows and values.
+template <int RPL>
+__device__ inline void gj_factor_panel(const double *M, int tr, int tc, int c0, int np, bool *act, double amax,
+                                       bool &singular, double *Lbuf, double *lpb, int *prow, double *pv, int *sflag,
+                                       int lane)
+{
+    double a[RPL][4], l[RPL][4];
+#pragma unroll
+    for (int h = 0; h < RPL; ++h)
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+            const int i = lane + 64 * h;
+            a[h][cc] = (cc < np && i < tr * 16) ? M[gj_slot(i, c0 + cc, tc)] : 0.0;
+            l[h][cc] = 0.0;
+        }
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+        if (cc < np) {
+            double best = -1.0;
+#pragma unroll
+            for (int h = 0; h < RPL; ++h) best = fmax(best, act[h] ? fabs(a[h][cc]) : -1.0);
+            const double mx = wave_max_bcast(best);
+            int p = 0;
+#pragma unroll
+            for (int h = RPL - 1; h >= 0; --h) {
+                const uint64_t msk = __ballot(act[h] && fabs(a[h][cc]) == mx);
+                if (msk) p = 64 * h + (__ffsll((unsigned long long)msk) - 1);
+            }
+            if (!(mx > 1e-13 * amax)) singular = true;
+            const int ph = p >> 6, pl = p & 63;
+            double prw[4];
+#pragma unroll
+            for (int c2 = 0; c2 < 4; ++c2) {
+                double src = a[0][c2];
+#pragma unroll
+                for (int h = 1; h < RPL; ++h)
+                    if (ph == h) src = a[h][c2];
+                prw[c2] = readlane_d(src, pl);
+            }
+            const double piv = singular ? 1.0 : prw[cc];
+            // 1 / piv: hardware reciprocal and two Newton steps
+            double rp = __builtin_amdgcn_rcp(piv);
+            rp = fma(rp, fma(-piv, rp, 1.0), rp);
+            rp = fma(rp, fma(-piv, rp, 1.0), rp);
+#pragma unroll
+            for (int h = 0; h < RPL; ++h) {
+                const bool me = (lane + 64 * h) == p;
+                if (me) act[h] = false;
+                const double mul = me ? 0.0 : a[h][cc] * rp;
+                l[h][cc] = mul;
+#pragma unroll
+                for (int c2 = cc + 1; c2 < 4; ++c2) a[h][c2] = fma(-mul, prw[c2], a[h][c2]);
+                if (me)
+#pragma unroll
+                    for (int c2 = 0; c2 < cc; ++c2) lpb[cc * 4 + c2] = l[h][c2];
+            }
+            if (lane == 0) {
+                prow[c0 + cc] = p;
+                pv[c0 + cc] = piv;
+                *sflag = singular;
+            }
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) {
+        const int i = lane + 64 * h;
+        if (i < tr * 16)
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) Lbuf[(i >> 4) * 64 + (i & 15) + 16 * cc] = -l[h][cc];
+    }
+}
+
+// Panel c0's rank-np update of tile column J, by the one wavefront that owns
+// the column for this panel: its B operand holds the panel's U rows, by forward
+// substitution over the pivot rows (u_c[j] = a[p_c][j] - sum_{c' < c}
+// L[p_c][c'] u_c'[j]), all read before the column's first write; then one MFMA
+// per row tile. Columns up to the panel's last get B = 0 and stay as they are.
+__device__ inline void gj_update_column(double *M, int tr, int tc, int J, int c0, int np, const int *prow,
+                                        const double *lpb, const double *Lbuf, int lane)
+{
+    const int cend = c0 + np, cl = lane >> 4, j = 16 * J + (lane & 15);
+    double u[4], bv = 0.0;
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+        double x = 0.0;
+        if (cc < np && j >= cend) {
+            x = M[gj_slot(prow[c0 + cc], j, tc)];
+#pragma unroll
+            for (int c2 = 0; c2 < cc; ++c2) x = fma(-lpb[cc * 4 + c2], u[c2], x);
+        }
+        u[cc] = x;
+        if (cc == cl) bv = x;
+    }
+    for (int I = 0; I < tr; ++I) {
+        const double av = Lbuf[I * 64 + lane];
+        double2 *cp = (double2 *)(M + (((I * tc + J) * 64 + lane) << 2));
+        const double2 c01 = cp[0], c23 = cp[1];
+        v4d acc = {c01.x, c01.y, c23.x, c23.y};
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        cp[0] = make_double2(acc[0], acc[1]);
+        cp[1] = make_double2(acc[2], acc[3]);
+    }
+}
+
+// NW wavefronts per system; RPL rows per lane in the panel factorization
+// (ns <= 64 * RPL).
+template <int DIM, bool INTERP, int NW, int RPL>
+__global__ __launch_bounds__(64 * NW) void weights_kernel_gj(const double *__restrict__ xyz,
+                                                             const double *__restrict__ ctr,
+                                                             const int32_t *__restrict__ nbr, int64_t n, int q, int m,
+                                                             int phs, double *__restrict__ w,
+                                                             int64_t *__restrict__ bad)
+{
+    constexpr int R = INTERP ? 1 : DIM + 1;
+    constexpr int NT = 64 * NW;
+    extern __shared__ __attribute__((aligned(16))) double gsm[];
+    __shared__ int exs[128 * 3];
+    __shared__ int prow[128];
+    __shared__ double redm[NW];
+    __shared__ int sflag;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t i0 = blockIdx.x;
+    if (i0 >= n) return;
+    const int ns = q + m, nc = ns + R;
+    const int tr = (ns + 15) >> 4, tc = (nc + 15) >> 4;
+    double *M = gsm;                      // tr * tc tiles of 256
+    double *Lb = M + tr * tc * 256;       // [2][tr][64]: -L of a panel in the MFMA A layout
+    double *pv = Lb + 2 * tr * 64;        // [ns] pivot values
+    double *lp = pv + ns;                 // [2][4][4] multipliers of a panel's pivot rows
+    double *xs = lp + 32;                 // [q][DIM] scaled cloud
+
+    // centre and scale: s = distance to the q-th neighbour (interpolation:
+    // to the farthest cloud point, the same point in distance order)
+    double c[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) c[d] = ctr[i0 * DIM + d];
+    const int64_t jl = nbr[i0 * q + q - 1];
+    const double s = sqrt(sqdist_exact<DIM>(c, xyz + jl * DIM));
+    for (int a = tid; a < q; a += NT) {
+        const int64_t j = nbr[i0 * q + a];
+        for (int d = 0; d < DIM; ++d) xs[a * DIM + d] = (xyz[j * DIM + d] - c[d]) / s;
+    }
+    if (tid < m) {
+        int ex[3];
+        monomial_exponents<DIM>(tid, ex);
+        exs[tid * 3 + 0] = ex[0];
+        exs[tid * 3 + 1] = ex[1];
+        exs[tid * 3 + 2] = ex[2];
+    }
+    __syncthreads();
+
+    // the matrix, slot by slot (slot order: conflict-free LDS writes)
+    double amax = 0.0;
+    const int nslot = tr * tc * 256;
+    for (int e = tid; e < nslot; e += NT) {
+        const int v = e & 3, l = (e >> 2) & 63, t = e >> 8;
+        const int I = t / tc, J = t - I * tc;
+        const int i = 16 * I + 4 * v + (l >> 4), j = 16 * J + (l & 15);
+        const double a = gj_entry<DIM, INTERP>(i, j, q, ns, phs, xs, exs);
+        M[e] = a;
+        if (j < ns) amax = fmax(amax, fabs(a));
+    }
+    amax = wave_max_dpp(amax);
+    if (lane == 0) redm[wv] = amax;
+    __syncthreads();
+    amax = 0.0;
+#pragma unroll
+    for (int u = 0; u < NW; ++u) amax = fmax(amax, redm[u]);
+
+    bool act[RPL];
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) act[h] = lane + 64 * h < ns;
+    bool singular = false;
+    if (tid == 0) sflag = 0;   // ordered before its readers by the panels' barriers
+    // Look-ahead: while the other wavefronts apply panel c0's update to their
+    // tile columns, wavefront 0 updates tile column J0 (which holds the next
+    // panel) and factors the next panel, so one barrier per panel orders all.
+    // Lb and lp are double-buffered by panel parity.
+    if (wv == 0) gj_factor_panel<RPL>(M, tr, tc, 0, min(4, ns), act, amax, singular, Lb, lp, prow, pv, &sflag, lane);
+    __syncthreads();
+    for (int c0 = 0; c0 < ns; c0 += 4) {
+        const int np = min(4, ns - c0), cend = c0 + np, J0 = cend >> 4, buf = (c0 >> 2) & 1;
+        const double *Lcur = Lb + buf * tr * 64;
+        const double *lcur = lp + buf * 16;
+        if (wv == 0) {
+            if (J0 < tc) gj_update_column(M, tr, tc, J0, c0, np, prow, lcur, Lcur, lane);
+            if (cend < ns)
+                gj_factor_panel<RPL>(M, tr, tc, cend, min(4, ns - cend), act, amax, singular,
+                                     Lb + (buf ^ 1) * tr * 64, lp + (buf ^ 1) * 16, prow, pv, &sflag, lane);
+        }
+        if (NW == 1 || wv > 0) {
+            const int step = (NW == 1) ? 1 : NW - 1;
+            for (int J = J0 + ((NW == 1) ? 1 : wv); J < tc; J += step)
+                gj_update_column(M, tr, tc, J, c0, np, prow, lcur, Lcur, lane);
+        }
+        __syncthreads();
+    }
+
+    // unknown k = right-hand side of its pivot row over the pivot
+    singular = sflag != 0;
+    for (int k = tid; k < q; k += NT) {
+        const int p = prow[k];
+        const double dg = singular ? 1.0 : pv[k];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double x = M[gj_slot(p, ns + r, tc)] / dg;
+            const double sc = INTERP ? 1.0 : ((r < DIM) ? s : s * s);
+            w[(int64_t)r * n * q + i0 * q + k] = INTERP ? x : x / sc;
+        }
+    }
+    if (singular && tid == 0) atomicMin((unsigned long long *)bad, (unsigned long long)i0);
+}
+
 // out[f][j] = sum_a w[j][a] field_f[nbr[j][a]], in cloud order a = 0..q-1
 __global__ __launch_bounds__(kBlock) void interp_apply(int64_t nq, int q, const int32_t *__restrict__ nbr,
                                                        const double *__restrict__ w, int nfield, int64_t n,
@@ -543,10 +910,27 @@ int launch_weights(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q,
     if (ns <= 128) {
         // systems of 65-128 unknowns: the matrix lives in LDS
         const int R = dim + 1;
-        const size_t lds = sizeof(double) * (size_t)(ns + R) * 128;
         int dev = 0, lim = 0;
         RB_HIP(hipGetDevice(&dev));
         RB_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        const size_t gjl = gj_lds_bytes(q, ns, ns + R, dim);
+        if (gjl + 2048 <= (size_t)lim) {
+            // blocked Gauss-Jordan, MFMA trailing updates, four wavefronts
+            if (dim == 2) {
+                RB_HIP(hipFuncSetAttribute((const void *)weights_kernel_gj<2, false, 4, 2>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)gjl));
+                hipLaunchKernelGGL((weights_kernel_gj<2, false, 4, 2>), grid, dim3(256), gjl, s, xyz, xyz, nbr, n, q,
+                                   m, phs, w, bad_dev);
+            } else {
+                RB_HIP(hipFuncSetAttribute((const void *)weights_kernel_gj<3, false, 4, 2>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)gjl));
+                hipLaunchKernelGGL((weights_kernel_gj<3, false, 4, 2>), grid, dim3(256), gjl, s, xyz, xyz, nbr, n, q,
+                                   m, phs, w, bad_dev);
+            }
+            RB_HIP(hipGetLastError());
+            return RBFFD_OK;
+        }
+        const size_t lds = sizeof(double) * (size_t)(ns + R) * 128;
         const size_t fixed = sizeof(double) * (kMaxQ * 3 + 4 + 2 * kRowThreads) + sizeof(int) * (128 * 3 + 4 + 128);
         if (lds + fixed > (size_t)lim)
             return fail(RBFFD_E_ARG, "collocation system needs " + std::to_string(lds + fixed) +
@@ -640,12 +1024,29 @@ int launch_interp(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int64_t
     RB_INTERP(56)
     RB_INTERP(64)
 #undef RB_INTERP
+    int dev = 0, lim = 0;
+    RB_HIP(hipGetDevice(&dev));
+    RB_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     if (!launched) {
         // 65-128 unknowns: one workgroup per query point, the matrix in LDS
+        const size_t gjl = gj_lds_bytes(q, ns, ns + 1, dim);
+        if (gjl + 2048 <= (size_t)lim) {
+            if (dim == 2) {
+                RB_HIP(hipFuncSetAttribute((const void *)weights_kernel_gj<2, true, 4, 2>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)gjl));
+                hipLaunchKernelGGL((weights_kernel_gj<2, true, 4, 2>), dim3((unsigned)nq), dim3(256), gjl, s, xyz,
+                                   qxyz, nbr, nq, q, m, phs, w, bad_dev);
+            } else {
+                RB_HIP(hipFuncSetAttribute((const void *)weights_kernel_gj<3, true, 4, 2>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)gjl));
+                hipLaunchKernelGGL((weights_kernel_gj<3, true, 4, 2>), dim3((unsigned)nq), dim3(256), gjl, s, xyz,
+                                   qxyz, nbr, nq, q, m, phs, w, bad_dev);
+            }
+            launched = true;
+        }
+    }
+    if (!launched) {
         const size_t lds = sizeof(double) * (size_t)(ns + 1) * 128;
-        int dev = 0, lim = 0;
-        RB_HIP(hipGetDevice(&dev));
-        RB_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
         const size_t fixed =
             sizeof(double) * (kMaxQ * 3 + 4 + 2 * kRowThreads) + sizeof(int) * (128 * 3 + 4 + 128);
         if (lds + fixed > (size_t)lim) return fail(RBFFD_E_ARG, "interpolation system does not fit the device's LDS");
