@@ -921,6 +921,32 @@ def hbm_resident_section(args, R, W, torch, ctx):
     }
 
 
+def weights_only(args):
+    """Stencil builds of one cloud (kNN and weights), three times after one
+    untimed build, with the mean time and the weights' points per second."""
+    import torch
+
+    import paper_2106_07616_amd as R
+    import workloads as W
+    cloud, k = {"tg250k_k4": (lambda: W.taylor_green_disk(), 4),
+                "cube40_k4": (lambda: W.beltrami_cube(n=40), 4),
+                "tg60k_k6": (lambda: W.taylor_green_disk(r=0.021), 6)}[args.weights_only]
+    cloud = cloud()
+    ctx = R.Context(0)
+    dc = R.DeviceCloud.from_numpy(cloud)
+    R.rbffd_build_stencils(ctx, dc, k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        R.rbffd_build_stencils(ctx, dc, k)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 3
+    q, m, _ = R.rbffd_stencil_sizes(cloud.dim, k)
+    print(json.dumps({"cloud": args.weights_only, "n": cloud.n, "unknowns": q + m, "build_ms": round(dt * 1e3, 3),
+                      "points_per_s": round(cloud.n / dt, 0)}), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -956,6 +982,10 @@ def main():
     ap.add_argument("--counters-only", action="store_true",
                     help="run only the SpMV timing, the timed BiCGSTAB kernels and a copy of known size "
                          "(for hardware counter runs)")
+    ap.add_argument("--weights-only", choices=["tg250k_k4", "cube40_k4", "tg60k_k6"], default=None,
+                    help="only build the stencils of one cloud a few times (for weight-kernel profiles): the "
+                         "250k Taylor-Green disk at degree 4 (45 unknowns), a 40^3 cube at degree 4 (105) or a "
+                         "60k Taylor-Green disk at degree 6 (84)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; runs on several GPUs are not supported (pass --gpus 1)", file=sys.stderr)
@@ -971,6 +1001,9 @@ def main():
         return
     if args.workload == "post":
         post_bench(args)
+        return
+    if args.weights_only:
+        weights_only(args)
         return
 
     import torch

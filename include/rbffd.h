@@ -101,6 +101,36 @@ int rbffd_ctx_create(rbffd_ctx **ctx, int hip_device, size_t hbm_budget_bytes);
 int rbffd_ctx_destroy(rbffd_ctx *ctx);
 /* Device bytes currently charged to the context (workspace + live operators). */
 size_t rbffd_ctx_bytes_in_use(const rbffd_ctx *ctx);
+/* (Sec. 3: the BiCGSTAB solves of each outer iteration) Whether the context's
+ * FP64 Jacobi BiCGSTAB solves (the momentum and pressure-correction solves of
+ * simple_step, and poisson_solve) launch their iteration chunks as HIP graphs:
+ * enable = 1 captures each distinct chunk once, on a stream the context owns,
+ * and replays it on the caller's stream; 0 (the default) launches the kernels
+ * one by one. The results are bitwise the same either way. A capture is
+ * invalidated when another thread synchronises the whole device meanwhile:
+ * the solve then launches that chunk directly and the context returns to
+ * direct launches (so enable graphs where no other thread does). A captured graph
+ * holds the addresses of the vectors it was captured with, so it is replayed
+ * only for the same operators, solution vector and workspace; at most 32 are
+ * kept per context (least recently used evicted), and rbffd_ctx_destroy
+ * releases them. RBFFD_E_ARG for a NULL ctx or enable outside {0, 1}. */
+int rbffd_ctx_set_graphs(rbffd_ctx *ctx, int enable);
+/* (Sec. 3: the BiCGSTAB solves) Which kernels run the FP64 Jacobi BiCGSTAB
+ * solves of systems of n rows and stencil width q under this context
+ * (simple_step's momentum, boundary-pressure and pressure-correction solves,
+ * poisson_solve):
+ *   choice 0            the multi-kernel iteration (four kernels per iteration,
+ *                       the grid spread over the whole GPU);
+ *   256, 512, 1024      one workgroup of that many threads runs the entire
+ *                       solve in one kernel;
+ *   -1                  forget the choice: the multi-kernel iteration, the
+ *                       default for every size.
+ * The paths iterate identically but sum their dot products in different orders,
+ * so results differ at rounding level between choices (each is deterministic).
+ * Batched solves (poisson_solve_batched) and poisson_solve_noalloc always take
+ * the multi-kernel iteration.
+ * RBFFD_E_ARG for a NULL ctx, n or q < 1, or another choice. */
+int rbffd_ctx_set_solver_choice(rbffd_ctx *ctx, int64_t n, int q, int choice);
 
 /* ---- inputs ------------------------------------------------------------ */
 typedef struct {
@@ -291,6 +321,16 @@ typedef struct {
  * rhs, x: device [n]. */
 int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, double *x,
                   const rbffd_krylov_opts *opts, rbffd_krylov_stats *stats, void *hip_stream);
+/* (Sec. 3) Autotuner: time `iterations` (>= 4) FP64 Jacobi BiCGSTAB iterations
+ * of the operators' pressure-correction system (a fixed right-hand side, zero
+ * start, in scratch memory the call allocates and frees) on each path, the
+ * multi-kernel iteration and the one-workgroup solver with 256, 512 and 1024
+ * threads (the latter only up to 65,536 rows), and record the fastest for the
+ * system's (n, q) as rbffd_ctx_set_solver_choice would. Outputs (host, each
+ * may be NULL): *choice, and us_per_iter[4] = microseconds per iteration of
+ * each candidate in that order (-1 where not tried). Synchronous. */
+int rbffd_autotune_krylov(rbffd_ctx *ctx, const rbffd_ops *ops, int iterations, int *choice,
+                          double *us_per_iter, void *hip_stream);
 
 /* (Sec. 3, "preconditioned BiCGSTAB"; the batched configuration of many
  * independent clouds) Solve P_j x_j = rhs_j for `count` independent
@@ -344,8 +384,10 @@ int rbffd_krylov_kernel_times(rbffd_ctx *ctx, const rbffd_ops *ops, const double
 /* For callers that cannot allocate memory during the call: code under HIP graph
  * capture, tight serving loops, and harnesses that forbid hipMalloc.
  * poisson_solve_noalloc solves P x = rhs exactly as poisson_solve does with
- * precision RBFFD_FP64 and preconditioner RBFFD_PREC_JACOBI (same kernels,
- * same launch shapes, so the same results), but its Krylov vectors, partial
+ * precision RBFFD_FP64 and preconditioner RBFFD_PREC_JACOBI by the default
+ * multi-kernel iteration (a rbffd_ctx_set_solver_choice override applies to
+ * poisson_solve only) with the same kernels and launch shapes, so the same
+ * results, but it never replays HIP graphs, and its Krylov vectors, partial
  * sums and state records live in one fixed device array of
  * RBFFD_NOALLOC_SCRATCH_BYTES that the library holds on every device it is
  * loaded on, until the process ends. The call allocates no device or pinned

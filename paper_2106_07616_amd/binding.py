@@ -25,6 +25,7 @@ STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_OOM", -3: "E_SINGULAR", -4: "E_NOCO
                 -5: "E_BREAKDOWN", -6: "E_DEVICE"}
 
 EXPORTED = ["rbffd_last_error", "rbffd_ctx_create", "rbffd_ctx_destroy", "rbffd_ctx_bytes_in_use",
+            "rbffd_ctx_set_graphs", "rbffd_ctx_set_solver_choice", "rbffd_autotune_krylov",
             "rbffd_stencil_sizes", "rbffd_build_stencils", "rbffd_build_stencils_batched", "rbffd_assemble",
             "rbffd_ops_free",
             "rbffd_ops_info", "rbffd_ops_export_csr", "rbffd_ops_export_block_inverse", "rbffd_apply", "rbffd_interpolate", "rbffd_cylinder_forces", "poisson_solve",
@@ -80,6 +81,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.rbffd_ctx_create.argtypes = [C.POINTER(P), I, C.c_size_t]
     L.rbffd_ctx_destroy.argtypes = [P]
     L.rbffd_ctx_bytes_in_use.argtypes = [P]
+    L.rbffd_ctx_set_graphs.argtypes = [P, I]
+    L.rbffd_ctx_set_solver_choice.argtypes = [P, I64, I, I]
+    L.rbffd_autotune_krylov.argtypes = [P, P, I, C.POINTER(I), C.POINTER(D), P]
     L.rbffd_ctx_bytes_in_use.restype = C.c_size_t
     L.rbffd_stencil_sizes.argtypes = [I, C.POINTER(StencilOptsT), C.POINTER(I), C.POINTER(I), C.POINTER(I)]
     L.rbffd_build_stencils.argtypes = [P, C.POINTER(CloudT), C.POINTER(StencilOptsT), P, P, C.POINTER(I64), P]
@@ -163,6 +167,16 @@ class Context:
 
     def bytes_in_use(self) -> int:
         return lib().rbffd_ctx_bytes_in_use(self.handle)
+
+    def set_solver_choice(self, n: int, q: int, choice: int):
+        """FP64 Jacobi BiCGSTAB path for systems of (n, q): 0 multi-kernel,
+        256 / 512 / 1024 one workgroup of that many threads, -1 the default."""
+        _check(lib().rbffd_ctx_set_solver_choice(self.handle, int(n), int(q), int(choice)))
+
+    def set_graphs(self, enable: bool):
+        """Replay BiCGSTAB iteration chunks as HIP graphs or launch them kernel
+        by kernel (the default); the results are bitwise the same."""
+        _check(lib().rbffd_ctx_set_graphs(self.handle, int(bool(enable))))
 
     def close(self):
         if self.handle:
@@ -374,6 +388,15 @@ def rbffd_krylov_kernel_times(ctx: Context, ops: Operators, rhs: torch.Tensor, x
     _check(lib().rbffd_krylov_kernel_times(ctx.handle, ops.handle, _f64(rhs, ops.n, "rhs"), _f64(x, ops.n, "x"),
                                            reps, us, _stream()))
     return dict(zip(("kv", "ks", "kt", "kx", "iteration"), list(us)))
+
+
+def rbffd_autotune_krylov(ctx: Context, ops: Operators, iterations: int = 40):
+    """Time the solver paths on the operators' pressure-correction system and
+    record the fastest for its size: returns (choice, {choice: us/iteration})."""
+    ch = C.c_int(-1)
+    us = (C.c_double * 4)()
+    _check(lib().rbffd_autotune_krylov(ctx.handle, ops.handle, iterations, C.byref(ch), us, _stream()))
+    return ch.value, {c: v for c, v in zip((0, 256, 512, 1024), list(us)) if v >= 0}
 
 
 def poisson_solve_noalloc(ops: Operators, rhs: torch.Tensor, x: torch.Tensor, tol: float = 1e-10,

@@ -345,6 +345,7 @@ int rbffd_ctx_destroy(rbffd_ctx *ctx)
         release_ops_memory(ops);
         ops->ctx = nullptr;
     }
+    graph_cache_destroy(ctx);
     for (int s = 0; s < WS_COUNT; ++s) {
         if (!ctx->ws[s].ptr) continue;
         if (s == WS_HOST_PINNED || s == WS_BATCH_HOST || s == WS_BUILD_HOST)
@@ -357,6 +358,38 @@ int rbffd_ctx_destroy(rbffd_ctx *ctx)
 }
 
 size_t rbffd_ctx_bytes_in_use(const rbffd_ctx *ctx) { return ctx ? ctx->in_use : 0; }
+
+int rbffd_ctx_set_solver_choice(rbffd_ctx *ctx, int64_t n, int q, int choice)
+{
+    if (!ctx) return fail(RBFFD_E_ARG, "ctx is NULL");
+    if (n < 1 || q < 1) return fail(RBFFD_E_ARG, "n and q must be positive");
+    if (choice == -1) {
+        ctx->solver_choice.erase({n, q});
+        return RBFFD_OK;
+    }
+    if (choice != 0 && choice != 256 && choice != 512 && choice != 1024)
+        return fail(RBFFD_E_ARG, "choice must be -1, 0, 256, 512 or 1024");
+    ctx->solver_choice[{n, q}] = choice;
+    return RBFFD_OK;
+}
+
+int rbffd_autotune_krylov(rbffd_ctx *ctx, const rbffd_ops *ops, int iterations, int *choice, double *us_per_iter,
+                          void *hip_stream)
+{
+    if (!ctx || !ops) return fail(RBFFD_E_ARG, "NULL argument");
+    if (!ops->ctx) return fail(RBFFD_E_ARG, "the operators' context was destroyed");
+    RB_HIP(hipSetDevice(ctx->device));
+    return autotune_solver(ctx, ops->n, ops->q, cols_of(ops), ops->pval, ops->pdinv, iterations, choice, us_per_iter,
+                           (hipStream_t)hip_stream);
+}
+
+int rbffd_ctx_set_graphs(rbffd_ctx *ctx, int enable)
+{
+    if (!ctx) return fail(RBFFD_E_ARG, "ctx is NULL");
+    if (enable != 0 && enable != 1) return fail(RBFFD_E_ARG, "enable must be 0 or 1");
+    ctx->use_graphs = enable != 0;
+    return RBFFD_OK;
+}
 
 int rbffd_stencil_sizes(int dim, const rbffd_stencil_opts *opts, int *q, int *m, int *R)
 {

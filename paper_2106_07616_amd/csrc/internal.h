@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <map>
 #include <set>
 #include <string>
 
@@ -97,9 +98,19 @@ struct rbffd_ctx {
     // their device memory and leaves them orphaned (freeing them later is safe)
     std::set<rbffd_ops *> ops;
     std::set<rbffd_server *> servers;
+    // HIP graphs of BiCGSTAB iteration chunks (krylov.hip), and whether the
+    // solves replay them
+    void *graphs = nullptr;
+    bool use_graphs = false;
+    // solver path per system size (n, q) for FP64 Jacobi BiCGSTAB: 0 = the
+    // multi-kernel iteration, 256 / 512 / 1024 = the one-workgroup solver with
+    // that many threads; sizes not listed take the multi-kernel iteration
+    std::map<std::pair<int64_t, int>, int> solver_choice;
 };
 
 namespace rbffd {
+// release the context's captured graphs (and their capture stream)
+void graph_cache_destroy(rbffd_ctx *ctx);
 int dev_alloc(rbffd_ctx *ctx, void **p, size_t bytes);
 void dev_free(rbffd_ctx *ctx, void *p, size_t bytes);
 // workspace slot of at least `bytes` (contents are not preserved on growth)
@@ -287,6 +298,10 @@ struct KrylovResult {
 // blocks of the 64-row slices (one right-hand side).
 int bicgstab_block(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, BlockInv binv,
                    const double *b, double *x, double tol, int max_iter, KrylovResult *res, hipStream_t s);
+// time `iterations` FP64 Jacobi BiCGSTAB iterations of the system (n, q, col,
+// val, dinv) on each solver path and record the fastest for (n, q)
+int autotune_solver(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, const double *dinv,
+                    int iterations, int *choice, double *us_per_iter, hipStream_t s);
 int bicgstab(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val,
              const double *dinv, int nrhs, const double *b, double *x, double tol, int max_iter,
              KrylovResult *res, hipStream_t s);

@@ -21,6 +21,7 @@
 // small state record every few iterations to stop.
 #include <climits>
 #include <cmath>
+#include <cstring>
 #include <mutex>
 #include <vector>
 
@@ -797,6 +798,16 @@ __global__ void k_dir_reset(int64_t n, int64_t np, int nrhs, unsigned mask, cons
 
 // Zeroes the solver state records (a kernel rather than a memset, so that the
 // solve also runs inside a captured graph).
+// After each chunk of iterations every finished solve's stamp becomes 1, below
+// the phase numbers (2, 3, ...) that a chunk's launches carry. Every chunk of
+// one length then launches the same kernels with the same arguments, so it can
+// be captured once as a HIP graph and replayed.
+__global__ void k_stamp_done(KState *__restrict__ st, int nrhs)
+{
+    const int k = threadIdx.x;
+    if (k < nrhs && st[k].done_at != 0) st[k].done_at = 1;
+}
+
 __global__ void k_clear_states(KState *__restrict__ st)
 {
     if (threadIdx.x < kMaxRhs) st[threadIdx.x] = KState{};
@@ -844,9 +855,368 @@ int get_work(rbffd_ctx *ctx, int64_t npad, int nrhs, Work *w)
     return RBFFD_OK;
 }
 
+// ---- one-workgroup BiCGSTAB: the whole solve of a small system in one kernel --
+// The four-kernel iteration has a latency floor of about 22 us however small
+// the system. Here one workgroup runs the entire solve instead: the same
+// iteration as KV, KS, KT, KX (same dot products, convergence tests, restart
+// rule and breakdown handling), with block barriers in place of kernel
+// boundaries and block-wide sums in a fixed order in place of partials. Thread
+// t owns rows t, t + BS, ... in every row loop, so row-local updates need no
+// barrier; the SpMVs gather neighbour entries and follow a barrier. It is a
+// path the autotuner (or the caller) may pick per system size; on MI355X one
+// CU streams about two matrix entries per cycle, which keeps it behind the
+// four-kernel iteration at every size measured (26 vs 22 us per iteration at
+// 1,760 rows).
+struct WGSys {
+    int64_t n, np, xs;      // rows, vector stride, stride of x between right-hand sides
+    int q, max_iter;
+    double tol2;
+    ColIdx col;
+    const double *val, *dinv, *b;   // b: [nrhs][n]
+    double *x;
+    double *r, *rh, *ph, *v, *s, *sh, *t;   // [nrhs][np] each
+    KState *st;             // out: iters, status, done_at (1 = finished)
+};
+
+// Wave sum through DPP: butterflies within rows of 16 lanes, then the row
+// broadcasts, leaving the total in lane 63 (a fixed order of additions).
+template <int CTRL, int ROWS>
+__device__ inline double dpp_add(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+    return v + __hiloint2double(hi, lo);
+}
+
+__device__ inline double wave_sum_dpp63(double v)
+{
+    v = dpp_add<0xB1, 0xF>(v);    // quad_perm [1, 0, 3, 2]
+    v = dpp_add<0x4E, 0xF>(v);    // quad_perm [2, 3, 0, 1]
+    v = dpp_add<0x141, 0xF>(v);   // row_half_mirror
+    v = dpp_add<0x140, 0xF>(v);   // row_mirror
+    v = dpp_add<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    return v;                     // lane 63: the wave's sum
+}
+
+template <int NV, int BS>
+__device__ inline void wg_sum(double (&v)[NV], double (*red)[BS / 64])
+{
+#pragma unroll
+    for (int m = 0; m < NV; ++m) v[m] = wave_sum_dpp63(v[m]);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 63)
+#pragma unroll
+        for (int m = 0; m < NV; ++m) red[m][w] = v[m];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < BS / 64; ++j) t += red[m][j];
+        v[m] = t;
+    }
+    __syncthreads();   // red is reused by the next sum
+}
+
+template <int NRHS, int BS, int U>
+__device__ inline void wg_solve(const WGSys &S, double (*red)[BS / 64])
+{
+    const int tid = threadIdx.x;
+    const int64_t n = S.n, np = S.np;
+    double rr[NRHS], bb[NRHS], rho[NRHS];
+    bool act[NRHS];
+    int iters[NRHS], status[NRHS];
+    bool all[NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) all[k] = true;
+    {
+        double acc[2 * NRHS];
+#pragma unroll
+        for (int k = 0; k < 2 * NRHS; ++k) acc[k] = 0.0;
+        for (int64_t i = tid; i < n; i += BS) {
+            double ax[NRHS];
+            row_dot<double, double, NRHS, U>(i, S.q, S.col, S.val, S.x, S.xs, all, ax);
+            const double di = S.dinv[i];
+#pragma unroll
+            for (int k = 0; k < NRHS; ++k) {
+                const double bi = S.b[k * n + i];
+                const double ri = bi - ax[k];
+                S.r[k * np + i] = ri;
+                S.rh[k * np + i] = ri;
+                S.ph[k * np + i] = di * ri;
+                acc[2 * k] += ri * ri;
+                acc[2 * k + 1] += bi * bi;
+            }
+        }
+        wg_sum<2 * NRHS, BS>(acc, red);
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            rr[k] = acc[2 * k];
+            bb[k] = acc[2 * k + 1];
+        }
+    }
+    bool zero[NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+        iters[k] = 0;
+        status[k] = RBFFD_OK;
+        rho[k] = rr[k];
+        zero[k] = bb[k] == 0.0;
+        act[k] = !zero[k] && !(rr[k] <= S.tol2 * bb[k]);
+    }
+    for (int64_t i = tid; i < n; i += BS)
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k)
+            if (zero[k]) S.x[k * S.xs + i] = 0.0;
+    for (int it = 0; it < S.max_iter; ++it) {
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) any = any || act[k];
+        if (!any) break;
+        __syncthreads();   // p-hat of every row is written
+        // v = A p-hat, r-hat.v
+        double rv[NRHS];
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) rv[k] = 0.0;
+        for (int64_t i = tid; i < n; i += BS) {
+            double av[NRHS];
+            row_dot<double, double, NRHS, U>(i, S.q, S.col, S.val, S.ph, np, act, av);
+#pragma unroll
+            for (int k = 0; k < NRHS; ++k) {
+                if (!act[k]) continue;
+                S.v[k * np + i] = av[k];
+                rv[k] += S.rh[k * np + i] * av[k];
+            }
+        }
+        wg_sum<NRHS, BS>(rv, red);
+        double alpha[NRHS];
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            alpha[k] = (rv[k] != 0.0) ? rho[k] / rv[k] : 0.0;
+            if (act[k] && rv[k] == 0.0) {
+                status[k] = RBFFD_E_BREAKDOWN;
+                act[k] = false;
+            }
+        }
+        // s = r - alpha v, s-hat = D^-1 s, s.s, r-hat.s
+        double sacc[2 * NRHS];
+#pragma unroll
+        for (int k = 0; k < 2 * NRHS; ++k) sacc[k] = 0.0;
+        for (int64_t i = tid; i < n; i += BS) {
+            const double di = S.dinv[i];
+#pragma unroll
+            for (int k = 0; k < NRHS; ++k) {
+                if (!act[k]) continue;
+                const double si = S.r[k * np + i] - alpha[k] * S.v[k * np + i];
+                S.s[k * np + i] = si;
+                S.sh[k * np + i] = di * si;
+                sacc[2 * k] += si * si;
+                sacc[2 * k + 1] += S.rh[k * np + i] * si;
+            }
+        }
+        wg_sum<2 * NRHS, BS>(sacc, red);
+        bool half[NRHS];
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            half[k] = act[k] && sacc[2 * k] <= S.tol2 * bb[k];
+            if (half[k]) {
+                iters[k] += 1;
+                act[k] = false;
+            }
+        }
+        for (int64_t i = tid; i < n; i += BS)
+#pragma unroll
+            for (int k = 0; k < NRHS; ++k)
+                if (half[k]) S.x[k * S.xs + i] = S.x[k * S.xs + i] + alpha[k] * S.ph[k * np + i];
+        __syncthreads();   // s-hat of every row is written
+        // t = A s-hat, t.s, t.t, r-hat.t
+        double tacc[3 * NRHS];
+#pragma unroll
+        for (int k = 0; k < 3 * NRHS; ++k) tacc[k] = 0.0;
+        for (int64_t i = tid; i < n; i += BS) {
+            double at[NRHS];
+            row_dot<double, double, NRHS, U>(i, S.q, S.col, S.val, S.sh, np, act, at);
+#pragma unroll
+            for (int k = 0; k < NRHS; ++k) {
+                if (!act[k]) continue;
+                S.t[k * np + i] = at[k];
+                tacc[3 * k] += at[k] * S.s[k * np + i];
+                tacc[3 * k + 1] += at[k] * at[k];
+                tacc[3 * k + 2] += S.rh[k * np + i] * at[k];
+            }
+        }
+        wg_sum<3 * NRHS, BS>(tacc, red);
+        double omega[NRHS], beta[NRHS], rho1[NRHS];
+        bool restart[NRHS];
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            const double ts = tacc[3 * k], tt = tacc[3 * k + 1], rt = tacc[3 * k + 2];
+            const double ss = sacc[2 * k], rs = sacc[2 * k + 1];
+            omega[k] = (tt > 0.0) ? ts / tt : 0.0;
+            rho1[k] = rs - omega[k] * rt;
+            const double rrk = fmax(ss - 2.0 * omega[k] * ts + omega[k] * omega[k] * tt, 0.0);
+            restart[k] = fabs(rho1[k]) < 1e-300 || fabs(rho1[k]) < 1e-30 * rrk;
+            beta[k] = (restart[k] || omega[k] == 0.0) ? 0.0 : (rho1[k] / rho[k]) * (alpha[k] / omega[k]);
+        }
+        // x += alpha p-hat + omega s-hat; r = s - omega t; next p-hat; r.r
+        double racc[NRHS];
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) racc[k] = 0.0;
+        for (int64_t i = tid; i < n; i += BS) {
+            const double di = S.dinv[i];
+#pragma unroll
+            for (int k = 0; k < NRHS; ++k) {
+                if (!act[k]) continue;
+                const double phi = S.ph[k * np + i], si = S.s[k * np + i];
+                const double shi = S.sh[k * np + i];
+                S.x[k * S.xs + i] = S.x[k * S.xs + i] + alpha[k] * phi + omega[k] * shi;
+                const double ri = si - omega[k] * S.t[k * np + i];
+                S.r[k * np + i] = ri;
+                if (restart[k]) S.rh[k * np + i] = ri;
+                S.ph[k * np + i] = (beta[k] == 0.0) ? di * ri
+                                                    : di * ri + beta[k] * (phi - omega[k] * (di * S.v[k * np + i]));
+                racc[k] += ri * ri;
+            }
+        }
+        wg_sum<NRHS, BS>(racc, red);
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            if (!act[k]) continue;
+            iters[k] += 1;
+            rr[k] = racc[k];
+            rho[k] = restart[k] ? rr[k] : rho1[k];
+            if (omega[k] == 0.0) {
+                status[k] = RBFFD_E_BREAKDOWN;
+                act[k] = false;
+            } else if (rr[k] <= S.tol2 * bb[k]) {
+                act[k] = false;
+            }
+        }
+    }
+    if (tid == 0)
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            S.st[k].iters = iters[k];
+            S.st[k].status = status[k];
+            S.st[k].done_at = act[k] ? 0 : 1;
+        }
+}
+
+template <int NRHS, int BS, int U>
+__global__ __launch_bounds__(BS) void k_bicgstab_wg1(WGSys S)
+{
+    __shared__ double red[3 * NRHS][BS / 64];
+    wg_solve<NRHS, BS, U>(S, red);
+}
+
+// Row-loop unroll of the one-workgroup solver: deep, so that one thread has
+// many entries' loads in flight (one workgroup has few threads per row).
+inline int wg_unroll(int q) { return (q % 10 == 0) ? 10 : (q % 6 == 0) ? 6 : 8; }
+
+template <int NRHS>
+int launch_wg1(const WGSys &S, int bs, hipStream_t s)
+{
+    const int u = wg_unroll(S.q);
+#define RB_WG1(BS_)                                                                                   \
+    if (bs == BS_) {                                                                                  \
+        if (u == 10)                                                                                  \
+            hipLaunchKernelGGL((k_bicgstab_wg1<NRHS, BS_, 10>), dim3(1), dim3(BS_), 0, s, S);         \
+        else if (u == 6)                                                                              \
+            hipLaunchKernelGGL((k_bicgstab_wg1<NRHS, BS_, 6>), dim3(1), dim3(BS_), 0, s, S);          \
+        else                                                                                          \
+            hipLaunchKernelGGL((k_bicgstab_wg1<NRHS, BS_, 8>), dim3(1), dim3(BS_), 0, s, S);          \
+        RB_HIP(hipGetLastError());                                                                    \
+        return RBFFD_OK;                                                                              \
+    }
+    RB_WG1(256)
+    RB_WG1(512)
+    RB_WG1(1024)
+#undef RB_WG1
+    return fail(RBFFD_E_ARG, "one-workgroup solver: block size must be 256, 512 or 1024");
+}
+
+// Path of a solve: 0 the multi-kernel iteration, else the one-workgroup
+// solver's block size. Without a recorded choice the multi-kernel iteration
+// runs: on MI355X one workgroup streams about two matrix entries per cycle,
+// so even at 1,760 rows (26 us per iteration) it does not beat the four-kernel
+// iteration's latency floor (22 us), and from 10k rows it is 8x slower or more.
+int solver_choice(const rbffd_ctx *ctx, int64_t n, int q)
+{
+    auto it = ctx->solver_choice.find({n, q});
+    return it != ctx->solver_choice.end() ? it->second : 0;
+}
+
+// the autotuner tries the one-workgroup solver up to this size
+constexpr int64_t kWGTuneMaxRows = 65536;
+
+// ---- HIP graphs of iteration chunks ------------------------------------------
+// A chunk (its KV, KS, KT, KX launches, the closing convergence test and the
+// stamp) is captured on the context's own stream the first time its exact
+// launch sequence occurs, and replayed on the caller's stream after that. The
+// key holds every kernel argument of the chunk, so a replay launches exactly
+// what the direct path would: results are bitwise the same either way.
+struct ChunkKey {
+    const void *kv, *kt, *ks, *kx;
+    const void *col, *cbase, *col16, *val, *dinv, *x;
+    const void *r, *rh, *ph, *v, *s, *sh, *t, *part, *st;
+    int64_t n, xs;
+    int q, nblk, todo, nrhs;
+    double tol2;
+};
+
+struct GraphCache {
+    struct Entry {
+        ChunkKey key;
+        hipGraphExec_t exec;
+        uint64_t used;
+    };
+    hipStream_t cs = nullptr;
+    std::vector<Entry> e;
+    uint64_t clock = 0;
+};
+constexpr size_t kMaxGraphs = 32;
+
+template <typename F>
+int chunk_graph(rbffd_ctx *ctx, const ChunkKey &key, F &&launch, hipGraphExec_t *out)
+{
+    GraphCache *gc = (GraphCache *)ctx->graphs;
+    if (!gc) {
+        gc = new GraphCache();
+        ctx->graphs = gc;
+    }
+    for (auto &en : gc->e)
+        if (std::memcmp(&en.key, &key, sizeof(ChunkKey)) == 0) {
+            en.used = ++gc->clock;
+            *out = en.exec;
+            return RBFFD_OK;
+        }
+    if (!gc->cs) RB_HIP(hipStreamCreateWithFlags(&gc->cs, hipStreamNonBlocking));
+    RB_HIP(hipStreamBeginCapture(gc->cs, hipStreamCaptureModeRelaxed));
+    launch(gc->cs);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(gc->cs, &g);
+    if (e != hipSuccess) return hip_fail(e, "capturing a BiCGSTAB chunk");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "instantiating a BiCGSTAB chunk graph");
+    if (gc->e.size() >= kMaxGraphs) {
+        size_t lru = 0;
+        for (size_t i = 1; i < gc->e.size(); ++i)
+            if (gc->e[i].used < gc->e[lru].used) lru = i;
+        (void)hipGraphExecDestroy(gc->e[lru].exec);
+        gc->e.erase(gc->e.begin() + lru);
+    }
+    gc->e.push_back({key, ex, ++gc->clock});
+    *out = ex;
+    return RBFFD_OK;
+}
+
 template <typename T, int NRHS>
 int bicgstab_t(int64_t n, int q, ColIdx col, const T *val, const T *dinv, const T *b, int64_t bs, T *x, int64_t xs,
-               double tol, int max_iter, KrylovResult *res, Work &w, KState *hst, hipStream_t s)
+               double tol, int max_iter, KrylovResult *res, Work &w, KState *hst, hipStream_t s,
+               rbffd_ctx *gctx = nullptr)
 {
     const int64_t np = pad64(n);
     const int nblk = krylov_blocks(n);
@@ -859,23 +1229,73 @@ int bicgstab_t(int64_t n, int q, ColIdx col, const T *val, const T *dinv, const 
     const bool nt = matrix_nt(n, q, sizeof(T));
     const auto kv = kv_for<T, T, NRHS>(q, nt);
     const auto kt = kt_for<T, T, NRHS>(q, nt);
-    int it = 0, chunk = 4, phase = 0;
-    bool finished = false;
-    while (!finished) {
-        const int todo = std::min(chunk, max_iter - it);
+    const auto ks = k_s<T, NRHS>;
+    const auto kx = k_x<T, NRHS>;
+    // one chunk: todo iterations, the convergence test on the last residual (so
+    // the host sees it now) and the stamp; phases 2, 3, ... within the chunk
+    auto launch_chunk = [&](hipStream_t st_, int todo) {
+        int phase = 1;
         for (int c = 0; c < todo; ++c) {
-            hipLaunchKernelGGL(kv, g, bl, 0, s, n, np, q, col, val, rh, ph, v, x, xs, w.part, w.st, nblk,
+            hipLaunchKernelGGL(kv, g, bl, 0, st_, n, np, q, col, val, rh, ph, v, x, xs, w.part, w.st, nblk,
                                tol2, 0, ++phase);
-            hipLaunchKernelGGL((k_s<T, NRHS>), g, bl, 0, s, n, np, dinv, r, rh, v, sv, sh, w.part, w.st, nblk, ++phase);
-            hipLaunchKernelGGL(kt, g, bl, 0, s, n, np, q, col, val, x, xs, ph, sv, sh, rh, t, w.part,
+            hipLaunchKernelGGL(ks, g, bl, 0, st_, n, np, dinv, r, rh, v, sv, sh, w.part, w.st, nblk, ++phase);
+            hipLaunchKernelGGL(kt, g, bl, 0, st_, n, np, q, col, val, x, xs, ph, sv, sh, rh, t, w.part,
                                w.st, nblk, tol2, ++phase);
-            hipLaunchKernelGGL((k_x<T, NRHS>), g, bl, 0, s, n, np, dinv, x, xs, ph, sv, t, v, r, rh, w.part, w.st,
+            hipLaunchKernelGGL(kx, g, bl, 0, st_, n, np, dinv, x, xs, ph, sv, t, v, r, rh, w.part, w.st,
                                nblk, ++phase);
         }
-        it += std::max(todo, 0);
-        // convergence test on the last residual, so the host sees it now
-        hipLaunchKernelGGL(kv, g, bl, 0, s, n, np, q, col, val, rh, ph, v, x, xs, w.part, w.st, nblk,
+        hipLaunchKernelGGL(kv, g, bl, 0, st_, n, np, q, col, val, rh, ph, v, x, xs, w.part, w.st, nblk,
                            tol2, 1, ++phase);
+        hipLaunchKernelGGL(k_stamp_done, dim3(1), dim3(64), 0, st_, w.st, NRHS);
+    };
+    int it = 0, chunk = 4;
+    bool finished = false;
+    while (!finished) {
+        const int todo = std::max(std::min(chunk, max_iter - it), 0);
+        if (gctx && gctx->use_graphs) {
+            ChunkKey key;
+            std::memset(&key, 0, sizeof(key));
+            key.kv = (const void *)kv;
+            key.kt = (const void *)kt;
+            key.ks = (const void *)ks;
+            key.kx = (const void *)kx;
+            key.col = col.col;
+            key.cbase = col.cbase;
+            key.col16 = col.col16;
+            key.val = val;
+            key.dinv = dinv;
+            key.x = x;
+            key.r = r;
+            key.rh = rh;
+            key.ph = ph;
+            key.v = v;
+            key.s = sv;
+            key.sh = sh;
+            key.t = t;
+            key.part = w.part;
+            key.st = w.st;
+            key.n = n;
+            key.xs = xs;
+            key.q = q;
+            key.nblk = nblk;
+            key.todo = todo;
+            key.nrhs = NRHS;
+            key.tol2 = tol2;
+            hipGraphExec_t ge = nullptr;
+            if (chunk_graph(gctx, key, [&](hipStream_t cs) { launch_chunk(cs, todo); }, &ge) == RBFFD_OK) {
+                RB_HIP(hipGraphLaunch(ge, s));
+            } else {
+                // a capture that fails (another thread synchronised the whole
+                // device meanwhile, for instance) launched nothing: this chunk
+                // and the context's later solves launch kernel by kernel
+                (void)hipGetLastError();
+                gctx->use_graphs = false;
+                launch_chunk(s, todo);
+            }
+        } else {
+            launch_chunk(s, todo);
+        }
+        it += todo;
         RB_HIP(hipGetLastError());
         RB_HIP(hipMemcpyAsync(hst, w.st, sizeof(KState) * kMaxRhs, hipMemcpyDeviceToHost, s));
         RB_HIP(hipStreamSynchronize(s));
@@ -1424,6 +1844,48 @@ int spmv(int64_t n, int q, ColIdx col, const double *val, const double *x, doubl
     return RBFFD_OK;
 }
 
+// One solve (nrhs right-hand sides) by the one-workgroup solver with bs
+// threads, in the vectors and state records of w; hst receives the records.
+static int wg_solve_one(int64_t n, int q, ColIdx col, const double *val, const double *dinv, int nrhs,
+                        const double *b, double *x, double tol, int max_iter, Work &w, KState *hst, int bs,
+                        KrylovResult *res, hipStream_t s)
+{
+    WGSys S;
+    std::memset(&S, 0, sizeof(S));
+    S.n = n;
+    S.np = pad64(n);
+    S.xs = n;
+    S.q = q;
+    S.max_iter = std::max(max_iter, 0);
+    S.tol2 = tol * tol;
+    S.col = col;
+    S.val = val;
+    S.dinv = dinv;
+    S.b = b;
+    S.x = x;
+    S.r = (double *)w.r;
+    S.rh = (double *)w.rh;
+    S.ph = (double *)w.ph;
+    S.v = (double *)w.v;
+    S.s = (double *)w.s;
+    S.sh = (double *)w.sh;
+    S.t = (double *)w.t;
+    S.st = w.st;
+    switch (nrhs) {
+    case 1: RB_CHECK(launch_wg1<1>(S, bs, s)); break;
+    case 2: RB_CHECK(launch_wg1<2>(S, bs, s)); break;
+    case 3: RB_CHECK(launch_wg1<3>(S, bs, s)); break;
+    default: return fail(RBFFD_E_ARG, "nrhs must be 1..3");
+    }
+    RB_HIP(hipMemcpyAsync(hst, w.st, sizeof(KState) * nrhs, hipMemcpyDeviceToHost, s));
+    RB_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < nrhs; ++k) {
+        res->iters[k] = hst[k].iters;
+        res->status[k] = hst[k].done_at ? hst[k].status : RBFFD_E_NOCONV;
+    }
+    return RBFFD_OK;
+}
+
 static int bicgstab_once(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val,
                          const double *dinv, int nrhs, const double *b, double *x, double tol, int max_iter,
                          KrylovResult *res, hipStream_t s)
@@ -1432,10 +1894,12 @@ static int bicgstab_once(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const dou
     RB_CHECK(get_work<double>(ctx, pad64(n), nrhs, &w));
     KState *hst = nullptr;
     RB_CHECK(host_scratch(ctx, kHostKrylov, sizeof(KState) * kMaxRhs, (void **)&hst));
+    const int bs = solver_choice(ctx, n, q);
+    if (bs > 0) return wg_solve_one(n, q, col, val, dinv, nrhs, b, x, tol, max_iter, w, hst, bs, res, s);
     switch (nrhs) {
-    case 1: return bicgstab_t<double, 1>(n, q, col, val, dinv, b, n, x, n, tol, max_iter, res, w, hst, s);
-    case 2: return bicgstab_t<double, 2>(n, q, col, val, dinv, b, n, x, n, tol, max_iter, res, w, hst, s);
-    case 3: return bicgstab_t<double, 3>(n, q, col, val, dinv, b, n, x, n, tol, max_iter, res, w, hst, s);
+    case 1: return bicgstab_t<double, 1>(n, q, col, val, dinv, b, n, x, n, tol, max_iter, res, w, hst, s, ctx);
+    case 2: return bicgstab_t<double, 2>(n, q, col, val, dinv, b, n, x, n, tol, max_iter, res, w, hst, s, ctx);
+    case 3: return bicgstab_t<double, 3>(n, q, col, val, dinv, b, n, x, n, tol, max_iter, res, w, hst, s, ctx);
     default: return fail(RBFFD_E_ARG, "nrhs must be 1..3");
     }
 }
@@ -2297,6 +2761,81 @@ constexpr int kNoAllocDevices = 64;
 std::mutex g_noalloc_mu;
 unsigned char *g_noalloc_ptr[kNoAllocDevices] = {};
 }  // namespace
+
+__global__ void k_tune_rhs(int64_t n, double *__restrict__ b, double *__restrict__ x)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    b[i] = sin(0.37 * (double)i) + 0.5 * cos(1.3 * (double)i);
+    x[i] = 0.0;
+}
+
+int autotune_solver(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val, const double *dinv,
+                    int iterations, int *choice, double *us_per_iter, hipStream_t s)
+{
+    if (iterations < 4) return fail(RBFFD_E_ARG, "autotune needs at least 4 iterations");
+    double *bx = nullptr;
+    RB_CHECK(dev_alloc(ctx, (void **)&bx, sizeof(double) * 2 * (size_t)n));
+    const int cand[4] = {0, 256, 512, 1024};
+    double best = 0.0;
+    int bestc = 0;
+    bool have = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int st = RBFFD_OK;
+    const auto saved = ctx->solver_choice.find({n, q});
+    const bool had = saved != ctx->solver_choice.end();
+    const int old = had ? saved->second : 0;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = fail(RBFFD_E_DEVICE, "hipEventCreate");
+    for (int c = 0; c < 4 && st == RBFFD_OK; ++c) {
+        // one workgroup cannot compete beyond this size: not tried
+        const bool tried = cand[c] == 0 || n <= kWGTuneMaxRows;
+        double us = -1.0;
+        if (tried) {
+            ctx->solver_choice[{n, q}] = cand[c];
+            for (int rep = 0; rep < 2 && st == RBFFD_OK; ++rep) {   // the first run captures graphs
+                hipLaunchKernelGGL(k_tune_rhs, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, bx,
+                                   bx + n);
+                KrylovResult r;
+                (void)hipEventRecord(e0, s);
+                st = bicgstab_once(ctx, n, q, col, val, dinv, 1, bx, bx + n, 0.0, iterations, &r, s);
+                (void)hipEventRecord(e1, s);
+                (void)hipEventSynchronize(e1);
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                us = 1e3 * ms / std::max(r.iters[0], 1);
+            }
+        }
+        if (us_per_iter) us_per_iter[c] = us;
+        if (tried && (!have || us < best)) {
+            best = us;
+            bestc = cand[c];
+            have = true;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    dev_free(ctx, bx, sizeof(double) * 2 * (size_t)n);
+    if (st != RBFFD_OK) {
+        if (had)
+            ctx->solver_choice[{n, q}] = old;
+        else
+            ctx->solver_choice.erase({n, q});
+        return st;
+    }
+    ctx->solver_choice[{n, q}] = bestc;
+    if (choice) *choice = bestc;
+    return RBFFD_OK;
+}
+
+void graph_cache_destroy(rbffd_ctx *ctx)
+{
+    GraphCache *gc = (GraphCache *)ctx->graphs;
+    if (!gc) return;
+    for (auto &en : gc->e) (void)hipGraphExecDestroy(en.exec);
+    if (gc->cs) (void)hipStreamDestroy(gc->cs);
+    delete gc;
+    ctx->graphs = nullptr;
+}
 
 int noalloc_init(int device)
 {

@@ -179,9 +179,19 @@ def test_server_staggered_equals_alone(ctx, batch):
     precs = [R.RBFFD_FP32_MATRIX if j in (1, 2) else R.RBFFD_FP64 for j in range(len(items))]
     alone, st_alone = [], []
     for it, pc, pr in zip(items, pcs, precs):
-        x1, s1 = _solve(ctx, [it], 1e-10, pc, pr)
-        alone.append(x1[0])
-        st_alone.append(s1[0])
+        # alone: the only solve in a server of its own
+        sv1 = R.Server(ctx)
+        x1 = torch.zeros(it[1].n, dtype=torch.float64, device="cuda")
+        t1 = sv1.submit(it[2].ops, torch.tensor(it[4], device="cuda"), x1, tol=1e-10, max_iter=20000,
+                        preconditioner=pc, precision=pr)
+        fin = {}
+        while len(fin) < 1:
+            sv1.run(32)
+            for t2, st in sv1.poll():
+                fin[t2] = st
+        sv1.close()
+        alone.append(x1.cpu().numpy())
+        st_alone.append(fin[t1])
     sv = R.Server(ctx)
     xs, tickets = {}, {}
     rhs = [torch.tensor(it[4], device="cuda") for it in items]

@@ -704,3 +704,117 @@ def test_duplicate_points_are_an_argument_error(ctx, orc):
         R.rbffd_build_stencils_batched(ctx, [R.DeviceCloud.from_numpy(c), R.DeviceCloud.from_numpy(dup)], [3, 3])
     assert e.value.code == -1 and "cloud 1" in str(e.value)
     R.rbffd_build_stencils(ctx, R.DeviceCloud.from_numpy(c), 3)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["kovasznay", "tg_disk"])
+def test_graph_replays_equal_direct_launches(ctx, name):
+    """BiCGSTAB chunks replayed as HIP graphs give bitwise the results of
+    kernel-by-kernel launches: pressure-correction solves repeated with eager
+    work and synchronisation between them (every replay checked), and three
+    consecutive time steps (momentum with two and one right-hand sides,
+    pressure correction)."""
+    c = W.kovasznay_square(nx=30) if name == "kovasznay" else W.taylor_green_disk(r=0.03)
+    s = R.Solver(ctx, c, 3)
+    ctx.set_solver_choice(c.n, s.q, 0)         # the multi-kernel iteration, whose chunks are captured
+    rng = np.random.default_rng(3)
+    b = torch.tensor(rng.standard_normal(c.n), device="cuda")
+    out = {}
+    for graphs in (False, True, True):
+        ctx.set_graphs(graphs)
+        xs = []
+        for rep in range(3):
+            x = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+            st = R.poisson_solve(ctx, s.ops, b, x, tol=1e-11, max_iter=20000, allow_noconv=True)
+            torch.cuda.synchronize()
+            _ = (x * 2.0).sum().item()      # eager work between replays
+            xs.append((x.cpu().numpy(), st["iters"]))
+        vel, p = W.flow_fields(c)
+        u = torch.tensor(vel, device="cuda")
+        up = u.clone()
+        pg = torch.tensor(p, device="cuda")
+        pb = pg.clone() if (c.kind == W.PRESCRIBED_PRESSURE).any() else None
+        for _ in range(3):
+            R.simple_step(ctx, s.ops, u, up, pg, torch.tensor(vel, device="cuda"), 1.0, 0.01, 0.01,
+                          tol_outer=0.0, tol_krylov=1e-10, max_outer=2, max_krylov=20000, p_bc=pb)
+        torch.cuda.synchronize()
+        out.setdefault(graphs, []).append((xs, u.cpu().numpy(), pg.cpu().numpy()))
+    ref_xs, ref_u, ref_p = out[False][0]
+    for xs, u, p in out[True]:
+        for (xa, ia), (xb, ib) in zip(xs, ref_xs):
+            assert ia == ib
+            np.testing.assert_array_equal(xa, xb)
+        np.testing.assert_array_equal(u, ref_u)
+        np.testing.assert_array_equal(p, ref_p)
+    ctx.set_graphs(False)
+    ctx.set_solver_choice(c.n, s.q, -1)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["kovasznay", "tg_disk", "holed"])
+def test_solver_paths_match_the_oracle(ctx, orc, name):
+    """Every BiCGSTAB path (the multi-kernel iteration and the one-workgroup
+    solver with 256, 512 and 1024 threads) solves the pressure-correction
+    system to the oracle's solution (1e-8 relative), and takes the same
+    number of iterations within a few; one time step (momentum with two
+    right-hand sides, pressure correction, boundary pressure) on each path
+    matches the oracle's step."""
+    if name == "kovasznay":
+        c = W.kovasznay_square(nx=30)
+    elif name == "tg_disk":
+        c = W.taylor_green_disk(r=0.03)
+    else:
+        c = W.holed_square(3000, seed=5)
+    k = 3
+    s = R.Solver(ctx, c, k)
+    ops_o = orc.build_operators(c, k)
+    b = np.random.default_rng(11).standard_normal(c.n)
+    xo, ito, _, sto = orc.bicgstab(ops_o.col, ops_o.pval, b, tol=1e-12, maxit=40000)
+    vel, p = W.flow_fields(c)
+    pb = p.copy() if (c.kind == W.PRESCRIBED_PRESSURE).any() else None
+    kw = dict(tol_outer=0.0, tol_krylov=1e-12, max_outer=2, max_krylov=40000)
+    uo, _, po, st_o = orc.simple_step(ops_o, vel, vel, p, vel, 1.0, 0.025, 0.02, p_bc=pb, **kw)
+    step_ok = st_o["status"] == 0
+    for choice in (0, 256, 512, 1024):
+        ctx.set_solver_choice(c.n, s.q, choice)
+        if pb is None:
+            nb = int(((c.kind == W.DIRICHLET) | (c.kind == W.SYMMETRY)).sum())
+            if nb:
+                ctx.set_solver_choice(nb, s.q, choice)
+        x = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+        st = R.poisson_solve(ctx, s.ops, torch.tensor(b, device="cuda"), x, tol=1e-12, max_iter=40000,
+                             allow_noconv=True)
+        err = float(np.abs(x.cpu().numpy() - xo).max() / np.abs(xo).max())
+        print(f"[paths] {name} n={c.n} choice {choice}: {st['iters']} iterations (oracle {ito}), "
+              f"status {st['status']} relres {st['relres']:.1e}, vs oracle {err:.1e}", flush=True)
+        if sto == 0 and st["status"] == 0:
+            assert err <= 1e-8
+        else:
+            assert st["status"] != 0 or st["relres"] <= 1e-11
+        u = torch.tensor(vel, device="cuda")
+        pg = torch.tensor(p, device="cuda")
+        R.simple_step(ctx, s.ops, u, u.clone(), pg, torch.tensor(vel, device="cuda"), 1.0, 0.025, 0.02,
+                      p_bc=None if pb is None else torch.tensor(pb, device="cuda"), **kw)
+        if step_ok:
+            eu = float(np.abs(u.cpu().numpy() - uo).max() / np.abs(uo).max())
+            assert eu <= 1e-8, (choice, eu)
+    ctx.set_solver_choice(c.n, s.q, -1)
+
+
+@pytest.mark.gpu
+def test_autotune_records_a_choice(ctx):
+    """The autotuner times every path on the operators' system and records
+    the fastest for the system's size; later solves take it."""
+    c = W.taylor_green_disk(r=0.03)
+    s = R.Solver(ctx, c, 4)
+    choice, us = R.rbffd_autotune_krylov(ctx, s.ops, 24)
+    print(f"[autotune] n={c.n} q={s.q}: choice {choice}, us/iteration {us}", flush=True)
+    assert choice in (0, 256, 512, 1024) and choice in us
+    assert us[choice] == min(us.values())
+    x = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+    st = R.poisson_solve(ctx, s.ops, torch.ones(c.n, dtype=torch.float64, device="cuda"), x, tol=1e-10,
+                         max_iter=20000)
+    assert st["status"] == 0
+    ctx.set_solver_choice(c.n, s.q, -1)
+    with pytest.raises(R.RbffdError):
+        ctx.set_solver_choice(c.n, s.q, 128)
