@@ -497,6 +497,28 @@ int simple_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev,
                 const double *u_bc, const double *p_bc, const rbffd_step_opts *opts,
                 rbffd_step_stats *stats, void *hip_stream);
 
+/* (Sec. 3 and the step list of Sec. 3.2, over many independent clouds: the
+ * batched configuration) One BDF time step of `count` clouds at once, each
+ * exactly as simple_step defines it, with its own options (opts[j]: dt, BDF
+ * coefficients, tolerances, limits, preconditioner). The per-cloud kernels run
+ * cloud by cloud; every Krylov stage (the momentum solves, one system per
+ * velocity component; the pressure corrections; the boundary pressures) is one
+ * batched solve over the clouds still iterating, as in poisson_solve_batched,
+ * so a cloud's fields do not depend on the other clouds in the call. A cloud
+ * leaves the outer iteration when its own Delta meets its own tol_outer.
+ *   ops, u, u_prev, p, u_bc, p_bc, opts, stats: host arrays of `count`; the
+ *     device arrays they point to are laid out as for simple_step; p_bc[j] may
+ *     be NULL for a cloud without prescribed-pressure points; stats[j] receives
+ *     cloud j's statistics.
+ * Restrictions (RBFFD_E_ARG before any launch): FP64 only, no symmetry points,
+ * every ops[j] distinct and of this context. Returns RBFFD_OK, or the first
+ * cloud's failure (E_NOCONV / E_BREAKDOWN; every cloud's own status is in
+ * stats). The operators' momentum values are overwritten, as by simple_step. */
+int simple_step_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops, double *const *u,
+                        double *const *u_prev, double *const *p, const double *const *u_bc,
+                        const double *const *p_bc, const rbffd_step_opts *opts, rbffd_step_stats *stats,
+                        void *hip_stream);
+
 /* (Sec. 3.2) |lambda|max of the discrete convection-diffusion operator
  * -rho (u0 . grad) + mu Laplacian on interior rows (boundary rows zero), by
  * `iters` normalised power iterations from x_i = 1 + (i mod 7)/7; a Courant

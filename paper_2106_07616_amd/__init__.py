@@ -11,11 +11,11 @@ from .binding import (BDF1, BDF2, RBFFD_FP32_IR, RBFFD_FP32_MATRIX, RBFFD_FP64, 
                       Context, DeviceCloud, Operators, RbffdError, Server, lib, poisson_solve, poisson_solve_batched,
                       poisson_solve_noalloc, rbffd_autotune_krylov, rbffd_krylov_kernel_times,
                       rbffd_assemble, rbffd_build_stencils, rbffd_build_stencils_batched, rbffd_convdiff_lambda, rbffd_cylinder_forces, rbffd_interpolate,
-                      rbffd_stencil_sizes, simple_step)
+                      rbffd_stencil_sizes, simple_step, simple_step_batched)
 from .driver import Solver, outer_tolerance
 
 __all__ = ["BDF1", "BDF2", "RBFFD_FP32_IR", "RBFFD_FP32_MATRIX", "RBFFD_FP64", "RBFFD_PREC_BLOCK64", "RBFFD_PREC_JACOBI",
            "Context", "DeviceCloud", "Operators", "RbffdError", "Server", "lib", "poisson_solve", "poisson_solve_batched",
            "poisson_solve_noalloc", "rbffd_autotune_krylov", "rbffd_krylov_kernel_times",
            "rbffd_assemble", "rbffd_build_stencils", "rbffd_build_stencils_batched", "rbffd_convdiff_lambda", "rbffd_cylinder_forces", "rbffd_interpolate",
-           "rbffd_stencil_sizes", "simple_step", "Solver", "outer_tolerance"]
+           "rbffd_stencil_sizes", "simple_step", "simple_step_batched", "Solver", "outer_tolerance"]

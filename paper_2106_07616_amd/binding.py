@@ -31,7 +31,7 @@ EXPORTED = ["rbffd_last_error", "rbffd_ctx_create", "rbffd_ctx_destroy", "rbffd_
             "rbffd_ops_info", "rbffd_ops_export_csr", "rbffd_ops_export_block_inverse", "rbffd_apply", "rbffd_interpolate", "rbffd_cylinder_forces", "poisson_solve",
             "poisson_solve_noalloc", "poisson_solve_batched", "rbffd_krylov_kernel_times",
             "rbffd_server_create", "rbffd_server_destroy", "rbffd_server_submit", "rbffd_server_run",
-            "rbffd_server_poll", "simple_step", "rbffd_convdiff_lambda"]
+            "rbffd_server_poll", "simple_step", "simple_step_batched", "rbffd_convdiff_lambda"]
 
 
 class RbffdError(RuntimeError):
@@ -110,6 +110,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.rbffd_server_run.argtypes = [P, I, C.POINTER(I), P]
     L.rbffd_server_poll.argtypes = [P, I, C.POINTER(I64), C.POINTER(KrylovStatsT), C.POINTER(I)]
     L.simple_step.argtypes = [P, P, P, P, P, P, P, C.POINTER(StepOptsT), C.POINTER(StepStatsT), P]
+    L.simple_step_batched.argtypes = [P, I, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(P),
+                                      C.POINTER(P), C.POINTER(StepOptsT), C.POINTER(StepStatsT), P]
     L.rbffd_convdiff_lambda.argtypes = [P, P, P, D, D, I, C.POINTER(D), P]
     return L
 
@@ -495,6 +497,40 @@ def simple_step(ctx: Context, ops: Operators, u: torch.Tensor, u_prev: torch.Ten
     return dict(outer_iters=s.outer_iters, krylov_mom=s.krylov_mom, krylov_p=s.krylov_p, krylov_b=s.krylov_b,
                 status=s.status, delta=s.delta, eps_steady=s.eps_steady, div_l1=s.div_l1,
                 final_relres_p=s.final_relres_p, krylov_relres_max=s.krylov_relres_max)
+
+
+def _stats_dict(s):
+    return dict(outer_iters=s.outer_iters, krylov_mom=s.krylov_mom, krylov_p=s.krylov_p, krylov_b=s.krylov_b,
+                status=s.status, delta=s.delta, eps_steady=s.eps_steady, div_l1=s.div_l1,
+                final_relres_p=s.final_relres_p, krylov_relres_max=s.krylov_relres_max)
+
+
+def simple_step_batched(ctx: Context, ops: list, u: list, u_prev: list, p: list, u_bc: list, rho: float, mu: float,
+                        dts: list, alpha=BDF2, tol_outer=1e-6, tol_krylov: float = 1e-10, max_outer: int = 50,
+                        max_krylov: int = 5000, p_bc: list | None = None, preconditioner: int = RBFFD_PREC_JACOBI):
+    """One time step of many clouds at once, in place on each cloud's u, u_prev,
+    p (FP64); dts[j] is cloud j's time step, tol_outer a value for all or one
+    per cloud. Returns the list of per-cloud stats; limits reached and
+    breakdowns are reported there, not raised."""
+    cnt = len(ops)
+    tols = list(tol_outer) if isinstance(tol_outer, (list, tuple)) else [tol_outer] * cnt
+    if not (len(u) == len(u_prev) == len(p) == len(u_bc) == len(dts) == cnt):
+        raise ValueError("one entry per cloud in every list")
+    p_bc = p_bc or [None] * cnt
+    PA = C.c_void_p * cnt
+    hs = (C.c_void_p * cnt)(*[o.handle.value if hasattr(o.handle, "value") else o.handle for o in ops])
+    uu = PA(*[_f64(a, o.dim * o.n, "u") for a, o in zip(u, ops)])
+    up = PA(*[_f64(a, o.dim * o.n, "u_prev") for a, o in zip(u_prev, ops)])
+    pp = PA(*[_f64(a, o.n, "p") for a, o in zip(p, ops)])
+    ub = PA(*[_f64(a, o.dim * o.n, "u_bc") for a, o in zip(u_bc, ops)])
+    pb = PA(*[_f64(a, o.n, "p_bc") for a, o in zip(p_bc, ops)])
+    opts = (StepOptsT * cnt)(*[StepOptsT(rho, mu, dt, (C.c_double * 3)(*alpha), to, tol_krylov, max_outer,
+                                         max_krylov, RBFFD_FP64, preconditioner, (C.c_double * 3)(0.0, 0.0, 0.0))
+                               for dt, to in zip(dts, tols)])
+    stats = (StepStatsT * cnt)()
+    st = lib().simple_step_batched(ctx.handle, cnt, hs, uu, up, pp, ub, pb, opts, stats, _stream())
+    _check(st, allow=(RBFFD_E_NOCONV, RBFFD_E_BREAKDOWN))
+    return [_stats_dict(s) for s in stats]
 
 
 def rbffd_convdiff_lambda(ctx: Context, ops: Operators, u0: torch.Tensor, rho: float, mu: float,

@@ -1148,6 +1148,42 @@ int simple_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev,
     return st;
 }
 
+int simple_step_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops, double *const *u,
+                        double *const *u_prev, double *const *p, const double *const *u_bc,
+                        const double *const *p_bc, const rbffd_step_opts *opts, rbffd_step_stats *stats,
+                        void *hip_stream)
+{
+    if (!ctx || !ops || !u || !u_prev || !p || !u_bc || !p_bc || !opts || !stats)
+        return fail(RBFFD_E_ARG, "NULL argument");
+    if (count < 1) return fail(RBFFD_E_ARG, "count must be >= 1");
+    std::set<const rbffd_ops *> seen;
+    for (int j = 0; j < count; ++j) {
+        const std::string at = " (cloud " + std::to_string(j) + ")";
+        const rbffd_ops *op = ops[j];
+        const rbffd_step_opts *o = &opts[j];
+        if (!op || !u[j] || !u_prev[j] || !p[j] || !u_bc[j]) return fail(RBFFD_E_ARG, "NULL argument" + at);
+        if (!op->ctx) return fail(RBFFD_E_ARG, "the operators' context was destroyed" + at);
+        if (op->ctx != ctx) return fail(RBFFD_E_ARG, "operators of another context" + at);
+        if (!seen.insert(op).second) return fail(RBFFD_E_ARG, "the same operators appear twice" + at);
+        if (op->n_prescribed > 0 && !p_bc[j])
+            return fail(RBFFD_E_ARG, "p_bc is required: the cloud has prescribed-pressure points" + at);
+        if (op->n_symmetry > 0) return fail(RBFFD_E_ARG, "clouds with symmetry points step one at a time" + at);
+        if (!(o->rho > 0.0) || !(o->mu >= 0.0) || !(o->dt > 0.0) || !std::isfinite(o->dt))
+            return fail(RBFFD_E_ARG, "rho, mu, dt must be positive and finite" + at);
+        for (int d = 0; d < 3; ++d)
+            if (!std::isfinite(o->force[d])) return fail(RBFFD_E_ARG, "the body force must be finite" + at);
+        if (!(o->alpha[0] != 0.0) || !std::isfinite(o->alpha[1]) || !std::isfinite(o->alpha[2]))
+            return fail(RBFFD_E_ARG, "bad BDF coefficients" + at);
+        if (o->max_outer < 1 || o->max_krylov < 1 || !(o->tol_krylov >= 0.0) || !(o->tol_outer >= 0.0))
+            return fail(RBFFD_E_ARG, "bad iteration limits or tolerances" + at);
+        if (o->precision != RBFFD_FP64) return fail(RBFFD_E_ARG, "batched steps run in FP64" + at);
+        if (o->preconditioner != RBFFD_PREC_JACOBI && o->preconditioner != RBFFD_PREC_BLOCK64)
+            return fail(RBFFD_E_ARG, "unknown preconditioner" + at);
+    }
+    RB_HIP(hipSetDevice(ctx->device));
+    return run_step_batched(ctx, count, ops, u, u_prev, p, u_bc, p_bc, opts, stats, (hipStream_t)hip_stream);
+}
+
 int rbffd_convdiff_lambda(rbffd_ctx *ctx, const rbffd_ops *ops, const double *u0, double rho,
                           double mu, int iters, double *lambda_out, void *hip_stream)
 {

@@ -351,6 +351,9 @@ int poisson_solve_noalloc_impl(int device, int64_t n, int q, ColIdx col, const d
 int residual_norms(rbffd_ctx *ctx, int64_t n, int q, ColIdx col, const double *val,
                    int nrhs, const double *b, const double *x, double *relres_out, hipStream_t s);
 
+int run_step_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops, double *const *u,
+                     double *const *u_prev, double *const *p, const double *const *u_bc, const double *const *p_bc,
+                     const rbffd_step_opts *o, rbffd_step_stats *st, hipStream_t s);
 int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, double *p,
              const double *u_bc, const double *p_bc, const rbffd_step_opts *o, rbffd_step_stats *st,
              hipStream_t s);

@@ -9,6 +9,7 @@
 // with the change Delta. Only Delta (8 bytes) returns to the host per
 // iteration.
 #include <cmath>
+#include <vector>
 
 #include "internal.h"
 
@@ -641,6 +642,300 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
     if (status != RBFFD_OK)
         return fail(status, status == RBFFD_E_NOCONV ? "simple_step: an iteration limit was reached"
                                                      : "simple_step: Krylov breakdown");
+    return RBFFD_OK;
+}
+
+// ---- one time step of many independent clouds -------------------------------
+// The outer iteration of run_step on every cloud at once: the per-cloud kernels
+// (momentum matrix and right-hand sides, divergence, pressure updates,
+// corrections, Delta) are launched cloud by cloud, and each Krylov stage is one
+// batched solve over the clouds still iterating (bicgstab_batched: every
+// system owns its blocks and reductions, so a cloud's result does not depend on
+// the others). A cloud leaves the outer loop when its own Delta meets its own
+// tolerance. FP64; no symmetry points (their momentum rows differ between
+// components).
+int run_step_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops, double *const *u,
+                     double *const *u_prev, double *const *p, const double *const *u_bc, const double *const *p_bc,
+                     const rbffd_step_opts *o, rbffd_step_stats *st, hipStream_t s)
+{
+    // per-cloud workspace: the run_step buffers, packed
+    std::vector<StepBufs> B(count);
+    std::vector<size_t> off(count + 1, 0);
+    for (int j = 0; j < count; ++j) {
+        const int64_t n = ops[j]->n, nbv = std::max<int64_t>(ops[j]->nb, 1);
+        const int dim = ops[j]->dim;
+        const size_t words = (size_t)n * (4 * dim + 4) + (kMaxRhs * kMaxBlocks + 8) + 2 * (size_t)nbv;
+        off[j + 1] = off[j] + (words + 31) / 32 * 32;
+    }
+    char *w = nullptr;
+    RB_CHECK(workspace(ctx, WS_STEP, sizeof(double) * (off[count] + 2 * (size_t)count), (void **)&w));
+    double *base = (double *)w;
+    double *deltas = base + off[count];   // [count][2] (Delta, rate) of each cloud, one read-back
+    for (int j = 0; j < count; ++j) {
+        const int64_t n = ops[j]->n, nbv = std::max<int64_t>(ops[j]->nb, 1);
+        const int dim = ops[j]->dim;
+        double *b = base + off[j];
+        B[j].ur = b;
+        B[j].ut = B[j].ur + dim * n;
+        B[j].un = B[j].ut + dim * n;
+        B[j].bm = B[j].un + dim * n;
+        B[j].pr = B[j].bm + dim * n;
+        B[j].pa = B[j].pr + n;
+        B[j].pc = B[j].pa + n;
+        B[j].f = B[j].pc + n;
+        B[j].part = B[j].f + n;
+        B[j].scal = B[j].part + kMaxRhs * kMaxBlocks;
+        B[j].bb = B[j].scal + 8;
+        B[j].pb = B[j].bb + nbv;
+    }
+    std::vector<double> hdelta(count, 0.0);
+    std::vector<int> active(count, 1), outer(count, 0), kit_m(count, 0), kit_p(count, 0), kit_b(count, 0),
+        status(count, RBFFD_OK);
+    std::vector<double> relres_p(count, 0.0), relres_max(count, 0.0);
+    for (int j = 0; j < count; ++j) {
+        const rbffd_ops *op = ops[j];
+        const int gn = (int)((op->n + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_start, dim3(gn), dim3(kBlock), 0, s, op->n, op->dim, op->kind, u[j], u_bc[j], p[j], B[j].ur,
+                           B[j].pr);
+    }
+    RB_HIP(hipGetLastError());
+    int max_outer = 0;
+    for (int j = 0; j < count; ++j) max_outer = std::max(max_outer, o[j].max_outer);
+    std::vector<BatchSystem> sys;
+    std::vector<int> owner, it_v, st_v;
+    std::vector<double> rr_v;
+    auto solve = [&](int kind) -> int {
+        // kind 0: momentum (one system per component), 1: pressure correction, 2: boundary pressure
+        if (sys.empty()) return RBFFD_OK;
+        it_v.assign(sys.size(), 0);
+        st_v.assign(sys.size(), 0);
+        rr_v.assign(sys.size(), 0.0);
+        // one batched call per (tolerance, iteration limit): clouds usually share them
+        std::vector<char> done(sys.size(), 0);
+        for (size_t a = 0; a < sys.size(); ++a) {
+            if (done[a]) continue;
+            const rbffd_step_opts &oa = o[owner[a]];
+            std::vector<size_t> idx;
+            for (size_t b = a; b < sys.size(); ++b)
+                if (!done[b] && o[owner[b]].tol_krylov == oa.tol_krylov && o[owner[b]].max_krylov == oa.max_krylov) {
+                    idx.push_back(b);
+                    done[b] = 1;
+                }
+            std::vector<BatchSystem> sub;
+            for (size_t b : idx) sub.push_back(sys[b]);
+            std::vector<int> si(sub.size()), ss(sub.size());
+            std::vector<double> sr(sub.size());
+            RB_CHECK(bicgstab_batched(ctx, (int)sub.size(), sub.data(), oa.tol_krylov, oa.max_krylov, si.data(),
+                                      ss.data(), sr.data(), s));
+            for (size_t t = 0; t < idx.size(); ++t) {
+                it_v[idx[t]] = si[t];
+                st_v[idx[t]] = ss[t];
+                rr_v[idx[t]] = sr[t];
+            }
+        }
+        for (size_t a = 0; a < sys.size(); ++a) {
+            const int j = owner[a];
+            (kind == 0 ? kit_m : kind == 1 ? kit_p : kit_b)[j] += it_v[a];
+            relres_max[j] = std::max(relres_max[j], rr_v[a]);
+            if (kind == 1) relres_p[j] = rr_v[a];
+            if (st_v[a] != RBFFD_OK && status[j] == RBFFD_OK) status[j] = st_v[a];
+        }
+        return RBFFD_OK;
+    };
+    for (int it = 1; it <= max_outer; ++it) {
+        bool any = false;
+        for (int j = 0; j < count; ++j) {
+            if (active[j] && it > o[j].max_outer) active[j] = 0;
+            any = any || active[j];
+        }
+        if (!any) break;
+        // step 2: momentum matrices and right-hand sides, then one batched solve
+        sys.clear();
+        owner.clear();
+        for (int j = 0; j < count; ++j) {
+            if (!active[j]) continue;
+            const rbffd_ops *op = ops[j];
+            const rbffd_step_opts &oj = o[j];
+            const int64_t n = op->n, vs = op->npad * op->q;
+            const int gpad = (int)((op->npad + kBlock - 1) / kBlock);
+            const Force3 force{{oj.force[0], oj.force[1], oj.force[2]}};
+            if (op->dim == 2)
+                hipLaunchKernelGGL(k_momentum<2>, dim3(gpad), dim3(kBlock), 0, s, n, op->q, op->col, op->val, vs,
+                                   op->kind, op->normal, B[j].ur, u[j], u_prev[j], u_bc[j], B[j].pr, oj.rho, oj.mu, oj.dt,
+                                   oj.alpha[0], oj.alpha[1], oj.alpha[2], force, 0, op->mval, op->mdinv, B[j].bm);
+            else
+                hipLaunchKernelGGL(k_momentum<3>, dim3(gpad), dim3(kBlock), 0, s, n, op->q, op->col, op->val, vs,
+                                   op->kind, op->normal, B[j].ur, u[j], u_prev[j], u_bc[j], B[j].pr, oj.rho, oj.mu, oj.dt,
+                                   oj.alpha[0], oj.alpha[1], oj.alpha[2], force, 0, op->mval, op->mdinv, B[j].bm);
+            RB_HIP(hipMemcpyAsync(B[j].ut, B[j].ur, sizeof(double) * n * op->dim, hipMemcpyDeviceToDevice, s));
+            for (int e = 0; e < op->dim; ++e) {
+                BatchSystem y{};
+                y.n = n;
+                y.q = op->q;
+                y.col = cols_of(op);
+                y.val = op->mval;
+                y.dinv = op->mdinv;
+                y.b = B[j].bm + (int64_t)e * n;
+                y.x = B[j].ut + (int64_t)e * n;
+                y.binv = kNoBlockInv;
+                y.val32 = nullptr;
+                sys.push_back(y);
+                owner.push_back(j);
+            }
+        }
+        RB_HIP(hipGetLastError());
+        RB_CHECK(solve(0));
+        // step 3: pressure corrections from p' = 0, one batched solve
+        sys.clear();
+        owner.clear();
+        for (int j = 0; j < count; ++j) {
+            if (!active[j]) continue;
+            const rbffd_ops *op = ops[j];
+            const rbffd_step_opts &oj = o[j];
+            const int64_t n = op->n, vs = op->npad * op->q;
+            const int gn = (int)((n + kBlock - 1) / kBlock);
+            const double mass = oj.rho * oj.alpha[0] / oj.dt;
+            if (op->dim == 2)
+                hipLaunchKernelGGL(k_div_rhs<2>, dim3(gn), dim3(kBlock), 0, s, n, op->q, op->col, op->val, vs, op->kind,
+                                   op->pin, B[j].ut, mass, B[j].f);
+            else
+                hipLaunchKernelGGL(k_div_rhs<3>, dim3(gn), dim3(kBlock), 0, s, n, op->q, op->col, op->val, vs, op->kind,
+                                   op->pin, B[j].ut, mass, B[j].f);
+            RB_HIP(hipMemsetAsync(B[j].pc, 0, sizeof(double) * n, s));
+            BatchSystem y{};
+            y.n = n;
+            y.q = op->q;
+            y.col = cols_of(op);
+            y.val = op->pval;
+            y.dinv = op->pdinv;
+            y.b = B[j].f;
+            y.x = B[j].pc;
+            y.binv = oj.preconditioner == RBFFD_PREC_BLOCK64 ? binv_of(op) : kNoBlockInv;
+            y.val32 = nullptr;
+            sys.push_back(y);
+            owner.push_back(j);
+        }
+        RB_HIP(hipGetLastError());
+        RB_CHECK(solve(1));
+        // steps 4-5: interior pressure; boundary pressures, one batched solve
+        sys.clear();
+        owner.clear();
+        for (int j = 0; j < count; ++j) {
+            if (!active[j]) continue;
+            const rbffd_ops *op = ops[j];
+            const rbffd_step_opts &oj = o[j];
+            const int64_t n = op->n, vs = op->npad * op->q;
+            const int gn = (int)((n + kBlock - 1) / kBlock);
+            const Force3 force{{oj.force[0], oj.force[1], oj.force[2]}};
+            hipLaunchKernelGGL(k_p_interior, dim3(gn), dim3(kBlock), 0, s, n, op->kind, B[j].pr, B[j].pc,
+                               p_bc[j] ? p_bc[j] : B[j].pr, B[j].pa);
+            if (op->nb > 0) {
+                const unsigned gb = (unsigned)((op->nb + kBlock - 1) / kBlock);
+                if (op->dim == 2)
+                    hipLaunchKernelGGL(k_boundary_rhs<2>, dim3(gb), dim3(kBlock), 0, s, n, op->nb, op->q, op->col,
+                                       op->val, vs, op->pval, op->kind, op->normal, op->bidx, B[j].ut, u[j], u_prev[j],
+                                       B[j].pa, B[j].pr, oj.rho, oj.mu, oj.dt, oj.alpha[0], oj.alpha[1], oj.alpha[2],
+                                       force, B[j].bb, B[j].pb);
+                else
+                    hipLaunchKernelGGL(k_boundary_rhs<3>, dim3(gb), dim3(kBlock), 0, s, n, op->nb, op->q, op->col,
+                                       op->val, vs, op->pval, op->kind, op->normal, op->bidx, B[j].ut, u[j], u_prev[j],
+                                       B[j].pa, B[j].pr, oj.rho, oj.mu, oj.dt, oj.alpha[0], oj.alpha[1], oj.alpha[2],
+                                       force, B[j].bb, B[j].pb);
+                BatchSystem y{};
+                y.n = op->nb;
+                y.q = op->q;
+                y.col = cols_plain(op->gcol);
+                y.val = op->gval;
+                y.dinv = op->gdinv;
+                y.b = B[j].bb;
+                y.x = B[j].pb;
+                y.binv = kNoBlockInv;
+                y.val32 = nullptr;
+                sys.push_back(y);
+                owner.push_back(j);
+            }
+        }
+        RB_HIP(hipGetLastError());
+        RB_CHECK(solve(2));
+        // steps 6-7: scatter the pressures, correct the velocities, Delta
+        for (int j = 0; j < count; ++j) {
+            if (!active[j]) continue;
+            const rbffd_ops *op = ops[j];
+            const rbffd_step_opts &oj = o[j];
+            const int64_t n = op->n, vs = op->npad * op->q;
+            const int gn = (int)((n + kBlock - 1) / kBlock);
+            const int nblk = blocks_for(n);
+            const double coef = oj.dt / (oj.rho * oj.alpha[0]);
+            hipLaunchKernelGGL(k_p_scatter, dim3(gn), dim3(kBlock), 0, s, n, op->kind, op->bpos, B[j].pa, B[j].pb,
+                               B[j].pr);
+            if (op->dim == 2)
+                hipLaunchKernelGGL(k_correct<2>, dim3(nblk), dim3(kBlock), 0, s, n, op->q, op->col, op->val, vs, op->kind,
+                                   B[j].pc, B[j].ut, B[j].ur, coef, B[j].un, B[j].part);
+            else
+                hipLaunchKernelGGL(k_correct<3>, dim3(nblk), dim3(kBlock), 0, s, n, op->q, op->col, op->val, vs, op->kind,
+                                   B[j].pc, B[j].ut, B[j].ur, coef, B[j].un, B[j].part);
+            hipLaunchKernelGGL(k_finish_sums, dim3(1), dim3(kBlock), 0, s, B[j].part, nblk, op->dim, n, oj.dt,
+                               deltas + 2 * j);
+        }
+        RB_HIP(hipGetLastError());
+        double *hd = nullptr;   // pinned; the batched solves are done with their staging by now
+        RB_CHECK(workspace(ctx, WS_BATCH_HOST, sizeof(double) * 2 * (size_t)count, (void **)&hd));
+        RB_HIP(hipMemcpyAsync(hd, deltas, sizeof(double) * 2 * count, hipMemcpyDeviceToHost, s));
+        RB_HIP(hipStreamSynchronize(s));
+        for (int j = 0; j < count; ++j) {
+            if (!active[j]) continue;
+            hdelta[j] = hd[2 * j];
+            outer[j] = it;
+            std::swap(B[j].ur, B[j].un);
+            if (hdelta[j] < o[j].tol_outer) active[j] = 0;
+        }
+    }
+    // steady rates, continuity errors, time-level rotation, statistics
+    for (int j = 0; j < count; ++j) {
+        const rbffd_ops *op = ops[j];
+        const int64_t n = op->n, vs = op->npad * op->q;
+        const int nblk = blocks_for(n);
+        hipLaunchKernelGGL(k_absdiff, dim3(nblk), dim3(kBlock), 0, s, n, op->dim, B[j].ur, u[j], B[j].part);
+        hipLaunchKernelGGL(k_finish_sums, dim3(1), dim3(kBlock), 0, s, B[j].part, nblk, op->dim, n, o[j].dt,
+                           B[j].scal + 2);
+        if (op->dim == 2)
+            hipLaunchKernelGGL(k_div_abs<2>, dim3(nblk), dim3(kBlock), 0, s, n, op->q, op->col, op->val, vs, op->kind,
+                               B[j].ur, B[j].part);
+        else
+            hipLaunchKernelGGL(k_div_abs<3>, dim3(nblk), dim3(kBlock), 0, s, n, op->q, op->col, op->val, vs, op->kind,
+                               B[j].ur, B[j].part);
+        hipLaunchKernelGGL(k_finish_ratio, dim3(1), dim3(kBlock), 0, s, B[j].part, nblk, B[j].scal + 4);
+        const size_t vec = sizeof(double) * n;
+        RB_HIP(hipMemcpyAsync(u_prev[j], u[j], vec * op->dim, hipMemcpyDeviceToDevice, s));
+        RB_HIP(hipMemcpyAsync(u[j], B[j].ur, vec * op->dim, hipMemcpyDeviceToDevice, s));
+        RB_HIP(hipMemcpyAsync(p[j], B[j].pr, vec, hipMemcpyDeviceToDevice, s));
+    }
+    RB_HIP(hipGetLastError());
+    std::vector<double> sc(3 * (size_t)count);
+    for (int j = 0; j < count; ++j)
+        RB_HIP(hipMemcpyAsync(&sc[3 * j], B[j].scal + 2, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
+    RB_HIP(hipStreamSynchronize(s));
+    int first_fail = RBFFD_OK;
+    for (int j = 0; j < count; ++j) {
+        if (outer[j] >= o[j].max_outer && hdelta[j] >= o[j].tol_outer && status[j] == RBFFD_OK &&
+            o[j].tol_outer > 0.0)
+            status[j] = RBFFD_E_NOCONV;   // tol_outer <= 0 asks for exactly max_outer iterations
+        rbffd_step_stats &t = st[j];
+        t.outer_iters = outer[j];
+        t.krylov_mom = kit_m[j];
+        t.krylov_p = kit_p[j];
+        t.krylov_b = kit_b[j];
+        t.status = status[j];
+        t.delta = hdelta[j];
+        t.eps_steady = sc[3 * j + 1];
+        t.div_l1 = sc[3 * j + 2];
+        t.final_relres_p = relres_p[j];
+        t.krylov_relres_max = relres_max[j];
+        if (status[j] != RBFFD_OK && first_fail == RBFFD_OK) first_fail = status[j];
+    }
+    if (first_fail != RBFFD_OK)
+        return fail(first_fail, "simple_step_batched: an iteration limit was reached or a Krylov solve broke down "
+                                "(per-cloud status in stats)");
     return RBFFD_OK;
 }
 
