@@ -624,6 +624,7 @@ int rbffd_ops_export_block_inverse(const rbffd_ops *ops, float *out, void *hip_s
     if (!ops->ctx) return fail(RBFFD_E_ARG, "the operators' context was destroyed");
     RB_HIP(hipSetDevice(ops->ctx->device));
     hipStream_t s = (hipStream_t)hip_stream;
+    RB_CHECK(ensure_block_inverse(ops, s));
     RB_CHECK(expand_block_inverse(ops, out, s));
     RB_HIP(hipStreamSynchronize(s));
     return RBFFD_OK;
@@ -945,6 +946,7 @@ int poisson_solve(rbffd_ctx *ctx, const rbffd_ops *ops, const double *rhs, doubl
     if (opts->preconditioner != RBFFD_PREC_JACOBI && opts->preconditioner != RBFFD_PREC_BLOCK64)
         return fail(RBFFD_E_ARG, "unknown preconditioner");
     const bool block = opts->preconditioner == RBFFD_PREC_BLOCK64;
+    if (block) RB_CHECK(ensure_block_inverse(ops, s));
     if (block && opts->precision == RBFFD_FP64)
         st = bicgstab_block(ctx, ops->n, ops->q, cols_of(ops), ops->pval, binv_of(ops), rhs, x, opts->tol,
                             opts->max_iter, &res, s);
@@ -1031,6 +1033,10 @@ int poisson_solve_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops
         if (!ops[j]->ctx) return fail(RBFFD_E_ARG, "the operators' context was destroyed");
         if (f32 && !ops[j]->pval32)
             return fail(RBFFD_E_ARG, "system " + std::to_string(j) + " was assembled without FP32 copies");
+        if (block) {
+            RB_HIP(hipSetDevice(ctx->device));
+            RB_CHECK(ensure_block_inverse(ops[j], (hipStream_t)hip_stream));
+        }
         sys[j] = BatchSystem{ops[j]->n, ops[j]->q, cols_of(ops[j]), ops[j]->pval, ops[j]->pdinv, rhs[j], x[j],
                              block ? binv_of(ops[j]) : kNoBlockInv, f32 ? ops[j]->pval32 : nullptr};
     }
@@ -1090,6 +1096,11 @@ int rbffd_server_submit(rbffd_server *sv, const rbffd_ops *ops, const double *rh
     const bool f32 = opts->precision == RBFFD_FP32_MATRIX;
     if (f32 && !ops->pval32) return fail(RBFFD_E_ARG, "operators were assembled without FP32 copies");
     RB_HIP(hipSetDevice(sv->ctx->device));
+    if (opts->preconditioner == RBFFD_PREC_BLOCK64 && !ops->pbinv) {
+        // built once, on the null stream, and finished before the server uses it
+        RB_CHECK(ensure_block_inverse(ops, nullptr));
+        RB_HIP(hipStreamSynchronize(nullptr));
+    }
     const BatchSystem sys{ops->n, ops->q, cols_of(ops), ops->pval, ops->pdinv, rhs, x,
                           opts->preconditioner == RBFFD_PREC_BLOCK64 ? binv_of(ops) : kNoBlockInv,
                           f32 ? ops->pval32 : nullptr};

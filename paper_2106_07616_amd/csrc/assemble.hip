@@ -367,12 +367,8 @@ int assemble_ops(rbffd_ctx *ctx, const rbffd_cloud *cloud, int q, int k, int phs
                            ops->normal, ops->pin, n, q, ops->pval, ops->pdinv);
     RB_HIP(hipGetLastError());
 
-    // block-Jacobi preconditioner of the pressure-correction matrix
-    RB_CHECK(alloc_ops(ops, &ops->pbinv, (size_t)npad * 64));
-    RB_CHECK(alloc_ops(ops, &ops->pbscale, (size_t)nslices));
-    hipLaunchKernelGGL(block_inverse, dim3(nslices), dim3(64), 0, s, ops->col, ops->pval, n, q, ops->pbinv,
-                       ops->pbscale);
-    RB_HIP(hipGetLastError());
+    // the block-Jacobi inverses of the pressure-correction matrix are built at
+    // the first solve that asks for them (ensure_block_inverse)
 
     // boundary numbering
     int32_t *flag = nullptr, *pos = nullptr, *flag2 = nullptr, *pos2 = nullptr;
@@ -431,6 +427,30 @@ int launch_to_fp32(const double *x, float *y, int64_t m, hipStream_t s)
 {
     hipLaunchKernelGGL(to_fp32, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, x, y, m);
     RB_HIP(hipGetLastError());
+    return RBFFD_OK;
+}
+
+int ensure_block_inverse(const rbffd_ops *cops, hipStream_t s)
+{
+    if (cops->pbinv) return RBFFD_OK;
+    // the inverses depend on the pressure-correction values only, which stay as
+    // assembled: building them late gives what building them at assembly would
+    rbffd_ops *ops = const_cast<rbffd_ops *>(cops);
+    const unsigned nslices = (unsigned)(ops->npad / 64);
+    __half *bi = nullptr;
+    float *bs = nullptr;
+    RB_CHECK(alloc_ops(ops, &bi, (size_t)ops->npad * 64));
+    int st = alloc_ops(ops, &bs, (size_t)nslices);
+    if (st != RBFFD_OK) {
+        (void)hipFree(bi);
+        ops->ctx->in_use -= sizeof(__half) * (size_t)ops->npad * 64;
+        ops->bytes -= sizeof(__half) * (size_t)ops->npad * 64;
+        return st;
+    }
+    hipLaunchKernelGGL(block_inverse, dim3(nslices), dim3(64), 0, s, ops->col, ops->pval, ops->n, ops->q, bi, bs);
+    RB_HIP(hipGetLastError());
+    ops->pbinv = bi;
+    ops->pbscale = bs;
     return RBFFD_OK;
 }
 

@@ -180,6 +180,8 @@ struct BlockInv {
 };
 
 inline BlockInv binv_of(const rbffd_ops *ops) { return BlockInv{ops->pbinv, ops->pbscale}; }
+// build the operators' block inverses if no solve has asked for them yet
+int ensure_block_inverse(const rbffd_ops *ops, hipStream_t s);
 
 // Points whose pressure correction has a homogeneous Neumann row and whose
 // pressure comes from the normal momentum equation (Sec. 3.1).

@@ -553,6 +553,7 @@ int run_step(rbffd_ctx *ctx, const rbffd_ops *ops, double *u, double *u_prev, do
         RB_HIP(hipMemsetAsync(B.pc, 0, vec, s));
         KrylovResult kp;
         const bool block = o->preconditioner == RBFFD_PREC_BLOCK64;
+        if (block) RB_CHECK(ensure_block_inverse(ops, s));
         if (fp32)
             RB_CHECK(bicgstab_mixed(ctx, o->precision, n, q, cols_of(ops), ops->pval, ops->pval32, ops->pdinv32,
                                     ops->pdinv, block ? binv_of(ops) : kNoBlockInv, 1, B.f, B.pc, o->tol_krylov,
@@ -810,6 +811,7 @@ int run_step_batched(rbffd_ctx *ctx, int count, const rbffd_ops *const *ops, dou
             y.dinv = op->pdinv;
             y.b = B[j].f;
             y.x = B[j].pc;
+            if (oj.preconditioner == RBFFD_PREC_BLOCK64) RB_CHECK(ensure_block_inverse(op, s));
             y.binv = oj.preconditioner == RBFFD_PREC_BLOCK64 ? binv_of(op) : kNoBlockInv;
             y.val32 = nullptr;
             sys.push_back(y);
