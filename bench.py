@@ -1032,7 +1032,8 @@ def weights_only(args):
     import workloads as W
     cloud, k = {"tg250k_k4": (lambda: W.taylor_green_disk(), 4),
                 "cube40_k4": (lambda: W.beltrami_cube(n=40), 4),
-                "tg60k_k6": (lambda: W.taylor_green_disk(r=0.021), 6)}[args.weights_only]
+                "tg60k_k6": (lambda: W.taylor_green_disk(r=0.021), 6),
+                "beltrami100_k3": (lambda: W.beltrami_cube(n=100), 3)}[args.weights_only]
     cloud = cloud()
     ctx = R.Context(0)
     dc = R.DeviceCloud.from_numpy(cloud)
@@ -1084,7 +1085,7 @@ def main():
     ap.add_argument("--counters-only", action="store_true",
                     help="run only the SpMV timing, the timed BiCGSTAB kernels and a copy of known size "
                          "(for hardware counter runs)")
-    ap.add_argument("--weights-only", choices=["tg250k_k4", "cube40_k4", "tg60k_k6"], default=None,
+    ap.add_argument("--weights-only", choices=["tg250k_k4", "cube40_k4", "tg60k_k6", "beltrami100_k3"], default=None,
                     help="only build the stencils of one cloud a few times (for weight-kernel profiles): the "
                          "250k Taylor-Green disk at degree 4 (45 unknowns), a 40^3 cube at degree 4 (105) or a "
                          "60k Taylor-Green disk at degree 6 (84)")

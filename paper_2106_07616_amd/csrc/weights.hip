@@ -104,33 +104,39 @@ __device__ inline double monomial(const int *ex, const double *x)
     return v;
 }
 
-// graded monomial order: by total degree, then descending x power, then y power
+// graded monomial order: by total degree, then descending x power, then
+// descending y power. Closed form: the degree t is the first with more than
+// alpha monomials of degree <= t, and the position r within degree t fixes the
+// powers (a short loop over the x power in 3-D). A search that returns from a
+// nested loop unrolls into a divergent branch chain whose saved exec masks
+// spill scalar registers.
+template <int DIM>
+__device__ inline int monomials_below(int t)
+{
+    return DIM == 2 ? t * (t + 1) / 2 : t * (t + 1) * (t + 2) / 6;
+}
+
 template <int DIM>
 __device__ inline void monomial_exponents(int alpha, int *ex)
 {
-    int idx = 0;
-    for (int t = 0; t <= 16; ++t) {
-        for (int a = t; a >= 0; --a) {
-            if (DIM == 2) {
-                if (idx == alpha) {
-                    ex[0] = a;
-                    ex[1] = t - a;
-                    ex[2] = 0;
-                    return;
-                }
-                ++idx;
-            } else {
-                for (int b = t - a; b >= 0; --b) {
-                    if (idx == alpha) {
-                        ex[0] = a;
-                        ex[1] = b;
-                        ex[2] = t - a - b;
-                        return;
-                    }
-                    ++idx;
-                }
-            }
+    int t = 0;
+#pragma unroll 1
+    while (monomials_below<DIM>(t + 1) <= alpha) ++t;
+    int r = alpha - monomials_below<DIM>(t);
+    if (DIM == 2) {
+        ex[0] = t - r;
+        ex[1] = r;
+        ex[2] = 0;
+    } else {
+        int a = t;
+#pragma unroll 1
+        while (r > t - a) {
+            r -= t - a + 1;
+            --a;
         }
+        ex[0] = a;
+        ex[1] = t - a - r;
+        ex[2] = r;
     }
 }
 
@@ -141,8 +147,18 @@ __device__ inline void monomial_exponents(int alpha, int *ex)
 // The work of one point lives in weights_point, so that the batched kernel
 // below runs the same arithmetic for the points of many clouds. xs and exs are
 // the block's LDS buffers (kMaxQ * DIM doubles, 64 * 3 ints).
+// Elimination segment length of the register kernel by system width: fully
+// unrolled (1) up to 32 unknowns, pairs of steps above (measured on MI355X
+// against lengths 3, 4, 8 and 16 and a fully unrolled kernel, whose 48- and
+// 64-wide bodies are 140-220 KB of code).
+template <int NSP>
+constexpr int weights_segment()
+{
+    return NSP <= 32 ? 1 : 2;
+}
+
 template <int NSP, int DIM, bool INTERP>
-__device__ inline void weights_point(const double *__restrict__ xyz, const double *__restrict__ ctr,
+__device__ __forceinline__ void weights_point(const double *__restrict__ xyz, const double *__restrict__ ctr,
                                      const int32_t *__restrict__ nbr, int64_t n, int q, int m, int phs,
                                      double *__restrict__ w, int64_t *__restrict__ bad, int64_t i, double *xs,
                                      int *exs)
@@ -181,20 +197,29 @@ __device__ inline void weights_point(const double *__restrict__ xyz, const doubl
         myex[1] = exs[(lane - q) * 3 + 1];
         myex[2] = exs[(lane - q) * 3 + 2];
     }
+    // Columns are computed in a runtime loop per segment of SEG and dropped into
+    // their (constant-index) registers by a select, which keeps the code small.
+    constexpr int SEG = weights_segment<NSP>();
 #pragma unroll
-    for (int b = 0; b < NSP; ++b) {
-        double v = 0.0;
-        if (lane < q) {
-            if (b < q) {
-                const double r = sqrt(sqdist_exact<DIM>(mine, xs + b * DIM));
-                v = (phs == 3) ? r * r * r : r * r * r * r * r;
-            } else if (b < ns) {
-                v = monomial<DIM>(exs + (b - q) * 3, mine);
+    for (int b0 = 0; b0 < NSP; b0 += SEG) {
+#pragma unroll 1
+        for (int t = 0; t < SEG; ++t) {
+            const int b = b0 + t;
+            double v = 0.0;
+            if (lane < q) {
+                if (b < q) {
+                    const double r = sqrt(sqdist_exact<DIM>(mine, xs + b * DIM));
+                    v = (phs == 3) ? r * r * r : r * r * r * r * r;
+                } else if (b < ns) {
+                    v = monomial<DIM>(exs + (b - q) * 3, mine);
+                }
+            } else if (lane < ns) {
+                if (b < q) v = monomial<DIM>(myex, xs + b * DIM);
             }
-        } else if (lane < ns) {
-            if (b < q) v = monomial<DIM>(myex, xs + b * DIM);
+#pragma unroll
+            for (int tt = 0; tt < SEG; ++tt)
+                if (b0 + tt < NSP && t == tt) a_[b0 + tt] = v;
         }
-        a_[b] = v;
     }
     {
         // right-hand sides: L phi(|x - x_lane|) and L P_alpha at the centre
@@ -239,25 +264,39 @@ __device__ inline void weights_point(const double *__restrict__ xyz, const doubl
     bool active = lane < ns;
     int mystep = -1;
     bool singular = false;
+    // The steps run in segments of SEG: the segment loop is unrolled (so every
+    // register index is a constant) and the steps inside a segment are a
+    // runtime loop that updates the segment's remaining columns. A fully
+    // unrolled elimination is over 100 KB of code for 45+ unknowns, more than
+    // the instruction cache; segmenting costs ~15% extra column updates and
+    // gives the same arithmetic, column by column.
 #pragma unroll
-    for (int k = 0; k < NSP; ++k) {
-        if (k < ns) {
-            const double v = active ? fabs(a_[k]) : -1.0;
+    for (int k0 = 0; k0 < NSP; k0 += SEG) {
+        const int kend = min(k0 + SEG, ns);
+#pragma unroll 1
+        for (int k = k0; k < kend; ++k) {
+            double ak = a_[k0];
+#pragma unroll
+            for (int t = 1; t < SEG; ++t)
+                if (k0 + t < NSP && k == k0 + t) ak = a_[k0 + t];
+            const double v = active ? fabs(ak) : -1.0;
             const double mx = wave_max_dpp(v);
             const uint64_t msk = __ballot(active && v == mx);
             const int p = msk ? (__ffsll((unsigned long long)msk) - 1) : 0;
             if (!(mx > 1e-13 * amax)) singular = true;
-            double piv = readlane_d(a_[k], p);
+            double piv = readlane_d(ak, p);
             if (singular) piv = 1.0;
             if (lane == p) {
                 active = false;
                 mystep = k;
             }
-            const double l = active ? a_[k] / piv : 0.0;
+            const double l = active ? ak / piv : 0.0;
 #pragma unroll
-            for (int j = k + 1; j < NC; ++j) {
-                const double u = readlane_d(a_[j], p);
-                a_[j] = fma(-l, u, a_[j]);
+            for (int j = k0 + 1; j < NC; ++j) {
+                if (j >= k0 + SEG || j > k) {
+                    const double u = readlane_d(a_[j], p);
+                    a_[j] = fma(-l, u, a_[j]);
+                }
             }
         }
     }
@@ -267,18 +306,23 @@ __device__ inline void weights_point(const double *__restrict__ xyz, const doubl
 #pragma unroll
     for (int r = 0; r < R; ++r) xout[r] = 0.0;
 #pragma unroll
-    for (int k = NSP - 1; k >= 0; --k) {
-        if (k < ns) {
+    for (int k0 = ((NSP - 1) / SEG) * SEG; k0 >= 0; k0 -= SEG) {
+#pragma unroll 1
+        for (int k = min(k0 + SEG, ns) - 1; k >= k0; --k) {
+            double ak = a_[k0];
+#pragma unroll
+            for (int t = 1; t < SEG; ++t)
+                if (k0 + t < NSP && k == k0 + t) ak = a_[k0 + t];
             const uint64_t msk = __ballot(mystep == k);
             const int p = msk ? (__ffsll((unsigned long long)msk) - 1) : 0;
-            double dgl = readlane_d(a_[k], p);
+            double dgl = readlane_d(ak, p);
             if (singular) dgl = 1.0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const double y = readlane_d(a_[NSP + r], p);
                 const double xk = y / dgl;
                 if (lane == k) xout[r] = xk;
-                if (mystep >= 0 && mystep < k) a_[NSP + r] = fma(-a_[k], xk, a_[NSP + r]);
+                if (mystep >= 0 && mystep < k) a_[NSP + r] = fma(-ak, xk, a_[NSP + r]);
             }
         }
     }
@@ -312,8 +356,8 @@ __global__ __launch_bounds__(64) void weights_kernel(const double *__restrict__ 
 // with that cloud's sizes, so every point gets exactly the arithmetic of the
 // one-cloud kernel. Each cloud has its own singular-point slot. Clouds of
 // different widths go to different launches: one kernel covering every width
-// would hold the widest path's registers (248 VGPRs against 115 at width 16)
-// and run the narrow systems at a quarter of their occupancy.
+// would hold the widest path's registers (167 VGPRs against 58 at width 16)
+// and run the narrow systems at a third of their occupancy.
 template <int NSP, int DIM>
 __global__ __launch_bounds__(64) void weights_batched_kernel(const WeightSys *__restrict__ sys, int count,
                                                              int64_t *__restrict__ bad)
