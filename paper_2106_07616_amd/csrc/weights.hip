@@ -14,11 +14,13 @@
 //    in registers; the pivot search is a DPP wave max-reduction, the pivot row
 //    is broadcast lane-to-scalar with readlane, and the rank-1 update is one
 //    FP64 FMA per entry (LU, then back substitution);
-//  - 65-128 unknowns (2D degree 6, 3D degree 4): four wavefronts per system,
-//    the matrix in LDS in MFMA tiles, blocked Gauss-Jordan in panels of four
-//    columns whose rank-4 updates run on v_mfma_f64_16x16x4 (below). Where
-//    that layout does not fit the workgroup's LDS (128 unknowns with four
-//    right-hand sides), an unblocked LDS kernel takes the system.
+//  - 65-112 unknowns with their right-hand sides (2D degree 6, 3D degree 4):
+//    blocked Gauss-Jordan in panels of four columns whose rank-4 updates run
+//    on v_mfma_f64_16x16x4, the matrix in registers as MFMA tiles spread over
+//    two or four wavefronts (below);
+//  - up to 128: the same elimination with the tiles in LDS, and where that
+//    layout does not fit the workgroup's LDS (128 unknowns with four
+//    right-hand sides), an unblocked LDS kernel.
 // On gfx950 the FP64 matrix-core rate equals the FP64 vector rate: the MFMA
 // path pays by replacing per-entry LDS traffic and broadcasts with one
 // instruction per 16 x 16 tile, not by a higher ceiling.
@@ -689,10 +691,11 @@ __host__ __device__ inline size_t gj_lds_bytes(int q, int ns, int nc, int dim)
 // eliminates the column from the panel's later columns. Writes -L to Lbuf in the
 // MFMA A layout, the pivot rows' multipliers for earlier panel columns to lpb,
 // and the pivot rows and values.
-template <int RPL>
-__device__ inline void gj_factor_panel(const double *M, int tr, int tc, int c0, int np, bool *act, double amax,
-                                       bool &singular, double *Lbuf, double *lpb, int *prow, double *pv, int *sflag,
-                                       int lane)
+// ld(i, cc) gives entry (i, c0 + cc) for the rows i < rows.
+template <int RPL, typename Load>
+__device__ inline void gj_factor_panel_with(Load ld, int rows, int c0, int np, bool *act, double amax,
+                                            bool &singular, double *Lbuf, double *lpb, int *prow, double *pv,
+                                            int *sflag, int lane)
 {
     double a[RPL][4], l[RPL][4];
 #pragma unroll
@@ -700,7 +703,7 @@ __device__ inline void gj_factor_panel(const double *M, int tr, int tc, int c0, 
 #pragma unroll
         for (int cc = 0; cc < 4; ++cc) {
             const int i = lane + 64 * h;
-            a[h][cc] = (cc < np && i < tr * 16) ? M[gj_slot(i, c0 + cc, tc)] : 0.0;
+            a[h][cc] = (cc < np && i < rows) ? ld(i, cc) : 0.0;
             l[h][cc] = 0.0;
         }
 #pragma unroll
@@ -754,10 +757,19 @@ __device__ inline void gj_factor_panel(const double *M, int tr, int tc, int c0, 
 #pragma unroll
     for (int h = 0; h < RPL; ++h) {
         const int i = lane + 64 * h;
-        if (i < tr * 16)
+        if (i < rows)
 #pragma unroll
             for (int cc = 0; cc < 4; ++cc) Lbuf[(i >> 4) * 64 + (i & 15) + 16 * cc] = -l[h][cc];
     }
+}
+
+template <int RPL>
+__device__ inline void gj_factor_panel(const double *M, int tr, int tc, int c0, int np, bool *act, double amax,
+                                       bool &singular, double *Lbuf, double *lpb, int *prow, double *pv, int *sflag,
+                                       int lane)
+{
+    gj_factor_panel_with<RPL>([=](int i, int cc) { return M[gj_slot(i, c0 + cc, tc)]; }, tr * 16, c0, np, act,
+                              amax, singular, Lbuf, lpb, prow, pv, sflag, lane);
 }
 
 // Panel c0's rank-np update of tile column J, by the one wavefront that owns
@@ -900,6 +912,265 @@ __global__ __launch_bounds__(64 * NW) void weights_kernel_gj(const double *__res
     if (singular && tid == 0) atomicMin((unsigned long long *)bad, (unsigned long long)i0);
 }
 
+// Calls f(std::integral_constant<int, k>) for k = 0 .. N - 1, so that f can
+// index register arrays with k.
+template <int K>
+struct IntC {
+    static constexpr int value = K;
+};
+template <int N, int K = 0, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (K < N) {
+        f(IntC<K>{});
+        static_for<N, K + 1>(f);
+    }
+}
+
+// Systems of 65-112 unknowns (right-hand sides included) with the matrix in
+// registers: TR x TC tiles of 16 x 16 in the MFMA accumulator layout (lane l:
+// column l % 16, rows 4 v + l / 16 in register v), tile column J held by
+// wavefront J % NW, and the same Gauss-Jordan in panels of four columns as
+// the kernel above. Per panel, the panel's owner passes its columns through
+// LDS to the register factorisation (pivot rule, multipliers, -L in the A
+// layout); every wavefront passes its part of the raw pivot rows through LDS to
+// its B operands (forward substitution over the pivot rows), and every tile
+// takes its rank-4 update in one MFMA. With no matrix in LDS, two systems
+// share a CU and one's serial panel chain overlaps the other's updates.
+template <int DIM, bool INTERP, int TR, int TC, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void weights_kernel_gjr(const double *__restrict__ xyz,
+                                                              const double *__restrict__ ctr,
+                                                              const int32_t *__restrict__ nbr, int64_t n, int q,
+                                                              int m, int phs, double *__restrict__ w,
+                                                              int64_t *__restrict__ bad)
+{
+    constexpr int R = INTERP ? 1 : DIM + 1;
+    constexpr int RPL = (TR * 16 + 63) / 64;
+    constexpr int TCW = (TC + NW - 1) / NW;   // tile columns per wavefront
+    constexpr int NT = 64 * NW;
+    __shared__ double xs[kMaxQ * DIM];
+    __shared__ int exs[128 * 3];
+    __shared__ __attribute__((aligned(16))) double S[TR * 256];   // a tile column; the right-hand sides
+    __shared__ double P[TR * 64];                                  // the panel: row i, column c0 + cc at 4 i + cc
+    __shared__ double Lb[2][TR * 64];                              // -L of a panel, MFMA A layout (by parity)
+    __shared__ double Ur[NW][4][TCW * 16];                         // raw pivot rows, a wavefront's tile columns
+    __shared__ double lp[2][16];
+    __shared__ double pv[TR * 16];
+    __shared__ int prow[TR * 16];
+    __shared__ double redm[NW];
+    __shared__ int sflag;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4, cl = lane & 15;
+    const int64_t i0 = blockIdx.x;
+    if (i0 >= n) return;
+    const int ns = q + m;
+
+    double c[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) c[d] = ctr[i0 * DIM + d];
+    const int64_t jl = nbr[i0 * q + q - 1];
+    const double s = sqrt(sqdist_exact<DIM>(c, xyz + jl * DIM));
+    for (int a = tid; a < q; a += NT) {
+        const int64_t j = nbr[i0 * q + a];
+        for (int d = 0; d < DIM; ++d) xs[a * DIM + d] = (xyz[j * DIM + d] - c[d]) / s;
+    }
+    for (int a = tid; a < m; a += NT) {
+        int ex[3];
+        monomial_exponents<DIM>(a, ex);
+        exs[a * 3 + 0] = ex[0];
+        exs[a * 3 + 1] = ex[1];
+        exs[a * 3 + 2] = ex[2];
+    }
+    if (tid == 0) sflag = 0;
+    __syncthreads();
+
+    // the matrix, a tile column at a time through LDS (entries in slot order),
+    // each column into its owner's registers
+    v4d T[TR][TCW];
+    double amax = 0.0;
+#pragma unroll
+    for (int J = 0; J < TC; ++J) {
+#pragma unroll 1
+        for (int e = tid; e < TR * 256; e += NT) {
+            const int v = e & 3, l = (e >> 2) & 63, I = e >> 8;
+            const int i = 16 * I + 4 * v + (l >> 4), j = 16 * J + (l & 15);
+            const double a = gj_entry<DIM, INTERP>(i, j, q, ns, phs, xs, exs);
+            S[e] = a;
+            if (j < ns) amax = fmax(amax, fabs(a));
+        }
+        __syncthreads();
+        if (wv == J % NW)
+#pragma unroll
+            for (int I = 0; I < TR; ++I) {
+                const double2 *sp = (const double2 *)(S + ((I * 64 + lane) << 2));
+                const double2 a01 = sp[0], a23 = sp[1];
+                T[I][J / NW] = (v4d){a01.x, a01.y, a23.x, a23.y};
+            }
+        __syncthreads();
+    }
+    amax = wave_max_dpp(amax);
+    if (lane == 0) redm[wv] = amax;
+    __syncthreads();
+    amax = 0.0;
+#pragma unroll
+    for (int u = 0; u < NW; ++u) amax = fmax(amax, redm[u]);
+
+    bool act[RPL];
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) act[h] = lane + 64 * h < ns;
+
+    // Factor the panel at column c1 (its owner only): its columns through LDS
+    // to the register factorisation, -L and the pivot-row multipliers into the
+    // buffers of parity b.
+    auto factor = [&](int c1, int b) {
+        const int J1 = c1 >> 4, sp = (c1 >> 2) & 3;
+        const int cc = cl - 4 * sp;
+        const bool inp = cc >= 0 && cc < 4;
+#pragma unroll
+        for (int jj = 0; jj < TCW; ++jj)
+            if (jj == J1 / NW) {
+                if (inp)
+#pragma unroll
+                    for (int I = 0; I < TR; ++I)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) P[(16 * I + 4 * v + g) * 4 + cc] = T[I][jj][v];
+            }
+        bool singular = sflag != 0;
+        gj_factor_panel_with<RPL>([&](int i, int cc2) { return P[i * 4 + cc2]; }, TR * 16, c1, min(4, ns - c1), act,
+                                  amax, singular, Lb[b], lp[b], prow, pv, &sflag, lane);
+    };
+    if (wv == 0) factor(0, 0);
+    __syncthreads();
+
+    // One runtime loop over the panels; tile accesses stay constant-indexed in
+    // loops over the wavefront's tile columns under uniform tests. Look-ahead:
+    // the owner of the next panel's tile column updates that column first and
+    // factors the next panel while the other wavefronts update theirs, so one
+    // barrier per panel orders everything.
+#pragma unroll 1
+    for (int c0 = 0; c0 < ns; c0 += 4) {
+        const int np = min(4, ns - c0), cend = c0 + np, J0 = c0 >> 4, buf = (c0 >> 2) & 1;
+        // the panel's pivot rows leave the active set; the raw pivot rows of
+        // this wavefront's tile columns to its LDS rows (row p sits in
+        // register (p % 16) / 4 of row tile p / 16, lanes 16 (p % 4) + 0..15)
+        for (int cc = 0; cc < np; ++cc) {
+            const int p = __builtin_amdgcn_readfirstlane(prow[c0 + cc]);
+#pragma unroll
+            for (int h = 0; h < RPL; ++h)
+                if (lane + 64 * h == p) act[h] = false;
+            const int pI = p >> 4, pv4 = (p & 15) >> 2;
+            const bool mine = g == (p & 3);
+#pragma unroll
+            for (int I = 0; I < TR; ++I)
+                if (I == pI)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (v == pv4) {
+                            if (mine)
+#pragma unroll
+                                for (int jj = 0; jj < TCW; ++jj) Ur[wv][cc][16 * jj + cl] = T[I][jj][v];
+                        }
+        }
+        double av[TR], lpv[6];
+#pragma unroll
+        for (int I = 0; I < TR; ++I) av[I] = Lb[buf][I * 64 + lane];
+        // the pivot rows' multipliers of earlier panel columns: (1,0) (2,0)
+        // (2,1) (3,0) (3,1) (3,2)
+        lpv[0] = lp[buf][4];
+        lpv[1] = lp[buf][8];
+        lpv[2] = lp[buf][9];
+        lpv[3] = lp[buf][12];
+        lpv[4] = lp[buf][13];
+        lpv[5] = lp[buf][14];
+        // rank-4 update of tile column jj (columns left of the panel's tile
+        // column are finished and skipped; B is zero up to the panel's end)
+        auto update = [&](auto jjc) {
+            constexpr int jj = decltype(jjc)::value;
+            const int J = NW * jj + wv;
+            if (J >= TC || J < J0) return;
+            const int j = 16 * J + cl;
+            double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
+            if (j >= cend) {
+                const double *ur = &Ur[wv][0][16 * jj + cl];
+                u0 = ur[0];
+                if (np > 1) u1 = fma(-lpv[0], u0, ur[TCW * 16]);
+                if (np > 2) u2 = fma(-lpv[2], u1, fma(-lpv[1], u0, ur[2 * TCW * 16]));
+                if (np > 3) u3 = fma(-lpv[5], u2, fma(-lpv[4], u1, fma(-lpv[3], u0, ur[3 * TCW * 16])));
+            }
+            const double bv = (g == 0) ? u0 : (g == 1) ? u1 : (g == 2) ? u2 : u3;
+#pragma unroll
+            for (int I = 0; I < TR; ++I)
+                T[I][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[I], bv, T[I][jj], 0, 0, 0);
+        };
+        const int J1 = cend >> 4;
+        const bool ahead = cend < ns && wv == J1 % NW;
+        if (ahead) {
+            static_for<TCW>([&](auto jjc) {
+                if (decltype(jjc)::value == J1 / NW) update(jjc);
+            });
+            factor(cend, buf ^ 1);
+            static_for<TCW>([&](auto jjc) {
+                if (decltype(jjc)::value != J1 / NW) update(jjc);
+            });
+        } else {
+            static_for<TCW>([&](auto jjc) { update(jjc); });
+        }
+        __syncthreads();
+    }
+
+    // unknown k = right-hand side of its pivot row over the pivot
+#pragma unroll
+    for (int jj = 0; jj < TCW; ++jj) {
+        const int r = 16 * (NW * jj + wv) + cl - ns;
+        if (r >= 0 && r < R)
+#pragma unroll
+            for (int I = 0; I < TR; ++I)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) S[(16 * I + 4 * v + g) * 4 + r] = T[I][jj][v];
+    }
+    __syncthreads();
+    const bool singular = sflag != 0;
+    for (int k = tid; k < q; k += NT) {
+        const int p = prow[k];
+        const double dg = singular ? 1.0 : pv[k];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double x = S[p * 4 + r] / dg;
+            const double sc = INTERP ? 1.0 : ((r < DIM) ? s : s * s);
+            w[(int64_t)r * n * q + i0 * q + k] = INTERP ? x : x / sc;
+        }
+    }
+    if (singular && tid == 0) atomicMin((unsigned long long *)bad, (unsigned long long)i0);
+}
+
+// The register Gauss-Jordan kernel for tiles (TR, TC) = (ceil(ns / 16),
+// ceil((ns + R) / 16)) when an instance exists; false otherwise. The
+// wavefront count keeps each wavefront's tiles and working set within 256
+// registers (two wavefronts per SIMD): two up to six tile columns, four for
+// seven (measured: 2D k = 6 at 84 unknowns 8.0 ms with two against 12.3 with
+// four; 3D k = 4 at 105 unknowns 20.8 ms with four against 24.3 with two).
+template <bool INTERP>
+bool launch_gjr(int dim, int ns, int nc, dim3 grid, hipStream_t s, const double *xyz, const double *ctr,
+                const int32_t *nbr, int64_t n, int q, int m, int phs, double *w, int64_t *bad)
+{
+    const int tr = (ns + 15) >> 4, tc = (nc + 15) >> 4;
+#define RB_GJR(TR_, TC_, NW_)                                                                              \
+    if (tr == TR_ && tc == TC_) {                                                                          \
+        if (dim == 2)                                                                                      \
+            hipLaunchKernelGGL((weights_kernel_gjr<2, INTERP, TR_, TC_, NW_>), grid, dim3(64 * NW_), 0, s, xyz, ctr, \
+                               nbr, n, q, m, phs, w, bad);                                                 \
+        else                                                                                               \
+            hipLaunchKernelGGL((weights_kernel_gjr<3, INTERP, TR_, TC_, NW_>), grid, dim3(64 * NW_), 0, s, xyz, ctr, \
+                               nbr, n, q, m, phs, w, bad);                                                 \
+        return true;                                                                                       \
+    }
+    RB_GJR(5, 5, 2)
+    RB_GJR(5, 6, 2)
+    RB_GJR(6, 6, 2)
+    RB_GJR(6, 7, 4)
+    RB_GJR(7, 7, 4)
+#undef RB_GJR
+    return false;
+}
+
 // out[f][j] = sum_a w[j][a] field_f[nbr[j][a]], in cloud order a = 0..q-1
 __global__ __launch_bounds__(kBlock) void interp_apply(int64_t nq, int q, const int32_t *__restrict__ nbr,
                                                        const double *__restrict__ w, int nfield, int64_t n,
@@ -951,6 +1222,10 @@ int launch_weights(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int q,
     RB_WEIGHTS(56)
     RB_WEIGHTS(64)
 #undef RB_WEIGHTS
+    if (launch_gjr<false>(dim, ns, ns + dim + 1, grid, s, xyz, xyz, nbr, n, q, m, phs, w, bad_dev)) {
+        RB_HIP(hipGetLastError());
+        return RBFFD_OK;
+    }
     if (ns <= 128) {
         // systems of 65-128 unknowns: the matrix lives in LDS
         const int R = dim + 1;
@@ -1071,6 +1346,8 @@ int launch_interp(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, int64_t
     int dev = 0, lim = 0;
     RB_HIP(hipGetDevice(&dev));
     RB_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    if (!launched)
+        launched = launch_gjr<true>(dim, ns, ns + 1, dim3((unsigned)nq), s, xyz, qxyz, nbr, nq, q, m, phs, w, bad_dev);
     if (!launched) {
         // 65-128 unknowns: one workgroup per query point, the matrix in LDS
         const size_t gjl = gj_lds_bytes(q, ns, ns + 1, dim);

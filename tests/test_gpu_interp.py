@@ -132,6 +132,28 @@ def test_interpolation_edge_cases(ctx):
                                None, C.byref(bad), R.binding._stream()) == -1      # degree 7
 
 
+@pytest.mark.parametrize("dim,k,q", [(2, 5, 59), (2, 6, 68), (3, 4, 61), (3, 4, 90)])
+def test_interpolation_system_sizes(ctx, orc, dim, k, q):
+    """Interpolation weights (one right-hand side) through the register
+    Gauss-Jordan kernel's tile shapes 5 x 6 (80 + 1 unknowns), 6 x 7 (96 + 1,
+    2D and 3D) and the LDS kernel (125 + 1): clouds bit-exact with the oracle,
+    weights within 1e-10 row-relative, values within 1e-12."""
+    c = W.kovasznay_square(nx=14) if dim == 2 else W.scattered_cube(8, seed=5)
+    rng = np.random.default_rng(31)
+    lo, hi = c.xyz.min(0), c.xyz.max(0)
+    pts = lo + (hi - lo) * rng.uniform(0.05, 0.95, size=(40, dim))
+    f = np.stack([np.sin(c.xyz[:, 0]) + c.xyz[:, 1] ** 2])
+    vo, nbr_o, w_o = orc.interpolate(c.xyz, k, pts, f, q=q)
+    out, nbr, w = R.rbffd_interpolate(ctx, R.DeviceCloud.from_numpy(c), k, torch.tensor(pts, device="cuda"),
+                                      torch.tensor(f, device="cuda"), q=q, return_stencils=True)
+    nbr, w, out = nbr.cpu().numpy(), w.cpu().numpy(), out.cpu().numpy()
+    ew = float((np.abs(w - w_o).max(1) / np.abs(w_o).max(1)).max())
+    ev = float(np.abs(out - vo).max())
+    print(f"[interp] dim {dim} k {k} q {q}: weights {ew:.1e}, values {ev:.1e}", flush=True)
+    np.testing.assert_array_equal(nbr, nbr_o)
+    assert ew <= 1e-10 and ev <= 1e-12
+
+
 @pytest.mark.parametrize("k", [4, 6])
 def test_periodic_interpolation_matches_oracle(ctx, orc, k):
     """Interpolation on the periodic Taylor-Green square at points next to the
