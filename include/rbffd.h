@@ -183,8 +183,9 @@ int rbffd_build_stencils(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_s
  * computes them (bitwise the same). The neighbour search runs cloud by cloud;
  * the weights of all clouds with at most 64 unknowns (q + m) are built in one
  * launch per (dimension, register width) present, each 64-lane block taking
- * one point of one cloud; clouds of 65-128 unknowns take the LDS kernel one
- * by one. Clouds may differ in size, degree, cloud size and PHS power.
+ * one point of one cloud; clouds of 65-128 unknowns take the Gauss-Jordan
+ * kernels one by one. Clouds may differ in size, degree, cloud size and PHS
+ * power.
  *   clouds, opts: HOST arrays of `count` descriptions and options
  *   nbr, w:       HOST arrays of `count` device pointers: nbr[j] [n_j][q_j]
  *                 int32, w[j] [R_j][n_j][q_j] double (outputs)

@@ -455,7 +455,7 @@ int rbffd_build_stencils_batched(rbffd_ctx *ctx, int count, const rbffd_cloud *c
         if (!nbr[j] || !w[j]) return fail(RBFFD_E_ARG, "nbr or w is NULL" + at);
         if (qs[j] + ms[j] > 128) return fail(RBFFD_E_ARG, "collocation systems larger than 128 are not supported" + at);
         if (is_periodic(c)) return fail(RBFFD_E_ARG, "periodic clouds are built one at a time (rbffd_build_stencils)" + at);
-        width[j] = weight_width(qs[j] + ms[j]);   // 0: 65-128 unknowns, the LDS kernel
+        width[j] = weight_width(qs[j] + ms[j]);   // 0: 65-128 unknowns, the Gauss-Jordan kernels
     }
     RB_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)hip_stream;
@@ -514,7 +514,7 @@ int rbffd_build_stencils_batched(rbffd_ctx *ctx, int count, const rbffd_cloud *c
         if (wd > 0) {
             RB_CHECK(launch_weights_batched(dim, wd, (int)nt, dsys + t0, blocks[g], dbad + t0, s));
         } else {
-            // systems of 65-128 unknowns: the two-wavefront LDS kernel, cloud by cloud
+            // systems of 65-128 unknowns: the Gauss-Jordan kernels, cloud by cloud
             for (size_t t = t0; t < t0 + nt; ++t) {
                 const int j = order[t];
                 RB_CHECK(launch_weights(ctx, dim, clouds[j].n, clouds[j].xyz, qs[j], nbr[j], opts[j].poly_degree,
