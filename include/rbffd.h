@@ -52,12 +52,14 @@ extern "C" {
 /* ---- precision of the Krylov sweeps ------------------------------------ */
 #define RBFFD_FP64 0            /* everything in FP64                                  */
 #define RBFFD_FP32_IR 1         /* FP32 matrix values and Krylov vectors, FP64 row and dot
-                                   accumulation; the FP64 residual b - A x replaces the
-                                   recursive one whenever it has fallen 10x (reliable
-                                   updates), until the FP64 residual meets the tolerance;
-                                   FP64 sweeps finish a solve that stalls in FP32         */
+                                   accumulation, inside FP64 iterative refinement: each
+                                   time the recursive residual has fallen 10x, the FP64
+                                   residual b - A x replaces it and BiCGSTAB restarts from
+                                   it, until the FP64 residual meets the tolerance; FP64
+                                   sweeps finish a solve that stalls in FP32             */
 #define RBFFD_FP32_MATRIX 2     /* as RBFFD_FP32_IR with FP32 matrix values but FP64 Krylov
-                                   vectors: 1/3 fewer matrix bytes at q >= 20 with
+                                   vectors, refined each time the recursive residual has
+                                   fallen 100x: 1/3 fewer matrix bytes at q >= 20 with
                                    nearly the FP64 iteration count                      */
 
 /* ---- preconditioner of the pressure-correction solve ------------------- */
