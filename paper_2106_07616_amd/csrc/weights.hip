@@ -76,6 +76,34 @@ __device__ inline double wave_max_dpp(double v)
     return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
 }
 
+// The same maximum with the cross-row steps as DPP row broadcasts (rows 1
+// and 3 take lane 15 of the row before, then rows 2 and 3 take lane 31), so
+// that lane 63 holds it: one readlane instead of four.
+__device__ inline double dpp_bcast_max(double v, int sel)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    int lo2, hi2;
+    if (sel == 0) {   // row_bcast:15 into rows 1 and 3
+        lo2 = __builtin_amdgcn_update_dpp(lo, lo, 0x142, 0xA, 0xF, false);
+        hi2 = __builtin_amdgcn_update_dpp(hi, hi, 0x142, 0xA, 0xF, false);
+    } else {          // row_bcast:31 into rows 2 and 3
+        lo2 = __builtin_amdgcn_update_dpp(lo, lo, 0x143, 0xC, 0xF, false);
+        hi2 = __builtin_amdgcn_update_dpp(hi, hi, 0x143, 0xC, 0xF, false);
+    }
+    return fmax(v, __hiloint2double(hi2, lo2));
+}
+
+__device__ inline double wave_max_bcast(double v)
+{
+    v = dpp_max_step(v, 0);
+    v = dpp_max_step(v, 1);
+    v = dpp_max_step(v, 2);
+    v = dpp_max_step(v, 3);
+    v = dpp_bcast_max(v, 0);
+    v = dpp_bcast_max(v, 1);
+    return readlane_d(v, 63);
+}
+
 template <int DIM>
 __device__ inline double sqdist_exact(const double *a, const double *b)
 {
@@ -282,7 +310,7 @@ __device__ __forceinline__ void weights_point(const double *__restrict__ xyz, co
             for (int t = 1; t < SEG; ++t)
                 if (k0 + t < NSP && k == k0 + t) ak = a_[k0 + t];
             const double v = active ? fabs(ak) : -1.0;
-            const double mx = wave_max_dpp(v);
+            const double mx = wave_max_bcast(v);
             const uint64_t msk = __ballot(active && v == mx);
             const int p = msk ? (__ffsll((unsigned long long)msk) - 1) : 0;
             if (!(mx > 1e-13 * amax)) singular = true;
@@ -602,34 +630,6 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 __device__ inline int gj_slot(int i, int j, int tc)
 {
     return ((((i >> 4) * tc + (j >> 4)) * 64 + 16 * (i & 3) + (j & 15)) << 2) + ((i & 15) >> 2);
-}
-
-// The same maximum with the cross-row steps as DPP row broadcasts (rows 1
-// and 3 take lane 15 of the row before, then rows 2 and 3 take lane 31), so
-// that lane 63 holds it: one readlane instead of four.
-__device__ inline double dpp_bcast_max(double v, int sel)
-{
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    int lo2, hi2;
-    if (sel == 0) {   // row_bcast:15 into rows 1 and 3
-        lo2 = __builtin_amdgcn_update_dpp(lo, lo, 0x142, 0xA, 0xF, false);
-        hi2 = __builtin_amdgcn_update_dpp(hi, hi, 0x142, 0xA, 0xF, false);
-    } else {          // row_bcast:31 into rows 2 and 3
-        lo2 = __builtin_amdgcn_update_dpp(lo, lo, 0x143, 0xC, 0xF, false);
-        hi2 = __builtin_amdgcn_update_dpp(hi, hi, 0x143, 0xC, 0xF, false);
-    }
-    return fmax(v, __hiloint2double(hi2, lo2));
-}
-
-__device__ inline double wave_max_bcast(double v)
-{
-    v = dpp_max_step(v, 0);
-    v = dpp_max_step(v, 1);
-    v = dpp_max_step(v, 2);
-    v = dpp_max_step(v, 3);
-    v = dpp_bcast_max(v, 0);
-    v = dpp_bcast_max(v, 1);
-    return readlane_d(v, 63);
 }
 
 // Entry (i, j) of the augmented system [A | B] of a point: rows and columns
