@@ -937,8 +937,8 @@ __device__ __forceinline__ void static_for(F &&f)
 // its B operands (forward substitution over the pivot rows), and every tile
 // takes its rank-4 update in one MFMA. With no matrix in LDS, two systems
 // share a CU and one's serial panel chain overlaps the other's updates.
-template <int DIM, bool INTERP, int TR, int TC, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void weights_kernel_gjr(const double *__restrict__ xyz,
+template <int DIM, bool INTERP, int TR, int TC, int NW, int WPE>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE))) void weights_kernel_gjr(const double *__restrict__ xyz,
                                                               const double *__restrict__ ctr,
                                                               const int32_t *__restrict__ nbr, int64_t n, int q,
                                                               int m, int phs, double *__restrict__ w,
@@ -1142,11 +1142,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 }
 
 // The register Gauss-Jordan kernel for tiles (TR, TC) = (ceil(ns / 16),
-// ceil((ns + R) / 16)) when an instance exists; false otherwise. The
-// wavefront count keeps each wavefront's tiles and working set within 256
-// registers (two wavefronts per SIMD): two up to six tile columns, four for
-// seven (measured: 2D k = 6 at 84 unknowns 8.0 ms with two against 12.3 with
-// four; 3D k = 4 at 105 unknowns 20.8 ms with four against 24.3 with two).
+// ceil((ns + R) / 16)) when an instance exists; false otherwise. NW, the
+// wavefronts per system, and WPE, the wavefronts the compiler budgets per
+// SIMD, set how many systems share a CU: two wavefronts at two per SIMD (256
+// VGPRs each) up to six tile columns; four wavefronts at three per SIMD (168
+// VGPRs, a few spilled at seven columns) for seven. Measured on MI355X: 2D
+// k = 6 (84 unknowns) 8.0 ms with two wavefronts against 12.3 with four;
+// 3D k = 4 (105 unknowns) 17.8 ms with four at three per SIMD, 20.8 at two
+// per SIMD, 24.3 with two wavefronts.
 template <bool INTERP>
 bool launch_gjr(int dim, int ns, int nc, dim3 grid, hipStream_t s, const double *xyz, const double *ctr,
                 const int32_t *nbr, int64_t n, int q, int m, int phs, double *w, int64_t *bad)
@@ -1154,12 +1157,13 @@ bool launch_gjr(int dim, int ns, int nc, dim3 grid, hipStream_t s, const double 
     const int tr = (ns + 15) >> 4, tc = (nc + 15) >> 4;
 #define RB_GJR(TR_, TC_, NW_)                                                                              \
     if (tr == TR_ && tc == TC_) {                                                                          \
+        constexpr int wpe = (NW_ == 4) ? 3 : 2;                                                            \
         if (dim == 2)                                                                                      \
-            hipLaunchKernelGGL((weights_kernel_gjr<2, INTERP, TR_, TC_, NW_>), grid, dim3(64 * NW_), 0, s, xyz, ctr, \
-                               nbr, n, q, m, phs, w, bad);                                                 \
+            hipLaunchKernelGGL((weights_kernel_gjr<2, INTERP, TR_, TC_, NW_, wpe>), grid, dim3(64 * NW_), 0, s,   \
+                               xyz, ctr, nbr, n, q, m, phs, w, bad);                                       \
         else                                                                                               \
-            hipLaunchKernelGGL((weights_kernel_gjr<3, INTERP, TR_, TC_, NW_>), grid, dim3(64 * NW_), 0, s, xyz, ctr, \
-                               nbr, n, q, m, phs, w, bad);                                                 \
+            hipLaunchKernelGGL((weights_kernel_gjr<3, INTERP, TR_, TC_, NW_, wpe>), grid, dim3(64 * NW_), 0, s,   \
+                               xyz, ctr, nbr, n, q, m, phs, w, bad);                                       \
         return true;                                                                                       \
     }
     RB_GJR(5, 5, 2)
