@@ -1144,12 +1144,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE))) 
 // The register Gauss-Jordan kernel for tiles (TR, TC) = (ceil(ns / 16),
 // ceil((ns + R) / 16)) when an instance exists; false otherwise. NW, the
 // wavefronts per system, and WPE, the wavefronts the compiler budgets per
-// SIMD, set how many systems share a CU: two wavefronts at two per SIMD (256
-// VGPRs each) up to six tile columns; four wavefronts at three per SIMD (168
-// VGPRs, a few spilled at seven columns) for seven. Measured on MI355X: 2D
-// k = 6 (84 unknowns) 8.0 ms with two wavefronts against 12.3 with four;
-// 3D k = 4 (105 unknowns) 17.8 ms with four at three per SIMD, 20.8 at two
-// per SIMD, 24.3 with two wavefronts.
+// SIMD (three: 168 VGPRs), set how many systems share a CU: three wavefronts
+// up to six tile columns (four systems per CU), four at seven (three per CU;
+// the 7 x 7 shape spills a few dwords). Measured on MI355X: 2D k = 6 (84
+// unknowns) 7.7 ms, against 8.0 with two wavefronts at two per SIMD and 12.3
+// with four; 3D k = 4 (105 unknowns) 17.8 ms, against 20.8 at two per SIMD
+// and 24.3 with two wavefronts.
 template <bool INTERP>
 bool launch_gjr(int dim, int ns, int nc, dim3 grid, hipStream_t s, const double *xyz, const double *ctr,
                 const int32_t *nbr, int64_t n, int q, int m, int phs, double *w, int64_t *bad)
@@ -1157,7 +1157,7 @@ bool launch_gjr(int dim, int ns, int nc, dim3 grid, hipStream_t s, const double 
     const int tr = (ns + 15) >> 4, tc = (nc + 15) >> 4;
 #define RB_GJR(TR_, TC_, NW_)                                                                              \
     if (tr == TR_ && tc == TC_) {                                                                          \
-        constexpr int wpe = (NW_ == 4) ? 3 : 2;                                                            \
+        constexpr int wpe = 3;                                                                             \
         if (dim == 2)                                                                                      \
             hipLaunchKernelGGL((weights_kernel_gjr<2, INTERP, TR_, TC_, NW_, wpe>), grid, dim3(64 * NW_), 0, s,   \
                                xyz, ctr, nbr, n, q, m, phs, w, bad);                                       \
@@ -1166,9 +1166,9 @@ bool launch_gjr(int dim, int ns, int nc, dim3 grid, hipStream_t s, const double 
                                xyz, ctr, nbr, n, q, m, phs, w, bad);                                       \
         return true;                                                                                       \
     }
-    RB_GJR(5, 5, 2)
-    RB_GJR(5, 6, 2)
-    RB_GJR(6, 6, 2)
+    RB_GJR(5, 5, 3)
+    RB_GJR(5, 6, 3)
+    RB_GJR(6, 6, 3)
     RB_GJR(6, 7, 4)
     RB_GJR(7, 7, 4)
 #undef RB_GJR
