@@ -17,7 +17,7 @@
 //  - 65-112 unknowns with their right-hand sides (2D degree 6, 3D degree 4):
 //    blocked Gauss-Jordan in panels of four columns whose rank-4 updates run
 //    on v_mfma_f64_16x16x4, the matrix in registers as MFMA tiles spread over
-//    two or four wavefronts (below);
+//    three or four wavefronts (below);
 //  - up to 128: the same elimination with the tiles in LDS, and where that
 //    layout does not fit the workgroup's LDS (128 unknowns with four
 //    right-hand sides), an unblocked LDS kernel.
@@ -935,14 +935,13 @@ __device__ __forceinline__ void static_for(F &&f)
 // LDS to the register factorisation (pivot rule, multipliers, -L in the A
 // layout); every wavefront passes its part of the raw pivot rows through LDS to
 // its B operands (forward substitution over the pivot rows), and every tile
-// takes its rank-4 update in one MFMA. With no matrix in LDS, two systems
-// share a CU and one's serial panel chain overlaps the other's updates.
+// takes its rank-4 update in one MFMA. With no matrix in LDS, three or four
+// systems share a CU and one's serial panel chain overlaps the others'
+// updates. WPE is the wavefronts per SIMD that the register budget allows.
 template <int DIM, bool INTERP, int TR, int TC, int NW, int WPE>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE))) void weights_kernel_gjr(const double *__restrict__ xyz,
-                                                              const double *__restrict__ ctr,
-                                                              const int32_t *__restrict__ nbr, int64_t n, int q,
-                                                              int m, int phs, double *__restrict__ w,
-                                                              int64_t *__restrict__ bad)
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE))) void weights_kernel_gjr(
+    const double *__restrict__ xyz, const double *__restrict__ ctr, const int32_t *__restrict__ nbr, int64_t n, int q,
+    int m, int phs, double *__restrict__ w, int64_t *__restrict__ bad)
 {
     constexpr int R = INTERP ? 1 : DIM + 1;
     constexpr int RPL = (TR * 16 + 63) / 64;
