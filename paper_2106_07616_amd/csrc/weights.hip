@@ -713,6 +713,13 @@ __device__ inline void gj_factor_panel_with(Load ld, int rows, int c0, int np, b
 #pragma unroll
             for (int h = 0; h < RPL; ++h) best = fmax(best, act[h] ? fabs(a[h][cc]) : -1.0);
             const double mx = wave_max_bcast(best);
+            // 1 / |pivot| = 1 / mx (hardware reciprocal, two Newton steps),
+            // started while the pivot row is still being found; every step is
+            // odd in its argument, so the signed reciprocal is its negation
+            // for a negative pivot, bit for bit
+            double rm = __builtin_amdgcn_rcp(mx);
+            rm = fma(rm, fma(-mx, rm, 1.0), rm);
+            rm = fma(rm, fma(-mx, rm, 1.0), rm);
             int p = 0;
 #pragma unroll
             for (int h = RPL - 1; h >= 0; --h) {
@@ -731,10 +738,7 @@ __device__ inline void gj_factor_panel_with(Load ld, int rows, int c0, int np, b
                 prw[c2] = readlane_d(src, pl);
             }
             const double piv = singular ? 1.0 : prw[cc];
-            // 1 / piv: hardware reciprocal and two Newton steps
-            double rp = __builtin_amdgcn_rcp(piv);
-            rp = fma(rp, fma(-piv, rp, 1.0), rp);
-            rp = fma(rp, fma(-piv, rp, 1.0), rp);
+            const double rp = singular ? 1.0 : (prw[cc] < 0.0 ? -rm : rm);
 #pragma unroll
             for (int h = 0; h < RPL; ++h) {
                 const bool me = (lane + 64 * h) == p;
