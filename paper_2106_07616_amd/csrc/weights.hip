@@ -14,13 +14,13 @@
 //    in registers; the pivot search is a DPP wave max-reduction, the pivot row
 //    is broadcast lane-to-scalar with readlane, and the rank-1 update is one
 //    FP64 FMA per entry (LU, then back substitution);
-//  - 65-112 unknowns with their right-hand sides (2D degree 6, 3D degree 4):
-//    blocked Gauss-Jordan in panels of four columns whose rank-4 updates run
-//    on v_mfma_f64_16x16x4, the matrix in registers as MFMA tiles spread over
-//    three or four wavefronts (below);
-//  - up to 128: the same elimination with the tiles in LDS, and where that
-//    layout does not fit the workgroup's LDS (128 unknowns with four
-//    right-hand sides), an unblocked LDS kernel.
+//  - 65 unknowns and up, at most 128 columns with the right-hand sides (2D
+//    degree 6, 3D degree 4): blocked Gauss-Jordan in panels of four columns
+//    whose rank-4 updates run on v_mfma_f64_16x16x4, the matrix in registers
+//    as MFMA tiles spread over three or four wavefronts (below);
+//  - up to 128 unknowns with more columns: the same elimination with the
+//    tiles in LDS (up to 159 KB), and an unblocked LDS kernel on devices whose
+//    workgroups cannot hold those tiles.
 // On gfx950 the FP64 matrix-core rate equals the FP64 vector rate: the MFMA
 // path pays by replacing per-entry LDS traffic and broadcasts with one
 // instruction per 16 x 16 tile, not by a higher ceiling.
@@ -931,10 +931,11 @@ __device__ __forceinline__ void static_for(F &&f)
     }
 }
 
-// Systems of 65-112 unknowns (right-hand sides included) with the matrix in
-// registers: TR x TC tiles of 16 x 16 in the MFMA accumulator layout (lane l:
-// column l % 16, rows 4 v + l / 16 in register v), tile column J held by
-// wavefront J % NW, and the same Gauss-Jordan in panels of four columns as
+// Systems of 65 unknowns and up, at most 128 columns with the right-hand
+// sides, with the matrix in registers: TR x TC tiles of 16 x 16 in the MFMA
+// accumulator layout (lane l: column l % 16, rows 4 v + l / 16 in register
+// v), tile column J held by wavefront J % NW, and the same Gauss-Jordan in
+// panels of four columns as
 // the kernel above. Per panel, the panel's owner passes its columns through
 // LDS to the register factorisation (pivot rule, multipliers, -L in the A
 // layout); every wavefront passes its part of the raw pivot rows through LDS to
@@ -1148,11 +1149,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE))) 
 // ceil((ns + R) / 16)) when an instance exists; false otherwise. NW, the
 // wavefronts per system, and WPE, the wavefronts the compiler budgets per
 // SIMD (three: 168 VGPRs), set how many systems share a CU: three wavefronts
-// up to six tile columns (four systems per CU), four at seven (three per CU;
-// the 7 x 7 shape spills a few dwords). Measured on MI355X: 2D k = 6 (84
-// unknowns) 7.7 ms, against 8.0 with two wavefronts at two per SIMD and 12.3
-// with four; 3D k = 4 (105 unknowns) 17.8 ms, against 20.8 at two per SIMD
-// and 24.3 with two wavefronts.
+// up to six tile columns (four systems per CU), four at seven and eight
+// (three per CU; the widest shapes spill up to 40 dwords). Measured on
+// MI355X: 2D k = 6 (84 unknowns) 7.7 ms, against 8.0 with two wavefronts at
+// two per SIMD and 12.3 with four; 3D k = 4 (105 unknowns) 17.8 ms, against
+// 20.8 at two per SIMD and 24.3 with two wavefronts; 8 x 8 tiles (121
+// unknowns) 17.5 ms at three per SIMD, 20.2 at two.
 template <bool INTERP>
 bool launch_gjr(int dim, int ns, int nc, dim3 grid, hipStream_t s, const double *xyz, const double *ctr,
                 const int32_t *nbr, int64_t n, int q, int m, int phs, double *w, int64_t *bad)
@@ -1174,6 +1176,8 @@ bool launch_gjr(int dim, int ns, int nc, dim3 grid, hipStream_t s, const double 
     RB_GJR(6, 6, 3)
     RB_GJR(6, 7, 4)
     RB_GJR(7, 7, 4)
+    RB_GJR(7, 8, 4)
+    RB_GJR(8, 8, 4)
 #undef RB_GJR
     return false;
 }

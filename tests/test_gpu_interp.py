@@ -136,8 +136,8 @@ def test_interpolation_edge_cases(ctx):
 def test_interpolation_system_sizes(ctx, orc, dim, k, q):
     """Interpolation weights (one right-hand side) through the register
     Gauss-Jordan kernel's tile shapes 5 x 6 (80 + 1 unknowns), 6 x 7 (96 + 1,
-    2D and 3D) and the LDS kernel (125 + 1): clouds bit-exact with the oracle,
-    weights within 1e-10 row-relative, values within 1e-12."""
+    2D and 3D) and 8 x 8 (125 + 1): clouds bit-exact with the oracle, weights
+    within 1e-10 row-relative, values within 1e-12."""
     c = W.kovasznay_square(nx=14) if dim == 2 else W.scattered_cube(8, seed=5)
     rng = np.random.default_rng(31)
     lo, hi = c.xyz.min(0), c.xyz.max(0)

@@ -366,14 +366,16 @@ def test_polynomial_flow_step(case, ctx, orc, which):
 @pytest.mark.parametrize("dim,k,q,phs", [(2, 1, 6, 3), (2, 3, 28, 3), (2, 4, 40, 3), (2, 2, 20, 5), (3, 2, 26, 3),
                                           (3, 3, 44, 5), (2, 6, 56, 3), (3, 4, 70, 3), (2, 5, 100, 5),
                                           (3, 3, 65, 3), (2, 5, 50, 3), (2, 5, 57, 5), (3, 3, 58, 3),
-                                          (2, 6, 67, 5), (3, 4, 60, 3), (3, 4, 76, 3)])
+                                          (2, 6, 67, 5), (3, 4, 60, 3), (3, 4, 76, 3), (3, 4, 90, 3),
+                                          (3, 4, 93, 3)])
 def test_weights_all_system_sizes(ctx, orc, dim, k, q, phs):
     """Every kernel shape of the weights against the oracle (r^3 and r^5):
     register rows of 9 to 64 unknowns on one wavefront; the register
     Gauss-Jordan kernel's tile shapes (rows x columns of 16) 5 x 5 (71
-    unknowns), 5 x 6 (78, 2D and 3D), 6 x 6 (84, 85), 6 x 7 (95, 2D and 3D)
-    and 7 x 7 (105); the LDS Gauss-Jordan kernel beyond (111 + 4 right-hand
-    sides, 121). Clouds bit-exact, weights within 1e-10 row-relative."""
+    unknowns), 5 x 6 (78, 2D and 3D), 6 x 6 (84, 85), 6 x 7 (95, 2D and 3D),
+    7 x 7 (105), 7 x 8 (111 + 4 right-hand sides) and 8 x 8 (121); beyond
+    128 columns the LDS Gauss-Jordan kernel (125 + 4 and 128 + 4, 159 KB of
+    LDS). Clouds bit-exact, weights within 1e-10 row-relative."""
     c = W.kovasznay_square(nx=14) if dim == 2 else W.scattered_cube(8, seed=5)
     nbr, w, _ = R.rbffd_build_stencils(ctx, R.DeviceCloud.from_numpy(c), k, q, phs)
     nbr_o = orc.knn(c.xyz, q)
