@@ -9,6 +9,7 @@
 
 #include "forces.h"
 #include "internal.h"
+#include "periodic.h"
 
 namespace rbffd {
 
@@ -106,59 +107,28 @@ static bool is_periodic(const rbffd_cloud *c)
     return false;
 }
 
-// Stencils of a cloud that wraps along its periodic axes (Sec. 3.1): ghost
-// images x_j +- period e_d of the points within a band of each periodic face
-// are appended, the neighbour search and the weights run on the augmented
-// points (the images' own coordinates: clouds near one face take points from
-// the other), and neighbour indices are mapped back to the points they are
-// images of. The band starts at twice the radius that holds q points at the
-// mean density and doubles until every point's q-th neighbour lies within it,
-// which makes the search exact.
-// The periodic box of a cloud: its coordinates on the host, their bounds, a
-// first band width (twice the radius holding q points at the mean density)
-// and the shift vectors m in {-1, 0, 1}^dim, nonzero only along periodic axes.
-struct PeriodicBox {
-    int dim = 2;
-    int64_t n = 0;
-    const double *L = nullptr;
-    std::vector<double> x;
-    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-    double band = 0.0;
-    std::vector<std::array<int, 3>> shifts;
-};
-
-static int periodic_box(const rbffd_cloud *cloud, int q, hipStream_t s, PeriodicBox *b)
+// The periodic box of a cloud (Sec. 3.1) for images: its bounds (from the
+// device), a first band width (twice the radius holding q points at the mean
+// density) and the shift vectors m in {-1, 0, 1}^3, nonzero only along
+// periodic axes, in lexicographic order.
+static int periodic_setup(rbffd_ctx *ctx, const rbffd_cloud *cloud, int q, hipStream_t s, PeriodicShifts *P,
+                          double *band)
 {
     const int dim = cloud->dim;
     const int64_t n = cloud->n;
-    b->dim = dim;
-    b->n = n;
-    b->L = cloud->period;
-    b->x.resize((size_t)n * dim);
-    RB_HIP(hipMemcpyAsync(b->x.data(), cloud->xyz, sizeof(double) * n * dim, hipMemcpyDeviceToHost, s));
-    RB_HIP(hipStreamSynchronize(s));
-    for (int d = 0; d < dim; ++d) {
-        b->lo[d] = INFINITY;
-        b->hi[d] = -INFINITY;
-    }
-    for (int64_t i = 0; i < n; ++i)
-        for (int d = 0; d < dim; ++d) {
-            const double v = b->x[i * dim + d];
-            if (!std::isfinite(v)) return fail(RBFFD_E_ARG, "non-finite coordinates");
-            b->lo[d] = std::min(b->lo[d], v);
-            b->hi[d] = std::max(b->hi[d], v);
-        }
-    const double *L = b->L;
+    const double *L = cloud->period;
+    RB_CHECK(device_bbox(ctx, dim, n, cloud->xyz, P->lo, P->hi, s));
     double vol = 1.0;
     for (int d = 0; d < dim; ++d) {
-        if (L[d] > 0.0 && !(b->hi[d] - b->lo[d] < L[d]))
+        P->L[d] = L[d];
+        if (L[d] > 0.0 && !(P->hi[d] - P->lo[d] < L[d]))
             return fail(RBFFD_E_ARG, "the cloud's extent along a periodic axis is not below its period");
-        vol *= (L[d] > 0.0) ? L[d] : std::max(b->hi[d] - b->lo[d], 1e-300);
+        vol *= (L[d] > 0.0) ? L[d] : std::max(P->hi[d] - P->lo[d], 1e-300);
     }
     const double pi = 3.14159265358979323846;
-    b->band = 2.0 * ((dim == 2) ? std::sqrt(q * vol / (pi * (double)n))
-                                : std::cbrt(3.0 * q * vol / (4.0 * pi * (double)n)));
-    b->shifts.clear();
+    *band = 2.0 * ((dim == 2) ? std::sqrt(q * vol / (pi * (double)n))
+                              : std::cbrt(3.0 * q * vol / (4.0 * pi * (double)n)));
+    P->count = 0;
     for (int a = -1; a <= 1; ++a)
         for (int bb = -1; bb <= 1; ++bb)
             for (int c = -1; c <= 1; ++c) {
@@ -166,107 +136,71 @@ static int periodic_box(const rbffd_cloud *cloud, int q, hipStream_t s, Periodic
                 bool ok = !(a == 0 && bb == 0 && c == 0);
                 for (int d = 0; d < 3; ++d)
                     if (m[d] != 0 && (d >= dim || !(L[d] > 0.0))) ok = false;
-                if (ok) b->shifts.push_back({a, bb, c});
+                if (!ok) continue;
+                for (int d = 0; d < 3; ++d) P->m[P->count][d] = m[d];
+                ++P->count;
             }
     return RBFFD_OK;
 }
 
-// The points followed by their images x_j + m L (coordinates formed as x + L
-// or x - L) that lie within `band` of the box along every periodic axis;
-// owner[r] is the point row r stands for.
-static void periodic_images(const PeriodicBox &b, double band, std::vector<double> &aug, std::vector<int32_t> &owner)
-{
-    const int dim = b.dim;
-    const double *L = b.L;
-    aug = b.x;
-    owner.resize((size_t)b.n);
-    for (int64_t i = 0; i < b.n; ++i) owner[i] = (int32_t)i;
-    for (const auto &m : b.shifts)
-        for (int64_t j = 0; j < b.n; ++j) {
-            double y[3];
-            bool keep = true;
-            for (int d = 0; d < dim; ++d) {
-                const double v = b.x[j * dim + d];
-                y[d] = (m[d] > 0) ? v + L[d] : ((m[d] < 0) ? v - L[d] : v);
-                if (L[d] > 0.0 && (y[d] < b.lo[d] - band || y[d] > b.hi[d] + band)) keep = false;
-            }
-            if (!keep) continue;
-            for (int d = 0; d < dim; ++d) aug.push_back(y[d]);
-            owner.push_back((int32_t)j);
-        }
-}
-
+// Stencils of a cloud that wraps along its periodic axes (Sec. 3.1): ghost
+// images x_j +- period e_d of the points within a band of each periodic face
+// are appended, the neighbour search and the weights run on the augmented
+// points (the images' own coordinates: clouds near one face take points from
+// the other), and neighbour indices are mapped back to the points they are
+// images of. The band starts at twice the radius that holds q points at the
+// mean density and doubles until every point's q-th neighbour lies within it,
+// which makes the search exact. Every step over the points runs on the
+// device; the host sees the bounding box, the image count and two flags.
 static int stencils_periodic(rbffd_ctx *ctx, const rbffd_cloud *cloud, const rbffd_stencil_opts *opts, int q,
                              int32_t *nbr, double *w, int64_t *bad_point, hipStream_t s)
 {
     const int dim = cloud->dim;
     const int64_t n = cloud->n;
-    PeriodicBox box;
-    RB_CHECK(periodic_box(cloud, q, s, &box));
-    const std::vector<double> &x = box.x;
-    double band = box.band;
-    int64_t *bad_dev = nullptr;
-    RB_CHECK(workspace(ctx, WS_MISC, sizeof(int64_t), (void **)&bad_dev));
-    int64_t *hb = nullptr;
-    RB_CHECK(host_scratch(ctx, kHostMisc, sizeof(int64_t), (void **)&hb));
-    std::vector<int32_t> hn((size_t)n * q);
+    PeriodicShifts P;
+    double band = 0.0;
+    RB_CHECK(periodic_setup(ctx, cloud, q, s, &P, &band));
+    int64_t *flags = nullptr;   // [0]: singular point, [1]: cloud with a repeated point, [2]: q-th beyond the band
+    RB_CHECK(workspace(ctx, WS_MISC, 3 * sizeof(int64_t), (void **)&flags));
+    int64_t *hf = nullptr;
+    RB_CHECK(host_scratch(ctx, kHostMisc, 3 * sizeof(int64_t), (void **)&hf));
     for (int attempt = 0; attempt < 12; ++attempt, band *= 2.0) {
-        std::vector<double> aug;
-        std::vector<int32_t> owner;
-        periodic_images(box, band, aug, owner);
-        const int64_t naug = (int64_t)owner.size();
-        if (naug >= (int64_t(1) << 31)) return fail(RBFFD_E_ARG, "too many periodic images");
-        double *aug_dev = nullptr;
-        const size_t abytes = sizeof(double) * naug * dim;
-        RB_CHECK(dev_alloc(ctx, (void **)&aug_dev, abytes));
-        int st = RBFFD_OK;
-        hipError_t e = hipMemcpyAsync(aug_dev, aug.data(), abytes, hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) st = hip_fail(e, "periodic images");
-        if (st == RBFFD_OK) st = launch_knn_points(ctx, dim, naug, aug_dev, n, aug_dev, q, nbr, s);
+        P.band = band;
+        double *aug = nullptr;
+        int32_t *owner = nullptr;
+        int64_t naug = 0;
+        size_t abytes = 0, obytes = 0;
+        RB_CHECK(launch_periodic_images(ctx, dim, n, cloud->xyz, P, &aug, &owner, &naug, &abytes, &obytes, s));
+        int st = launch_knn_points(ctx, dim, naug, aug, n, aug, q, nbr, s);
+        if (st == RBFFD_OK) st = launch_periodic_inside(dim, n, aug, aug, q, nbr, band, nullptr, (int *)(flags + 2), s);
         if (st == RBFFD_OK) {
-            e = hipMemcpyAsync(hn.data(), nbr, sizeof(int32_t) * n * q, hipMemcpyDeviceToHost, s);
+            hipError_t e = hipMemcpyAsync(hf + 2, flags + 2, sizeof(int64_t), hipMemcpyDeviceToHost, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
             if (e != hipSuccess) st = hip_fail(e, "periodic neighbours");
         }
-        bool inside = true;
-        for (int64_t i = 0; st == RBFFD_OK && i < n && inside; ++i) {
-            const int64_t j = hn[i * q + q - 1];
-            double d2 = 0.0;
-            for (int d = 0; d < dim; ++d) {
-                const double dd = aug[j * dim + d] - x[i * dim + d];
-                d2 += dd * dd;
-            }
-            inside = std::sqrt(d2) <= band;
-        }
-        if (st == RBFFD_OK && !inside) {
-            dev_free(ctx, aug_dev, abytes);
+        if (st == RBFFD_OK && *(const int *)(hf + 2) != 0) {
+            dev_free(ctx, aug, abytes);
+            dev_free(ctx, owner, obytes);
             continue;   // a q-th neighbour beyond the band: widen it
         }
         if (st == RBFFD_OK)
-            st = launch_weights(ctx, dim, n, aug_dev, q, nbr, opts->poly_degree, opts->phs_power, w, bad_dev, s);
+            st = launch_weights(ctx, dim, n, aug, q, nbr, opts->poly_degree, opts->phs_power, w, flags, s);
+        // neighbour indices back to the points they are images of; a point may
+        // appear in a cloud only once
+        if (st == RBFFD_OK) st = launch_periodic_remap(n, q, owner, nbr, flags + 1, s);
         if (st == RBFFD_OK) {
-            e = hipMemcpyAsync(hb, bad_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+            hipError_t e = hipMemcpyAsync(hf, flags, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
             if (e != hipSuccess) st = hip_fail(e, "periodic weights");
         }
         (void)hipStreamSynchronize(s);
-        dev_free(ctx, aug_dev, abytes);
+        dev_free(ctx, aug, abytes);
+        dev_free(ctx, owner, obytes);
         RB_CHECK(st);
-        // neighbour indices back to the points they are images of; a point may
-        // appear in a cloud only once
-        std::vector<int32_t> row((size_t)q);
-        for (int64_t i = 0; i < n; ++i) {
-            for (int a = 0; a < q; ++a) row[a] = owner[hn[i * q + a]];
-            std::vector<int32_t> sorted(row);
-            std::sort(sorted.begin(), sorted.end());
-            if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
-                return fail(RBFFD_E_ARG, "point " + std::to_string(i) +
-                                             ": its cloud holds two images of one point (period too small for q)");
-            for (int a = 0; a < q; ++a) hn[i * q + a] = row[a];
-        }
-        RB_HIP(hipMemcpyAsync(nbr, hn.data(), sizeof(int32_t) * n * q, hipMemcpyHostToDevice, s));
-        RB_HIP(hipStreamSynchronize(s));
-        const int64_t bad = (*hb == INT64_MAX) ? -1 : *hb;
+        if (hf[1] != INT64_MAX)
+            return fail(RBFFD_E_ARG, "point " + std::to_string(hf[1]) +
+                                         ": its cloud holds two images of one point (period too small for q)");
+        const int64_t bad = (hf[0] == INT64_MAX) ? -1 : hf[0];
         if (bad_point) *bad_point = bad;
         if (bad >= 0) return fail(RBFFD_E_SINGULAR, "singular collocation system at point " + std::to_string(bad));
         return RBFFD_OK;
@@ -655,101 +589,68 @@ static int interpolate_periodic(rbffd_ctx *ctx, const rbffd_cloud *cloud, const 
 {
     const int dim = cloud->dim;
     const int64_t n = cloud->n;
-    PeriodicBox box;
-    RB_CHECK(periodic_box(cloud, q, s, &box));
-    const double *L = cloud->period;
-    std::vector<double> hq((size_t)nq * dim);
-    RB_HIP(hipMemcpyAsync(hq.data(), qxyz, sizeof(double) * nq * dim, hipMemcpyDeviceToHost, s));
-    RB_HIP(hipStreamSynchronize(s));
-    std::vector<double> outside((size_t)nq, 0.0);   // largest distance of a query outside the box along an axis
-    for (int64_t t = 0; t < nq; ++t)
-        for (int d = 0; d < dim; ++d) {
-            double &v = hq[t * dim + d];
-            if (!std::isfinite(v)) return fail(RBFFD_E_ARG, "non-finite query coordinates");
-            if (!(L[d] > 0.0)) continue;
-            if (v < box.lo[d] || v >= box.lo[d] + L[d]) {
-                double r = std::fmod(v - box.lo[d], L[d]);
-                if (r < 0.0) r += L[d];
-                v = box.lo[d] + r;
-            }
-            outside[t] = std::max(outside[t], std::max(box.lo[d] - v, v - box.hi[d]));
-        }
-    const size_t qbytes = sizeof(double) * nq * dim;
+    PeriodicShifts P;
+    double band = 0.0;
+    RB_CHECK(periodic_setup(ctx, cloud, q, s, &P, &band));
+    // the queries, wrapped into the box, and their margins, on the device
+    const size_t qbytes = sizeof(double) * nq * (dim + 1);
     double *qdev = nullptr;
     RB_CHECK(dev_alloc(ctx, (void **)&qdev, qbytes));
-    int64_t *bad_dev = nullptr, *hb = nullptr;
-    int st = workspace(ctx, WS_MISC, sizeof(int64_t), (void **)&bad_dev);
-    if (st == RBFFD_OK) st = host_scratch(ctx, kHostMisc, sizeof(int64_t), (void **)&hb);
+    double *margin = qdev + nq * dim;
+    int64_t *flags = nullptr, *hf = nullptr;   // [0]: singular query, [1]: cloud with a repeated point, [2]: flag
+    int st = workspace(ctx, WS_MISC, 3 * sizeof(int64_t), (void **)&flags);
+    if (st == RBFFD_OK) st = host_scratch(ctx, kHostMisc, 3 * sizeof(int64_t), (void **)&hf);
     hipError_t e = hipSuccess;
-    if (st == RBFFD_OK) {
-        e = hipMemcpyAsync(qdev, hq.data(), qbytes, hipMemcpyHostToDevice, s);
+    if (st == RBFFD_OK && nq > 0) {
+        e = hipMemcpyAsync(qdev, qxyz, sizeof(double) * nq * dim, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) st = hip_fail(e, "periodic queries");
     }
-    std::vector<int32_t> hn((size_t)nq * q);
-    double band = box.band;
+    if (st == RBFFD_OK) st = launch_periodic_wrap(dim, nq, qdev, P, margin, (int *)(flags + 2), s);
+    if (st == RBFFD_OK) {
+        e = hipMemcpyAsync(hf + 2, flags + 2, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = hip_fail(e, "periodic queries");
+        else if (*(const int *)(hf + 2) != 0) st = fail(RBFFD_E_ARG, "non-finite query coordinates");
+    }
     bool done = false;
     for (int attempt = 0; st == RBFFD_OK && !done && attempt < 12; ++attempt, band *= 2.0) {
-        std::vector<double> aug;
-        std::vector<int32_t> owner;
-        periodic_images(box, band, aug, owner);
-        const int64_t naug = (int64_t)owner.size();
-        if (naug >= (int64_t(1) << 31)) {
-            st = fail(RBFFD_E_ARG, "too many periodic images");
-            break;
-        }
-        double *aug_dev = nullptr;
-        const size_t abytes = sizeof(double) * naug * dim;
-        st = dev_alloc(ctx, (void **)&aug_dev, abytes);
+        P.band = band;
+        double *aug = nullptr;
+        int32_t *owner = nullptr;
+        int64_t naug = 0;
+        size_t abytes = 0, obytes = 0;
+        st = launch_periodic_images(ctx, dim, n, cloud->xyz, P, &aug, &owner, &naug, &abytes, &obytes, s);
         if (st != RBFFD_OK) break;
-        e = hipMemcpyAsync(aug_dev, aug.data(), abytes, hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) st = hip_fail(e, "periodic images");
-        if (st == RBFFD_OK) st = launch_knn_points(ctx, dim, naug, aug_dev, nq, qdev, q, nbr, s);
+        st = launch_knn_points(ctx, dim, naug, aug, nq, qdev, q, nbr, s);
+        // no image left out can be nearer than band less the query's margin
+        if (st == RBFFD_OK) st = launch_periodic_inside(dim, nq, qdev, aug, q, nbr, band, margin, (int *)(flags + 2), s);
         if (st == RBFFD_OK) {
-            e = hipMemcpyAsync(hn.data(), nbr, sizeof(int32_t) * nq * q, hipMemcpyDeviceToHost, s);
+            e = hipMemcpyAsync(hf + 2, flags + 2, sizeof(int64_t), hipMemcpyDeviceToHost, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
             if (e != hipSuccess) st = hip_fail(e, "periodic neighbours");
         }
-        bool inside = true;
-        for (int64_t t = 0; st == RBFFD_OK && t < nq && inside; ++t) {
-            const int64_t j = hn[t * q + q - 1];
-            double d2 = 0.0;
-            for (int d = 0; d < dim; ++d) {
-                const double dd = aug[j * dim + d] - hq[t * dim + d];
-                d2 += dd * dd;
-            }
-            inside = std::sqrt(d2) <= band - outside[t];
-        }
-        if (st == RBFFD_OK && inside) {
+        if (st == RBFFD_OK && *(const int *)(hf + 2) == 0) {
             done = true;
-            st = launch_interp(ctx, dim, naug, aug_dev, nq, qdev, q, nbr, opts->poly_degree, opts->phs_power, w,
-                               bad_dev, 0, nullptr, nullptr, s);
+            st = launch_interp(ctx, dim, naug, aug, nq, qdev, q, nbr, opts->poly_degree, opts->phs_power, w, flags, 0,
+                               nullptr, nullptr, s);
+            // image indices back to the points they stand for; a point may
+            // appear in a cloud only once
+            if (st == RBFFD_OK) st = launch_periodic_remap(nq, q, owner, nbr, flags + 1, s);
             if (st == RBFFD_OK) {
-                e = hipMemcpyAsync(hb, bad_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+                e = hipMemcpyAsync(hf, flags, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s);
                 if (e == hipSuccess) e = hipStreamSynchronize(s);
                 if (e != hipSuccess) st = hip_fail(e, "periodic interpolation weights");
             }
-            // image indices back to the points they stand for; a point may
-            // appear in a cloud only once
-            std::vector<int32_t> row((size_t)q);
-            for (int64_t t = 0; st == RBFFD_OK && t < nq; ++t) {
-                for (int a = 0; a < q; ++a) row[a] = owner[hn[t * q + a]];
-                std::vector<int32_t> sorted(row);
-                std::sort(sorted.begin(), sorted.end());
-                if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
-                    st = fail(RBFFD_E_ARG, "query " + std::to_string(t) +
-                                               ": its cloud holds two images of one point (period too small for q)");
-                for (int a = 0; a < q; ++a) hn[t * q + a] = row[a];
-            }
+            if (st == RBFFD_OK && hf[1] != INT64_MAX)
+                st = fail(RBFFD_E_ARG, "query " + std::to_string(hf[1]) +
+                                           ": its cloud holds two images of one point (period too small for q)");
         }
         (void)hipStreamSynchronize(s);
-        dev_free(ctx, aug_dev, abytes);
+        dev_free(ctx, aug, abytes);
+        dev_free(ctx, owner, obytes);
     }
     if (st == RBFFD_OK && !done) st = fail(RBFFD_E_ARG, "no band of periodic images holds every cloud");
-    if (st == RBFFD_OK) {
-        e = hipMemcpyAsync(nbr, hn.data(), sizeof(int32_t) * nq * q, hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) st = hip_fail(e, "periodic clouds");
-    }
-    const int64_t bad = (st == RBFFD_OK && *hb != INT64_MAX) ? *hb : -1;
+    const int64_t bad = (st == RBFFD_OK && hf[0] != INT64_MAX) ? hf[0] : -1;
     if (st == RBFFD_OK && bad < 0) st = launch_interp_apply(nq, q, nbr, w, nfield, n, fields, out, s);
     (void)hipStreamSynchronize(s);
     dev_free(ctx, qdev, qbytes);

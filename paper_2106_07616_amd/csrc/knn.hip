@@ -12,6 +12,7 @@
 #include <cmath>
 
 #include "internal.h"
+#include "periodic.h"
 
 namespace rbffd {
 
@@ -358,6 +359,114 @@ int scan_exclusive(rbffd_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, h
     return st;
 }
 
+// ---- periodic clouds (Sec. 3.1) -------------------------------------------
+// Image of point j under shift k: x + L or x - L along the shifted axes (the
+// same floating-point operations as any host-side construction), kept when
+// within band of the box along every periodic axis.
+template <int DIM>
+__device__ inline bool periodic_image(const double *__restrict__ xyz, int64_t j, const PeriodicShifts &P, int k,
+                                      double *y)
+{
+    bool keep = true;
+    for (int d = 0; d < DIM; ++d) {
+        const double v = xyz[j * DIM + d];
+        const int md = P.m[k][d];
+        y[d] = (md > 0) ? v + P.L[d] : ((md < 0) ? v - P.L[d] : v);
+        if (P.L[d] > 0.0 && (y[d] < P.lo[d] - P.band || y[d] > P.hi[d] + P.band)) keep = false;
+    }
+    return keep;
+}
+
+// flag[k n + j] = 1 when point j's image under shift k is kept
+template <int DIM>
+__global__ void periodic_flags(const double *__restrict__ xyz, int64_t n, PeriodicShifts P, int32_t *__restrict__ flag)
+{
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= n * P.count) return;
+    const int k = (int)(idx / n);
+    const int64_t j = idx - (int64_t)k * n;
+    double y[3];
+    flag[idx] = periodic_image<DIM>(xyz, j, P, k, y) ? 1 : 0;
+}
+
+// rows 0..n-1: the points; row n + pos[k n + j]: the kept image of point j
+// under shift k
+template <int DIM>
+__global__ void periodic_scatter(const double *__restrict__ xyz, int64_t n, PeriodicShifts P,
+                                 const int32_t *__restrict__ flag, const int32_t *__restrict__ pos,
+                                 double *__restrict__ aug, int32_t *__restrict__ owner)
+{
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx < n) {
+        for (int d = 0; d < DIM; ++d) aug[idx * DIM + d] = xyz[idx * DIM + d];
+        owner[idx] = (int32_t)idx;
+        return;
+    }
+    const int64_t t = idx - n;
+    if (t >= n * P.count || !flag[t]) return;
+    const int k = (int)(t / n);
+    const int64_t j = t - (int64_t)k * n;
+    double y[3];
+    periodic_image<DIM>(xyz, j, P, k, y);
+    const int64_t r = n + pos[t];
+    for (int d = 0; d < DIM; ++d) aug[r * DIM + d] = y[d];
+    owner[r] = (int32_t)j;
+}
+
+template <int DIM>
+__global__ void periodic_inside(const double *__restrict__ qxyz, int64_t nq, const double *__restrict__ aug, int q,
+                                const int32_t *__restrict__ nbr, double band, const double *__restrict__ margin,
+                                int *__restrict__ outside)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= nq) return;
+    const int64_t j = nbr[t * q + q - 1];
+    const double d2 = sqdist_exact<DIM>(qxyz + t * DIM, aug + j * DIM);
+    if (!(sqrt(d2) <= (margin ? band - margin[t] : band))) atomicOr(outside, 1);
+}
+
+template <int DIM>
+__global__ void periodic_wrap(double *__restrict__ qxyz, int64_t nq, PeriodicShifts P, double *__restrict__ margin,
+                              int *__restrict__ nonfinite)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= nq) return;
+    double out = 0.0;
+    for (int d = 0; d < DIM; ++d) {
+        double v = qxyz[t * DIM + d];
+        if (!isfinite(v)) {
+            atomicOr(nonfinite, 1);
+            return;
+        }
+        if (!(P.L[d] > 0.0)) continue;
+        if (v < P.lo[d] || v >= P.lo[d] + P.L[d]) {
+            double r = fmod(v - P.lo[d], P.L[d]);
+            if (r < 0.0) r += P.L[d];
+            v = P.lo[d] + r;
+            qxyz[t * DIM + d] = v;
+        }
+        out = fmax(out, fmax(P.lo[d] - v, v - P.hi[d]));
+    }
+    margin[t] = out;
+}
+
+__global__ void periodic_remap(int64_t n, int q, const int32_t *__restrict__ owner, int32_t *__restrict__ nbr,
+                               unsigned long long *__restrict__ first_dup)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t *row = nbr + i * q;
+    for (int a = 0; a < q; ++a) row[a] = owner[row[a]];
+    bool dup = false;
+    for (int a = 0; a < q && !dup; ++a)
+        for (int b = a + 1; b < q; ++b)
+            if (row[a] == row[b]) {
+                dup = true;
+                break;
+            }
+    if (dup) atomicMin(first_dup, (unsigned long long)i);
+}
+
 // Duplicate points (an input error). A point that coincides with another has
 // that point at squared distance 0 among its two nearest, since clouds are in
 // (d^2, index) order, so the first two entries of each cloud decide it: the
@@ -385,6 +494,130 @@ int launch_dup_check(int dim, int64_t n, const double *xyz, int q, const int32_t
         hipLaunchKernelGGL(dup_check_kernel<2>, grid, block, 0, s, xyz, nbr, n, q, (unsigned long long *)first);
     else
         hipLaunchKernelGGL(dup_check_kernel<3>, grid, block, 0, s, xyz, nbr, n, q, (unsigned long long *)first);
+    RB_HIP(hipGetLastError());
+    return RBFFD_OK;
+}
+
+int device_bbox(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, double *lo, double *hi, hipStream_t s)
+{
+    const int nbb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + kBlock - 1) / kBlock));
+    double *part = nullptr;
+    RB_CHECK(dev_alloc(ctx, (void **)&part, sizeof(double) * (nbb * 6 + 6)));
+    double *bb = part + nbb * 6;
+    if (dim == 2)
+        hipLaunchKernelGGL(bbox_partial<2>, dim3(nbb), dim3(kBlock), 0, s, xyz, n, part);
+    else
+        hipLaunchKernelGGL(bbox_partial<3>, dim3(nbb), dim3(kBlock), 0, s, xyz, n, part);
+    hipLaunchKernelGGL(bbox_final, dim3(1), dim3(64), 0, s, part, nbb, bb);
+    double hb[6];
+    hipError_t e = hipMemcpyAsync(hb, bb, sizeof(hb), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dev_free(ctx, part, sizeof(double) * (nbb * 6 + 6));
+    if (e != hipSuccess) return hip_fail(e, "bounding box");
+    for (int d = 0; d < dim; ++d) {
+        if (!std::isfinite(hb[d]) || !std::isfinite(hb[3 + d])) return fail(RBFFD_E_ARG, "non-finite coordinates");
+        lo[d] = hb[d];
+        hi[d] = hb[3 + d];
+    }
+    return RBFFD_OK;
+}
+
+int launch_periodic_images(rbffd_ctx *ctx, int dim, int64_t n, const double *xyz, const PeriodicShifts &P,
+                           double **aug, int32_t **owner, int64_t *naug, size_t *abytes, size_t *obytes,
+                           hipStream_t s)
+{
+    *aug = nullptr;
+    *owner = nullptr;
+    const int64_t m = n * P.count;
+    int32_t *flag = nullptr;
+    const size_t fbytes = sizeof(int32_t) * (2 * m + 1);
+    RB_CHECK(dev_alloc(ctx, (void **)&flag, fbytes));
+    int32_t *pos = flag + m;
+    int st = RBFFD_OK;
+    int32_t total = 0;
+    if (m > 0) {
+        const dim3 g((unsigned)((m + kBlock - 1) / kBlock));
+        if (dim == 2)
+            hipLaunchKernelGGL(periodic_flags<2>, g, dim3(kBlock), 0, s, xyz, n, P, flag);
+        else
+            hipLaunchKernelGGL(periodic_flags<3>, g, dim3(kBlock), 0, s, xyz, n, P, flag);
+        if (hipGetLastError() != hipSuccess) st = fail(RBFFD_E_DEVICE, "periodic image flags launch failed");
+        if (st == RBFFD_OK) st = scan_exclusive(ctx, flag, pos, m, s);
+        if (st == RBFFD_OK) {
+            hipError_t e = hipMemcpyAsync(&total, pos + m, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) st = hip_fail(e, "periodic image count");
+        }
+    }
+    const int64_t rows = n + (int64_t)total;
+    if (st == RBFFD_OK && rows >= (int64_t(1) << 31)) st = fail(RBFFD_E_ARG, "too many periodic images");
+    *abytes = sizeof(double) * (size_t)rows * dim;
+    *obytes = sizeof(int32_t) * (size_t)rows;
+    if (st == RBFFD_OK) st = dev_alloc(ctx, (void **)aug, *abytes);
+    if (st == RBFFD_OK) {
+        st = dev_alloc(ctx, (void **)owner, *obytes);
+        if (st != RBFFD_OK) {
+            dev_free(ctx, *aug, *abytes);
+            *aug = nullptr;
+        }
+    }
+    if (st == RBFFD_OK) {
+        const dim3 g((unsigned)((n + m + kBlock - 1) / kBlock));
+        if (dim == 2)
+            hipLaunchKernelGGL(periodic_scatter<2>, g, dim3(kBlock), 0, s, xyz, n, P, flag, pos, *aug, *owner);
+        else
+            hipLaunchKernelGGL(periodic_scatter<3>, g, dim3(kBlock), 0, s, xyz, n, P, flag, pos, *aug, *owner);
+        if (hipGetLastError() != hipSuccess) st = fail(RBFFD_E_DEVICE, "periodic image scatter launch failed");
+        (void)hipStreamSynchronize(s);
+    }
+    dev_free(ctx, flag, fbytes);
+    *naug = rows;
+    if (st != RBFFD_OK && *aug) {
+        dev_free(ctx, *aug, *abytes);
+        dev_free(ctx, *owner, *obytes);
+        *aug = nullptr;
+        *owner = nullptr;
+    }
+    return st;
+}
+
+int launch_periodic_inside(int dim, int64_t nq, const double *qxyz, const double *aug, int q, const int32_t *nbr,
+                           double band, const double *margin, int *outside, hipStream_t s)
+{
+    const int zero = 0;
+    RB_HIP(hipMemcpyAsync(outside, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+    if (nq <= 0) return RBFFD_OK;
+    const dim3 g((unsigned)((nq + kBlock - 1) / kBlock));
+    if (dim == 2)
+        hipLaunchKernelGGL(periodic_inside<2>, g, dim3(kBlock), 0, s, qxyz, nq, aug, q, nbr, band, margin, outside);
+    else
+        hipLaunchKernelGGL(periodic_inside<3>, g, dim3(kBlock), 0, s, qxyz, nq, aug, q, nbr, band, margin, outside);
+    RB_HIP(hipGetLastError());
+    return RBFFD_OK;
+}
+
+int launch_periodic_wrap(int dim, int64_t nq, double *qxyz, const PeriodicShifts &P, double *margin, int *nonfinite,
+                         hipStream_t s)
+{
+    const int zero = 0;
+    RB_HIP(hipMemcpyAsync(nonfinite, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+    if (nq <= 0) return RBFFD_OK;
+    const dim3 g((unsigned)((nq + kBlock - 1) / kBlock));
+    if (dim == 2)
+        hipLaunchKernelGGL(periodic_wrap<2>, g, dim3(kBlock), 0, s, qxyz, nq, P, margin, nonfinite);
+    else
+        hipLaunchKernelGGL(periodic_wrap<3>, g, dim3(kBlock), 0, s, qxyz, nq, P, margin, nonfinite);
+    RB_HIP(hipGetLastError());
+    return RBFFD_OK;
+}
+
+int launch_periodic_remap(int64_t n, int q, const int32_t *owner, int32_t *nbr, int64_t *first_dup, hipStream_t s)
+{
+    const long long init = LLONG_MAX;
+    RB_HIP(hipMemcpyAsync(first_dup, &init, sizeof(init), hipMemcpyHostToDevice, s));
+    if (n <= 0) return RBFFD_OK;
+    hipLaunchKernelGGL(periodic_remap, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, q, owner,
+                       nbr, (unsigned long long *)first_dup);
     RB_HIP(hipGetLastError());
     return RBFFD_OK;
 }
