@@ -1,6 +1,5 @@
 // C ABI entry points, context and error handling.
 #include <algorithm>
-#include <array>
 #include <cmath>
 #include <cstring>
 #include <new>
