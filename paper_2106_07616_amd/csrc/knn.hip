@@ -97,14 +97,31 @@ __global__ __launch_bounds__(kBlock) void bbox_partial(const double *__restrict_
     }
 }
 
-__global__ void bbox_final(const double *__restrict__ part, int np, double *__restrict__ out)
+// One wavefront (64 threads): lane l folds partials l, l + 64, ... of the six
+// extents, then a shuffle reduction finishes them. Minima and maxima are exact
+// in any order, and the partials hold no NaN (bbox_partial widens the box to
+// +-infinity instead).
+__global__ __launch_bounds__(64) void bbox_final(const double *__restrict__ part, int np, double *__restrict__ out)
 {
-    if (threadIdx.x < 6) {
-        const bool isMin = threadIdx.x < 3;
-        double r = isMin ? DBL_MAX : -DBL_MAX;
-        for (int j = 0; j < np; ++j) r = isMin ? fmin(r, part[j * 6 + threadIdx.x]) : fmax(r, part[j * 6 + threadIdx.x]);
-        out[threadIdx.x] = r;
-    }
+    const int l = threadIdx.x;
+    double r[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) r[d] = (d < 3) ? DBL_MAX : -DBL_MAX;
+    for (int j = l; j < np; j += 64)
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            const double v = part[j * 6 + d];
+            r[d] = (d < 3) ? fmin(r[d], v) : fmax(r[d], v);
+        }
+#pragma unroll
+    for (int d = 0; d < 6; ++d)
+        for (int o = 32; o > 0; o >>= 1) {
+            const double u = __shfl_xor(r[d], o, 64);
+            r[d] = (d < 3) ? fmin(r[d], u) : fmax(r[d], u);
+        }
+    if (l == 0)
+#pragma unroll
+        for (int d = 0; d < 6; ++d) out[d] = r[d];
 }
 
 // ---- binning ------------------------------------------------------------
