@@ -18,18 +18,20 @@ namespace rbffd {
 namespace {
 
 // One workgroup per 64-row slice: the slice's clouds are staged in LDS, each
-// lane ranks its row's neighbours by index and scatters weights into the slot
-// of that rank.
+// lane ranks its row's neighbours by index and writes the column indices in
+// rank order; then the workgroup copies the weights in cloud order (coalesced
+// reads) into the slot of each entry's rank.
 __global__ __launch_bounds__(64) void sort_rows(const int32_t *__restrict__ nbr, const double *__restrict__ w,
                                                 int64_t n, int q, int R, int32_t *__restrict__ col,
                                                 double *__restrict__ val, int64_t vstride)
 {
-    extern __shared__ int32_t sh[];   // [64][q+1]
+    extern __shared__ int32_t sh[];                  // [64][q+1] neighbour indices
+    int16_t *rk = (int16_t *)(sh + 64 * (q + 1));    // [64][q] ranks
     const int64_t i0 = (int64_t)blockIdx.x * 64;
     const int t = threadIdx.x;
-    const int64_t rows = min((int64_t)64, n - i0);
-    for (int64_t e = t; e < rows * q; e += 64) {
-        const int64_t r = e / q, a = e % q;
+    const int rows = (int)min((int64_t)64, n - i0);
+    for (int e = t; e < rows * q; e += 64) {
+        const int r = e / q, a = e % q;
         sh[r * (q + 1) + a] = nbr[(i0 + r) * q + a];
     }
     __syncthreads();
@@ -40,17 +42,22 @@ __global__ __launch_bounds__(64) void sort_rows(const int32_t *__restrict__ nbr,
             col[slot] = 0;
             for (int r = 0; r < R; ++r) val[r * vstride + slot] = 0.0;
         }
-        return;
+    } else {
+        const int32_t *mine = sh + t * (q + 1);
+        for (int a = 0; a < q; ++a) {
+            const int32_t c = mine[a];
+            int rank = 0;
+            for (int b = 0; b < q; ++b) rank += (mine[b] < c);
+            rk[t * q + a] = (int16_t)rank;
+            col[ell_at(i, rank, q)] = c;
+        }
     }
-    const int32_t *mine = sh + t * (q + 1);
-    for (int a = 0; a < q; ++a) {
-        const int32_t c = mine[a];
-        int rank = 0;
-        for (int b = 0; b < q; ++b) rank += (mine[b] < c);
-        const int64_t slot = ell_at(i, rank, q);
-        col[slot] = c;
-        for (int r = 0; r < R; ++r) val[r * vstride + slot] = w[(int64_t)r * n * q + i * q + a];
-    }
+    __syncthreads();
+    for (int r = 0; r < R; ++r)
+        for (int e = t; e < rows * q; e += 64) {
+            const int row = e / q;
+            val[r * vstride + ell_at(i0 + row, rk[e], q)] = w[(int64_t)r * n * q + i0 * q + e];
+        }
 }
 
 // Pressure-correction matrix rows and its Jacobi diagonal.
@@ -353,8 +360,8 @@ int assemble_ops(rbffd_ctx *ctx, const rbffd_cloud *cloud, int q, int k, int phs
     }
 
     const unsigned nslices = (unsigned)(npad / 64);
-    hipLaunchKernelGGL(sort_rows, dim3(nslices), dim3(64), sizeof(int32_t) * 64 * (q + 1), s, nbr, w, n, q, ops->R,
-                       ops->col, ops->val, nnz);
+    hipLaunchKernelGGL(sort_rows, dim3(nslices), dim3(64), sizeof(int32_t) * 64 * (q + 1) + sizeof(int16_t) * 64 * q,
+                       s, nbr, w, n, q, ops->R, ops->col, ops->val, nnz);
     RB_HIP(hipGetLastError());
     hipLaunchKernelGGL(slice_offsets, dim3(nslices), dim3(64), 0, s, ops->col, n, q, ops->cbase, ops->col16);
     RB_HIP(hipGetLastError());
